@@ -1,0 +1,435 @@
+"""Plain, slow, obviously-correct FP64 reference for one noisy Grover iteration.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): never imported by the
+product path.
+
+Conventions (all from the paper, Sec. 2.2 "Multi-qubit states"):
+  * an n_q-qubit state is the array C_n, n = 0 .. 2^n_q - 1, in standard order;
+  * n = sum_i q_i 2^(n_q - i) (Eq. staten): qubit 1 is the most significant
+    bit, qubit n_q the least significant;
+  * a one-qubit operator on qubit i_s couples the partner pair
+    n_1 = n_0 + 2^(n_q - i_s) (Eqs. pair0, pair1 and the "stride" of Sec. 3).
+
+Gate lists are sequences of tuples, applied left to right (first tuple first):
+  ("H", i_s)                      Hadamard on qubit i_s (Eq. NOTH)
+  ("ONEOP", i_s, op)              any 2x2 complex operator, op[a][b] = <a|op|b>
+  ("HALL",)                       Hadamard on every qubit (Eq. HALL, Sec. 4.3)
+  ("ORACLE",)                     sign flip of every marked item (Eq. oracle1)
+  ("INV",)                        2|0..0><0..0| - I (Eq. inversion)
+  ("D2", i_s, alpha, beta, gamma) Wigner D^(1/2) noise rotation (Sec. 6.3)
+"""
+
+import math
+
+import numpy as np
+
+__all__ = [
+    "stride", "pair_indices", "pair_indices_loop", "quartet_indices",
+    "section_seat", "same_section",
+    "PAULI_X", "PAULI_Y", "PAULI_Z", "IDENTITY", "NOT", "HADAMARD",
+    "apply_oneop", "apply_oneop_loop", "hall", "hall2_sign", "hall2",
+    "oracle_flip", "inversion",
+    "rz", "ry", "d2_matrix", "d2_derivatives",
+    "grover_gates", "apply_gate", "apply_gate_adjoint", "evaluate",
+    "readout", "adjoint_grad", "fd_grad_angles", "fd_grad_psi",
+    "kron_operator", "dense_circuit",
+    "grover_closed_form", "diffusion_closed_form",
+]
+
+# ---------------------------------------------------------------------------
+# Index map (Sec. 2.2, Eqs. staten / pair0 / pair1; Sec. 3; Sec. 4 Eq. twoopB)
+# ---------------------------------------------------------------------------
+
+
+def stride(nq, i_s):
+    """Stride of qubit i_s: the step 2^(n_q - i_s) from n_0 to its partner (Sec. 3)."""
+    if not 1 <= i_s <= nq:
+        raise ValueError("qubit label must lie in 1..nq")
+    return 1 << (nq - i_s)
+
+
+def pair_indices(nq, i_s):
+    """All 2^n_q / 2 partner pairs (n_0, n_1) for qubit i_s, n_0 ascending.
+
+    Eq. pair0 gives n_0 = n - q_{i_s} 2^(n_q-i_s); the pairs are enumerated by
+    the labels n whose qubit i_s is 0, and n_1 = n_0 + stride (Sec. 3).
+    """
+    n = np.arange(1 << nq, dtype=np.int64)
+    q = (n >> (nq - i_s)) & 1
+    n0 = n[q == 0]
+    return n0, n0 + stride(nq, i_s)
+
+
+def pair_indices_loop(nq, i_s):
+    """Pure-Python version of :func:`pair_indices` through binary labels.
+
+    Builds each label's bit array B(1..n_q) (the dectobin routine of Sec. 2.2),
+    keeps labels with B(i_s) = 0, and forms the partner by setting B(i_s) = 1
+    and converting back (bintodec).  For small n_q only.
+    """
+    pairs0, pairs1 = [], []
+    for n in range(1 << nq):
+        bits = [(n >> (nq - i)) & 1 for i in range(1, nq + 1)]
+        if bits[i_s - 1] == 0:
+            partner = list(bits)
+            partner[i_s - 1] = 1
+            pairs0.append(sum(b << (nq - i) for i, b in enumerate(bits, start=1)))
+            pairs1.append(sum(b << (nq - i) for i, b in enumerate(partner, start=1)))
+    return np.array(pairs0, dtype=np.int64), np.array(pairs1, dtype=np.int64)
+
+
+def quartet_indices(nq, is1, is2):
+    """Amplitude quartets (n_00, n_01, n_10, n_11) of Sec. 4, Eq. twoopB.
+
+    n_01 = n_00 + 2^(n_q - is2), n_10 = n_00 + 2^(n_q - is1); 2^n_q / 4 quartets.
+    """
+    if is1 == is2:
+        raise ValueError("two-qubit operator needs two distinct qubits")
+    n = np.arange(1 << nq, dtype=np.int64)
+    free = (((n >> (nq - is1)) & 1) == 0) & (((n >> (nq - is2)) & 1) == 0)
+    n00 = n[free]
+    s1, s2 = stride(nq, is1), stride(nq, is2)
+    return n00, n00 + s2, n00 + s1, n00 + s1 + s2
+
+
+def section_seat(n, nq, p):
+    """Processor (section) and seat of label n with N_P = 2^p ranks (Sec. 3.2)."""
+    nx = (1 << nq) >> p  # NPART = 2^(n_q - p)
+    return n // nx, n % nx
+
+
+def same_section(nq, i_s, p):
+    """Locality rule of Sec. 3.1: the pair of qubit i_s is on one rank iff i_s > p."""
+    return i_s > p
+
+
+# ---------------------------------------------------------------------------
+# One-qubit operators (Eq. Pauli, Eq. NOTH; Eq. resmat1 of Sec. 3)
+# ---------------------------------------------------------------------------
+
+IDENTITY = np.eye(2, dtype=np.complex128)
+PAULI_X = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+PAULI_Y = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+PAULI_Z = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+NOT = PAULI_X
+HADAMARD = (PAULI_X + PAULI_Z) / math.sqrt(2.0)
+
+
+def apply_oneop(psi, nq, i_s, op):
+    """Return Omega_s psi for a 2x2 operator on qubit i_s (Eq. resmat1).
+
+    For every pair, (C~_n0, C~_n1) = op (C_n0, C_n1) with op[a][b] = <a|op|b>.
+    The state is viewed as (2^(i_s-1), 2, 2^(n_q-i_s)); axis 1 is q_{i_s}, so
+    v[:, 0, :] are the C_n0 and v[:, 1, :] their partners one stride away.
+    """
+    psi = np.asarray(psi, dtype=np.complex128)
+    op = np.asarray(op, dtype=np.complex128)
+    v = psi.reshape(1 << (i_s - 1), 2, 1 << (nq - i_s))
+    c0, c1 = v[:, 0, :], v[:, 1, :]
+    out = np.empty_like(v)
+    out[:, 0, :] = op[0, 0] * c0 + op[0, 1] * c1
+    out[:, 1, :] = op[1, 0] * c0 + op[1, 1] * c1
+    return out.reshape(-1)
+
+
+def apply_oneop_loop(psi, nq, i_s, op):
+    """Eq. resmat1 pair by pair over :func:`pair_indices_loop` (small n_q only)."""
+    out = np.array(psi, dtype=np.complex128)
+    n0s, n1s = pair_indices_loop(nq, i_s)
+    for n0, n1 in zip(n0s, n1s):
+        a, b = psi[n0], psi[n1]
+        out[n0] = op[0][0] * a + op[0][1] * b
+        out[n1] = op[1][0] * a + op[1][1] * b
+    return out
+
+
+def hall(psi, nq):
+    """HALL: the Hadamard on qubits 1..n_q in turn (Eq. HALL, Sec. 4.3)."""
+    for i_s in range(1, nq + 1):
+        psi = apply_oneop(psi, nq, i_s, HADAMARD)
+    return psi
+
+
+def hall2_sign(nq, n, n_prime):
+    """The sign s_{n,n'} of Sec. 4.3 (function SH).
+
+    (-1)^delta where delta counts the qubits i with B(i) = B'(i) = 1.
+    """
+    delta = sum(((n >> (nq - i)) & 1) & ((n_prime >> (nq - i)) & 1) for i in range(1, nq + 1))
+    return -1 if delta % 2 else 1
+
+
+def hall2(psi, nq):
+    """HALL2: C~_n = 2^(-n_q/2) sum_n' s_{n,n'} C_n' (Sec. 4.3), O(4^n_q), brute force."""
+    size = 1 << nq
+    s = np.empty((size, size), dtype=np.float64)
+    for n in range(size):
+        for m in range(size):
+            s[n, m] = hall2_sign(nq, n, m)
+    return (s @ np.asarray(psi, dtype=np.complex128)) / (2.0 ** (nq / 2.0))
+
+
+def oracle_flip(psi, marked):
+    """Oracle of Eq. oracle1, extended to several marked items: C_x -> -C_x."""
+    out = np.array(psi, dtype=np.complex128)
+    for x in marked:
+        out[x] = -out[x]
+    return out
+
+
+def inversion(psi):
+    """Inv = 2|0..0><0..0| - I (Eq. inversion): every C_n with n != 0 changes sign."""
+    out = -np.asarray(psi, dtype=np.complex128)
+    out[0] = psi[0]
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Noise rotation D^(1/2)(alpha, beta, gamma) (Sec. 6.3, subroutine D2)
+# ---------------------------------------------------------------------------
+#
+# Reading adopted where the paper is silent: D = R_z(alpha) R_y(beta) R_z(gamma),
+# R_z(phi) = diag(e^{-i phi/2}, e^{+i phi/2}), R_y(beta) the real rotation by
+# beta/2; rows/columns are m = +1/2 (spin up = |0>, Sec. 2.1) then m = -1/2.
+
+
+def rz(phi):
+    return np.array([[np.exp(-0.5j * phi), 0.0], [0.0, np.exp(0.5j * phi)]], dtype=np.complex128)
+
+
+def ry(beta):
+    c, s = math.cos(0.5 * beta), math.sin(0.5 * beta)
+    return np.array([[c, -s], [s, c]], dtype=np.complex128)
+
+
+def _drz(phi):
+    return np.array([[-0.5j * np.exp(-0.5j * phi), 0.0], [0.0, 0.5j * np.exp(0.5j * phi)]],
+                    dtype=np.complex128)
+
+
+def _dry(beta):
+    c, s = math.cos(0.5 * beta), math.sin(0.5 * beta)
+    return 0.5 * np.array([[-s, -c], [c, -s]], dtype=np.complex128)
+
+
+def d2_matrix(alpha, beta, gamma):
+    """Wigner rotation D^(1/2)(alpha, beta, gamma) as the product of three rotations."""
+    return rz(alpha) @ ry(beta) @ rz(gamma)
+
+
+def d2_derivatives(alpha, beta, gamma):
+    """(dD/dalpha, dD/dbeta, dD/dgamma) by the product rule on the three factors."""
+    return (_drz(alpha) @ ry(beta) @ rz(gamma),
+            rz(alpha) @ _dry(beta) @ rz(gamma),
+            rz(alpha) @ ry(beta) @ _drz(gamma))
+
+
+# ---------------------------------------------------------------------------
+# Circuits: the Grover operator of Sec. 5.1 with the noise of Sec. 6.3
+# ---------------------------------------------------------------------------
+
+
+def grover_gates(noise=None):
+    """One Grover iteration G = HALL . Inv . HALL . Oracle (Sec. 5.1).
+
+    Operator products act right to left, so the Oracle comes first in the list.
+    ``noise`` = (qhit, eloc, alpha, beta, gamma) inserts one D2 at stage
+    boundary eloc in 0..4 (before the Oracle, after the Oracle, after the first
+    HALL, after Inv, after the second HALL), as in Sec. 6.3.
+    """
+    steps = [("ORACLE",), ("HALL",), ("INV",), ("HALL",)]
+    if noise is None:
+        return steps
+    qhit, eloc, alpha, beta, gamma = noise
+    if not 0 <= eloc <= 4:
+        raise ValueError("eloc must be a stage boundary 0..4")
+    return steps[:eloc] + [("D2", int(qhit), float(alpha), float(beta), float(gamma))] + steps[eloc:]
+
+
+def _gate_matrix(gate):
+    kind = gate[0]
+    if kind == "H":
+        return HADAMARD
+    if kind == "ONEOP":
+        return np.asarray(gate[2], dtype=np.complex128)
+    if kind == "D2":
+        return d2_matrix(*gate[2:5])
+    raise ValueError(kind)
+
+
+def apply_gate(psi, nq, gate, marked):
+    """Apply one gate tuple (see the module docstring) to psi."""
+    kind = gate[0]
+    if kind in ("H", "ONEOP", "D2"):
+        return apply_oneop(psi, nq, gate[1], _gate_matrix(gate))
+    if kind == "HALL":
+        return hall(psi, nq)
+    if kind == "ORACLE":
+        return oracle_flip(psi, marked)
+    if kind == "INV":
+        return inversion(psi)
+    raise ValueError("unknown gate kind %r" % (kind,))
+
+
+def apply_gate_adjoint(psi, nq, gate, marked):
+    """Apply the Hermitian adjoint of one gate (HALL, Oracle and Inv are self-adjoint)."""
+    kind = gate[0]
+    if kind in ("H", "ONEOP", "D2"):
+        return apply_oneop(psi, nq, gate[1], _gate_matrix(gate).conj().T)
+    return apply_gate(psi, nq, gate, marked)
+
+
+def readout(psi, marked):
+    """(L, norm): L = sum_{n in M} |C_n|^2, the success probability read out in Sec. 5.1,
+    and sum_n |C_n|^2; both correctly rounded with math.fsum."""
+    p = np.abs(np.asarray(psi)) ** 2
+    return math.fsum(float(p[x]) for x in marked), math.fsum(p.tolist())
+
+
+def evaluate(nq, gates, marked, psi_in):
+    """Apply ``gates`` in list order to psi_in (used as given, not renormalised).
+
+    Returns (psi_out, L, norm) with L and norm from :func:`readout`.
+    """
+    psi = np.array(psi_in, dtype=np.complex128)
+    if psi.shape != (1 << nq,):
+        raise ValueError("psi_in must have 2^nq amplitudes")
+    for g in gates:
+        psi = apply_gate(psi, nq, g, marked)
+    L, norm = readout(psi, marked)
+    return psi, L, norm
+
+
+# ---------------------------------------------------------------------------
+# Gradients (not in the paper): store-all adjoint and central differences
+# ---------------------------------------------------------------------------
+
+
+def adjoint_grad(nq, gates, marked, psi_in, dL=1.0):
+    """Gradient of dL * L by a store-all reverse sweep.
+
+    Keeps every intermediate state psi_k, seeds lambda_K = dL * P_M psi_K,
+    and for each gate from last to first adds 2 Re <lambda_k| dU_k/dtheta |psi_{k-1}>
+    to the angle gradient before setting lambda_{k-1} = U_k^dagger lambda_k.
+    Returns (grad_psi, grad_angles): grad_psi = 2 lambda_0 in the real-pair
+    convention (real part = dL/dRe psi_in, imaginary part = dL/dIm psi_in) and
+    grad_angles a (n_D2, 3) array in gate-list order.
+    """
+    states = [np.array(psi_in, dtype=np.complex128)]
+    for g in gates:
+        states.append(apply_gate(states[-1], nq, g, marked))
+    lam = np.zeros_like(states[-1])
+    for x in marked:
+        lam[x] = dL * states[-1][x]
+    d2_positions = [k for k, g in enumerate(gates) if g[0] == "D2"]
+    grads = np.zeros((len(d2_positions), 3))
+    for k in range(len(gates) - 1, -1, -1):
+        g = gates[k]
+        if g[0] == "D2":
+            row = d2_positions.index(k)
+            for t, dmat in enumerate(d2_derivatives(*g[2:5])):
+                dpsi = apply_oneop(states[k], nq, g[1], dmat)
+                grads[row, t] = 2.0 * float(np.vdot(lam, dpsi).real)
+        lam = apply_gate_adjoint(lam, nq, g, marked)
+    return 2.0 * lam, grads
+
+
+def _with_angle(gates, row, t, value):
+    d2_positions = [k for k, g in enumerate(gates) if g[0] == "D2"]
+    k = d2_positions[row]
+    g = list(gates[k])
+    g[2 + t] = value
+    out = list(gates)
+    out[k] = tuple(g)
+    return out
+
+
+def fd_grad_angles(nq, gates, marked, psi_in, h=1e-6):
+    """Central differences of L with respect to every D2 angle."""
+    n_d2 = sum(1 for g in gates if g[0] == "D2")
+    out = np.zeros((n_d2, 3))
+    d2_positions = [k for k, g in enumerate(gates) if g[0] == "D2"]
+    for row in range(n_d2):
+        for t in range(3):
+            base = gates[d2_positions[row]][2 + t]
+            lp = evaluate(nq, _with_angle(gates, row, t, base + h), marked, psi_in)[1]
+            lm = evaluate(nq, _with_angle(gates, row, t, base - h), marked, psi_in)[1]
+            out[row, t] = (lp - lm) / (2.0 * h)
+    return out
+
+
+def fd_grad_psi(nq, gates, marked, psi_in, index, part, h=1e-6):
+    """Central difference of L with respect to Re (part=0) or Im (part=1) of psi_in[index]."""
+    step = h if part == 0 else 1j * h
+    pp = np.array(psi_in, dtype=np.complex128)
+    pm = np.array(psi_in, dtype=np.complex128)
+    pp[index] += step
+    pm[index] -= step
+    return (evaluate(nq, gates, marked, pp)[1] - evaluate(nq, gates, marked, pm)[1]) / (2.0 * h)
+
+
+# ---------------------------------------------------------------------------
+# Brute force and closed forms (independent routes used as pins)
+# ---------------------------------------------------------------------------
+
+
+def kron_operator(nq, i_s, op):
+    """Full 2^n_q x 2^n_q matrix I x .. x op x .. x I with qubit 1 leftmost.
+
+    Uses the tensor-product rule of the footnote in Sec. 2.1; independent of the
+    stride formula.  Small n_q only.
+    """
+    m = np.ones((1, 1), dtype=np.complex128)
+    for i in range(1, nq + 1):
+        m = np.kron(m, np.asarray(op, dtype=np.complex128) if i == i_s else IDENTITY)
+    return m
+
+
+def dense_circuit(nq, gates, marked):
+    """Dense matrix of a gate list, built from Kronecker products (small n_q only)."""
+    size = 1 << nq
+    u = np.eye(size, dtype=np.complex128)
+    for g in gates:
+        kind = g[0]
+        if kind in ("H", "ONEOP", "D2"):
+            m = kron_operator(nq, g[1], _gate_matrix(g))
+        elif kind == "HALL":
+            m = np.ones((1, 1), dtype=np.complex128)
+            for _ in range(nq):
+                m = np.kron(m, HADAMARD)
+        elif kind == "ORACLE":
+            m = np.eye(size, dtype=np.complex128)
+            for x in marked:
+                m[x, x] = -1.0
+        elif kind == "INV":
+            e0 = np.zeros((size, 1))
+            e0[0, 0] = 1.0
+            m = 2.0 * (e0 @ e0.T) - np.eye(size)
+        else:
+            raise ValueError(kind)
+        u = m @ u
+    return u
+
+
+def grover_closed_form(nq, k, x):
+    """Amplitudes after k noise-free Grover iterations from HALL|0..0>.
+
+    Textbook rotation picture behind the paper's n_t (Sec. 5.1):
+    C_x = sin((2k+1) theta), C_{n != x} = cos((2k+1) theta) / sqrt(N - 1),
+    sin theta = N^(-1/2).
+    """
+    size = 1 << nq
+    theta = math.asin(1.0 / math.sqrt(size))
+    out = np.full(size, math.cos((2 * k + 1) * theta) / math.sqrt(size - 1), dtype=np.complex128)
+    out[x] = math.sin((2 * k + 1) * theta)
+    return out
+
+
+def diffusion_closed_form(psi):
+    """HALL . Inv . HALL psi = 2 <s|psi> |s> - psi, i.e. C~_n = 2 mean(C) - C_n.
+
+    Follows from Inv = 2|0><0| - I (Eq. inversion) and HALL|0..0> = |s>, the
+    uniform state (Eq. Shor1); valid at any n_q.
+    """
+    psi = np.asarray(psi, dtype=np.complex128)
+    return 2.0 * psi.mean() - psi

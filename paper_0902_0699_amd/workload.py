@@ -1,0 +1,112 @@
+"""Seeded synthetic inputs shaped like the paper's Grover workload.
+
+This module is shared by the tests, the benchmark and the CPU reference.  It
+draws random numbers and assembles gate lists; it holds none of the method's
+arithmetic (no gate is applied here).
+
+Draw order for one instance, from ``numpy.random.default_rng(seed)`` (PCG64):
+  x     = integers(0, N)          marked item (the Oracle's target, Sec. 5.1)
+  qhit  = integers(1, nq + 1)     qubit struck by the noise rotation (Sec. 6.3)
+  eloc  = integers(0, 5)          stage boundary of the noise rotation
+  alpha = uniform(0, 2 pi), beta = uniform(0, pi), gamma = 0 (Sec. 6.3 footnote)
+  psi   = standard_normal(N) + 1j * standard_normal(N), then normalised:
+          a Haar-random pure state, the paper's domain being normalised states.
+The batched workload first draws every n_q, then the instances in index order;
+instance 0 is the noise-free universe (its noise draws are made and ignored so
+that the stream does not depend on that rule).
+
+Gate lists use the tuple vocabulary of the paper's routines:
+  ("H", i_s), ("ONEOP", i_s, op2x2), ("HALL",), ("ORACLE",), ("INV",),
+  ("D2", i_s, alpha, beta, gamma); tuples apply left to right.
+"""
+
+import math
+
+import numpy as np
+
+CHUNK = 1 << 22
+NORM_BLOCK = 1 << 16
+
+# Workload sizes: the single-instance parity case, the paper's largest case
+# ("up to 30 qubits", Sec. 1), and the multiverse batch.
+NQ_SMALL = 20
+NQ_LARGE = 30
+BATCH_INSTANCES = 4096
+BATCH_NQ_MIN = 10
+BATCH_NQ_SPAN = 10
+
+SEEDS = {"small_fp64": 0, "large_fp64": 1, "large_fp32": 2, "batched": 3, "gradient": 4}
+
+
+def haar_state(rng, nq, chunk=CHUNK):
+    """Draw N real normals, then N imaginary normals, and normalise (chunked, same stream)."""
+    size = 1 << nq
+    psi = np.empty(size, dtype=np.complex128)
+    pairs = psi.view(np.float64).reshape(size, 2)
+    for part in (0, 1):
+        for start in range(0, size, chunk):
+            stop = min(size, start + chunk)
+            pairs[start:stop, part] = rng.standard_normal(stop - start)
+    # Norm from fixed-size blocks combined with fsum, so it does not depend on ``chunk``.
+    sums = []
+    for start in range(0, size, NORM_BLOCK):
+        seg = pairs[start:start + NORM_BLOCK]
+        sums.append(float(np.einsum("ij,ij->", seg, seg)))
+    psi /= math.sqrt(math.fsum(sums))
+    return psi
+
+
+def grover_gates(noise=None):
+    """Gate list of one Grover iteration, Oracle first (G = HALL.Inv.HALL.Oracle),
+    with an optional D2 inserted at stage boundary eloc."""
+    steps = [("ORACLE",), ("HALL",), ("INV",), ("HALL",)]
+    if noise is None:
+        return steps
+    qhit, eloc, alpha, beta, gamma = noise
+    return steps[:eloc] + [("D2", int(qhit), float(alpha), float(beta), float(gamma))] + steps[eloc:]
+
+
+def draw_instance(rng, nq, noisy=True, with_state=True):
+    """One noisy Grover instance: dict(nq, marked, noise, gates, psi)."""
+    size = 1 << nq
+    x = int(rng.integers(0, size))
+    qhit = int(rng.integers(1, nq + 1))
+    eloc = int(rng.integers(0, 5))
+    alpha = float(rng.uniform(0.0, 2.0 * math.pi))
+    beta = float(rng.uniform(0.0, math.pi))
+    noise = (qhit, eloc, alpha, beta, 0.0) if noisy else None
+    inst = {"nq": nq, "marked": [x], "noise": noise, "gates": grover_gates(noise)}
+    inst["psi"] = haar_state(rng, nq) if with_state else None
+    return inst
+
+
+def single_instance(seed, nq):
+    """The single-instance workloads: one noisy iteration at n_q qubits from ``seed``."""
+    return draw_instance(np.random.default_rng(seed), nq)
+
+
+def batch_sizes(rng, count=BATCH_INSTANCES, nq_min=BATCH_NQ_MIN, span=BATCH_NQ_SPAN):
+    """n_q,i = nq_min + floor(span * u), u ~ U[0,1): sizes log-uniform over 2^span."""
+    u = rng.random(count)
+    return [nq_min + int(math.floor(span * v)) for v in u]
+
+
+def batch_instances(seed, count=BATCH_INSTANCES, nq_min=BATCH_NQ_MIN, span=BATCH_NQ_SPAN):
+    """The multiverse batch: instance 0 noise-free, the others each with one D2."""
+    rng = np.random.default_rng(seed)
+    sizes = batch_sizes(rng, count, nq_min, span)
+    return [draw_instance(rng, nq, noisy=(i != 0)) for i, nq in enumerate(sizes)]
+
+
+def fd_subset(seed, inst, count=64):
+    """Inputs checked by central differences: the three angles, Re/Im of psi[x],
+    then count-5 further (index, part) components drawn from a stream seeded by
+    ``seed`` + 1000."""
+    rng = np.random.default_rng(seed + 1000)
+    size = 1 << inst["nq"]
+    x = inst["marked"][0]
+    comps = [("angle", 0), ("angle", 1), ("angle", 2), ("psi", (x, 0)), ("psi", (x, 1))]
+    idx = rng.integers(0, size, count - 5)
+    part = rng.integers(0, 2, count - 5)
+    comps += [("psi", (int(i), int(p))) for i, p in zip(idx, part)]
+    return comps

@@ -1,0 +1,206 @@
+/*
+ * libpaperkern -- state-vector gate sweeps for MI355X (gfx950).
+ *
+ * The library applies gate lists to n_q-qubit state vectors as described in
+ * Tabakin & Julia-Diaz, "QCMPI: a parallel environment for quantum computing":
+ *   - amplitudes C_n, n = 0 .. 2^n_q - 1, in standard order, n = sum_i q_i 2^(n_q-i)
+ *     (Sec. 2.2, Eq. staten): qubit 1 is the most significant bit;
+ *   - a one-qubit operator on qubit i_s updates every partner pair
+ *     (n_0, n_0 + 2^(n_q-i_s)) by its 2x2 matrix (Sec. 3, Eq. resmat1, routine OneOpA);
+ *   - HALL is the Hadamard on every qubit (Sec. 4.3, Eq. HALL);
+ *   - ORACLE flips the sign of the marked amplitudes (Sec. 5.1, Eq. oracle1);
+ *   - INV = 2|0..0><0..0| - I flips every amplitude except C_0 (Sec. 5.1, Eq. inversion);
+ *   - D2 is the Wigner rotation D^(1/2)(alpha, beta, gamma) used as one-qubit
+ *     noise (Sec. 6.3), read as R_z(alpha) R_y(beta) R_z(gamma) with
+ *     R_z(phi) = diag(e^{-i phi/2}, e^{+i phi/2}) and rows/columns m = +1/2 (|0>), -1/2 (|1>).
+ * The scalar read out is L = sum_{n in M} |C_n|^2 over the marked set M, the
+ * success probability of the Grover search (Sec. 5.1).
+ *
+ * Memory: every state-sized buffer (inputs, outputs, workspace) is allocated by
+ * the caller on the current HIP device and stays owned by the caller; a plan owns
+ * only its small gate/schedule tables and captured graphs.  States are arrays of
+ * interleaved complex numbers (re, im) in standard order: double2 for PK_FP64,
+ * float2 for PK_FP32.  All device pointers must be 16-byte aligned.
+ *
+ * Errors: every entry point returns PK_OK (0) or a negative code; nothing throws
+ * or aborts across this boundary.  pk_last_error() gives the text of the last
+ * failure on a plan (including the HIP error string for PK_EDEVICE).
+ * Streams: calls enqueue work on `stream` (a hipStream_t, NULL = null stream) and
+ * do not synchronise the host; a plan may be used by one stream at a time,
+ * distinct plans are independent.
+ */
+#ifndef PAPERKERN_H
+#define PAPERKERN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---------------------------------------------------------------- */
+#define PK_OK 0
+#define PK_EINVAL (-1)        /* an argument violates the documented contract          */
+#define PK_ENOMEM (-2)        /* host allocation failed or a buffer is too small        */
+#define PK_EDEVICE (-3)       /* a HIP call failed; see pk_last_error()                 */
+#define PK_EUNSUPPORTED (-4)  /* well-formed request outside what this build computes   */
+
+/* ---- precisions ------------------------------------------------------------------ */
+#define PK_FP64 0 /* complex128 storage, FP64 arithmetic                                  */
+#define PK_FP32 1 /* complex64 storage, FP32 arithmetic, FP64 final reductions            */
+
+/* ---- gate kinds (one pk_gate each; applied in list order, first gate first) ------- */
+#define PK_GATE_ONEOP 0  /* any 2x2 complex operator on qubit is1 (Sec. 3, Eq. resmat1)    */
+#define PK_GATE_H 1      /* Hadamard on qubit is1 (Sec. 3, Eq. NOTH)                       */
+#define PK_GATE_HALL 2   /* Hadamard on qubits 1..n_q (Sec. 4.3, Eq. HALL)                 */
+#define PK_GATE_ORACLE 3 /* C_x -> -C_x for every x of the marked set (Sec. 5.1)          */
+#define PK_GATE_INV 4    /* C_n -> -C_n for n != 0 (Sec. 5.1, Eq. inversion)              */
+#define PK_GATE_D2 5     /* D^(1/2)(alpha, beta, gamma) on qubit is1 (Sec. 6.3)           */
+
+/* ---- workspace queries ----------------------------------------------------------- */
+#define PK_OP_EVAL 0
+#define PK_OP_BACKWARD 1
+
+typedef struct pk_gate {
+    int32_t kind;     /* PK_GATE_*                                                        */
+    int32_t is1;      /* target qubit, 1..n_q (1 = most significant); ignored for
+                         HALL, ORACLE and INV                                             */
+    int32_t is2;      /* reserved for two-qubit gates; must be 0                          */
+    int32_t k;        /* reserved; must be 0                                              */
+    double op[8];     /* ONEOP only: row-major 2x2 complex, op[2*(2a+b)] = Re<a|Op|b>,
+                         op[2*(2a+b)+1] = Im<a|Op|b>; entries must be finite              */
+    double angle[3];  /* D2 only: alpha, beta, gamma (radians, finite)                    */
+} pk_gate;
+
+typedef struct pk_problem {
+    int32_t nq;             /* qubits: 1..30 for PK_FP64, 1..31 for PK_FP32             */
+    int32_t n_gates;        /* >= 0                                                       */
+    const pk_gate* gates;   /* host array of n_gates, copied by pk_create                 */
+    int64_t n_marked;       /* size of the marked set M, 0..64                            */
+    const int64_t* marked;  /* host array of distinct labels in [0, 2^nq); copied         */
+} pk_problem;
+
+typedef struct pk_plan pk_plan;
+
+/*
+ * pk_create -- validate n_inst problems and compile their pass schedules.
+ * Gates on distinct qubits commute and diagonal gates commute with each other;
+ * the compiler uses only those two facts to group gates into passes over the
+ * state (each pass reads and writes every amplitude once).  The schedule is host
+ * data; device tables are uploaded on first use.  Errors: PK_EINVAL for nq out of
+ * range, a qubit label outside 1..nq, nonzero is2/k, non-finite op or angle,
+ * duplicate or out-of-range marked labels, n_inst < 1, unknown prec or kind;
+ * PK_ENOMEM if host allocation fails.  On error *out is set to NULL.
+ */
+int pk_create(const pk_problem* probs, int32_t n_inst, int32_t prec, pk_plan** out);
+
+/*
+ * pk_set_tiling -- choose the pass kernel's tile: 2^tile_bits amplitudes per
+ * workgroup (fp64: 4..13, fp32: 4..14), of which the carrier_bits lowest state
+ * bits (0..6) are always part of a tile so that each memory run is
+ * 2^carrier_bits contiguous amplitudes; fuse = 0 turns fusion off (one sweep per
+ * gate, the plain form).  Re-compiles the schedule and drops captured graphs.
+ * Defaults: the largest tile, 4 carriers, fusion on.  PK_EINVAL when out of range.
+ */
+int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_t fuse);
+
+/* Number of passes (full sweeps over the state) one evaluation of instance `inst` makes. */
+int pk_plan_passes(const pk_plan* plan, int32_t inst, int32_t* passes);
+
+/*
+ * pk_plan_describe -- JSON text of the compiled schedule (passes, tile bits,
+ * stages and their gate lists).  Writes at most `cap` bytes including the NUL;
+ * *needed receives the full size.  Host-only; for tests and tools.
+ */
+int pk_plan_describe(const pk_plan* plan, char* buf, int64_t cap, int64_t* needed);
+
+/* Element offsets of each instance in a packed state buffer: offsets[n_inst + 1],
+ * offsets[i] = sum_{j<i} 2^nq_j; states of a batch lie back to back in that order. */
+int pk_plan_offsets(const pk_plan* plan, int64_t* offsets);
+
+/* Number of D2 gates over all instances (instance order, then gate order); the
+ * angle arrays below hold 3 doubles (alpha, beta, gamma) per D2 gate. */
+int pk_plan_n_angles(const pk_plan* plan, int64_t* n_d2);
+
+/*
+ * pk_workspace_bytes -- device workspace that op (PK_OP_EVAL or PK_OP_BACKWARD)
+ * needs.  EVAL needs small tables and partial sums; BACKWARD in addition one
+ * state-sized buffer for the recomputed state.  Contents need not be initialised.
+ */
+int pk_workspace_bytes(const pk_plan* plan, int32_t op, int64_t* bytes);
+
+/*
+ * pk_evaluate -- apply the gate list of a single-instance plan (n_inst == 1).
+ *   psi_in   device, 2^nq complex, read; may equal psi_out (in place, as the paper's psi)
+ *   psi_out  device, 2^nq complex, written
+ *   L_out    device double[1]: L = sum_{x in M} |C~_x|^2 (FP64 final combine)
+ *   norm_out device double[1] or NULL: sum_n |C~_n|^2 (diagnostic)
+ *   angles   device double[3 * n_d2] or NULL (NULL = the angles given to pk_create)
+ *   workspace device, >= pk_workspace_bytes(PK_OP_EVAL)
+ * The launches are captured once into a hipGraph per pointer set and replayed.
+ * Errors: PK_EINVAL (NULL/misaligned pointer, batched plan), PK_EDEVICE.
+ */
+int pk_evaluate(pk_plan* plan, const void* psi_in, void* psi_out, double* L_out, double* norm_out,
+                const double* angles, void* workspace, void* stream);
+
+/*
+ * pk_evaluate_batched -- evaluate every instance of the plan ("multiverses",
+ * Sec. 6.2) in one persistent launch replayed from a hipGraph.  States are
+ * packed at pk_plan_offsets(); L_out and norm_out (or NULL) hold n_inst doubles.
+ * Other arguments as pk_evaluate.
+ */
+int pk_evaluate_batched(pk_plan* plan, const void* psi_in, void* psi_out, double* L_out,
+                        double* norm_out, const double* angles, void* workspace, void* stream);
+
+/*
+ * pk_backward -- gradient of sum_i dL[i] * L_i by the adjoint method with
+ * recomputation: starting from psi_out (as produced by pk_evaluate with the same
+ * angles) the state is walked back through the adjoint gates while
+ * lambda = dL * P_M psi_out is propagated alongside; no intermediate state is stored.
+ *   psi_out     device, read
+ *   dL          device double[n_inst]
+ *   grad_psi_in device complex, written: Re = dL/dRe psi_in, Im = dL/dIm psi_in
+ *   grad_angles device double[3 * n_d2] or NULL, written (d/dalpha, d/dbeta, d/dgamma)
+ *   angles      device double[3 * n_d2] or NULL, as for pk_evaluate
+ *   workspace   device, >= pk_workspace_bytes(PK_OP_BACKWARD)
+ * Single-instance plans only.  PK_EUNSUPPORTED when an ONEOP gate is not
+ * unitary (its inverse is then not its adjoint and the state cannot be walked back).
+ */
+int pk_backward(pk_plan* plan, const void* psi_out, const double* dL, void* grad_psi_in,
+                double* grad_angles, const double* angles, void* workspace, void* stream);
+
+/*
+ * pk_pair_indices -- the partner pairs of qubit i_s (Sec. 2.2, Eqs. pair0/pair1):
+ * for r = first .. first+count-1, n0[r] is the r-th label (ascending) whose qubit
+ * i_s is 0 and n1[r] = n0[r] + 2^(nq - i_s).  Written to device arrays by a
+ * kernel using the library's index arithmetic.  PK_EINVAL when nq is outside
+ * 1..31, i_s outside 1..nq or the range exceeds 2^nq / 2 pairs.
+ */
+int pk_pair_indices(int32_t nq, int32_t i_s, int64_t first, int64_t count, int64_t* n0,
+                    int64_t* n1, void* stream);
+
+/*
+ * pk_time_passes -- measurement helper: runs one evaluation of a single-instance
+ * plan pass by pass with HIP events around every kernel on `stream`, waits for
+ * it, and writes the duration of each launch in milliseconds to ms[max_n]
+ * (the count written goes to *n).  Arguments as pk_evaluate.
+ */
+int pk_time_passes(pk_plan* plan, const void* psi_in, void* psi_out, double* L_out,
+                   const double* angles, void* workspace, void* stream, double* ms, int32_t max_n,
+                   int32_t* n);
+
+/* Frees plan-owned host and device tables and graphs.  NULL is a no-op. */
+void pk_destroy(pk_plan* plan);
+
+/* Static text for a return code. */
+const char* pk_strerror(int code);
+
+/* Text of the last error recorded on `plan` ("" when none); NULL plan gives the
+ * last error of pk_create/pk_pair_indices on this thread. */
+const char* pk_last_error(const pk_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAPERKERN_H */

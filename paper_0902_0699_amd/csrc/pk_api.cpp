@@ -1,0 +1,506 @@
+// The C-ABI of libpaperkern: argument checks, device tables, graph capture.
+#include <hip/hip_runtime.h>
+
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "paperkern.h"
+#include "pk_launch.h"
+#include "pk_plan.h"
+
+using namespace pk;
+
+namespace {
+
+thread_local std::string g_error;
+
+enum GraphSlot { G_EVAL = 0, G_BATCH = 1, G_BWD = 2, G_SLOTS = 3 };
+
+struct DevPlan {
+    Plan host;
+    void* exec[G_SLOTS] = {nullptr, nullptr, nullptr};
+    const void* key[G_SLOTS][8] = {};
+    hipStream_t cap = nullptr;
+    int n_cu = 0;
+};
+
+DevPlan* dp(pk_plan* p) { return reinterpret_cast<DevPlan*>(p); }
+const DevPlan* dp(const pk_plan* p) { return reinterpret_cast<const DevPlan*>(p); }
+
+int fail(DevPlan* d, int code, const std::string& msg) {
+    if (d)
+        d->host.last_error = msg;
+    else
+        g_error = msg;
+    return code;
+}
+
+int hip_fail(DevPlan* d, hipError_t e, const char* where) {
+    return fail(d, PK_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool valid(const pk_plan* p) { return p && dp(p)->host.magic == 0x504b504cu; }
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+void drop_graphs(DevPlan* d) {
+    for (int s = 0; s < G_SLOTS; ++s) {
+        if (d->exec[s]) hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(d->exec[s]));
+        d->exec[s] = nullptr;
+        std::memset(d->key[s], 0, sizeof d->key[s]);
+    }
+}
+
+void drop_device(DevPlan* d) {
+    drop_graphs(d);
+    if (d->host.d_tables) hipFree(d->host.d_tables);
+    d->host.d_tables = nullptr;
+    d->host.device = -1;
+}
+
+template <typename T>
+void put(std::vector<char>& buf, size_t off, const std::vector<T>& v) {
+    if (!v.empty()) std::memcpy(buf.data() + off, v.data(), v.size() * sizeof(T));
+}
+
+int ensure_device(DevPlan* d) {
+    Plan& P = d->host;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(d, e, "hipGetDevice");
+    if (P.d_tables) {
+        if (dev != P.device) return fail(d, PK_EINVAL, "plan was first used on another device");
+        return PK_OK;
+    }
+    TableLayout t = table_layout(&P);
+    std::vector<char> buf(t.total, 0);
+    put(buf, t.passes, P.passes);
+    put(buf, t.stages, P.stages);
+    put(buf, t.ops, P.ops);
+    put(buf, t.flips, P.flips);
+    put(buf, t.mats, P.static_mats);
+    put(buf, t.mats + P.static_mats.size() * sizeof(double), P.default_angles);
+    put(buf, t.idesc, P.idesc);
+    put(buf, t.order, P.order);
+    std::vector<Reduction> r = eval_reductions(&P);
+    std::vector<Reduction> rb = backward_reductions(&P);
+    r.insert(r.end(), rb.begin(), rb.end());
+    put(buf, t.red, r);
+    void* ptr = nullptr;
+    e = hipMalloc(&ptr, t.total);
+    if (e != hipSuccess) return hip_fail(d, e, "hipMalloc(plan tables)");
+    e = hipMemcpy(ptr, buf.data(), t.total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(ptr);
+        return hip_fail(d, e, "hipMemcpy(plan tables)");
+    }
+    P.d_tables = ptr;
+    P.d_tables_bytes = t.total;
+    P.device = dev;
+    if (!d->cap) {
+        e = hipStreamCreateWithFlags(&d->cap, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(d, e, "hipStreamCreate");
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) d->n_cu = prop.multiProcessorCount;
+    if (d->n_cu <= 0) d->n_cu = 256;
+    return PK_OK;
+}
+
+template <typename T>
+T* at(void* base, size_t off) {
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
+}
+
+struct EvalArgs {
+    const void* psi_in;
+    void* psi_out;
+    double* L_out;
+    double* norm_out;
+    const double* angles;
+    void* ws;
+};
+
+PassLaunch base_launch(DevPlan* d, void* ws, int op) {
+    Plan& P = d->host;
+    TableLayout t = table_layout(&P);
+    WsLayout w = workspace_layout(&P, op);
+    PassLaunch L{};
+    L.passes = at<Pass>(P.d_tables, t.passes);
+    L.stages = at<Stage>(P.d_tables, t.stages);
+    L.ops = at<Op>(P.d_tables, t.ops);
+    L.flips = at<Flip>(P.d_tables, t.flips);
+    L.mats = at<double>(ws, w.mats);
+    L.partials = at<double>(ws, w.partials);
+    L.reads = at<double>(ws, w.reads);
+    L.gpart = at<double>(ws, w.gpart);
+    L.fp64 = P.prec == PK_FP64;
+    return L;
+}
+
+const double* angle_src(DevPlan* d, const double* angles) {
+    if (angles) return angles;
+    TableLayout t = table_layout(&d->host);
+    return at<double>(d->host.d_tables, t.mats + d->host.static_mats.size() * sizeof(double));
+}
+
+hipError_t enqueue_prep(DevPlan* d, void* ws, const double* angles, int op, int n_counters, hipStream_t st) {
+    Plan& P = d->host;
+    TableLayout t = table_layout(&P);
+    WsLayout w = workspace_layout(&P, op);
+    return launch_prep(at<double>(ws, w.mats), at<double>(P.d_tables, t.mats), P.n_static, angle_src(d, angles),
+                       P.n_d2, at<unsigned int>(ws, w.counters), n_counters, st);
+}
+
+// Evaluation of a single-instance plan: prep, every forward pass, final combine.
+hipError_t enqueue_eval(DevPlan* d, const EvalArgs& a, hipStream_t st, std::vector<hipEvent_t>* ev) {
+    Plan& P = d->host;
+    hipError_t e = enqueue_prep(d, a.ws, a.angles, PK_OP_EVAL, 0, st);
+    if (e != hipSuccess) return e;
+    PassLaunch L = base_launch(d, a.ws, PK_OP_EVAL);
+    L.src0 = a.psi_in;
+    L.dst0 = a.psi_out;
+    L.want_norm = a.norm_out != nullptr;
+    L.nv = 1;
+    const Instance& in = P.inst[0];
+    for (size_t p = 0; p < in.fwd.size(); ++p) {
+        L.pass = (int)p;
+        L.kmax = in.fwd[p].kmax;
+        L.ntiles = in.fwd[p].ntiles;
+        if (ev) hipEventRecord((*ev)[2 * p], st);
+        e = launch_pass(L, st);
+        if (ev) hipEventRecord((*ev)[2 * p + 1], st);
+        if (e != hipSuccess) return e;
+    }
+    TableLayout t = table_layout(&P);
+    return launch_reduce(at<Reduction>(P.d_tables, t.red), 2 * (int)P.inst.size(), static_cast<double*>(a.ws),
+                         a.L_out, a.norm_out, nullptr, st);
+}
+
+int batched_kmax(const Plan& P) {
+    int km = 10;
+    for (const auto& in : P.inst)
+        for (const auto& hp : in.fwd) km = hp.kmax > km ? hp.kmax : km;
+    return km;
+}
+
+hipError_t enqueue_batched(DevPlan* d, const EvalArgs& a, hipStream_t st) {
+    Plan& P = d->host;
+    hipError_t e = enqueue_prep(d, a.ws, a.angles, PK_OP_EVAL, 1, st);
+    if (e != hipSuccess) return e;
+    PassLaunch L = base_launch(d, a.ws, PK_OP_EVAL);
+    L.src0 = a.psi_in;
+    L.dst0 = a.psi_out;
+    L.want_norm = a.norm_out != nullptr;
+    L.nv = 1;
+    L.kmax = batched_kmax(P);
+    TableLayout t = table_layout(&P);
+    WsLayout w = workspace_layout(&P, PK_OP_EVAL);
+    BatchLaunch B{};
+    B.idesc = at<InstDesc>(P.d_tables, t.idesc);
+    B.order = at<int32_t>(P.d_tables, t.order);
+    B.n_inst = (int32_t)P.inst.size();
+    B.queue = at<unsigned int>(a.ws, w.counters);
+    B.L_out = a.L_out;
+    B.norm_out = a.norm_out;
+    const bool fp64 = P.prec == PK_FP64;
+    const int lds_per_wg = (1 << L.kmax) * (fp64 ? 16 : 8);
+    int per_cu = (160 * 1024) / lds_per_wg;
+    if (per_cu < 1) per_cu = 1;
+    if (per_cu > 8) per_cu = 8;
+    long grid = (long)d->n_cu * per_cu;
+    if (grid > (long)P.inst.size()) grid = (long)P.inst.size();
+    B.grid = (unsigned)grid;
+    return launch_batched(L, B, st);
+}
+
+struct BwdArgs {
+    const void* psi_out;
+    const double* dL;
+    void* grad_psi;
+    double* grad_angles;
+    const double* angles;
+    void* ws;
+};
+
+hipError_t enqueue_backward(DevPlan* d, const BwdArgs& a, hipStream_t st) {
+    Plan& P = d->host;
+    hipError_t e = enqueue_prep(d, a.ws, a.angles, PK_OP_BACKWARD, 0, st);
+    if (e != hipSuccess) return e;
+    WsLayout w = workspace_layout(&P, PK_OP_BACKWARD);
+    PassLaunch L = base_launch(d, a.ws, PK_OP_BACKWARD);
+    L.src0 = a.psi_out;
+    L.dst0 = at<void>(a.ws, w.state);
+    L.dst1 = a.grad_psi;
+    L.dL = a.dL;
+    L.want_norm = 0;
+    L.nv = 2;
+    const Instance& in = P.inst[0];
+    for (size_t p = 0; p < in.bwd.size(); ++p) {
+        L.pass = P.n_fwd_passes + (int)p;
+        L.kmax = in.bwd[p].kmax;
+        L.ntiles = in.bwd[p].ntiles;
+        e = launch_pass(L, st);
+        if (e != hipSuccess) return e;
+    }
+    if (!a.grad_angles || P.d2_grad.empty()) return hipSuccess;
+    TableLayout t = table_layout(&P);
+    return launch_reduce(at<Reduction>(P.d_tables, t.red) + 2 * P.inst.size(), 3 * (int)P.d2_grad.size(),
+                         static_cast<double*>(a.ws), nullptr, nullptr, a.grad_angles, st);
+}
+
+bool no_graph() {
+    const char* v = std::getenv("PK_NO_GRAPH");
+    return v && v[0] && v[0] != '0';
+}
+
+// Replays the cached graph for `slot` when the pointer set matches, else
+// captures `fn` on the plan's capture stream and instantiates it.
+template <typename Fn>
+int run_graphed(DevPlan* d, int slot, const void* const (&key)[8], hipStream_t st, Fn fn) {
+    if (no_graph()) {
+        hipError_t e = fn(st);
+        return e == hipSuccess ? PK_OK : hip_fail(d, e, "kernel launch");
+    }
+    if (!d->exec[slot] || std::memcmp(d->key[slot], key, sizeof key) != 0) {
+        if (d->exec[slot]) hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(d->exec[slot]));
+        d->exec[slot] = nullptr;
+        hipError_t e = hipStreamBeginCapture(d->cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(d, e, "hipStreamBeginCapture");
+        hipError_t le = fn(d->cap);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(d->cap, &g);
+        if (le != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return hip_fail(d, le, "kernel launch (capture)");
+        }
+        if (e != hipSuccess) return hip_fail(d, e, "hipStreamEndCapture");
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(d, e, "hipGraphInstantiate");
+        d->exec[slot] = ex;
+        std::memcpy(d->key[slot], key, sizeof key);
+    }
+    hipError_t e = hipGraphLaunch(reinterpret_cast<hipGraphExec_t>(d->exec[slot]), st);
+    return e == hipSuccess ? PK_OK : hip_fail(d, e, "hipGraphLaunch");
+}
+
+int check_eval_args(DevPlan* d, const void* psi_in, void* psi_out, double* L_out, double* norm_out,
+                    const double* angles, void* ws) {
+    if (!psi_in || !psi_out || !L_out || !ws) return fail(d, PK_EINVAL, "NULL pointer argument");
+    if (!aligned(psi_in, 16) || !aligned(psi_out, 16) || !aligned(ws, 256) || !aligned(L_out, 8) ||
+        (norm_out && !aligned(norm_out, 8)) || (angles && !aligned(angles, 8)))
+        return fail(d, PK_EINVAL, "misaligned pointer (states 16 B, workspace 256 B, doubles 8 B)");
+    return PK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pk_create(const pk_problem* probs, int32_t n_inst, int32_t prec, pk_plan** out) {
+    if (!out) return fail(nullptr, PK_EINVAL, "out is NULL");
+    *out = nullptr;
+    DevPlan* d = new (std::nothrow) DevPlan();
+    if (!d) return fail(nullptr, PK_ENOMEM, "out of host memory");
+    std::string err;
+    int rc;
+    try {
+        rc = compile_plan(&d->host, probs, n_inst, prec, &err);
+    } catch (const std::bad_alloc&) {
+        rc = PK_ENOMEM;
+        err = "out of host memory";
+    } catch (...) {
+        rc = PK_EINVAL;
+        err = "plan compilation failed";
+    }
+    if (rc != PK_OK) {
+        delete d;
+        return fail(nullptr, rc, err);
+    }
+    *out = reinterpret_cast<pk_plan*>(d);
+    return PK_OK;
+}
+
+int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_t fuse) {
+    if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");
+    DevPlan* d = dp(plan);
+    const int kmax = d->host.prec == PK_FP64 ? 13 : 14;
+    if (tile_bits < 4 || tile_bits > kmax) return fail(d, PK_EINVAL, "tile_bits out of range");
+    if (carrier_bits < 0 || carrier_bits > 6 || carrier_bits > tile_bits - 1)
+        return fail(d, PK_EINVAL, "carrier_bits out of range");
+    if (fuse != 0 && fuse != 1) return fail(d, PK_EINVAL, "fuse must be 0 or 1");
+    d->host.tiling = Tiling{tile_bits, carrier_bits, fuse};
+    drop_device(d);
+    std::string err;
+    try {
+        int rc = recompile(&d->host, &err);
+        if (rc != PK_OK) return fail(d, rc, err);
+    } catch (const std::bad_alloc&) {
+        return fail(d, PK_ENOMEM, "out of host memory");
+    }
+    return PK_OK;
+}
+
+int pk_plan_passes(const pk_plan* plan, int32_t inst, int32_t* passes) {
+    if (!valid(plan) || !passes) return fail(nullptr, PK_EINVAL, "invalid argument");
+    const Plan& P = dp(plan)->host;
+    if (inst < 0 || inst >= (int)P.inst.size()) return PK_EINVAL;
+    *passes = (int32_t)P.inst[inst].fwd.size();
+    return PK_OK;
+}
+
+int pk_plan_describe(const pk_plan* plan, char* buf, int64_t cap, int64_t* needed) {
+    if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");
+    std::string s = describe(&dp(plan)->host);
+    if (needed) *needed = (int64_t)s.size() + 1;
+    if (buf && cap > 0) {
+        size_t n = s.size() < (size_t)(cap - 1) ? s.size() : (size_t)(cap - 1);
+        std::memcpy(buf, s.data(), n);
+        buf[n] = 0;
+    }
+    return PK_OK;
+}
+
+int pk_plan_offsets(const pk_plan* plan, int64_t* offsets) {
+    if (!valid(plan) || !offsets) return fail(nullptr, PK_EINVAL, "invalid argument");
+    const Plan& P = dp(plan)->host;
+    for (size_t i = 0; i < P.inst.size(); ++i) offsets[i] = P.inst[i].off;
+    offsets[P.inst.size()] = P.total_elems;
+    return PK_OK;
+}
+
+int pk_plan_n_angles(const pk_plan* plan, int64_t* n_d2) {
+    if (!valid(plan) || !n_d2) return fail(nullptr, PK_EINVAL, "invalid argument");
+    *n_d2 = dp(plan)->host.n_d2;
+    return PK_OK;
+}
+
+int pk_workspace_bytes(const pk_plan* plan, int32_t op, int64_t* bytes) {
+    if (!valid(plan) || !bytes) return fail(nullptr, PK_EINVAL, "invalid argument");
+    if (op != PK_OP_EVAL && op != PK_OP_BACKWARD) return fail(nullptr, PK_EINVAL, "unknown op");
+    *bytes = (int64_t)workspace_layout(&dp(plan)->host, op).total;
+    return PK_OK;
+}
+
+int pk_evaluate(pk_plan* plan, const void* psi_in, void* psi_out, double* L_out, double* norm_out,
+                const double* angles, void* workspace, void* stream) {
+    if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");
+    DevPlan* d = dp(plan);
+    if (d->host.inst.size() != 1) return fail(d, PK_EINVAL, "pk_evaluate needs a single-instance plan");
+    int rc = check_eval_args(d, psi_in, psi_out, L_out, norm_out, angles, workspace);
+    if (rc != PK_OK) return rc;
+    rc = ensure_device(d);
+    if (rc != PK_OK) return rc;
+    EvalArgs a{psi_in, psi_out, L_out, norm_out, angles, workspace};
+    const void* const key[8] = {psi_in, psi_out, L_out, norm_out, angles, workspace, nullptr, nullptr};
+    return run_graphed(d, G_EVAL, key, static_cast<hipStream_t>(stream),
+                       [&](hipStream_t s) { return enqueue_eval(d, a, s, nullptr); });
+}
+
+int pk_evaluate_batched(pk_plan* plan, const void* psi_in, void* psi_out, double* L_out, double* norm_out,
+                        const double* angles, void* workspace, void* stream) {
+    if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");
+    DevPlan* d = dp(plan);
+    int rc = check_eval_args(d, psi_in, psi_out, L_out, norm_out, angles, workspace);
+    if (rc != PK_OK) return rc;
+    rc = ensure_device(d);
+    if (rc != PK_OK) return rc;
+    EvalArgs a{psi_in, psi_out, L_out, norm_out, angles, workspace};
+    const void* const key[8] = {psi_in, psi_out, L_out, norm_out, angles, workspace, nullptr, nullptr};
+    return run_graphed(d, G_BATCH, key, static_cast<hipStream_t>(stream),
+                       [&](hipStream_t s) { return enqueue_batched(d, a, s); });
+}
+
+int pk_backward(pk_plan* plan, const void* psi_out, const double* dL, void* grad_psi_in, double* grad_angles,
+                const double* angles, void* workspace, void* stream) {
+    if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");
+    DevPlan* d = dp(plan);
+    if (d->host.inst.size() != 1) return fail(d, PK_EINVAL, "pk_backward needs a single-instance plan");
+    if (!d->host.backward_ok)
+        return fail(d, PK_EUNSUPPORTED, "a ONEOP gate is not unitary: its adjoint is not its inverse");
+    if (!psi_out || !dL || !grad_psi_in || !workspace) return fail(d, PK_EINVAL, "NULL pointer argument");
+    if (!aligned(psi_out, 16) || !aligned(grad_psi_in, 16) || !aligned(workspace, 256) || !aligned(dL, 8) ||
+        (grad_angles && !aligned(grad_angles, 8)) || (angles && !aligned(angles, 8)))
+        return fail(d, PK_EINVAL, "misaligned pointer");
+    int rc = ensure_device(d);
+    if (rc != PK_OK) return rc;
+    BwdArgs a{psi_out, dL, grad_psi_in, grad_angles, angles, workspace};
+    const void* const key[8] = {psi_out, dL, grad_psi_in, grad_angles, angles, workspace, nullptr, nullptr};
+    return run_graphed(d, G_BWD, key, static_cast<hipStream_t>(stream),
+                       [&](hipStream_t s) { return enqueue_backward(d, a, s); });
+}
+
+int pk_pair_indices(int32_t nq, int32_t i_s, int64_t first, int64_t count, int64_t* n0, int64_t* n1,
+                    void* stream) {
+    if (nq < 1 || nq > 31) return fail(nullptr, PK_EINVAL, "nq out of 1..31");
+    if (i_s < 1 || i_s > nq) return fail(nullptr, PK_EINVAL, "i_s out of 1..nq");
+    const int64_t npairs = (int64_t)1 << (nq - 1);
+    if (first < 0 || count < 0 || first + count > npairs) return fail(nullptr, PK_EINVAL, "pair range out of bounds");
+    if (count > 0 && (!n0 || !n1)) return fail(nullptr, PK_EINVAL, "NULL output");
+    hipError_t e = launch_pairs(nq, i_s, first, count, n0, n1, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? PK_OK : hip_fail(nullptr, e, "pair_index_kernel");
+}
+
+int pk_time_passes(pk_plan* plan, const void* psi_in, void* psi_out, double* L_out, const double* angles,
+                   void* workspace, void* stream, double* ms, int32_t max_n, int32_t* n) {
+    if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");
+    DevPlan* d = dp(plan);
+    if (d->host.inst.size() != 1) return fail(d, PK_EINVAL, "single-instance plans only");
+    if (!ms || !n || max_n < 0) return fail(d, PK_EINVAL, "NULL output");
+    int rc = check_eval_args(d, psi_in, psi_out, L_out, nullptr, angles, workspace);
+    if (rc != PK_OK) return rc;
+    rc = ensure_device(d);
+    if (rc != PK_OK) return rc;
+    const size_t np = d->host.inst[0].fwd.size();
+    std::vector<hipEvent_t> ev(2 * np, nullptr);
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) return fail(d, PK_EDEVICE, "hipEventCreate");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    EvalArgs a{psi_in, psi_out, L_out, nullptr, angles, workspace};
+    hipError_t e = enqueue_eval(d, a, st, &ev);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    int w = 0;
+    if (e == hipSuccess) {
+        for (size_t p = 0; p < np && w < max_n; ++p) {
+            float t = 0.f;
+            hipEventElapsedTime(&t, ev[2 * p], ev[2 * p + 1]);
+            ms[w++] = t;
+        }
+    }
+    for (auto& x : ev) hipEventDestroy(x);
+    *n = w;
+    return e == hipSuccess ? PK_OK : hip_fail(d, e, "pk_time_passes");
+}
+
+void pk_destroy(pk_plan* plan) {
+    if (!valid(plan)) return;
+    DevPlan* d = dp(plan);
+    drop_device(d);
+    if (d->cap) hipStreamDestroy(d->cap);
+    d->host.magic = 0;
+    delete d;
+}
+
+const char* pk_strerror(int code) {
+    switch (code) {
+    case PK_OK: return "success";
+    case PK_EINVAL: return "invalid argument";
+    case PK_ENOMEM: return "out of memory";
+    case PK_EDEVICE: return "HIP device error";
+    case PK_EUNSUPPORTED: return "unsupported request";
+    default: return "unknown error code";
+    }
+}
+
+const char* pk_last_error(const pk_plan* plan) {
+    if (!plan) return g_error.c_str();
+    if (!valid(plan)) return "invalid plan";
+    return dp(plan)->host.last_error.c_str();
+}
+
+}  // extern "C"

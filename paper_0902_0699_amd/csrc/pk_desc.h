@@ -1,0 +1,106 @@
+// Schedule tables shared by the host plan compiler and the device kernels.
+//
+// A plan lowers a gate list to passes.  One pass streams the whole state
+// once: the state is cut into tiles of 2^k amplitudes whose labels differ only
+// in k chosen bit positions (the tile bits, always including the lowest
+// "carrier" bits so that every memory run is contiguous), every tile is loaded
+// into one workgroup, the pass's gates are applied, and the tile is written
+// back.  Inside a tile, each thread holds 16 amplitudes in registers whose
+// local labels differ in 4 "register bits"; a stage applies the gates on those
+// 4 bits as butterflies in registers, and an LDS exchange moves the tile to the
+// next stage's register bits.  This is the pair update of Sec. 3 (Eq. resmat1)
+// applied to all partner pairs of a qubit at once, grouped so that the state
+// is read from HBM once per group of qubits instead of once per gate.
+#pragma once
+#include <stdint.h>
+
+namespace pk {
+
+constexpr int kRegBits = 4;          // register bits per stage
+constexpr int kRegs = 1 << kRegBits; // amplitudes per thread
+constexpr int kMaxTileBits = 14;     // fp32 limit (fp64: 13), LDS = 2^k * element
+constexpr int kMaxQubits = 31;
+constexpr int kMaxNV = 2;            // vectors carried by a pass: psi, or psi and lambda
+
+enum OpKind : int16_t {
+    OP_H = 0,      // unnormalised Hadamard butterfly (x+y, x-y) on register bit a
+    OP_MAT = 1,    // 2x2 complex matrix mats[arg] on register bit a
+    OP_FLIP = 2,   // negate the amplitude flips[arg] (Oracle items, Inv's C_0 fix)
+    OP_SCALE = 3,  // multiply every amplitude by the pass scale
+    OP_READ = 4,   // reads[flips[arg].slot] = |C|^2 of the amplitude flips[arg]
+    OP_SEED = 5,   // lambda = dL * psi at the amplitude flips[arg] (backward start)
+    OP_D2BWD = 6,  // backward D2: psi <- D^H psi, grad += Re<lambda|dD|psi>, lambda <- D^H lambda
+};
+
+struct Op {
+    int16_t kind;
+    int8_t a;      // register bit 0..3 for OP_H / OP_MAT / OP_D2BWD
+    int8_t pad;
+    int32_t arg;   // matrix index (OP_MAT, OP_D2BWD: first of its five), flip index (FLIP/READ/SEED)
+    float gscale;  // OP_D2BWD: 1/s^2 for the deferred scale s carried at that point
+    int32_t gslot; // OP_D2BWD: base of this gate's gradient partials
+};
+
+struct Stage {
+    int8_t rb[kRegBits];  // local tile bit held by register bit a (-1 when the tile has < 4 bits)
+    int8_t rbs[kRegBits]; // the same bits sorted ascending (-1 entries last)
+    int32_t op_begin;
+    int32_t op_count;
+};
+
+// One amplitude addressed by (tile, local label) in a given pass.
+struct Flip {
+    int64_t tile;
+    int32_t j;
+    int32_t slot; // READ: readout slot; SEED: instance index
+};
+
+enum PassFlags : int32_t {
+    PASS_FIRST = 1,    // read from the input buffers
+    PASS_LAST = 2,     // final pass of the instance
+    PASS_NORM = 4,     // accumulate sum |C|^2 partials (when norm requested)
+    PASS_SKIP_V0 = 8,  // do not store vector 0 (backward: the recovered psi_in is not needed)
+    PASS_SEED_V1 = 16, // vector 1 is not read: it starts as zero and is seeded (backward start)
+};
+
+struct Pass {
+    int32_t k;           // tile bits
+    int32_t nfree;       // nq - k free bits (tile id bits)
+    int32_t nstages;
+    int32_t stage_begin;
+    int64_t ntiles;      // 2^nfree
+    int64_t state_off;   // element offset of the instance in the packed buffer
+    int32_t flags;
+    int32_t inst;
+    double scale;        // applied by OP_SCALE
+    int32_t part_base;   // norm partials: part_base + tile
+    int32_t kmax;        // kernel instance (workgroup = 2^(kmax-4) threads)
+    int32_t ntrun;       // runs of consecutive tile bits
+    int32_t nfrun;       // runs of consecutive free bits
+    int8_t tpos[16];     // global bit position of local tile bit l
+    // A run (src, len, dst) moves bits src..src+len-1 of a label to dst..dst+len-1.
+    int8_t trun[16][3];  // local tile label -> state label
+    int8_t frun[16][3];  // tile index -> state label
+};
+
+// Per-instance entry of a batched launch: one workgroup runs all passes of
+// one instance, so no two workgroups ever depend on each other.
+struct InstDesc {
+    int32_t first_pass;
+    int32_t npass;
+    int32_t read_base;
+    int32_t nmarked;
+    int64_t part_base;
+    int64_t ntiles_last;
+};
+
+// One output of the final FP64 combine: out[index] = sum of count doubles at
+// workspace + src (in doubles), summed in a fixed order.
+struct Reduction {
+    int32_t target;  // 0: L, 1: norm, 2: angle gradient
+    int32_t index;
+    int64_t src;
+    int64_t count;
+};
+
+} // namespace pk

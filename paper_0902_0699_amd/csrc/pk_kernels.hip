@@ -1,0 +1,679 @@
+// Device kernels for gfx950: the fused tile pass, the batched multiverse
+// launch, the table preparation and the final FP64 combine.
+//
+// One workgroup owns one tile of 2^k amplitudes (labels that differ only in the
+// pass's k tile bits).  Thread t holds 16 amplitudes in registers; in stage s
+// their local labels are jt(s) | roff_s(i), i = 0..15, where register bit a of
+// i sits on local tile bit rb[a] and the thread index fills the other bits in
+// ascending order.  A one-qubit gate on a register bit is then a butterfly over
+// register pairs (i, i | 2^a): the 2x2 pair update of Sec. 3 (Eq. resmat1) on
+// every partner pair of the tile at once.  Between stages the tile goes through
+// LDS to bring the next four bits into registers.  The first and last stages
+// keep the lowest tile bits on the lane index, so HBM is read and written in
+// contiguous runs.
+#include <hip/hip_runtime.h>
+
+#include "pk_desc.h"
+#include "pk_launch.h"
+
+namespace pk {
+
+template <typename R>
+struct Cplx;
+template <>
+struct Cplx<double> {
+    using T = double2;
+};
+template <>
+struct Cplx<float> {
+    using T = float2;
+};
+
+struct KArgs {
+    const Pass* passes;
+    const Stage* stages;
+    const Op* ops;
+    const Flip* flips;
+    const double* mats;
+    const void* src0;  // vector 0 input of the first pass
+    void* dst0;        // vector 0 output (and input of later passes)
+    void* dst1;        // vector 1 (lambda) in/out, backward only
+    double* partials;
+    double* reads;
+    double* gpart;
+    const double* dL;
+    int32_t pass;
+    int32_t want_norm;
+};
+
+// LDS bank swizzle on 16-byte slots: XOR of the label's higher 3-bit groups
+// into its low 3 bits.  Linear over XOR, so phys(a ^ b) = phys(a) ^ phys(b).
+__device__ __forceinline__ unsigned phys(unsigned j) {
+    return j ^ (((j >> 3) ^ (j >> 6) ^ (j >> 9) ^ (j >> 12)) & 7u);
+}
+
+// Thread index spread over the local bits that are not register bits.
+__device__ __forceinline__ unsigned thread_label(unsigned t, const Stage* S, int nrb) {
+    for (int q = 0; q < nrb; ++q) {
+        const int p = S->rbs[q];
+        t = ((t >> p) << (p + 1)) | (t & ((1u << p) - 1u));
+    }
+    return t;
+}
+
+// Layout of one stage: per-thread label base and the uniform offsets of the
+// four register bits (as labels, as LDS slots and as state offsets).
+struct Layout {
+    unsigned jt;     // thread's label base
+    unsigned pj;     // phys(jt)
+    unsigned r[4];   // 1 << rb[a] (0 for missing bits)
+    unsigned p[4];   // phys(1 << rb[a])
+};
+
+__device__ __forceinline__ Layout make_layout(const Stage* S, int nrb, unsigned tid) {
+    Layout L;
+    L.jt = thread_label(tid, S, nrb);
+    L.pj = phys(L.jt);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        L.r[a] = a < nrb ? (1u << S->rb[a]) : 0u;
+        L.p[a] = phys(L.r[a]);
+    }
+    return L;
+}
+
+__device__ __forceinline__ unsigned roff(const Layout& L, int i) {
+    return ((i & 1) ? L.r[0] : 0u) | ((i & 2) ? L.r[1] : 0u) | ((i & 4) ? L.r[2] : 0u) |
+           ((i & 8) ? L.r[3] : 0u);
+}
+__device__ __forceinline__ unsigned poff(const Layout& L, int i) {
+    return ((i & 1) ? L.p[0] : 0u) ^ ((i & 2) ? L.p[1] : 0u) ^ ((i & 4) ? L.p[2] : 0u) ^
+           ((i & 8) ? L.p[3] : 0u);
+}
+
+// State offsets of a stage used for HBM access: thread part and register parts.
+struct GOff {
+    int64_t gt;
+    int64_t g[4];
+};
+
+// Moves the bits of `x` along the runs (src, len, dst).
+__device__ __forceinline__ int64_t deposit(int64_t x, const int8_t (*run)[3], int nrun) {
+    int64_t r = 0;
+    for (int q = 0; q < nrun; ++q) {
+        const int src = run[q][0], len = run[q][1], dst = run[q][2];
+        r |= ((x >> src) & (((int64_t)1 << len) - 1)) << dst;
+    }
+    return r;
+}
+
+__device__ __forceinline__ GOff make_goff(const Pass* P, const Stage* S, const Layout& L, int nrb) {
+    GOff G;
+    G.gt = deposit((int64_t)L.jt, P->trun, P->ntrun);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) G.g[a] = a < nrb ? ((int64_t)1 << P->tpos[S->rb[a]]) : 0;
+    return G;
+}
+
+__device__ __forceinline__ int64_t goff(const GOff& G, int i) {
+    return ((i & 1) ? G.g[0] : 0) + ((i & 2) ? G.g[1] : 0) + ((i & 4) ? G.g[2] : 0) +
+           ((i & 8) ? G.g[3] : 0);
+}
+
+// ---------------------------------------------------------------------------- gate bodies
+
+template <int A, int NV, typename T>
+__device__ __forceinline__ void op_h(T (&v)[NV][16]) {
+#pragma unroll
+    for (int n = 0; n < NV; ++n)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (i & (1 << A)) continue;
+            const int j = i | (1 << A);
+            T x = v[n][i], y = v[n][j];
+            v[n][i].x = x.x + y.x;
+            v[n][i].y = x.y + y.y;
+            v[n][j].x = x.x - y.x;
+            v[n][j].y = x.y - y.y;
+        }
+}
+
+// (x, y) <- M (x, y) with M row-major complex [m0+i m1, m2+i m3; m4+i m5, m6+i m7]
+template <typename T, typename R>
+__device__ __forceinline__ void pair_mat(T& x, T& y, const R (&m)[8]) {
+    const T a = x, b = y;
+    x.x = m[0] * a.x - m[1] * a.y + m[2] * b.x - m[3] * b.y;
+    x.y = m[0] * a.y + m[1] * a.x + m[2] * b.y + m[3] * b.x;
+    y.x = m[4] * a.x - m[5] * a.y + m[6] * b.x - m[7] * b.y;
+    y.y = m[4] * a.y + m[5] * a.x + m[6] * b.y + m[7] * b.x;
+}
+
+template <int A, int NV, typename T, typename R>
+__device__ __forceinline__ void op_m(T (&v)[NV][16], const R (&m)[8]) {
+#pragma unroll
+    for (int n = 0; n < NV; ++n)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (i & (1 << A)) continue;
+            pair_mat(v[n][i], v[n][i | (1 << A)], m);
+        }
+}
+
+// Backward step through a D2 gate: psi <- D^H psi; then for every angle,
+// g += Re( conj(lambda) . (dD/dtheta) psi ); then lambda <- D^H lambda.
+// One derivative matrix at a time keeps the register footprint small.
+template <int A, int NV, typename T, typename R>
+__device__ __forceinline__ void op_d2bwd(T (&v)[NV][16], const R (&mh)[8], const double* dmats,
+                                         double (&g)[3]) {
+    if constexpr (NV == 2) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (!(i & (1 << A))) pair_mat(v[0][i], v[0][i | (1 << A)], mh);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            double m[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) m[e] = dmats[8 * t + e];
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                if (i & (1 << A)) continue;
+                const int j = i | (1 << A);
+                const double p0x = v[0][i].x, p0y = v[0][i].y, p1x = v[0][j].x, p1y = v[0][j].y;
+                const double t0x = m[0] * p0x - m[1] * p0y + m[2] * p1x - m[3] * p1y;
+                const double t0y = m[0] * p0y + m[1] * p0x + m[2] * p1y + m[3] * p1x;
+                const double t1x = m[4] * p0x - m[5] * p0y + m[6] * p1x - m[7] * p1y;
+                const double t1y = m[4] * p0y + m[5] * p0x + m[6] * p1y + m[7] * p1x;
+                acc += (double)v[1][i].x * t0x + (double)v[1][i].y * t0y + (double)v[1][j].x * t1x +
+                       (double)v[1][j].y * t1y;
+            }
+            g[t] += acc;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (!(i & (1 << A))) pair_mat(v[1][i], v[1][i | (1 << A)], mh);
+    }
+}
+
+template <int NV, typename T>
+__device__ __forceinline__ void dispatch_h(T (&v)[NV][16], int a) {
+    switch (a) {
+    case 0: op_h<0, NV>(v); break;
+    case 1: op_h<1, NV>(v); break;
+    case 2: op_h<2, NV>(v); break;
+    default: op_h<3, NV>(v); break;
+    }
+}
+
+template <int NV, typename T, typename R>
+__device__ __forceinline__ void dispatch_m(T (&v)[NV][16], int a, const R (&m)[8]) {
+    switch (a) {
+    case 0: op_m<0, NV>(v, m); break;
+    case 1: op_m<1, NV>(v, m); break;
+    case 2: op_m<2, NV>(v, m); break;
+    default: op_m<3, NV>(v, m); break;
+    }
+}
+
+template <int NV, typename T, typename R>
+__device__ __forceinline__ void dispatch_d2bwd(T (&v)[NV][16], int a, const R (&mh)[8], const double* dmats,
+                                               double (&g)[3]) {
+    switch (a) {
+    case 0: op_d2bwd<0, NV>(v, mh, dmats, g); break;
+    case 1: op_d2bwd<1, NV>(v, mh, dmats, g); break;
+    case 2: op_d2bwd<2, NV>(v, mh, dmats, g); break;
+    default: op_d2bwd<3, NV>(v, mh, dmats, g); break;
+    }
+}
+
+// Sum of one double per thread over the workgroup; result valid in thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum(double x, double* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[wave] = x;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < (NT + 63) / 64; ++w) s += red[w];
+    }
+    __syncthreads();
+    return s;
+}
+
+// ---------------------------------------------------------------------------- one tile
+
+template <typename R, int NV, int KMAX>
+__device__ __forceinline__ void process_tile(const KArgs& a, const Pass* __restrict__ P, int64_t tile,
+                                             typename Cplx<R>::T* lds, double* red) {
+    using T = typename Cplx<R>::T;
+    constexpr int NT = 1 << (KMAX - 4);
+    const int k = P->k;
+    const int nrb = k < 4 ? k : 4;
+    const int nreg = 1 << nrb;
+    const unsigned tid = threadIdx.x;
+    const unsigned nact = k >= 4 ? (1u << (k - 4)) : 1u;
+    const bool active = tid < nact;
+
+    const int64_t base = P->state_off + deposit(tile, P->frun, P->nfrun);
+    const int flags = P->flags;
+
+    T v[NV][16];
+#pragma unroll
+    for (int n = 0; n < NV; ++n)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[n][i] = T{0, 0};
+
+    // ---- load in the first stage's layout
+    const Stage* S = a.stages + P->stage_begin;
+    Layout L = make_layout(S, nrb, tid);
+    {
+        const GOff G = make_goff(P, S, L, nrb);
+        const T* in0 = reinterpret_cast<const T*>((flags & PASS_FIRST) ? a.src0 : a.dst0);
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (i < nreg) v[0][i] = in0[base + G.gt + goff(G, i)];
+            if constexpr (NV == 2) {
+                if (!(flags & PASS_SEED_V1)) {
+                    const T* in1 = reinterpret_cast<const T*>(a.dst1);
+#pragma unroll
+                    for (int i = 0; i < 16; ++i)
+                        if (i < nreg) v[1][i] = in1[base + G.gt + goff(G, i)];
+                }
+            }
+        }
+    }
+
+    double nsum = 0.0, ncomp = 0.0;
+    const int nstages = P->nstages;
+    for (int s = 0; s < nstages; ++s) {
+        if (s > 0) {
+            // ---- LDS exchange: previous layout out, this layout in
+            const Stage* Sn = a.stages + P->stage_begin + s;
+            const Layout Ln = make_layout(Sn, nrb, tid);
+#pragma unroll
+            for (int n = 0; n < NV; ++n) {
+                if (active) {
+#pragma unroll
+                    for (int i = 0; i < 16; ++i)
+                        if (i < nreg) lds[L.pj ^ poff(L, i)] = v[n][i];
+                }
+                __syncthreads();
+                if (active) {
+#pragma unroll
+                    for (int i = 0; i < 16; ++i)
+                        if (i < nreg) v[n][i] = lds[Ln.pj ^ poff(Ln, i)];
+                }
+                __syncthreads();
+            }
+            S = Sn;
+            L = Ln;
+        }
+        // ---- the stage's gates, in order
+        const int op_count = S->op_count;
+        const Op* ops = a.ops + S->op_begin;
+        for (int o = 0; o < op_count; ++o) {
+            const Op op = ops[o];
+            switch (op.kind) {
+            case OP_H:
+                dispatch_h<NV>(v, op.a);
+                break;
+            case OP_MAT: {
+                R m[8];
+                const double* mp = a.mats + 8 * op.arg;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) m[e] = (R)mp[e];
+                dispatch_m<NV>(v, op.a, m);
+                break;
+            }
+            case OP_FLIP:
+            case OP_READ:
+            case OP_SEED: {
+                const Flip f = a.flips[op.arg];
+                if (f.tile == tile && active) {
+                    const unsigned jrel = (unsigned)f.j ^ L.jt;
+                    const unsigned rmask = L.r[0] | L.r[1] | L.r[2] | L.r[3];
+                    if ((jrel & ~rmask) == 0u) {
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) {
+                            if (i < nreg && roff(L, i) == jrel) {
+                                if (op.kind == OP_FLIP) {
+#pragma unroll
+                                    for (int n = 0; n < NV; ++n) {
+                                        v[n][i].x = -v[n][i].x;
+                                        v[n][i].y = -v[n][i].y;
+                                    }
+                                } else if (op.kind == OP_READ) {
+                                    const double x = v[0][i].x, y = v[0][i].y;
+                                    a.reads[f.slot] = x * x + y * y;
+                                } else if constexpr (NV == 2) {
+                                    const R d = (R)a.dL[f.slot];
+                                    v[1][i].x = d * v[0][i].x;
+                                    v[1][i].y = d * v[0][i].y;
+                                }
+                            }
+                        }
+                    }
+                }
+                break;
+            }
+            case OP_SCALE: {
+                const R sc = (R)P->scale;
+#pragma unroll
+                for (int n = 0; n < NV; ++n)
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        v[n][i].x *= sc;
+                        v[n][i].y *= sc;
+                    }
+                break;
+            }
+            case OP_D2BWD: {
+                R mh[8];
+                const double* mp = a.mats + 8 * op.arg;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) mh[e] = (R)mp[8 + e];
+                double g[3] = {0.0, 0.0, 0.0};
+                if (active) dispatch_d2bwd<NV>(v, op.a, mh, mp + 16, g);
+                const double scale = 2.0 * (double)op.gscale;
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    const double tot = block_sum<NT>(g[t], red);
+                    if (tid == 0) a.gpart[op.gslot + t * P->ntiles + tile] = scale * tot;
+                }
+                break;
+            }
+            default:
+                break;
+            }
+        }
+    }
+
+    // ---- norm partial of the final state (FP64 for FP64 data; Neumaier-
+    //      compensated FP32 lane sums, then FP64, for FP32 data)
+    if (a.want_norm && (flags & PASS_LAST)) {
+        double part = 0.0;
+        if (active) {
+            if constexpr (sizeof(R) == 8) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    if (i < nreg) part += v[0][i].x * v[0][i].x + v[0][i].y * v[0][i].y;
+            } else {
+                float s = 0.0f, c = 0.0f;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    if (i >= nreg) continue;
+                    const float term = v[0][i].x * v[0][i].x + v[0][i].y * v[0][i].y;
+                    const float t = s + term;
+                    c += (fabsf(s) >= fabsf(term)) ? ((s - t) + term) : ((term - t) + s);
+                    s = t;
+                }
+                part = (double)s + (double)c;
+            }
+        }
+        const double tot = block_sum<NT>(part, red);
+        if (tid == 0) a.partials[P->part_base + tile] = tot;
+    }
+    (void)nsum;
+    (void)ncomp;
+
+    // ---- store in the last stage's layout
+    {
+        const GOff G = make_goff(P, S, L, nrb);
+        if (active) {
+            if (!(flags & PASS_SKIP_V0)) {
+                T* out0 = reinterpret_cast<T*>(a.dst0);
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    if (i < nreg) out0[base + G.gt + goff(G, i)] = v[0][i];
+            }
+            if constexpr (NV == 2) {
+                T* out1 = reinterpret_cast<T*>(a.dst1);
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    if (i < nreg) out1[base + G.gt + goff(G, i)] = v[1][i];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------- kernels
+
+template <typename R, int NV, int KMAX>
+__global__ void __launch_bounds__(1 << (KMAX - 4)) pass_kernel(KArgs a) {
+    using T = typename Cplx<R>::T;
+    __shared__ T lds[1 << KMAX];
+    __shared__ double red[16];
+    const Pass* P = a.passes + a.pass;
+    const int64_t ntiles = P->ntiles;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+        process_tile<R, NV, KMAX>(a, P, tile, lds, red);
+}
+
+// Multiverse batch: each workgroup takes whole instances from a queue (largest
+// first) and runs all their passes itself, then writes L and the norm.
+template <typename R, int KMAX>
+__global__ void __launch_bounds__(1 << (KMAX - 4))
+    batched_kernel(KArgs a, const InstDesc* idesc, const int32_t* order, int32_t n_inst,
+                   unsigned int* queue, double* L_out, double* norm_out) {
+    using T = typename Cplx<R>::T;
+    constexpr int NT = 1 << (KMAX - 4);
+    __shared__ T lds[1 << KMAX];
+    __shared__ double red[16];
+    __shared__ int item;
+    for (;;) {
+        if (threadIdx.x == 0) item = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int it = item;
+        __syncthreads();
+        if (it >= n_inst) break;
+        const int inst = order[it];
+        const InstDesc D = idesc[inst];
+        for (int p = 0; p < D.npass; ++p) {
+            const Pass* P = a.passes + D.first_pass + p;
+            const int64_t ntiles = P->ntiles;
+            for (int64_t tile = 0; tile < ntiles; ++tile) process_tile<R, 1, KMAX>(a, P, tile, lds, red);
+            // this workgroup's stores must be visible to its own loads of the next pass
+            __threadfence_block();
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            double L = 0.0;
+            for (int m = 0; m < D.nmarked; ++m) L += a.reads[D.read_base + m];
+            L_out[inst] = L;
+        }
+        if (norm_out) {
+            double s = 0.0;
+            for (int64_t t = threadIdx.x; t < D.ntiles_last; t += NT) s += a.partials[D.part_base + t];
+            const double tot = block_sum<NT>(s, red);
+            if (threadIdx.x == 0) norm_out[inst] = tot;
+        }
+        __syncthreads();
+    }
+}
+
+// Copies the static operators and builds the D2 matrices from the angles:
+// per D2 gate five matrices D, D^H, dD/dalpha, dD/dbeta, dD/dgamma with
+// D = R_z(alpha) R_y(beta) R_z(gamma) written out element by element.
+__global__ void prep_kernel(double* mats, const double* smats, int32_t n_static, const double* angles,
+                            int32_t n_d2, unsigned int* counters, int32_t n_counters) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n_counters) counters[t] = 0u;
+    if (t < 16 * n_static) mats[t] = smats[t];
+    if (t < n_d2) {
+        const double al = angles[3 * t], be = angles[3 * t + 1], ga = angles[3 * t + 2];
+        double c, s, cp, sp, cm, sm;
+        sincos(0.5 * be, &s, &c);
+        sincos(0.5 * (al + ga), &sp, &cp);  // e^{i(al+ga)/2}
+        sincos(0.5 * (al - ga), &sm, &cm);  // e^{i(al-ga)/2}
+        double* m = mats + 16 * n_static + 40 * t;
+        // D00 = e^{-i(a+g)/2} c, D01 = -e^{-i(a-g)/2} s, D10 = e^{i(a-g)/2} s, D11 = e^{i(a+g)/2} c
+        const double D[8] = {cp * c, -sp * c, -cm * s, sm * s, cm * s, sm * s, cp * c, sp * c};
+        for (int e = 0; e < 8; ++e) m[e] = D[e];
+        // D^H[a][b] = conj(D[b][a])
+        const double H[8] = {D[0], -D[1], D[4], -D[5], D[2], -D[3], D[6], -D[7]};
+        for (int e = 0; e < 8; ++e) m[8 + e] = H[e];
+        // dD/dalpha = diag(-i/2, i/2) D : row 0 times -i/2, row 1 times i/2
+        const double Da[8] = {0.5 * D[1], -0.5 * D[0], 0.5 * D[3], -0.5 * D[2],
+                              -0.5 * D[5], 0.5 * D[4], -0.5 * D[7], 0.5 * D[6]};
+        for (int e = 0; e < 8; ++e) m[16 + e] = Da[e];
+        // dD/dbeta: c -> -s/2 and s -> c/2 in every element
+        const double Db[8] = {-0.5 * cp * s, 0.5 * sp * s, -0.5 * cm * c, 0.5 * sm * c,
+                              0.5 * cm * c, 0.5 * sm * c, -0.5 * cp * s, -0.5 * sp * s};
+        for (int e = 0; e < 8; ++e) m[24 + e] = Db[e];
+        // dD/dgamma = D diag(-i/2, i/2) : column 0 times -i/2, column 1 times i/2
+        const double Dg[8] = {0.5 * D[1], -0.5 * D[0], -0.5 * D[3], 0.5 * D[2],
+                              0.5 * D[5], -0.5 * D[4], -0.5 * D[7], 0.5 * D[6]};
+        for (int e = 0; e < 8; ++e) m[32 + e] = Dg[e];
+    }
+}
+
+// Final FP64 combine, one workgroup per output, fixed summation order.
+__global__ void __launch_bounds__(256) reduce_kernel(const Reduction* red, int32_t n, const double* ws,
+                                                     double* L_out, double* norm_out, double* grad_out) {
+    __shared__ double sred[16];
+    const int e = blockIdx.x;
+    if (e >= n) return;
+    const Reduction r = red[e];
+    double* out = r.target == 0 ? L_out : (r.target == 1 ? norm_out : grad_out);
+    if (!out) return;
+    double s = 0.0;
+    for (int64_t t = threadIdx.x; t < r.count; t += 256) s += ws[r.src + t];
+    const double tot = block_sum<256>(s, sred);
+    if (threadIdx.x == 0) out[r.index] = tot;
+}
+
+// Partner pairs of qubit i_s (Eqs. pair0 / pair1): the r-th label with bit
+// (nq - i_s) clear is r with a zero bit inserted at that position.
+__global__ void pair_index_kernel(int32_t nq, int32_t i_s, int64_t first, int64_t count, int64_t* n0,
+                                  int64_t* n1) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= count) return;
+    const int b = nq - i_s;
+    const int64_t q = first + r;
+    const int64_t lo = q & (((int64_t)1 << b) - 1);
+    const int64_t m0 = ((q >> b) << (b + 1)) | lo;
+    n0[r] = m0;
+    n1[r] = m0 + ((int64_t)1 << b);
+}
+
+// ---------------------------------------------------------------------------- host launchers
+
+template <typename R, int NV, int KMAX>
+static hipError_t launch_pass_t(const KArgs& a, int64_t ntiles, hipStream_t st) {
+    const int64_t cap = (int64_t)1 << 30;
+    const unsigned grid = (unsigned)(ntiles < cap ? ntiles : cap);
+    hipLaunchKernelGGL((pass_kernel<R, NV, KMAX>), dim3(grid), dim3(1 << (KMAX - 4)), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename R, int NV>
+static hipError_t launch_pass_r(int kmax, const KArgs& a, int64_t ntiles, hipStream_t st) {
+    switch (kmax) {
+    case 10: return launch_pass_t<R, NV, 10>(a, ntiles, st);
+    case 11: return launch_pass_t<R, NV, 11>(a, ntiles, st);
+    case 12: return launch_pass_t<R, NV, 12>(a, ntiles, st);
+    case 13: return launch_pass_t<R, NV, 13>(a, ntiles, st);
+    case 14:
+        if constexpr (sizeof(R) == 4) return launch_pass_t<R, NV, 14>(a, ntiles, st);
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pass(const PassLaunch& L, hipStream_t st) {
+    KArgs a;
+    a.passes = L.passes;
+    a.stages = L.stages;
+    a.ops = L.ops;
+    a.flips = L.flips;
+    a.mats = L.mats;
+    a.src0 = L.src0;
+    a.dst0 = L.dst0;
+    a.dst1 = L.dst1;
+    a.partials = L.partials;
+    a.reads = L.reads;
+    a.gpart = L.gpart;
+    a.dL = L.dL;
+    a.pass = L.pass;
+    a.want_norm = L.want_norm;
+    if (L.fp64) {
+        return L.nv == 2 ? launch_pass_r<double, 2>(L.kmax, a, L.ntiles, st)
+                         : launch_pass_r<double, 1>(L.kmax, a, L.ntiles, st);
+    }
+    return L.nv == 2 ? launch_pass_r<float, 2>(L.kmax, a, L.ntiles, st)
+                     : launch_pass_r<float, 1>(L.kmax, a, L.ntiles, st);
+}
+
+template <typename R, int KMAX>
+static hipError_t launch_batched_t(const KArgs& a, const BatchLaunch& B, hipStream_t st) {
+    hipLaunchKernelGGL((batched_kernel<R, KMAX>), dim3(B.grid), dim3(1 << (KMAX - 4)), 0, st, a, B.idesc,
+                       B.order, B.n_inst, B.queue, B.L_out, B.norm_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_batched(const PassLaunch& L, const BatchLaunch& B, hipStream_t st) {
+    KArgs a;
+    a.passes = L.passes;
+    a.stages = L.stages;
+    a.ops = L.ops;
+    a.flips = L.flips;
+    a.mats = L.mats;
+    a.src0 = L.src0;
+    a.dst0 = L.dst0;
+    a.dst1 = nullptr;
+    a.partials = L.partials;
+    a.reads = L.reads;
+    a.gpart = nullptr;
+    a.dL = nullptr;
+    a.pass = 0;
+    a.want_norm = L.want_norm;
+    if (L.fp64) {
+        switch (L.kmax) {
+        case 10: return launch_batched_t<double, 10>(a, B, st);
+        case 11: return launch_batched_t<double, 11>(a, B, st);
+        case 12: return launch_batched_t<double, 12>(a, B, st);
+        case 13: return launch_batched_t<double, 13>(a, B, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (L.kmax) {
+    case 10: return launch_batched_t<float, 10>(a, B, st);
+    case 11: return launch_batched_t<float, 11>(a, B, st);
+    case 12: return launch_batched_t<float, 12>(a, B, st);
+    case 13: return launch_batched_t<float, 13>(a, B, st);
+    case 14: return launch_batched_t<float, 14>(a, B, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_prep(double* mats, const double* smats, int n_static, const double* angles, int n_d2,
+                       unsigned int* counters, int n_counters, hipStream_t st) {
+    int n = 16 * n_static;
+    if (n_d2 > n) n = n_d2;
+    if (n_counters > n) n = n_counters;
+    if (n < 1) n = 1;
+    hipLaunchKernelGGL(prep_kernel, dim3((n + 255) / 256), dim3(256), 0, st, mats, smats, n_static, angles,
+                       n_d2, counters, n_counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const Reduction* red, int n, const double* ws, double* L_out, double* norm_out,
+                         double* grad_out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_kernel, dim3(n), dim3(256), 0, st, red, n, ws, L_out, norm_out, grad_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pairs(int nq, int i_s, int64_t first, int64_t count, int64_t* n0, int64_t* n1,
+                        hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const int64_t blocks = (count + 255) / 256;
+    hipLaunchKernelGGL(pair_index_kernel, dim3((unsigned)blocks), dim3(256), 0, st, nq, i_s, first, count, n0,
+                       n1);
+    return hipGetLastError();
+}
+
+}  // namespace pk

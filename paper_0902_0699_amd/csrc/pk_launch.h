@@ -1,0 +1,50 @@
+// Host-side launchers of the device kernels (defined in pk_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pk_desc.h"
+
+namespace pk {
+
+struct PassLaunch {
+    const Pass* passes;
+    const Stage* stages;
+    const Op* ops;
+    const Flip* flips;
+    const double* mats;
+    const void* src0;
+    void* dst0;
+    void* dst1;
+    double* partials;
+    double* reads;
+    double* gpart;
+    const double* dL;
+    int32_t pass;
+    int32_t want_norm;
+    int32_t kmax;
+    int32_t nv;
+    int32_t fp64;
+    int64_t ntiles;
+};
+
+struct BatchLaunch {
+    const InstDesc* idesc;
+    const int32_t* order;
+    int32_t n_inst;
+    unsigned int* queue;
+    double* L_out;
+    double* norm_out;
+    unsigned grid;
+};
+
+hipError_t launch_pass(const PassLaunch& L, hipStream_t st);
+hipError_t launch_batched(const PassLaunch& L, const BatchLaunch& B, hipStream_t st);
+hipError_t launch_prep(double* mats, const double* smats, int n_static, const double* angles, int n_d2,
+                       unsigned int* counters, int n_counters, hipStream_t st);
+hipError_t launch_reduce(const Reduction* red, int n, const double* ws, double* L_out, double* norm_out,
+                         double* grad_out, hipStream_t st);
+hipError_t launch_pairs(int nq, int i_s, int64_t first, int64_t count, int64_t* n0, int64_t* n1,
+                        hipStream_t st);
+
+}  // namespace pk

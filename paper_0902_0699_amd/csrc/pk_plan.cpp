@@ -1,0 +1,707 @@
+// Plan compiler: validates gate lists and lowers them to pass / stage / op tables.
+//
+// Legality rests on two facts about the gates of the paper: one-qubit gates on
+// different qubits commute (each acts on its own tensor factor, Sec. 2.1), and
+// diagonal sign operations (Oracle, Inv; Sec. 5.1) commute with each other.
+// Any order of the primitives that keeps every non-commuting pair in list
+// order computes the same state, so the compiler may gather all gates on a set
+// of qubits into one pass over the state.
+#include "pk_plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <set>
+
+namespace pk {
+
+namespace {
+
+constexpr int kKernelMinBits = 10;    // smallest kernel instance: one wavefront of 64 threads
+constexpr int kBackwardMaxBits = 12;  // largest backward tile (psi and lambda in registers)
+
+bool finite8(const double* v, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+bool is_unitary(const double* m) {
+    // m row-major complex 2x2; check M^H M = I
+    double a[2][2][2];
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) {
+            a[r][c][0] = m[2 * (2 * r + c)];
+            a[r][c][1] = m[2 * (2 * r + c) + 1];
+        }
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            double re = 0, im = 0;
+            for (int r = 0; r < 2; ++r) {  // conj(a[r][i]) * a[r][j]
+                re += a[r][i][0] * a[r][j][0] + a[r][i][1] * a[r][j][1];
+                im += a[r][i][0] * a[r][j][1] - a[r][i][1] * a[r][j][0];
+            }
+            if (std::fabs(re - (i == j ? 1.0 : 0.0)) > 1e-12 || std::fabs(im) > 1e-12) return false;
+        }
+    return true;
+}
+
+// Forward scan: which not-yet-scheduled primitives can run in a pass (or stage)
+// whose register/tile bit set is `in_set`.  A gate is blocked by an earlier
+// unscheduled gate on the same bit or an earlier unscheduled diagonal op; a
+// diagonal op is blocked by any earlier unscheduled gate.
+struct ScanItem {
+    bool diag;
+    int bit;
+};
+
+int scan(const std::vector<ScanItem>& items, const std::vector<char>& done,
+         const std::vector<char>& in_set, int nbits, int max_gates, std::vector<int>* out) {
+    std::vector<char> blocked(nbits, 0);
+    bool blocked_gate = false, blocked_diag = false;
+    int count = 0, gates = 0;
+    for (size_t i = 0; i < items.size(); ++i) {
+        if (done[i]) continue;
+        const ScanItem& it = items[i];
+        if (it.diag) {
+            if (!blocked_gate) {
+                ++count;
+                if (out) out->push_back((int)i);
+            } else {
+                blocked_diag = true;
+            }
+        } else {
+            bool ok = !blocked[it.bit] && !blocked_diag && in_set[it.bit] &&
+                      (max_gates < 0 || gates < max_gates);
+            if (ok) {
+                ++count;
+                ++gates;
+                if (out) out->push_back((int)i);
+            } else {
+                blocked[it.bit] = 1;
+                blocked_gate = true;
+            }
+        }
+    }
+    return count;
+}
+
+struct ScaleState {
+    int h = 0;    // unnormalised Hadamards not yet compensated (each contributes sqrt 2)
+    int sign = 1; // sign folded out of Inv
+};
+
+int64_t extract(int64_t x, const std::vector<int>& bits) {
+    int64_t r = 0;
+    for (size_t l = 0; l < bits.size(); ++l) r |= ((x >> bits[l]) & 1) << l;
+    return r;
+}
+
+struct Compiler {
+    Plan* plan;
+    Instance* in;
+    bool backward;
+    int k, C, RB;
+
+    std::vector<int> free_bits(const std::vector<int>& tbits) const {
+        std::vector<char> used(in->nq, 0);
+        for (int b : tbits) used[b] = 1;
+        std::vector<int> f;
+        for (int b = 0; b < in->nq; ++b)
+            if (!used[b]) f.push_back(b);
+        return f;
+    }
+
+    int add_flip(const std::vector<int>& tbits, int64_t x, int slot) {
+        Flip f;
+        f.j = (int32_t)extract(x, tbits);
+        f.tile = extract(x, free_bits(tbits));
+        f.slot = slot;
+        plan->flips.push_back(f);
+        return (int)plan->flips.size() - 1;
+    }
+
+    // Stage planning inside one pass.  `items` are the pass's primitives in
+    // scheduled order with bits given as local tile bits.
+    std::vector<std::pair<std::vector<int>, std::vector<int>>> plan_stages(
+        const std::vector<ScanItem>& items) const {
+        const int n = (int)items.size();
+        std::vector<char> done(n, 0);
+        int left = n;
+        auto io_ok = [&](int lb) { return (k - C >= RB) ? lb >= C : true; };
+        std::vector<std::pair<std::vector<int>, std::vector<int>>> stages;
+        bool first = true;
+        while (left > 0) {
+            // Does everything left fit in one stage that can also store?
+            std::set<int> need;
+            for (int i = 0; i < n; ++i)
+                if (!done[i] && !items[i].diag) need.insert(items[i].bit);
+            bool fits = (int)need.size() <= RB;
+            for (int b : need) fits = fits && io_ok(b);
+            std::vector<int> rb;
+            if (fits) {
+                rb.assign(need.begin(), need.end());
+                for (int b = k - 1; b >= 0 && (int)rb.size() < RB; --b)
+                    if (io_ok(b) && std::find(rb.begin(), rb.end(), b) == rb.end()) rb.push_back(b);
+            } else {
+                while ((int)rb.size() < RB) {
+                    int best = -1, best_gain = -1, best_pref = -1;
+                    for (int b = 0; b < k; ++b) {
+                        if (std::find(rb.begin(), rb.end(), b) != rb.end()) continue;
+                        if (first && !io_ok(b)) continue;
+                        std::vector<char> in_set(k, 0);
+                        for (int r : rb) in_set[r] = 1;
+                        in_set[b] = 1;
+                        int g = scan(items, done, in_set, k, -1, nullptr);
+                        // first stage: prefer high bits; later: bits that cannot be
+                        // stored from (low carriers) first, then low bits
+                        int pref = first ? b : ((!io_ok(b) ? 1000 : 0) + (k - b));
+                        if (g > best_gain || (g == best_gain && pref > best_pref)) {
+                            best = b;
+                            best_gain = g;
+                            best_pref = pref;
+                        }
+                    }
+                    rb.push_back(best);
+                }
+            }
+            std::vector<char> in_set(k, 0);
+            for (int r : rb) in_set[r] = 1;
+            std::vector<int> sel;
+            scan(items, done, in_set, k, -1, &sel);
+            for (int i : sel) done[i] = 1;
+            left -= (int)sel.size();
+            stages.push_back({rb, sel});
+            first = false;
+            if (fits) break;
+        }
+        bool last_ok = !stages.empty();
+        if (last_ok)
+            for (int r : stages.back().first) last_ok = last_ok && io_ok(r);
+        if (!last_ok) {
+            std::vector<int> rb;
+            for (int b = k - 1; b >= 0 && (int)rb.size() < RB; --b)
+                if (io_ok(b)) rb.push_back(b);
+            stages.push_back({rb, {}});
+        }
+        return stages;
+    }
+
+    void compile(const std::vector<Prim>& prims, std::vector<HostPass>* out) {
+        const int nq = in->nq;
+        const int n = (int)prims.size();
+        std::vector<ScanItem> items(n);
+        for (int i = 0; i < n; ++i) items[i] = {prims[i].kind != Prim::GATE, prims[i].bit};
+        std::vector<char> done(n, 0);
+        int left = n;
+        ScaleState sc;
+        int pass_no = 0;
+        const int max_gates = plan->tiling.fuse ? -1 : 1;
+        do {
+            // --- choose the tile bits: carriers, then greedy by gain
+            std::vector<char> in_t(nq, 0);
+            std::vector<int> t;
+            for (int b = 0; b < C; ++b) {
+                in_t[b] = 1;
+                t.push_back(b);
+            }
+            while ((int)t.size() < k) {
+                int best = -1, best_gain = -1;
+                for (int b = 0; b < nq; ++b) {
+                    if (in_t[b]) continue;
+                    in_t[b] = 1;
+                    int g = scan(items, done, in_t, nq, max_gates, nullptr);
+                    in_t[b] = 0;
+                    if (g > best_gain) {
+                        best = b;
+                        best_gain = g;
+                    }
+                }
+                in_t[best] = 1;
+                t.push_back(best);
+            }
+            std::sort(t.begin(), t.end());
+            std::vector<int> sel;
+            scan(items, done, in_t, nq, max_gates, &sel);
+            for (int i : sel) done[i] = 1;
+            left -= (int)sel.size();
+            const bool last = (left == 0);
+
+            // --- local items and stages
+            std::vector<int> local_of(nq, -1);
+            for (int l = 0; l < k; ++l) local_of[t[l]] = l;
+            std::vector<ScanItem> litems;
+            for (int i : sel) litems.push_back({items[i].diag, items[i].diag ? 0 : local_of[items[i].bit]});
+            auto st = plan_stages(litems);
+
+            HostPass hp;
+            hp.k = k;
+            hp.tbits = t;
+            hp.ntiles = (int64_t)1 << (nq - k);
+            hp.kmax = std::max(k, kKernelMinBits);
+            if (pass_no == 0) hp.flags |= PASS_FIRST | (backward ? PASS_SEED_V1 : 0);
+            if (last) hp.flags |= PASS_LAST | (backward ? PASS_SKIP_V0 : 0);
+            for (size_t s = 0; s < st.size(); ++s) {
+                HostStage hs;
+                for (int a = 0; a < kRegBits; ++a) hs.rb[a] = a < (int)st[s].first.size() ? st[s].first[a] : -1;
+                auto reg_of = [&](int lb) {
+                    for (int a = 0; a < kRegBits; ++a)
+                        if (hs.rb[a] == lb) return a;
+                    return -1;
+                };
+                if (s == 0 && pass_no == 0 && backward) {
+                    for (size_t m = 0; m < in->marked.size(); ++m) {
+                        Op o{};
+                        o.kind = OP_SEED;
+                        o.arg = add_flip(t, in->marked[m], (int)(in - plan->inst.data()));
+                        hs.ops.push_back(o);
+                    }
+                }
+                for (int li : st[s].second) {
+                    const Prim& p = prims[sel[li]];
+                    if (p.kind == Prim::ORACLE) {
+                        for (int64_t x : in->marked) {
+                            Op o{};
+                            o.kind = OP_FLIP;
+                            o.arg = add_flip(t, x, 0);
+                            hs.ops.push_back(o);
+                        }
+                    } else if (p.kind == Prim::INV) {
+                        sc.sign = -sc.sign;
+                        Op o{};
+                        o.kind = OP_FLIP;
+                        o.arg = add_flip(t, 0, 0);
+                        hs.ops.push_back(o);
+                    } else {
+                        Op o{};
+                        o.a = (int8_t)reg_of(local_of[p.bit]);
+                        if (p.gk == Prim::GH) {
+                            o.kind = OP_H;
+                            ++sc.h;
+                        } else if (p.gk == Prim::GMAT) {
+                            o.kind = OP_MAT;
+                            o.arg = 2 * p.idx + (backward ? 1 : 0);
+                        } else if (!backward) {
+                            o.kind = OP_MAT;
+                            o.arg = 2 * plan->n_static + 5 * p.idx;
+                        } else {
+                            o.kind = OP_D2BWD;
+                            o.arg = 2 * plan->n_static + 5 * p.idx;  // D, D^H, dD/dalpha, dD/dbeta, dD/dgamma
+                            o.gscale = (float)std::ldexp(1.0, -sc.h);
+                            o.gslot = (int32_t)plan->n_gpart;
+                            plan->d2_grad.push_back({p.idx, plan->n_gpart, hp.ntiles});
+                            plan->n_gpart += 3 * hp.ntiles;
+                        }
+                        hs.ops.push_back(o);
+                    }
+                }
+                hp.stages.push_back(hs);
+            }
+            // --- deferred scaling: powers of two each pass, the rest at the end
+            HostStage& fin = hp.stages.back();
+            if (last) {
+                double s = std::ldexp((double)sc.sign, -(sc.h / 2));
+                if (sc.h % 2) s *= std::sqrt(0.5);
+                if (backward) s *= 2.0;  // grad psi_in = 2 lambda_0
+                hp.scale = s;
+                sc = ScaleState{};
+            } else {
+                int e = sc.h / 2;
+                hp.scale = std::ldexp(1.0, -e);
+                sc.h -= 2 * e;
+            }
+            if (hp.scale != 1.0) {
+                Op o{};
+                o.kind = OP_SCALE;
+                fin.ops.push_back(o);
+            }
+            if (last && !backward) {
+                for (size_t m = 0; m < in->marked.size(); ++m) {
+                    Op o{};
+                    o.kind = OP_READ;
+                    o.arg = add_flip(t, in->marked[m], in->read_base + (int)m);
+                    fin.ops.push_back(o);
+                }
+            }
+            out->push_back(hp);
+            ++pass_no;
+        } while (left > 0);
+    }
+};
+
+std::string fmt(const char* f, long long a = 0, long long b = 0) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, f, a, b);
+    return buf;
+}
+
+}  // namespace
+
+int compile_plan(Plan* plan, const pk_problem* probs, int n_inst, int prec, std::string* err) {
+    if (prec != PK_FP64 && prec != PK_FP32) {
+        *err = "prec must be PK_FP64 or PK_FP32";
+        return PK_EINVAL;
+    }
+    if (n_inst < 1 || !probs) {
+        *err = "need at least one problem";
+        return PK_EINVAL;
+    }
+    plan->prec = prec;
+    plan->tiling = Tiling{prec == PK_FP64 ? 13 : 14, 4, 1};
+    const int nq_max = prec == PK_FP64 ? 30 : 31;
+    int64_t off = 0;
+    int d2 = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        const pk_problem& p = probs[i];
+        Instance in;
+        if (p.nq < 1 || p.nq > nq_max) {
+            *err = fmt("instance %lld: nq=%lld out of range", i, p.nq);
+            return PK_EINVAL;
+        }
+        in.nq = p.nq;
+        in.off = off;
+        off += (int64_t)1 << p.nq;
+        if (p.n_gates < 0 || (p.n_gates > 0 && !p.gates)) {
+            *err = fmt("instance %lld: bad gate array", i);
+            return PK_EINVAL;
+        }
+        if (p.n_marked < 0 || p.n_marked > 64 || (p.n_marked > 0 && !p.marked)) {
+            *err = fmt("instance %lld: marked set must hold 0..64 labels", i);
+            return PK_EINVAL;
+        }
+        std::set<int64_t> seen;
+        for (int64_t m = 0; m < p.n_marked; ++m) {
+            int64_t x = p.marked[m];
+            if (x < 0 || x >= ((int64_t)1 << p.nq)) {
+                *err = fmt("instance %lld: marked label %lld out of range", i, x);
+                return PK_EINVAL;
+            }
+            if (!seen.insert(x).second) {
+                *err = fmt("instance %lld: duplicate marked label %lld", i, x);
+                return PK_EINVAL;
+            }
+            in.marked.push_back(x);
+        }
+        in.d2_base = d2;
+        for (int g = 0; g < p.n_gates; ++g) {
+            const pk_gate& gt = p.gates[g];
+            if (gt.is2 != 0 || gt.k != 0) {
+                *err = fmt("instance %lld gate %lld: two-qubit fields must be 0", i, g);
+                return PK_EINVAL;
+            }
+            bool needs_qubit = gt.kind == PK_GATE_ONEOP || gt.kind == PK_GATE_H || gt.kind == PK_GATE_D2;
+            if (needs_qubit && (gt.is1 < 1 || gt.is1 > p.nq)) {
+                *err = fmt("instance %lld gate %lld: qubit label out of 1..nq", i, g);
+                return PK_EINVAL;
+            }
+            Prim pr{};
+            switch (gt.kind) {
+            case PK_GATE_ONEOP:
+                if (!finite8(gt.op, 8)) {
+                    *err = fmt("instance %lld gate %lld: non-finite operator", i, g);
+                    return PK_EINVAL;
+                }
+                if (!is_unitary(gt.op)) plan->backward_ok = false;
+                pr = {Prim::GATE, p.nq - gt.is1, Prim::GMAT, plan->n_static};
+                for (int e = 0; e < 8; ++e) plan->static_mats.push_back(gt.op[e]);
+                // adjoint: (M^H)[a][b] = conj(M[b][a])
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b) {
+                        plan->static_mats.push_back(gt.op[2 * (2 * b + a)]);
+                        plan->static_mats.push_back(-gt.op[2 * (2 * b + a) + 1]);
+                    }
+                ++plan->n_static;
+                in.prims.push_back(pr);
+                break;
+            case PK_GATE_H:
+                in.prims.push_back({Prim::GATE, p.nq - gt.is1, Prim::GH, 0});
+                break;
+            case PK_GATE_HALL:
+                for (int q = 1; q <= p.nq; ++q) in.prims.push_back({Prim::GATE, p.nq - q, Prim::GH, 0});
+                break;
+            case PK_GATE_ORACLE:
+                in.prims.push_back({Prim::ORACLE, 0, Prim::GH, 0});
+                break;
+            case PK_GATE_INV:
+                in.prims.push_back({Prim::INV, 0, Prim::GH, 0});
+                break;
+            case PK_GATE_D2:
+                if (!finite8(gt.angle, 3)) {
+                    *err = fmt("instance %lld gate %lld: non-finite angle", i, g);
+                    return PK_EINVAL;
+                }
+                in.prims.push_back({Prim::GATE, p.nq - gt.is1, Prim::GD2, d2});
+                for (int e = 0; e < 3; ++e) plan->default_angles.push_back(gt.angle[e]);
+                ++d2;
+                break;
+            default:
+                *err = fmt("instance %lld gate %lld: unknown kind", i, g);
+                return PK_EINVAL;
+            }
+        }
+        in.n_d2 = d2 - in.d2_base;
+        plan->max_nq = std::max(plan->max_nq, p.nq);
+        plan->inst.push_back(std::move(in));
+    }
+    plan->n_d2 = d2;
+    plan->total_elems = off;
+    return recompile(plan, err);
+}
+
+int recompile(Plan* plan, std::string* err) {
+    (void)err;
+    plan->passes.clear();
+    plan->stages.clear();
+    plan->ops.clear();
+    plan->flips.clear();
+    plan->idesc.clear();
+    plan->order.clear();
+    plan->d2_grad.clear();
+    plan->n_partials = 0;
+    plan->n_reads = 0;
+    plan->n_gpart = 0;
+    int read_base = 0;
+    for (auto& in : plan->inst) {
+        in.read_base = read_base;
+        read_base += (int)in.marked.size();
+    }
+    plan->n_reads = read_base;
+
+    for (int dir = 0; dir < 2; ++dir) {
+        for (auto& in : plan->inst) {
+            Compiler c;
+            c.plan = plan;
+            c.in = &in;
+            c.backward = dir == 1;
+            // two state vectors per tile in the backward pass: cap the tile at 2^12
+            // amplitudes so that both fit in registers without spilling
+            const int kcap = c.backward ? std::min(plan->tiling.tile_bits, kBackwardMaxBits) : plan->tiling.tile_bits;
+            c.k = std::min(kcap, in.nq);
+            c.C = std::min(plan->tiling.carrier_bits, c.k);
+            c.RB = std::min(kRegBits, c.k);
+            std::vector<Prim> prims = in.prims;
+            if (c.backward) std::reverse(prims.begin(), prims.end());
+            auto& dst = c.backward ? in.bwd : in.fwd;
+            dst.clear();
+            if (c.backward) in.gpart_base = (int)plan->n_gpart;
+            c.compile(prims, &dst);
+            if (!c.backward) {
+                dst.back().part_base = (int)plan->n_partials;
+                plan->n_partials += dst.back().ntiles;
+            }
+        }
+    }
+    // flatten: all forward passes (instance order), then all backward passes
+    auto emit = [&](Instance& in, int idx, HostPass& hp) {
+        Pass p{};
+        p.k = hp.k;
+        p.nfree = in.nq - hp.k;
+        p.nstages = (int)hp.stages.size();
+        p.stage_begin = (int)plan->stages.size();
+        p.ntiles = hp.ntiles;
+        p.state_off = in.off;
+        p.flags = hp.flags;
+        p.inst = idx;
+        p.scale = hp.scale;
+        p.part_base = hp.part_base;
+        p.kmax = hp.kmax;
+        std::memset(p.tpos, -1, sizeof p.tpos);
+        for (int l = 0; l < hp.k; ++l) p.tpos[l] = (int8_t)hp.tbits[l];
+        std::vector<char> used(in.nq, 0);
+        for (int b : hp.tbits) used[b] = 1;
+        std::vector<int> fbits;
+        for (int b = 0; b < in.nq; ++b)
+            if (!used[b]) fbits.push_back(b);
+        // runs of consecutive positions: (source bit, length, destination bit)
+        auto runs = [](const std::vector<int>& pos, int8_t (*out)[3]) {
+            int n = 0;
+            for (size_t i = 0; i < pos.size();) {
+                size_t j = i + 1;
+                while (j < pos.size() && pos[j] == pos[j - 1] + 1) ++j;
+                out[n][0] = (int8_t)i;
+                out[n][1] = (int8_t)(j - i);
+                out[n][2] = (int8_t)pos[i];
+                ++n;
+                i = j;
+            }
+            return n;
+        };
+        p.ntrun = runs(hp.tbits, p.trun);
+        p.nfrun = runs(fbits, p.frun);
+        for (auto& hs : hp.stages) {
+            Stage s{};
+            int nrb = 0;
+            for (int a = 0; a < kRegBits; ++a) {
+                s.rb[a] = (int8_t)hs.rb[a];
+                if (hs.rb[a] >= 0) s.rbs[nrb++] = (int8_t)hs.rb[a];
+            }
+            std::sort(s.rbs, s.rbs + nrb);
+            for (int a = nrb; a < kRegBits; ++a) s.rbs[a] = -1;
+            s.op_begin = (int)plan->ops.size();
+            s.op_count = (int)hs.ops.size();
+            for (auto& o : hs.ops) plan->ops.push_back(o);
+            plan->stages.push_back(s);
+        }
+        plan->passes.push_back(p);
+    };
+    for (size_t i = 0; i < plan->inst.size(); ++i)
+        for (auto& hp : plan->inst[i].fwd) emit(plan->inst[i], (int)i, hp);
+    plan->n_fwd_passes = (int)plan->passes.size();
+    for (size_t i = 0; i < plan->inst.size(); ++i)
+        for (auto& hp : plan->inst[i].bwd) emit(plan->inst[i], (int)i, hp);
+
+    // batched launch tables
+    int first = 0;
+    for (size_t i = 0; i < plan->inst.size(); ++i) {
+        const Instance& in = plan->inst[i];
+        InstDesc d{};
+        d.first_pass = first;
+        d.npass = (int)in.fwd.size();
+        d.read_base = in.read_base;
+        d.nmarked = (int)in.marked.size();
+        d.part_base = in.fwd.back().part_base;
+        d.ntiles_last = in.fwd.back().ntiles;
+        first += d.npass;
+        plan->idesc.push_back(d);
+        plan->order.push_back((int)i);
+    }
+    std::stable_sort(plan->order.begin(), plan->order.end(),
+                     [&](int a, int b) { return plan->inst[a].nq > plan->inst[b].nq; });
+    return PK_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+TableLayout table_layout(const Plan* plan) {
+    TableLayout t{};
+    size_t o = 0;
+    t.passes = o;
+    o = align256(o + plan->passes.size() * sizeof(Pass));
+    t.stages = o;
+    o = align256(o + plan->stages.size() * sizeof(Stage));
+    t.ops = o;
+    o = align256(o + plan->ops.size() * sizeof(Op));
+    t.flips = o;
+    o = align256(o + plan->flips.size() * sizeof(Flip));
+    t.mats = o;  // static matrices followed by the default angles
+    o = align256(o + (plan->static_mats.size() + plan->default_angles.size()) * sizeof(double));
+    t.idesc = o;
+    o = align256(o + plan->idesc.size() * sizeof(InstDesc));
+    t.order = o;
+    o = align256(o + plan->order.size() * sizeof(int32_t));
+    t.red = o;  // evaluation reductions, then backward reductions
+    o = align256(o + (2 * plan->inst.size() + 3 * plan->d2_grad.size()) * sizeof(Reduction));
+    t.total = std::max<size_t>(o, 256);
+    return t;
+}
+
+WsLayout workspace_layout(const Plan* plan, int op) {
+    WsLayout w{};
+    size_t o = 0;
+    w.mats = o;
+    o = align256(o + (size_t)(2 * plan->n_static + 5 * plan->n_d2) * 8 * sizeof(double));
+    w.partials = o;
+    o = align256(o + (size_t)plan->n_partials * sizeof(double));
+    w.reads = o;
+    o = align256(o + (size_t)plan->n_reads * sizeof(double));
+    w.gpart = o;
+    if (op == PK_OP_BACKWARD) o = align256(o + (size_t)plan->n_gpart * sizeof(double));
+    w.counters = o;
+    o = align256(o + (plan->inst.size() + 8) * sizeof(int64_t));
+    w.state = o;
+    if (op == PK_OP_BACKWARD) {
+        size_t esz = plan->prec == PK_FP64 ? 16 : 8;
+        int64_t maxn = 0;
+        for (auto& in : plan->inst) maxn = std::max<int64_t>(maxn, (int64_t)1 << in.nq);
+        o = align256(o + (size_t)maxn * esz);
+    }
+    w.total = std::max<size_t>(o, 256);
+    return w;
+}
+
+std::vector<Reduction> eval_reductions(const Plan* plan) {
+    WsLayout w = workspace_layout(plan, PK_OP_EVAL);
+    std::vector<Reduction> r;
+    for (size_t i = 0; i < plan->inst.size(); ++i) {
+        const InstDesc& d = plan->idesc[i];
+        r.push_back({0, (int)i, (int64_t)(w.reads / 8) + d.read_base, d.nmarked});
+        r.push_back({1, (int)i, (int64_t)(w.partials / 8) + d.part_base, d.ntiles_last});
+    }
+    return r;
+}
+
+std::vector<Reduction> backward_reductions(const Plan* plan) {
+    WsLayout w = workspace_layout(plan, PK_OP_BACKWARD);
+    std::vector<Reduction> r;
+    for (const auto& g : plan->d2_grad)
+        for (int t = 0; t < 3; ++t)
+            r.push_back({2, 3 * g.d + t, (int64_t)(w.gpart / 8) + g.gslot + t * g.nt, g.nt});
+    return r;
+}
+
+std::string describe(const Plan* plan) {
+    std::string s = "{\"prec\":";
+    s += plan->prec == PK_FP64 ? "\"fp64\"" : "\"fp32\"";
+    s += ",\"tile_bits\":" + std::to_string(plan->tiling.tile_bits);
+    s += ",\"carrier_bits\":" + std::to_string(plan->tiling.carrier_bits);
+    s += ",\"fuse\":" + std::to_string(plan->tiling.fuse);
+    s += ",\"n_static\":" + std::to_string(plan->n_static);
+    s += ",\"n_d2\":" + std::to_string(plan->n_d2);
+    s += ",\"instances\":[";
+    const char* kinds[] = {"H", "MAT", "FLIP", "SCALE", "READ", "SEED", "D2BWD"};
+    for (size_t i = 0; i < plan->inst.size(); ++i) {
+        const Instance& in = plan->inst[i];
+        if (i) s += ",";
+        s += "{\"nq\":" + std::to_string(in.nq) + ",\"offset\":" + std::to_string(in.off);
+        for (int dir = 0; dir < 2; ++dir) {
+            s += dir == 0 ? ",\"forward\":[" : ",\"backward\":[";
+            const auto& ps = dir == 0 ? in.fwd : in.bwd;
+            for (size_t p = 0; p < ps.size(); ++p) {
+                const HostPass& hp = ps[p];
+                if (p) s += ",";
+                s += "{\"k\":" + std::to_string(hp.k) + ",\"flags\":" + std::to_string(hp.flags);
+                char buf[64];
+                std::snprintf(buf, sizeof buf, "%.17g", hp.scale);
+                s += ",\"scale\":";
+                s += buf;
+                s += ",\"tile_bits\":[";
+                for (size_t l = 0; l < hp.tbits.size(); ++l) s += (l ? "," : "") + std::to_string(hp.tbits[l]);
+                s += "],\"stages\":[";
+                for (size_t st = 0; st < hp.stages.size(); ++st) {
+                    const HostStage& hs = hp.stages[st];
+                    if (st) s += ",";
+                    s += "{\"rb\":[";
+                    for (int a = 0; a < kRegBits; ++a) s += (a ? "," : "") + std::to_string(hs.rb[a]);
+                    s += "],\"ops\":[";
+                    for (size_t o = 0; o < hs.ops.size(); ++o) {
+                        const Op& op = hs.ops[o];
+                        if (o) s += ",";
+                        s += "{\"kind\":\"";
+                        s += kinds[op.kind];
+                        s += "\",\"a\":" + std::to_string(op.a) + ",\"arg\":" + std::to_string(op.arg);
+                        if (op.kind == OP_FLIP || op.kind == OP_READ || op.kind == OP_SEED) {
+                            const Flip& f = plan->flips[op.arg];
+                            s += ",\"tile\":" + std::to_string(f.tile) + ",\"j\":" + std::to_string(f.j) +
+                                 ",\"slot\":" + std::to_string(f.slot);
+                        }
+                        if (op.kind == OP_D2BWD) {
+                            std::snprintf(buf, sizeof buf, "%.9g", (double)op.gscale);
+                            s += ",\"gscale\":";
+                            s += buf;
+                        }
+                        s += "}";
+                    }
+                    s += "]}";
+                }
+                s += "]}";
+            }
+            s += "]";
+        }
+        s += "}";
+    }
+    s += "]}";
+    return s;
+}
+
+}  // namespace pk

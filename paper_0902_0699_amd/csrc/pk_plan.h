@@ -1,0 +1,115 @@
+// Host-side plan: validated problems and their compiled pass schedules.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "pk_desc.h"
+#include "paperkern.h"
+
+namespace pk {
+
+// A primitive operation of the gate list: a one-qubit gate on one state bit,
+// or a diagonal sign operation on the whole state.
+struct Prim {
+    enum Kind { GATE, ORACLE, INV } kind;
+    int bit;  // GATE: state bit b = nq - i_s (bit 0 is qubit n_q, the least significant)
+    enum GKind { GH, GMAT, GD2 } gk;
+    int idx;  // GMAT: static matrix index; GD2: global D2 index
+};
+
+struct HostStage {
+    int rb[kRegBits];
+    std::vector<Op> ops;
+};
+
+struct HostPass {
+    int k = 0;
+    std::vector<int> tbits;  // global bits of the tile, ascending (local bit l -> tbits[l])
+    std::vector<HostStage> stages;
+    int flags = 0;
+    double scale = 1.0;
+    int64_t ntiles = 0;
+    int part_base = 0;
+    int kmax = 13;
+};
+
+struct Instance {
+    int nq = 0;
+    int64_t off = 0;
+    std::vector<int64_t> marked;
+    std::vector<Prim> prims;
+    int d2_base = 0;
+    int n_d2 = 0;
+    std::vector<HostPass> fwd;
+    std::vector<HostPass> bwd;
+    int read_base = 0;   // readout slots
+    int gpart_base = 0;  // backward gradient partial base
+};
+
+struct Tiling {
+    int tile_bits;
+    int carrier_bits;
+    int fuse;
+};
+
+struct Plan {
+    uint32_t magic = 0x504b504cu;
+    int prec = PK_FP64;
+    std::vector<Instance> inst;
+    std::vector<double> static_mats;   // 8 doubles per ONEOP matrix, then its adjoint
+    std::vector<double> default_angles; // 3 per D2
+    int n_d2 = 0;
+    int n_static = 0;
+    bool backward_ok = true;
+    Tiling tiling{13, 4, 1};
+    std::string last_error;
+
+    // flattened tables (forward passes of all instances, then backward passes)
+    std::vector<Pass> passes;
+    std::vector<Stage> stages;
+    std::vector<Op> ops;
+    std::vector<Flip> flips;
+    std::vector<InstDesc> idesc;    // batched launch: per-instance pass ranges
+    std::vector<int32_t> order;     // instances by decreasing size (largest first)
+    struct D2Grad { int d; int64_t gslot; int64_t nt; };
+    std::vector<D2Grad> d2_grad;    // where each D2's backward partials live
+    int n_fwd_passes = 0;
+    int64_t n_partials = 0;         // norm partials (sum over instances of last-pass tiles)
+    int64_t n_reads = 0;
+    int64_t n_gpart = 0;
+    int64_t total_elems = 0;
+    int max_nq = 0;
+
+    // device state (uploaded lazily)
+    int device = -1;
+    void* d_tables = nullptr;
+    size_t d_tables_bytes = 0;
+    void* capture_stream = nullptr;
+    void* graph_exec[2] = {nullptr, nullptr};  // [0] evaluate, [1] batched
+    const void* graph_key[2][8] = {};
+};
+
+// Validates and compiles; returns PK_OK or an error code with plan->last_error set.
+int compile_plan(Plan* plan, const pk_problem* probs, int n_inst, int prec, std::string* err);
+int recompile(Plan* plan, std::string* err);
+std::string describe(const Plan* plan);
+
+// Byte offsets of the device table arrays inside plan->d_tables.
+struct TableLayout {
+    size_t passes, stages, ops, flips, mats, idesc, order, red, total;
+};
+TableLayout table_layout(const Plan* plan);
+
+// Final-combine lists (L and norm per instance; angle gradients) for a workspace layout.
+std::vector<Reduction> eval_reductions(const Plan* plan);
+std::vector<Reduction> backward_reductions(const Plan* plan);
+
+// Workspace layout (byte offsets) for op = PK_OP_EVAL / PK_OP_BACKWARD.
+struct WsLayout {
+    size_t mats, partials, reads, gpart, counters, state, total;
+};
+WsLayout workspace_layout(const Plan* plan, int op);
+
+} // namespace pk

@@ -1,0 +1,149 @@
+"""Executes a compiled pass schedule (the JSON of pk_plan_describe) on the CPU.
+
+Test helper for the host plan compiler: it applies every op of every stage in
+schedule order to the whole state, addressing each op the way the kernel
+does (local tile bit -> state bit through the pass's tile bits; Flip entries
+as (tile, local label)), with unnormalised Hadamard butterflies and the pass
+scales the compiler chose.  Agreement with the oracle shows that the
+compiler's reordering, scale bookkeeping, matrix indices and flip encoding
+are right; the kernels are checked separately on the GPU.
+"""
+
+import numpy as np
+
+import oracle as O
+
+
+def _matrix_table(problems, desc):
+    statics = []
+    d2 = []
+    for p in problems:
+        for g in p["gates"]:
+            if g[0] == "ONEOP":
+                statics.append(np.asarray(g[2], dtype=np.complex128))
+            if g[0] == "D2":
+                d2.append(tuple(float(v) for v in g[2:5]))
+    assert len(statics) == desc["n_static"] and len(d2) == desc["n_d2"]
+
+    def mat(m):
+        ns = desc["n_static"]
+        if m < 2 * ns:
+            M = statics[m // 2]
+            return M if m % 2 == 0 else M.conj().T
+        d, r = divmod(m - 2 * ns, 5)
+        D = O.d2_matrix(*d2[d])
+        if r == 0:
+            return D
+        if r == 1:
+            return D.conj().T
+        return O.d2_derivatives(*d2[d])[r - 2]
+
+    return mat
+
+
+def _apply_bit(vec, nq, bit, M):
+    v = vec.reshape(1 << (nq - 1 - bit), 2, 1 << bit)
+    a, b = v[:, 0, :].copy(), v[:, 1, :].copy()
+    v[:, 0, :] = M[0, 0] * a + M[0, 1] * b
+    v[:, 1, :] = M[1, 0] * a + M[1, 1] * b
+
+
+def _global_index(nq, tbits, tile, j):
+    free = [b for b in range(nq) if b not in tbits]
+    g = 0
+    for l, b in enumerate(tbits):
+        g |= ((j >> l) & 1) << b
+    for f, b in enumerate(free):
+        g |= ((tile >> f) & 1) << b
+    return g
+
+
+def check_stage_shapes(nq, p):
+    """Register bits are distinct local bits; gate ops name a register bit."""
+    k = p["k"]
+    for st in p["stages"]:
+        rb = [r for r in st["rb"] if r >= 0]
+        assert len(rb) == min(4, k) and len(set(rb)) == len(rb) and all(0 <= r < k for r in rb)
+        for op in st["ops"]:
+            if op["kind"] in ("H", "MAT", "D2BWD"):
+                assert 0 <= op["a"] < len(rb)
+    assert sorted(p["tile_bits"]) == p["tile_bits"] and len(p["tile_bits"]) == k
+    assert all(0 <= b < nq for b in p["tile_bits"])
+
+
+def run_forward(problems, desc, inst, psi_in):
+    """Returns (psi_out, L) of instance ``inst`` by executing its forward schedule."""
+    mat = _matrix_table(problems, desc)
+    info = desc["instances"][inst]
+    nq = info["nq"]
+    psi = np.array(psi_in, dtype=np.complex128)
+    reads = {}
+    H = np.array([[1, 1], [1, -1]], dtype=np.complex128)
+    for p in info["forward"]:
+        check_stage_shapes(nq, p)
+        tb = p["tile_bits"]
+        for st in p["stages"]:
+            for op in st["ops"]:
+                kind = op["kind"]
+                if kind in ("H", "MAT"):
+                    bit = tb[st["rb"][op["a"]]]
+                    _apply_bit(psi, nq, bit, H if kind == "H" else mat(op["arg"]))
+                elif kind == "FLIP":
+                    psi[_global_index(nq, tb, op["tile"], op["j"])] *= -1
+                elif kind == "SCALE":
+                    psi *= p["scale"]
+                elif kind == "READ":
+                    g = _global_index(nq, tb, op["tile"], op["j"])
+                    reads[op["slot"]] = abs(psi[g]) ** 2
+                else:
+                    raise AssertionError("unexpected forward op %s" % kind)
+    return psi, sum(reads[s] for s in sorted(reads))
+
+
+def run_backward(problems, desc, inst, psi_out, dL):
+    """Returns (grad_psi_in, grad_angles) by executing the backward schedule."""
+    mat = _matrix_table(problems, desc)
+    info = desc["instances"][inst]
+    nq = info["nq"]
+    psi = np.array(psi_out, dtype=np.complex128)
+    lam = np.zeros_like(psi)
+    grads = {}
+    H = np.array([[1, 1], [1, -1]], dtype=np.complex128)
+    for p in info["backward"]:
+        check_stage_shapes(nq, p)
+        tb = p["tile_bits"]
+        for st in p["stages"]:
+            for op in st["ops"]:
+                kind = op["kind"]
+                if kind in ("H", "MAT"):
+                    bit = tb[st["rb"][op["a"]]]
+                    M = H if kind == "H" else mat(op["arg"])
+                    _apply_bit(psi, nq, bit, M)
+                    _apply_bit(lam, nq, bit, M)
+                elif kind == "FLIP":
+                    g = _global_index(nq, tb, op["tile"], op["j"])
+                    psi[g] *= -1
+                    lam[g] *= -1
+                elif kind == "SCALE":
+                    psi *= p["scale"]
+                    lam *= p["scale"]
+                elif kind == "SEED":
+                    g = _global_index(nq, tb, op["tile"], op["j"])
+                    lam[g] = dL * psi[g]
+                elif kind == "D2BWD":
+                    bit = tb[st["rb"][op["a"]]]
+                    _apply_bit(psi, nq, bit, mat(op["arg"] + 1))
+                    for t in range(3):
+                        dpsi = psi.copy()
+                        _apply_bit(dpsi, nq, bit, mat(op["arg"] + 2 + t))
+                        d = (op["arg"] - 2 * desc["n_static"]) // 5
+                        grads[(d, t)] = 2.0 * op["gscale"] * float(np.vdot(lam, dpsi).real)
+                    _apply_bit(lam, nq, bit, mat(op["arg"] + 1))
+                else:
+                    raise AssertionError("unexpected backward op %s" % kind)
+    n_d2 = len({d for d, _ in grads})
+    ga = np.zeros((n_d2, 3))
+    d0 = min([d for d, _ in grads], default=0)
+    for (d, t), v in grads.items():
+        ga[d - d0, t] = v
+    return lam, ga

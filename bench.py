@@ -1,0 +1,303 @@
+#!/usr/bin/env python
+"""Throughput of the noisy Grover iteration on one MI355X.
+
+Default workload: one noisy Grover iteration (Oracle, HALL, Inv, HALL plus one D2
+noise rotation) on an n_q = 30 state in FP64 (2^30 amplitudes, 16 GiB), seed 1,
+inputs resident in HBM.  One step = one evaluation of that iteration (every
+pass over the state plus the FP64 readout of L and the norm).  Prints one JSON
+line: evaluations/s, the roofline of the dominant kernel (the fused pass), the
+FP32 variant's speedup at its stated tolerance, and the CPU oracle's rate.
+
+    python bench.py [--steps K] [--warmup W] [--extra]
+
+--extra adds the 4096-instance batched form and the n_q = 30 gradient check.
+"""
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "hot-path evaluations/sec on 1 MI355X + % roofline; mixed vs FP64 speedup at tol"
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pass_kernel.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_0902_0699_amd", "csrc", "pk_kernels.hip")
+FP32_TOL = 1e-5
+CPU_SAMPLE_NQ = 24
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def stored_traffic(kernel_name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when
+    the kernel source changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha") != kernel_sha() or t.get("kernel") != kernel_name:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def single_run(torch, pk, W, prec, seed, nq, steps, warmup):
+    """Times `steps` evaluations of one instance; returns a dict of figures."""
+    t0 = time.perf_counter()
+    inst = W.single_instance(seed, nq)
+    log("generated n_q=%d seed %d input in %.1fs" % (nq, seed, time.perf_counter() - t0))
+    plan = pk.Plan({"nq": nq, "gates": inst["gates"], "marked": inst["marked"]}, prec=prec)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    x = torch.from_numpy(inst["psi"]).to(dt).to("cuda")
+    del inst["psi"]
+    y = torch.empty_like(x)
+    L = torch.empty(1, dtype=torch.float64, device="cuda")
+    norm = torch.empty(1, dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        pk.evaluate_into(plan, x, y, L, norm)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        pk.evaluate_into(plan, x, y, L, norm)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = ev0.elapsed_time(ev1) / steps
+    log("%s: %.3f ms/evaluation over %d steps (wall %.3fs)" % (prec, ms, steps, wall))
+    # per-launch durations of the pass kernel, HIP events around each launch
+    reps = []
+    for _ in range(3):
+        reps.append(pk.time_passes(plan, x, y))
+    per_pass = [float(np.mean([r[p] for r in reps])) for p in range(len(reps[0]))]
+    return {"plan": plan, "x": x, "y": y, "L": float(L.item()), "norm": float(norm.item()),
+            "ms": ms, "wall": wall, "per_pass_ms": per_pass, "passes": plan.passes(), "inst": inst}
+
+
+def copy_probe(torch, x, y):
+    """Bandwidth of torch's device copy on the same buffers (read + write of the state)."""
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    y.copy_(x)
+    e0.record()
+    for _ in range(3):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    return 2.0 * x.numel() * x.element_size() / (ms * 1e-3) / 1e9, ms
+
+
+def cpu_baseline(W, nq_target, amp_sweeps_target):
+    """The oracle, as it stands, on one bounded sample: one evaluation at n_q = 24."""
+    import oracle as O
+    inst = W.single_instance(1, CPU_SAMPLE_NQ)
+    t0 = time.perf_counter()
+    O.evaluate(CPU_SAMPLE_NQ, inst["gates"], inst["marked"], inst["psi"])
+    t = time.perf_counter() - t0
+    sweeps_sample = 2 * CPU_SAMPLE_NQ + 2
+    scale = (2.0 ** nq_target / 2.0 ** CPU_SAMPLE_NQ) * (amp_sweeps_target / sweeps_sample)
+    log("cpu oracle: %.2fs at n_q=%d, x%.1f to n_q=%d" % (t, CPU_SAMPLE_NQ, scale, nq_target))
+    return {"value": 1.0 / (t * scale), "unit": "evaluations/s", "cores": 1, "kind": "oracle",
+            "sample": "one FP64 NumPy oracle evaluation of the same noisy iteration at n_q=%d (seed 1), "
+                      "%.2f s, scaled by N*(2 n_q + 2) amplitude-sweeps to n_q=%d" % (CPU_SAMPLE_NQ, t, nq_target),
+            "sample_seconds": t}
+
+
+def batched_run(torch, pk, W, steps, warmup, prec):
+    t0 = time.perf_counter()
+    insts = W.batch_instances(W.SEEDS["batched"])
+    log("generated %d batched instances in %.1fs" % (len(insts), time.perf_counter() - t0))
+    probs = [{"nq": i["nq"], "gates": i["gates"], "marked": i["marked"]} for i in insts]
+    plan = pk.Plan(probs, prec=prec)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    packed = torch.from_numpy(np.concatenate([i["psi"] for i in insts])).to(dt).to("cuda")
+    out = torch.empty_like(packed)
+    for _ in range(warmup):
+        pk.evaluate_batched(plan, packed, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        pk.evaluate_batched(plan, packed, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_batched = e0.elapsed_time(e1) / steps
+    # plain form: one single-instance evaluation per instance, back to back
+    offs = plan.offsets()
+    singles = [pk.Plan(p, prec=prec) for p in probs]
+    views = [(packed[offs[k]:offs[k + 1]], out[offs[k]:offs[k + 1]]) for k in range(len(probs))]
+    for s, (a, b) in zip(singles, views):
+        pk.evaluate(s, a, out=b)
+    torch.cuda.synchronize()
+    e0.record()
+    for s, (a, b) in zip(singles, views):
+        pk.evaluate(s, a, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_loop = e0.elapsed_time(e1)
+    total = offs[-1]
+    esz = 16 if prec == "fp64" else 8
+    return {"instances": len(insts), "amplitudes": total, "dtype": "f64" if prec == "fp64" else "f32",
+            "ms_per_batch": ms_batched, "instances_per_s": len(insts) / (ms_batched * 1e-3),
+            "ms_loop_of_singles": ms_loop, "speedup_vs_loop": ms_loop / ms_batched,
+            "compulsory_GBs": 2.0 * total * esz / (ms_batched * 1e-3) / 1e9}
+
+
+def gradient_run(torch, pk, W, nq):
+    inst = W.single_instance(W.SEEDS["gradient"], nq)
+    plan = pk.Plan({"nq": nq, "gates": inst["gates"], "marked": inst["marked"]})
+    x = torch.from_numpy(inst["psi"]).to("cuda")
+    ang = torch.tensor(list(inst["noise"][2:5]), dtype=torch.float64, device="cuda")
+    out, L, _ = pk.evaluate(plan, x, angles=ang, want_norm=False)
+    dL = torch.ones(1, dtype=torch.float64, device="cuda")
+    gpsi, gang = pk.backward(plan, out, dL, angles=ang)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        pk.backward(plan, out, dL, angles=ang)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_bwd = e0.elapsed_time(e1) / 3
+    comps = W.fd_subset(W.SEEDS["gradient"], inst)
+    h = 1e-6
+    L_of = lambda xx, aa: pk.evaluate(plan, xx, angles=aa, want_norm=False)[1].item()
+    fd, ad = [], []
+    for kind, where in comps:
+        if kind == "angle":
+            ap, am = ang.clone(), ang.clone()
+            ap[where] += h
+            am[where] -= h
+            fd.append((L_of(x, ap) - L_of(x, am)) / (2 * h))
+            ad.append(gang[where].item())
+        else:
+            idx, part = where
+            step = h if part == 0 else 1j * h
+            orig = x[idx].clone()
+            x[idx] = orig + step
+            lp = L_of(x, ang)
+            x[idx] = orig - step
+            lm = L_of(x, ang)
+            x[idx] = orig
+            fd.append((lp - lm) / (2 * h))
+            g = gpsi[idx].item()
+            ad.append(g.real if part == 0 else g.imag)
+    fd, ad = np.array(fd), np.array(ad)
+    err = float(np.max(np.abs(fd - ad)) / np.max(np.abs(ad)))
+    return {"nq": nq, "ms_backward": ms_bwd, "fd_inputs": len(comps), "fd_h": h,
+            "normwise_rel_err": err, "tol": 1e-6, "within_tol": err <= 1e-6,
+            "backward_passes": len(plan.describe()["instances"][0]["backward"])}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--nq", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--extra", action="store_true", help="also time the batched form and the gradient check")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this library runs on one GPU; a run on %d GPUs is not provided "
+              "(instances and amplitude blocks would shard across GPUs, but that path is not built)"
+              % max(args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_0902_0699_amd import paperkern as pk
+    from paper_0902_0699_amd import workload as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    nq = args.nq
+    N = 1 << nq
+    r64 = single_run(torch, pk, W, "fp64", W.SEEDS["large_fp64"], nq, args.steps, args.warmup)
+    value = 1000.0 / r64["ms"]
+    passes = r64["passes"]
+    # dominant kernel: the fused pass (every pass moves the whole state once: 32 B per amplitude)
+    bytes_per_launch = 32.0 * N
+    pass_ms = float(np.mean(r64["per_pass_ms"]))
+    achieved = bytes_per_launch / (pass_ms * 1e-3) / 1e9
+    kname = "pass_kernel<double,1,13>"
+    traffic = stored_traffic(kname)
+    copy_gbs, copy_ms = copy_probe(torch, r64["x"], r64["y"])
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "evaluations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "one noisy Grover iteration (Oracle, HALL, Inv, HALL, one D2 rotation) on "
+                               "a Haar-random n_q=%d state, FP64, seed 1" % nq,
+                   "nq": nq, "amplitudes": N, "passes": passes, "marked": 1},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "kernel": kname, "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "avg_launch_ms": pass_ms, "per_pass_ms": r64["per_pass_ms"]},
+        "compulsory_floor_frac": (32.0 * N / (r64["ms"] * 1e-3) / 1e9) / PEAK_HBM_GBS,
+        "copy_probe": {"GBs": copy_gbs, "ms": copy_ms, "frac_of_peak": copy_gbs / PEAK_HBM_GBS,
+                       "pass_frac_of_copy": achieved / copy_gbs},
+        "L": r64["L"], "norm": r64["norm"],
+    }
+    del r64
+    torch.cuda.empty_cache()
+    if not args.no_mixed:
+        r32 = single_run(torch, pk, W, "fp32", W.SEEDS["large_fp32"], nq, args.steps, args.warmup)
+        # accuracy at full size: the same instance through the FP64 path (parity-tested
+        # against the FP64 oracle) as the reference
+        plan64 = pk.Plan(r32["plan"].problems[0])
+        x64 = r32["x"].to(torch.complex128)
+        y64, L64, n64 = pk.evaluate(plan64, x64)
+        err = float(torch.linalg.vector_norm(r32["y"].to(torch.complex128) - y64) / torch.linalg.vector_norm(y64))
+        dL = abs(r32["L"] - L64.item())
+        line["mixed"] = {"dtype": "f32", "value": 1000.0 / r32["ms"], "ms_per_step": r32["ms"],
+                         "speedup_vs_fp64": line["ms_per_step"] / r32["ms"], "passes": r32["passes"],
+                         "rel_err_psi": err, "abs_err_L": dL, "L": r32["L"], "tol": FP32_TOL,
+                         "within_tol": err <= FP32_TOL and dL <= FP32_TOL,
+                         "reference": "FP64 path on the same FP32-rounded input",
+                         "avg_launch_ms": float(np.mean(r32["per_pass_ms"])),
+                         "achieved_GBs": 16.0 * N / (float(np.mean(r32["per_pass_ms"])) * 1e-3) / 1e9}
+        del r32, x64, y64
+        torch.cuda.empty_cache()
+    if args.extra:
+        line["batched"] = {p: batched_run(torch, pk, W, max(3, args.steps // 4), 1, p) for p in ("fp64", "fp32")}
+        torch.cuda.empty_cache()
+        line["gradient"] = gradient_run(torch, pk, W, nq)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(W, nq, 2 * nq + 2)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -9,8 +9,9 @@ Draw order for one instance, from ``numpy.random.default_rng(seed)`` (PCG64):
   qhit  = integers(1, nq + 1)     qubit struck by the noise rotation (Sec. 6.3)
   eloc  = integers(0, 5)          stage boundary of the noise rotation
   alpha = uniform(0, 2 pi), beta = uniform(0, pi), gamma = 0 (Sec. 6.3 footnote)
-  psi   = standard_normal(N) + 1j * standard_normal(N), then normalised:
-          a Haar-random pure state, the paper's domain being normalised states.
+  key   = integers(0, 2^63), then psi from per-block streams keyed by (key, block)
+          (see haar_state): complex normals, normalised -- a Haar-random pure
+          state, the paper's domain being normalised states.
 The batched workload first draws every n_q, then the instances in index order;
 instance 0 is the noise-free universe (its noise draws are made and ignored so
 that the stream does not depend on that rule).
@@ -21,11 +22,11 @@ Gate lists use the tuple vocabulary of the paper's routines:
 """
 
 import math
+import os
 
 import numpy as np
 
-CHUNK = 1 << 22
-NORM_BLOCK = 1 << 16
+BLOCK = 1 << 20  # amplitudes per independent random stream
 
 # Workload sizes: the single-instance parity case, the paper's largest case
 # ("up to 30 qubits", Sec. 1), and the multiverse batch.
@@ -38,20 +39,41 @@ BATCH_NQ_SPAN = 10
 SEEDS = {"small_fp64": 0, "large_fp64": 1, "large_fp32": 2, "batched": 3, "gradient": 4}
 
 
-def haar_state(rng, nq, chunk=CHUNK):
-    """Draw N real normals, then N imaginary normals, and normalise (chunked, same stream)."""
+def _block_normals(key, block, size):
+    """2*size normals of block ``block``: its own PCG64 stream keyed by (key, block)."""
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([key, block])))
+    return g.standard_normal(2 * size)
+
+
+def haar_state(rng, nq, threads=None):
+    """Haar-random pure state: complex normals, then normalised.
+
+    A 63-bit key is drawn from ``rng``; amplitude block b (BLOCK amplitudes)
+    takes 2*BLOCK normals from its own PCG64 stream seeded by (key, b): real
+    parts first, then imaginary parts.  Blocks are independent, so they are
+    drawn in parallel threads; the result does not depend on the thread count.
+    """
     size = 1 << nq
+    key = int(rng.integers(0, 1 << 63))
     psi = np.empty(size, dtype=np.complex128)
     pairs = psi.view(np.float64).reshape(size, 2)
-    for part in (0, 1):
-        for start in range(0, size, chunk):
-            stop = min(size, start + chunk)
-            pairs[start:stop, part] = rng.standard_normal(stop - start)
-    # Norm from fixed-size blocks combined with fsum, so it does not depend on ``chunk``.
-    sums = []
-    for start in range(0, size, NORM_BLOCK):
-        seg = pairs[start:start + NORM_BLOCK]
-        sums.append(float(np.einsum("ij,ij->", seg, seg)))
+    bsize = min(size, BLOCK)
+    nblocks = size // bsize
+
+    def fill(b):
+        z = _block_normals(key, b, bsize)
+        seg = pairs[b * bsize:(b + 1) * bsize]
+        seg[:, 0] = z[:bsize]
+        seg[:, 1] = z[bsize:]
+        return float(np.einsum("ij,ij->", seg, seg))
+
+    if nblocks == 1:
+        sums = [fill(0)]
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        workers = threads or min(16, os.cpu_count() or 1)
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            sums = list(ex.map(fill, range(nblocks)))
     psi /= math.sqrt(math.fsum(sums))
     return psi
 

@@ -358,11 +358,13 @@ def test_unitary_norm_invariant_random_circuit():
 # --------------------------------------------------------------------------- generator
 
 
-def test_generator_chunking_keeps_the_stream():
-    a = W.haar_state(np.random.default_rng(3), 12, chunk=1 << 12)
-    b = W.haar_state(np.random.default_rng(3), 12, chunk=1000)
+def test_generator_does_not_depend_on_thread_count():
+    a = W.haar_state(np.random.default_rng(3), 22, threads=1)
+    b = W.haar_state(np.random.default_rng(3), 22, threads=5)
     np.testing.assert_array_equal(a, b)
     assert abs(np.vdot(a, a).real - 1.0) < 1e-14
+    c = W.haar_state(np.random.default_rng(3), 8)
+    assert abs(np.vdot(c, c).real - 1.0) < 1e-14
 
 
 def test_generator_draw_order_and_domains():

@@ -22,7 +22,7 @@ constexpr int kMaxTileBits = 14;     // fp32 limit (fp64: 13), LDS = 2^k * eleme
 constexpr int kMaxQubits = 31;
 constexpr int kMaxNV = 2;            // vectors carried by a pass: psi, or psi and lambda
 
-enum OpKind : int16_t {
+enum OpKind : int32_t {
     OP_H = 0,      // unnormalised Hadamard butterfly (x+y, x-y) on register bit a
     OP_MAT = 1,    // 2x2 complex matrix mats[arg] on register bit a
     OP_FLIP = 2,   // negate the amplitude flips[arg] (Oracle items, Inv's C_0 fix)
@@ -32,18 +32,20 @@ enum OpKind : int16_t {
     OP_D2BWD = 6,  // backward D2: psi <- D^H psi, grad += Re<lambda|dD|psi>, lambda <- D^H lambda
 };
 
+// All table fields are 32- or 64-bit so that the kernels read them with scalar
+// loads from the constant address space.
 struct Op {
-    int16_t kind;
-    int8_t a;      // register bit 0..3 for OP_H / OP_MAT / OP_D2BWD
-    int8_t pad;
-    int32_t arg;   // matrix index (OP_MAT, OP_D2BWD: first of its five), flip index (FLIP/READ/SEED)
-    float gscale;  // OP_D2BWD: 1/s^2 for the deferred scale s carried at that point
-    int32_t gslot; // OP_D2BWD: base of this gate's gradient partials
+    int32_t kind;
+    int32_t a;      // register bit 0..3 for OP_H / OP_MAT / OP_D2BWD
+    int32_t arg;    // matrix index (OP_MAT, OP_D2BWD: first of its five), flip index (FLIP/READ/SEED)
+    int32_t gslot;  // OP_D2BWD: base of this gate's gradient partials
+    float gscale;   // OP_D2BWD: 1/s^2 for the deferred scale s carried at that point
+    int32_t pad;
 };
 
 struct Stage {
-    int8_t rb[kRegBits];  // local tile bit held by register bit a (-1 when the tile has < 4 bits)
-    int8_t rbs[kRegBits]; // the same bits sorted ascending (-1 entries last)
+    int32_t rb[kRegBits];  // local tile bit held by register bit a (-1 when the tile has < 4 bits)
+    int32_t rbs[kRegBits]; // the same bits sorted ascending (-1 entries last)
     int32_t op_begin;
     int32_t op_count;
 };
@@ -58,29 +60,34 @@ struct Flip {
 enum PassFlags : int32_t {
     PASS_FIRST = 1,    // read from the input buffers
     PASS_LAST = 2,     // final pass of the instance
-    PASS_NORM = 4,     // accumulate sum |C|^2 partials (when norm requested)
+    PASS_NORM = 4,     // (reserved)
     PASS_SKIP_V0 = 8,  // do not store vector 0 (backward: the recovered psi_in is not needed)
     PASS_SEED_V1 = 16, // vector 1 is not read: it starts as zero and is seeded (backward start)
+    PASS_WIDE = 32,    // a thread's byte offset inside a tile may exceed 32 bits
+};
+
+constexpr int kMaxRuns = 16;
+
+// A run (src, len, dst) moves bits src..src+len-1 of a label to dst..dst+len-1.
+struct Run {
+    int32_t src, len, dst, pad;
 };
 
 struct Pass {
     int32_t k;           // tile bits
-    int32_t nfree;       // nq - k free bits (tile id bits)
     int32_t nstages;
     int32_t stage_begin;
-    int64_t ntiles;      // 2^nfree
-    int64_t state_off;   // element offset of the instance in the packed buffer
     int32_t flags;
-    int32_t inst;
+    int64_t ntiles;      // 2^(nq - k)
+    int64_t state_off;   // element offset of the instance in the packed buffer
     double scale;        // applied by OP_SCALE
     int32_t part_base;   // norm partials: part_base + tile
     int32_t kmax;        // kernel instance (workgroup = 2^(kmax-4) threads)
     int32_t ntrun;       // runs of consecutive tile bits
     int32_t nfrun;       // runs of consecutive free bits
-    int8_t tpos[16];     // global bit position of local tile bit l
-    // A run (src, len, dst) moves bits src..src+len-1 of a label to dst..dst+len-1.
-    int8_t trun[16][3];  // local tile label -> state label
-    int8_t frun[16][3];  // tile index -> state label
+    int32_t tpos[16];    // global bit position of local tile bit l
+    Run trun[kMaxRuns];  // local tile label -> state label
+    Run frun[kMaxRuns];  // tile index -> state label
 };
 
 // Per-instance entry of a batched launch: one workgroup runs all passes of

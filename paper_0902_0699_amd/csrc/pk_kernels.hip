@@ -16,6 +16,11 @@
 #include "pk_desc.h"
 #include "pk_launch.h"
 
+// Descriptor tables are read through the constant address space so that the
+// uniform reads become scalar loads: they then never wait on vector memory
+// traffic (the prefetched tile, the previous tile's stores).
+#define PK_CONST __attribute__((address_space(4)))
+
 namespace pk {
 
 template <typename R>
@@ -46,23 +51,25 @@ struct KArgs {
     int32_t want_norm;
 };
 
-// LDS bank swizzle on 16-byte slots: XOR of the label's higher 3-bit groups
-// into its low 3 bits.  Linear over XOR, so phys(a ^ b) = phys(a) ^ phys(b).
-__device__ __forceinline__ unsigned phys(unsigned j) {
-    return j ^ (((j >> 3) ^ (j >> 6) ^ (j >> 9) ^ (j >> 12)) & 7u);
+template <typename X>
+__device__ __forceinline__ const PK_CONST X* cptr(const X* p) {
+    return (const PK_CONST X*)(p);
 }
 
-// Thread index spread over the local bits that are not register bits.
-__device__ __forceinline__ unsigned thread_label(unsigned t, const Stage* S, int nrb) {
-    for (int q = 0; q < nrb; ++q) {
-        const int p = S->rbs[q];
-        t = ((t >> p) << (p + 1)) | (t & ((1u << p) - 1u));
-    }
-    return t;
+// LDS bank swizzle on element slots: the label's higher W-bit groups are XORed
+// into its low W bits, with 2^W elements = 256 bytes, one pass over the LDS
+// banks.  Whatever bits a stage puts on the lane index, any 256 contiguous
+// bytes' worth of lanes then hit distinct banks.  Linear over XOR, so
+// phys(a ^ b) = phys(a) ^ phys(b).
+template <int ESZ>
+__device__ __forceinline__ unsigned phys(unsigned j) {
+    constexpr int W = ESZ == 16 ? 4 : 5;
+    constexpr unsigned M = (1u << W) - 1u;
+    return j ^ (((j >> W) ^ (j >> (2 * W)) ^ (j >> (3 * W))) & M);
 }
 
 // Layout of one stage: per-thread label base and the uniform offsets of the
-// four register bits (as labels, as LDS slots and as state offsets).
+// four register bits (as labels and as LDS slots).
 struct Layout {
     unsigned jt;     // thread's label base
     unsigned pj;     // phys(jt)
@@ -70,14 +77,21 @@ struct Layout {
     unsigned p[4];   // phys(1 << rb[a])
 };
 
-__device__ __forceinline__ Layout make_layout(const Stage* S, int nrb, unsigned tid) {
+template <int ESZ>
+__device__ __forceinline__ Layout make_layout(const PK_CONST Stage* S, int nrb, unsigned tid) {
     Layout L;
-    L.jt = thread_label(tid, S, nrb);
-    L.pj = phys(L.jt);
+    unsigned t = tid;
+    // spread the thread index over the local bits that are not register bits
+    for (int q = 0; q < nrb; ++q) {
+        const int p = S->rbs[q];
+        t = ((t >> p) << (p + 1)) | (t & ((1u << p) - 1u));
+    }
+    L.jt = t;
+    L.pj = phys<ESZ>(t);
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
         L.r[a] = a < nrb ? (1u << S->rb[a]) : 0u;
-        L.p[a] = phys(L.r[a]);
+        L.p[a] = phys<ESZ>(L.r[a]);
     }
     return L;
 }
@@ -91,23 +105,25 @@ __device__ __forceinline__ unsigned poff(const Layout& L, int i) {
            ((i & 8) ? L.p[3] : 0u);
 }
 
-// State offsets of a stage used for HBM access: thread part and register parts.
-struct GOff {
-    int64_t gt;
-    int64_t g[4];
-};
-
 // Moves the bits of `x` along the runs (src, len, dst).
-__device__ __forceinline__ int64_t deposit(int64_t x, const int8_t (*run)[3], int nrun) {
+__device__ __forceinline__ int64_t deposit(int64_t x, const PK_CONST Run* run, int nrun) {
     int64_t r = 0;
     for (int q = 0; q < nrun; ++q) {
-        const int src = run[q][0], len = run[q][1], dst = run[q][2];
+        const int src = run[q].src, len = run[q].len, dst = run[q].dst;
         r |= ((x >> src) & (((int64_t)1 << len) - 1)) << dst;
     }
     return r;
 }
 
-__device__ __forceinline__ GOff make_goff(const Pass* P, const Stage* S, const Layout& L, int nrb) {
+// State offsets of a stage used for HBM access: the thread's part (elements)
+// and the uniform parts of the four register bits.
+struct GOff {
+    int64_t gt;
+    int64_t g[4];
+};
+
+__device__ __forceinline__ GOff make_goff(const PK_CONST Pass* P, const PK_CONST Stage* S, const Layout& L,
+                                          int nrb) {
     GOff G;
     G.gt = deposit((int64_t)L.jt, P->trun, P->ntrun);
 #pragma unroll
@@ -163,7 +179,7 @@ __device__ __forceinline__ void op_m(T (&v)[NV][16], const R (&m)[8]) {
 // g += Re( conj(lambda) . (dD/dtheta) psi ); then lambda <- D^H lambda.
 // One derivative matrix at a time keeps the register footprint small.
 template <int A, int NV, typename T, typename R>
-__device__ __forceinline__ void op_d2bwd(T (&v)[NV][16], const R (&mh)[8], const double* dmats,
+__device__ __forceinline__ void op_d2bwd(T (&v)[NV][16], const R (&mh)[8], const PK_CONST double* dmats,
                                          double (&g)[3]) {
     if constexpr (NV == 2) {
 #pragma unroll
@@ -216,8 +232,8 @@ __device__ __forceinline__ void dispatch_m(T (&v)[NV][16], int a, const R (&m)[8
 }
 
 template <int NV, typename T, typename R>
-__device__ __forceinline__ void dispatch_d2bwd(T (&v)[NV][16], int a, const R (&mh)[8], const double* dmats,
-                                               double (&g)[3]) {
+__device__ __forceinline__ void dispatch_d2bwd(T (&v)[NV][16], int a, const R (&mh)[8],
+                                               const PK_CONST double* dmats, double (&g)[3]) {
     switch (a) {
     case 0: op_d2bwd<0, NV>(v, mh, dmats, g); break;
     case 1: op_d2bwd<1, NV>(v, mh, dmats, g); break;
@@ -244,55 +260,118 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
 
 // ---------------------------------------------------------------------------- one tile
 
-template <typename R, int NV, int KMAX>
-__device__ __forceinline__ void process_tile(const KArgs& a, const Pass* __restrict__ P, int64_t tile,
-                                             typename Cplx<R>::T* lds, double* red) {
-    using T = typename Cplx<R>::T;
-    constexpr int NT = 1 << (KMAX - 4);
+// Per-pass constants of a workgroup: they do not depend on the tile.
+struct PassCtx {
+    int nrb, nreg, flags, nstages;
+    bool active;
+    Layout L0, Ll;  // first (load) and last (store) stage layouts
+    GOff G0, Gl;
+};
+
+template <int ESZ>
+__device__ __forceinline__ PassCtx make_ctx(const KArgs& a, const PK_CONST Pass* P) {
+    PassCtx C;
     const int k = P->k;
-    const int nrb = k < 4 ? k : 4;
-    const int nreg = 1 << nrb;
-    const unsigned tid = threadIdx.x;
+    C.nrb = k < 4 ? k : 4;
+    C.nreg = 1 << C.nrb;
+    C.flags = P->flags;
+    C.nstages = P->nstages;
     const unsigned nact = k >= 4 ? (1u << (k - 4)) : 1u;
-    const bool active = tid < nact;
+    C.active = threadIdx.x < nact;
+    const PK_CONST Stage* S0 = cptr(a.stages) + P->stage_begin;
+    const PK_CONST Stage* Sl = S0 + (C.nstages - 1);
+    C.L0 = make_layout<ESZ>(S0, C.nrb, threadIdx.x);
+    C.Ll = make_layout<ESZ>(Sl, C.nrb, threadIdx.x);
+    C.G0 = make_goff(P, S0, C.L0, C.nrb);
+    C.Gl = make_goff(P, Sl, C.Ll, C.nrb);
+    return C;
+}
 
-    const int64_t base = P->state_off + deposit(tile, P->frun, P->nfrun);
-    const int flags = P->flags;
-
-    T v[NV][16];
+// HBM -> registers in the first stage's layout.  `base` is the tile's first
+// state label.  The uniform part (tile base + register offset) and the thread's
+// part stay apart, so each load is a 64-bit scalar base plus a 32-bit lane
+// offset; a wide pass (lane offsets beyond 32 bits) adds in 64 bits.
+template <typename R, int NV>
+__device__ __forceinline__ void load_tile(const KArgs& a, const PassCtx& C, int64_t base,
+                                          typename Cplx<R>::T (&v)[NV][16]) {
+    using T = typename Cplx<R>::T;
+    if (C.nreg < 16 || NV == 2) {
 #pragma unroll
-    for (int n = 0; n < NV; ++n)
+        for (int n = 0; n < NV; ++n)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) v[n][i] = T{0, 0};
-
-    // ---- load in the first stage's layout
-    const Stage* S = a.stages + P->stage_begin;
-    Layout L = make_layout(S, nrb, tid);
-    {
-        const GOff G = make_goff(P, S, L, nrb);
-        const T* in0 = reinterpret_cast<const T*>((flags & PASS_FIRST) ? a.src0 : a.dst0);
-        if (active) {
+            for (int i = 0; i < 16; ++i) v[n][i] = T{0, 0};
+    }
+    if (!C.active) return;
+    const char* in0 = reinterpret_cast<const char*>((C.flags & PASS_FIRST) ? a.src0 : a.dst0);
+    const char* in1 = reinterpret_cast<const char*>(a.dst1);
+    const bool read1 = NV == 2 && !(C.flags & PASS_SEED_V1);
+    if (!(C.flags & PASS_WIDE)) {
+        const uint32_t lane = (uint32_t)C.G0.gt * (uint32_t)sizeof(T);
 #pragma unroll
-            for (int i = 0; i < 16; ++i)
-                if (i < nreg) v[0][i] = in0[base + G.gt + goff(G, i)];
-            if constexpr (NV == 2) {
-                if (!(flags & PASS_SEED_V1)) {
-                    const T* in1 = reinterpret_cast<const T*>(a.dst1);
+        for (int i = 0; i < 16; ++i) {
+            if (i >= C.nreg) continue;
+            const int64_t u = (base + goff(C.G0, i)) * (int64_t)sizeof(T);
+            v[0][i] = *reinterpret_cast<const T*>(in0 + u + lane);
+            if constexpr (NV == 2)
+                if (read1) v[1][i] = *reinterpret_cast<const T*>(in1 + u + lane);
+        }
+    } else {
 #pragma unroll
-                    for (int i = 0; i < 16; ++i)
-                        if (i < nreg) v[1][i] = in1[base + G.gt + goff(G, i)];
-                }
-            }
+        for (int i = 0; i < 16; ++i) {
+            if (i >= C.nreg) continue;
+            const int64_t e = base + C.G0.gt + goff(C.G0, i);
+            v[0][i] = reinterpret_cast<const T*>(in0)[e];
+            if constexpr (NV == 2)
+                if (read1) v[1][i] = reinterpret_cast<const T*>(in1)[e];
         }
     }
+}
 
-    double nsum = 0.0, ncomp = 0.0;
-    const int nstages = P->nstages;
-    for (int s = 0; s < nstages; ++s) {
+// Registers -> HBM in the last stage's layout.
+template <typename R, int NV>
+__device__ __forceinline__ void store_tile(const KArgs& a, const PassCtx& C, int64_t base,
+                                           const typename Cplx<R>::T (&v)[NV][16]) {
+    using T = typename Cplx<R>::T;
+    if (!C.active) return;
+    char* out0 = reinterpret_cast<char*>(a.dst0);
+    char* out1 = reinterpret_cast<char*>(a.dst1);
+    const bool write0 = !(C.flags & PASS_SKIP_V0);
+    if (!(C.flags & PASS_WIDE)) {
+        const uint32_t lane = (uint32_t)C.Gl.gt * (uint32_t)sizeof(T);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (i >= C.nreg) continue;
+            const int64_t u = (base + goff(C.Gl, i)) * (int64_t)sizeof(T);
+            if (write0) *reinterpret_cast<T*>(out0 + u + lane) = v[0][i];
+            if constexpr (NV == 2) *reinterpret_cast<T*>(out1 + u + lane) = v[1][i];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (i >= C.nreg) continue;
+            const int64_t e = base + C.Gl.gt + goff(C.Gl, i);
+            if (write0) reinterpret_cast<T*>(out0)[e] = v[0][i];
+            if constexpr (NV == 2) reinterpret_cast<T*>(out1)[e] = v[1][i];
+        }
+    }
+}
+
+// Every stage of the pass on one tile held in registers, then the norm partial.
+template <typename R, int NV, int KMAX>
+__device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass* P, const PassCtx& C,
+                                             int64_t tile, typename Cplx<R>::T (&v)[NV][16],
+                                             typename Cplx<R>::T* lds, double* red) {
+    constexpr int NT = 1 << (KMAX - 4);
+    const unsigned tid = threadIdx.x;
+    const bool active = C.active;
+    const int nreg = C.nreg;
+    const PK_CONST Stage* S = cptr(a.stages) + P->stage_begin;
+    Layout L = C.L0;
+    for (int s = 0; s < C.nstages; ++s) {
         if (s > 0) {
             // ---- LDS exchange: previous layout out, this layout in
-            const Stage* Sn = a.stages + P->stage_begin + s;
-            const Layout Ln = make_layout(Sn, nrb, tid);
+            const PK_CONST Stage* Sn = S + 1;
+            const Layout Ln = (s == C.nstages - 1) ? C.Ll : make_layout<(int)sizeof(R) * 2>(Sn, C.nrb, tid);
 #pragma unroll
             for (int n = 0; n < NV; ++n) {
                 if (active) {
@@ -313,43 +392,46 @@ __device__ __forceinline__ void process_tile(const KArgs& a, const Pass* __restr
         }
         // ---- the stage's gates, in order
         const int op_count = S->op_count;
-        const Op* ops = a.ops + S->op_begin;
+        const PK_CONST Op* ops = cptr(a.ops) + S->op_begin;
         for (int o = 0; o < op_count; ++o) {
-            const Op op = ops[o];
-            switch (op.kind) {
+            const int kind = ops[o].kind;
+            const int ra = ops[o].a;
+            const int arg = ops[o].arg;
+            switch (kind) {
             case OP_H:
-                dispatch_h<NV>(v, op.a);
+                dispatch_h<NV>(v, ra);
                 break;
             case OP_MAT: {
                 R m[8];
-                const double* mp = a.mats + 8 * op.arg;
+                const PK_CONST double* mp = cptr(a.mats) + 8 * arg;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) m[e] = (R)mp[e];
-                dispatch_m<NV>(v, op.a, m);
+                dispatch_m<NV>(v, ra, m);
                 break;
             }
             case OP_FLIP:
             case OP_READ:
             case OP_SEED: {
-                const Flip f = a.flips[op.arg];
-                if (f.tile == tile && active) {
-                    const unsigned jrel = (unsigned)f.j ^ L.jt;
+                const PK_CONST Flip* f = cptr(a.flips) + arg;
+                if (f->tile == tile && active) {
+                    const unsigned jrel = (unsigned)f->j ^ L.jt;
                     const unsigned rmask = L.r[0] | L.r[1] | L.r[2] | L.r[3];
+                    const int slot = f->slot;
                     if ((jrel & ~rmask) == 0u) {
 #pragma unroll
                         for (int i = 0; i < 16; ++i) {
                             if (i < nreg && roff(L, i) == jrel) {
-                                if (op.kind == OP_FLIP) {
+                                if (kind == OP_FLIP) {
 #pragma unroll
                                     for (int n = 0; n < NV; ++n) {
                                         v[n][i].x = -v[n][i].x;
                                         v[n][i].y = -v[n][i].y;
                                     }
-                                } else if (op.kind == OP_READ) {
+                                } else if (kind == OP_READ) {
                                     const double x = v[0][i].x, y = v[0][i].y;
-                                    a.reads[f.slot] = x * x + y * y;
+                                    a.reads[slot] = x * x + y * y;
                                 } else if constexpr (NV == 2) {
-                                    const R d = (R)a.dL[f.slot];
+                                    const R d = (R)a.dL[slot];
                                     v[1][i].x = d * v[0][i].x;
                                     v[1][i].y = d * v[0][i].y;
                                 }
@@ -372,16 +454,17 @@ __device__ __forceinline__ void process_tile(const KArgs& a, const Pass* __restr
             }
             case OP_D2BWD: {
                 R mh[8];
-                const double* mp = a.mats + 8 * op.arg;
+                const PK_CONST double* mp = cptr(a.mats) + 8 * arg;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) mh[e] = (R)mp[8 + e];
                 double g[3] = {0.0, 0.0, 0.0};
-                if (active) dispatch_d2bwd<NV>(v, op.a, mh, mp + 16, g);
-                const double scale = 2.0 * (double)op.gscale;
+                if (active) dispatch_d2bwd<NV>(v, ra, mh, mp + 16, g);
+                const double scale = 2.0 * (double)ops[o].gscale;
+                const int gslot = ops[o].gslot;
 #pragma unroll
                 for (int t = 0; t < 3; ++t) {
                     const double tot = block_sum<NT>(g[t], red);
-                    if (tid == 0) a.gpart[op.gslot + t * P->ntiles + tile] = scale * tot;
+                    if (tid == 0) a.gpart[gslot + t * P->ntiles + tile] = scale * tot;
                 }
                 break;
             }
@@ -393,7 +476,7 @@ __device__ __forceinline__ void process_tile(const KArgs& a, const Pass* __restr
 
     // ---- norm partial of the final state (FP64 for FP64 data; Neumaier-
     //      compensated FP32 lane sums, then FP64, for FP32 data)
-    if (a.want_norm && (flags & PASS_LAST)) {
+    if (a.want_norm && (C.flags & PASS_LAST)) {
         double part = 0.0;
         if (active) {
             if constexpr (sizeof(R) == 8) {
@@ -416,25 +499,52 @@ __device__ __forceinline__ void process_tile(const KArgs& a, const Pass* __restr
         const double tot = block_sum<NT>(part, red);
         if (tid == 0) a.partials[P->part_base + tile] = tot;
     }
-    (void)nsum;
-    (void)ncomp;
+}
 
-    // ---- store in the last stage's layout
-    {
-        const GOff G = make_goff(P, S, L, nrb);
-        if (active) {
-            if (!(flags & PASS_SKIP_V0)) {
-                T* out0 = reinterpret_cast<T*>(a.dst0);
-#pragma unroll
-                for (int i = 0; i < 16; ++i)
-                    if (i < nreg) out0[base + G.gt + goff(G, i)] = v[0][i];
-            }
-            if constexpr (NV == 2) {
-                T* out1 = reinterpret_cast<T*>(a.dst1);
-#pragma unroll
-                for (int i = 0; i < 16; ++i)
-                    if (i < nreg) out1[base + G.gt + goff(G, i)] = v[1][i];
-            }
+// Tiles first, first + stride, ... of one pass.  With one vector, two register
+// buffers alternate: the next tile's HBM loads are issued before the current
+// tile's LDS stages, so memory traffic overlaps the exchange work of the one
+// workgroup an LDS-sized tile leaves per CU.  The prefetch is unconditional
+// (past the end it re-reads the current tile) so the wait counts stay static.
+template <typename R, int NV, int KMAX>
+__device__ __forceinline__ void run_tiles(const KArgs& a, const PK_CONST Pass* P, int64_t first,
+                                          int64_t stride, typename Cplx<R>::T* lds, double* red) {
+    using T = typename Cplx<R>::T;
+    const int64_t ntiles = P->ntiles;
+    if (first >= ntiles) return;
+    const PassCtx C = make_ctx<(int)sizeof(R) * 2>(a, P);
+    const int64_t off = P->state_off;
+    const int nfrun = P->nfrun;
+    auto base_of = [&](int64_t t) { return off + deposit(t, P->frun, nfrun); };
+    if constexpr (NV == 2) {
+        // two vectors already fill the register file: no second buffer
+        for (int64_t tile = first; tile < ntiles; tile += stride) {
+            T v[NV][16];
+            const int64_t base = base_of(tile);
+            load_tile<R, NV>(a, C, base, v);
+            compute_tile<R, NV, KMAX>(a, P, C, tile, v, lds, red);
+            store_tile<R, NV>(a, C, base, v);
+        }
+    } else {
+        T va[1][16], vb[1][16];
+        int64_t ta = first;
+        int64_t basea = base_of(ta);
+        load_tile<R, 1>(a, C, basea, va);
+        for (;;) {
+            const int64_t tb = ta + stride;
+            const int64_t baseb = base_of(tb < ntiles ? tb : ta);
+            load_tile<R, 1>(a, C, baseb, vb);
+            compute_tile<R, 1, KMAX>(a, P, C, ta, va, lds, red);
+            store_tile<R, 1>(a, C, basea, va);
+            if (tb >= ntiles) break;
+            const int64_t tc = tb + stride;
+            const int64_t basec = base_of(tc < ntiles ? tc : tb);
+            load_tile<R, 1>(a, C, basec, va);
+            compute_tile<R, 1, KMAX>(a, P, C, tb, vb, lds, red);
+            store_tile<R, 1>(a, C, baseb, vb);
+            if (tc >= ntiles) break;
+            ta = tc;
+            basea = basec;
         }
     }
 }
@@ -446,18 +556,15 @@ __global__ void __launch_bounds__(1 << (KMAX - 4)) pass_kernel(KArgs a) {
     using T = typename Cplx<R>::T;
     __shared__ T lds[1 << KMAX];
     __shared__ double red[16];
-    const Pass* P = a.passes + a.pass;
-    const int64_t ntiles = P->ntiles;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-        process_tile<R, NV, KMAX>(a, P, tile, lds, red);
+    run_tiles<R, NV, KMAX>(a, cptr(a.passes) + a.pass, blockIdx.x, gridDim.x, lds, red);
 }
 
 // Multiverse batch: each workgroup takes whole instances from a queue (largest
 // first) and runs all their passes itself, then writes L and the norm.
 template <typename R, int KMAX>
 __global__ void __launch_bounds__(1 << (KMAX - 4))
-    batched_kernel(KArgs a, const InstDesc* idesc, const int32_t* order, int32_t n_inst,
-                   unsigned int* queue, double* L_out, double* norm_out) {
+    batched_kernel(KArgs a, const InstDesc* idesc, const int32_t* order, int32_t n_inst, unsigned int* queue,
+                   double* L_out, double* norm_out) {
     using T = typename Cplx<R>::T;
     constexpr int NT = 1 << (KMAX - 4);
     __shared__ T lds[1 << KMAX];
@@ -469,24 +576,24 @@ __global__ void __launch_bounds__(1 << (KMAX - 4))
         const int it = item;
         __syncthreads();
         if (it >= n_inst) break;
-        const int inst = order[it];
-        const InstDesc D = idesc[inst];
-        for (int p = 0; p < D.npass; ++p) {
-            const Pass* P = a.passes + D.first_pass + p;
-            const int64_t ntiles = P->ntiles;
-            for (int64_t tile = 0; tile < ntiles; ++tile) process_tile<R, 1, KMAX>(a, P, tile, lds, red);
+        const int inst = cptr(order)[it];
+        const PK_CONST InstDesc* D = cptr(idesc) + inst;
+        const int npass = D->npass;
+        for (int p = 0; p < npass; ++p) {
+            run_tiles<R, 1, KMAX>(a, cptr(a.passes) + D->first_pass + p, 0, 1, lds, red);
             // this workgroup's stores must be visible to its own loads of the next pass
             __threadfence_block();
             __syncthreads();
         }
         if (threadIdx.x == 0) {
             double L = 0.0;
-            for (int m = 0; m < D.nmarked; ++m) L += a.reads[D.read_base + m];
+            for (int m = 0; m < D->nmarked; ++m) L += a.reads[D->read_base + m];
             L_out[inst] = L;
         }
         if (norm_out) {
             double s = 0.0;
-            for (int64_t t = threadIdx.x; t < D.ntiles_last; t += NT) s += a.partials[D.part_base + t];
+            const int64_t nt = D->ntiles_last, pb = D->part_base;
+            for (int64_t t = threadIdx.x; t < nt; t += NT) s += a.partials[pb + t];
             const double tot = block_sum<NT>(s, red);
             if (threadIdx.x == 0) norm_out[inst] = tot;
         }
@@ -561,23 +668,35 @@ __global__ void pair_index_kernel(int32_t nq, int32_t i_s, int64_t first, int64_
 
 // ---------------------------------------------------------------------------- host launchers
 
+// Persistent launch: as many workgroups as fit on the device at once (capped by
+// the tile count); each walks its tiles with the load of the next one in flight.
 template <typename R, int NV, int KMAX>
-static hipError_t launch_pass_t(const KArgs& a, int64_t ntiles, hipStream_t st) {
-    const int64_t cap = (int64_t)1 << 30;
-    const unsigned grid = (unsigned)(ntiles < cap ? ntiles : cap);
-    hipLaunchKernelGGL((pass_kernel<R, NV, KMAX>), dim3(grid), dim3(1 << (KMAX - 4)), 0, st, a);
+static hipError_t launch_pass_t(const KArgs& a, int64_t ntiles, int64_t grid_cap, hipStream_t st) {
+    static int resident = 0;  // workgroups per device, queried once per kernel instance
+    if (resident == 0) {
+        int dev = 0, ncu = 0, per_cu = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        auto kfn = pass_kernel<R, NV, KMAX>;
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, 1 << (KMAX - 4), 0);
+        resident = (ncu > 0 ? ncu : 256) * (per_cu > 0 ? per_cu : 1);
+    }
+    int64_t grid = grid_cap > 0 ? grid_cap : resident;
+    if (grid > ntiles) grid = ntiles;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL((pass_kernel<R, NV, KMAX>), dim3((unsigned)grid), dim3(1 << (KMAX - 4)), 0, st, a);
     return hipGetLastError();
 }
 
 template <typename R, int NV>
-static hipError_t launch_pass_r(int kmax, const KArgs& a, int64_t ntiles, hipStream_t st) {
+static hipError_t launch_pass_r(int kmax, const KArgs& a, int64_t ntiles, int64_t cap, hipStream_t st) {
     switch (kmax) {
-    case 10: return launch_pass_t<R, NV, 10>(a, ntiles, st);
-    case 11: return launch_pass_t<R, NV, 11>(a, ntiles, st);
-    case 12: return launch_pass_t<R, NV, 12>(a, ntiles, st);
-    case 13: return launch_pass_t<R, NV, 13>(a, ntiles, st);
+    case 10: return launch_pass_t<R, NV, 10>(a, ntiles, cap, st);
+    case 11: return launch_pass_t<R, NV, 11>(a, ntiles, cap, st);
+    case 12: return launch_pass_t<R, NV, 12>(a, ntiles, cap, st);
+    case 13: return launch_pass_t<R, NV, 13>(a, ntiles, cap, st);
     case 14:
-        if constexpr (sizeof(R) == 4) return launch_pass_t<R, NV, 14>(a, ntiles, st);
+        if constexpr (sizeof(R) == 4) return launch_pass_t<R, NV, 14>(a, ntiles, cap, st);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
@@ -600,11 +719,11 @@ hipError_t launch_pass(const PassLaunch& L, hipStream_t st) {
     a.pass = L.pass;
     a.want_norm = L.want_norm;
     if (L.fp64) {
-        return L.nv == 2 ? launch_pass_r<double, 2>(L.kmax, a, L.ntiles, st)
-                         : launch_pass_r<double, 1>(L.kmax, a, L.ntiles, st);
+        return L.nv == 2 ? launch_pass_r<double, 2>(L.kmax, a, L.ntiles, L.grid_cap, st)
+                         : launch_pass_r<double, 1>(L.kmax, a, L.ntiles, L.grid_cap, st);
     }
-    return L.nv == 2 ? launch_pass_r<float, 2>(L.kmax, a, L.ntiles, st)
-                     : launch_pass_r<float, 1>(L.kmax, a, L.ntiles, st);
+    return L.nv == 2 ? launch_pass_r<float, 2>(L.kmax, a, L.ntiles, L.grid_cap, st)
+                     : launch_pass_r<float, 1>(L.kmax, a, L.ntiles, L.grid_cap, st);
 }
 
 template <typename R, int KMAX>

@@ -275,7 +275,7 @@ struct Compiler {
                         hs.ops.push_back(o);
                     } else {
                         Op o{};
-                        o.a = (int8_t)reg_of(local_of[p.bit]);
+                        o.a = reg_of(local_of[p.bit]);
                         if (p.gk == Prim::GH) {
                             o.kind = OP_H;
                             ++sc.h;
@@ -496,32 +496,30 @@ int recompile(Plan* plan, std::string* err) {
     auto emit = [&](Instance& in, int idx, HostPass& hp) {
         Pass p{};
         p.k = hp.k;
-        p.nfree = in.nq - hp.k;
         p.nstages = (int)hp.stages.size();
         p.stage_begin = (int)plan->stages.size();
         p.ntiles = hp.ntiles;
         p.state_off = in.off;
         p.flags = hp.flags;
-        p.inst = idx;
         p.scale = hp.scale;
         p.part_base = hp.part_base;
         p.kmax = hp.kmax;
-        std::memset(p.tpos, -1, sizeof p.tpos);
-        for (int l = 0; l < hp.k; ++l) p.tpos[l] = (int8_t)hp.tbits[l];
+        for (int l = 0; l < 16; ++l) p.tpos[l] = l < hp.k ? hp.tbits[l] : -1;
         std::vector<char> used(in.nq, 0);
         for (int b : hp.tbits) used[b] = 1;
         std::vector<int> fbits;
         for (int b = 0; b < in.nq; ++b)
             if (!used[b]) fbits.push_back(b);
         // runs of consecutive positions: (source bit, length, destination bit)
-        auto runs = [](const std::vector<int>& pos, int8_t (*out)[3]) {
+        auto runs = [](const std::vector<int>& pos, Run* out) {
             int n = 0;
             for (size_t i = 0; i < pos.size();) {
                 size_t j = i + 1;
                 while (j < pos.size() && pos[j] == pos[j - 1] + 1) ++j;
-                out[n][0] = (int8_t)i;
-                out[n][1] = (int8_t)(j - i);
-                out[n][2] = (int8_t)pos[i];
+                out[n].src = (int32_t)i;
+                out[n].len = (int32_t)(j - i);
+                out[n].dst = pos[i];
+                out[n].pad = 0;
                 ++n;
                 i = j;
             }
@@ -529,12 +527,24 @@ int recompile(Plan* plan, std::string* err) {
         };
         p.ntrun = runs(hp.tbits, p.trun);
         p.nfrun = runs(fbits, p.frun);
+        // byte offsets of a thread inside a tile in the load / store layouts
+        const int esz = plan->prec == PK_FP64 ? 16 : 8;
+        for (int which = 0; which < 2; ++which) {
+            const HostStage& hs = which == 0 ? hp.stages.front() : hp.stages.back();
+            uint64_t maxoff = 0;
+            for (int l = 0; l < hp.k; ++l) {
+                bool reg = false;
+                for (int a = 0; a < kRegBits; ++a) reg = reg || hs.rb[a] == l;
+                if (!reg) maxoff += (uint64_t)1 << hp.tbits[l];
+            }
+            if (maxoff * (uint64_t)esz >= ((uint64_t)1 << 32)) p.flags |= PASS_WIDE;
+        }
         for (auto& hs : hp.stages) {
             Stage s{};
             int nrb = 0;
             for (int a = 0; a < kRegBits; ++a) {
-                s.rb[a] = (int8_t)hs.rb[a];
-                if (hs.rb[a] >= 0) s.rbs[nrb++] = (int8_t)hs.rb[a];
+                s.rb[a] = hs.rb[a];
+                if (hs.rb[a] >= 0) s.rbs[nrb++] = hs.rb[a];
             }
             std::sort(s.rbs, s.rbs + nrb);
             for (int a = nrb; a < kRegBits; ++a) s.rbs[a] = -1;

@@ -104,6 +104,14 @@ int pk_create(const pk_problem* probs, int32_t n_inst, int32_t prec, pk_plan** o
  */
 int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_t fuse);
 
+/*
+ * pk_set_launch -- resident workgroups per CU for the pass kernels of
+ * pk_evaluate and pk_backward (1..8), or 0 for as many as the kernel's
+ * resources allow (the default).  More than fit only queue up.  Drops captured
+ * graphs.  PK_EINVAL when out of range.
+ */
+int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu);
+
 /* Number of passes (full sweeps over the state) one evaluation of instance `inst` makes. */
 int pk_plan_passes(const pk_plan* plan, int32_t inst, int32_t* passes);
 

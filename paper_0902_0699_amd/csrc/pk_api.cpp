@@ -170,6 +170,7 @@ hipError_t enqueue_eval(DevPlan* d, const EvalArgs& a, hipStream_t st, std::vect
         L.pass = (int)p;
         L.kmax = in.fwd[p].kmax;
         L.ntiles = in.fwd[p].ntiles;
+        L.grid_cap = P.tiling.wgs_per_cu;
         if (ev) hipEventRecord((*ev)[2 * p], st);
         e = launch_pass(L, st);
         if (ev) hipEventRecord((*ev)[2 * p + 1], st);
@@ -243,6 +244,7 @@ hipError_t enqueue_backward(DevPlan* d, const BwdArgs& a, hipStream_t st) {
         L.pass = P.n_fwd_passes + (int)p;
         L.kmax = in.bwd[p].kmax;
         L.ntiles = in.bwd[p].ntiles;
+        L.grid_cap = P.tiling.wgs_per_cu;
         e = launch_pass(L, st);
         if (e != hipSuccess) return e;
     }
@@ -334,7 +336,7 @@ int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_
     if (carrier_bits < 0 || carrier_bits > 6 || carrier_bits > tile_bits - 1)
         return fail(d, PK_EINVAL, "carrier_bits out of range");
     if (fuse != 0 && fuse != 1) return fail(d, PK_EINVAL, "fuse must be 0 or 1");
-    d->host.tiling = Tiling{tile_bits, carrier_bits, fuse};
+    d->host.tiling = Tiling{tile_bits, carrier_bits, fuse, d->host.tiling.wgs_per_cu};
     drop_device(d);
     std::string err;
     try {
@@ -343,6 +345,15 @@ int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_
     } catch (const std::bad_alloc&) {
         return fail(d, PK_ENOMEM, "out of host memory");
     }
+    return PK_OK;
+}
+
+int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu) {
+    if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");
+    DevPlan* d = dp(plan);
+    if (wgs_per_cu < 0 || wgs_per_cu > 8) return fail(d, PK_EINVAL, "wgs_per_cu must be 0..8");
+    d->host.tiling.wgs_per_cu = wgs_per_cu;
+    drop_graphs(d);
     return PK_OK;
 }
 

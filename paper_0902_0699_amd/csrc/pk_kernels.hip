@@ -671,17 +671,18 @@ __global__ void pair_index_kernel(int32_t nq, int32_t i_s, int64_t first, int64_
 // Persistent launch: as many workgroups as fit on the device at once (capped by
 // the tile count); each walks its tiles with the load of the next one in flight.
 template <typename R, int NV, int KMAX>
-static hipError_t launch_pass_t(const KArgs& a, int64_t ntiles, int64_t grid_cap, hipStream_t st) {
-    static int resident = 0;  // workgroups per device, queried once per kernel instance
-    if (resident == 0) {
-        int dev = 0, ncu = 0, per_cu = 0;
+static hipError_t launch_pass_t(const KArgs& a, int64_t ntiles, int64_t wgs_per_cu, hipStream_t st) {
+    static int ncu = 0, per_cu = 0;  // queried once per kernel instance
+    if (ncu == 0) {
+        int dev = 0;
         hipGetDevice(&dev);
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
         auto kfn = pass_kernel<R, NV, KMAX>;
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, 1 << (KMAX - 4), 0);
-        resident = (ncu > 0 ? ncu : 256) * (per_cu > 0 ? per_cu : 1);
+        if (ncu <= 0) ncu = 256;
+        if (per_cu <= 0) per_cu = 1;
     }
-    int64_t grid = grid_cap > 0 ? grid_cap : resident;
+    int64_t grid = (int64_t)ncu * (wgs_per_cu > 0 ? wgs_per_cu : per_cu);
     if (grid > ntiles) grid = ntiles;
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL((pass_kernel<R, NV, KMAX>), dim3((unsigned)grid), dim3(1 << (KMAX - 4)), 0, st, a);

@@ -26,7 +26,7 @@ struct PassLaunch {
     int32_t nv;
     int32_t fp64;
     int64_t ntiles;
-    int64_t grid_cap;  // workgroups of a pass launch; 0 = all that fit on the device
+    int64_t grid_cap;  // workgroups per CU of a pass launch; 0 = as many as fit
 };
 
 struct BatchLaunch {

@@ -348,7 +348,7 @@ int compile_plan(Plan* plan, const pk_problem* probs, int n_inst, int prec, std:
         return PK_EINVAL;
     }
     plan->prec = prec;
-    plan->tiling = Tiling{prec == PK_FP64 ? 13 : 14, 4, 1};
+    plan->tiling = Tiling{prec == PK_FP64 ? 13 : 14, 4, 1, 0};
     const int nq_max = prec == PK_FP64 ? 30 : 31;
     int64_t off = 0;
     int d2 = 0;

@@ -52,6 +52,7 @@ struct Tiling {
     int tile_bits;
     int carrier_bits;
     int fuse;
+    int wgs_per_cu = 0;  // resident workgroups per CU for pass launches (0 = occupancy limit)
 };
 
 struct Plan {

@@ -96,7 +96,8 @@ int pk_create(const pk_problem* probs, int32_t n_inst, int32_t prec, pk_plan** o
 
 /*
  * pk_set_tiling -- choose the pass kernel's tile: 2^tile_bits amplitudes per
- * workgroup (fp64: 4..13, fp32: 4..14), of which the carrier_bits lowest state
+ * workgroup (fp64: 4..13, fp32: 4..14; tiles below 2^(reg_bits + 6) leave
+ * threads of the smallest kernel idle), of which the carrier_bits lowest state
  * bits (0..6) are always part of a tile so that each memory run is
  * 2^carrier_bits contiguous amplitudes; fuse = 0 turns fusion off (one sweep per
  * gate, the plain form).  Re-compiles the schedule and drops captured graphs.
@@ -105,12 +106,15 @@ int pk_create(const pk_problem* probs, int32_t n_inst, int32_t prec, pk_plan** o
 int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_t fuse);
 
 /*
- * pk_set_launch -- resident workgroups per CU for the pass kernels of
- * pk_evaluate and pk_backward (1..8), or 0 for as many as the kernel's
- * resources allow (the default).  More than fit only queue up.  Drops captured
+ * pk_set_launch -- launch shape of the pass kernels: wgs_per_cu resident
+ * workgroups per CU (1..8, or 0 for as many as the kernel's resources allow,
+ * the default; more than fit only queue up), and reg_bits = 4 or 5 register
+ * bits per thread in forward passes (16 or 32 amplitudes per thread, a
+ * workgroup of 2^(tile_bits - reg_bits) threads; 0 keeps 4).  Backward passes
+ * always use 4.  Changing reg_bits re-compiles the schedule.  Drops captured
  * graphs.  PK_EINVAL when out of range.
  */
-int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu);
+int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu, int32_t reg_bits);
 
 /* Number of passes (full sweeps over the state) one evaluation of instance `inst` makes. */
 int pk_plan_passes(const pk_plan* plan, int32_t inst, int32_t* passes);

@@ -8,6 +8,7 @@ Every HIP source is compiled with packed FP32 instructions disabled.
 import os
 import subprocess
 import sys
+import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -38,16 +39,25 @@ def build(verbose=False, jobs=3):
         cmd = [HIPCC, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + common
         if verbose:
             print(" ".join(cmd), flush=True)
-        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
-        if len([p for p in procs if p[1].poll() is None]) >= jobs:
-            procs[0][1].wait()
-    for src, p in procs:
-        out, _ = p.communicate()
+        # compiler output goes to a file: a pipe nobody reads would block the compiler
+        log = open(obj + ".log", "w+b")
+        procs.append((src, subprocess.Popen(cmd, stdout=log, stderr=subprocess.STDOUT), log))
+        while len([p for p in procs if p[1].poll() is None]) >= jobs:
+            time.sleep(0.2)
+    failed = []
+    for src, p, log in procs:
+        p.wait()
+        log.seek(0)
+        out = log.read().decode(errors="replace")
+        log.close()
         if p.returncode != 0:
-            sys.stderr.write(out.decode(errors="replace"))
-            raise RuntimeError("hipcc failed on %s" % src)
-        if verbose and out:
-            sys.stderr.write(out.decode(errors="replace"))
+            failed.append((src, out))
+        elif verbose and out:
+            sys.stderr.write(out)
+    for src, out in failed:
+        sys.stderr.write(out)
+    if failed:
+        raise RuntimeError("hipcc failed on %s" % ", ".join(s for s, _ in failed))
     tmp = LIB + ".tmp"
     link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

@@ -171,6 +171,7 @@ hipError_t enqueue_eval(DevPlan* d, const EvalArgs& a, hipStream_t st, std::vect
         L.kmax = in.fwd[p].kmax;
         L.ntiles = in.fwd[p].ntiles;
         L.grid_cap = P.tiling.wgs_per_cu;
+        L.rbits = in.fwd[p].rbits;
         if (ev) hipEventRecord((*ev)[2 * p], st);
         e = launch_pass(L, st);
         if (ev) hipEventRecord((*ev)[2 * p + 1], st);
@@ -182,7 +183,7 @@ hipError_t enqueue_eval(DevPlan* d, const EvalArgs& a, hipStream_t st, std::vect
 }
 
 int batched_kmax(const Plan& P) {
-    int km = 10;
+    int km = P.inst[0].fwd[0].rbits + 6;
     for (const auto& in : P.inst)
         for (const auto& hp : in.fwd) km = hp.kmax > km ? hp.kmax : km;
     return km;
@@ -198,6 +199,7 @@ hipError_t enqueue_batched(DevPlan* d, const EvalArgs& a, hipStream_t st) {
     L.want_norm = a.norm_out != nullptr;
     L.nv = 1;
     L.kmax = batched_kmax(P);
+    L.rbits = P.inst[0].fwd[0].rbits;
     TableLayout t = table_layout(&P);
     WsLayout w = workspace_layout(&P, PK_OP_EVAL);
     BatchLaunch B{};
@@ -245,6 +247,7 @@ hipError_t enqueue_backward(DevPlan* d, const BwdArgs& a, hipStream_t st) {
         L.kmax = in.bwd[p].kmax;
         L.ntiles = in.bwd[p].ntiles;
         L.grid_cap = P.tiling.wgs_per_cu;
+        L.rbits = in.bwd[p].rbits;
         e = launch_pass(L, st);
         if (e != hipSuccess) return e;
     }
@@ -336,7 +339,7 @@ int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_
     if (carrier_bits < 0 || carrier_bits > 6 || carrier_bits > tile_bits - 1)
         return fail(d, PK_EINVAL, "carrier_bits out of range");
     if (fuse != 0 && fuse != 1) return fail(d, PK_EINVAL, "fuse must be 0 or 1");
-    d->host.tiling = Tiling{tile_bits, carrier_bits, fuse, d->host.tiling.wgs_per_cu};
+    d->host.tiling = Tiling{tile_bits, carrier_bits, fuse, d->host.tiling.wgs_per_cu, d->host.tiling.reg_bits};
     drop_device(d);
     std::string err;
     try {
@@ -348,12 +351,27 @@ int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_
     return PK_OK;
 }
 
-int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu) {
+int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu, int32_t reg_bits) {
     if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");
     DevPlan* d = dp(plan);
     if (wgs_per_cu < 0 || wgs_per_cu > 8) return fail(d, PK_EINVAL, "wgs_per_cu must be 0..8");
+    if (reg_bits != 0 && reg_bits != 4 && reg_bits != 5) return fail(d, PK_EINVAL, "reg_bits must be 0, 4 or 5");
+    const int rb = reg_bits == 0 ? 4 : reg_bits;
+    const bool recompile_needed = rb != d->host.tiling.reg_bits;
     d->host.tiling.wgs_per_cu = wgs_per_cu;
-    drop_graphs(d);
+    d->host.tiling.reg_bits = rb;
+    if (recompile_needed) {
+        drop_device(d);
+        std::string err;
+        try {
+            int rc = recompile(&d->host, &err);
+            if (rc != PK_OK) return fail(d, rc, err);
+        } catch (const std::bad_alloc&) {
+            return fail(d, PK_ENOMEM, "out of host memory");
+        }
+    } else {
+        drop_graphs(d);
+    }
     return PK_OK;
 }
 

@@ -16,8 +16,7 @@
 
 namespace pk {
 
-constexpr int kRegBits = 4;          // register bits per stage
-constexpr int kRegs = 1 << kRegBits; // amplitudes per thread
+constexpr int kMaxRegBits = 5;       // register bits per stage (4 or 5): 16 or 32 amplitudes per thread
 constexpr int kMaxTileBits = 14;     // fp32 limit (fp64: 13), LDS = 2^k * element
 constexpr int kMaxQubits = 31;
 constexpr int kMaxNV = 2;            // vectors carried by a pass: psi, or psi and lambda
@@ -44,8 +43,8 @@ struct Op {
 };
 
 struct Stage {
-    int32_t rb[kRegBits];  // local tile bit held by register bit a (-1 when the tile has < 4 bits)
-    int32_t rbs[kRegBits]; // the same bits sorted ascending (-1 entries last)
+    int32_t rb[kMaxRegBits];  // local tile bit held by register bit a (-1 when unused)
+    int32_t rbs[kMaxRegBits]; // the same bits sorted ascending (-1 entries last)
     int32_t op_begin;
     int32_t op_count;
 };
@@ -82,7 +81,8 @@ struct Pass {
     int64_t state_off;   // element offset of the instance in the packed buffer
     double scale;        // applied by OP_SCALE
     int32_t part_base;   // norm partials: part_base + tile
-    int32_t kmax;        // kernel instance (workgroup = 2^(kmax-4) threads)
+    int32_t kmax;        // kernel instance (workgroup = 2^(kmax - rbits) threads)
+    int32_t rbits;       // register bits per thread
     int32_t ntrun;       // runs of consecutive tile bits
     int32_t nfrun;       // runs of consecutive free bits
     int32_t tpos[16];    // global bit position of local tile bit l

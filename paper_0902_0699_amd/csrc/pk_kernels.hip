@@ -71,10 +71,10 @@ __device__ __forceinline__ unsigned phys(unsigned j) {
 // Layout of one stage: per-thread label base and the uniform offsets of the
 // four register bits (as labels and as LDS slots).
 struct Layout {
-    unsigned jt;     // thread's label base
-    unsigned pj;     // phys(jt)
-    unsigned r[4];   // 1 << rb[a] (0 for missing bits)
-    unsigned p[4];   // phys(1 << rb[a])
+    unsigned jt;               // thread's label base
+    unsigned pj;               // phys(jt)
+    unsigned r[kMaxRegBits];   // 1 << rb[a] (0 for missing bits)
+    unsigned p[kMaxRegBits];   // phys(1 << rb[a])
 };
 
 template <int ESZ>
@@ -89,7 +89,7 @@ __device__ __forceinline__ Layout make_layout(const PK_CONST Stage* S, int nrb, 
     L.jt = t;
     L.pj = phys<ESZ>(t);
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < kMaxRegBits; ++a) {
         L.r[a] = a < nrb ? (1u << S->rb[a]) : 0u;
         L.p[a] = phys<ESZ>(L.r[a]);
     }
@@ -98,11 +98,11 @@ __device__ __forceinline__ Layout make_layout(const PK_CONST Stage* S, int nrb, 
 
 __device__ __forceinline__ unsigned roff(const Layout& L, int i) {
     return ((i & 1) ? L.r[0] : 0u) | ((i & 2) ? L.r[1] : 0u) | ((i & 4) ? L.r[2] : 0u) |
-           ((i & 8) ? L.r[3] : 0u);
+           ((i & 8) ? L.r[3] : 0u) | ((i & 16) ? L.r[4] : 0u);
 }
 __device__ __forceinline__ unsigned poff(const Layout& L, int i) {
     return ((i & 1) ? L.p[0] : 0u) ^ ((i & 2) ? L.p[1] : 0u) ^ ((i & 4) ? L.p[2] : 0u) ^
-           ((i & 8) ? L.p[3] : 0u);
+           ((i & 8) ? L.p[3] : 0u) ^ ((i & 16) ? L.p[4] : 0u);
 }
 
 // Moves the bits of `x` along the runs (src, len, dst).
@@ -119,7 +119,7 @@ __device__ __forceinline__ int64_t deposit(int64_t x, const PK_CONST Run* run, i
 // and the uniform parts of the four register bits.
 struct GOff {
     int64_t gt;
-    int64_t g[4];
+    int64_t g[kMaxRegBits];
 };
 
 __device__ __forceinline__ GOff make_goff(const PK_CONST Pass* P, const PK_CONST Stage* S, const Layout& L,
@@ -127,23 +127,23 @@ __device__ __forceinline__ GOff make_goff(const PK_CONST Pass* P, const PK_CONST
     GOff G;
     G.gt = deposit((int64_t)L.jt, P->trun, P->ntrun);
 #pragma unroll
-    for (int a = 0; a < 4; ++a) G.g[a] = a < nrb ? ((int64_t)1 << P->tpos[S->rb[a]]) : 0;
+    for (int a = 0; a < kMaxRegBits; ++a) G.g[a] = a < nrb ? ((int64_t)1 << P->tpos[S->rb[a]]) : 0;
     return G;
 }
 
 __device__ __forceinline__ int64_t goff(const GOff& G, int i) {
     return ((i & 1) ? G.g[0] : 0) + ((i & 2) ? G.g[1] : 0) + ((i & 4) ? G.g[2] : 0) +
-           ((i & 8) ? G.g[3] : 0);
+           ((i & 8) ? G.g[3] : 0) + ((i & 16) ? G.g[4] : 0);
 }
 
 // ---------------------------------------------------------------------------- gate bodies
 
-template <int A, int NV, typename T>
-__device__ __forceinline__ void op_h(T (&v)[NV][16]) {
+template <int A, int NV, int NR, typename T>
+__device__ __forceinline__ void op_h(T (&v)[NV][NR]) {
 #pragma unroll
     for (int n = 0; n < NV; ++n)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < NR; ++i) {
             if (i & (1 << A)) continue;
             const int j = i | (1 << A);
             T x = v[n][i], y = v[n][j];
@@ -164,12 +164,12 @@ __device__ __forceinline__ void pair_mat(T& x, T& y, const R (&m)[8]) {
     y.y = m[4] * a.y + m[5] * a.x + m[6] * b.y + m[7] * b.x;
 }
 
-template <int A, int NV, typename T, typename R>
-__device__ __forceinline__ void op_m(T (&v)[NV][16], const R (&m)[8]) {
+template <int A, int NV, int NR, typename T, typename R>
+__device__ __forceinline__ void op_m(T (&v)[NV][NR], const R (&m)[8]) {
 #pragma unroll
     for (int n = 0; n < NV; ++n)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < NR; ++i) {
             if (i & (1 << A)) continue;
             pair_mat(v[n][i], v[n][i | (1 << A)], m);
         }
@@ -178,12 +178,12 @@ __device__ __forceinline__ void op_m(T (&v)[NV][16], const R (&m)[8]) {
 // Backward step through a D2 gate: psi <- D^H psi; then for every angle,
 // g += Re( conj(lambda) . (dD/dtheta) psi ); then lambda <- D^H lambda.
 // One derivative matrix at a time keeps the register footprint small.
-template <int A, int NV, typename T, typename R>
-__device__ __forceinline__ void op_d2bwd(T (&v)[NV][16], const R (&mh)[8], const PK_CONST double* dmats,
+template <int A, int NV, int NR, typename T, typename R>
+__device__ __forceinline__ void op_d2bwd(T (&v)[NV][NR], const R (&mh)[8], const PK_CONST double* dmats,
                                          double (&g)[3]) {
     if constexpr (NV == 2) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
+        for (int i = 0; i < NR; ++i)
             if (!(i & (1 << A))) pair_mat(v[0][i], v[0][i | (1 << A)], mh);
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
@@ -192,7 +192,7 @@ __device__ __forceinline__ void op_d2bwd(T (&v)[NV][16], const R (&mh)[8], const
             for (int e = 0; e < 8; ++e) m[e] = dmats[8 * t + e];
             double acc = 0.0;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
+            for (int i = 0; i < NR; ++i) {
                 if (i & (1 << A)) continue;
                 const int j = i | (1 << A);
                 const double p0x = v[0][i].x, p0y = v[0][i].y, p1x = v[0][j].x, p1y = v[0][j].y;
@@ -206,39 +206,48 @@ __device__ __forceinline__ void op_d2bwd(T (&v)[NV][16], const R (&mh)[8], const
             g[t] += acc;
         }
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
+        for (int i = 0; i < NR; ++i)
             if (!(i & (1 << A))) pair_mat(v[1][i], v[1][i | (1 << A)], mh);
     }
 }
 
-template <int NV, typename T>
-__device__ __forceinline__ void dispatch_h(T (&v)[NV][16], int a) {
+template <int NV, int NR, typename T>
+__device__ __forceinline__ void dispatch_h(T (&v)[NV][NR], int a) {
     switch (a) {
-    case 0: op_h<0, NV>(v); break;
-    case 1: op_h<1, NV>(v); break;
-    case 2: op_h<2, NV>(v); break;
-    default: op_h<3, NV>(v); break;
+    case 0: op_h<0, NV, NR>(v); break;
+    case 1: op_h<1, NV, NR>(v); break;
+    case 2: op_h<2, NV, NR>(v); break;
+    case 3: op_h<3, NV, NR>(v); break;
+    default:
+        if constexpr (NR > 16) op_h<4, NV, NR>(v);
+        break;
     }
 }
 
-template <int NV, typename T, typename R>
-__device__ __forceinline__ void dispatch_m(T (&v)[NV][16], int a, const R (&m)[8]) {
+template <int NV, int NR, typename T, typename R>
+__device__ __forceinline__ void dispatch_m(T (&v)[NV][NR], int a, const R (&m)[8]) {
     switch (a) {
-    case 0: op_m<0, NV>(v, m); break;
-    case 1: op_m<1, NV>(v, m); break;
-    case 2: op_m<2, NV>(v, m); break;
-    default: op_m<3, NV>(v, m); break;
+    case 0: op_m<0, NV, NR>(v, m); break;
+    case 1: op_m<1, NV, NR>(v, m); break;
+    case 2: op_m<2, NV, NR>(v, m); break;
+    case 3: op_m<3, NV, NR>(v, m); break;
+    default:
+        if constexpr (NR > 16) op_m<4, NV, NR>(v, m);
+        break;
     }
 }
 
-template <int NV, typename T, typename R>
-__device__ __forceinline__ void dispatch_d2bwd(T (&v)[NV][16], int a, const R (&mh)[8],
+template <int NV, int NR, typename T, typename R>
+__device__ __forceinline__ void dispatch_d2bwd(T (&v)[NV][NR], int a, const R (&mh)[8],
                                                const PK_CONST double* dmats, double (&g)[3]) {
     switch (a) {
-    case 0: op_d2bwd<0, NV>(v, mh, dmats, g); break;
-    case 1: op_d2bwd<1, NV>(v, mh, dmats, g); break;
-    case 2: op_d2bwd<2, NV>(v, mh, dmats, g); break;
-    default: op_d2bwd<3, NV>(v, mh, dmats, g); break;
+    case 0: op_d2bwd<0, NV, NR>(v, mh, dmats, g); break;
+    case 1: op_d2bwd<1, NV, NR>(v, mh, dmats, g); break;
+    case 2: op_d2bwd<2, NV, NR>(v, mh, dmats, g); break;
+    case 3: op_d2bwd<3, NV, NR>(v, mh, dmats, g); break;
+    default:
+        if constexpr (NR > 16) op_d2bwd<4, NV, NR>(v, mh, dmats, g);
+        break;
     }
 }
 
@@ -268,15 +277,15 @@ struct PassCtx {
     GOff G0, Gl;
 };
 
-template <int ESZ>
+template <int ESZ, int RB>
 __device__ __forceinline__ PassCtx make_ctx(const KArgs& a, const PK_CONST Pass* P) {
     PassCtx C;
     const int k = P->k;
-    C.nrb = k < 4 ? k : 4;
+    C.nrb = k < RB ? k : RB;
     C.nreg = 1 << C.nrb;
     C.flags = P->flags;
     C.nstages = P->nstages;
-    const unsigned nact = k >= 4 ? (1u << (k - 4)) : 1u;
+    const unsigned nact = k >= RB ? (1u << (k - RB)) : 1u;
     C.active = threadIdx.x < nact;
     const PK_CONST Stage* S0 = cptr(a.stages) + P->stage_begin;
     const PK_CONST Stage* Sl = S0 + (C.nstages - 1);
@@ -291,15 +300,15 @@ __device__ __forceinline__ PassCtx make_ctx(const KArgs& a, const PK_CONST Pass*
 // state label.  The uniform part (tile base + register offset) and the thread's
 // part stay apart, so each load is a 64-bit scalar base plus a 32-bit lane
 // offset; a wide pass (lane offsets beyond 32 bits) adds in 64 bits.
-template <typename R, int NV>
+template <typename R, int NV, int NR>
 __device__ __forceinline__ void load_tile(const KArgs& a, const PassCtx& C, int64_t base,
-                                          typename Cplx<R>::T (&v)[NV][16]) {
+                                          typename Cplx<R>::T (&v)[NV][NR]) {
     using T = typename Cplx<R>::T;
-    if (C.nreg < 16 || NV == 2) {
+    if (C.nreg < NR || NV == 2) {
 #pragma unroll
         for (int n = 0; n < NV; ++n)
 #pragma unroll
-            for (int i = 0; i < 16; ++i) v[n][i] = T{0, 0};
+            for (int i = 0; i < NR; ++i) v[n][i] = T{0, 0};
     }
     if (!C.active) return;
     const char* in0 = reinterpret_cast<const char*>((C.flags & PASS_FIRST) ? a.src0 : a.dst0);
@@ -308,7 +317,7 @@ __device__ __forceinline__ void load_tile(const KArgs& a, const PassCtx& C, int6
     if (!(C.flags & PASS_WIDE)) {
         const uint32_t lane = (uint32_t)C.G0.gt * (uint32_t)sizeof(T);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < NR; ++i) {
             if (i >= C.nreg) continue;
             const int64_t u = (base + goff(C.G0, i)) * (int64_t)sizeof(T);
             v[0][i] = *reinterpret_cast<const T*>(in0 + u + lane);
@@ -317,7 +326,7 @@ __device__ __forceinline__ void load_tile(const KArgs& a, const PassCtx& C, int6
         }
     } else {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < NR; ++i) {
             if (i >= C.nreg) continue;
             const int64_t e = base + C.G0.gt + goff(C.G0, i);
             v[0][i] = reinterpret_cast<const T*>(in0)[e];
@@ -328,9 +337,9 @@ __device__ __forceinline__ void load_tile(const KArgs& a, const PassCtx& C, int6
 }
 
 // Registers -> HBM in the last stage's layout.
-template <typename R, int NV>
+template <typename R, int NV, int NR>
 __device__ __forceinline__ void store_tile(const KArgs& a, const PassCtx& C, int64_t base,
-                                           const typename Cplx<R>::T (&v)[NV][16]) {
+                                           const typename Cplx<R>::T (&v)[NV][NR]) {
     using T = typename Cplx<R>::T;
     if (!C.active) return;
     char* out0 = reinterpret_cast<char*>(a.dst0);
@@ -339,7 +348,7 @@ __device__ __forceinline__ void store_tile(const KArgs& a, const PassCtx& C, int
     if (!(C.flags & PASS_WIDE)) {
         const uint32_t lane = (uint32_t)C.Gl.gt * (uint32_t)sizeof(T);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < NR; ++i) {
             if (i >= C.nreg) continue;
             const int64_t u = (base + goff(C.Gl, i)) * (int64_t)sizeof(T);
             if (write0) *reinterpret_cast<T*>(out0 + u + lane) = v[0][i];
@@ -347,7 +356,7 @@ __device__ __forceinline__ void store_tile(const KArgs& a, const PassCtx& C, int
         }
     } else {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < NR; ++i) {
             if (i >= C.nreg) continue;
             const int64_t e = base + C.Gl.gt + goff(C.Gl, i);
             if (write0) reinterpret_cast<T*>(out0)[e] = v[0][i];
@@ -357,11 +366,12 @@ __device__ __forceinline__ void store_tile(const KArgs& a, const PassCtx& C, int
 }
 
 // Every stage of the pass on one tile held in registers, then the norm partial.
-template <typename R, int NV, int KMAX>
+template <typename R, int NV, int KMAX, int RB>
 __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass* P, const PassCtx& C,
-                                             int64_t tile, typename Cplx<R>::T (&v)[NV][16],
+                                             int64_t tile, typename Cplx<R>::T (&v)[NV][1 << RB],
                                              typename Cplx<R>::T* lds, double* red) {
-    constexpr int NT = 1 << (KMAX - 4);
+    constexpr int NT = 1 << (KMAX - RB);
+    constexpr int NR = 1 << RB;
     const unsigned tid = threadIdx.x;
     const bool active = C.active;
     const int nreg = C.nreg;
@@ -376,13 +386,13 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
             for (int n = 0; n < NV; ++n) {
                 if (active) {
 #pragma unroll
-                    for (int i = 0; i < 16; ++i)
+                    for (int i = 0; i < NR; ++i)
                         if (i < nreg) lds[L.pj ^ poff(L, i)] = v[n][i];
                 }
                 __syncthreads();
                 if (active) {
 #pragma unroll
-                    for (int i = 0; i < 16; ++i)
+                    for (int i = 0; i < NR; ++i)
                         if (i < nreg) v[n][i] = lds[Ln.pj ^ poff(Ln, i)];
                 }
                 __syncthreads();
@@ -399,14 +409,14 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
             const int arg = ops[o].arg;
             switch (kind) {
             case OP_H:
-                dispatch_h<NV>(v, ra);
+                dispatch_h<NV, NR>(v, ra);
                 break;
             case OP_MAT: {
                 R m[8];
                 const PK_CONST double* mp = cptr(a.mats) + 8 * arg;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) m[e] = (R)mp[e];
-                dispatch_m<NV>(v, ra, m);
+                dispatch_m<NV, NR>(v, ra, m);
                 break;
             }
             case OP_FLIP:
@@ -415,11 +425,11 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
                 const PK_CONST Flip* f = cptr(a.flips) + arg;
                 if (f->tile == tile && active) {
                     const unsigned jrel = (unsigned)f->j ^ L.jt;
-                    const unsigned rmask = L.r[0] | L.r[1] | L.r[2] | L.r[3];
+                    const unsigned rmask = L.r[0] | L.r[1] | L.r[2] | L.r[3] | L.r[4];
                     const int slot = f->slot;
                     if ((jrel & ~rmask) == 0u) {
 #pragma unroll
-                        for (int i = 0; i < 16; ++i) {
+                        for (int i = 0; i < NR; ++i) {
                             if (i < nreg && roff(L, i) == jrel) {
                                 if (kind == OP_FLIP) {
 #pragma unroll
@@ -446,7 +456,7 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
 #pragma unroll
                 for (int n = 0; n < NV; ++n)
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) {
+                    for (int i = 0; i < NR; ++i) {
                         v[n][i].x *= sc;
                         v[n][i].y *= sc;
                     }
@@ -458,7 +468,7 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
 #pragma unroll
                 for (int e = 0; e < 8; ++e) mh[e] = (R)mp[8 + e];
                 double g[3] = {0.0, 0.0, 0.0};
-                if (active) dispatch_d2bwd<NV>(v, ra, mh, mp + 16, g);
+                if (active) dispatch_d2bwd<NV, NR>(v, ra, mh, mp + 16, g);
                 const double scale = 2.0 * (double)ops[o].gscale;
                 const int gslot = ops[o].gslot;
 #pragma unroll
@@ -481,12 +491,12 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
         if (active) {
             if constexpr (sizeof(R) == 8) {
 #pragma unroll
-                for (int i = 0; i < 16; ++i)
+                for (int i = 0; i < NR; ++i)
                     if (i < nreg) part += v[0][i].x * v[0][i].x + v[0][i].y * v[0][i].y;
             } else {
                 float s = 0.0f, c = 0.0f;
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
+                for (int i = 0; i < NR; ++i) {
                     if (i >= nreg) continue;
                     const float term = v[0][i].x * v[0][i].x + v[0][i].y * v[0][i].y;
                     const float t = s + term;
@@ -506,42 +516,43 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
 // tile's LDS stages, so memory traffic overlaps the exchange work of the one
 // workgroup an LDS-sized tile leaves per CU.  The prefetch is unconditional
 // (past the end it re-reads the current tile) so the wait counts stay static.
-template <typename R, int NV, int KMAX>
+template <typename R, int NV, int KMAX, int RB>
 __device__ __forceinline__ void run_tiles(const KArgs& a, const PK_CONST Pass* P, int64_t first,
                                           int64_t stride, typename Cplx<R>::T* lds, double* red) {
     using T = typename Cplx<R>::T;
+    constexpr int NR = 1 << RB;
     const int64_t ntiles = P->ntiles;
     if (first >= ntiles) return;
-    const PassCtx C = make_ctx<(int)sizeof(R) * 2>(a, P);
+    const PassCtx C = make_ctx<(int)sizeof(R) * 2, RB>(a, P);
     const int64_t off = P->state_off;
     const int nfrun = P->nfrun;
     auto base_of = [&](int64_t t) { return off + deposit(t, P->frun, nfrun); };
     if constexpr (NV == 2) {
         // two vectors already fill the register file: no second buffer
         for (int64_t tile = first; tile < ntiles; tile += stride) {
-            T v[NV][16];
+            T v[NV][NR];
             const int64_t base = base_of(tile);
-            load_tile<R, NV>(a, C, base, v);
-            compute_tile<R, NV, KMAX>(a, P, C, tile, v, lds, red);
-            store_tile<R, NV>(a, C, base, v);
+            load_tile<R, NV, NR>(a, C, base, v);
+            compute_tile<R, NV, KMAX, RB>(a, P, C, tile, v, lds, red);
+            store_tile<R, NV, NR>(a, C, base, v);
         }
     } else {
-        T va[1][16], vb[1][16];
+        T va[1][NR], vb[1][NR];
         int64_t ta = first;
         int64_t basea = base_of(ta);
-        load_tile<R, 1>(a, C, basea, va);
+        load_tile<R, 1, NR>(a, C, basea, va);
         for (;;) {
             const int64_t tb = ta + stride;
             const int64_t baseb = base_of(tb < ntiles ? tb : ta);
-            load_tile<R, 1>(a, C, baseb, vb);
-            compute_tile<R, 1, KMAX>(a, P, C, ta, va, lds, red);
-            store_tile<R, 1>(a, C, basea, va);
+            load_tile<R, 1, NR>(a, C, baseb, vb);
+            compute_tile<R, 1, KMAX, RB>(a, P, C, ta, va, lds, red);
+            store_tile<R, 1, NR>(a, C, basea, va);
             if (tb >= ntiles) break;
             const int64_t tc = tb + stride;
             const int64_t basec = base_of(tc < ntiles ? tc : tb);
-            load_tile<R, 1>(a, C, basec, va);
-            compute_tile<R, 1, KMAX>(a, P, C, tb, vb, lds, red);
-            store_tile<R, 1>(a, C, baseb, vb);
+            load_tile<R, 1, NR>(a, C, basec, va);
+            compute_tile<R, 1, KMAX, RB>(a, P, C, tb, vb, lds, red);
+            store_tile<R, 1, NR>(a, C, baseb, vb);
             if (tc >= ntiles) break;
             ta = tc;
             basea = basec;
@@ -551,22 +562,22 @@ __device__ __forceinline__ void run_tiles(const KArgs& a, const PK_CONST Pass* P
 
 // ---------------------------------------------------------------------------- kernels
 
-template <typename R, int NV, int KMAX>
-__global__ void __launch_bounds__(1 << (KMAX - 4)) pass_kernel(KArgs a) {
+template <typename R, int NV, int KMAX, int RB>
+__global__ void __launch_bounds__(1 << (KMAX - RB)) pass_kernel(KArgs a) {
     using T = typename Cplx<R>::T;
     __shared__ T lds[1 << KMAX];
     __shared__ double red[16];
-    run_tiles<R, NV, KMAX>(a, cptr(a.passes) + a.pass, blockIdx.x, gridDim.x, lds, red);
+    run_tiles<R, NV, KMAX, RB>(a, cptr(a.passes) + a.pass, blockIdx.x, gridDim.x, lds, red);
 }
 
 // Multiverse batch: each workgroup takes whole instances from a queue (largest
 // first) and runs all their passes itself, then writes L and the norm.
-template <typename R, int KMAX>
-__global__ void __launch_bounds__(1 << (KMAX - 4))
+template <typename R, int KMAX, int RB>
+__global__ void __launch_bounds__(1 << (KMAX - RB))
     batched_kernel(KArgs a, const InstDesc* idesc, const int32_t* order, int32_t n_inst, unsigned int* queue,
                    double* L_out, double* norm_out) {
     using T = typename Cplx<R>::T;
-    constexpr int NT = 1 << (KMAX - 4);
+    constexpr int NT = 1 << (KMAX - RB);
     __shared__ T lds[1 << KMAX];
     __shared__ double red[16];
     __shared__ int item;
@@ -580,7 +591,7 @@ __global__ void __launch_bounds__(1 << (KMAX - 4))
         const PK_CONST InstDesc* D = cptr(idesc) + inst;
         const int npass = D->npass;
         for (int p = 0; p < npass; ++p) {
-            run_tiles<R, 1, KMAX>(a, cptr(a.passes) + D->first_pass + p, 0, 1, lds, red);
+            run_tiles<R, 1, KMAX, RB>(a, cptr(a.passes) + D->first_pass + p, 0, 1, lds, red);
             // this workgroup's stores must be visible to its own loads of the next pass
             __threadfence_block();
             __syncthreads();
@@ -670,40 +681,53 @@ __global__ void pair_index_kernel(int32_t nq, int32_t i_s, int64_t first, int64_
 
 // Persistent launch: as many workgroups as fit on the device at once (capped by
 // the tile count); each walks its tiles with the load of the next one in flight.
-template <typename R, int NV, int KMAX>
+template <typename R, int NV, int KMAX, int RB>
 static hipError_t launch_pass_t(const KArgs& a, int64_t ntiles, int64_t wgs_per_cu, hipStream_t st) {
     static int ncu = 0, per_cu = 0;  // queried once per kernel instance
     if (ncu == 0) {
         int dev = 0;
         hipGetDevice(&dev);
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-        auto kfn = pass_kernel<R, NV, KMAX>;
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, 1 << (KMAX - 4), 0);
+        auto kfn = pass_kernel<R, NV, KMAX, RB>;
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, 1 << (KMAX - RB), 0);
         if (ncu <= 0) ncu = 256;
         if (per_cu <= 0) per_cu = 1;
     }
     int64_t grid = (int64_t)ncu * (wgs_per_cu > 0 ? wgs_per_cu : per_cu);
     if (grid > ntiles) grid = ntiles;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL((pass_kernel<R, NV, KMAX>), dim3((unsigned)grid), dim3(1 << (KMAX - 4)), 0, st, a);
+    hipLaunchKernelGGL((pass_kernel<R, NV, KMAX, RB>), dim3((unsigned)grid), dim3(1 << (KMAX - RB)), 0, st, a);
     return hipGetLastError();
 }
 
-template <typename R, int NV>
+// Kernel instances: one vector with 4 or 5 register bits, two vectors with 4.
+template <typename R, int NV, int RB>
 static hipError_t launch_pass_r(int kmax, const KArgs& a, int64_t ntiles, int64_t cap, hipStream_t st) {
-    switch (kmax) {
-    case 10: return launch_pass_t<R, NV, 10>(a, ntiles, cap, st);
-    case 11: return launch_pass_t<R, NV, 11>(a, ntiles, cap, st);
-    case 12: return launch_pass_t<R, NV, 12>(a, ntiles, cap, st);
-    case 13: return launch_pass_t<R, NV, 13>(a, ntiles, cap, st);
-    case 14:
-        if constexpr (sizeof(R) == 4) return launch_pass_t<R, NV, 14>(a, ntiles, cap, st);
-        return hipErrorInvalidValue;
-    default: return hipErrorInvalidValue;
+    if constexpr (RB == 4) {
+        switch (kmax) {
+        case 10: return launch_pass_t<R, NV, 10, 4>(a, ntiles, cap, st);
+        case 11: return launch_pass_t<R, NV, 11, 4>(a, ntiles, cap, st);
+        case 12: return launch_pass_t<R, NV, 12, 4>(a, ntiles, cap, st);
+        case 13: return launch_pass_t<R, NV, 13, 4>(a, ntiles, cap, st);
+        case 14:
+            if constexpr (sizeof(R) == 4) return launch_pass_t<R, NV, 14, 4>(a, ntiles, cap, st);
+            return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (kmax) {
+        case 11: return launch_pass_t<R, NV, 11, 5>(a, ntiles, cap, st);
+        case 12: return launch_pass_t<R, NV, 12, 5>(a, ntiles, cap, st);
+        case 13: return launch_pass_t<R, NV, 13, 5>(a, ntiles, cap, st);
+        case 14:
+            if constexpr (sizeof(R) == 4) return launch_pass_t<R, NV, 14, 5>(a, ntiles, cap, st);
+            return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+        }
     }
 }
 
-hipError_t launch_pass(const PassLaunch& L, hipStream_t st) {
+static KArgs kargs(const PassLaunch& L) {
     KArgs a;
     a.passes = L.passes;
     a.stages = L.stages;
@@ -719,54 +743,55 @@ hipError_t launch_pass(const PassLaunch& L, hipStream_t st) {
     a.dL = L.dL;
     a.pass = L.pass;
     a.want_norm = L.want_norm;
-    if (L.fp64) {
-        return L.nv == 2 ? launch_pass_r<double, 2>(L.kmax, a, L.ntiles, L.grid_cap, st)
-                         : launch_pass_r<double, 1>(L.kmax, a, L.ntiles, L.grid_cap, st);
-    }
-    return L.nv == 2 ? launch_pass_r<float, 2>(L.kmax, a, L.ntiles, L.grid_cap, st)
-                     : launch_pass_r<float, 1>(L.kmax, a, L.ntiles, L.grid_cap, st);
+    return a;
 }
 
-template <typename R, int KMAX>
+hipError_t launch_pass(const PassLaunch& L, hipStream_t st) {
+    const KArgs a = kargs(L);
+    if (L.nv == 2) {
+        if (L.rbits != 4) return hipErrorInvalidValue;
+        return L.fp64 ? launch_pass_r<double, 2, 4>(L.kmax, a, L.ntiles, L.grid_cap, st)
+                      : launch_pass_r<float, 2, 4>(L.kmax, a, L.ntiles, L.grid_cap, st);
+    }
+    if (L.rbits == 5)
+        return L.fp64 ? launch_pass_r<double, 1, 5>(L.kmax, a, L.ntiles, L.grid_cap, st)
+                      : launch_pass_r<float, 1, 5>(L.kmax, a, L.ntiles, L.grid_cap, st);
+    return L.fp64 ? launch_pass_r<double, 1, 4>(L.kmax, a, L.ntiles, L.grid_cap, st)
+                  : launch_pass_r<float, 1, 4>(L.kmax, a, L.ntiles, L.grid_cap, st);
+}
+
+template <typename R, int KMAX, int RB>
 static hipError_t launch_batched_t(const KArgs& a, const BatchLaunch& B, hipStream_t st) {
-    hipLaunchKernelGGL((batched_kernel<R, KMAX>), dim3(B.grid), dim3(1 << (KMAX - 4)), 0, st, a, B.idesc,
+    hipLaunchKernelGGL((batched_kernel<R, KMAX, RB>), dim3(B.grid), dim3(1 << (KMAX - RB)), 0, st, a, B.idesc,
                        B.order, B.n_inst, B.queue, B.L_out, B.norm_out);
     return hipGetLastError();
 }
 
+template <typename R, int RB>
+static hipError_t launch_batched_r(int kmax, const KArgs& a, const BatchLaunch& B, hipStream_t st) {
+    switch (kmax) {
+    case 10:
+        if constexpr (RB == 4) return launch_batched_t<R, 10, 4>(a, B, st);
+        return hipErrorInvalidValue;
+    case 11: return launch_batched_t<R, 11, RB>(a, B, st);
+    case 12: return launch_batched_t<R, 12, RB>(a, B, st);
+    case 13: return launch_batched_t<R, 13, RB>(a, B, st);
+    case 14:
+        if constexpr (sizeof(R) == 4) return launch_batched_t<R, 14, RB>(a, B, st);
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_batched(const PassLaunch& L, const BatchLaunch& B, hipStream_t st) {
-    KArgs a;
-    a.passes = L.passes;
-    a.stages = L.stages;
-    a.ops = L.ops;
-    a.flips = L.flips;
-    a.mats = L.mats;
-    a.src0 = L.src0;
-    a.dst0 = L.dst0;
+    KArgs a = kargs(L);
     a.dst1 = nullptr;
-    a.partials = L.partials;
-    a.reads = L.reads;
     a.gpart = nullptr;
     a.dL = nullptr;
     a.pass = 0;
-    a.want_norm = L.want_norm;
-    if (L.fp64) {
-        switch (L.kmax) {
-        case 10: return launch_batched_t<double, 10>(a, B, st);
-        case 11: return launch_batched_t<double, 11>(a, B, st);
-        case 12: return launch_batched_t<double, 12>(a, B, st);
-        case 13: return launch_batched_t<double, 13>(a, B, st);
-        default: return hipErrorInvalidValue;
-        }
-    }
-    switch (L.kmax) {
-    case 10: return launch_batched_t<float, 10>(a, B, st);
-    case 11: return launch_batched_t<float, 11>(a, B, st);
-    case 12: return launch_batched_t<float, 12>(a, B, st);
-    case 13: return launch_batched_t<float, 13>(a, B, st);
-    case 14: return launch_batched_t<float, 14>(a, B, st);
-    default: return hipErrorInvalidValue;
-    }
+    if (L.rbits == 5)
+        return L.fp64 ? launch_batched_r<double, 5>(L.kmax, a, B, st) : launch_batched_r<float, 5>(L.kmax, a, B, st);
+    return L.fp64 ? launch_batched_r<double, 4>(L.kmax, a, B, st) : launch_batched_r<float, 4>(L.kmax, a, B, st);
 }
 
 hipError_t launch_prep(double* mats, const double* smats, int n_static, const double* angles, int n_d2,

@@ -25,6 +25,7 @@ struct PassLaunch {
     int32_t kmax;
     int32_t nv;
     int32_t fp64;
+    int32_t rbits;     // register bits per thread (4 or 5)
     int64_t ntiles;
     int64_t grid_cap;  // workgroups per CU of a pass launch; 0 = as many as fit
 };

@@ -18,7 +18,7 @@ namespace pk {
 
 namespace {
 
-constexpr int kKernelMinBits = 10;    // smallest kernel instance: one wavefront of 64 threads
+constexpr int kWaveBits = 6;          // smallest kernel instance: one wavefront of 64 threads
 constexpr int kBackwardMaxBits = 12;  // largest backward tile (psi and lambda in registers)
 
 bool finite8(const double* v, int n) {
@@ -103,6 +103,7 @@ struct Compiler {
     Instance* in;
     bool backward;
     int k, C, RB;
+    int RBITS;  // register bits of the kernel instance (RB may be smaller for tiny tiles)
 
     std::vector<int> free_bits(const std::vector<int>& tbits) const {
         std::vector<char> used(in->nq, 0);
@@ -239,14 +240,15 @@ struct Compiler {
             hp.k = k;
             hp.tbits = t;
             hp.ntiles = (int64_t)1 << (nq - k);
-            hp.kmax = std::max(k, kKernelMinBits);
+            hp.rbits = RBITS;
+            hp.kmax = std::max(k, RBITS + kWaveBits);
             if (pass_no == 0) hp.flags |= PASS_FIRST | (backward ? PASS_SEED_V1 : 0);
             if (last) hp.flags |= PASS_LAST | (backward ? PASS_SKIP_V0 : 0);
             for (size_t s = 0; s < st.size(); ++s) {
                 HostStage hs;
-                for (int a = 0; a < kRegBits; ++a) hs.rb[a] = a < (int)st[s].first.size() ? st[s].first[a] : -1;
+                for (int a = 0; a < kMaxRegBits; ++a) hs.rb[a] = a < (int)st[s].first.size() ? st[s].first[a] : -1;
                 auto reg_of = [&](int lb) {
-                    for (int a = 0; a < kRegBits; ++a)
+                    for (int a = 0; a < kMaxRegBits; ++a)
                         if (hs.rb[a] == lb) return a;
                     return -1;
                 };
@@ -348,7 +350,7 @@ int compile_plan(Plan* plan, const pk_problem* probs, int n_inst, int prec, std:
         return PK_EINVAL;
     }
     plan->prec = prec;
-    plan->tiling = Tiling{prec == PK_FP64 ? 13 : 14, 4, 1, 0};
+    plan->tiling = Tiling{prec == PK_FP64 ? 13 : 14, 4, 1, 0, 4};
     const int nq_max = prec == PK_FP64 ? 30 : 31;
     int64_t off = 0;
     int d2 = 0;
@@ -479,7 +481,8 @@ int recompile(Plan* plan, std::string* err) {
             const int kcap = c.backward ? std::min(plan->tiling.tile_bits, kBackwardMaxBits) : plan->tiling.tile_bits;
             c.k = std::min(kcap, in.nq);
             c.C = std::min(plan->tiling.carrier_bits, c.k);
-            c.RB = std::min(kRegBits, c.k);
+            c.RBITS = c.backward ? 4 : plan->tiling.reg_bits;
+            c.RB = std::min(c.RBITS, c.k);
             std::vector<Prim> prims = in.prims;
             if (c.backward) std::reverse(prims.begin(), prims.end());
             auto& dst = c.backward ? in.bwd : in.fwd;
@@ -504,6 +507,7 @@ int recompile(Plan* plan, std::string* err) {
         p.scale = hp.scale;
         p.part_base = hp.part_base;
         p.kmax = hp.kmax;
+        p.rbits = hp.rbits;
         for (int l = 0; l < 16; ++l) p.tpos[l] = l < hp.k ? hp.tbits[l] : -1;
         std::vector<char> used(in.nq, 0);
         for (int b : hp.tbits) used[b] = 1;
@@ -534,7 +538,7 @@ int recompile(Plan* plan, std::string* err) {
             uint64_t maxoff = 0;
             for (int l = 0; l < hp.k; ++l) {
                 bool reg = false;
-                for (int a = 0; a < kRegBits; ++a) reg = reg || hs.rb[a] == l;
+                for (int a = 0; a < kMaxRegBits; ++a) reg = reg || hs.rb[a] == l;
                 if (!reg) maxoff += (uint64_t)1 << hp.tbits[l];
             }
             if (maxoff * (uint64_t)esz >= ((uint64_t)1 << 32)) p.flags |= PASS_WIDE;
@@ -542,12 +546,12 @@ int recompile(Plan* plan, std::string* err) {
         for (auto& hs : hp.stages) {
             Stage s{};
             int nrb = 0;
-            for (int a = 0; a < kRegBits; ++a) {
+            for (int a = 0; a < kMaxRegBits; ++a) {
                 s.rb[a] = hs.rb[a];
                 if (hs.rb[a] >= 0) s.rbs[nrb++] = hs.rb[a];
             }
             std::sort(s.rbs, s.rbs + nrb);
-            for (int a = nrb; a < kRegBits; ++a) s.rbs[a] = -1;
+            for (int a = nrb; a < kMaxRegBits; ++a) s.rbs[a] = -1;
             s.op_begin = (int)plan->ops.size();
             s.op_count = (int)hs.ops.size();
             for (auto& o : hs.ops) plan->ops.push_back(o);
@@ -670,7 +674,8 @@ std::string describe(const Plan* plan) {
             for (size_t p = 0; p < ps.size(); ++p) {
                 const HostPass& hp = ps[p];
                 if (p) s += ",";
-                s += "{\"k\":" + std::to_string(hp.k) + ",\"flags\":" + std::to_string(hp.flags);
+                s += "{\"k\":" + std::to_string(hp.k) + ",\"rbits\":" + std::to_string(hp.rbits) +
+                     ",\"flags\":" + std::to_string(hp.flags);
                 char buf[64];
                 std::snprintf(buf, sizeof buf, "%.17g", hp.scale);
                 s += ",\"scale\":";
@@ -682,7 +687,7 @@ std::string describe(const Plan* plan) {
                     const HostStage& hs = hp.stages[st];
                     if (st) s += ",";
                     s += "{\"rb\":[";
-                    for (int a = 0; a < kRegBits; ++a) s += (a ? "," : "") + std::to_string(hs.rb[a]);
+                    for (int a = 0; a < kMaxRegBits; ++a) s += (a ? "," : "") + std::to_string(hs.rb[a]);
                     s += "],\"ops\":[";
                     for (size_t o = 0; o < hs.ops.size(); ++o) {
                         const Op& op = hs.ops[o];

@@ -20,7 +20,7 @@ struct Prim {
 };
 
 struct HostStage {
-    int rb[kRegBits];
+    int rb[kMaxRegBits];
     std::vector<Op> ops;
 };
 
@@ -33,6 +33,7 @@ struct HostPass {
     int64_t ntiles = 0;
     int part_base = 0;
     int kmax = 13;
+    int rbits = 4;
 };
 
 struct Instance {
@@ -53,6 +54,7 @@ struct Tiling {
     int carrier_bits;
     int fuse;
     int wgs_per_cu = 0;  // resident workgroups per CU for pass launches (0 = occupancy limit)
+    int reg_bits = 4;    // register bits per thread in forward passes (4 or 5)
 };
 
 struct Plan {

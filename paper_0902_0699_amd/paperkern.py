@@ -41,7 +41,7 @@ class PkProblem(ctypes.Structure):
 SIGNATURES = {
     "pk_create": (ctypes.c_int, [ctypes.POINTER(PkProblem), _c_int32, _c_int32, ctypes.POINTER(_vp)]),
     "pk_set_tiling": (ctypes.c_int, [_vp, _c_int32, _c_int32, _c_int32]),
-    "pk_set_launch": (ctypes.c_int, [_vp, _c_int32]),
+    "pk_set_launch": (ctypes.c_int, [_vp, _c_int32, _c_int32]),
     "pk_plan_passes": (ctypes.c_int, [_vp, _c_int32, ctypes.POINTER(_c_int32)]),
     "pk_plan_describe": (ctypes.c_int, [_vp, ctypes.c_char_p, _c_int64, ctypes.POINTER(_c_int64)]),
     "pk_plan_offsets": (ctypes.c_int, [_vp, ctypes.POINTER(_c_int64)]),
@@ -154,8 +154,9 @@ class Plan:
         _check(lib().pk_set_tiling(self.handle, tile_bits, carrier_bits, fuse), self.handle)
         self._ws = {}
 
-    def set_launch(self, wgs_per_cu):
-        _check(lib().pk_set_launch(self.handle, wgs_per_cu), self.handle)
+    def set_launch(self, wgs_per_cu=0, reg_bits=0):
+        _check(lib().pk_set_launch(self.handle, wgs_per_cu, reg_bits), self.handle)
+        self._ws = {}
 
     def passes(self, inst=0):
         n = ctypes.c_int32()

@@ -63,7 +63,7 @@ def check_stage_shapes(nq, p):
     k = p["k"]
     for st in p["stages"]:
         rb = [r for r in st["rb"] if r >= 0]
-        assert len(rb) == min(4, k) and len(set(rb)) == len(rb) and all(0 <= r < k for r in rb)
+        assert len(rb) == min(p["rbits"], k) and len(set(rb)) == len(rb) and all(0 <= r < k for r in rb)
         for op in st["ops"]:
             if op["kind"] in ("H", "MAT", "D2BWD"):
                 assert 0 <= op["a"] < len(rb)

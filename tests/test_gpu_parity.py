@@ -40,11 +40,13 @@ def _relerr(got, want):
     return float(np.linalg.norm(got - want) / np.linalg.norm(want))
 
 
-def _run(problem, psi, prec="fp64", tiling=None, inplace=False):
+def _run(problem, psi, prec="fp64", tiling=None, inplace=False, launch=None):
     pk = _pk()
     plan = pk.Plan(problem, prec=prec)
     if tiling:
         plan.set_tiling(*tiling)
+    if launch:
+        plan.set_launch(*launch)
     dt = torch.complex128 if prec == "fp64" else torch.complex64
     x = _dev(psi, dt)
     out = x if inplace else None
@@ -117,16 +119,18 @@ def test_ragged_sizes_fp64(nq, eloc):
     assert abs(L - Lw) <= TOL64 and abs(norm - nw) <= TOL64
 
 
-@pytest.mark.parametrize("tiling", [(4, 0, 1), (6, 2, 1), (10, 4, 1), (11, 4, 1), (12, 4, 1), (13, 6, 1),
-                                    (10, 4, 0), (13, 4, 0)])
-def test_tilings_fp64(tiling):
+@pytest.mark.parametrize("tiling,launch", [((4, 0, 1), None), ((6, 2, 1), None), ((10, 4, 1), None),
+                                           ((11, 4, 1), (2, 4)), ((12, 4, 1), None), ((13, 6, 1), None),
+                                           ((10, 4, 0), None), ((13, 4, 0), None), ((13, 4, 1), (0, 5)),
+                                           ((12, 4, 1), (0, 5)), ((7, 2, 1), (0, 5)), ((11, 3, 1), (1, 5))])
+def test_tilings_fp64(tiling, launch):
     nq = 15
     rng = np.random.default_rng(sum(tiling))
     prob = {"nq": nq, "gates": W.grover_gates((4, 1, 0.3, 1.1, 0.0)) + [("ONEOP", 15, O.PAULI_Y), ("H", 3)],
             "marked": [17, 30000]}
     psi = _state(rng, nq)
-    _say("tiling %s" % (tiling,))
-    _, got, L, _ = _run(prob, psi, tiling=tiling)
+    _say("tiling %s launch %s" % (tiling, launch))
+    _, got, L, _ = _run(prob, psi, tiling=tiling, launch=launch)
     want, Lw, _ = O.evaluate(nq, prob["gates"], prob["marked"], psi)
     assert _relerr(got, want) <= TOL64 and abs(L - Lw) <= TOL64
 
@@ -220,12 +224,12 @@ def test_angles_override_matches_rebuilt_plan():
 # --------------------------------------------------------------------------- FP32
 
 
-@pytest.mark.parametrize("nq", [3, 12, 20])
-def test_fp32_against_fp64_oracle(nq):
+@pytest.mark.parametrize("nq,reg_bits", [(3, 4), (12, 4), (20, 4), (12, 5), (20, 5)])
+def test_fp32_against_fp64_oracle(nq, reg_bits):
     inst = W.single_instance(W.SEEDS["large_fp32"], nq)
     prob = {"nq": nq, "gates": inst["gates"], "marked": inst["marked"]}
-    _say("fp32 nq=%d" % nq)
-    _, got, L, norm = _run(prob, inst["psi"], prec="fp32")
+    _say("fp32 nq=%d reg_bits=%d" % (nq, reg_bits))
+    _, got, L, norm = _run(prob, inst["psi"], prec="fp32", launch=(0, reg_bits))
     want, Lw, nw = O.evaluate(nq, inst["gates"], inst["marked"], inst["psi"])
     err = _relerr(got, want)
     _say("fp32 nq=%d normwise error %.3e |dL| %.3e" % (nq, err, abs(L - Lw)))
@@ -237,12 +241,13 @@ def test_fp32_against_fp64_oracle(nq):
 # --------------------------------------------------------------------------- batched
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_batched_against_oracle(prec):
+@pytest.mark.parametrize("prec,reg_bits", [("fp64", 4), ("fp32", 4), ("fp64", 5), ("fp32", 5)])
+def test_batched_against_oracle(prec, reg_bits):
     pk = _pk()
     insts = W.batch_instances(W.SEEDS["batched"], count=48, nq_min=3, span=13)
     probs = [{"nq": i["nq"], "gates": i["gates"], "marked": i["marked"]} for i in insts]
     plan = pk.Plan(probs, prec=prec)
+    plan.set_launch(0, reg_bits)
     offs = plan.offsets()
     packed = np.concatenate([i["psi"] for i in insts])
     dt = torch.complex128 if prec == "fp64" else torch.complex64

@@ -67,6 +67,10 @@ def test_fp32_allows_31_qubits_and_tiling_limits():
     with pytest.raises(pk.PaperkernError):
         plan64.set_tiling(14)
     with pytest.raises(pk.PaperkernError):
+        plan64.set_launch(0, 6)
+    with pytest.raises(pk.PaperkernError):
+        plan64.set_launch(9, 4)
+    with pytest.raises(pk.PaperkernError):
         plan64.set_tiling(10, carrier_bits=7)
     with pytest.raises(pk.PaperkernError):
         plan64.set_tiling(10, fuse=2)
@@ -90,6 +94,10 @@ def test_pass_counts_at_thirty_qubits():
     assert plan.passes() == 5
     plan32 = pk.Plan({"nq": 30, "gates": inst["gates"], "marked": inst["marked"]}, prec="fp32")
     assert plan32.passes() == 5
+    plan.set_launch(0, 5)
+    assert plan.passes() == 5
+    stages = [len(p["stages"]) for p in plan.describe()["instances"][0]["forward"]]
+    assert sum(stages) <= 13  # five register bits: fewer LDS exchanges than with four
     plan.set_tiling(13, 4, fuse=0)
     assert plan.passes() == 61  # one sweep per one-qubit gate (2 HALL x 30 + D2)
 
@@ -104,10 +112,12 @@ def test_pair_indices_rejects_bad_ranges():
 # --------------------------------------------------------------------------- schedules
 
 
-def _check_forward(problem, psi, tiling=None, prec="fp64"):
+def _check_forward(problem, psi, tiling=None, prec="fp64", reg_bits=4):
     plan = pk.Plan(problem, prec=prec)
     if tiling:
         plan.set_tiling(*tiling)
+    if reg_bits != 4:
+        plan.set_launch(0, reg_bits)
     desc = plan.describe()
     got, L = run_forward([problem], desc, 0, psi)
     want, Lw, _ = O.evaluate(problem["nq"], problem["gates"], problem["marked"], psi)
@@ -118,12 +128,13 @@ def _check_forward(problem, psi, tiling=None, prec="fp64"):
 
 @pytest.mark.parametrize("nq", [1, 2, 3, 4, 5, 8, 13, 14, 16])
 @pytest.mark.parametrize("eloc", [0, 2, 4])
-def test_grover_schedule_matches_oracle(nq, eloc):
+@pytest.mark.parametrize("reg_bits", [4, 5])
+def test_grover_schedule_matches_oracle(nq, eloc, reg_bits):
     rng = np.random.default_rng(nq * 10 + eloc)
     qhit = int(rng.integers(1, nq + 1))
     prob = {"nq": nq, "gates": W.grover_gates((qhit, eloc, 1.1, 0.6, 0.2)),
             "marked": [int(rng.integers(0, 1 << nq))]}
-    _check_forward(prob, _state(rng, nq))
+    _check_forward(prob, _state(rng, nq), reg_bits=reg_bits)
 
 
 @pytest.mark.parametrize("tiling", [(4, 0, 1), (5, 2, 1), (6, 3, 1), (7, 4, 1), (6, 2, 0), (10, 6, 1)])

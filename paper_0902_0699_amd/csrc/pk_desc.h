@@ -42,11 +42,33 @@ struct Op {
     int32_t pad;
 };
 
+// One sub-stage: a fixed sequence of optional steps applied to the registers,
+// in this order: seed, flip, matrix, Hadamards (mask 1), flip, Hadamards
+// (mask 2), matrix, backward D2, scale, read.  A stage's op list is packed into
+// as many sub-stages as its order needs; only the first of them exchanges the
+// tile through LDS (`exchange`), the others keep the layout.  Straight-line
+// steps instead of an op loop let the compiler update the register tile in
+// place.
 struct Stage {
     int32_t rb[kMaxRegBits];  // local tile bit held by register bit a (-1 when unused)
     int32_t rbs[kMaxRegBits]; // the same bits sorted ascending (-1 entries last)
-    int32_t op_begin;
-    int32_t op_count;
+    int32_t exchange;         // 1: move the tile into this layout through LDS first
+    int32_t seed;             // flip index of a SEED (backward start) or -1
+    int32_t flip_pre;         // flip index or -1
+    int32_t mat_pre_a;        // register bit of a matrix before the Hadamards, or -1
+    int32_t mat_pre;          // its matrix index
+    int32_t hmask1;           // register bits that get a Hadamard
+    int32_t flip_mid;         // flip index between the two Hadamard masks, or -1
+    int32_t hmask2;
+    int32_t mat_post_a;       // register bit of a matrix after the Hadamards, or -1
+    int32_t mat_post;
+    int32_t d2b_a;            // backward D2 on this register bit, or -1
+    int32_t d2b_mat;          // first of its five matrices
+    int32_t d2b_gslot;        // base of its gradient partials
+    float d2b_gscale;         // 1/s^2 for the deferred scale s at that point
+    int32_t scale;            // 1: multiply by the pass scale
+    int32_t read;             // flip index of a READ or -1
+    int32_t pad;
 };
 
 // One amplitude addressed by (tile, local label) in a given pass.

@@ -138,19 +138,23 @@ __device__ __forceinline__ int64_t goff(const GOff& G, int i) {
 
 // ---------------------------------------------------------------------------- gate bodies
 
+// Hadamard butterfly (x, y) <- (x + y, x - y), unnormalised, written to update
+// both registers in place: x += y, then y = x_new - 2 y (one rounding more than
+// x - y, well inside the FP64 and FP32 tolerances).  In-place updates let the
+// compiler keep the tile in one set of registers through the predicated steps.
 template <int A, int NV, int NR, typename T>
 __device__ __forceinline__ void op_h(T (&v)[NV][NR]) {
+    using R = decltype(v[0][0].x);
 #pragma unroll
     for (int n = 0; n < NV; ++n)
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
             if (i & (1 << A)) continue;
             const int j = i | (1 << A);
-            T x = v[n][i], y = v[n][j];
-            v[n][i].x = x.x + y.x;
-            v[n][i].y = x.y + y.y;
-            v[n][j].x = x.x - y.x;
-            v[n][j].y = x.y - y.y;
+            v[n][i].x += v[n][j].x;
+            v[n][i].y += v[n][j].y;
+            v[n][j].x = fma((R)-2, v[n][j].x, v[n][i].x);
+            v[n][j].y = fma((R)-2, v[n][j].y, v[n][i].y);
         }
 }
 
@@ -211,44 +215,36 @@ __device__ __forceinline__ void op_d2bwd(T (&v)[NV][NR], const R (&mh)[8], const
     }
 }
 
+// Hadamards on the register bits set in `mask` (distinct bits commute).
 template <int NV, int NR, typename T>
-__device__ __forceinline__ void dispatch_h(T (&v)[NV][NR], int a) {
-    switch (a) {
-    case 0: op_h<0, NV, NR>(v); break;
-    case 1: op_h<1, NV, NR>(v); break;
-    case 2: op_h<2, NV, NR>(v); break;
-    case 3: op_h<3, NV, NR>(v); break;
-    default:
-        if constexpr (NR > 16) op_h<4, NV, NR>(v);
-        break;
-    }
+__device__ __forceinline__ void apply_hmask(T (&v)[NV][NR], int mask) {
+    if (mask & 1) op_h<0, NV, NR>(v);
+    if (mask & 2) op_h<1, NV, NR>(v);
+    if (mask & 4) op_h<2, NV, NR>(v);
+    if (mask & 8) op_h<3, NV, NR>(v);
+    if constexpr (NR > 16)
+        if (mask & 16) op_h<4, NV, NR>(v);
 }
 
 template <int NV, int NR, typename T, typename R>
-__device__ __forceinline__ void dispatch_m(T (&v)[NV][NR], int a, const R (&m)[8]) {
-    switch (a) {
-    case 0: op_m<0, NV, NR>(v, m); break;
-    case 1: op_m<1, NV, NR>(v, m); break;
-    case 2: op_m<2, NV, NR>(v, m); break;
-    case 3: op_m<3, NV, NR>(v, m); break;
-    default:
-        if constexpr (NR > 16) op_m<4, NV, NR>(v, m);
-        break;
-    }
+__device__ __forceinline__ void apply_mat(T (&v)[NV][NR], int a, const R (&m)[8]) {
+    if (a == 0) op_m<0, NV, NR>(v, m);
+    if (a == 1) op_m<1, NV, NR>(v, m);
+    if (a == 2) op_m<2, NV, NR>(v, m);
+    if (a == 3) op_m<3, NV, NR>(v, m);
+    if constexpr (NR > 16)
+        if (a == 4) op_m<4, NV, NR>(v, m);
 }
 
 template <int NV, int NR, typename T, typename R>
-__device__ __forceinline__ void dispatch_d2bwd(T (&v)[NV][NR], int a, const R (&mh)[8],
-                                               const PK_CONST double* dmats, double (&g)[3]) {
-    switch (a) {
-    case 0: op_d2bwd<0, NV, NR>(v, mh, dmats, g); break;
-    case 1: op_d2bwd<1, NV, NR>(v, mh, dmats, g); break;
-    case 2: op_d2bwd<2, NV, NR>(v, mh, dmats, g); break;
-    case 3: op_d2bwd<3, NV, NR>(v, mh, dmats, g); break;
-    default:
-        if constexpr (NR > 16) op_d2bwd<4, NV, NR>(v, mh, dmats, g);
-        break;
-    }
+__device__ __forceinline__ void apply_d2bwd(T (&v)[NV][NR], int a, const R (&mh)[8], const PK_CONST double* dmats,
+                                            double (&g)[3]) {
+    if (a == 0) op_d2bwd<0, NV, NR>(v, mh, dmats, g);
+    if (a == 1) op_d2bwd<1, NV, NR>(v, mh, dmats, g);
+    if (a == 2) op_d2bwd<2, NV, NR>(v, mh, dmats, g);
+    if (a == 3) op_d2bwd<3, NV, NR>(v, mh, dmats, g);
+    if constexpr (NR > 16)
+        if (a == 4) op_d2bwd<4, NV, NR>(v, mh, dmats, g);
 }
 
 // Sum of one double per thread over the workgroup; result valid in thread 0.
@@ -365,6 +361,44 @@ __device__ __forceinline__ void store_tile(const KArgs& a, const PassCtx& C, int
     }
 }
 
+// One-amplitude steps on the element flips[f] when it lies in this tile and
+// thread: KIND 0 negates it (Oracle, Inv's C_0), 1 stores |C|^2 to its readout
+// slot, 2 seeds lambda = dL * psi there.  Written as selects, so the register
+// tile is updated in place.
+template <int NV, int NR, int KIND, typename T>
+__device__ __forceinline__ void element_op(const KArgs& a, T (&v)[NV][NR], const Layout& L, int f, int64_t tile,
+                                           int nreg, bool active) {
+    const PK_CONST Flip* fl = cptr(a.flips) + f;
+    if (fl->tile != tile || !active) return;
+    const unsigned jrel = (unsigned)fl->j ^ L.jt;
+    unsigned rmask = 0;
+#pragma unroll
+    for (int q = 0; q < kMaxRegBits; ++q) rmask |= L.r[q];
+    if ((jrel & ~rmask) != 0u) return;
+    const int slot = fl->slot;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        if (i >= nreg) continue;
+        const bool hit = roff(L, i) == jrel;
+        if constexpr (KIND == 0) {
+#pragma unroll
+            for (int n = 0; n < NV; ++n) {
+                v[n][i].x = hit ? -v[n][i].x : v[n][i].x;
+                v[n][i].y = hit ? -v[n][i].y : v[n][i].y;
+            }
+        } else if constexpr (KIND == 1) {
+            if (hit) {
+                const double x = v[0][i].x, y = v[0][i].y;
+                a.reads[slot] = x * x + y * y;
+            }
+        } else if constexpr (NV == 2) {
+            const auto d = (decltype(v[0][0].x))a.dL[slot];
+            v[1][i].x = hit ? d * v[0][i].x : v[1][i].x;
+            v[1][i].y = hit ? d * v[0][i].y : v[1][i].y;
+        }
+    }
+}
+
 // Every stage of the pass on one tile held in registers, then the norm partial.
 template <typename R, int NV, int KMAX, int RB>
 __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass* P, const PassCtx& C,
@@ -377,11 +411,10 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
     const int nreg = C.nreg;
     const PK_CONST Stage* S = cptr(a.stages) + P->stage_begin;
     Layout L = C.L0;
-    for (int s = 0; s < C.nstages; ++s) {
-        if (s > 0) {
+    for (int s = 0; s < C.nstages; ++s, ++S) {
+        if (s > 0 && S->exchange) {
             // ---- LDS exchange: previous layout out, this layout in
-            const PK_CONST Stage* Sn = S + 1;
-            const Layout Ln = (s == C.nstages - 1) ? C.Ll : make_layout<(int)sizeof(R) * 2>(Sn, C.nrb, tid);
+            const Layout Ln = (s == C.nstages - 1) ? C.Ll : make_layout<(int)sizeof(R) * 2>(S, C.nrb, tid);
 #pragma unroll
             for (int n = 0; n < NV; ++n) {
                 if (active) {
@@ -397,91 +430,58 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
                 }
                 __syncthreads();
             }
-            S = Sn;
             L = Ln;
         }
-        // ---- the stage's gates, in order
-        const int op_count = S->op_count;
-        const PK_CONST Op* ops = cptr(a.ops) + S->op_begin;
-        for (int o = 0; o < op_count; ++o) {
-            const int kind = ops[o].kind;
-            const int ra = ops[o].a;
-            const int arg = ops[o].arg;
-            switch (kind) {
-            case OP_H:
-                dispatch_h<NV, NR>(v, ra);
-                break;
-            case OP_MAT: {
-                R m[8];
-                const PK_CONST double* mp = cptr(a.mats) + 8 * arg;
+        // ---- the sub-stage's steps, in their fixed order
+        if constexpr (NV == 2) {
+            if (S->seed >= 0) element_op<NV, NR, 2>(a, v, L, S->seed, tile, nreg, active);
+        }
+        if (S->flip_pre >= 0) element_op<NV, NR, 0>(a, v, L, S->flip_pre, tile, nreg, active);
+        if (S->mat_pre_a >= 0) {
+            R m[8];
+            const PK_CONST double* mp = cptr(a.mats) + 8 * S->mat_pre;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) m[e] = (R)mp[e];
-                dispatch_m<NV, NR>(v, ra, m);
-                break;
-            }
-            case OP_FLIP:
-            case OP_READ:
-            case OP_SEED: {
-                const PK_CONST Flip* f = cptr(a.flips) + arg;
-                if (f->tile == tile && active) {
-                    const unsigned jrel = (unsigned)f->j ^ L.jt;
-                    const unsigned rmask = L.r[0] | L.r[1] | L.r[2] | L.r[3] | L.r[4];
-                    const int slot = f->slot;
-                    if ((jrel & ~rmask) == 0u) {
+            for (int e = 0; e < 8; ++e) m[e] = (R)mp[e];
+            apply_mat<NV, NR>(v, S->mat_pre_a, m);
+        }
+        apply_hmask<NV, NR>(v, S->hmask1);
+        if (S->flip_mid >= 0) element_op<NV, NR, 0>(a, v, L, S->flip_mid, tile, nreg, active);
+        apply_hmask<NV, NR>(v, S->hmask2);
+        if (S->mat_post_a >= 0) {
+            R m[8];
+            const PK_CONST double* mp = cptr(a.mats) + 8 * S->mat_post;
 #pragma unroll
-                        for (int i = 0; i < NR; ++i) {
-                            if (i < nreg && roff(L, i) == jrel) {
-                                if (kind == OP_FLIP) {
-#pragma unroll
-                                    for (int n = 0; n < NV; ++n) {
-                                        v[n][i].x = -v[n][i].x;
-                                        v[n][i].y = -v[n][i].y;
-                                    }
-                                } else if (kind == OP_READ) {
-                                    const double x = v[0][i].x, y = v[0][i].y;
-                                    a.reads[slot] = x * x + y * y;
-                                } else if constexpr (NV == 2) {
-                                    const R d = (R)a.dL[slot];
-                                    v[1][i].x = d * v[0][i].x;
-                                    v[1][i].y = d * v[0][i].y;
-                                }
-                            }
-                        }
-                    }
-                }
-                break;
-            }
-            case OP_SCALE: {
-                const R sc = (R)P->scale;
-#pragma unroll
-                for (int n = 0; n < NV; ++n)
-#pragma unroll
-                    for (int i = 0; i < NR; ++i) {
-                        v[n][i].x *= sc;
-                        v[n][i].y *= sc;
-                    }
-                break;
-            }
-            case OP_D2BWD: {
+            for (int e = 0; e < 8; ++e) m[e] = (R)mp[e];
+            apply_mat<NV, NR>(v, S->mat_post_a, m);
+        }
+        if constexpr (NV == 2) {
+            if (S->d2b_a >= 0) {
                 R mh[8];
-                const PK_CONST double* mp = cptr(a.mats) + 8 * arg;
+                const PK_CONST double* mp = cptr(a.mats) + 8 * S->d2b_mat;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) mh[e] = (R)mp[8 + e];
                 double g[3] = {0.0, 0.0, 0.0};
-                if (active) dispatch_d2bwd<NV, NR>(v, ra, mh, mp + 16, g);
-                const double scale = 2.0 * (double)ops[o].gscale;
-                const int gslot = ops[o].gslot;
+                if (active) apply_d2bwd<NV, NR>(v, S->d2b_a, mh, mp + 16, g);
+                const double scale = 2.0 * (double)S->d2b_gscale;
+                const int gslot = S->d2b_gslot;
 #pragma unroll
                 for (int t = 0; t < 3; ++t) {
                     const double tot = block_sum<NT>(g[t], red);
                     if (tid == 0) a.gpart[gslot + t * P->ntiles + tile] = scale * tot;
                 }
-                break;
-            }
-            default:
-                break;
             }
         }
+        if (S->scale) {
+            const R sc = (R)P->scale;
+#pragma unroll
+            for (int n = 0; n < NV; ++n)
+#pragma unroll
+                for (int i = 0; i < NR; ++i) {
+                    v[n][i].x *= sc;
+                    v[n][i].y *= sc;
+                }
+        }
+        if (S->read >= 0) element_op<NV, NR, 1>(a, v, L, S->read, tile, nreg, active);
     }
 
     // ---- norm partial of the final state (FP64 for FP64 data; Neumaier-

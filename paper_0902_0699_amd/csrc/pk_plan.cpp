@@ -98,6 +98,79 @@ int64_t extract(int64_t x, const std::vector<int>& bits) {
     return r;
 }
 
+// Packs one stage's op list into fixed-slot sub-stages (see Stage).  Ops keep
+// their order: each goes to the first free slot at or after the previous op's
+// slot, and a new sub-stage (same layout, no exchange) starts when none fits.
+// Hadamards collected in one mask act on distinct register bits and commute.
+enum Slot { S_SEED = 0, S_FLIP_PRE, S_MAT_PRE, S_H1, S_FLIP_MID, S_H2, S_MAT_POST, S_D2B, S_SCALE, S_READ };
+
+Stage blank_sub(const HostStage& hs, int exchange) {
+    Stage s{};
+    int nrb = 0;
+    for (int a = 0; a < kMaxRegBits; ++a) {
+        s.rb[a] = hs.rb[a];
+        if (hs.rb[a] >= 0) s.rbs[nrb++] = hs.rb[a];
+    }
+    std::sort(s.rbs, s.rbs + nrb);
+    for (int a = nrb; a < kMaxRegBits; ++a) s.rbs[a] = -1;
+    s.exchange = exchange;
+    s.seed = s.flip_pre = s.flip_mid = s.read = -1;
+    s.mat_pre_a = s.mat_post_a = s.d2b_a = -1;
+    return s;
+}
+
+int place(Stage& s, int cursor, const Op& o) {
+    switch (o.kind) {
+    case OP_SEED:
+        if (cursor <= S_SEED && s.seed < 0) { s.seed = o.arg; return S_SEED; }
+        return -1;
+    case OP_FLIP:
+        if (cursor <= S_FLIP_PRE && s.flip_pre < 0) { s.flip_pre = o.arg; return S_FLIP_PRE; }
+        if (cursor <= S_FLIP_MID && s.flip_mid < 0) { s.flip_mid = o.arg; return S_FLIP_MID; }
+        return -1;
+    case OP_MAT:
+        if (cursor <= S_MAT_PRE && s.mat_pre_a < 0) { s.mat_pre_a = o.a; s.mat_pre = o.arg; return S_MAT_PRE; }
+        if (cursor <= S_MAT_POST && s.mat_post_a < 0) { s.mat_post_a = o.a; s.mat_post = o.arg; return S_MAT_POST; }
+        return -1;
+    case OP_H:
+        if (cursor <= S_H1 && !(s.hmask1 >> o.a & 1)) { s.hmask1 |= 1 << o.a; return S_H1; }
+        if (cursor <= S_H2 && !(s.hmask2 >> o.a & 1)) { s.hmask2 |= 1 << o.a; return S_H2; }
+        return -1;
+    case OP_D2BWD:
+        if (cursor <= S_D2B && s.d2b_a < 0) {
+            s.d2b_a = o.a; s.d2b_mat = o.arg; s.d2b_gslot = o.gslot; s.d2b_gscale = o.gscale;
+            return S_D2B;
+        }
+        return -1;
+    case OP_SCALE:
+        if (cursor <= S_SCALE && !s.scale) { s.scale = 1; return S_SCALE; }
+        return -1;
+    case OP_READ:
+        if (cursor <= S_READ && s.read < 0) { s.read = o.arg; return S_READ; }
+        return -1;
+    default:
+        return -1;
+    }
+}
+
+std::vector<Stage> pack_stage(const HostStage& hs) {
+    std::vector<Stage> subs;
+    Stage cur = blank_sub(hs, 1);
+    int cursor = 0;
+    for (const Op& o : hs.ops) {
+        int slot = place(cur, cursor, o);
+        if (slot < 0) {
+            subs.push_back(cur);
+            cur = blank_sub(hs, 0);
+            cursor = 0;
+            slot = place(cur, cursor, o);
+        }
+        cursor = slot;
+    }
+    subs.push_back(cur);
+    return subs;
+}
+
 struct Compiler {
     Plan* plan;
     Instance* in;
@@ -326,6 +399,10 @@ struct Compiler {
                     fin.ops.push_back(o);
                 }
             }
+            for (const HostStage& hs : hp.stages) {
+                std::vector<Stage> sub = pack_stage(hs);
+                hp.subs.insert(hp.subs.end(), sub.begin(), sub.end());
+            }
             out->push_back(hp);
             ++pass_no;
         } while (left > 0);
@@ -499,7 +576,6 @@ int recompile(Plan* plan, std::string* err) {
     auto emit = [&](Instance& in, int idx, HostPass& hp) {
         Pass p{};
         p.k = hp.k;
-        p.nstages = (int)hp.stages.size();
         p.stage_begin = (int)plan->stages.size();
         p.ntiles = hp.ntiles;
         p.state_off = in.off;
@@ -543,20 +619,8 @@ int recompile(Plan* plan, std::string* err) {
             }
             if (maxoff * (uint64_t)esz >= ((uint64_t)1 << 32)) p.flags |= PASS_WIDE;
         }
-        for (auto& hs : hp.stages) {
-            Stage s{};
-            int nrb = 0;
-            for (int a = 0; a < kMaxRegBits; ++a) {
-                s.rb[a] = hs.rb[a];
-                if (hs.rb[a] >= 0) s.rbs[nrb++] = hs.rb[a];
-            }
-            std::sort(s.rbs, s.rbs + nrb);
-            for (int a = nrb; a < kMaxRegBits; ++a) s.rbs[a] = -1;
-            s.op_begin = (int)plan->ops.size();
-            s.op_count = (int)hs.ops.size();
-            for (auto& o : hs.ops) plan->ops.push_back(o);
-            plan->stages.push_back(s);
-        }
+        p.nstages = (int)hp.subs.size();
+        for (const Stage& st : hp.subs) plan->stages.push_back(st);
         plan->passes.push_back(p);
     };
     for (size_t i = 0; i < plan->inst.size(); ++i)
@@ -709,11 +773,34 @@ std::string describe(const Plan* plan) {
                     }
                     s += "]}";
                 }
+                s += "],\"subs\":[";
+                for (size_t q = 0; q < hp.subs.size(); ++q) {
+                    const Stage& u = hp.subs[q];
+                    if (q) s += ",";
+                    std::snprintf(buf, sizeof buf, "%.9g", (double)u.d2b_gscale);
+                    s += "{\"rb\":[";
+                    for (int a = 0; a < kMaxRegBits; ++a) s += (a ? "," : "") + std::to_string(u.rb[a]);
+                    s += "],\"exchange\":" + std::to_string(u.exchange) + ",\"seed\":" + std::to_string(u.seed) +
+                         ",\"flip_pre\":" + std::to_string(u.flip_pre) + ",\"mat_pre_a\":" +
+                         std::to_string(u.mat_pre_a) + ",\"mat_pre\":" + std::to_string(u.mat_pre) +
+                         ",\"hmask1\":" + std::to_string(u.hmask1) + ",\"flip_mid\":" +
+                         std::to_string(u.flip_mid) + ",\"hmask2\":" + std::to_string(u.hmask2) +
+                         ",\"mat_post_a\":" + std::to_string(u.mat_post_a) + ",\"mat_post\":" +
+                         std::to_string(u.mat_post) + ",\"d2b_a\":" + std::to_string(u.d2b_a) +
+                         ",\"d2b_mat\":" + std::to_string(u.d2b_mat) + ",\"d2b_gscale\":" + buf +
+                         ",\"scale\":" + std::to_string(u.scale) + ",\"read\":" + std::to_string(u.read) + "}";
+                }
                 s += "]}";
             }
             s += "]";
         }
         s += "}";
+    }
+    s += "],\"flips\":[";
+    for (size_t f = 0; f < plan->flips.size(); ++f) {
+        const Flip& fl = plan->flips[f];
+        if (f) s += ",";
+        s += "[" + std::to_string(fl.tile) + "," + std::to_string(fl.j) + "," + std::to_string(fl.slot) + "]";
     }
     s += "]}";
     return s;

@@ -28,6 +28,7 @@ struct HostPass {
     int k = 0;
     std::vector<int> tbits;  // global bits of the tile, ascending (local bit l -> tbits[l])
     std::vector<HostStage> stages;
+    std::vector<Stage> subs;  // the stages packed into fixed-slot sub-stages (device form)
     int flags = 0;
     double scale = 1.0;
     int64_t ntiles = 0;

@@ -71,7 +71,81 @@ def check_stage_shapes(nq, p):
     assert all(0 <= b < nq for b in p["tile_bits"])
 
 
+def _flip_index(desc, nq, tb, f):
+    tile, j, slot = desc["flips"][f]
+    return _global_index(nq, tb, tile, j), slot
+
+
+def _run_subs(problems, desc, inst, direction, psi, lam=None, dL=1.0):
+    """Executes the packed sub-stages (the form the kernel runs) of one direction."""
+    mat = _matrix_table(problems, desc)
+    info = desc["instances"][inst]
+    nq = info["nq"]
+    H = np.array([[1, 1], [1, -1]], dtype=np.complex128)
+    vecs = [psi] if lam is None else [psi, lam]
+    reads, grads = {}, {}
+    for p in info[direction]:
+        check_stage_shapes(nq, p)
+        tb = p["tile_bits"]
+        assert p["subs"] and p["subs"][0]["exchange"] == 1
+        for u in p["subs"]:
+            rb = u["rb"]
+            if u["seed"] >= 0:
+                g, _ = _flip_index(desc, nq, tb, u["seed"])
+                vecs[1][g] = dL * vecs[0][g]
+            if u["flip_pre"] >= 0:
+                g, _ = _flip_index(desc, nq, tb, u["flip_pre"])
+                for v in vecs:
+                    v[g] *= -1
+            if u["mat_pre_a"] >= 0:
+                for v in vecs:
+                    _apply_bit(v, nq, tb[rb[u["mat_pre_a"]]], mat(u["mat_pre"]))
+            for a in range(5):
+                if u["hmask1"] >> a & 1:
+                    for v in vecs:
+                        _apply_bit(v, nq, tb[rb[a]], H)
+            if u["flip_mid"] >= 0:
+                g, _ = _flip_index(desc, nq, tb, u["flip_mid"])
+                for v in vecs:
+                    v[g] *= -1
+            for a in range(5):
+                if u["hmask2"] >> a & 1:
+                    for v in vecs:
+                        _apply_bit(v, nq, tb[rb[a]], H)
+            if u["mat_post_a"] >= 0:
+                for v in vecs:
+                    _apply_bit(v, nq, tb[rb[u["mat_post_a"]]], mat(u["mat_post"]))
+            if u["d2b_a"] >= 0:
+                bit = tb[rb[u["d2b_a"]]]
+                m0 = u["d2b_mat"]
+                _apply_bit(vecs[0], nq, bit, mat(m0 + 1))
+                d = (m0 - 2 * desc["n_static"]) // 5
+                for t in range(3):
+                    dpsi = vecs[0].copy()
+                    _apply_bit(dpsi, nq, bit, mat(m0 + 2 + t))
+                    grads[(d, t)] = 2.0 * u["d2b_gscale"] * float(np.vdot(vecs[1], dpsi).real)
+                _apply_bit(vecs[1], nq, bit, mat(m0 + 1))
+            if u["scale"]:
+                for v in vecs:
+                    v *= p["scale"]
+            if u["read"] >= 0:
+                g, slot = _flip_index(desc, nq, tb, u["read"])
+                reads[slot] = abs(vecs[0][g]) ** 2
+    return vecs, reads, grads
+
+
 def run_forward(problems, desc, inst, psi_in):
+    """Returns (psi_out, L) of instance ``inst`` by executing its packed forward schedule,
+    after checking that the op-level form gives the same state."""
+    psi_ops, L_ops = run_forward_ops(problems, desc, inst, psi_in)
+    vecs, reads, _ = _run_subs(problems, desc, inst, "forward", np.array(psi_in, dtype=np.complex128))
+    L = sum(reads[s] for s in sorted(reads))
+    np.testing.assert_allclose(vecs[0], psi_ops, rtol=0, atol=1e-13)
+    assert abs(L - L_ops) <= 1e-14 * max(1.0, abs(L_ops)), (L, L_ops)
+    return vecs[0], L
+
+
+def run_forward_ops(problems, desc, inst, psi_in):
     """Returns (psi_out, L) of instance ``inst`` by executing its forward schedule."""
     mat = _matrix_table(problems, desc)
     info = desc["instances"][inst]
@@ -101,6 +175,22 @@ def run_forward(problems, desc, inst, psi_in):
 
 
 def run_backward(problems, desc, inst, psi_out, dL):
+    """Returns (grad_psi_in, grad_angles) from the packed backward schedule, after
+    checking it against the op-level form."""
+    g_ops, a_ops = run_backward_ops(problems, desc, inst, psi_out, dL)
+    psi = np.array(psi_out, dtype=np.complex128)
+    vecs, _, grads = _run_subs(problems, desc, inst, "backward", psi, np.zeros_like(psi), dL)
+    n_d2 = len({d for d, _ in grads})
+    ga = np.zeros((n_d2, 3))
+    d0 = min([d for d, _ in grads], default=0)
+    for (d, t), v in grads.items():
+        ga[d - d0, t] = v
+    np.testing.assert_allclose(vecs[1], g_ops, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(ga, a_ops, rtol=0, atol=1e-13)
+    return vecs[1], ga
+
+
+def run_backward_ops(problems, desc, inst, psi_out, dL):
     """Returns (grad_psi_in, grad_angles) by executing the backward schedule."""
     mat = _matrix_table(problems, desc)
     info = desc["instances"][inst]

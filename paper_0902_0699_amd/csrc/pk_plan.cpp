@@ -12,7 +12,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <set>
+#include <string>
 
 namespace pk {
 
@@ -177,6 +179,9 @@ struct Compiler {
     bool backward;
     int k, C, RB;
     int RBITS;  // register bits of the kernel instance (RB may be smaller for tiny tiles)
+    // cut decisions depend only on the structure (nq, tiling, item kinds and bits,
+    // what is done); instances of a batch often share it
+    std::map<std::string, std::vector<int>>* cut_cache = nullptr;
 
     std::vector<int> free_bits(const std::vector<int>& tbits) const {
         std::vector<char> used(in->nq, 0);
@@ -262,6 +267,126 @@ struct Compiler {
         return stages;
     }
 
+    // Tile bits of the next pass: the carriers, then greedily the bits that let
+    // the most pending primitives run; returns the primitives the pass takes.
+    std::vector<int> choose_tile(const std::vector<ScanItem>& items, const std::vector<char>& done,
+                                 std::vector<int>* sel) const {
+        const int nq = in->nq;
+        const int max_gates = plan->tiling.fuse ? -1 : 1;
+        std::vector<char> in_t(nq, 0);
+        std::vector<int> t;
+        for (int b = 0; b < C; ++b) {
+            in_t[b] = 1;
+            t.push_back(b);
+        }
+        while ((int)t.size() < k) {
+            int best = -1, best_gain = -1;
+            for (int b = 0; b < nq; ++b) {
+                if (in_t[b]) continue;
+                in_t[b] = 1;
+                int g = scan(items, done, in_t, nq, max_gates, nullptr);
+                in_t[b] = 0;
+                if (g > best_gain) {
+                    best = b;
+                    best_gain = g;
+                }
+            }
+            in_t[best] = 1;
+            t.push_back(best);
+        }
+        std::sort(t.begin(), t.end());
+        sel->clear();
+        scan(items, done, in_t, nq, max_gates, sel);
+        return t;
+    }
+
+    std::vector<ScanItem> local_items(const std::vector<ScanItem>& items, const std::vector<int>& t,
+                                      const std::vector<int>& sel, size_t count) const {
+        std::vector<int> local_of(in->nq, -1);
+        for (int l = 0; l < (int)t.size(); ++l) local_of[t[l]] = l;
+        std::vector<ScanItem> litems;
+        for (size_t j = 0; j < count; ++j) {
+            const ScanItem& it = items[sel[j]];
+            litems.push_back({it.diag, it.diag ? 0 : local_of[it.bit]});
+        }
+        return litems;
+    }
+
+    // Cost of finishing the schedule greedily from `done`: (passes, sum of
+    // squared stage counts).  Used to compare cuts of the current pass.
+    std::pair<int, int> greedy_rest(const std::vector<ScanItem>& items, std::vector<char> done, int left) const {
+        int passes = 0, cost = 0;
+        std::vector<int> sel;
+        while (left > 0) {
+            auto t = choose_tile(items, done, &sel);
+            int ns = (int)plan_stages(local_items(items, t, sel, sel.size())).size();
+            for (int i : sel) done[i] = 1;
+            left -= (int)sel.size();
+            ++passes;
+            cost += ns * ns;
+        }
+        return {passes, cost};
+    }
+
+    // The pass may leave gates on some of its tile bits to later passes: a scan
+    // with those bits removed still respects every ordering constraint.  Bits
+    // are dropped greedily while that lowers (pass count, sum of squared stage
+    // counts) of the whole remaining schedule, so one pass does not take all
+    // the stages its tile allows when a later pass can absorb them for free.
+    std::vector<int> choose_cut(const std::vector<ScanItem>& items, const std::vector<char>& done, int left,
+                                const std::vector<int>& t, const std::vector<int>& sel) const {
+        if ((int)sel.size() == left || !plan->tiling.fuse) return sel;
+        const int nq = in->nq;
+        std::string key;
+        if (cut_cache) {
+            int32_t hdr[4] = {nq, k, C, RB};
+            key.append((const char*)hdr, sizeof hdr);
+            for (size_t i = 0; i < items.size(); ++i) key.push_back(items[i].diag ? (char)-1 : (char)items[i].bit);
+            key.append(done.begin(), done.end());
+            auto it = cut_cache->find(key);
+            if (it != cut_cache->end()) return it->second;
+        }
+        auto cost_of = [&](const std::vector<int>& s) {
+            std::vector<char> d = done;
+            for (int i : s) d[i] = 1;
+            int ns = (int)plan_stages(local_items(items, t, s, s.size())).size();
+            auto rest = greedy_rest(items, d, left - (int)s.size());
+            return std::pair<int, int>{1 + rest.first, ns * ns + rest.second};
+        };
+        std::vector<char> in_t(nq, 0);
+        for (int b : t) in_t[b] = 1;
+        std::vector<int> best = sel;
+        auto best_cost = cost_of(sel);
+        for (;;) {
+            std::vector<int> round_best;
+            auto round_cost = best_cost;
+            int drop = -1;
+            for (int b : t) {
+                if (!in_t[b]) continue;
+                bool used = false;
+                for (int i : best) used = used || (!items[i].diag && items[i].bit == b);
+                if (!used) continue;
+                in_t[b] = 0;
+                std::vector<int> s;
+                scan(items, done, in_t, nq, -1, &s);
+                in_t[b] = 1;
+                if (s.empty()) continue;
+                auto c = cost_of(s);
+                if (c < round_cost) {
+                    round_cost = c;
+                    round_best = s;
+                    drop = b;
+                }
+            }
+            if (drop < 0) break;
+            in_t[drop] = 0;
+            best = round_best;
+            best_cost = round_cost;
+        }
+        if (cut_cache) (*cut_cache)[key] = best;
+        return best;
+    }
+
     void compile(const std::vector<Prim>& prims, std::vector<HostPass>* out) {
         const int nq = in->nq;
         const int n = (int)prims.size();
@@ -271,33 +396,10 @@ struct Compiler {
         int left = n;
         ScaleState sc;
         int pass_no = 0;
-        const int max_gates = plan->tiling.fuse ? -1 : 1;
         do {
-            // --- choose the tile bits: carriers, then greedy by gain
-            std::vector<char> in_t(nq, 0);
-            std::vector<int> t;
-            for (int b = 0; b < C; ++b) {
-                in_t[b] = 1;
-                t.push_back(b);
-            }
-            while ((int)t.size() < k) {
-                int best = -1, best_gain = -1;
-                for (int b = 0; b < nq; ++b) {
-                    if (in_t[b]) continue;
-                    in_t[b] = 1;
-                    int g = scan(items, done, in_t, nq, max_gates, nullptr);
-                    in_t[b] = 0;
-                    if (g > best_gain) {
-                        best = b;
-                        best_gain = g;
-                    }
-                }
-                in_t[best] = 1;
-                t.push_back(best);
-            }
-            std::sort(t.begin(), t.end());
             std::vector<int> sel;
-            scan(items, done, in_t, nq, max_gates, &sel);
+            std::vector<int> t = choose_tile(items, done, &sel);
+            sel = choose_cut(items, done, left, t, sel);
             for (int i : sel) done[i] = 1;
             left -= (int)sel.size();
             const bool last = (left == 0);
@@ -305,9 +407,7 @@ struct Compiler {
             // --- local items and stages
             std::vector<int> local_of(nq, -1);
             for (int l = 0; l < k; ++l) local_of[t[l]] = l;
-            std::vector<ScanItem> litems;
-            for (int i : sel) litems.push_back({items[i].diag, items[i].diag ? 0 : local_of[items[i].bit]});
-            auto st = plan_stages(litems);
+            auto st = plan_stages(local_items(items, t, sel, sel.size()));
 
             HostPass hp;
             hp.k = k;
@@ -548,8 +648,10 @@ int recompile(Plan* plan, std::string* err) {
     plan->n_reads = read_base;
 
     for (int dir = 0; dir < 2; ++dir) {
+        std::map<std::string, std::vector<int>> cut_cache;
         for (auto& in : plan->inst) {
             Compiler c;
+            c.cut_cache = &cut_cache;
             c.plan = plan;
             c.in = &in;
             c.backward = dir == 1;

@@ -33,7 +33,7 @@ __all__ = [
     "grover_gates", "apply_gate", "apply_gate_adjoint", "evaluate",
     "readout", "adjoint_grad", "fd_grad_angles", "fd_grad_psi",
     "kron_operator", "dense_circuit",
-    "grover_closed_form", "diffusion_closed_form",
+    "grover_closed_form", "diffusion_closed_form", "grover_sampled",
 ]
 
 # ---------------------------------------------------------------------------
@@ -433,3 +433,95 @@ def diffusion_closed_form(psi):
     """
     psi = np.asarray(psi, dtype=np.complex128)
     return 2.0 * psi.mean() - psi
+
+
+def grover_sampled(nq, gates, marked, psi_in, indices):
+    """Exact amplitudes of one Grover iteration at chosen labels, for any n_q.
+
+    ``gates`` must be ORACLE, HALL, INV, HALL (Sec. 5.1) with at most one D2 at
+    a stage boundary (Sec. 6.3).  Three identities remove every sweep:
+
+      * HALL . Inv . HALL = 2|s><s| - I, from Inv = 2|0><0| - I (Eq. inversion),
+        HALL|0..0> = |s> (Eq. Shor1) and HALL^2 = I;
+      * HALL . D_q . HALL = (H D H)_q, since H^2 = I on every other qubit;
+      * <0|HALL v> = N^(-1/2) sum_n v_n and <2^b|HALL v> = N^(-1/2) sum_n (-1)^(n_b) v_n.
+
+    Every intermediate vector v is then known through a function giving v_n at
+    any labels and its two half sums V_c = sum over n with bit b = c of v_n (b
+    the state bit of the D2 qubit).  The half sums of psi_in are the only pass
+    over the whole state.  Returns (amplitudes at ``indices``, L).
+    """
+    psi = np.asarray(psi_in, dtype=np.complex128)
+    size = 1 << nq
+    if psi.shape != (size,):
+        raise ValueError("psi_in must have 2^nq amplitudes")
+    kinds = [g[0] for g in gates]
+    steps = [k for k in kinds if k != "D2"]
+    if steps != ["ORACLE", "HALL", "INV", "HALL"] or kinds.count("D2") > 1:
+        raise ValueError("grover_sampled takes one Grover iteration with at most one D2")
+    eloc = kinds.index("D2") if "D2" in kinds else None
+    if eloc is not None:
+        d2 = gates[eloc]
+        b = nq - d2[1]
+        D = d2_matrix(*d2[2:5])
+    else:
+        b, D = 0, IDENTITY
+    Ms = np.array(sorted(set(int(x) for x in marked)), dtype=np.int64)
+    bit = 1 << b
+
+    def half_sums(v):
+        w = v.reshape(size >> (b + 1), 2, bit)
+        return w[:, 0, :].sum(), w[:, 1, :].sum()
+
+    def oracle(f, V):
+        def g(n):
+            out = np.array(f(n), dtype=np.complex128)
+            out[np.isin(n, Ms)] *= -1.0
+            return out
+        fx = f(Ms)
+        up = ((Ms >> b) & 1).astype(bool)
+        return g, (V[0] - 2.0 * fx[~up].sum(), V[1] - 2.0 * fx[up].sum())
+
+    def one_qubit(f, V, M):  # Eq. resmat1 on bit b
+        def g(n):
+            up = ((n >> b) & 1).astype(bool)
+            n0 = n & ~np.int64(bit)
+            a0, a1 = f(n0), f(n0 | bit)
+            return np.where(up, M[1, 0] * a0 + M[1, 1] * a1, M[0, 0] * a0 + M[0, 1] * a1)
+        return g, (M[0, 0] * V[0] + M[0, 1] * V[1], M[1, 0] * V[0] + M[1, 1] * V[1])
+
+    def diffusion(f, V):  # HALL . Inv . HALL
+        tot = V[0] + V[1]
+        return (lambda n: 2.0 * tot / size - f(n)), (tot - V[0], tot - V[1])
+
+    def diffusion_d2_inside(f, V, after_inv):
+        # HALL . Inv . D . HALL = 2 |s> <0|D HALL - (H D H)_q            (eloc 2)
+        # HALL . D . Inv . HALL = 2 HALL D|0> <0|HALL - (H D H)_q        (eloc 3)
+        g_dt, _ = one_qubit(f, V, HADAMARD @ D @ HADAMARD)
+        tot, alt = V[0] + V[1], V[0] - V[1]
+        if not after_inv:
+            c = 2.0 * (D[0, 0] * tot + D[0, 1] * alt) / size
+            return lambda n: c - g_dt(n)
+
+        def g(n):
+            sign = 1.0 - 2.0 * ((n >> b) & 1)
+            return 2.0 * tot * (D[0, 0] + D[1, 0] * sign) / size - g_dt(n)
+        return g
+
+    f = lambda n: psi[n]
+    V = half_sums(psi)
+    if eloc == 0:
+        f, V = one_qubit(f, V, D)
+    f, V = oracle(f, V)
+    if eloc == 1:
+        f, V = one_qubit(f, V, D)
+    if eloc in (2, 3):
+        f = diffusion_d2_inside(f, V, eloc == 3)
+    else:
+        f, V = diffusion(f, V)
+        if eloc == 4:
+            f, V = one_qubit(f, V, D)
+    idx = np.asarray(indices, dtype=np.int64)
+    vals = f(idx)
+    L = math.fsum(float(abs(v) ** 2) for v in f(Ms)) if len(Ms) else 0.0
+    return vals, L

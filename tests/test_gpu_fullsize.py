@@ -1,0 +1,137 @@
+"""GPU parity at the full workload sizes (n_q = 30), in the launch configuration that
+bench.py times (default tiling and launch).
+
+The gate-by-gate oracle cannot hold a 2^30-amplitude state in reasonable time, so
+the expected values come from oracle.grover_sampled: exact amplitudes of one Grover
+iteration at sampled labels through the diffusion identity (pinned against the
+gate-by-gate oracle on the CPU).  Compared per config:
+
+  * amplitudes at 2^16 seeded random labels plus the marked label, its partner on
+    the noisy qubit, 0 and N - 1: the root-mean-square error scaled by sqrt(N)
+    estimates the normwise error ||psi_gpu - psi_ref|| / ||psi_ref||;
+  * L against the closed form; the norm against ||psi_in||^2 (unitary circuit);
+  * the gradient (c4) against central differences on the 64-input subset.
+
+Each test prints its config before touching the GPU and needs ~50 GiB of host
+memory at most (the FP64 input state plus the generator's blocks).
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_0902_0699_amd import workload as W
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+NQ = W.NQ_LARGE
+TOL64 = 1e-12
+TOL32 = 1e-5
+SAMPLES = 1 << 16
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _labels(inst, seed):
+    nq = inst["nq"]
+    rng = np.random.default_rng(seed + 2000)
+    x = inst["marked"][0]
+    extra = [x, 0, (1 << nq) - 1]
+    if inst["noise"] is not None:
+        extra.append(x ^ (1 << (nq - inst["noise"][0])))
+    return np.unique(np.concatenate([rng.integers(0, 1 << nq, SAMPLES), np.array(extra, dtype=np.int64)]))
+
+
+def _check_sampled(prec, seed):
+    from paper_0902_0699_amd import paperkern as pk
+
+    _say("full size: n_q=%d %s seed %d" % (NQ, prec, seed))
+    inst = W.single_instance(seed, NQ)
+    psi = inst["psi"]
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    if prec == "fp32":
+        psi = psi.astype(np.complex64).astype(np.complex128)  # the input the FP32 path sees
+    idx = _labels(inst, seed)
+    want, L_ref = O.grover_sampled(NQ, inst["gates"], inst["marked"], psi, idx)
+    norm_in = float(np.vdot(psi, psi).real)
+
+    plan = pk.Plan({"nq": NQ, "gates": inst["gates"], "marked": inst["marked"]}, prec=prec)
+    x = torch.from_numpy(psi).to(dt).to("cuda")
+    del psi, inst["psi"]
+    y, L, norm = pk.evaluate(plan, x)
+    got = y[torch.from_numpy(idx).to("cuda")].cpu().numpy().astype(np.complex128)
+    L, norm = float(L.item()), float(norm.item())
+    del x, y
+    torch.cuda.empty_cache()
+
+    err = math.sqrt(np.mean(np.abs(got - want) ** 2) * (1 << NQ) / norm_in)
+    tol = TOL64 if prec == "fp64" else TOL32
+    _say("  passes %d  est. normwise err %.3e  |dL| %.3e (L %.6e)  |dnorm| %.3e"
+         % (plan.passes(), err, abs(L - L_ref), L_ref, abs(norm - norm_in)))
+    assert err <= tol
+    assert abs(L - L_ref) <= tol * max(1.0, L_ref) * norm_in
+    assert abs(norm - norm_in) <= tol * norm_in
+
+
+@pytest.mark.timeout(900)
+def test_c1_fp64_full_size_sampled():
+    _check_sampled("fp64", W.SEEDS["large_fp64"])
+
+
+@pytest.mark.timeout(900)
+def test_c2_fp32_full_size_sampled():
+    _check_sampled("fp32", W.SEEDS["large_fp32"])
+
+
+@pytest.mark.timeout(900)
+def test_c4_gradient_full_size_against_finite_differences():
+    from paper_0902_0699_amd import paperkern as pk
+
+    seed = W.SEEDS["gradient"]
+    _say("full size gradient: n_q=%d fp64 seed %d" % (NQ, seed))
+    inst = W.single_instance(seed, NQ)
+    comps = W.fd_subset(seed, inst)
+    plan = pk.Plan({"nq": NQ, "gates": inst["gates"], "marked": inst["marked"]})
+    x = torch.from_numpy(inst["psi"]).to("cuda")
+    del inst["psi"]
+    ang = torch.tensor(list(inst["noise"][2:5]), dtype=torch.float64, device="cuda")
+    out, _, _ = pk.evaluate(plan, x, angles=ang, want_norm=False)
+    dL = torch.ones(1, dtype=torch.float64, device="cuda")
+    gpsi, gang = pk.backward(plan, out, dL, angles=ang)
+    del out
+    h = 1e-6
+
+    def L_of(aa):
+        return pk.evaluate(plan, x, angles=aa, want_norm=False)[1].item()
+
+    fd, ad = [], []
+    for kind, where in comps:
+        if kind == "angle":
+            ap, am = ang.clone(), ang.clone()
+            ap[where] += h
+            am[where] -= h
+            fd.append((L_of(ap) - L_of(am)) / (2 * h))
+            ad.append(gang[where].item())
+        else:
+            i, part = where
+            step = h if part == 0 else 1j * h
+            orig = x[i].clone()
+            x[i] = orig + step
+            lp = L_of(ang)
+            x[i] = orig - step
+            lm = L_of(ang)
+            x[i] = orig
+            fd.append((lp - lm) / (2 * h))
+            g = gpsi[i].item()
+            ad.append(g.real if part == 0 else g.imag)
+    fd, ad = np.array(fd), np.array(ad)
+    err = float(np.max(np.abs(fd - ad)) / np.max(np.abs(ad)))
+    _say("  64 inputs: normwise FD vs adjoint %.3e; angle grads %s" % (err, gang.cpu().numpy()))
+    assert err <= 1e-6

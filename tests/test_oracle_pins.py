@@ -355,6 +355,37 @@ def test_unitary_norm_invariant_random_circuit():
     assert abs(norm - 1.0) < 1e-13
 
 
+# --------------------------------------------------------------------------- full-size route
+
+
+@pytest.mark.parametrize("eloc", [None, 0, 1, 2, 3, 4])
+@pytest.mark.parametrize("nq", [1, 2, 5, 9])
+def test_grover_sampled_matches_gate_by_gate_evaluation(nq, eloc):
+    """The closed-form route used at n_q = 30 (diffusion identity, H D H on the noisy
+    qubit, half sums) against the gate-by-gate oracle, which the Kronecker and
+    HALL2 pins above fix.  A wrong sign, a swapped D index or a wrong half sum in
+    any eloc branch fails here."""
+    rng = np.random.default_rng(700 + 10 * nq + (eloc if eloc is not None else 9))
+    for rep in range(3):
+        qhit = int(rng.integers(1, nq + 1))
+        noise = None if eloc is None else (qhit, eloc, *rng.uniform(0.1, 3.0, 2), float(rng.uniform(-1, 1)))
+        gates = O.grover_gates(noise)
+        marked = sorted({int(v) for v in rng.integers(0, 1 << nq, int(rng.integers(1, 4)))})
+        psi = _rand_state(rng, nq) * 1.3  # off the unit sphere on purpose
+        want, Lw, _ = O.evaluate(nq, gates, marked, psi)
+        idx = rng.permutation(1 << nq)
+        got, L = O.grover_sampled(nq, gates, marked, psi, idx)
+        np.testing.assert_allclose(got, want[idx], rtol=0, atol=1e-14)
+        assert abs(L - Lw) <= 1e-14 * max(1.0, Lw)
+
+
+def test_grover_sampled_rejects_other_circuits():
+    with pytest.raises(ValueError):
+        O.grover_sampled(3, [("HALL",)], [1], np.ones(8), [0])
+    with pytest.raises(ValueError):
+        O.grover_sampled(3, O.grover_gates() + [("D2", 1, 0.1, 0.2, 0.0)] * 2, [1], np.ones(8), [0])
+
+
 # --------------------------------------------------------------------------- generator
 
 

@@ -140,7 +140,7 @@ def cpu_baseline(W, nq_target, amp_sweeps_target):
             "sample_seconds": t}
 
 
-def batched_run(torch, pk, W, steps, warmup, prec):
+def batched_run(torch, pk, W, autotune, steps, warmup, prec):
     t0 = time.perf_counter()
     insts = W.batch_instances(W.SEEDS["batched"])
     log("generated %d batched instances in %.1fs" % (len(insts), time.perf_counter() - t0))
@@ -149,6 +149,12 @@ def batched_run(torch, pk, W, steps, warmup, prec):
     dt = torch.complex128 if prec == "fp64" else torch.complex64
     packed = torch.from_numpy(np.concatenate([i["psi"] for i in insts])).to(dt).to("cuda")
     out = torch.empty_like(packed)
+    t0 = time.perf_counter()
+    best, table = autotune.tune(plan, lambda: pk.evaluate_batched(plan, packed, out=out), op="batched")
+    default = [ms for c, ms in table if c["tile_bits"] == (13 if prec == "fp64" else 14)
+               and c["carrier_bits"] == 4 and c["reg_bits"] == 4]
+    log("batched %s: tuned over %d settings in %.1fs: %s (%.3f ms; default tile %.3f ms)"
+        % (prec, len(table), time.perf_counter() - t0, best, table[0][1], default[0] if default else float("nan")))
     for _ in range(warmup):
         pk.evaluate_batched(plan, packed, out=out)
     torch.cuda.synchronize()
@@ -177,7 +183,9 @@ def batched_run(torch, pk, W, steps, warmup, prec):
     return {"instances": len(insts), "amplitudes": total, "dtype": "f64" if prec == "fp64" else "f32",
             "ms_per_batch": ms_batched, "instances_per_s": len(insts) / (ms_batched * 1e-3),
             "ms_loop_of_singles": ms_loop, "speedup_vs_loop": ms_loop / ms_batched,
-            "compulsory_GBs": 2.0 * total * esz / (ms_batched * 1e-3) / 1e9}
+            "compulsory_GBs": 2.0 * total * esz / (ms_batched * 1e-3) / 1e9,
+            "tuned": best, "tuning_candidates": len(table),
+            "ms_default_tile": default[0] if default else None}
 
 
 def gradient_run(torch, pk, W, nq):
@@ -244,6 +252,7 @@ def main():
         sys.exit(2)
 
     import torch
+    from paper_0902_0699_amd import autotune
     from paper_0902_0699_amd import paperkern as pk
     from paper_0902_0699_amd import workload as W
 
@@ -308,7 +317,7 @@ def main():
         del r32, x64, y64
         torch.cuda.empty_cache()
     if args.extra:
-        line["batched"] = {p: batched_run(torch, pk, W, max(3, args.steps // 4), 1, p) for p in ("fp64", "fp32")}
+        line["batched"] = {p: batched_run(torch, pk, W, autotune, max(3, args.steps // 4), 1, p) for p in ("fp64", "fp32")}
         torch.cuda.empty_cache()
         line["gradient"] = gradient_run(torch, pk, W, nq)
     if not args.no_cpu_baseline:

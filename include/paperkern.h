@@ -100,17 +100,24 @@ int pk_create(const pk_problem* probs, int32_t n_inst, int32_t prec, pk_plan** o
  * threads of the smallest kernel idle), of which the carrier_bits lowest state
  * bits (0..6) are always part of a tile so that each memory run is
  * 2^carrier_bits contiguous amplitudes; fuse = 0 turns fusion off (one sweep per
- * gate, the plain form).  Re-compiles the schedule and drops captured graphs.
- * Defaults: the largest tile, 4 carriers, fusion on.  PK_EINVAL when out of range.
+ * gate, the plain form).  lane_order picks which other tile bits the lanes of
+ * a wave cover next to the carriers when a tile is read or written: 0 the
+ * lowest state bits, 1 (default) bits whose byte stride is below 4 KiB or at
+ * least 4 MiB first -- on MI355X a wave-wide load whose lane groups lie 4 KiB
+ * to 2 MiB apart streams up to a third slower.  Either order gives the same
+ * result.  Re-compiles the schedule and drops captured graphs.  Defaults:
+ * 2^13-amplitude tiles (FP64 and FP32), 4 carriers, fusion on, lane_order 1.
+ * PK_EINVAL when out of range.
  */
-int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_t fuse);
+int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_t fuse, int32_t lane_order);
 
 /*
  * pk_set_launch -- launch shape of the pass kernels: wgs_per_cu resident
  * workgroups per CU (1..8, or 0 for as many as the kernel's resources allow,
  * the default; more than fit only queue up), and reg_bits = 4 or 5 register
  * bits per thread in forward passes (16 or 32 amplitudes per thread, a
- * workgroup of 2^(tile_bits - reg_bits) threads; 0 keeps 4).  Backward passes
+ * workgroup of 2^(tile_bits - reg_bits) threads; 0 selects the default: 4 for
+ * FP64, 5 for FP32).  Backward passes
  * always use 4.  Changing reg_bits re-compiles the schedule.  Drops captured
  * graphs.  PK_EINVAL when out of range.
  */

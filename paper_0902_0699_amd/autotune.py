@@ -1,0 +1,128 @@
+"""Autotuner for the pass kernels' tile and launch parameters.
+
+The best tile for a workload depends on the memory system's response to the
+pass's access pattern and on the kernel's register and LDS footprint, which are
+measured, not modelled. ``tune`` therefore times every candidate setting of a
+plan on the caller's own buffers. A candidate is:
+
+* tile bits;
+* carrier bits;
+* the lane order of the IO stages;
+* register bits per thread;
+* resident workgroups per CU.
+
+Timing uses HIP events around a few graph replays. ``tune`` keeps the fastest
+setting, leaves it applied to the plan, and returns it with the table of
+timings.
+
+If ``PK_TUNE_CACHE`` names a JSON file, choices are remembered there. The key
+is the device name, the precision, the operation and a hash of the problem's
+structure (sizes, gate kinds and qubits). A later ``tune`` of the same workload
+then applies the cached choice without timing.
+"""
+
+import hashlib
+import itertools
+import json
+import os
+
+from . import paperkern as pk
+
+FIELDS = ("tile_bits", "carrier_bits", "lane_order", "reg_bits", "wgs_per_cu")
+
+
+def candidates(prec, op):
+    """Candidate settings for one precision (pk.PK_FP64 / pk.PK_FP32) and operation
+    ("eval" or "batched")."""
+    kmax = 13 if prec == pk.PK_FP64 else 14
+    tiles = [kmax, kmax - 1, kmax - 2]
+    if op == "batched":
+        tiles.append(kmax - 3)
+    out = []
+    for k, c, rb in itertools.product(tiles, (4, 5), (4, 5)):
+        if k - rb < 6:
+            continue
+        out.append({"tile_bits": k, "carrier_bits": c, "lane_order": 1, "reg_bits": rb, "wgs_per_cu": 0})
+    return out
+
+
+def apply(plan, cfg):
+    plan.set_tiling(cfg["tile_bits"], cfg["carrier_bits"], 1, cfg["lane_order"])
+    plan.set_launch(cfg["wgs_per_cu"], cfg["reg_bits"])
+
+
+def signature(plan, op):
+    """Hash of what the schedule depends on: precision, operation, and per instance
+    the size and the gate kinds with their qubits (not angles, operators or marks)."""
+    h = hashlib.sha256()
+    h.update(("%s|%s|" % (plan.prec, op)).encode())
+    for p in plan.problems:
+        h.update(("n%d:" % p["nq"]).encode())
+        for g in p["gates"]:
+            qubit = g[1] if g[0] in ("H", "ONEOP", "D2") else ""
+            h.update(("%s%s," % (g[0], qubit)).encode())
+        h.update(("m%d;" % len(p.get("marked", []))).encode())
+    return h.hexdigest()[:20]
+
+
+def _device_name(torch):
+    try:
+        return torch.cuda.get_device_name(0)
+    except Exception:  # pragma: no cover - name lookup is informational
+        return "unknown"
+
+
+def _load_cache(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _time(torch, run, reps, warmup):
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(plan, run, op="eval", reps=3, warmup=1, cands=None, use_cache=True):
+    """Times ``run()`` (one evaluation with ``plan``) under every candidate setting;
+    applies and returns (best setting, [(setting, ms), ...]) sorted by time."""
+    import torch
+
+    key = "%s|%s" % (_device_name(torch), signature(plan, op))
+    path = os.environ.get("PK_TUNE_CACHE")
+    if use_cache and path:
+        hit = _load_cache(path).get(key)
+        if hit:
+            apply(plan, hit["best"])
+            return hit["best"], [(c, ms) for c, ms in hit["table"]]
+    table = []
+    for cfg in (cands if cands is not None else candidates(plan.prec, op)):
+        try:
+            apply(plan, cfg)
+        except pk.PaperkernError:
+            continue
+        table.append((dict(cfg), _time(torch, run, reps, warmup)))
+    if not table:
+        raise pk.PaperkernError(pk.PK_EINVAL, "no candidate setting was accepted")
+    table.sort(key=lambda t: t[1])
+    best = table[0][0]
+    apply(plan, best)
+    if path:
+        cache = _load_cache(path)
+        cache[key] = {"best": best, "table": table}
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1)
+        os.replace(tmp, path)
+    return best, table

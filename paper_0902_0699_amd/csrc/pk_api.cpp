@@ -331,7 +331,7 @@ int pk_create(const pk_problem* probs, int32_t n_inst, int32_t prec, pk_plan** o
     return PK_OK;
 }
 
-int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_t fuse) {
+int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_t fuse, int32_t lane_order) {
     if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");
     DevPlan* d = dp(plan);
     const int kmax = d->host.prec == PK_FP64 ? 13 : 14;
@@ -339,7 +339,9 @@ int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_
     if (carrier_bits < 0 || carrier_bits > 6 || carrier_bits > tile_bits - 1)
         return fail(d, PK_EINVAL, "carrier_bits out of range");
     if (fuse != 0 && fuse != 1) return fail(d, PK_EINVAL, "fuse must be 0 or 1");
-    d->host.tiling = Tiling{tile_bits, carrier_bits, fuse, d->host.tiling.wgs_per_cu, d->host.tiling.reg_bits};
+    if (lane_order != 0 && lane_order != 1) return fail(d, PK_EINVAL, "lane_order must be 0 or 1");
+    d->host.tiling = Tiling{tile_bits, carrier_bits, fuse, d->host.tiling.wgs_per_cu, d->host.tiling.reg_bits,
+                            lane_order};
     drop_device(d);
     std::string err;
     try {
@@ -356,7 +358,7 @@ int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu, int32_t reg_bits) {
     DevPlan* d = dp(plan);
     if (wgs_per_cu < 0 || wgs_per_cu > 8) return fail(d, PK_EINVAL, "wgs_per_cu must be 0..8");
     if (reg_bits != 0 && reg_bits != 4 && reg_bits != 5) return fail(d, PK_EINVAL, "reg_bits must be 0, 4 or 5");
-    const int rb = reg_bits == 0 ? 4 : reg_bits;
+    const int rb = reg_bits == 0 ? default_reg_bits(d->host.prec) : reg_bits;
     const bool recompile_needed = rb != d->host.tiling.reg_bits;
     d->host.tiling.wgs_per_cu = wgs_per_cu;
     d->host.tiling.reg_bits = rb;

@@ -56,7 +56,16 @@ struct Tiling {
     int fuse;
     int wgs_per_cu = 0;  // resident workgroups per CU for pass launches (0 = occupancy limit)
     int reg_bits = 4;    // register bits per thread in forward passes (4 or 5)
+    int lane_order = 1;  // 1: lanes cover tile bits of good DRAM stride next to the carriers
 };
+
+// Default tile and register bits per precision, the fastest settings measured
+// for the n_q = 30 Grover iteration: FP64 tiles of 2^13 amplitudes with 16 per
+// thread (2^9 threads); FP32 tiles of 2^13 with 32 per thread (2^8 threads) -- the
+// 2^14 FP32 tile with 16 per thread needs 1024 threads, whose 128-register cap
+// spills the register tile.
+inline int default_tile_bits(int /*prec*/) { return 13; }
+inline int default_reg_bits(int prec) { return prec == PK_FP64 ? 4 : 5; }
 
 struct Plan {
     uint32_t magic = 0x504b504cu;

@@ -40,7 +40,7 @@ class PkProblem(ctypes.Structure):
 
 SIGNATURES = {
     "pk_create": (ctypes.c_int, [ctypes.POINTER(PkProblem), _c_int32, _c_int32, ctypes.POINTER(_vp)]),
-    "pk_set_tiling": (ctypes.c_int, [_vp, _c_int32, _c_int32, _c_int32]),
+    "pk_set_tiling": (ctypes.c_int, [_vp, _c_int32, _c_int32, _c_int32, _c_int32]),
     "pk_set_launch": (ctypes.c_int, [_vp, _c_int32, _c_int32]),
     "pk_plan_passes": (ctypes.c_int, [_vp, _c_int32, ctypes.POINTER(_c_int32)]),
     "pk_plan_describe": (ctypes.c_int, [_vp, ctypes.c_char_p, _c_int64, ctypes.POINTER(_c_int64)]),
@@ -150,8 +150,8 @@ class Plan:
     def n_inst(self):
         return len(self.problems)
 
-    def set_tiling(self, tile_bits, carrier_bits=4, fuse=1):
-        _check(lib().pk_set_tiling(self.handle, tile_bits, carrier_bits, fuse), self.handle)
+    def set_tiling(self, tile_bits, carrier_bits=4, fuse=1, lane_order=1):
+        _check(lib().pk_set_tiling(self.handle, tile_bits, carrier_bits, fuse, lane_order), self.handle)
         self._ws = {}
 
     def set_launch(self, wgs_per_cu=0, reg_bits=0):

@@ -67,7 +67,7 @@ def check_stage_shapes(nq, p):
         for op in st["ops"]:
             if op["kind"] in ("H", "MAT", "D2BWD"):
                 assert 0 <= op["a"] < len(rb)
-    assert sorted(p["tile_bits"]) == p["tile_bits"] and len(p["tile_bits"]) == k
+    assert len(set(p["tile_bits"])) == len(p["tile_bits"]) == k
     assert all(0 <= b < nq for b in p["tile_bits"])
 
 

@@ -135,6 +135,18 @@ def test_tilings_fp64(tiling, launch):
     assert _relerr(got, want) <= TOL64 and abs(L - Lw) <= TOL64
 
 
+@pytest.mark.parametrize("lane_order", [0, 1])
+def test_lane_orders_fp64(lane_order):
+    """n_q = 20 tiles mix state bits 8..17 with bits >= 18, so the two lane orders
+    lay the tiles out differently in registers and LDS; both match the oracle."""
+    inst = W.single_instance(W.SEEDS["small_fp64"], W.NQ_SMALL)
+    prob = {"nq": inst["nq"], "gates": inst["gates"], "marked": inst["marked"]}
+    _say("lane_order %d at n_q=%d" % (lane_order, inst["nq"]))
+    _, got, L, _ = _run(prob, inst["psi"], tiling=(13, 4, 1, lane_order))
+    want, Lw, _ = O.evaluate(inst["nq"], prob["gates"], prob["marked"], inst["psi"])
+    assert _relerr(got, want) <= TOL64 and abs(L - Lw) <= TOL64
+
+
 def test_sign_operations_bit_exact():
     """Oracle and Inv alone only change signs: exact equality, any size and tiling."""
     rng = np.random.default_rng(5)
@@ -283,6 +295,30 @@ def test_backward_against_oracle_adjoint(nq, eloc):
     wpsi, wang = O.adjoint_grad(nq, gates, marked, psi, 0.75)
     assert _relerr(gpsi.cpu().numpy(), wpsi) <= 1e-10
     np.testing.assert_allclose(gang.cpu().numpy(), wang.reshape(-1), rtol=1e-10, atol=1e-13)
+
+
+def test_autotuned_batched_plan_matches_oracle():
+    """The tuner times every candidate on the caller's buffers and leaves the fastest
+    applied; the tuned plan still matches the oracle instance by instance."""
+    pk = _pk()
+    from paper_0902_0699_amd import autotune as AT
+    insts = W.batch_instances(W.SEEDS["batched"], count=48, nq_min=6, span=10)
+    probs = [{"nq": i["nq"], "gates": i["gates"], "marked": i["marked"]} for i in insts]
+    plan = pk.Plan(probs)
+    packed = _dev(np.concatenate([i["psi"] for i in insts]))
+    out = torch.empty_like(packed)
+    _say("autotune batched 48 instances")
+    best, table = AT.tune(plan, lambda: pk.evaluate_batched(plan, packed, out=out), op="batched",
+                          reps=2, use_cache=False)
+    assert best == table[0][0] and all(table[i][1] <= table[i + 1][1] for i in range(len(table) - 1))
+    res, L, _ = pk.evaluate_batched(plan, packed)
+    torch.cuda.synchronize()
+    res = res.cpu().numpy()
+    offs = plan.offsets()
+    for k, (p, inst) in enumerate(zip(probs, insts)):
+        want, Lw, _ = O.evaluate(p["nq"], p["gates"], p["marked"], inst["psi"])
+        assert _relerr(res[offs[k]:offs[k + 1]], want) <= TOL64
+        assert abs(float(L[k]) - Lw) <= TOL64
 
 
 def test_backward_rejects_non_unitary_oneop():

@@ -74,6 +74,8 @@ def test_fp32_allows_31_qubits_and_tiling_limits():
         plan64.set_tiling(10, carrier_bits=7)
     with pytest.raises(pk.PaperkernError):
         plan64.set_tiling(10, fuse=2)
+    with pytest.raises(pk.PaperkernError):
+        plan64.set_tiling(10, lane_order=2)
 
 
 def test_offsets_and_angles_bookkeeping():
@@ -100,6 +102,52 @@ def test_pass_counts_at_thirty_qubits():
     assert sum(stages) <= 13  # five register bits: fewer LDS exchanges than with four
     plan.set_tiling(13, 4, fuse=0)
     assert plan.passes() == 61  # one sweep per one-qubit gate (2 HALL x 30 + D2)
+
+
+@pytest.mark.parametrize("lane_order", [0, 1])
+def test_lane_order_relabels_tile_bits_only(lane_order):
+    """With lane_order 1 a tile that mixes state bits 8..17 with bits >= 18 lists the
+    latter first after the carriers; either order computes the oracle's state."""
+    nq = 20
+    inst = W.single_instance(0, nq)
+    prob = {"nq": nq, "gates": inst["gates"], "marked": inst["marked"]}
+    plan = pk.Plan(prob)
+    plan.set_tiling(13, 4, 1, lane_order)
+    desc = plan.describe()
+    tbs = [p["tile_bits"] for p in desc["instances"][0]["forward"]]
+    mixed = [tb for tb in tbs if any(8 <= b < 18 for b in tb) and any(b >= 18 for b in tb)]
+    assert mixed
+    for tb in mixed:
+        assert tb[:4] == [0, 1, 2, 3]
+        rest = tb[4:]
+        if lane_order == 0:
+            assert rest == sorted(rest)
+        else:
+            good = [b for b in rest if b < 8 or b >= 18]
+            assert rest[:len(good)] == sorted(good) and rest != sorted(rest)
+    got, L = run_forward([prob], desc, 0, inst["psi"])
+    want, Lw, _ = O.evaluate(nq, prob["gates"], prob["marked"], inst["psi"])
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
+    assert abs(L - Lw) < 1e-13
+
+
+def test_autotune_candidates_are_accepted_and_signature_is_structural():
+    from paper_0902_0699_amd import autotune as AT
+    insts = W.batch_instances(3, count=12)
+    probs = [{"nq": i["nq"], "gates": i["gates"], "marked": i["marked"]} for i in insts]
+    for prec in ("fp64", "fp32"):
+        plan = pk.Plan(probs, prec=prec)
+        cands = AT.candidates(plan.prec, "batched")
+        assert len(cands) >= 8 and all(set(c) == set(AT.FIELDS) for c in cands)
+        for c in cands:
+            AT.apply(plan, c)  # host-side recompile; raises if a candidate were invalid
+        assert plan.passes() >= 1
+    # same structure, other angles and marks: same key; other qubit: other key
+    a = [{"nq": 12, "gates": W.grover_gates((3, 2, 0.1, 0.2, 0.0)), "marked": [5]}]
+    b = [{"nq": 12, "gates": W.grover_gates((3, 2, 1.1, 2.2, 0.0)), "marked": [77]}]
+    c = [{"nq": 12, "gates": W.grover_gates((4, 2, 0.1, 0.2, 0.0)), "marked": [5]}]
+    sig = lambda pr: AT.signature(pk.Plan(pr), "eval")
+    assert sig(a) == sig(b) != sig(c)
 
 
 def test_pair_indices_rejects_bad_ranges():

@@ -151,8 +151,8 @@ def batched_run(torch, pk, W, autotune, steps, warmup, prec):
     out = torch.empty_like(packed)
     t0 = time.perf_counter()
     best, table = autotune.tune(plan, lambda: pk.evaluate_batched(plan, packed, out=out), op="batched")
-    default = [ms for c, ms in table if c["tile_bits"] == (13 if prec == "fp64" else 14)
-               and c["carrier_bits"] == 4 and c["reg_bits"] == 4]
+    default = [ms for c, ms in table if c["tile_bits"] == 13 and c["carrier_bits"] == 4
+               and c["reg_bits"] == (4 if prec == "fp64" else 5) and c["min_team_tiles"] == 64]
     log("batched %s: tuned over %d settings in %.1fs: %s (%.3f ms; default tile %.3f ms)"
         % (prec, len(table), time.perf_counter() - t0, best, table[0][1], default[0] if default else float("nan")))
     for _ in range(warmup):

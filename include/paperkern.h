@@ -123,6 +123,31 @@ int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_
  */
 int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu, int32_t reg_bits);
 
+/*
+ * pk_set_batch -- shape of pk_evaluate_batched's persistent launch (Sec. 6.2:
+ * independent multiverses).  Workgroups that share an XCD, and so an L2, form
+ * teams of team_size; each team runs the passes of its large instances
+ * together, with a device-scope barrier between passes, so that an instance
+ * too large for one workgroup is spread over many CUs.  An instance is large
+ * when its first pass has at least min_team_tiles * team_size tiles.  Every
+ * other instance is taken whole by one workgroup from a queue, largest first.
+ * team_size 0 turns teams off.  Defaults 16 and 64 (instances of 2^22 or more
+ * amplitudes at the default tile: below that a single workgroup's sweep costs
+ * less than the barriers' device-scope fences).  A team barrier that has not completed within about half a
+ * second (the launch's workgroups are not all resident, e.g. the GPU is shared)
+ * gives up: that instance's L_out and norm_out entries are NaN.  Drops the
+ * plan's device tables and graphs.  PK_EINVAL when out of range (team_size
+ * 0..64, min_team_tiles 1..4096).
+ */
+int pk_set_batch(pk_plan* plan, int32_t team_size, int32_t min_team_tiles);
+
+/*
+ * pk_batch_teams -- the team split pk_evaluate_batched uses on the current
+ * device: number of teams and of instances run by teams.  Uploads the plan's
+ * tables to the current device if needed (no kernel runs).
+ */
+int pk_batch_teams(pk_plan* plan, int32_t* n_teams, int32_t* n_team_instances);
+
 /* Number of passes (full sweeps over the state) one evaluation of instance `inst` makes. */
 int pk_plan_passes(const pk_plan* plan, int32_t inst, int32_t* passes);
 

@@ -9,7 +9,8 @@ plan on the caller's own buffers. A candidate is:
 * carrier bits;
 * the lane order of the IO stages;
 * register bits per thread;
-* resident workgroups per CU.
+* resident workgroups per CU;
+* the team size and threshold of the batched launch.
 
 Timing uses HIP events around a few graph replays. ``tune`` keeps the fastest
 setting, leaves it applied to the plan, and returns it with the table of
@@ -28,7 +29,7 @@ import os
 
 from . import paperkern as pk
 
-FIELDS = ("tile_bits", "carrier_bits", "lane_order", "reg_bits", "wgs_per_cu")
+FIELDS = ("tile_bits", "carrier_bits", "lane_order", "reg_bits", "wgs_per_cu", "team_size", "min_team_tiles")
 
 
 def candidates(prec, op):
@@ -38,17 +39,20 @@ def candidates(prec, op):
     tiles = [kmax, kmax - 1, kmax - 2]
     if op == "batched":
         tiles.append(kmax - 3)
+    teams = ((16, 64), (16, 8)) if op == "batched" else ((16, 64),)
     out = []
-    for k, c, rb in itertools.product(tiles, (4, 5), (4, 5)):
+    for k, c, rb, (ts, mt) in itertools.product(tiles, (4, 5), (4, 5), teams):
         if k - rb < 6:
             continue
-        out.append({"tile_bits": k, "carrier_bits": c, "lane_order": 1, "reg_bits": rb, "wgs_per_cu": 0})
+        out.append({"tile_bits": k, "carrier_bits": c, "lane_order": 1, "reg_bits": rb, "wgs_per_cu": 0,
+                    "team_size": ts, "min_team_tiles": mt})
     return out
 
 
 def apply(plan, cfg):
     plan.set_tiling(cfg["tile_bits"], cfg["carrier_bits"], 1, cfg["lane_order"])
     plan.set_launch(cfg["wgs_per_cu"], cfg["reg_bits"])
+    plan.set_batch(cfg.get("team_size", 16), cfg.get("min_team_tiles", 64))
 
 
 def signature(plan, op):

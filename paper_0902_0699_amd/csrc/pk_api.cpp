@@ -25,7 +25,20 @@ struct DevPlan {
     const void* key[G_SLOTS][8] = {};
     hipStream_t cap = nullptr;
     int n_cu = 0;
+    unsigned batch_grid = 0;  // persistent grid of the batched launch
+    uint64_t spin_ticks = 0;  // half a second of the device wall clock
 };
+
+// MI355X has 8 XCDs and dispatches workgroups round-robin over them; the count
+// only shapes the batched teams (which workgroups share an L2), not results.
+constexpr int kXcds = 8;
+
+int batched_kmax(const Plan& P) {
+    int km = P.inst[0].fwd[0].rbits + 6;
+    for (const auto& in : P.inst)
+        for (const auto& hp : in.fwd) km = hp.kmax > km ? hp.kmax : km;
+    return km;
+}
 
 DevPlan* dp(pk_plan* p) { return reinterpret_cast<DevPlan*>(p); }
 const DevPlan* dp(const pk_plan* p) { return reinterpret_cast<const DevPlan*>(p); }
@@ -75,6 +88,20 @@ int ensure_device(DevPlan* d) {
         if (dev != P.device) return fail(d, PK_EINVAL, "plan was first used on another device");
         return PK_OK;
     }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) d->n_cu = prop.multiProcessorCount;
+    if (d->n_cu <= 0) d->n_cu = 256;
+    int wall_khz = 0;
+    if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || wall_khz <= 0)
+        wall_khz = 100000;
+    d->spin_ticks = (uint64_t)wall_khz * 500;  // 0.5 s
+    // batched launch: as many workgroups as are resident at once, in teams
+    int per_cu = batched_blocks_per_cu(batched_kmax(P), P.inst[0].fwd[0].rbits, P.prec == PK_FP64);
+    if (per_cu < 1) per_cu = 1;
+    if (per_cu > 8) per_cu = 8;
+    d->batch_grid = (unsigned)(d->n_cu * per_cu);
+    P.team = team_schedule(&P, d->batch_grid, d->n_cu % kXcds == 0 ? kXcds : 1);
+
     TableLayout t = table_layout(&P);
     std::vector<char> buf(t.total, 0);
     put(buf, t.passes, P.passes);
@@ -84,7 +111,9 @@ int ensure_device(DevPlan* d) {
     put(buf, t.mats, P.static_mats);
     put(buf, t.mats + P.static_mats.size() * sizeof(double), P.default_angles);
     put(buf, t.idesc, P.idesc);
-    put(buf, t.order, P.order);
+    put(buf, t.order, P.team.solo);
+    put(buf, t.team_off, P.team.team_off);
+    put(buf, t.team_list, P.team.team_list);
     std::vector<Reduction> r = eval_reductions(&P);
     std::vector<Reduction> rb = backward_reductions(&P);
     r.insert(r.end(), rb.begin(), rb.end());
@@ -104,9 +133,6 @@ int ensure_device(DevPlan* d) {
         e = hipStreamCreateWithFlags(&d->cap, hipStreamNonBlocking);
         if (e != hipSuccess) return hip_fail(d, e, "hipStreamCreate");
     }
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) d->n_cu = prop.multiProcessorCount;
-    if (d->n_cu <= 0) d->n_cu = 256;
     return PK_OK;
 }
 
@@ -182,16 +208,10 @@ hipError_t enqueue_eval(DevPlan* d, const EvalArgs& a, hipStream_t st, std::vect
                          a.L_out, a.norm_out, nullptr, st);
 }
 
-int batched_kmax(const Plan& P) {
-    int km = P.inst[0].fwd[0].rbits + 6;
-    for (const auto& in : P.inst)
-        for (const auto& hp : in.fwd) km = hp.kmax > km ? hp.kmax : km;
-    return km;
-}
-
 hipError_t enqueue_batched(DevPlan* d, const EvalArgs& a, hipStream_t st) {
     Plan& P = d->host;
-    hipError_t e = enqueue_prep(d, a.ws, a.angles, PK_OP_EVAL, 1, st);
+    const TeamSchedule& ts = P.team;
+    hipError_t e = enqueue_prep(d, a.ws, a.angles, PK_OP_EVAL, 2 + ts.n_teams, st);
     if (e != hipSuccess) return e;
     PassLaunch L = base_launch(d, a.ws, PK_OP_EVAL);
     L.src0 = a.psi_in;
@@ -202,22 +222,21 @@ hipError_t enqueue_batched(DevPlan* d, const EvalArgs& a, hipStream_t st) {
     L.rbits = P.inst[0].fwd[0].rbits;
     TableLayout t = table_layout(&P);
     WsLayout w = workspace_layout(&P, PK_OP_EVAL);
-    BatchLaunch B{};
+    BatchArgs B{};
     B.idesc = at<InstDesc>(P.d_tables, t.idesc);
     B.order = at<int32_t>(P.d_tables, t.order);
-    B.n_inst = (int32_t)P.inst.size();
+    B.team_off = at<int32_t>(P.d_tables, t.team_off);
+    B.team_list = at<int32_t>(P.d_tables, t.team_list);
     B.queue = at<unsigned int>(a.ws, w.counters);
+    B.bars = at<unsigned int>(a.ws, w.counters) + 2;
     B.L_out = a.L_out;
     B.norm_out = a.norm_out;
-    const bool fp64 = P.prec == PK_FP64;
-    const int lds_per_wg = (1 << L.kmax) * (fp64 ? 16 : 8);
-    int per_cu = (160 * 1024) / lds_per_wg;
-    if (per_cu < 1) per_cu = 1;
-    if (per_cu > 8) per_cu = 8;
-    long grid = (long)d->n_cu * per_cu;
-    if (grid > (long)P.inst.size()) grid = (long)P.inst.size();
-    B.grid = (unsigned)grid;
-    return launch_batched(L, B, st);
+    B.n_solo = (int32_t)ts.solo.size();
+    B.n_teams = ts.n_teams;
+    B.team_size = ts.team_size;
+    B.n_xcd = ts.n_xcd;
+    B.spin_ticks = d->spin_ticks;
+    return launch_batched(L, B, d->batch_grid, st);
 }
 
 struct BwdArgs {
@@ -374,6 +393,26 @@ int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu, int32_t reg_bits) {
     } else {
         drop_graphs(d);
     }
+    return PK_OK;
+}
+
+int pk_set_batch(pk_plan* plan, int32_t team_size, int32_t min_team_tiles) {
+    if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");
+    DevPlan* d = dp(plan);
+    if (team_size < 0 || team_size > 64) return fail(d, PK_EINVAL, "team_size must be 0..64");
+    if (min_team_tiles < 1 || min_team_tiles > 4096) return fail(d, PK_EINVAL, "min_team_tiles must be 1..4096");
+    d->host.batch = BatchConfig{team_size, min_team_tiles};
+    drop_device(d);  // the team schedule is part of the device tables
+    return PK_OK;
+}
+
+int pk_batch_teams(pk_plan* plan, int32_t* n_teams, int32_t* n_team_instances) {
+    if (!valid(plan) || !n_teams || !n_team_instances) return fail(nullptr, PK_EINVAL, "invalid argument");
+    DevPlan* d = dp(plan);
+    const int rc = ensure_device(d);
+    if (rc != PK_OK) return rc;
+    *n_teams = d->host.team.n_teams;
+    *n_team_instances = (int32_t)d->host.team.team_list.size();
     return PK_OK;
 }
 

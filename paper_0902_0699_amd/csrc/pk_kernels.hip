@@ -13,6 +13,8 @@
 // contiguous runs.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "pk_desc.h"
 #include "pk_launch.h"
 
@@ -511,17 +513,16 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
     }
 }
 
-// Tiles first, first + stride, ... of one pass.  With one vector, two register
+// Tiles first, first + stride, ... (below ntiles) of one pass.  With one vector, two register
 // buffers alternate: the next tile's HBM loads are issued before the current
 // tile's LDS stages, so memory traffic overlaps the exchange work of the one
 // workgroup an LDS-sized tile leaves per CU.  The prefetch is unconditional
 // (past the end it re-reads the current tile) so the wait counts stay static.
 template <typename R, int NV, int KMAX, int RB>
 __device__ __forceinline__ void run_tiles(const KArgs& a, const PK_CONST Pass* P, int64_t first,
-                                          int64_t stride, typename Cplx<R>::T* lds, double* red) {
+                                          int64_t stride, int64_t ntiles, typename Cplx<R>::T* lds, double* red) {
     using T = typename Cplx<R>::T;
     constexpr int NR = 1 << RB;
-    const int64_t ntiles = P->ntiles;
     if (first >= ntiles) return;
     const PassCtx C = make_ctx<(int)sizeof(R) * 2, RB>(a, P);
     const int64_t off = P->state_off;
@@ -567,48 +568,115 @@ __global__ void __launch_bounds__(1 << (KMAX - RB)) pass_kernel(KArgs a) {
     using T = typename Cplx<R>::T;
     __shared__ T lds[1 << KMAX];
     __shared__ double red[16];
-    run_tiles<R, NV, KMAX, RB>(a, cptr(a.passes) + a.pass, blockIdx.x, gridDim.x, lds, red);
+    const PK_CONST Pass* P = cptr(a.passes) + a.pass;
+    run_tiles<R, NV, KMAX, RB>(a, P, blockIdx.x, gridDim.x, P->ntiles, lds, red);
 }
 
-// Multiverse batch: each workgroup takes whole instances from a queue (largest
-// first) and runs all their passes itself, then writes L and the norm.
+// Team barrier of the batched launch: every member adds one to the team's
+// counter after its tiles, then waits until all team_size members of this
+// round have.  Device-scope fences on both sides make the members' stores
+// visible across CUs and XCDs.  The wait is bounded by `ticks` of the
+// constant-rate wall clock: on time-out (the team's workgroups are not all
+// resident) the barrier returns false, and a workgroup whose barrier failed
+// once no longer waits at later ones, so every wave reaches the kernel's end.
+__device__ __forceinline__ bool team_barrier(unsigned int* bar, unsigned int target, uint64_t ticks, bool broken,
+                                             int* flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(bar, 1u);
+        int ok = 0;
+        if (!broken) {
+            const uint64_t t0 = wall_clock64();
+            for (;;) {
+                if (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) {
+                    ok = 1;
+                    break;
+                }
+                if (wall_clock64() - t0 > ticks) break;
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __threadfence();
+        *flag = ok;
+    }
+    __syncthreads();
+    return *flag != 0;
+}
+
+// L and the norm of one finished instance, written by one workgroup.
+template <int NT>
+__device__ __forceinline__ void finish_instance(const KArgs& a, const PK_CONST InstDesc* D, int inst, bool ok,
+                                                double* L_out, double* norm_out, double* red) {
+    if (threadIdx.x == 0) {
+        double L = 0.0;
+        for (int m = 0; m < D->nmarked; ++m) L += a.reads[D->read_base + m];
+        L_out[inst] = ok ? L : __builtin_nan("");
+    }
+    if (norm_out) {
+        double s = 0.0;
+        const int64_t nt = D->ntiles_last, pb = D->part_base;
+        for (int64_t t = threadIdx.x; t < nt; t += NT) s += a.partials[pb + t];
+        const double tot = block_sum<NT>(s, red);
+        if (threadIdx.x == 0) norm_out[inst] = ok ? tot : __builtin_nan("");
+    }
+    __syncthreads();
+}
+
+// Multiverse batch in one persistent launch.  First the teams: the j-th
+// workgroup of XCD x (w = j * n_xcd + x) is member j mod team_size of team
+// (j / team_size) * n_xcd + x; a team walks the passes of its large instances
+// together, its members taking the tiles of each pass in turn, with a team
+// barrier between passes.  Then every workgroup takes whole instances from the
+// queue (largest first) and runs all their passes itself.
 template <typename R, int KMAX, int RB>
-__global__ void __launch_bounds__(1 << (KMAX - RB))
-    batched_kernel(KArgs a, const InstDesc* idesc, const int32_t* order, int32_t n_inst, unsigned int* queue,
-                   double* L_out, double* norm_out) {
+__global__ void __launch_bounds__(1 << (KMAX - RB)) batched_kernel(KArgs a, BatchArgs b) {
     using T = typename Cplx<R>::T;
     constexpr int NT = 1 << (KMAX - RB);
     __shared__ T lds[1 << KMAX];
     __shared__ double red[16];
     __shared__ int item;
+    __shared__ int flag;
+    const PK_CONST InstDesc* idesc = cptr(b.idesc);
+    const int w = blockIdx.x;
+    const int xcd = w % b.n_xcd, j = w / b.n_xcd;
+    const int team = b.team_size > 0 ? (j / b.team_size) * b.n_xcd + xcd : b.n_teams;
+    if (team < b.n_teams) {
+        const int member = j % b.team_size;
+        unsigned int target = 0;
+        bool broken = false;
+        const int q0 = cptr(b.team_off)[team], q1 = cptr(b.team_off)[team + 1];
+        for (int q = q0; q < q1; ++q) {
+            const int inst = cptr(b.team_list)[q];
+            const PK_CONST InstDesc* D = idesc + inst;
+            bool ok = true;
+            for (int p = 0; p < D->npass; ++p) {
+                const PK_CONST Pass* P = cptr(a.passes) + D->first_pass + p;
+                run_tiles<R, 1, KMAX, RB>(a, P, member, b.team_size, P->ntiles, lds, red);
+                target += (unsigned int)b.team_size;
+                const bool passed = team_barrier(b.bars + team, target, b.spin_ticks, broken, &flag);
+                broken = broken || !passed;
+                ok = ok && passed;
+            }
+            if (member == 0) finish_instance<NT>(a, D, inst, ok, b.L_out, b.norm_out, red);
+        }
+    }
     for (;;) {
-        if (threadIdx.x == 0) item = (int)atomicAdd(queue, 1u);
+        if (threadIdx.x == 0) item = (int)atomicAdd(b.queue, 1u);
         __syncthreads();
         const int it = item;
         __syncthreads();
-        if (it >= n_inst) break;
-        const int inst = cptr(order)[it];
-        const PK_CONST InstDesc* D = cptr(idesc) + inst;
-        const int npass = D->npass;
-        for (int p = 0; p < npass; ++p) {
-            run_tiles<R, 1, KMAX, RB>(a, cptr(a.passes) + D->first_pass + p, 0, 1, lds, red);
+        if (it >= b.n_solo) break;
+        const int inst = cptr(b.order)[it];
+        const PK_CONST InstDesc* D = idesc + inst;
+        for (int p = 0; p < D->npass; ++p) {
+            const PK_CONST Pass* P = cptr(a.passes) + D->first_pass + p;
+            run_tiles<R, 1, KMAX, RB>(a, P, 0, 1, P->ntiles, lds, red);
             // this workgroup's stores must be visible to its own loads of the next pass
             __threadfence_block();
             __syncthreads();
         }
-        if (threadIdx.x == 0) {
-            double L = 0.0;
-            for (int m = 0; m < D->nmarked; ++m) L += a.reads[D->read_base + m];
-            L_out[inst] = L;
-        }
-        if (norm_out) {
-            double s = 0.0;
-            const int64_t nt = D->ntiles_last, pb = D->part_base;
-            for (int64_t t = threadIdx.x; t < nt; t += NT) s += a.partials[pb + t];
-            const double tot = block_sum<NT>(s, red);
-            if (threadIdx.x == 0) norm_out[inst] = tot;
-        }
-        __syncthreads();
+        finish_instance<NT>(a, D, inst, true, b.L_out, b.norm_out, red);
     }
 }
 
@@ -761,37 +829,68 @@ hipError_t launch_pass(const PassLaunch& L, hipStream_t st) {
 }
 
 template <typename R, int KMAX, int RB>
-static hipError_t launch_batched_t(const KArgs& a, const BatchLaunch& B, hipStream_t st) {
-    hipLaunchKernelGGL((batched_kernel<R, KMAX, RB>), dim3(B.grid), dim3(1 << (KMAX - RB)), 0, st, a, B.idesc,
-                       B.order, B.n_inst, B.queue, B.L_out, B.norm_out);
+static hipError_t launch_batched_t(const KArgs& a, const BatchArgs& B, unsigned grid, hipStream_t st) {
+    hipLaunchKernelGGL((batched_kernel<R, KMAX, RB>), dim3(grid), dim3(1 << (KMAX - RB)), 0, st, a, B);
     return hipGetLastError();
 }
 
-template <typename R, int RB>
-static hipError_t launch_batched_r(int kmax, const KArgs& a, const BatchLaunch& B, hipStream_t st) {
-    switch (kmax) {
-    case 10:
-        if constexpr (RB == 4) return launch_batched_t<R, 10, 4>(a, B, st);
-        return hipErrorInvalidValue;
-    case 11: return launch_batched_t<R, 11, RB>(a, B, st);
-    case 12: return launch_batched_t<R, 12, RB>(a, B, st);
-    case 13: return launch_batched_t<R, 13, RB>(a, B, st);
-    case 14:
-        if constexpr (sizeof(R) == 4) return launch_batched_t<R, 14, RB>(a, B, st);
-        return hipErrorInvalidValue;
-    default: return hipErrorInvalidValue;
-    }
+template <typename R, int KMAX, int RB>
+static int batched_occupancy_t() {
+    int per_cu = 0;
+    auto kfn = batched_kernel<R, KMAX, RB>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, 1 << (KMAX - RB), 0) != hipSuccess) return 0;
+    return per_cu;
 }
 
-hipError_t launch_batched(const PassLaunch& L, const BatchLaunch& B, hipStream_t st) {
+// Kernel instances of the batched launch: KMAX 10..13 (14 for FP32), RB 4 or 5.
+template <typename R, int RB, typename F>
+static auto batched_instance(int kmax, F&& f) {
+    switch (kmax) {
+    case 10:
+        if constexpr (RB == 4) return f(std::integral_constant<int, 10>{});
+        break;
+    case 11: return f(std::integral_constant<int, 11>{});
+    case 12: return f(std::integral_constant<int, 12>{});
+    case 13: return f(std::integral_constant<int, 13>{});
+    case 14:
+        if constexpr (sizeof(R) == 4) return f(std::integral_constant<int, 14>{});
+        break;
+    default: break;
+    }
+    return decltype(f(std::integral_constant<int, 13>{})){};
+}
+
+template <typename R, int RB>
+static hipError_t launch_batched_r(int kmax, const KArgs& a, const BatchArgs& B, unsigned grid, hipStream_t st) {
+    bool found = false;
+    hipError_t e = batched_instance<R, RB>(kmax, [&](auto K) {
+        found = true;
+        return launch_batched_t<R, decltype(K)::value, RB>(a, B, grid, st);
+    });
+    return found ? e : hipErrorInvalidValue;
+}
+
+hipError_t launch_batched(const PassLaunch& L, const BatchArgs& B, unsigned grid, hipStream_t st) {
     KArgs a = kargs(L);
     a.dst1 = nullptr;
     a.gpart = nullptr;
     a.dL = nullptr;
     a.pass = 0;
     if (L.rbits == 5)
-        return L.fp64 ? launch_batched_r<double, 5>(L.kmax, a, B, st) : launch_batched_r<float, 5>(L.kmax, a, B, st);
-    return L.fp64 ? launch_batched_r<double, 4>(L.kmax, a, B, st) : launch_batched_r<float, 4>(L.kmax, a, B, st);
+        return L.fp64 ? launch_batched_r<double, 5>(L.kmax, a, B, grid, st)
+                      : launch_batched_r<float, 5>(L.kmax, a, B, grid, st);
+    return L.fp64 ? launch_batched_r<double, 4>(L.kmax, a, B, grid, st)
+                  : launch_batched_r<float, 4>(L.kmax, a, B, grid, st);
+}
+
+template <typename R, int RB>
+static int batched_occupancy_r(int kmax) {
+    return batched_instance<R, RB>(kmax, [&](auto K) { return batched_occupancy_t<R, decltype(K)::value, RB>(); });
+}
+
+int batched_blocks_per_cu(int kmax, int rbits, bool fp64) {
+    if (rbits == 5) return fp64 ? batched_occupancy_r<double, 5>(kmax) : batched_occupancy_r<float, 5>(kmax);
+    return fp64 ? batched_occupancy_r<double, 4>(kmax) : batched_occupancy_r<float, 4>(kmax);
 }
 
 hipError_t launch_prep(double* mats, const double* smats, int n_static, const double* angles, int n_d2,

@@ -30,18 +30,27 @@ struct PassLaunch {
     int64_t grid_cap;  // workgroups per CU of a pass launch; 0 = as many as fit
 };
 
-struct BatchLaunch {
+// Device arguments of the batched launch (see batched_kernel).
+struct BatchArgs {
     const InstDesc* idesc;
-    const int32_t* order;
-    int32_t n_inst;
-    unsigned int* queue;
+    const int32_t* order;      // queue order: instances taken whole by one workgroup
+    const int32_t* team_off;   // n_teams + 1 offsets into team_list
+    const int32_t* team_list;  // large instances of each team
+    unsigned int* queue;       // next queue position (cleared before the launch)
+    unsigned int* bars;        // one barrier counter per team (cleared before the launch)
     double* L_out;
     double* norm_out;
-    unsigned grid;
+    uint64_t spin_ticks;       // bound of one team barrier wait, in wall-clock ticks
+    int32_t n_solo;
+    int32_t n_teams;
+    int32_t team_size;
+    int32_t n_xcd;
 };
 
 hipError_t launch_pass(const PassLaunch& L, hipStream_t st);
-hipError_t launch_batched(const PassLaunch& L, const BatchLaunch& B, hipStream_t st);
+hipError_t launch_batched(const PassLaunch& L, const BatchArgs& B, unsigned grid, hipStream_t st);
+// Resident workgroups per CU of the batched kernel instance (0 if unknown).
+int batched_blocks_per_cu(int kmax, int rbits, bool fp64);
 hipError_t launch_prep(double* mats, const double* smats, int n_static, const double* angles, int n_d2,
                        unsigned int* counters, int n_counters, hipStream_t st);
 hipError_t launch_reduce(const Reduction* red, int n, const double* ws, double* L_out, double* norm_out,

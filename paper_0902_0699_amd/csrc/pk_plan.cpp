@@ -768,6 +768,39 @@ int recompile(Plan* plan, std::string* err) {
     return PK_OK;
 }
 
+TeamSchedule team_schedule(const Plan* plan, int64_t grid, int n_xcd) {
+    TeamSchedule ts;
+    const int S = plan->batch.team_size;
+    if (n_xcd < 1 || grid % n_xcd != 0) n_xcd = 1;
+    ts.n_xcd = n_xcd;
+    ts.team_size = S;
+    const int64_t per_xcd = grid / n_xcd;
+    if (S > 0 && per_xcd >= S) ts.n_teams = (int)std::min<int64_t>((per_xcd / S) * n_xcd, kMaxTeams);
+    // a team index must name whole groups of S workgroups of one XCD
+    ts.n_teams -= ts.n_teams % n_xcd;
+    std::vector<std::vector<int32_t>> lists(ts.n_teams);
+    std::vector<double> load(ts.n_teams, 0.0);
+    for (int32_t i : plan->order) {
+        const Instance& in = plan->inst[i];
+        const bool large = ts.n_teams > 0 && in.fwd.front().ntiles >= (int64_t)plan->batch.min_team_tiles * S;
+        if (!large) {
+            ts.solo.push_back(i);
+            continue;
+        }
+        int best = 0;
+        for (int t = 1; t < ts.n_teams; ++t)
+            if (load[t] < load[best]) best = t;
+        lists[best].push_back(i);
+        load[best] += (double)in.fwd.size() * (double)((int64_t)1 << in.nq);
+    }
+    ts.team_off.push_back(0);
+    for (auto& l : lists) {
+        ts.team_list.insert(ts.team_list.end(), l.begin(), l.end());
+        ts.team_off.push_back((int32_t)ts.team_list.size());
+    }
+    return ts;
+}
+
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 TableLayout table_layout(const Plan* plan) {
@@ -785,8 +818,12 @@ TableLayout table_layout(const Plan* plan) {
     o = align256(o + (plan->static_mats.size() + plan->default_angles.size()) * sizeof(double));
     t.idesc = o;
     o = align256(o + plan->idesc.size() * sizeof(InstDesc));
-    t.order = o;
-    o = align256(o + plan->order.size() * sizeof(int32_t));
+    t.order = o;  // the queue order of the batched launch (instances left to single workgroups)
+    o = align256(o + plan->inst.size() * sizeof(int32_t));
+    t.team_off = o;
+    o = align256(o + (kMaxTeams + 1) * sizeof(int32_t));
+    t.team_list = o;
+    o = align256(o + plan->inst.size() * sizeof(int32_t));
     t.red = o;  // evaluation reductions, then backward reductions
     o = align256(o + (2 * plan->inst.size() + 3 * plan->d2_grad.size()) * sizeof(Reduction));
     t.total = std::max<size_t>(o, 256);
@@ -804,8 +841,8 @@ WsLayout workspace_layout(const Plan* plan, int op) {
     o = align256(o + (size_t)plan->n_reads * sizeof(double));
     w.gpart = o;
     if (op == PK_OP_BACKWARD) o = align256(o + (size_t)plan->n_gpart * sizeof(double));
-    w.counters = o;
-    o = align256(o + (plan->inst.size() + 8) * sizeof(int64_t));
+    w.counters = o;  // batched queue, barrier time-out flag, one barrier counter per team
+    o = align256(o + (plan->inst.size() + 8 + kMaxTeams) * sizeof(int64_t));
     w.state = o;
     if (op == PK_OP_BACKWARD) {
         size_t esz = plan->prec == PK_FP64 ? 16 : 8;

@@ -26,7 +26,7 @@ struct HostStage {
 
 struct HostPass {
     int k = 0;
-    std::vector<int> tbits;  // global bits of the tile, ascending (local bit l -> tbits[l])
+    std::vector<int> tbits;  // state bits of the tile: local bit l is tbits[l], carriers first
     std::vector<HostStage> stages;
     std::vector<Stage> subs;  // the stages packed into fixed-slot sub-stages (device form)
     int flags = 0;
@@ -67,6 +67,38 @@ struct Tiling {
 inline int default_tile_bits(int /*prec*/) { return 13; }
 inline int default_reg_bits(int prec) { return prec == PK_FP64 ? 4 : 5; }
 
+// Batched launch.  Workgroups that share an XCD (and so an L2) form teams of
+// team_size; a team runs the passes of its large instances together, with a
+// barrier between passes, so that an instance too large for one workgroup is
+// still spread over many CUs.  An instance is large when its first pass has at
+// least min_team_tiles * team_size tiles.  Every other instance is taken whole
+// by one workgroup from a queue.  team_size 0 turns teams off.  The device-scope
+// fences of a team barrier cost more than a single workgroup's sweep of an
+// instance of up to ~2^20 amplitudes, hence the high default threshold.
+struct BatchConfig {
+    int team_size = 16;
+    int min_team_tiles = 64;
+};
+
+constexpr int kMaxTeams = 512;
+
+struct Plan;
+
+struct TeamSchedule {
+    int n_teams = 0;
+    int team_size = 0;
+    int n_xcd = 1;
+    std::vector<int32_t> team_off;   // n_teams + 1 offsets into team_list
+    std::vector<int32_t> team_list;  // the large instances of each team, largest first
+    std::vector<int32_t> solo;       // the rest, largest first (the queue's order)
+};
+
+// Teams for a persistent grid of `grid` workgroups dispatched round-robin over
+// n_xcd XCDs: workgroup w sits on XCD w mod n_xcd; the j-th workgroup of an XCD
+// (j = w / n_xcd) is member j mod team_size of that XCD's team j / team_size.
+// Large instances go to teams by longest-processing-time first.
+TeamSchedule team_schedule(const Plan* plan, int64_t grid, int n_xcd);
+
 struct Plan {
     uint32_t magic = 0x504b504cu;
     int prec = PK_FP64;
@@ -77,6 +109,8 @@ struct Plan {
     int n_static = 0;
     bool backward_ok = true;
     Tiling tiling{13, 4, 1};
+    BatchConfig batch;
+    TeamSchedule team;              // the schedule of the current device grid
     std::string last_error;
 
     // flattened tables (forward passes of all instances, then backward passes)
@@ -111,7 +145,7 @@ std::string describe(const Plan* plan);
 
 // Byte offsets of the device table arrays inside plan->d_tables.
 struct TableLayout {
-    size_t passes, stages, ops, flips, mats, idesc, order, red, total;
+    size_t passes, stages, ops, flips, mats, idesc, order, team_off, team_list, red, total;
 };
 TableLayout table_layout(const Plan* plan);
 

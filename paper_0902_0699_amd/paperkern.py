@@ -41,6 +41,8 @@ class PkProblem(ctypes.Structure):
 SIGNATURES = {
     "pk_create": (ctypes.c_int, [ctypes.POINTER(PkProblem), _c_int32, _c_int32, ctypes.POINTER(_vp)]),
     "pk_set_tiling": (ctypes.c_int, [_vp, _c_int32, _c_int32, _c_int32, _c_int32]),
+    "pk_set_batch": (ctypes.c_int, [_vp, _c_int32, _c_int32]),
+    "pk_batch_teams": (ctypes.c_int, [_vp, ctypes.POINTER(_c_int32), ctypes.POINTER(_c_int32)]),
     "pk_set_launch": (ctypes.c_int, [_vp, _c_int32, _c_int32]),
     "pk_plan_passes": (ctypes.c_int, [_vp, _c_int32, ctypes.POINTER(_c_int32)]),
     "pk_plan_describe": (ctypes.c_int, [_vp, ctypes.c_char_p, _c_int64, ctypes.POINTER(_c_int64)]),
@@ -153,6 +155,16 @@ class Plan:
     def set_tiling(self, tile_bits, carrier_bits=4, fuse=1, lane_order=1):
         _check(lib().pk_set_tiling(self.handle, tile_bits, carrier_bits, fuse, lane_order), self.handle)
         self._ws = {}
+
+    def set_batch(self, team_size=16, min_team_tiles=64):
+        _check(lib().pk_set_batch(self.handle, team_size, min_team_tiles), self.handle)
+        self._ws = {}
+
+    def batch_teams(self):
+        """(teams, instances run by teams) of the batched launch on the current device."""
+        t, n = _c_int32(), _c_int32()
+        _check(lib().pk_batch_teams(self.handle, ctypes.byref(t), ctypes.byref(n)), self.handle)
+        return t.value, n.value
 
     def set_launch(self, wgs_per_cu=0, reg_bits=0):
         _check(lib().pk_set_launch(self.handle, wgs_per_cu, reg_bits), self.handle)

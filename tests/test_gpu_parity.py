@@ -297,6 +297,76 @@ def test_backward_against_oracle_adjoint(nq, eloc):
     np.testing.assert_allclose(gang.cpu().numpy(), wang.reshape(-1), rtol=1e-10, atol=1e-13)
 
 
+@pytest.mark.parametrize("team_size,tile_bits,prec", [(4, 8, "fp64"), (64, 6, "fp64"), (16, 8, "fp32"),
+                                                      (0, 8, "fp64")])
+def test_batched_teams_against_oracle(team_size, tile_bits, prec):
+    """Large instances run by teams of workgroups (a device-scope barrier between
+    passes), the rest by single workgroups; small tiles make instances of
+    2^10..2^14 amplitudes large enough for teams.  team_size 0: teams off."""
+    pk = _pk()
+    insts = W.batch_instances(W.SEEDS["batched"], count=40, nq_min=10, span=5)
+    probs = [{"nq": i["nq"], "gates": i["gates"], "marked": i["marked"]} for i in insts]
+    plan = pk.Plan(probs, prec=prec)
+    plan.set_tiling(tile_bits, 4, 1)
+    plan.set_batch(team_size, 2)
+    n_teams, n_team_inst = plan.batch_teams()
+    _say("batched teams: size %d tile %d %s -> %d teams, %d team instances"
+         % (team_size, tile_bits, prec, n_teams, n_team_inst))
+    if team_size:
+        assert n_teams > 0 and n_team_inst > 0
+    else:
+        assert n_teams == 0 and n_team_inst == 0
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    packed = _dev(np.concatenate([i["psi"] for i in insts]), dt)
+    tol = TOL64 if prec == "fp64" else TOL32
+    for rep in range(2):  # graph replay: counters and barriers start from zero each launch
+        res, L, norm = pk.evaluate_batched(plan, packed)
+        torch.cuda.synchronize()
+        res = res.cpu().numpy().astype(np.complex128)
+        offs = plan.offsets()
+        for k, (p, inst) in enumerate(zip(probs, insts)):
+            want, Lw, nw = O.evaluate(p["nq"], p["gates"], p["marked"], inst["psi"])
+            assert _relerr(res[offs[k]:offs[k + 1]], want) <= tol
+            assert abs(float(L[k]) - Lw) <= tol and abs(float(norm[k]) - nw) <= tol
+
+
+def test_batched_large_instances_run_by_teams():
+    """Default settings: instances of 2^23 amplitudes go to teams (one workgroup per
+    instance would leave most CUs idle), small ones to the queue.  Outputs are
+    checked at sampled labels against the oracle's closed form."""
+    pk = _pk()
+    rng = np.random.default_rng(31)
+    insts = [W.draw_instance(rng, nq) for nq in (23, 11, 23, 9)]
+    probs = [{"nq": i["nq"], "gates": i["gates"], "marked": i["marked"]} for i in insts]
+    plan = pk.Plan(probs)
+    n_teams, n_team_inst = plan.batch_teams()
+    _say("large batch: %d teams, %d team instances" % (n_teams, n_team_inst))
+    assert n_teams > 0 and n_team_inst == 2
+    packed = _dev(np.concatenate([i["psi"] for i in insts]))
+    res, L, norm = pk.evaluate_batched(plan, packed)
+    torch.cuda.synchronize()
+    offs = plan.offsets()
+    for k, inst in enumerate(insts):
+        nq = inst["nq"]
+        idx = np.unique(np.concatenate([rng.integers(0, 1 << nq, 4096), inst["marked"]]))
+        want, Lw = O.grover_sampled(nq, inst["gates"], inst["marked"], inst["psi"], idx)
+        got = res[offs[k]:offs[k + 1]][torch.from_numpy(idx).to("cuda")].cpu().numpy()
+        err = math.sqrt(np.mean(np.abs(got - want) ** 2) * (1 << nq))
+        assert err <= TOL64 and abs(float(L[k]) - Lw) <= TOL64 and abs(float(norm[k]) - 1.0) <= TOL64
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = {}
+    for ts in (16, 0):
+        plan.set_batch(ts, 64)
+        out = torch.empty_like(packed)
+        pk.evaluate_batched(plan, packed, out=out)
+        e0.record()
+        pk.evaluate_batched(plan, packed, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        times[ts] = e0.elapsed_time(e1)
+    _say("  teams %.3f ms, single workgroups %.3f ms" % (times[16], times[0]))
+
+
 def test_autotuned_batched_plan_matches_oracle():
     """The tuner times every candidate on the caller's buffers and leaves the fastest
     applied; the tuned plan still matches the oracle instance by instance."""

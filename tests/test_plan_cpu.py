@@ -76,6 +76,11 @@ def test_fp32_allows_31_qubits_and_tiling_limits():
         plan64.set_tiling(10, fuse=2)
     with pytest.raises(pk.PaperkernError):
         plan64.set_tiling(10, lane_order=2)
+    with pytest.raises(pk.PaperkernError):
+        plan64.set_batch(65, 4)
+    with pytest.raises(pk.PaperkernError):
+        plan64.set_batch(16, 0)
+    plan64.set_batch(0, 1)
 
 
 def test_offsets_and_angles_bookkeeping():

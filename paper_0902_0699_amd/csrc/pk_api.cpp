@@ -106,7 +106,6 @@ int ensure_device(DevPlan* d) {
     std::vector<char> buf(t.total, 0);
     put(buf, t.passes, P.passes);
     put(buf, t.stages, P.stages);
-    put(buf, t.ops, P.ops);
     put(buf, t.flips, P.flips);
     put(buf, t.mats, P.static_mats);
     put(buf, t.mats + P.static_mats.size() * sizeof(double), P.default_angles);
@@ -157,7 +156,6 @@ PassLaunch base_launch(DevPlan* d, void* ws, int op) {
     PassLaunch L{};
     L.passes = at<Pass>(P.d_tables, t.passes);
     L.stages = at<Stage>(P.d_tables, t.stages);
-    L.ops = at<Op>(P.d_tables, t.ops);
     L.flips = at<Flip>(P.d_tables, t.flips);
     L.mats = at<double>(ws, w.mats);
     L.partials = at<double>(ws, w.partials);

@@ -5,10 +5,10 @@
 // in k chosen bit positions (the tile bits, always including the lowest
 // "carrier" bits so that every memory run is contiguous), every tile is loaded
 // into one workgroup, the pass's gates are applied, and the tile is written
-// back.  Inside a tile, each thread holds 16 amplitudes in registers whose
-// local labels differ in 4 "register bits"; a stage applies the gates on those
-// 4 bits as butterflies in registers, and an LDS exchange moves the tile to the
-// next stage's register bits.  This is the pair update of Sec. 3 (Eq. resmat1)
+// back.  Inside a tile, each thread holds 16 (or 32) amplitudes in registers
+// whose local labels differ in 4 (or 5) "register bits"; a stage applies the
+// gates on those bits as butterflies in registers, and an LDS exchange moves the
+// tile to the next stage's register bits.  This is the pair update of Sec. 3 (Eq. resmat1)
 // applied to all partner pairs of a qubit at once, grouped so that the state
 // is read from HBM once per group of qubits instead of once per gate.
 #pragma once
@@ -31,8 +31,8 @@ enum OpKind : int32_t {
     OP_D2BWD = 6,  // backward D2: psi <- D^H psi, grad += Re<lambda|dD|psi>, lambda <- D^H lambda
 };
 
-// All table fields are 32- or 64-bit so that the kernels read them with scalar
-// loads from the constant address space.
+// One step of a stage's op list, as the plan compiler schedules it on the host;
+// the list is then packed into sub-stages (Stage) for the device.
 struct Op {
     int32_t kind;
     int32_t a;      // register bit 0..3 for OP_H / OP_MAT / OP_D2BWD
@@ -42,6 +42,9 @@ struct Op {
     int32_t pad;
 };
 
+// Device tables below: all fields are 32- or 64-bit so that the kernels read
+// them with scalar loads from the constant address space.
+//
 // One sub-stage: a fixed sequence of optional steps applied to the registers,
 // in this order: seed, flip, matrix, Hadamards (mask 1), flip, Hadamards
 // (mask 2), matrix, backward D2, scale, read.  A stage's op list is packed into

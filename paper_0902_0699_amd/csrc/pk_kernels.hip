@@ -39,7 +39,6 @@ struct Cplx<float> {
 struct KArgs {
     const Pass* passes;
     const Stage* stages;
-    const Op* ops;
     const Flip* flips;
     const double* mats;
     const void* src0;  // vector 0 input of the first pass
@@ -799,7 +798,6 @@ static KArgs kargs(const PassLaunch& L) {
     KArgs a;
     a.passes = L.passes;
     a.stages = L.stages;
-    a.ops = L.ops;
     a.flips = L.flips;
     a.mats = L.mats;
     a.src0 = L.src0;

@@ -10,7 +10,6 @@ namespace pk {
 struct PassLaunch {
     const Pass* passes;
     const Stage* stages;
-    const Op* ops;
     const Flip* flips;
     const double* mats;
     const void* src0;

@@ -649,7 +649,6 @@ int recompile(Plan* plan, std::string* err) {
     (void)err;
     plan->passes.clear();
     plan->stages.clear();
-    plan->ops.clear();
     plan->flips.clear();
     plan->idesc.clear();
     plan->order.clear();
@@ -810,8 +809,6 @@ TableLayout table_layout(const Plan* plan) {
     o = align256(o + plan->passes.size() * sizeof(Pass));
     t.stages = o;
     o = align256(o + plan->stages.size() * sizeof(Stage));
-    t.ops = o;
-    o = align256(o + plan->ops.size() * sizeof(Op));
     t.flips = o;
     o = align256(o + plan->flips.size() * sizeof(Flip));
     t.mats = o;  // static matrices followed by the default angles

@@ -116,7 +116,6 @@ struct Plan {
     // flattened tables (forward passes of all instances, then backward passes)
     std::vector<Pass> passes;
     std::vector<Stage> stages;
-    std::vector<Op> ops;
     std::vector<Flip> flips;
     std::vector<InstDesc> idesc;    // batched launch: per-instance pass ranges
     std::vector<int32_t> order;     // instances by decreasing size (largest first)
@@ -133,9 +132,6 @@ struct Plan {
     int device = -1;
     void* d_tables = nullptr;
     size_t d_tables_bytes = 0;
-    void* capture_stream = nullptr;
-    void* graph_exec[2] = {nullptr, nullptr};  // [0] evaluate, [1] batched
-    const void* graph_key[2][8] = {};
 };
 
 // Validates and compiles; returns PK_OK or an error code with plan->last_error set.
@@ -145,7 +141,7 @@ std::string describe(const Plan* plan);
 
 // Byte offsets of the device table arrays inside plan->d_tables.
 struct TableLayout {
-    size_t passes, stages, ops, flips, mats, idesc, order, team_off, team_list, red, total;
+    size_t passes, stages, flips, mats, idesc, order, team_off, team_list, red, total;
 };
 TableLayout table_layout(const Plan* plan);
 

@@ -117,9 +117,8 @@ int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_
  * the default; more than fit only queue up), and reg_bits = 4 or 5 register
  * bits per thread in forward passes (16 or 32 amplitudes per thread, a
  * workgroup of 2^(tile_bits - reg_bits) threads; 0 selects the default: 4 for
- * FP64, 5 for FP32).  Backward passes
- * always use 4.  Changing reg_bits re-compiles the schedule.  Drops captured
- * graphs.  PK_EINVAL when out of range.
+ * FP64, 5 for FP32).  Backward passes always use 4.  Changing reg_bits
+ * re-compiles the schedule.  Drops captured graphs.  PK_EINVAL when out of range.
  */
 int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu, int32_t reg_bits);
 
@@ -133,11 +132,11 @@ int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu, int32_t reg_bits);
  * other instance is taken whole by one workgroup from a queue, largest first.
  * team_size 0 turns teams off.  Defaults 16 and 64 (instances of 2^22 or more
  * amplitudes at the default tile: below that a single workgroup's sweep costs
- * less than the barriers' device-scope fences).  A team barrier that has not completed within about half a
- * second (the launch's workgroups are not all resident, e.g. the GPU is shared)
- * gives up: that instance's L_out and norm_out entries are NaN.  Drops the
- * plan's device tables and graphs.  PK_EINVAL when out of range (team_size
- * 0..64, min_team_tiles 1..4096).
+ * less than the barriers' device-scope fences).  A team barrier that has not
+ * completed within about half a second (the launch's workgroups are not all
+ * resident, e.g. the GPU is shared) gives up: that instance's L_out and
+ * norm_out entries are NaN.  Drops the plan's device tables and graphs.
+ * PK_EINVAL when out of range (team_size 0..64, min_team_tiles 1..4096).
  */
 int pk_set_batch(pk_plan* plan, int32_t team_size, int32_t min_team_tiles);
 

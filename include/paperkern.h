@@ -105,11 +105,17 @@ int pk_create(const pk_problem* probs, int32_t n_inst, int32_t prec, pk_plan** o
  * lowest state bits, 1 (default) bits whose byte stride is below 4 KiB or at
  * least 4 MiB first -- on MI355X a wave-wide load whose lane groups lie 4 KiB
  * to 2 MiB apart streams up to a third slower.  Either order gives the same
- * result.  Re-compiles the schedule and drops captured graphs.  Defaults:
- * 2^13-amplitude tiles (FP64 and FP32), 4 carriers, fusion on, lane_order 1.
- * PK_EINVAL when out of range.
+ * result.  page_cap > 0: among tile bits the schedule could take equally, the
+ * compiler takes bits at byte strides of 2 MiB or more first while a tile has
+ * fewer than page_cap of them (0 = no preference, -1 = the default: 4 for FP64,
+ * 0 for FP32) -- a tile whose amplitudes span many 2 MiB pages misses the
+ * per-CU address translation cache on most loads, so these bits are best spread
+ * over the passes.  Re-compiles the schedule and drops captured graphs.
+ * Defaults: 2^13-amplitude tiles (FP64 and FP32), 4 carriers, fusion on,
+ * lane_order 1, page_cap -1.  PK_EINVAL when out of range (page_cap -1..16).
  */
-int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_t fuse, int32_t lane_order);
+int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_t fuse, int32_t lane_order,
+                  int32_t page_cap);
 
 /*
  * pk_set_launch -- launch shape of the pass kernels: wgs_per_cu resident

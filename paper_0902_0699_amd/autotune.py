@@ -50,7 +50,7 @@ def candidates(prec, op):
 
 
 def apply(plan, cfg):
-    plan.set_tiling(cfg["tile_bits"], cfg["carrier_bits"], 1, cfg["lane_order"])
+    plan.set_tiling(cfg["tile_bits"], cfg["carrier_bits"], 1, cfg["lane_order"], cfg.get("page_cap", -1))
     plan.set_launch(cfg["wgs_per_cu"], cfg["reg_bits"])
     plan.set_batch(cfg.get("team_size", 16), cfg.get("min_team_tiles", 64))
 

@@ -348,7 +348,8 @@ int pk_create(const pk_problem* probs, int32_t n_inst, int32_t prec, pk_plan** o
     return PK_OK;
 }
 
-int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_t fuse, int32_t lane_order) {
+int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_t fuse, int32_t lane_order,
+                  int32_t page_cap) {
     if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");
     DevPlan* d = dp(plan);
     const int kmax = d->host.prec == PK_FP64 ? 13 : 14;
@@ -357,8 +358,9 @@ int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_
         return fail(d, PK_EINVAL, "carrier_bits out of range");
     if (fuse != 0 && fuse != 1) return fail(d, PK_EINVAL, "fuse must be 0 or 1");
     if (lane_order != 0 && lane_order != 1) return fail(d, PK_EINVAL, "lane_order must be 0 or 1");
+    if (page_cap < -1 || page_cap > 16) return fail(d, PK_EINVAL, "page_cap must be -1..16");
     d->host.tiling = Tiling{tile_bits, carrier_bits, fuse, d->host.tiling.wgs_per_cu, d->host.tiling.reg_bits,
-                            lane_order};
+                            lane_order, page_cap < 0 ? default_page_cap(d->host.prec) : page_cap};
     drop_device(d);
     std::string err;
     try {

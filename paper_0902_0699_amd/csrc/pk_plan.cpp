@@ -279,9 +279,21 @@ struct Compiler {
             in_t[b] = 1;
             t.push_back(b);
         }
+        // Among bits of equal gain, take bits at byte strides of 2 MiB or more (each
+        // doubles the pages a tile touches) first while the tile has fewer than
+        // page_cap of them, so that no later pass is left with all of them.
+        const int pcap = plan->tiling.page_cap;
+        const int pbit = kPageByteBit - (plan->prec == PK_FP64 ? 4 : 3);
         while ((int)t.size() < k) {
             int best = -1, best_gain = -1;
-            for (int b = 0; b < nq; ++b) {
+            int npage = 0;
+            for (int b : t) npage += b >= pbit;
+            std::vector<int> cand;
+            if (pcap > 0 && npage < pcap)
+                for (int b = nq - 1; b >= pbit; --b) cand.push_back(b);
+            for (int b = 0; b < nq; ++b)
+                if (!(pcap > 0 && npage < pcap && b >= pbit)) cand.push_back(b);
+            for (int b : cand) {
                 if (in_t[b]) continue;
                 in_t[b] = 1;
                 int g = scan(items, done, in_t, nq, max_gates, nullptr);
@@ -544,7 +556,7 @@ int compile_plan(Plan* plan, const pk_problem* probs, int n_inst, int prec, std:
         return PK_EINVAL;
     }
     plan->prec = prec;
-    plan->tiling = Tiling{default_tile_bits(prec), 4, 1, 0, default_reg_bits(prec), 1};
+    plan->tiling = Tiling{default_tile_bits(prec), 4, 1, 0, default_reg_bits(prec), 1, default_page_cap(prec)};
     const int nq_max = prec == PK_FP64 ? 30 : 31;
     int64_t off = 0;
     int d2 = 0;

@@ -40,7 +40,7 @@ class PkProblem(ctypes.Structure):
 
 SIGNATURES = {
     "pk_create": (ctypes.c_int, [ctypes.POINTER(PkProblem), _c_int32, _c_int32, ctypes.POINTER(_vp)]),
-    "pk_set_tiling": (ctypes.c_int, [_vp, _c_int32, _c_int32, _c_int32, _c_int32]),
+    "pk_set_tiling": (ctypes.c_int, [_vp, _c_int32, _c_int32, _c_int32, _c_int32, _c_int32]),
     "pk_set_batch": (ctypes.c_int, [_vp, _c_int32, _c_int32]),
     "pk_batch_teams": (ctypes.c_int, [_vp, ctypes.POINTER(_c_int32), ctypes.POINTER(_c_int32)]),
     "pk_set_launch": (ctypes.c_int, [_vp, _c_int32, _c_int32]),
@@ -152,8 +152,8 @@ class Plan:
     def n_inst(self):
         return len(self.problems)
 
-    def set_tiling(self, tile_bits, carrier_bits=4, fuse=1, lane_order=1):
-        _check(lib().pk_set_tiling(self.handle, tile_bits, carrier_bits, fuse, lane_order), self.handle)
+    def set_tiling(self, tile_bits, carrier_bits=4, fuse=1, lane_order=1, page_cap=-1):
+        _check(lib().pk_set_tiling(self.handle, tile_bits, carrier_bits, fuse, lane_order, page_cap), self.handle)
         self._ws = {}
 
     def set_batch(self, team_size=16, min_team_tiles=64):

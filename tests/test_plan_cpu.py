@@ -155,6 +155,21 @@ def test_autotune_candidates_are_accepted_and_signature_is_structural():
     assert sig(a) == sig(b) != sig(c)
 
 
+def test_page_cap_spreads_large_stride_bits_over_passes():
+    """FP64 default (page_cap 4): no n_q = 30 tile holds more than 5 state bits >= 17
+    (2 MiB byte stride), still 5 passes; without the cap the pass holding Inv has 8."""
+    inst = W.draw_instance(np.random.default_rng(1), 30, with_state=False)
+    prob = {"nq": 30, "gates": inst["gates"], "marked": inst["marked"]}
+    plan = pk.Plan(prob)
+    tiles = [p["tile_bits"] for p in plan.describe()["instances"][0]["forward"]]
+    assert len(tiles) == 5 and max(sum(b >= 17 for b in tb) for tb in tiles) <= 5
+    plan.set_tiling(13, 4, 1, 1, 0)
+    tiles0 = [p["tile_bits"] for p in plan.describe()["instances"][0]["forward"]]
+    assert len(tiles0) == 5 and max(sum(b >= 17 for b in tb) for tb in tiles0) == 8
+    with pytest.raises(pk.PaperkernError):
+        plan.set_tiling(13, 4, 1, 1, 17)
+
+
 def test_pair_indices_rejects_bad_ranges():
     lib = pk.lib()
     assert lib.pk_pair_indices(0, 1, 0, 1, None, None, None) == pk.PK_EINVAL

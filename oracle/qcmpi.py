@@ -17,6 +17,13 @@ Gate lists are sequences of tuples, applied left to right (first tuple first):
   ("ORACLE",)                     sign flip of every marked item (Eq. oracle1)
   ("INV",)                        2|0..0><0..0| - I (Eq. inversion)
   ("D2", i_s, alpha, beta, gamma) Wigner D^(1/2) noise rotation (Sec. 6.3)
+  ("TWOOP", is1, is2, V)          any 4x4 operator on qubits is1, is2 (Eq. resmat2);
+                                  V[ab][cd] = <a b|V|c d>, a the value of qubit is1
+  ("CNOT", is1, is2)              control is1, target is2 (Sec. 4.2)
+  ("CPHASE", is1, is2)            diag(1, 1, 1, -1) (Sec. 4.2)
+  ("CPHASEK", is1, is2, k)        diag(1, 1, 1, e^{2 pi i / 2^k}) (Eq. cphasek)
+  ("SWAP", is1, is2)              exchanges the two qubits (the QFT of App. A)
+  ("D4", is1, is2, alpha, beta, gamma)  Wigner D^(3/2) two-qubit noise (Sec. 6.3)
 """
 
 import math
@@ -34,6 +41,9 @@ __all__ = [
     "readout", "adjoint_grad", "fd_grad_angles", "fd_grad_psi",
     "kron_operator", "dense_circuit",
     "grover_closed_form", "diffusion_closed_form", "grover_sampled",
+    "CNOT", "CPHASE", "SWAP", "cphasek", "apply_twoop", "apply_twoop_loop",
+    "wigner_small_d", "wigner_small_d_prime", "wigner_d", "d4_matrix", "d4_derivatives",
+    "kron_twoop", "TWO_QUBIT", "PARAMETRIC",
 ]
 
 # ---------------------------------------------------------------------------
@@ -185,6 +195,58 @@ def inversion(psi):
 
 
 # ---------------------------------------------------------------------------
+# Two-qubit operators (Sec. 4: Eqs. twoopA, twoopB, resmat2; Sec. 4.2)
+# ---------------------------------------------------------------------------
+#
+# Basis order of a 4x4 operator: |q_is1 q_is2> = |00>, |01>, |10>, |11>, index
+# 2 q_is1 + q_is2, whatever the significance of is1 and is2 in the label n
+# (Eq. twoopB lists n_00, n_01, n_10, n_11 that way).
+
+TWO_QUBIT = ("TWOOP", "CNOT", "CPHASE", "CPHASEK", "SWAP", "D4")
+PARAMETRIC = ("D2", "D4")
+
+CNOT = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]], dtype=np.complex128)
+CPHASE = np.diag([1, 1, 1, -1]).astype(np.complex128)
+SWAP = np.array([[1, 0, 0, 0], [0, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 1]], dtype=np.complex128)
+
+
+def cphasek(k):
+    """CPHASEK of Eq. cphasek: the phase e^{2 pi i / 2^k} on |11> only."""
+    return np.diag([1, 1, 1, np.exp(2j * math.pi / (1 << k))]).astype(np.complex128)
+
+
+def apply_twoop(psi, nq, is1, is2, op):
+    """Return V psi for a 4x4 operator on qubits is1, is2 (Eq. resmat2).
+
+    Every amplitude quartet (n_00, n_01, n_10, n_11) of Eq. twoopB (from
+    :func:`quartet_indices`) is replaced by V times it.
+    """
+    psi = np.asarray(psi, dtype=np.complex128)
+    op = np.asarray(op, dtype=np.complex128)
+    quart = quartet_indices(nq, is1, is2)
+    q = np.stack([psi[n] for n in quart])
+    r = op @ q
+    out = psi.copy()
+    for n, row in zip(quart, r):
+        out[n] = row
+    return out
+
+
+def apply_twoop_loop(psi, nq, is1, is2, op):
+    """Eq. resmat2 quartet by quartet in pure Python (small n_q only)."""
+    out = np.array(psi, dtype=np.complex128)
+    s1, s2 = stride(nq, is1), stride(nq, is2)
+    for n in range(1 << nq):
+        if (n // s1) % 2 or (n // s2) % 2:
+            continue
+        labels = [n, n + s2, n + s1, n + s1 + s2]
+        vals = [psi[m] for m in labels]
+        for a, m in enumerate(labels):
+            out[m] = sum(op[a][c] * vals[c] for c in range(4))
+    return out
+
+
+# ---------------------------------------------------------------------------
 # Noise rotation D^(1/2)(alpha, beta, gamma) (Sec. 6.3, subroutine D2)
 # ---------------------------------------------------------------------------
 #
@@ -225,6 +287,88 @@ def d2_derivatives(alpha, beta, gamma):
 
 
 # ---------------------------------------------------------------------------
+# Two-qubit noise D^(3/2)(alpha, beta, gamma) (Sec. 6.3, subroutine D4)
+# ---------------------------------------------------------------------------
+#
+# Reading adopted where the paper is silent: the 4x4 Wigner function of j = 3/2,
+# D_{m'm} = e^{-i m' alpha} d_{m'm}(beta) e^{-i m gamma} (the same Euler
+# convention as D2: for j = 1/2 it gives R_z(alpha) R_y(beta) R_z(gamma)), with
+# rows and columns m = 3/2, 1/2, -1/2, -3/2 taken as the two-qubit basis
+# |00>, |01>, |10>, |11>: m = 3/2 - (2 q_is1 + q_is2).
+
+
+def wigner_small_d(twoj, beta):
+    """d^j_{m'm}(beta), j = twoj / 2, from Wigner's formula; rows/cols m = j, j-1, .., -j.
+
+    d = sum_s (-1)^(m'-m+s) sqrt((j+m')!(j-m')!(j+m)!(j-m)!)
+        / ((j+m-s)! s! (m'-m+s)! (j-m'-s)!) cos(beta/2)^(2j+m-m'-2s) sin(beta/2)^(m'-m+2s).
+    """
+    return _wigner_small_d(twoj, beta, derivative=False)
+
+
+def wigner_small_d_prime(twoj, beta):
+    """d/dbeta of :func:`wigner_small_d`, term by term."""
+    return _wigner_small_d(twoj, beta, derivative=True)
+
+
+def _wigner_small_d(twoj, beta, derivative):
+    f = math.factorial
+    c, s = math.cos(0.5 * beta), math.sin(0.5 * beta)
+    n = twoj + 1
+    out = np.zeros((n, n))
+    # work with integers J = 2j, M = 2m so that factorial arguments stay integral
+    for r in range(n):
+        mp = twoj - 2 * r  # 2 m'
+        for col in range(n):
+            m = twoj - 2 * col  # 2 m
+            jpm, jmm = (twoj + mp) // 2, (twoj - mp) // 2  # j + m', j - m'
+            jpn, jmn = (twoj + m) // 2, (twoj - m) // 2  # j + m, j - m
+            dm = (mp - m) // 2  # m' - m
+            pref = math.sqrt(f(jpm) * f(jmm) * f(jpn) * f(jmn))
+            total = 0.0
+            for k in range(0, max(jpn, jmm) + 1):
+                if jpn - k < 0 or dm + k < 0 or jmm - k < 0:
+                    continue
+                coef = (-1) ** (dm + k) * pref / (f(jpn - k) * f(k) * f(dm + k) * f(jmm - k))
+                pc = twoj - dm - 2 * k  # exponent of cos
+                ps = dm + 2 * k  # exponent of sin
+                if not derivative:
+                    total += coef * c ** pc * s ** ps
+                else:
+                    term = 0.0
+                    if pc:
+                        term += -0.5 * pc * c ** (pc - 1) * s ** (ps + 1)
+                    if ps:
+                        term += 0.5 * ps * c ** (pc + 1) * s ** (ps - 1)
+                    total += coef * term
+            out[r, col] = total
+    return out
+
+
+def wigner_d(twoj, alpha, beta, gamma):
+    """D^j_{m'm}(alpha, beta, gamma) = e^{-i m' alpha} d^j_{m'm}(beta) e^{-i m gamma}."""
+    m = np.array([0.5 * (twoj - 2 * r) for r in range(twoj + 1)])
+    left = np.exp(-1j * m * alpha)
+    right = np.exp(-1j * m * gamma)
+    return left[:, None] * wigner_small_d(twoj, beta) * right[None, :]
+
+
+def d4_matrix(alpha, beta, gamma):
+    """D^(3/2)(alpha, beta, gamma) in the basis |q_is1 q_is2> (m = 3/2 - index)."""
+    return wigner_d(3, alpha, beta, gamma)
+
+
+def d4_derivatives(alpha, beta, gamma):
+    """(dD/dalpha, dD/dbeta, dD/dgamma) of :func:`d4_matrix`."""
+    m = np.array([1.5, 0.5, -0.5, -1.5])
+    D = d4_matrix(alpha, beta, gamma)
+    left = np.exp(-1j * m * alpha)
+    right = np.exp(-1j * m * gamma)
+    dbeta = left[:, None] * wigner_small_d_prime(3, beta) * right[None, :]
+    return (-1j * m[:, None] * D, dbeta, D * (-1j * m[None, :]))
+
+
+# ---------------------------------------------------------------------------
 # Circuits: the Grover operator of Sec. 5.1 with the noise of Sec. 6.3
 # ---------------------------------------------------------------------------
 
@@ -254,14 +398,40 @@ def _gate_matrix(gate):
         return np.asarray(gate[2], dtype=np.complex128)
     if kind == "D2":
         return d2_matrix(*gate[2:5])
+    if kind == "TWOOP":
+        return np.asarray(gate[3], dtype=np.complex128)
+    if kind == "CNOT":
+        return CNOT
+    if kind == "CPHASE":
+        return CPHASE
+    if kind == "CPHASEK":
+        return cphasek(gate[3])
+    if kind == "SWAP":
+        return SWAP
+    if kind == "D4":
+        return d4_matrix(*gate[3:6])
     raise ValueError(kind)
+
+
+def _angles(gate):
+    return gate[2:5] if gate[0] == "D2" else gate[3:6]
+
+
+def _derivatives(gate):
+    return d2_derivatives(*_angles(gate)) if gate[0] == "D2" else d4_derivatives(*_angles(gate))
+
+
+def _apply_matrix(psi, nq, gate, m):
+    if gate[0] in TWO_QUBIT:
+        return apply_twoop(psi, nq, gate[1], gate[2], m)
+    return apply_oneop(psi, nq, gate[1], m)
 
 
 def apply_gate(psi, nq, gate, marked):
     """Apply one gate tuple (see the module docstring) to psi."""
     kind = gate[0]
-    if kind in ("H", "ONEOP", "D2"):
-        return apply_oneop(psi, nq, gate[1], _gate_matrix(gate))
+    if kind in ("H", "ONEOP", "D2") or kind in TWO_QUBIT:
+        return _apply_matrix(psi, nq, gate, _gate_matrix(gate))
     if kind == "HALL":
         return hall(psi, nq)
     if kind == "ORACLE":
@@ -274,8 +444,8 @@ def apply_gate(psi, nq, gate, marked):
 def apply_gate_adjoint(psi, nq, gate, marked):
     """Apply the Hermitian adjoint of one gate (HALL, Oracle and Inv are self-adjoint)."""
     kind = gate[0]
-    if kind in ("H", "ONEOP", "D2"):
-        return apply_oneop(psi, nq, gate[1], _gate_matrix(gate).conj().T)
+    if kind in ("H", "ONEOP", "D2") or kind in TWO_QUBIT:
+        return _apply_matrix(psi, nq, gate, _gate_matrix(gate).conj().T)
     return apply_gate(psi, nq, gate, marked)
 
 
@@ -313,7 +483,7 @@ def adjoint_grad(nq, gates, marked, psi_in, dL=1.0):
     to the angle gradient before setting lambda_{k-1} = U_k^dagger lambda_k.
     Returns (grad_psi, grad_angles): grad_psi = 2 lambda_0 in the real-pair
     convention (real part = dL/dRe psi_in, imaginary part = dL/dIm psi_in) and
-    grad_angles a (n_D2, 3) array in gate-list order.
+    grad_angles a (n_param, 3) array, one row per D2 or D4 gate in gate-list order.
     """
     states = [np.array(psi_in, dtype=np.complex128)]
     for g in gates:
@@ -321,37 +491,36 @@ def adjoint_grad(nq, gates, marked, psi_in, dL=1.0):
     lam = np.zeros_like(states[-1])
     for x in marked:
         lam[x] = dL * states[-1][x]
-    d2_positions = [k for k, g in enumerate(gates) if g[0] == "D2"]
-    grads = np.zeros((len(d2_positions), 3))
+    positions = [k for k, g in enumerate(gates) if g[0] in PARAMETRIC]
+    grads = np.zeros((len(positions), 3))
     for k in range(len(gates) - 1, -1, -1):
         g = gates[k]
-        if g[0] == "D2":
-            row = d2_positions.index(k)
-            for t, dmat in enumerate(d2_derivatives(*g[2:5])):
-                dpsi = apply_oneop(states[k], nq, g[1], dmat)
+        if g[0] in PARAMETRIC:
+            row = positions.index(k)
+            for t, dmat in enumerate(_derivatives(g)):
+                dpsi = _apply_matrix(states[k], nq, g, dmat)
                 grads[row, t] = 2.0 * float(np.vdot(lam, dpsi).real)
         lam = apply_gate_adjoint(lam, nq, g, marked)
     return 2.0 * lam, grads
 
 
 def _with_angle(gates, row, t, value):
-    d2_positions = [k for k, g in enumerate(gates) if g[0] == "D2"]
-    k = d2_positions[row]
+    positions = [k for k, g in enumerate(gates) if g[0] in PARAMETRIC]
+    k = positions[row]
     g = list(gates[k])
-    g[2 + t] = value
+    g[(2 if g[0] == "D2" else 3) + t] = value
     out = list(gates)
     out[k] = tuple(g)
     return out
 
 
 def fd_grad_angles(nq, gates, marked, psi_in, h=1e-6):
-    """Central differences of L with respect to every D2 angle."""
-    n_d2 = sum(1 for g in gates if g[0] == "D2")
-    out = np.zeros((n_d2, 3))
-    d2_positions = [k for k, g in enumerate(gates) if g[0] == "D2"]
-    for row in range(n_d2):
+    """Central differences of L with respect to every D2 and D4 angle."""
+    positions = [k for k, g in enumerate(gates) if g[0] in PARAMETRIC]
+    out = np.zeros((len(positions), 3))
+    for row, k in enumerate(positions):
         for t in range(3):
-            base = gates[d2_positions[row]][2 + t]
+            base = _angles(gates[k])[t]
             lp = evaluate(nq, _with_angle(gates, row, t, base + h), marked, psi_in)[1]
             lm = evaluate(nq, _with_angle(gates, row, t, base - h), marked, psi_in)[1]
             out[row, t] = (lp - lm) / (2.0 * h)
@@ -385,6 +554,30 @@ def kron_operator(nq, i_s, op):
     return m
 
 
+def kron_twoop(nq, is1, is2, op):
+    """Full matrix of a 4x4 operator on qubits is1, is2 as a sum of Kronecker products:
+    sum_{ab,cd} V_{ab;cd} (.. x |a><c| at is1 x .. x |b><d| at is2 x ..), identity on
+    every other qubit, qubit 1 leftmost.  Independent of the quartet formula."""
+    op = np.asarray(op, dtype=np.complex128)
+    size = 1 << nq
+    out = np.zeros((size, size), dtype=np.complex128)
+    for a, b, c, d in np.ndindex(2, 2, 2, 2):
+        v = op[2 * a + b, 2 * c + d]
+        if v == 0:
+            continue
+        m = np.ones((1, 1), dtype=np.complex128)
+        for i in range(1, nq + 1):
+            if i == is1:
+                f = np.zeros((2, 2)); f[a, c] = 1.0
+            elif i == is2:
+                f = np.zeros((2, 2)); f[b, d] = 1.0
+            else:
+                f = IDENTITY
+            m = np.kron(m, f)
+        out += v * m
+    return out
+
+
 def dense_circuit(nq, gates, marked):
     """Dense matrix of a gate list, built from Kronecker products (small n_q only)."""
     size = 1 << nq
@@ -393,6 +586,8 @@ def dense_circuit(nq, gates, marked):
         kind = g[0]
         if kind in ("H", "ONEOP", "D2"):
             m = kron_operator(nq, g[1], _gate_matrix(g))
+        elif kind in TWO_QUBIT:
+            m = kron_twoop(nq, g[1], g[2], _gate_matrix(g))
         elif kind == "HALL":
             m = np.ones((1, 1), dtype=np.complex128)
             for _ in range(nq):

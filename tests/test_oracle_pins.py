@@ -355,6 +355,121 @@ def test_unitary_norm_invariant_random_circuit():
     assert abs(norm - 1.0) < 1e-13
 
 
+# --------------------------------------------------------------------------- two-qubit gates
+
+
+def _rand_op4(rng, unitary=False):
+    m = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+    if unitary:
+        m, _ = np.linalg.qr(m)
+    return m
+
+
+@pytest.mark.parametrize("nq", [2, 3, 5])
+def test_twoop_matches_kronecker_sum(nq):
+    """Eq. resmat2 on the quartets against sum_{ab,cd} V_{ab;cd} |a><c| x |b><d| placed at
+    qubits is1, is2 (Kronecker products, no stride formula), every ordered qubit pair."""
+    rng = np.random.default_rng(400 + nq)
+    psi = _rand_state(rng, nq)
+    for is1 in range(1, nq + 1):
+        for is2 in range(1, nq + 1):
+            if is1 == is2:
+                continue
+            V = _rand_op4(rng)
+            got = O.apply_twoop(psi, nq, is1, is2, V)
+            np.testing.assert_allclose(got, O.kron_twoop(nq, is1, is2, V) @ psi, rtol=0, atol=1e-13)
+            np.testing.assert_allclose(got, O.apply_twoop_loop(psi, nq, is1, is2, V), rtol=0, atol=1e-13)
+
+
+def test_named_two_qubit_gates_on_basis_states():
+    """CNOT: control is1 flips is2; CPHASE: -1 on |11>; SWAP exchanges the qubits;
+    CPHASEK(1) = CPHASE, CPHASEK(2) puts i on |11> (Sec. 4.2, Eq. cphasek).  Bit-exact."""
+    nq = 4
+    for n in range(1 << nq):
+        e = np.zeros(1 << nq, dtype=np.complex128)
+        e[n] = 1.0
+        for is1, is2 in [(1, 3), (4, 2), (2, 3)]:
+            b1, b2 = (n >> (nq - is1)) & 1, (n >> (nq - is2)) & 1
+            f = np.zeros_like(e)
+            f[n ^ (b1 << (nq - is2))] = 1.0
+            assert np.array_equal(O.apply_gate(e, nq, ("CNOT", is1, is2), []), f)
+            assert np.array_equal(O.apply_gate(e, nq, ("CPHASE", is1, is2), []), e * (-1 if b1 and b2 else 1))
+            m = n & ~(1 << (nq - is1)) & ~(1 << (nq - is2)) | (b2 << (nq - is1)) | (b1 << (nq - is2))
+            g = np.zeros_like(e)
+            g[m] = 1.0
+            assert np.array_equal(O.apply_gate(e, nq, ("SWAP", is1, is2), []), g)
+    np.testing.assert_allclose(O.cphasek(1), O.CPHASE, rtol=0, atol=1e-15)  # e^{i pi} rounds
+    np.testing.assert_allclose(O.cphasek(2), np.diag([1, 1, 1, 1j]), atol=1e-16)
+
+
+def test_swap_is_three_cnots_and_operand_order():
+    """SWAP = CNOT(1,2) CNOT(2,1) CNOT(1,2) as circuits; V on (is1, is2) equals
+    SWAP V SWAP on (is2, is1): the basis order |q_is1 q_is2> is followed."""
+    rng = np.random.default_rng(402)
+    nq = 4
+    psi = _rand_state(rng, nq)
+    three = [("CNOT", 1, 3), ("CNOT", 3, 1), ("CNOT", 1, 3)]
+    np.testing.assert_allclose(O.evaluate(nq, three, [], psi)[0], O.apply_gate(psi, nq, ("SWAP", 1, 3), []),
+                               rtol=0, atol=1e-15)
+    V = _rand_op4(rng)
+    np.testing.assert_allclose(O.apply_twoop(psi, nq, 2, 4, V), O.apply_twoop(psi, nq, 4, 2, O.SWAP @ V @ O.SWAP),
+                               rtol=0, atol=1e-14)
+
+
+def test_wigner_functions():
+    """Wigner's formula for j = 1/2 gives the D2 reading R_z R_y R_z; for j = 3/2 it
+    equals exp(-i beta J_y) with J_y from the ladder operators; textbook entries
+    d_{3/2,3/2} = cos^3, d_{3/2,-3/2} = -sin^3, d_{1/2,1/2} = cos (3 cos^2 - 2)."""
+    import scipy.linalg as sl
+    for beta in (0.0, 0.4, 1.7, math.pi, 2.9):
+        np.testing.assert_allclose(O.wigner_d(1, 0.3, beta, -0.8), O.d2_matrix(0.3, beta, -0.8), atol=1e-15)
+        j, ms = 1.5, [1.5, 0.5, -0.5, -1.5]
+        jp = np.zeros((4, 4))
+        for r in range(1, 4):
+            jp[r - 1, r] = math.sqrt(j * (j + 1) - ms[r] * (ms[r] + 1))
+        jy = (jp - jp.T) / 2j
+        d = O.wigner_small_d(3, beta)
+        np.testing.assert_allclose(d, sl.expm(-1j * beta * jy), atol=1e-14)
+        c, s = math.cos(beta / 2), math.sin(beta / 2)
+        assert abs(d[0, 0] - c ** 3) < 1e-15 and abs(d[0, 3] + s ** 3) < 1e-15
+        assert abs(d[1, 1] - c * (3 * c * c - 2)) < 1e-15
+    D = O.d4_matrix(0.7, 1.3, -0.2)
+    np.testing.assert_allclose(D.conj().T @ D, np.eye(4), atol=1e-14)
+    np.testing.assert_allclose(O.d4_matrix(0.0, 0.0, 0.0), np.eye(4), atol=1e-15)
+    np.testing.assert_allclose(O.d4_matrix(0.9, 0.0, 0.0), np.diag(np.exp(-0.9j * np.array([1.5, 0.5, -0.5, -1.5]))),
+                               atol=1e-15)
+
+
+def test_d4_derivatives_against_differences():
+    a = (0.7, 1.3, -0.2)
+    h = 1e-6
+    for t, dm in enumerate(O.d4_derivatives(*a)):
+        up, dn = list(a), list(a)
+        up[t] += h
+        dn[t] -= h
+        np.testing.assert_allclose(dm, (O.d4_matrix(*up) - O.d4_matrix(*dn)) / (2 * h), atol=1e-9)
+
+
+def test_adjoint_with_two_qubit_gates_against_dense_and_differences():
+    rng = np.random.default_rng(404)
+    nq = 5
+    psi = _rand_state(rng, nq)
+    gates = [("HALL",), ("D4", 2, 4, 0.4, 1.2, 0.3), ("CNOT", 5, 1), ("TWOOP", 3, 2, _rand_op4(rng, True)),
+             ("D2", 3, 0.2, 0.9, -0.5), ("CPHASEK", 1, 4, 3), ("ORACLE",), ("SWAP", 2, 5), ("INV",),
+             ("D4", 5, 3, -1.1, 0.6, 2.0), ("CPHASE", 4, 3), ("HALL",)]
+    marked = [6, 19]
+    U = O.dense_circuit(nq, gates, marked)
+    P = np.zeros((1 << nq, 1 << nq))
+    for x in marked:
+        P[x, x] = 1.0
+    out, L, _ = O.evaluate(nq, gates, marked, psi)
+    np.testing.assert_allclose(out, U @ psi, rtol=0, atol=1e-13)
+    gpsi, gang = O.adjoint_grad(nq, gates, marked, psi, 0.7)
+    np.testing.assert_allclose(gpsi, 0.7 * 2.0 * U.conj().T @ P @ U @ psi, rtol=0, atol=1e-13)
+    assert gang.shape == (3, 3)
+    np.testing.assert_allclose(gang, 0.7 * O.fd_grad_angles(nq, gates, marked, psi), rtol=1e-7, atol=1e-10)
+
+
 # --------------------------------------------------------------------------- full-size route
 
 

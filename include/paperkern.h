@@ -56,6 +56,17 @@ extern "C" {
 #define PK_GATE_ORACLE 3 /* C_x -> -C_x for every x of the marked set (Sec. 5.1)          */
 #define PK_GATE_INV 4    /* C_n -> -C_n for n != 0 (Sec. 5.1, Eq. inversion)              */
 #define PK_GATE_D2 5     /* D^(1/2)(alpha, beta, gamma) on qubit is1 (Sec. 6.3)           */
+/* Two-qubit gates act on qubits is1, is2 (distinct) in the basis |q_is1 q_is2> =
+ * |00>, |01>, |10>, |11> of Sec. 4 (Eqs. twoopB, resmat2), whatever the order of
+ * is1 and is2 in significance.                                                        */
+#define PK_GATE_TWOOP 6   /* any 4x4 complex operator (Eq. resmat2, routine TwoOpA)          */
+#define PK_GATE_CNOT 7    /* control is1, target is2 (Sec. 4.2)                              */
+#define PK_GATE_CPHASE 8  /* diag(1, 1, 1, -1) (Sec. 4.2)                                    */
+#define PK_GATE_CPHASEK 9 /* diag(1, 1, 1, e^{2 pi i / 2^k}), k = 1..62 (Eq. cphasek)        */
+#define PK_GATE_SWAP 10   /* exchanges qubits is1 and is2 (the QFT reordering of App. A)     */
+#define PK_GATE_D4 11     /* D^(3/2)(alpha, beta, gamma), the two-qubit noise of Sec. 6.3:
+                             Wigner's j = 3/2 function with the D2 Euler convention, rows and
+                             columns m = 3/2 - (2 q_is1 + q_is2)                               */
 
 /* ---- workspace queries ----------------------------------------------------------- */
 #define PK_OP_EVAL 0
@@ -65,11 +76,13 @@ typedef struct pk_gate {
     int32_t kind;     /* PK_GATE_*                                                        */
     int32_t is1;      /* target qubit, 1..n_q (1 = most significant); ignored for
                          HALL, ORACLE and INV                                             */
-    int32_t is2;      /* reserved for two-qubit gates; must be 0                          */
-    int32_t k;        /* reserved; must be 0                                              */
-    double op[8];     /* ONEOP only: row-major 2x2 complex, op[2*(2a+b)] = Re<a|Op|b>,
-                         op[2*(2a+b)+1] = Im<a|Op|b>; entries must be finite              */
-    double angle[3];  /* D2 only: alpha, beta, gamma (radians, finite)                    */
+    int32_t is2;      /* second qubit of a two-qubit gate, 1..n_q, != is1; else 0         */
+    int32_t k;        /* CPHASEK only: the exponent k (1..62); else 0                      */
+    double op[32];    /* ONEOP: row-major 2x2 complex in op[0..7], op[2*(2a+b)] = Re<a|Op|b>,
+                         op[2*(2a+b)+1] = Im<a|Op|b>; TWOOP: row-major 4x4 complex in
+                         op[0..31], op[2*(4a+b)] = Re<a|V|b> with a, b = 2 q_is1 + q_is2;
+                         entries must be finite                                           */
+    double angle[3];  /* D2 and D4: alpha, beta, gamma (radians, finite)                  */
 } pk_gate;
 
 typedef struct pk_problem {
@@ -167,8 +180,9 @@ int pk_plan_describe(const pk_plan* plan, char* buf, int64_t cap, int64_t* neede
  * offsets[i] = sum_{j<i} 2^nq_j; states of a batch lie back to back in that order. */
 int pk_plan_offsets(const pk_plan* plan, int64_t* offsets);
 
-/* Number of D2 gates over all instances (instance order, then gate order); the
- * angle arrays below hold 3 doubles (alpha, beta, gamma) per D2 gate. */
+/* Number of rotation gates (D2 and D4) over all instances (instance order, then
+ * gate order); the angle arrays below hold 3 doubles (alpha, beta, gamma) per
+ * rotation gate in that order. */
 int pk_plan_n_angles(const pk_plan* plan, int64_t* n_d2);
 
 /*
@@ -184,7 +198,8 @@ int pk_workspace_bytes(const pk_plan* plan, int32_t op, int64_t* bytes);
  *   psi_out  device, 2^nq complex, written
  *   L_out    device double[1]: L = sum_{x in M} |C~_x|^2 (FP64 final combine)
  *   norm_out device double[1] or NULL: sum_n |C~_n|^2 (diagnostic)
- *   angles   device double[3 * n_d2] or NULL (NULL = the angles given to pk_create)
+ *   angles   device double[3 * n_rot] or NULL (n_rot = D2 and D4 gates; NULL = the
+ *            angles given to pk_create)
  *   workspace device, >= pk_workspace_bytes(PK_OP_EVAL)
  * The launches are captured once into a hipGraph per pointer set and replayed.
  * Errors: PK_EINVAL (NULL/misaligned pointer, batched plan), PK_EDEVICE.
@@ -209,11 +224,13 @@ int pk_evaluate_batched(pk_plan* plan, const void* psi_in, void* psi_out, double
  *   psi_out     device, read
  *   dL          device double[n_inst]
  *   grad_psi_in device complex, written: Re = dL/dRe psi_in, Im = dL/dIm psi_in
- *   grad_angles device double[3 * n_d2] or NULL, written (d/dalpha, d/dbeta, d/dgamma)
- *   angles      device double[3 * n_d2] or NULL, as for pk_evaluate
+ *   grad_angles device double[3 * n_rot] or NULL, written (d/dalpha, d/dbeta, d/dgamma
+ *               per D2 or D4 gate)
+ *   angles      device double[3 * n_rot] or NULL, as for pk_evaluate
  *   workspace   device, >= pk_workspace_bytes(PK_OP_BACKWARD)
- * Single-instance plans only.  PK_EUNSUPPORTED when an ONEOP gate is not
- * unitary (its inverse is then not its adjoint and the state cannot be walked back).
+ * Single-instance plans only.  PK_EUNSUPPORTED when a ONEOP or TWOOP gate is
+ * not unitary (its inverse is then not its adjoint and the state cannot be
+ * walked back).
  */
 int pk_backward(pk_plan* plan, const void* psi_out, const double* dL, void* grad_psi_in,
                 double* grad_angles, const double* angles, void* workspace, void* stream);

@@ -109,6 +109,8 @@ int ensure_device(DevPlan* d) {
     put(buf, t.flips, P.flips);
     put(buf, t.mats, P.static_mats);
     put(buf, t.mats + P.static_mats.size() * sizeof(double), P.default_angles);
+    put(buf, t.mats4, P.static_mats4);
+    put(buf, t.params, P.params);
     put(buf, t.idesc, P.idesc);
     put(buf, t.order, P.team.solo);
     put(buf, t.team_off, P.team.team_off);
@@ -158,6 +160,7 @@ PassLaunch base_launch(DevPlan* d, void* ws, int op) {
     L.stages = at<Stage>(P.d_tables, t.stages);
     L.flips = at<Flip>(P.d_tables, t.flips);
     L.mats = at<double>(ws, w.mats);
+    L.mats4 = at<double>(ws, w.mats4);
     L.partials = at<double>(ws, w.partials);
     L.reads = at<double>(ws, w.reads);
     L.gpart = at<double>(ws, w.gpart);
@@ -175,8 +178,19 @@ hipError_t enqueue_prep(DevPlan* d, void* ws, const double* angles, int op, int 
     Plan& P = d->host;
     TableLayout t = table_layout(&P);
     WsLayout w = workspace_layout(&P, op);
-    return launch_prep(at<double>(ws, w.mats), at<double>(P.d_tables, t.mats), P.n_static, angle_src(d, angles),
-                       P.n_d2, at<unsigned int>(ws, w.counters), n_counters, st);
+    PrepArgs p{};
+    p.mats = at<double>(ws, w.mats);
+    p.smats = at<double>(P.d_tables, t.mats);
+    p.n_smats = (int32_t)P.static_mats.size();
+    p.mats4 = at<double>(ws, w.mats4);
+    p.smats4 = at<double>(P.d_tables, t.mats4);
+    p.n_smats4 = (int32_t)P.static_mats4.size();
+    p.angles = angle_src(d, angles);
+    p.params = at<ParamRef>(P.d_tables, t.params);
+    p.n_params = (int32_t)P.params.size();
+    p.counters = at<unsigned int>(ws, w.counters);
+    p.n_counters = n_counters;
+    return launch_prep(p, st);
 }
 
 // Evaluation of a single-instance plan: prep, every forward pass, final combine.
@@ -320,6 +334,31 @@ int check_eval_args(DevPlan* d, const void* psi_in, void* psi_out, double* L_out
     return PK_OK;
 }
 
+
+// Re-compiles after a tiling or launch change; on failure the previous
+// settings and schedule come back, so the plan stays usable.
+int recompile_or_restore(DevPlan* d, const Tiling& previous) {
+    std::string err;
+    int rc;
+    try {
+        rc = recompile(&d->host, &err);
+    } catch (const std::bad_alloc&) {
+        rc = PK_ENOMEM;
+        err = "out of host memory";
+    } catch (...) {
+        rc = PK_EINVAL;
+        err = "plan compilation failed";
+    }
+    if (rc == PK_OK) return PK_OK;
+    d->host.tiling = previous;
+    std::string ignored;
+    try {
+        recompile(&d->host, &ignored);
+    } catch (...) {
+    }
+    return fail(d, rc, err);
+}
+
 }  // namespace
 
 extern "C" {
@@ -359,17 +398,11 @@ int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_
     if (fuse != 0 && fuse != 1) return fail(d, PK_EINVAL, "fuse must be 0 or 1");
     if (lane_order != 0 && lane_order != 1) return fail(d, PK_EINVAL, "lane_order must be 0 or 1");
     if (page_cap < -1 || page_cap > 16) return fail(d, PK_EINVAL, "page_cap must be -1..16");
+    const Tiling previous = d->host.tiling;
     d->host.tiling = Tiling{tile_bits, carrier_bits, fuse, d->host.tiling.wgs_per_cu, d->host.tiling.reg_bits,
                             lane_order, page_cap < 0 ? default_page_cap(d->host.prec) : page_cap};
     drop_device(d);
-    std::string err;
-    try {
-        int rc = recompile(&d->host, &err);
-        if (rc != PK_OK) return fail(d, rc, err);
-    } catch (const std::bad_alloc&) {
-        return fail(d, PK_ENOMEM, "out of host memory");
-    }
-    return PK_OK;
+    return recompile_or_restore(d, previous);
 }
 
 int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu, int32_t reg_bits) {
@@ -379,20 +412,14 @@ int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu, int32_t reg_bits) {
     if (reg_bits != 0 && reg_bits != 4 && reg_bits != 5) return fail(d, PK_EINVAL, "reg_bits must be 0, 4 or 5");
     const int rb = reg_bits == 0 ? default_reg_bits(d->host.prec) : reg_bits;
     const bool recompile_needed = rb != d->host.tiling.reg_bits;
+    const Tiling previous = d->host.tiling;
     d->host.tiling.wgs_per_cu = wgs_per_cu;
     d->host.tiling.reg_bits = rb;
     if (recompile_needed) {
         drop_device(d);
-        std::string err;
-        try {
-            int rc = recompile(&d->host, &err);
-            if (rc != PK_OK) return fail(d, rc, err);
-        } catch (const std::bad_alloc&) {
-            return fail(d, PK_ENOMEM, "out of host memory");
-        }
-    } else {
-        drop_graphs(d);
+        return recompile_or_restore(d, previous);
     }
+    drop_graphs(d);
     return PK_OK;
 }
 
@@ -446,7 +473,7 @@ int pk_plan_offsets(const pk_plan* plan, int64_t* offsets) {
 
 int pk_plan_n_angles(const pk_plan* plan, int64_t* n_d2) {
     if (!valid(plan) || !n_d2) return fail(nullptr, PK_EINVAL, "invalid argument");
-    *n_d2 = dp(plan)->host.n_d2;
+    *n_d2 = (int64_t)dp(plan)->host.params.size();
     return PK_OK;
 }
 

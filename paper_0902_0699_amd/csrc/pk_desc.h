@@ -29,16 +29,18 @@ enum OpKind : int32_t {
     OP_READ = 4,   // reads[flips[arg].slot] = |C|^2 of the amplitude flips[arg]
     OP_SEED = 5,   // lambda = dL * psi at the amplitude flips[arg] (backward start)
     OP_D2BWD = 6,  // backward D2: psi <- D^H psi, grad += Re<lambda|dD|psi>, lambda <- D^H lambda
+    OP_MAT4 = 7,   // 4x4 complex matrix mats4[arg] on register bits 0 (qubit is1) and 1 (qubit is2)
+    OP_D4BWD = 8,  // backward D4 on register bits 0 and 1, as OP_D2BWD with 4x4 matrices
 };
 
 // One step of a stage's op list, as the plan compiler schedules it on the host;
 // the list is then packed into sub-stages (Stage) for the device.
 struct Op {
     int32_t kind;
-    int32_t a;      // register bit 0..3 for OP_H / OP_MAT / OP_D2BWD
-    int32_t arg;    // matrix index (OP_MAT, OP_D2BWD: first of its five), flip index (FLIP/READ/SEED)
-    int32_t gslot;  // OP_D2BWD: base of this gate's gradient partials
-    float gscale;   // OP_D2BWD: 1/s^2 for the deferred scale s carried at that point
+    int32_t a;      // register bit for OP_H / OP_MAT / OP_D2BWD
+    int32_t arg;    // matrix index (OP_MAT, OP_MAT4; D2BWD, D4BWD: first of five), flip index (FLIP/READ/SEED)
+    int32_t gslot;  // OP_D2BWD, OP_D4BWD: base of this gate's gradient partials
+    float gscale;   // OP_D2BWD, OP_D4BWD: 1/s^2 for the deferred scale s carried at that point
     int32_t pad;
 };
 
@@ -47,7 +49,7 @@ struct Op {
 //
 // One sub-stage: a fixed sequence of optional steps applied to the registers,
 // in this order: seed, flip, matrix, Hadamards (mask 1), flip, Hadamards
-// (mask 2), matrix, backward D2, scale, read.  A stage's op list is packed into
+// (mask 2), matrix, 4x4 matrix, backward D2, backward D4, scale, read.  A stage's op list is packed into
 // as many sub-stages as its order needs; only the first of them exchanges the
 // tile through LDS (`exchange`), the others keep the layout.  Straight-line
 // steps instead of an op loop let the compiler update the register tile in
@@ -69,6 +71,10 @@ struct Stage {
     int32_t d2b_mat;          // first of its five matrices
     int32_t d2b_gslot;        // base of its gradient partials
     float d2b_gscale;         // 1/s^2 for the deferred scale s at that point
+    int32_t mat4;             // 4x4 matrix on register bits 0 (qubit is1) and 1 (qubit is2), or -1
+    int32_t d4b_mat;          // backward D4 on register bits 0 and 1: first of its five matrices, or -1
+    int32_t d4b_gslot;
+    float d4b_gscale;
     int32_t scale;            // 1: multiply by the pass scale
     int32_t read;             // flip index of a READ or -1
     int32_t pad;
@@ -117,6 +123,13 @@ struct Pass {
 
 // Per-instance entry of a batched launch: one workgroup runs all passes of
 // one instance, so no two workgroups ever depend on each other.
+// A rotation parameter triple (alpha, beta, gamma) of the angle array: kind 0
+// is a D2 gate (five 2x2 matrices at slot), kind 1 a D4 gate (five 4x4 matrices).
+struct ParamRef {
+    int32_t kind;
+    int32_t slot;
+};
+
 struct InstDesc {
     int32_t first_pass;
     int32_t npass;

@@ -41,6 +41,7 @@ struct KArgs {
     const Stage* stages;
     const Flip* flips;
     const double* mats;
+    const double* mats4;  // 4x4 complex matrices of two-qubit gates, 32 doubles each
     const void* src0;  // vector 0 input of the first pass
     void* dst0;        // vector 0 output (and input of later passes)
     void* dst1;        // vector 1 (lambda) in/out, backward only
@@ -213,6 +214,77 @@ __device__ __forceinline__ void op_d2bwd(T (&v)[NV][NR], const R (&mh)[8], const
 #pragma unroll
         for (int i = 0; i < NR; ++i)
             if (!(i & (1 << A))) pair_mat(v[1][i], v[1][i | (1 << A)], mh);
+    }
+}
+
+// A two-qubit gate on register bits 0 (qubit is1) and 1 (qubit is2): the
+// registers i, i+2, i+1, i+3 (i = 0 mod 4) hold the amplitude quartet
+// |q_is1 q_is2> = |00>, |01>, |10>, |11> of one n_00 (Eqs. twoopB, resmat2) and
+// are replaced by M times it.  M is row-major complex (32 doubles), read row by
+// row through scalar loads.
+template <typename T>
+__device__ __forceinline__ void quartet_mat(T& x0, T& x1, T& x2, T& x3, const PK_CONST double* m) {
+    using R = decltype(x0.x);
+    const T in[4] = {x0, x1, x2, x3};
+    T out[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        R re = 0, im = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const R mr = (R)m[2 * (4 * r + c)], mi = (R)m[2 * (4 * r + c) + 1];
+            re += mr * in[c].x - mi * in[c].y;
+            im += mr * in[c].y + mi * in[c].x;
+        }
+        out[r].x = re;
+        out[r].y = im;
+    }
+    x0 = out[0];
+    x1 = out[1];
+    x2 = out[2];
+    x3 = out[3];
+}
+
+template <int NV, int NR, typename T>
+__device__ __forceinline__ void op_mat4(T (&v)[NV][NR], const PK_CONST double* m) {
+#pragma unroll
+    for (int n = 0; n < NV; ++n)
+#pragma unroll
+        for (int i = 0; i < NR; i += 4) quartet_mat(v[n][i], v[n][i + 2], v[n][i + 1], v[n][i + 3], m);
+}
+
+// Backward step through a D4 gate, as op_d2bwd with 4x4 matrices: psi <- D^H psi;
+// for every angle g += Re( conj(lambda) . (dD/dtheta) psi ); lambda <- D^H lambda.
+// `m` holds D, D^H, dD/dalpha, dD/dbeta, dD/dgamma (32 doubles each).
+template <int NV, int NR, typename T>
+__device__ __forceinline__ void op_d4bwd(T (&v)[NV][NR], const PK_CONST double* m, double (&g)[3]) {
+    if constexpr (NV == 2) {
+#pragma unroll
+        for (int i = 0; i < NR; i += 4) quartet_mat(v[0][i], v[0][i + 2], v[0][i + 1], v[0][i + 3], m + 32);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const PK_CONST double* dm = m + 64 + 32 * t;
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < NR; i += 4) {
+                const int idx[4] = {i, i + 2, i + 1, i + 3};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double re = 0.0, im = 0.0;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const double mr = dm[2 * (4 * r + c)], mi = dm[2 * (4 * r + c) + 1];
+                        const double px = v[0][idx[c]].x, py = v[0][idx[c]].y;
+                        re += mr * px - mi * py;
+                        im += mr * py + mi * px;
+                    }
+                    acc += (double)v[1][idx[r]].x * re + (double)v[1][idx[r]].y * im;
+                }
+            }
+            g[t] += acc;
+        }
+#pragma unroll
+        for (int i = 0; i < NR; i += 4) quartet_mat(v[1][i], v[1][i + 2], v[1][i + 1], v[1][i + 3], m + 32);
     }
 }
 
@@ -455,6 +527,7 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
             for (int e = 0; e < 8; ++e) m[e] = (R)mp[e];
             apply_mat<NV, NR>(v, S->mat_post_a, m);
         }
+        if (S->mat4 >= 0 && active) op_mat4<NV, NR>(v, cptr(a.mats4) + 32 * S->mat4);
         if constexpr (NV == 2) {
             if (S->d2b_a >= 0) {
                 R mh[8];
@@ -465,6 +538,17 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
                 if (active) apply_d2bwd<NV, NR>(v, S->d2b_a, mh, mp + 16, g);
                 const double scale = 2.0 * (double)S->d2b_gscale;
                 const int gslot = S->d2b_gslot;
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    const double tot = block_sum<NT>(g[t], red);
+                    if (tid == 0) a.gpart[gslot + t * P->ntiles + tile] = scale * tot;
+                }
+            }
+            if (S->d4b_mat >= 0) {
+                double g[3] = {0.0, 0.0, 0.0};
+                if (active) op_d4bwd<NV, NR>(v, cptr(a.mats4) + 32 * S->d4b_mat, g);
+                const double scale = 2.0 * (double)S->d4b_gscale;
+                const int gslot = S->d4b_gslot;
 #pragma unroll
                 for (int t = 0; t < 3; ++t) {
                     const double tot = block_sum<NT>(g[t], red);
@@ -679,39 +763,87 @@ __global__ void __launch_bounds__(1 << (KMAX - RB)) batched_kernel(KArgs a, Batc
     }
 }
 
-// Copies the static operators and builds the D2 matrices from the angles:
-// per D2 gate five matrices D, D^H, dD/dalpha, dD/dbeta, dD/dgamma with
+// D^(1/2): five 2x2 matrices D, D^H, dD/dalpha, dD/dbeta, dD/dgamma with
 // D = R_z(alpha) R_y(beta) R_z(gamma) written out element by element.
-__global__ void prep_kernel(double* mats, const double* smats, int32_t n_static, const double* angles,
-                            int32_t n_d2, unsigned int* counters, int32_t n_counters) {
+__device__ void build_d2(double* m, double al, double be, double ga) {
+    double c, s, cp, sp, cm, sm;
+    sincos(0.5 * be, &s, &c);
+    sincos(0.5 * (al + ga), &sp, &cp);  // e^{i(al+ga)/2}
+    sincos(0.5 * (al - ga), &sm, &cm);  // e^{i(al-ga)/2}
+    // D00 = e^{-i(a+g)/2} c, D01 = -e^{-i(a-g)/2} s, D10 = e^{i(a-g)/2} s, D11 = e^{i(a+g)/2} c
+    const double D[8] = {cp * c, -sp * c, -cm * s, sm * s, cm * s, sm * s, cp * c, sp * c};
+    for (int e = 0; e < 8; ++e) m[e] = D[e];
+    // D^H[a][b] = conj(D[b][a])
+    const double H[8] = {D[0], -D[1], D[4], -D[5], D[2], -D[3], D[6], -D[7]};
+    for (int e = 0; e < 8; ++e) m[8 + e] = H[e];
+    // dD/dalpha = diag(-i/2, i/2) D : row 0 times -i/2, row 1 times i/2
+    const double Da[8] = {0.5 * D[1], -0.5 * D[0], 0.5 * D[3], -0.5 * D[2],
+                          -0.5 * D[5], 0.5 * D[4], -0.5 * D[7], 0.5 * D[6]};
+    for (int e = 0; e < 8; ++e) m[16 + e] = Da[e];
+    // dD/dbeta: c -> -s/2 and s -> c/2 in every element
+    const double Db[8] = {-0.5 * cp * s, 0.5 * sp * s, -0.5 * cm * c, 0.5 * sm * c,
+                          0.5 * cm * c, 0.5 * sm * c, -0.5 * cp * s, -0.5 * sp * s};
+    for (int e = 0; e < 8; ++e) m[24 + e] = Db[e];
+    // dD/dgamma = D diag(-i/2, i/2) : column 0 times -i/2, column 1 times i/2
+    const double Dg[8] = {0.5 * D[1], -0.5 * D[0], -0.5 * D[3], 0.5 * D[2],
+                          0.5 * D[5], -0.5 * D[4], -0.5 * D[7], 0.5 * D[6]};
+    for (int e = 0; e < 8; ++e) m[32 + e] = Dg[e];
+}
+
+// D^(3/2): five 4x4 matrices.  D_{m'm} = e^{-i m' alpha} d_{m'm}(beta) e^{-i m gamma}
+// on rows/columns m = 3/2, 1/2, -1/2, -3/2, with the j = 3/2 small-d entries in
+// c = cos(beta/2), s = sin(beta/2) and their beta derivatives written out.
+__device__ void build_d4(double* m, double al, double be, double ga) {
+    double s, c;
+    sincos(0.5 * be, &s, &c);
+    const double r3 = 1.7320508075688772;  // sqrt(3)
+    const double c2 = c * c, s2 = s * s, c3 = c2 * c, s3 = s2 * s;
+    const double d[16] = {c3,           -r3 * c2 * s,       r3 * c * s2,        -s3,
+                          r3 * c2 * s,  c3 - 2.0 * c * s2,  s3 - 2.0 * c2 * s,  r3 * c * s2,
+                          r3 * c * s2,  2.0 * c2 * s - s3,  c3 - 2.0 * c * s2,  -r3 * c2 * s,
+                          s3,           r3 * c * s2,        r3 * c2 * s,        c3};
+    const double u = r3 * (0.5 * c3 - c * s2);   // d/dbeta of r3 c^2 s
+    const double w = r3 * (c2 * s - 0.5 * s3);   // d/dbeta of r3 c s^2
+    const double dd[16] = {-1.5 * c2 * s,  -u,                    w,                     -1.5 * c * s2,
+                           u,              -3.5 * c2 * s + s3,    3.5 * c * s2 - c3,     w,
+                           w,              c3 - 3.5 * c * s2,     -3.5 * c2 * s + s3,    -u,
+                           1.5 * c * s2,   w,                     u,                     -1.5 * c2 * s};
+    const double mq[4] = {1.5, 0.5, -0.5, -1.5};
+    for (int r = 0; r < 4; ++r)
+        for (int col = 0; col < 4; ++col) {
+            double sn, cs;
+            sincos(mq[r] * al + mq[col] * ga, &sn, &cs);  // e^{-i phi} = cs - i sn
+            const int e = 2 * (4 * r + col);
+            const double Dr = d[4 * r + col] * cs, Di = -d[4 * r + col] * sn;
+            m[e] = Dr;
+            m[e + 1] = Di;
+            // D^H[col][r] = conj(D[r][col])
+            m[32 + 2 * (4 * col + r)] = Dr;
+            m[32 + 2 * (4 * col + r) + 1] = -Di;
+            // dD/dalpha = -i m' D, dD/dgamma = -i m D: (-i k)(x + i y) = k y - i k x
+            m[64 + e] = mq[r] * Di;
+            m[64 + e + 1] = -mq[r] * Dr;
+            m[96 + e] = dd[4 * r + col] * cs;
+            m[96 + e + 1] = -dd[4 * r + col] * sn;
+            m[128 + e] = mq[col] * Di;
+            m[128 + e + 1] = -mq[col] * Dr;
+        }
+}
+
+// Copies the static operators (2x2 and 4x4) into the workspace, clears the
+// launch counters, and builds every rotation's five matrices from its angles.
+__global__ void prep_kernel(PrepArgs p) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n_counters) counters[t] = 0u;
-    if (t < 16 * n_static) mats[t] = smats[t];
-    if (t < n_d2) {
-        const double al = angles[3 * t], be = angles[3 * t + 1], ga = angles[3 * t + 2];
-        double c, s, cp, sp, cm, sm;
-        sincos(0.5 * be, &s, &c);
-        sincos(0.5 * (al + ga), &sp, &cp);  // e^{i(al+ga)/2}
-        sincos(0.5 * (al - ga), &sm, &cm);  // e^{i(al-ga)/2}
-        double* m = mats + 16 * n_static + 40 * t;
-        // D00 = e^{-i(a+g)/2} c, D01 = -e^{-i(a-g)/2} s, D10 = e^{i(a-g)/2} s, D11 = e^{i(a+g)/2} c
-        const double D[8] = {cp * c, -sp * c, -cm * s, sm * s, cm * s, sm * s, cp * c, sp * c};
-        for (int e = 0; e < 8; ++e) m[e] = D[e];
-        // D^H[a][b] = conj(D[b][a])
-        const double H[8] = {D[0], -D[1], D[4], -D[5], D[2], -D[3], D[6], -D[7]};
-        for (int e = 0; e < 8; ++e) m[8 + e] = H[e];
-        // dD/dalpha = diag(-i/2, i/2) D : row 0 times -i/2, row 1 times i/2
-        const double Da[8] = {0.5 * D[1], -0.5 * D[0], 0.5 * D[3], -0.5 * D[2],
-                              -0.5 * D[5], 0.5 * D[4], -0.5 * D[7], 0.5 * D[6]};
-        for (int e = 0; e < 8; ++e) m[16 + e] = Da[e];
-        // dD/dbeta: c -> -s/2 and s -> c/2 in every element
-        const double Db[8] = {-0.5 * cp * s, 0.5 * sp * s, -0.5 * cm * c, 0.5 * sm * c,
-                              0.5 * cm * c, 0.5 * sm * c, -0.5 * cp * s, -0.5 * sp * s};
-        for (int e = 0; e < 8; ++e) m[24 + e] = Db[e];
-        // dD/dgamma = D diag(-i/2, i/2) : column 0 times -i/2, column 1 times i/2
-        const double Dg[8] = {0.5 * D[1], -0.5 * D[0], -0.5 * D[3], 0.5 * D[2],
-                              0.5 * D[5], -0.5 * D[4], -0.5 * D[7], 0.5 * D[6]};
-        for (int e = 0; e < 8; ++e) m[32 + e] = Dg[e];
+    if (t < p.n_counters) p.counters[t] = 0u;
+    if (t < p.n_smats) p.mats[t] = p.smats[t];
+    if (t < p.n_smats4) p.mats4[t] = p.smats4[t];
+    if (t < p.n_params) {
+        const ParamRef r = p.params[t];
+        const double al = p.angles[3 * t], be = p.angles[3 * t + 1], ga = p.angles[3 * t + 2];
+        if (r.kind == 0)
+            build_d2(p.mats + p.n_smats + 40 * r.slot, al, be, ga);
+        else
+            build_d4(p.mats4 + p.n_smats4 + 160 * r.slot, al, be, ga);
     }
 }
 
@@ -800,6 +932,7 @@ static KArgs kargs(const PassLaunch& L) {
     a.stages = L.stages;
     a.flips = L.flips;
     a.mats = L.mats;
+    a.mats4 = L.mats4;
     a.src0 = L.src0;
     a.dst0 = L.dst0;
     a.dst1 = L.dst1;
@@ -891,14 +1024,13 @@ int batched_blocks_per_cu(int kmax, int rbits, bool fp64) {
     return fp64 ? batched_occupancy_r<double, 4>(kmax) : batched_occupancy_r<float, 4>(kmax);
 }
 
-hipError_t launch_prep(double* mats, const double* smats, int n_static, const double* angles, int n_d2,
-                       unsigned int* counters, int n_counters, hipStream_t st) {
-    int n = 16 * n_static;
-    if (n_d2 > n) n = n_d2;
-    if (n_counters > n) n = n_counters;
+hipError_t launch_prep(const PrepArgs& p, hipStream_t st) {
+    int n = p.n_smats;
+    if (p.n_smats4 > n) n = p.n_smats4;
+    if (p.n_params > n) n = p.n_params;
+    if (p.n_counters > n) n = p.n_counters;
     if (n < 1) n = 1;
-    hipLaunchKernelGGL(prep_kernel, dim3((n + 255) / 256), dim3(256), 0, st, mats, smats, n_static, angles,
-                       n_d2, counters, n_counters);
+    hipLaunchKernelGGL(prep_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p);
     return hipGetLastError();
 }
 

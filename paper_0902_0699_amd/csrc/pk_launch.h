@@ -12,6 +12,7 @@ struct PassLaunch {
     const Stage* stages;
     const Flip* flips;
     const double* mats;
+    const double* mats4;
     const void* src0;
     void* dst0;
     void* dst1;
@@ -50,8 +51,25 @@ hipError_t launch_pass(const PassLaunch& L, hipStream_t st);
 hipError_t launch_batched(const PassLaunch& L, const BatchArgs& B, unsigned grid, hipStream_t st);
 // Resident workgroups per CU of the batched kernel instance (0 if unknown).
 int batched_blocks_per_cu(int kmax, int rbits, bool fp64);
-hipError_t launch_prep(double* mats, const double* smats, int n_static, const double* angles, int n_d2,
-                       unsigned int* counters, int n_counters, hipStream_t st);
+// Workspace matrices for one launch: the static 2x2 and 4x4 operators are
+// copied, then each rotation's five matrices are built after them
+// (D2: 40 doubles at mats + n_smats + 40 * slot; D4: 160 doubles at
+// mats4 + n_smats4 + 160 * slot); n_counters launch counters are cleared.
+struct PrepArgs {
+    double* mats;
+    const double* smats;
+    int32_t n_smats;  // doubles
+    double* mats4;
+    const double* smats4;
+    int32_t n_smats4;  // doubles
+    const double* angles;
+    const ParamRef* params;
+    int32_t n_params;
+    unsigned int* counters;
+    int32_t n_counters;
+};
+
+hipError_t launch_prep(const PrepArgs& p, hipStream_t st);
 hipError_t launch_reduce(const Reduction* red, int n, const double* ws, double* L_out, double* norm_out,
                          double* grad_out, hipStream_t st);
 hipError_t launch_pairs(int nq, int i_s, int64_t first, int64_t count, int64_t* n0, int64_t* n1,

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <map>
 #include <set>
+#include <stdexcept>
 #include <string>
 
 namespace pk {
@@ -49,17 +50,41 @@ bool is_unitary(const double* m) {
     return true;
 }
 
+bool is_unitary4(const double* m) {
+    // m row-major complex 4x4; check M^H M = I
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            double re = 0, im = 0;
+            for (int r = 0; r < 4; ++r) {
+                const double ar = m[2 * (4 * r + i)], ai = m[2 * (4 * r + i) + 1];
+                const double br = m[2 * (4 * r + j)], bi = m[2 * (4 * r + j) + 1];
+                re += ar * br + ai * bi;
+                im += ar * bi - ai * br;
+            }
+            if (std::fabs(re - (i == j ? 1.0 : 0.0)) > 1e-12 || std::fabs(im) > 1e-12) return false;
+        }
+    return true;
+}
+
 // Forward scan: which not-yet-scheduled primitives can run in a pass (or stage)
 // whose register/tile bit set is `in_set`.  A gate is blocked by an earlier
-// unscheduled gate on the same bit or an earlier unscheduled diagonal op; a
-// diagonal op is blocked by any earlier unscheduled gate.
+// unscheduled gate on one of its bits or an earlier unscheduled diagonal op; a
+// diagonal op is blocked by any earlier unscheduled gate.  Two-qubit gates
+// need both bits in the set; `pair` further restricts them: PAIR_ANY (tiles),
+// PAIR_NONE (a stage without two-qubit gates), or (b1 << 8 | b2), the one
+// ordered pair a stage holds on register bits 0 and 1.
+constexpr int PAIR_ANY = -1;
+constexpr int PAIR_NONE = -2;
+
 struct ScanItem {
     bool diag;
     int bit;
+    int bit2;  // second bit of a two-qubit gate, -1 otherwise
 };
 
 int scan(const std::vector<ScanItem>& items, const std::vector<char>& done,
-         const std::vector<char>& in_set, int nbits, int max_gates, std::vector<int>* out) {
+         const std::vector<char>& in_set, int nbits, int max_gates, std::vector<int>* out,
+         int pair = PAIR_ANY) {
     std::vector<char> blocked(nbits, 0);
     bool blocked_gate = false, blocked_diag = false;
     int count = 0, gates = 0;
@@ -74,19 +99,33 @@ int scan(const std::vector<ScanItem>& items, const std::vector<char>& done,
                 blocked_diag = true;
             }
         } else {
+            const bool two = it.bit2 >= 0;
             bool ok = !blocked[it.bit] && !blocked_diag && in_set[it.bit] &&
                       (max_gates < 0 || gates < max_gates);
+            if (two)
+                ok = ok && !blocked[it.bit2] && in_set[it.bit2] && pair != PAIR_NONE &&
+                     (pair == PAIR_ANY || pair == ((it.bit << 8) | it.bit2));
             if (ok) {
                 ++count;
                 ++gates;
                 if (out) out->push_back((int)i);
             } else {
                 blocked[it.bit] = 1;
+                if (two) blocked[it.bit2] = 1;
                 blocked_gate = true;
             }
         }
     }
     return count;
+}
+
+// Pending two-qubit gates with exactly one bit in the set: a tie-break that
+// lets a greedy bit choice complete pairs (adding one bit alone enables none).
+int half_pairs(const std::vector<ScanItem>& items, const std::vector<char>& done, const std::vector<char>& in_set) {
+    int c = 0;
+    for (size_t i = 0; i < items.size(); ++i)
+        if (!done[i] && items[i].bit2 >= 0 && (in_set[items[i].bit] != in_set[items[i].bit2])) ++c;
+    return c;
 }
 
 struct ScaleState {
@@ -104,7 +143,9 @@ int64_t extract(int64_t x, const std::vector<int>& bits) {
 // their order: each goes to the first free slot at or after the previous op's
 // slot, and a new sub-stage (same layout, no exchange) starts when none fits.
 // Hadamards collected in one mask act on distinct register bits and commute.
-enum Slot { S_SEED = 0, S_FLIP_PRE, S_MAT_PRE, S_H1, S_FLIP_MID, S_H2, S_MAT_POST, S_D2B, S_SCALE, S_READ };
+enum Slot {
+    S_SEED = 0, S_FLIP_PRE, S_MAT_PRE, S_H1, S_FLIP_MID, S_H2, S_MAT_POST, S_MAT4, S_D2B, S_D4B, S_SCALE, S_READ
+};
 
 Stage blank_sub(const HostStage& hs, int exchange) {
     Stage s{};
@@ -118,6 +159,7 @@ Stage blank_sub(const HostStage& hs, int exchange) {
     s.exchange = exchange;
     s.seed = s.flip_pre = s.flip_mid = s.read = -1;
     s.mat_pre_a = s.mat_post_a = s.d2b_a = -1;
+    s.mat4 = s.d4b_mat = -1;
     return s;
 }
 
@@ -142,6 +184,15 @@ int place(Stage& s, int cursor, const Op& o) {
         if (cursor <= S_D2B && s.d2b_a < 0) {
             s.d2b_a = o.a; s.d2b_mat = o.arg; s.d2b_gslot = o.gslot; s.d2b_gscale = o.gscale;
             return S_D2B;
+        }
+        return -1;
+    case OP_MAT4:
+        if (cursor <= S_MAT4 && s.mat4 < 0) { s.mat4 = o.arg; return S_MAT4; }
+        return -1;
+    case OP_D4BWD:
+        if (cursor <= S_D4B && s.d4b_mat < 0) {
+            s.d4b_mat = o.arg; s.d4b_gslot = o.gslot; s.d4b_gscale = o.gscale;
+            return S_D4B;
         }
         return -1;
     case OP_SCALE:
@@ -202,7 +253,8 @@ struct Compiler {
     }
 
     // Stage planning inside one pass.  `items` are the pass's primitives in
-    // scheduled order with bits given as local tile bits.
+    // scheduled order with bits given as local tile bits.  A stage holds at most
+    // one ordered pair of two-qubit gate bits, on register bits 0 and 1.
     std::vector<std::pair<std::vector<int>, std::vector<int>>> plan_stages(
         const std::vector<ScanItem>& items) const {
         const int n = (int)items.size();
@@ -212,43 +264,78 @@ struct Compiler {
         std::vector<std::pair<std::vector<int>, std::vector<int>>> stages;
         bool first = true;
         while (left > 0) {
-            // Does everything left fit in one stage that can also store?
+            std::vector<int> pairs;  // ordered pairs of the pending two-qubit gates
             std::set<int> need;
-            for (int i = 0; i < n; ++i)
-                if (!done[i] && !items[i].diag) need.insert(items[i].bit);
-            bool fits = (int)need.size() <= RB;
+            for (int i = 0; i < n; ++i) {
+                if (done[i] || items[i].diag) continue;
+                need.insert(items[i].bit);
+                if (items[i].bit2 >= 0) {
+                    need.insert(items[i].bit2);
+                    const int pr = (items[i].bit << 8) | items[i].bit2;
+                    if (std::find(pairs.begin(), pairs.end(), pr) == pairs.end()) pairs.push_back(pr);
+                }
+            }
+            // Does everything left fit in one stage that can also store?
+            bool fits = (int)need.size() <= RB && pairs.size() <= 1;
             for (int b : need) fits = fits && io_ok(b);
             std::vector<int> rb;
+            int pair = PAIR_NONE;
             if (fits) {
-                rb.assign(need.begin(), need.end());
+                if (!pairs.empty()) {
+                    pair = pairs[0];
+                    rb = {pair >> 8, pair & 255};
+                }
+                for (int b : need)
+                    if (std::find(rb.begin(), rb.end(), b) == rb.end()) rb.push_back(b);
                 for (int b = k - 1; b >= 0 && (int)rb.size() < RB; --b)
                     if (io_ok(b) && std::find(rb.begin(), rb.end(), b) == rb.end()) rb.push_back(b);
             } else {
-                while ((int)rb.size() < RB) {
-                    int best = -1, best_gain = -1, best_pref = -1;
-                    for (int b = 0; b < k; ++b) {
-                        if (std::find(rb.begin(), rb.end(), b) != rb.end()) continue;
-                        if (first && !io_ok(b)) continue;
-                        std::vector<char> in_set(k, 0);
-                        for (int r : rb) in_set[r] = 1;
-                        in_set[b] = 1;
-                        int g = scan(items, done, in_set, k, -1, nullptr);
-                        // first stage: prefer high bits; later: bits that cannot be
-                        // stored from (low carriers) first, then low bits
-                        int pref = first ? b : ((!io_ok(b) ? 1000 : 0) + (k - b));
-                        if (g > best_gain || (g == best_gain && pref > best_pref)) {
-                            best = b;
-                            best_gain = g;
-                            best_pref = pref;
-                        }
+                // options: no two-qubit gate, or one of the first few pending pairs
+                std::vector<int> options = {PAIR_NONE};
+                for (size_t q = 0; q < pairs.size() && q < 4; ++q) options.push_back(pairs[q]);
+                int best_gain = -1;
+                for (int opt : options) {
+                    std::vector<int> r;
+                    if (opt >= 0) {
+                        const int b1 = opt >> 8, b2 = opt & 255;
+                        if (first && (!io_ok(b1) || !io_ok(b2))) continue;
+                        r = {b1, b2};
                     }
-                    rb.push_back(best);
+                    while ((int)r.size() < RB) {
+                        int best = -1, bg = -1, best_pref = -1;
+                        for (int b = 0; b < k; ++b) {
+                            if (std::find(r.begin(), r.end(), b) != r.end()) continue;
+                            if (first && !io_ok(b)) continue;
+                            std::vector<char> in_set(k, 0);
+                            for (int x : r) in_set[x] = 1;
+                            in_set[b] = 1;
+                            int g = scan(items, done, in_set, k, -1, nullptr, opt);
+                            // first stage: prefer high bits; later: bits that cannot be
+                            // stored from (low carriers) first, then low bits
+                            int pref = first ? b : ((!io_ok(b) ? 1000 : 0) + (k - b));
+                            if (g > bg || (g == bg && pref > best_pref)) {
+                                best = b;
+                                bg = g;
+                                best_pref = pref;
+                            }
+                        }
+                        if (best < 0) break;
+                        r.push_back(best);
+                    }
+                    std::vector<char> in_set(k, 0);
+                    for (int x : r) in_set[x] = 1;
+                    const int g = scan(items, done, in_set, k, -1, nullptr, opt);
+                    if (g > best_gain) {
+                        best_gain = g;
+                        rb = r;
+                        pair = opt;
+                    }
                 }
             }
             std::vector<char> in_set(k, 0);
             for (int r : rb) in_set[r] = 1;
             std::vector<int> sel;
-            scan(items, done, in_set, k, -1, &sel);
+            scan(items, done, in_set, k, -1, &sel, pair);
             for (int i : sel) done[i] = 1;
             left -= (int)sel.size();
             stages.push_back({rb, sel});
@@ -296,7 +383,7 @@ struct Compiler {
             for (int b : cand) {
                 if (in_t[b]) continue;
                 in_t[b] = 1;
-                int g = scan(items, done, in_t, nq, max_gates, nullptr);
+                int g = 2 * scan(items, done, in_t, nq, max_gates, nullptr) + half_pairs(items, done, in_t);
                 in_t[b] = 0;
                 if (g > best_gain) {
                     best = b;
@@ -309,6 +396,33 @@ struct Compiler {
         std::sort(t.begin(), t.end());
         sel->clear();
         scan(items, done, in_t, nq, max_gates, sel);
+        if (sel->empty()) {
+            // the greedy choice enables nothing (the half-pair tie-break can lead it
+            // away from the first pending two-qubit gate): build the tile around the
+            // first pending gate instead, which nothing earlier can block
+            int first = -1;
+            for (size_t i = 0; i < items.size() && first < 0; ++i)
+                if (!done[i] && !items[i].diag) first = (int)i;
+            std::fill(in_t.begin(), in_t.end(), 0);
+            t.clear();
+            for (int b = 0; b < C; ++b) {
+                in_t[b] = 1;
+                t.push_back(b);
+            }
+            if (first >= 0)
+                for (int b : {items[first].bit, items[first].bit2})
+                    if (b >= 0 && !in_t[b]) {
+                        in_t[b] = 1;
+                        t.push_back(b);
+                    }
+            for (int b = 0; b < nq && (int)t.size() < k; ++b)
+                if (!in_t[b]) {
+                    in_t[b] = 1;
+                    t.push_back(b);
+                }
+            std::sort(t.begin(), t.end());
+            scan(items, done, in_t, nq, max_gates, sel);
+        }
         return t;
     }
 
@@ -319,7 +433,7 @@ struct Compiler {
         std::vector<ScanItem> litems;
         for (size_t j = 0; j < count; ++j) {
             const ScanItem& it = items[sel[j]];
-            litems.push_back({it.diag, it.diag ? 0 : local_of[it.bit]});
+            litems.push_back({it.diag, it.diag ? 0 : local_of[it.bit], it.bit2 >= 0 ? local_of[it.bit2] : -1});
         }
         return litems;
     }
@@ -419,7 +533,7 @@ struct Compiler {
         const int nq = in->nq;
         const int n = (int)prims.size();
         std::vector<ScanItem> items(n);
-        for (int i = 0; i < n; ++i) items[i] = {prims[i].kind != Prim::GATE, prims[i].bit};
+        for (int i = 0; i < n; ++i) items[i] = {prims[i].kind != Prim::GATE, prims[i].bit, prims[i].bit2};
         std::vector<char> done(n, 0);
         int left = n;
         ScaleState sc;
@@ -486,6 +600,24 @@ struct Compiler {
                         } else if (p.gk == Prim::GMAT) {
                             o.kind = OP_MAT;
                             o.arg = 2 * p.idx + (backward ? 1 : 0);
+                        } else if (p.gk == Prim::GMAT4 || p.gk == Prim::GD4) {
+                            // the stage holds the pair on register bits 0 (is1) and 1 (is2)
+                            if (o.a != 0 || reg_of(local_of[p.bit2]) != 1) throw std::logic_error("two-qubit register pair");
+                            o.a = 0;
+                            if (p.gk == Prim::GMAT4) {
+                                o.kind = OP_MAT4;
+                                o.arg = 2 * p.idx + (backward ? 1 : 0);
+                            } else if (!backward) {
+                                o.kind = OP_MAT4;
+                                o.arg = 2 * plan->n_static4 + 5 * p.idx;
+                            } else {
+                                o.kind = OP_D4BWD;
+                                o.arg = 2 * plan->n_static4 + 5 * p.idx;  // D, D^H and the three derivatives
+                                o.gscale = (float)std::ldexp(1.0, -sc.h);
+                                o.gslot = (int32_t)plan->n_gpart;
+                                plan->d2_grad.push_back({p.param, plan->n_gpart, hp.ntiles});
+                                plan->n_gpart += 3 * hp.ntiles;
+                            }
                         } else if (!backward) {
                             o.kind = OP_MAT;
                             o.arg = 2 * plan->n_static + 5 * p.idx;
@@ -494,7 +626,7 @@ struct Compiler {
                             o.arg = 2 * plan->n_static + 5 * p.idx;  // D, D^H, dD/dalpha, dD/dbeta, dD/dgamma
                             o.gscale = (float)std::ldexp(1.0, -sc.h);
                             o.gslot = (int32_t)plan->n_gpart;
-                            plan->d2_grad.push_back({p.idx, plan->n_gpart, hp.ntiles});
+                            plan->d2_grad.push_back({p.param, plan->n_gpart, hp.ntiles});
                             plan->n_gpart += 3 * hp.ntiles;
                         }
                         hs.ops.push_back(o);
@@ -594,11 +726,25 @@ int compile_plan(Plan* plan, const pk_problem* probs, int n_inst, int prec, std:
         in.d2_base = d2;
         for (int g = 0; g < p.n_gates; ++g) {
             const pk_gate& gt = p.gates[g];
-            if (gt.is2 != 0 || gt.k != 0) {
+            const bool two = gt.kind == PK_GATE_TWOOP || gt.kind == PK_GATE_CNOT || gt.kind == PK_GATE_CPHASE ||
+                             gt.kind == PK_GATE_CPHASEK || gt.kind == PK_GATE_SWAP || gt.kind == PK_GATE_D4;
+            if (!two && (gt.is2 != 0 || gt.k != 0)) {
                 *err = fmt("instance %lld gate %lld: two-qubit fields must be 0", i, g);
                 return PK_EINVAL;
             }
-            bool needs_qubit = gt.kind == PK_GATE_ONEOP || gt.kind == PK_GATE_H || gt.kind == PK_GATE_D2;
+            if (two && (gt.is2 < 1 || gt.is2 > p.nq || gt.is2 == gt.is1)) {
+                *err = fmt("instance %lld gate %lld: second qubit label out of 1..nq or equal to the first", i, g);
+                return PK_EINVAL;
+            }
+            if (two && gt.kind != PK_GATE_CPHASEK && gt.k != 0) {
+                *err = fmt("instance %lld gate %lld: k is only for CPHASEK", i, g);
+                return PK_EINVAL;
+            }
+            if (gt.kind == PK_GATE_CPHASEK && (gt.k < 1 || gt.k > 62)) {
+                *err = fmt("instance %lld gate %lld: CPHASEK needs k in 1..62", i, g);
+                return PK_EINVAL;
+            }
+            bool needs_qubit = gt.kind == PK_GATE_ONEOP || gt.kind == PK_GATE_H || gt.kind == PK_GATE_D2 || two;
             if (needs_qubit && (gt.is1 < 1 || gt.is1 > p.nq)) {
                 *err = fmt("instance %lld gate %lld: qubit label out of 1..nq", i, g);
                 return PK_EINVAL;
@@ -639,9 +785,65 @@ int compile_plan(Plan* plan, const pk_problem* probs, int n_inst, int prec, std:
                     *err = fmt("instance %lld gate %lld: non-finite angle", i, g);
                     return PK_EINVAL;
                 }
-                in.prims.push_back({Prim::GATE, p.nq - gt.is1, Prim::GD2, d2});
+                pr = {Prim::GATE, p.nq - gt.is1, Prim::GD2, d2};
+                pr.param = (int)plan->params.size();
+                in.prims.push_back(pr);
+                plan->params.push_back({0, d2});
                 for (int e = 0; e < 3; ++e) plan->default_angles.push_back(gt.angle[e]);
                 ++d2;
+                break;
+            case PK_GATE_TWOOP:
+            case PK_GATE_CNOT:
+            case PK_GATE_CPHASE:
+            case PK_GATE_CPHASEK:
+            case PK_GATE_SWAP: {
+                // fixed 4x4 operator in the basis |q_is1 q_is2> (Eq. resmat2), row-major (re, im)
+                double m[32] = {0};
+                auto set = [&](int r, int c, double re, double im) {
+                    m[2 * (4 * r + c)] = re;
+                    m[2 * (4 * r + c) + 1] = im;
+                };
+                if (gt.kind == PK_GATE_TWOOP) {
+                    if (!finite8(gt.op, 32)) {
+                        *err = fmt("instance %lld gate %lld: non-finite operator", i, g);
+                        return PK_EINVAL;
+                    }
+                    for (int e = 0; e < 32; ++e) m[e] = gt.op[e];
+                    if (!is_unitary4(m)) plan->backward_ok = false;
+                } else if (gt.kind == PK_GATE_CNOT) {  // control is1, target is2 (Sec. 4.2)
+                    set(0, 0, 1, 0); set(1, 1, 1, 0); set(2, 3, 1, 0); set(3, 2, 1, 0);
+                } else if (gt.kind == PK_GATE_CPHASE) {  // diag(1, 1, 1, -1) (Sec. 4.2)
+                    set(0, 0, 1, 0); set(1, 1, 1, 0); set(2, 2, 1, 0); set(3, 3, -1, 0);
+                } else if (gt.kind == PK_GATE_CPHASEK) {  // diag(1, 1, 1, e^{2 pi i / 2^k}) (Eq. cphasek)
+                    const double ph = 2.0 * M_PI * std::ldexp(1.0, -gt.k);
+                    set(0, 0, 1, 0); set(1, 1, 1, 0); set(2, 2, 1, 0); set(3, 3, std::cos(ph), std::sin(ph));
+                } else {  // SWAP: |ab> -> |ba>
+                    set(0, 0, 1, 0); set(1, 2, 1, 0); set(2, 1, 1, 0); set(3, 3, 1, 0);
+                }
+                pr = {Prim::GATE, p.nq - gt.is1, Prim::GMAT4, plan->n_static4};
+                pr.bit2 = p.nq - gt.is2;
+                for (int e = 0; e < 32; ++e) plan->static_mats4.push_back(m[e]);
+                for (int a = 0; a < 4; ++a)  // adjoint
+                    for (int b = 0; b < 4; ++b) {
+                        plan->static_mats4.push_back(m[2 * (4 * b + a)]);
+                        plan->static_mats4.push_back(-m[2 * (4 * b + a) + 1]);
+                    }
+                ++plan->n_static4;
+                in.prims.push_back(pr);
+                break;
+            }
+            case PK_GATE_D4:
+                if (!finite8(gt.angle, 3)) {
+                    *err = fmt("instance %lld gate %lld: non-finite angle", i, g);
+                    return PK_EINVAL;
+                }
+                pr = {Prim::GATE, p.nq - gt.is1, Prim::GD4, plan->n_d4};
+                pr.bit2 = p.nq - gt.is2;
+                pr.param = (int)plan->params.size();
+                in.prims.push_back(pr);
+                plan->params.push_back({1, plan->n_d4});
+                for (int e = 0; e < 3; ++e) plan->default_angles.push_back(gt.angle[e]);
+                ++plan->n_d4;
                 break;
             default:
                 *err = fmt("instance %lld gate %lld: unknown kind", i, g);
@@ -690,6 +892,12 @@ int recompile(Plan* plan, std::string* err) {
             c.C = std::min(plan->tiling.carrier_bits, c.k);
             c.RBITS = c.backward ? 4 : plan->tiling.reg_bits;
             c.RB = std::min(c.RBITS, c.k);
+            bool has_two = false;
+            for (const Prim& pr : in.prims) has_two = has_two || pr.bit2 >= 0;
+            if (has_two && c.k < in.nq && c.k - c.C < 2) {
+                *err = "two-qubit gates need at least two non-carrier tile bits (tile_bits >= carrier_bits + 2)";
+                return PK_EINVAL;
+            }
             std::vector<Prim> prims = in.prims;
             if (c.backward) std::reverse(prims.begin(), prims.end());
             auto& dst = c.backward ? in.bwd : in.fwd;
@@ -825,6 +1033,10 @@ TableLayout table_layout(const Plan* plan) {
     o = align256(o + plan->flips.size() * sizeof(Flip));
     t.mats = o;  // static matrices followed by the default angles
     o = align256(o + (plan->static_mats.size() + plan->default_angles.size()) * sizeof(double));
+    t.mats4 = o;  // static two-qubit matrices
+    o = align256(o + plan->static_mats4.size() * sizeof(double));
+    t.params = o;
+    o = align256(o + plan->params.size() * sizeof(ParamRef));
     t.idesc = o;
     o = align256(o + plan->idesc.size() * sizeof(InstDesc));
     t.order = o;  // the queue order of the batched launch (instances left to single workgroups)
@@ -844,6 +1056,8 @@ WsLayout workspace_layout(const Plan* plan, int op) {
     size_t o = 0;
     w.mats = o;
     o = align256(o + (size_t)(2 * plan->n_static + 5 * plan->n_d2) * 8 * sizeof(double));
+    w.mats4 = o;
+    o = align256(o + (size_t)(2 * plan->n_static4 + 5 * plan->n_d4) * 32 * sizeof(double));
     w.partials = o;
     o = align256(o + (size_t)plan->n_partials * sizeof(double));
     w.reads = o;
@@ -891,8 +1105,15 @@ std::string describe(const Plan* plan) {
     s += ",\"fuse\":" + std::to_string(plan->tiling.fuse);
     s += ",\"n_static\":" + std::to_string(plan->n_static);
     s += ",\"n_d2\":" + std::to_string(plan->n_d2);
+    s += ",\"n_static4\":" + std::to_string(plan->n_static4);
+    s += ",\"n_d4\":" + std::to_string(plan->n_d4);
+    s += ",\"params\":[";
+    for (size_t q = 0; q < plan->params.size(); ++q)
+        s += (q ? "," : "") + std::string("[") + std::to_string(plan->params[q].kind) + "," +
+             std::to_string(plan->params[q].slot) + "]";
+    s += "]";
     s += ",\"instances\":[";
-    const char* kinds[] = {"H", "MAT", "FLIP", "SCALE", "READ", "SEED", "D2BWD"};
+    const char* kinds[] = {"H", "MAT", "FLIP", "SCALE", "READ", "SEED", "D2BWD", "MAT4", "D4BWD"};
     for (size_t i = 0; i < plan->inst.size(); ++i) {
         const Instance& in = plan->inst[i];
         if (i) s += ",";
@@ -929,7 +1150,7 @@ std::string describe(const Plan* plan) {
                             s += ",\"tile\":" + std::to_string(f.tile) + ",\"j\":" + std::to_string(f.j) +
                                  ",\"slot\":" + std::to_string(f.slot);
                         }
-                        if (op.kind == OP_D2BWD) {
+                        if (op.kind == OP_D2BWD || op.kind == OP_D4BWD) {
                             std::snprintf(buf, sizeof buf, "%.9g", (double)op.gscale);
                             s += ",\"gscale\":";
                             s += buf;
@@ -953,7 +1174,11 @@ std::string describe(const Plan* plan) {
                          ",\"mat_post_a\":" + std::to_string(u.mat_post_a) + ",\"mat_post\":" +
                          std::to_string(u.mat_post) + ",\"d2b_a\":" + std::to_string(u.d2b_a) +
                          ",\"d2b_mat\":" + std::to_string(u.d2b_mat) + ",\"d2b_gscale\":" + buf +
-                         ",\"scale\":" + std::to_string(u.scale) + ",\"read\":" + std::to_string(u.read) + "}";
+                         ",\"mat4\":" + std::to_string(u.mat4) + ",\"d4b_mat\":" + std::to_string(u.d4b_mat);
+                    std::snprintf(buf, sizeof buf, "%.9g", (double)u.d4b_gscale);
+                    s += ",\"d4b_gscale\":";
+                    s += buf;
+                    s += ",\"scale\":" + std::to_string(u.scale) + ",\"read\":" + std::to_string(u.read) + "}";
                 }
                 s += "]}";
             }

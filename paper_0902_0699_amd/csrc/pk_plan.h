@@ -15,8 +15,10 @@ namespace pk {
 struct Prim {
     enum Kind { GATE, ORACLE, INV } kind;
     int bit;  // GATE: state bit b = nq - i_s (bit 0 is qubit n_q, the least significant)
-    enum GKind { GH, GMAT, GD2 } gk;
-    int idx;  // GMAT: static matrix index; GD2: global D2 index
+    enum GKind { GH, GMAT, GD2, GMAT4, GD4 } gk;
+    int idx;         // GMAT / GMAT4: static matrix index; GD2 / GD4: global D2 / D4 index
+    int bit2 = -1;   // GMAT4 / GD4: state bit of the second qubit is2
+    int param = -1;  // GD2 / GD4: index of the gate's angle triple
 };
 
 struct HostStage {
@@ -112,9 +114,13 @@ struct Plan {
     int prec = PK_FP64;
     std::vector<Instance> inst;
     std::vector<double> static_mats;   // 8 doubles per ONEOP matrix, then its adjoint
-    std::vector<double> default_angles; // 3 per D2
+    std::vector<double> static_mats4;  // 32 doubles per fixed two-qubit matrix, then its adjoint
+    std::vector<double> default_angles; // 3 per D2 or D4 gate, in order
+    std::vector<ParamRef> params;      // what each angle triple drives
     int n_d2 = 0;
+    int n_d4 = 0;
     int n_static = 0;
+    int n_static4 = 0;
     bool backward_ok = true;
     Tiling tiling{13, 4, 1};
     BatchConfig batch;
@@ -127,8 +133,8 @@ struct Plan {
     std::vector<Flip> flips;
     std::vector<InstDesc> idesc;    // batched launch: per-instance pass ranges
     std::vector<int32_t> order;     // instances by decreasing size (largest first)
-    struct D2Grad { int d; int64_t gslot; int64_t nt; };
-    std::vector<D2Grad> d2_grad;    // where each D2's backward partials live
+    struct D2Grad { int d; int64_t gslot; int64_t nt; };  // d: angle triple index
+    std::vector<D2Grad> d2_grad;    // where each D2's or D4's backward partials live
     int n_fwd_passes = 0;
     int64_t n_partials = 0;         // norm partials (sum over instances of last-pass tiles)
     int64_t n_reads = 0;
@@ -149,7 +155,7 @@ std::string describe(const Plan* plan);
 
 // Byte offsets of the device table arrays inside plan->d_tables.
 struct TableLayout {
-    size_t passes, stages, flips, mats, idesc, order, team_off, team_list, red, total;
+    size_t passes, stages, flips, mats, mats4, params, idesc, order, team_off, team_list, red, total;
 };
 TableLayout table_layout(const Plan* plan);
 
@@ -159,7 +165,7 @@ std::vector<Reduction> backward_reductions(const Plan* plan);
 
 // Workspace layout (byte offsets) for op = PK_OP_EVAL / PK_OP_BACKWARD.
 struct WsLayout {
-    size_t mats, partials, reads, gpart, counters, state, total;
+    size_t mats, mats4, partials, reads, gpart, counters, state, total;
 };
 WsLayout workspace_layout(const Plan* plan, int op);
 

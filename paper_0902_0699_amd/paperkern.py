@@ -22,7 +22,9 @@ LIB_PATH = os.path.join(_HERE, "libpaperkern.so")
 PK_OK, PK_EINVAL, PK_ENOMEM, PK_EDEVICE, PK_EUNSUPPORTED = 0, -1, -2, -3, -4
 PK_FP64, PK_FP32 = 0, 1
 PK_OP_EVAL, PK_OP_BACKWARD = 0, 1
-GATE_KINDS = {"ONEOP": 0, "H": 1, "HALL": 2, "ORACLE": 3, "INV": 4, "D2": 5}
+GATE_KINDS = {"ONEOP": 0, "H": 1, "HALL": 2, "ORACLE": 3, "INV": 4, "D2": 5,
+              "TWOOP": 6, "CNOT": 7, "CPHASE": 8, "CPHASEK": 9, "SWAP": 10, "D4": 11}
+TWO_QUBIT = ("TWOOP", "CNOT", "CPHASE", "CPHASEK", "SWAP", "D4")
 
 # Entry points declared in include/paperkern.h with their ctypes signatures.
 _c_int32, _c_int64, _c_double, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
@@ -30,7 +32,7 @@ _c_int32, _c_int64, _c_double, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_do
 
 class PkGate(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("is1", ctypes.c_int32), ("is2", ctypes.c_int32),
-                ("k", ctypes.c_int32), ("op", ctypes.c_double * 8), ("angle", ctypes.c_double * 3)]
+                ("k", ctypes.c_int32), ("op", ctypes.c_double * 32), ("angle", ctypes.c_double * 3)]
 
 
 class PkProblem(ctypes.Structure):
@@ -97,17 +99,28 @@ def make_gate(g, nq=None):
     if kind not in GATE_KINDS:
         raise ValueError("unknown gate kind %r" % (kind,))
     pg.kind = GATE_KINDS[kind]
-    if kind in ("H", "ONEOP", "D2"):
+    if kind in ("H", "ONEOP", "D2") or kind in TWO_QUBIT:
         pg.is1 = int(g[1])
+    if kind in TWO_QUBIT:
+        pg.is2 = int(g[2])
     if kind == "ONEOP":
         op = np.asarray(g[2], dtype=np.complex128).reshape(2, 2)
         for a in range(2):
             for b in range(2):
                 pg.op[2 * (2 * a + b)] = op[a, b].real
                 pg.op[2 * (2 * a + b) + 1] = op[a, b].imag
-    if kind == "D2":
+    if kind == "TWOOP":
+        op = np.asarray(g[3], dtype=np.complex128).reshape(4, 4)
+        for a in range(4):
+            for b in range(4):
+                pg.op[2 * (4 * a + b)] = op[a, b].real
+                pg.op[2 * (4 * a + b) + 1] = op[a, b].imag
+    if kind == "CPHASEK":
+        pg.k = int(g[3])
+    if kind in ("D2", "D4"):
+        first = 2 if kind == "D2" else 3
         for t in range(3):
-            pg.angle[t] = float(g[2 + t])
+            pg.angle[t] = float(g[first + t])
     return pg
 
 

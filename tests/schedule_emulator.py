@@ -16,14 +16,38 @@ import oracle as O
 
 def _matrix_table(problems, desc):
     statics = []
+    statics4 = []
     d2 = []
+    d4 = []
     for p in problems:
         for g in p["gates"]:
             if g[0] == "ONEOP":
                 statics.append(np.asarray(g[2], dtype=np.complex128))
             if g[0] == "D2":
                 d2.append(tuple(float(v) for v in g[2:5]))
+            if g[0] == "TWOOP":
+                statics4.append(np.asarray(g[3], dtype=np.complex128))
+            if g[0] in ("CNOT", "CPHASE", "SWAP"):
+                statics4.append(getattr(O, g[0]))
+            if g[0] == "CPHASEK":
+                statics4.append(O.cphasek(g[3]))
+            if g[0] == "D4":
+                d4.append(tuple(float(v) for v in g[3:6]))
     assert len(statics) == desc["n_static"] and len(d2) == desc["n_d2"]
+    assert len(statics4) == desc["n_static4"] and len(d4) == desc["n_d4"]
+
+    def mat4(m):
+        ns = desc["n_static4"]
+        if m < 2 * ns:
+            M = statics4[m // 2]
+            return M if m % 2 == 0 else M.conj().T
+        d, r = divmod(m - 2 * ns, 5)
+        D = O.d4_matrix(*d4[d])
+        if r == 0:
+            return D
+        if r == 1:
+            return D.conj().T
+        return O.d4_derivatives(*d4[d])[r - 2]
 
     def mat(m):
         ns = desc["n_static"]
@@ -38,6 +62,7 @@ def _matrix_table(problems, desc):
             return D.conj().T
         return O.d2_derivatives(*d2[d])[r - 2]
 
+    mat.four = mat4
     return mat
 
 
@@ -46,6 +71,17 @@ def _apply_bit(vec, nq, bit, M):
     a, b = v[:, 0, :].copy(), v[:, 1, :].copy()
     v[:, 0, :] = M[0, 0] * a + M[0, 1] * b
     v[:, 1, :] = M[1, 0] * a + M[1, 1] * b
+
+
+def _apply_pair(vec, nq, bit1, bit2, M):
+    """4x4 M on the state bits (bit1, bit2) in the basis |q_bit1 q_bit2>."""
+    out = O.apply_twoop(vec, nq, nq - bit1, nq - bit2, M)
+    vec[:] = out
+
+
+def _param_row(desc, kind, slot):
+    """Row of the angle-gradient array (the angle triple index) of a D2 / D4 slot."""
+    return [i for i, p in enumerate(desc["params"]) if p == [kind, slot]][0]
 
 
 def _global_index(nq, tbits, tile, j):
@@ -67,6 +103,8 @@ def check_stage_shapes(nq, p):
         for op in st["ops"]:
             if op["kind"] in ("H", "MAT", "D2BWD"):
                 assert 0 <= op["a"] < len(rb)
+            if op["kind"] in ("MAT4", "D4BWD"):
+                assert op["a"] == 0 and len(rb) >= 2
     assert len(set(p["tile_bits"])) == len(p["tile_bits"]) == k
     assert all(0 <= b < nq for b in p["tile_bits"])
 
@@ -115,16 +153,29 @@ def _run_subs(problems, desc, inst, direction, psi, lam=None, dL=1.0):
             if u["mat_post_a"] >= 0:
                 for v in vecs:
                     _apply_bit(v, nq, tb[rb[u["mat_post_a"]]], mat(u["mat_post"]))
+            if u["mat4"] >= 0:
+                for v in vecs:
+                    _apply_pair(v, nq, tb[rb[0]], tb[rb[1]], mat.four(u["mat4"]))
             if u["d2b_a"] >= 0:
                 bit = tb[rb[u["d2b_a"]]]
                 m0 = u["d2b_mat"]
                 _apply_bit(vecs[0], nq, bit, mat(m0 + 1))
-                d = (m0 - 2 * desc["n_static"]) // 5
+                d = _param_row(desc, 0, (m0 - 2 * desc["n_static"]) // 5)
                 for t in range(3):
                     dpsi = vecs[0].copy()
                     _apply_bit(dpsi, nq, bit, mat(m0 + 2 + t))
                     grads[(d, t)] = 2.0 * u["d2b_gscale"] * float(np.vdot(vecs[1], dpsi).real)
                 _apply_bit(vecs[1], nq, bit, mat(m0 + 1))
+            if u["d4b_mat"] >= 0:
+                b1, b2 = tb[rb[0]], tb[rb[1]]
+                m0 = u["d4b_mat"]
+                _apply_pair(vecs[0], nq, b1, b2, mat.four(m0 + 1))
+                d = _param_row(desc, 1, (m0 - 2 * desc["n_static4"]) // 5)
+                for t in range(3):
+                    dpsi = vecs[0].copy()
+                    _apply_pair(dpsi, nq, b1, b2, mat.four(m0 + 2 + t))
+                    grads[(d, t)] = 2.0 * u["d4b_gscale"] * float(np.vdot(vecs[1], dpsi).real)
+                _apply_pair(vecs[1], nq, b1, b2, mat.four(m0 + 1))
             if u["scale"]:
                 for v in vecs:
                     v *= p["scale"]
@@ -162,6 +213,8 @@ def run_forward_ops(problems, desc, inst, psi_in):
                 if kind in ("H", "MAT"):
                     bit = tb[st["rb"][op["a"]]]
                     _apply_bit(psi, nq, bit, H if kind == "H" else mat(op["arg"]))
+                elif kind == "MAT4":
+                    _apply_pair(psi, nq, tb[st["rb"][0]], tb[st["rb"][1]], mat.four(op["arg"]))
                 elif kind == "FLIP":
                     psi[_global_index(nq, tb, op["tile"], op["j"])] *= -1
                 elif kind == "SCALE":
@@ -210,6 +263,19 @@ def run_backward_ops(problems, desc, inst, psi_out, dL):
                     M = H if kind == "H" else mat(op["arg"])
                     _apply_bit(psi, nq, bit, M)
                     _apply_bit(lam, nq, bit, M)
+                elif kind == "MAT4":
+                    b1, b2 = tb[st["rb"][0]], tb[st["rb"][1]]
+                    _apply_pair(psi, nq, b1, b2, mat.four(op["arg"]))
+                    _apply_pair(lam, nq, b1, b2, mat.four(op["arg"]))
+                elif kind == "D4BWD":
+                    b1, b2 = tb[st["rb"][0]], tb[st["rb"][1]]
+                    _apply_pair(psi, nq, b1, b2, mat.four(op["arg"] + 1))
+                    d = _param_row(desc, 1, (op["arg"] - 2 * desc["n_static4"]) // 5)
+                    for t in range(3):
+                        dpsi = psi.copy()
+                        _apply_pair(dpsi, nq, b1, b2, mat.four(op["arg"] + 2 + t))
+                        grads[(d, t)] = 2.0 * op["gscale"] * float(np.vdot(lam, dpsi).real)
+                    _apply_pair(lam, nq, b1, b2, mat.four(op["arg"] + 1))
                 elif kind == "FLIP":
                     g = _global_index(nq, tb, op["tile"], op["j"])
                     psi[g] *= -1
@@ -226,7 +292,7 @@ def run_backward_ops(problems, desc, inst, psi_out, dL):
                     for t in range(3):
                         dpsi = psi.copy()
                         _apply_bit(dpsi, nq, bit, mat(op["arg"] + 2 + t))
-                        d = (op["arg"] - 2 * desc["n_static"]) // 5
+                        d = _param_row(desc, 0, (op["arg"] - 2 * desc["n_static"]) // 5)
                         grads[(d, t)] = 2.0 * op["gscale"] * float(np.vdot(lam, dpsi).real)
                     _apply_bit(lam, nq, bit, mat(op["arg"] + 1))
                 else:

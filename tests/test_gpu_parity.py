@@ -414,3 +414,125 @@ def test_autograd_function_gradcheck():
         return pk.grover_eval(plan, p, a)[0]
 
     assert torch.autograd.gradcheck(f, (psi, ang), eps=1e-6, atol=1e-8, rtol=1e-6)
+
+
+# --------------------------------------------------------------------------- two-qubit gates
+
+
+def _gates2(rng, nq, count, unitary=True):
+    """Random lists mixing one-qubit gates, diagonal ops and the two-qubit kinds
+    (TWOOP, CNOT, CPHASE, CPHASEK, SWAP, D4 of Sec. 4 and Sec. 6.3)."""
+    gates = []
+    for _ in range(count):
+        r = int(rng.integers(0, 11))
+        q1, q2 = (int(v) for v in rng.choice(np.arange(1, nq + 1), 2, replace=False))
+        if r == 0:
+            gates.append(("H", q1))
+        elif r == 1:
+            gates.append(("D2", q1, *rng.uniform(0, 3, 3)))
+        elif r == 2:
+            gates.append(("ORACLE",))
+        elif r == 3:
+            gates.append(("INV",))
+        elif r == 4:
+            m = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+            if unitary:
+                m, _ = np.linalg.qr(m)
+            gates.append(("TWOOP", q1, q2, m))
+        elif r == 5:
+            gates.append(("CNOT", q1, q2))
+        elif r == 6:
+            gates.append(("CPHASE", q1, q2))
+        elif r == 7:
+            gates.append(("CPHASEK", q1, q2, int(rng.integers(1, 6))))
+        elif r == 8:
+            gates.append(("SWAP", q1, q2))
+        elif r == 9:
+            gates.append(("D4", q1, q2, *rng.uniform(-2, 2, 3)))
+        else:
+            gates.append(("HALL",))
+    return gates
+
+
+@pytest.mark.parametrize("nq,tiling,launch,prec", [(2, None, None, "fp64"), (5, None, None, "fp64"),
+                                                   (10, (6, 2, 1), None, "fp64"), (14, None, None, "fp64"),
+                                                   (14, (13, 4, 1), (0, 5), "fp64"), (12, (5, 0, 0), None, "fp64"),
+                                                   (15, (10, 4, 1), (2, 4), "fp64"), (14, None, None, "fp32"),
+                                                   (9, (6, 2, 1), (0, 4), "fp32")])
+def test_two_qubit_gates_against_oracle(nq, tiling, launch, prec):
+    rng = np.random.default_rng(500 + nq + (tiling[0] if tiling else 0))
+    gates = _gates2(rng, nq, 24, unitary=(nq % 2 == 0)) + [("CNOT", 1, nq), ("D4", nq, 1, 0.3, 1.9, -0.6)]
+    prob = {"nq": nq, "gates": gates, "marked": sorted({int(v) for v in rng.integers(0, 1 << nq, 2)})}
+    psi = _state(rng, nq)
+    _say("two-qubit n_q=%d tiling %s launch %s %s" % (nq, tiling, launch, prec))
+    _, got, L, norm = _run(prob, psi, prec=prec, tiling=tiling, launch=launch)
+    want, Lw, nw = O.evaluate(nq, gates, prob["marked"], psi)
+    tol = TOL64 if prec == "fp64" else TOL32
+    scale = max(1.0, float(np.linalg.norm(want)))
+    assert _relerr(got, want) <= tol
+    assert abs(L - Lw) <= tol * scale * scale and abs(norm - nw) <= tol * scale * scale
+
+
+def test_named_two_qubit_gates_bit_exact():
+    """CNOT, CPHASE and SWAP permute or negate amplitudes: the products with 0 and 1
+    entries are exact, so the GPU matches the oracle bit for bit."""
+    rng = np.random.default_rng(77)
+    nq = 12
+    gates = [("CNOT", 3, 9), ("SWAP", 12, 1), ("CPHASE", 5, 2), ("CNOT", 11, 4), ("SWAP", 6, 7), ("ORACLE",)]
+    psi = _state(rng, nq)
+    _, got, _, _ = _run({"nq": nq, "gates": gates, "marked": [100]}, psi)
+    want, _, _ = O.evaluate(nq, gates, [100], psi)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_two_qubit_batched_against_oracle():
+    pk = _pk()
+    rng = np.random.default_rng(78)
+    probs, psis = [], []
+    for nq in (3, 9, 14, 6, 11, 2):
+        probs.append({"nq": nq, "gates": _gates2(rng, nq, 12) + [("SWAP", 1, nq)], "marked": [0, (1 << nq) - 1]})
+        psis.append(_state(rng, nq))
+    plan = pk.Plan(probs)
+    res, L, _ = pk.evaluate_batched(plan, _dev(np.concatenate(psis)))
+    torch.cuda.synchronize()
+    res = res.cpu().numpy()
+    offs = plan.offsets()
+    for k, (p, psi) in enumerate(zip(probs, psis)):
+        want, Lw, _ = O.evaluate(p["nq"], p["gates"], p["marked"], psi)
+        assert _relerr(res[offs[k]:offs[k + 1]], want) <= TOL64 and abs(float(L[k]) - Lw) <= TOL64
+
+
+@pytest.mark.parametrize("nq", [4, 9, 14])
+def test_two_qubit_backward_against_oracle_adjoint(nq):
+    pk = _pk()
+    rng = np.random.default_rng(600 + nq)
+    gates = (W.grover_gates((2, 1, 0.5, 1.2, 0.3)) + [("D4", nq, 1, 0.4, -1.3, 0.8)] + _gates2(rng, nq, 16)
+             + [("D4", 2, 3, 1.1, 0.7, -0.2), ("CPHASEK", 1, nq, 3)])
+    marked = [int(rng.integers(0, 1 << nq)), 3]
+    psi = _state(rng, nq)
+    plan = pk.Plan({"nq": nq, "gates": gates, "marked": marked})
+    x = _dev(psi)
+    out, _, _ = pk.evaluate(plan, x, want_norm=False)
+    dL = torch.tensor([0.6], dtype=torch.float64, device="cuda")
+    _say("two-qubit backward n_q=%d" % nq)
+    gpsi, gang = pk.backward(plan, out, dL)
+    torch.cuda.synchronize()
+    wpsi, wang = O.adjoint_grad(nq, gates, marked, psi, 0.6)
+    assert _relerr(gpsi.cpu().numpy(), wpsi) <= 1e-10
+    np.testing.assert_allclose(gang.cpu().numpy().reshape(-1, 3), wang, rtol=1e-9, atol=1e-12)
+
+
+def test_gradcheck_with_d4_angles():
+    pk = _pk()
+    nq = 5
+    rng = np.random.default_rng(13)
+    gates = [("HALL",), ("D4", 2, 5, 0.3, 1.1, -0.4), ("CNOT", 1, 3), ("D2", 4, 0.2, 0.9, 0.0), ("ORACLE",),
+             ("HALL",), ("INV",), ("HALL",)]
+    plan = pk.Plan({"nq": nq, "gates": gates, "marked": [6, 19]})
+    psi = _dev(_state(rng, nq)).requires_grad_(True)
+    ang = torch.tensor([0.3, 1.1, -0.4, 0.2, 0.9, 0.0], dtype=torch.float64, device="cuda", requires_grad=True)
+
+    def f(p, a):
+        return pk.grover_eval(plan, p, a)[0]
+
+    assert torch.autograd.gradcheck(f, (psi, ang), eps=1e-6, atol=1e-8, rtol=1e-6)

@@ -269,6 +269,88 @@ def test_backward_schedule_matches_oracle_adjoint(nq, eloc, tiling):
     np.testing.assert_allclose(gang, wang, rtol=0, atol=1e-12)
 
 
+def _random_gates2(rng, nq, count, unitary=True):
+    """Random lists mixing one-qubit gates, diagonal ops and the two-qubit kinds."""
+    gates = []
+    for _ in range(count):
+        r = int(rng.integers(0, 11))
+        q1, q2 = (int(v) for v in rng.choice(np.arange(1, nq + 1), 2, replace=False))
+        if r == 0:
+            gates.append(("H", q1))
+        elif r == 1:
+            gates.append(("D2", q1, *rng.uniform(0, 3, 3)))
+        elif r == 2:
+            gates.append(("ORACLE",))
+        elif r == 3:
+            gates.append(("INV",))
+        elif r == 4:
+            m = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+            if unitary:
+                m, _ = np.linalg.qr(m)
+            gates.append(("TWOOP", q1, q2, m))
+        elif r == 5:
+            gates.append(("CNOT", q1, q2))
+        elif r == 6:
+            gates.append(("CPHASE", q1, q2))
+        elif r == 7:
+            gates.append(("CPHASEK", q1, q2, int(rng.integers(1, 6))))
+        elif r == 8:
+            gates.append(("SWAP", q1, q2))
+        elif r == 9:
+            gates.append(("D4", q1, q2, *rng.uniform(-2, 2, 3)))
+        else:
+            gates.append(("HALL",))
+    return gates
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_two_qubit_gate_schedules_match_oracle(seed):
+    rng = np.random.default_rng(3000 + seed)
+    nq = int(rng.integers(2, 11))
+    gates = _random_gates2(rng, nq, int(rng.integers(1, 30)), unitary=(seed % 2 == 0))
+    marked = sorted({int(v) for v in rng.integers(0, 1 << nq, int(rng.integers(0, 3)))})
+    prob = {"nq": nq, "gates": gates, "marked": marked}
+    tiling = [None, (4, 1, 1), (6, 2, 1), (5, 0, 0), (7, 3, 1)][seed % 5]
+    if tiling and tiling[0] > nq:
+        tiling = None
+    plan, desc = _check_forward(prob, _state(rng, nq), tiling, reg_bits=5 if seed % 3 == 2 else 4)
+    for p in desc["instances"][0]["forward"]:
+        for st in p["stages"]:
+            pairs = {(st["rb"][0], st["rb"][1]) for op in st["ops"] if op["kind"] == "MAT4"}
+            assert len(pairs) <= 1
+
+
+@pytest.mark.parametrize("nq,tiling", [(6, None), (9, (5, 2, 1)), (12, (6, 2, 1)), (11, (4, 0, 0))])
+def test_two_qubit_backward_schedule_matches_oracle_adjoint(nq, tiling):
+    rng = np.random.default_rng(90 + nq)
+    gates = (W.grover_gates((3, 2, 0.4, 1.3, 0.2)) + [("D4", nq, 1, 0.7, -1.1, 0.5), ("CNOT", 2, nq)]
+             + _random_gates2(rng, nq, 10) + [("D4", 2, 3, -0.3, 2.2, 1.0)])
+    prob = {"nq": nq, "gates": gates, "marked": [int(rng.integers(0, 1 << nq)), 1]}
+    psi = _state(rng, nq)
+    plan = pk.Plan(prob)
+    if tiling:
+        plan.set_tiling(*tiling)
+    desc = plan.describe()
+    psi_out, _, _ = O.evaluate(nq, gates, prob["marked"], psi)
+    gpsi, gang = run_backward([prob], desc, 0, psi_out, 0.5)
+    wpsi, wang = O.adjoint_grad(nq, gates, prob["marked"], psi, 0.5)
+    np.testing.assert_allclose(gpsi, wpsi, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(gang, wang, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("bad,msg", [
+    ({"nq": 4, "gates": [("CNOT", 2, 2)], "marked": []}, "second qubit"),
+    ({"nq": 4, "gates": [("SWAP", 1, 5)], "marked": []}, "second qubit"),
+    ({"nq": 4, "gates": [("CPHASEK", 1, 2, 0)], "marked": []}, "CPHASEK"),
+    ({"nq": 4, "gates": [("D4", 1, 2, np.nan, 0.0, 0.0)], "marked": []}, "non-finite"),
+    ({"nq": 4, "gates": [("TWOOP", 1, 2, np.full((4, 4), np.inf))], "marked": []}, "non-finite"),
+])
+def test_create_rejects_bad_two_qubit_gates(bad, msg):
+    with pytest.raises(pk.PaperkernError) as e:
+        pk.Plan(bad)
+    assert msg in str(e.value)
+
+
 def test_batched_plan_schedules_each_instance():
     insts = W.batch_instances(3, count=6, nq_min=3, span=6)
     probs = [{"nq": i["nq"], "gates": i["gates"], "marked": i["marked"]} for i in insts]

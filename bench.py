@@ -10,7 +10,8 @@ FP32 variant's speedup at its stated tolerance, and the CPU oracle's rate.
 
     python bench.py [--steps K] [--warmup W] [--extra]
 
---extra adds the 4096-instance batched form and the n_q = 30 gradient check.
+--extra adds the 4096-instance batched form, the n_q = 30 gradient check and a
+two-qubit (TwoOpA) brickwork circuit at n_q = 30.
 """
 
 import argparse
@@ -234,6 +235,54 @@ def gradient_run(torch, pk, W, nq):
             "backward_passes": len(plan.describe()["instances"][0]["backward"])}
 
 
+def brickwork_gates(nq, seed):
+    """Two layers of random unitary two-qubit gates on neighbouring qubits:
+    (1,2), (3,4), ..., then (2,3), (4,5), ... (seeded, QR of complex normals)."""
+    rng = np.random.default_rng(seed)
+    pairs = [(q, q + 1) for q in range(1, nq, 2)] + [(q, q + 1) for q in range(2, nq, 2)]
+    gates = []
+    for a, b in pairs:
+        m, _ = np.linalg.qr(rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4)))
+        gates.append(("TWOOP", a, b, m))
+    return gates
+
+
+def two_qubit_run(torch, pk, nq, steps):
+    """TwoOpA sweeps (Eq. resmat2) at full size: a brickwork circuit, fused and one
+    sweep per gate; the unitary circuit must keep the norm."""
+    gates = brickwork_gates(nq, 5)
+    N = 1 << nq
+    x = torch.randn(N, dtype=torch.complex128, device="cuda")
+    x /= torch.linalg.vector_norm(x)
+    y = torch.empty_like(x)
+    L = torch.empty(1, dtype=torch.float64, device="cuda")
+    norm = torch.empty(1, dtype=torch.float64, device="cuda")
+    out = {"workload": "brickwork of %d random unitary TwoOpA gates on neighbouring qubits, n_q=%d, FP64"
+                       % (len(gates), nq), "gates": len(gates)}
+    for label, fuse in (("fused", 1), ("unfused", 0)):
+        plan = pk.Plan({"nq": nq, "gates": gates, "marked": [0]})
+        if not fuse:
+            plan.set_tiling(13, 4, 0)
+        pk.evaluate_into(plan, x, y, L, norm)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = steps if fuse else 2
+        e0.record()
+        for _ in range(reps):
+            pk.evaluate_into(plan, x, y, L, norm)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        per_pass = [float(t) for t in pk.time_passes(plan, x, y)]
+        out[label] = {"passes": plan.passes(), "ms": ms, "gates_per_s": len(gates) / (ms * 1e-3),
+                      "mean_pass_GBs": 32.0 * N / (np.mean(per_pass) * 1e-3) / 1e9,
+                      "min_pass_GBs": 32.0 * N / (max(per_pass) * 1e-3) / 1e9,
+                      "norm_minus_1": float(norm.item()) - 1.0}
+        log("two-qubit %s: %d passes, %.2f ms" % (label, plan.passes(), ms))
+    out["fused_speedup"] = out["unfused"]["ms"] / out["fused"]["ms"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +369,8 @@ def main():
         line["batched"] = {p: batched_run(torch, pk, W, autotune, max(3, args.steps // 4), 1, p) for p in ("fp64", "fp32")}
         torch.cuda.empty_cache()
         line["gradient"] = gradient_run(torch, pk, W, nq)
+        torch.cuda.empty_cache()
+        line["two_qubit"] = two_qubit_run(torch, pk, nq, max(3, args.steps // 4))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(W, nq, 2 * nq + 2)
     print(json.dumps(line), flush=True)

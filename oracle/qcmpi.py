@@ -24,6 +24,13 @@ Gate lists are sequences of tuples, applied left to right (first tuple first):
   ("CPHASEK", is1, is2, k)        diag(1, 1, 1, e^{2 pi i / 2^k}) (Eq. cphasek)
   ("SWAP", is1, is2)              exchanges the two qubits (the QFT of App. A)
   ("D4", is1, is2, alpha, beta, gamma)  Wigner D^(3/2) two-qubit noise (Sec. 6.3)
+  ("QFT", first, n)               quantum Fourier transform of the register of qubits
+                                  first .. first+n-1 (App. A), applied by its definition
+                                  <n|QFT|n'> = N^(-1/2) e^{2 pi i n n'/N}, N = 2^n
+
+The Shor section (Sec. 7 steps 1-6, App. A) adds the register sizes, the
+loaded state of Eq. Shor2, the QFT ladder of App. A as a gate list, the
+register-1 marginal p(n) = sum_k |C_{n,k}|^2 and its closed form (Eq. probshor).
 """
 
 import math
@@ -44,6 +51,8 @@ __all__ = [
     "CNOT", "CPHASE", "SWAP", "cphasek", "apply_twoop", "apply_twoop_loop",
     "wigner_small_d", "wigner_small_d_prime", "wigner_d", "d4_matrix", "d4_derivatives",
     "kron_twoop", "TWO_QUBIT", "PARAMETRIC",
+    "ceil_log2", "shor_register_sizes", "shor_f", "shor_state", "qft_register", "qft_gates",
+    "marginal", "multiplicative_order", "probshor_marginal",
 ]
 
 # ---------------------------------------------------------------------------
@@ -438,6 +447,8 @@ def apply_gate(psi, nq, gate, marked):
         return oracle_flip(psi, marked)
     if kind == "INV":
         return inversion(psi)
+    if kind == "QFT":
+        return qft_register(psi, nq, gate[1], gate[2])
     raise ValueError("unknown gate kind %r" % (kind,))
 
 
@@ -446,6 +457,8 @@ def apply_gate_adjoint(psi, nq, gate, marked):
     kind = gate[0]
     if kind in ("H", "ONEOP", "D2") or kind in TWO_QUBIT:
         return _apply_matrix(psi, nq, gate, _gate_matrix(gate).conj().T)
+    if kind == "QFT":
+        return qft_register(psi, nq, gate[1], gate[2], inverse=True)
     return apply_gate(psi, nq, gate, marked)
 
 
@@ -720,3 +733,142 @@ def grover_sampled(nq, gates, marked, psi_in, indices):
     vals = f(idx)
     L = math.fsum(float(abs(v) ** 2) for v in f(Ms)) if len(Ms) else 0.0
     return vals, L
+
+
+# ---------------------------------------------------------------------------
+# Shor's data path (Sec. 7 steps 1-6) and the QFT (App. A)
+# ---------------------------------------------------------------------------
+
+
+def ceil_log2(x):
+    """Smallest integer e with 2^e >= x, for an integer x >= 1 (exact)."""
+    x = int(x)
+    if x < 1:
+        raise ValueError("ceil_log2 needs x >= 1")
+    return (x - 1).bit_length()
+
+
+def shor_register_sizes(M):
+    """(n_1, n_2) of Step 1: n_1 = Ceiling(log2 Q) with Q = 2^Ceiling(log2 M^2), so
+    that register one holds M^2; n_2 = Ceiling(log2 M), so that register two
+    holds every value below M."""
+    M = int(M)
+    if M < 2:
+        raise ValueError("M must be at least 2")
+    Q = 1 << ceil_log2(M * M)
+    return ceil_log2(Q), ceil_log2(M)
+
+
+def shor_f(xguess, M, n1):
+    """f(j) = xguess^j mod M for j = 0 .. 2^n_1 - 1 (Step 3, Eq. fperiod), by
+    repeated multiplication in Python integers."""
+    out = np.empty(1 << n1, dtype=np.int64)
+    v = 1 % M
+    for j in range(1 << n1):
+        out[j] = v
+        v = (v * xguess) % M
+    return out
+
+
+def shor_state(n1, n2, xguess, M):
+    """The loaded two-register state of Eq. Shor2:
+    |Psi> = 2^(-n_1/2) sum_n |n>_{n_1} |f(n)>_{n_2}, register one on qubits
+    1 .. n_1 (the high bits), so the amplitude of |n>|f(n)> sits at label
+    n 2^(n_2) + f(n).  The amplitude is the correctly rounded double of
+    2^(-n_1/2): sqrt(2) (correctly rounded) times an exact power of two."""
+    if M > (1 << n2):
+        raise ValueError("register two cannot hold M")
+    amp = 2.0 ** (-(n1 // 2)) if n1 % 2 == 0 else math.sqrt(2.0) * 2.0 ** (-((n1 + 1) // 2))
+    psi = np.zeros(1 << (n1 + n2), dtype=np.complex128)
+    f = shor_f(xguess, M, n1)
+    psi[(np.arange(1 << n1, dtype=np.int64) << n2) + f] = amp
+    return psi
+
+
+def qft_register(psi, nq, first, n, inverse=False):
+    """QFT of the register of qubits first .. first+n-1 (App. A):
+    <n|QFT|n'> = N^(-1/2) e^{2 pi i n n'/N}, N = 2^n, i.e. sqrt(N) times the
+    inverse DFT along that register's axis (numpy.fft.ifft; the adjoint is
+    N^(-1/2) times the forward DFT)."""
+    if not (1 <= first and n >= 1 and first + n - 1 <= nq):
+        raise ValueError("register out of range")
+    psi = np.asarray(psi, dtype=np.complex128)
+    hi = 1 << (first - 1)
+    lo = 1 << (nq - first - n + 1)
+    v = psi.reshape(hi, 1 << n, lo)
+    N = float(1 << n)
+    if inverse:
+        out = np.fft.fft(v, axis=1) / math.sqrt(N)
+    else:
+        out = np.fft.ifft(v, axis=1) * math.sqrt(N)
+    return out.reshape(-1)
+
+
+def qft_gates(n1, first=1):
+    """The QFT circuit of App. A as a gate list, on qubits first .. first+n_1-1:
+    for each qubit ic of the register a Hadamard, then CPHASEK between qubit ic
+    and each later qubit k with exponent k + 1 - ic (register-relative labels);
+    the Hadamard on the last qubit; then pair swaps (i, n_1 + 1 - i) that
+    restore standard order."""
+    g = []
+    o = first - 1
+    for ic in range(1, n1):
+        g.append(("H", o + ic))
+        for k in range(ic + 1, n1 + 1):
+            g.append(("CPHASEK", o + k, o + ic, k + 1 - ic))
+    g.append(("H", o + n1))
+    for i in range(1, n1 // 2 + 1):
+        g.append(("SWAP", o + i, o + n1 + 1 - i))
+    return g
+
+
+def marginal(psi, nq, n_low):
+    """p(n) = sum_k |C_{n,k}|^2 over the n_low low qubits (register two), for every
+    value n of the high nq - n_low qubits: the distribution of a measurement of
+    register one (Step 6).  FP64 sums."""
+    psi = np.asarray(psi, dtype=np.complex128)
+    v = psi.reshape(-1, 1 << n_low)
+    return (v.real ** 2 + v.imag ** 2).sum(axis=1)
+
+
+def multiplicative_order(xguess, M):
+    """The period r of f (Eq. fperiod): the smallest r > 0 with xguess^r = 1 mod M
+    (brute force; needs gcd(xguess, M) = 1)."""
+    if math.gcd(int(xguess), int(M)) != 1:
+        raise ValueError("xguess must be coprime to M")
+    v, r = xguess % M, 1
+    while v != 1 % M:
+        v = (v * xguess) % M
+        r += 1
+    return r
+
+
+def probshor_marginal(n1, xguess, M):
+    """Closed form of the register-one distribution after the QFT (Eqs. QFT1,
+    QFT2, probshor).  With N = 2^n_1 and the period r, the r register-two values
+    k = f(n_k), n_k = 0 .. r-1, each appear D_k = ceil((N - n_k)/r) times, and
+
+        |C_{n,k}|^2 = N^-2 [sin(D_k pi n r/N) / sin(pi n r/N)]^2,
+
+    which is D_k^2 / N^2 where n r/N is an integer (the 0/0 limit, the sum of D_k
+    ones).  Returns p(n) = sum_k |C_{n,k}|^2, n = 0 .. N-1.  Both sines are taken
+    of exactly reduced arguments (n r mod N, D n r mod N), since only sin^2
+    enters."""
+    N = 1 << n1
+    r = multiplicative_order(xguess, M)
+    n = np.arange(N, dtype=np.int64)
+    a = (n * r) % N
+    s1 = np.sin(np.pi * a / N)
+    p = np.zeros(N)
+    # D_k takes at most two values; group the k by it
+    counts = {}
+    for nk in range(r):
+        d = (N - nk + r - 1) // r
+        counts[d] = counts.get(d, 0) + 1
+    for d, cnt in counts.items():
+        b = (d * a) % N
+        s2 = np.sin(np.pi * b / N)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ratio2 = np.where(a == 0, float(d) * d, (s2 / np.where(a == 0, 1.0, s1)) ** 2)
+        p += cnt * ratio2 / (float(N) * N)
+    return p

@@ -523,3 +523,120 @@ def test_generator_draw_order_and_domains():
     batch = W.batch_instances(3, count=64)
     assert batch[0]["noise"] is None
     assert all(10 <= b["nq"] <= 19 for b in batch)
+
+
+# --------------------------------------------------------------------------- Shor data path and QFT
+
+
+def _golden_shor(tag):
+    rows = []
+    with open(os.path.join(GOLDEN, "shor_examples.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith(tag + ":"):
+                head, vals = line[len(tag) + 1:].split(":")
+                rows.append(([int(v) for v in head.split()], [int(v) for v in vals.split()]))
+    assert rows
+    return rows
+
+
+def test_shor_register_sizes_match_paper_examples():
+    for (M,), (n1, n2) in _golden_shor("sizes"):
+        assert O.shor_register_sizes(M) == (n1, n2)
+    # the defining inequalities, brute force over a range of M
+    for M in range(3, 400):
+        n1, n2 = O.shor_register_sizes(M)
+        assert 2 ** (n1 - 1) < M * M <= 2 ** n1
+        assert 2 ** (n2 - 1) < M <= 2 ** n2
+
+
+def test_shor_f_and_period_match_hand_values():
+    for (M, x), vals in _golden_shor("f"):
+        f = O.shor_f(x, M, 4)
+        np.testing.assert_array_equal(f[: len(vals)], vals)
+        r = O.multiplicative_order(x, M)
+        assert pow(x, r, M) == 1 and all(pow(x, q, M) != 1 for q in range(1, r))
+        np.testing.assert_array_equal(f[: len(vals)], [pow(x, j, M) for j in range(len(vals))])
+    with pytest.raises(ValueError):
+        O.multiplicative_order(3, 21)
+
+
+def test_shor_state_structure_and_rounded_amplitude():
+    from decimal import Decimal, getcontext
+
+    getcontext().prec = 60
+    for n1, n2, x, M in ((8, 4, 7, 15), (9, 5, 2, 21), (7, 3, 3, 5), (5, 3, 2, 7)):
+        psi = O.shor_state(n1, n2, x, M)
+        rows = psi.reshape(1 << n1, 1 << n2)
+        nz = np.nonzero(rows)
+        assert len(nz[0]) == 1 << n1 and (np.diff(nz[0]) == 1).all()  # one entry per row
+        np.testing.assert_array_equal(nz[1], [pow(x, j, M) for j in range(1 << n1)])
+        want = float(Decimal(2) ** (Decimal(-n1) / 2))  # correctly rounded 2^(-n1/2)
+        assert (rows[nz].real == want).all() and (rows[nz].imag == 0).all()
+        assert abs(np.vdot(psi, psi).real - 1.0) < 1e-14
+
+
+def test_qft_small_matrix_by_hand():
+    # N = 4: <n|QFT|n'> = i^(n n') / 2
+    want = 0.5 * np.array([[1, 1, 1, 1], [1, 1j, -1, -1j], [1, -1, 1, -1], [1, -1j, -1, 1j]])
+    cols = [O.qft_register(np.eye(4)[:, c], 2, 1, 2) for c in range(4)]
+    np.testing.assert_allclose(np.array(cols).T, want, atol=1e-15)
+
+
+def test_qft_basis_states_and_unitarity():
+    nq, n = 3, 3
+    N = 1 << n
+    for m in range(N):
+        e = np.zeros(N, dtype=complex)
+        e[m] = 1.0
+        out = O.qft_register(e, nq, 1, n)
+        for k in range(N):
+            ang = 2 * math.pi * ((m * k) % N) / N
+            assert abs(out[k] - complex(math.cos(ang), math.sin(ang)) / math.sqrt(N)) < 1e-15
+    rng = np.random.default_rng(11)
+    v = _rand_state(rng, 7)
+    back = O.apply_gate_adjoint(O.apply_gate(v, 7, ("QFT", 2, 4), []), 7, ("QFT", 2, 4), [])
+    np.testing.assert_allclose(back, v, atol=1e-15)
+
+
+@pytest.mark.parametrize("nq,first,n", [(5, 1, 5), (7, 1, 4), (8, 3, 4), (9, 2, 7), (6, 4, 3), (6, 6, 1)])
+def test_qft_ladder_of_appendix_a_equals_the_dft(nq, first, n):
+    rng = np.random.default_rng(nq * 100 + first * 10 + n)
+    v = _rand_state(rng, nq)
+    ladder = v.copy()
+    for g in O.qft_gates(n, first):
+        ladder = O.apply_gate(ladder, nq, g, [])
+    np.testing.assert_allclose(ladder, O.qft_register(v, nq, first, n), rtol=0, atol=1e-14)
+    # and through dense Kronecker products (tiny sizes)
+    if nq <= 6:
+        u = O.dense_circuit(nq, O.qft_gates(n, first), [])
+        np.testing.assert_allclose(u @ v, ladder, atol=1e-14)
+
+
+def test_marginal_brute_force():
+    rng = np.random.default_rng(5)
+    v = _rand_state(rng, 6) * 1.7
+    for n_low in range(0, 7):
+        want = [sum(abs(v[(n << n_low) + k]) ** 2 for k in range(1 << n_low)) for n in range(1 << (6 - n_low))]
+        np.testing.assert_allclose(O.marginal(v, 6, n_low), want, rtol=1e-14)
+
+
+def test_probshor_peaks_special_case():
+    for (n1, M, x), peaks in _golden_shor("peaks"):
+        p = O.probshor_marginal(n1, x, M)
+        r = O.multiplicative_order(x, M)
+        want = np.zeros(1 << n1)
+        want[peaks] = 1.0 / r
+        np.testing.assert_allclose(p, want, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("M,x", [(15, 7), (15, 2), (21, 2), (21, 5), (33, 5), (35, 3), (39, 7), (55, 2)])
+def test_probshor_closed_form_equals_qft_of_loaded_state(M, x):
+    n1, n2 = O.shor_register_sizes(M)
+    if n1 + n2 > 18:
+        n1 = 18 - n2  # smaller register one: the closed form holds for any n1
+    psi = O.shor_state(n1, n2, x, M)
+    p = O.marginal(O.qft_register(psi, n1 + n2, 1, n1), n1 + n2, n2)
+    q = O.probshor_marginal(n1, x, M)
+    np.testing.assert_allclose(p, q, rtol=0, atol=1e-14)
+    assert abs(q.sum() - 1.0) < 1e-12

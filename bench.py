@@ -10,8 +10,9 @@ FP32 variant's speedup at its stated tolerance, and the CPU oracle's rate.
 
     python bench.py [--steps K] [--warmup W] [--extra]
 
---extra adds the 4096-instance batched form, the n_q = 30 gradient check and a
-two-qubit (TwoOpA) brickwork circuit at n_q = 30.
+--extra adds the 4096-instance batched form, the n_q = 30 gradient check, a
+two-qubit (TwoOpA) brickwork circuit at n_q = 30 and Shor's data path at n_q = 30
+(load, QFT of register one, marginal; M = 899).
 """
 
 import argparse
@@ -283,6 +284,61 @@ def two_qubit_run(torch, pk, nq, steps):
     return out
 
 
+def shor_run(torch, pk, W, steps, prec):
+    """Shor's data path at n_q = 30 (Sec. 7): the loaded state of Eq. Shor2, the QFT
+    of register one (App. A) in place, and the distribution of register one; each
+    part timed with HIP events on the current stream."""
+    M = W.SHOR_M
+    x = W.shor_xguess(W.SEEDS["shor"])
+    n1, n2 = pk.shor_register_sizes(M)
+    nq = n1 + n2
+    N = 1 << nq
+    esz = 16 if prec == "fp64" else 8
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    psi = torch.empty(N, dtype=dt, device="cuda")
+    p = torch.empty(1 << n1, dtype=torch.float64, device="cuda")
+    L = torch.empty(1, dtype=torch.float64, device="cuda")
+    plan = pk.Plan({"nq": nq, "gates": [("QFT", 1, n1)], "marked": []}, prec=prec)
+
+    def run(ev=None):
+        if ev:
+            ev[0].record()
+        pk.shor_state(n1, n2, x, M, prec=prec, out=psi)
+        if ev:
+            ev[1].record()
+        pk.evaluate_into(plan, psi, psi, L)
+        if ev:
+            ev[2].record()
+        pk.marginal(psi, nq, n2, out=p)
+        if ev:
+            ev[3].record()
+
+    run()
+    torch.cuda.synchronize()
+    parts = np.zeros(3)
+    for _ in range(steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        run(ev)
+        torch.cuda.synchronize()
+        parts += [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
+    parts /= steps
+    per_pass = [float(t) for t in pk.time_passes(plan, psi, psi)]
+    run()
+    sum_p = float(p.sum().item())
+    ms = float(parts.sum())
+    out = {"workload": "Shor data path, M=%d xguess=%d: n1=%d, n2=%d (n_q=%d), %s" % (M, x, n1, n2, nq, prec.upper()),
+           "ms": ms, "runs_per_s": 1e3 / ms, "qft_passes": plan.passes(),
+           "load_ms": parts[0], "qft_ms": parts[1], "marginal_ms": parts[2],
+           "load_GBs": esz * N / (parts[0] * 1e-3) / 1e9,
+           "qft_mean_pass_GBs": 2.0 * esz * N / (np.mean(per_pass) * 1e-3) / 1e9,
+           "qft_min_pass_GBs": 2.0 * esz * N / (max(per_pass) * 1e-3) / 1e9,
+           "marginal_GBs": esz * N / (parts[2] * 1e-3) / 1e9, "sum_p_minus_1": sum_p - 1.0}
+    log("shor %s: load %.2f ms, QFT %.2f ms (%d passes), marginal %.2f ms"
+        % (prec, parts[0], parts[1], plan.passes(), parts[2]))
+    del psi
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -371,6 +427,9 @@ def main():
         line["gradient"] = gradient_run(torch, pk, W, nq)
         torch.cuda.empty_cache()
         line["two_qubit"] = two_qubit_run(torch, pk, nq, max(3, args.steps // 4))
+        torch.cuda.empty_cache()
+        line["shor"] = {p: shor_run(torch, pk, W, max(3, args.steps // 4), p) for p in ("fp64", "fp32")}
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(W, nq, 2 * nq + 2)
     print(json.dumps(line), flush=True)

@@ -67,6 +67,11 @@ extern "C" {
 #define PK_GATE_D4 11     /* D^(3/2)(alpha, beta, gamma), the two-qubit noise of Sec. 6.3:
                              Wigner's j = 3/2 function with the D2 Euler convention, rows and
                              columns m = 3/2 - (2 q_is1 + q_is2)                               */
+#define PK_GATE_QFT 12    /* quantum Fourier transform of the register of qubits is1 .. is1+k-1
+                             (k >= 1, is2 = 0): <n|QFT|n'> = 2^(-k/2) e^{2 pi i n n' / 2^k}, n the
+                             register's value with qubit is1 most significant (App. A).  Lowered
+                             to the circuit of App. A: Hadamards, CPHASEK(q, ic, q + 1 - ic) and
+                             the pair swaps that restore standard order                         */
 
 /* ---- workspace queries ----------------------------------------------------------- */
 #define PK_OP_EVAL 0
@@ -77,7 +82,7 @@ typedef struct pk_gate {
     int32_t is1;      /* target qubit, 1..n_q (1 = most significant); ignored for
                          HALL, ORACLE and INV                                             */
     int32_t is2;      /* second qubit of a two-qubit gate, 1..n_q, != is1; else 0         */
-    int32_t k;        /* CPHASEK only: the exponent k (1..62); else 0                      */
+    int32_t k;        /* CPHASEK: the exponent k (1..62); QFT: the register size; else 0   */
     double op[32];    /* ONEOP: row-major 2x2 complex in op[0..7], op[2*(2a+b)] = Re<a|Op|b>,
                          op[2*(2a+b)+1] = Im<a|Op|b>; TWOOP: row-major 4x4 complex in
                          op[0..31], op[2*(4a+b)] = Re<a|V|b> with a, b = 2 q_is1 + q_is2;
@@ -99,7 +104,10 @@ typedef struct pk_plan pk_plan;
  * pk_create -- validate n_inst problems and compile their pass schedules.
  * Gates on distinct qubits commute and diagonal gates commute with each other;
  * the compiler uses only those two facts to group gates into passes over the
- * state (each pass reads and writes every amplitude once).  The schedule is host
+ * state (each pass reads and writes every amplitude once).  Controlled phases
+ * (CPHASE, CPHASEK) run in any pass their order allows, whatever the tile; a
+ * SWAP of two qubits that are both inside a pass's tile moves no data (the
+ * tile is written back with the two qubits exchanged).  The schedule is host
  * data; device tables are uploaded on first use.  Errors: PK_EINVAL for nq out of
  * range, a qubit label outside 1..nq, nonzero is2/k, non-finite op or angle,
  * duplicate or out-of-range marked labels, n_inst < 1, unknown prec or kind;
@@ -244,6 +252,35 @@ int pk_backward(pk_plan* plan, const void* psi_out, const double* dL, void* grad
  */
 int pk_pair_indices(int32_t nq, int32_t i_s, int64_t first, int64_t count, int64_t* n0,
                     int64_t* n1, void* stream);
+
+/*
+ * pk_shor_state -- the loaded two-register state of Shor's algorithm (Sec. 7,
+ * Step 3, Eq. Shor2): register one (n1 qubits, qubits 1..n1, the high bits)
+ * holds every n < 2^n1 with equal weight and register two (n2 qubits, the low
+ * bits) holds f(n) = xguess^n mod M:
+ *     psi[n * 2^n2 + f(n)] = 2^(-n1/2),  every other amplitude 0.
+ *   n1, n2   register sizes: n1, n2 >= 1, n1 + n2 <= 30 (PK_FP64) or 31 (PK_FP32)
+ *   xguess   1 .. M-1 (Step 3 takes it coprime to M; not checked)
+ *   M        2 <= M <= 2^n2, M < 2^31
+ *   psi      device, 2^(n1+n2) complex of `prec`, written entirely (16-byte aligned)
+ * f is exact (64-bit integer arithmetic); the amplitude is the correctly rounded
+ * 2^(-n1/2) (FP32: that double rounded to float).  PK_EINVAL on any range error.
+ * Errors are reported through pk_last_error(NULL).
+ */
+int pk_shor_state(int32_t n1, int32_t n2, int64_t xguess, int64_t M, int32_t prec, void* psi, void* stream);
+
+/*
+ * pk_marginal -- the distribution of a measurement of the high nq - n_low qubits
+ * (Shor's register one, Step 6):
+ *     p[n] = sum_{k < 2^n_low} |psi[n * 2^n_low + k]|^2,  n < 2^(nq - n_low).
+ *   psi  device, 2^nq complex of `prec`, read (16-byte aligned)
+ *   p    device double[2^(nq - n_low)], written (8-byte aligned)
+ * FP64 sums (FP32 amplitudes are widened first) in an order fixed by n_low, so
+ * results are reproducible.  One read of the state; with fewer than ~1000
+ * segments of 2^14 or more amplitudes the launch cannot fill the GPU.
+ * PK_EINVAL for nq out of range, n_low outside 0..nq, NULL or misaligned pointers.
+ */
+int pk_marginal(int32_t nq, int32_t n_low, int32_t prec, const void* psi, double* p, void* stream);
 
 /*
  * pk_time_passes -- measurement helper: runs one evaluation of a single-instance

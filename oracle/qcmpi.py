@@ -52,7 +52,7 @@ __all__ = [
     "wigner_small_d", "wigner_small_d_prime", "wigner_d", "d4_matrix", "d4_derivatives",
     "kron_twoop", "TWO_QUBIT", "PARAMETRIC",
     "ceil_log2", "shor_register_sizes", "shor_f", "shor_state", "qft_register", "qft_gates",
-    "marginal", "multiplicative_order", "probshor_marginal",
+    "marginal", "multiplicative_order", "probshor_marginal", "shor_qft_amplitudes",
 ]
 
 # ---------------------------------------------------------------------------
@@ -872,3 +872,31 @@ def probshor_marginal(n1, xguess, M):
             ratio2 = np.where(a == 0, float(d) * d, (s2 / np.where(a == 0, 1.0, s1)) ** 2)
         p += cnt * ratio2 / (float(N) * N)
     return p
+
+
+def shor_qft_amplitudes(n1, n2, xguess, M, labels):
+    """Amplitudes of QFT(register one) applied to the state of Eq. Shor2, at chosen
+    labels n 2^n2 + k, for any n1 (Eq. QFT1 before the sum over j is done):
+
+        C_{n,k} = N^-1 sum_{j < N, f(j) = k} e^{2 pi i n j / N},   N = 2^n1,
+
+    with j running over n_k + d r (n_k < r the first j with f(j) = k, r the period);
+    zero when k is not a value of f.  Each phase is taken of the exactly reduced
+    n j mod N."""
+    N = 1 << n1
+    r = multiplicative_order(xguess, M)
+    first = {}
+    v = 1 % M
+    for j in range(r):
+        first.setdefault(v, j)
+        v = (v * xguess) % M
+    labels = np.asarray(labels, dtype=np.int64)
+    out = np.zeros(len(labels), dtype=np.complex128)
+    for i, lab in enumerate(labels):
+        n, k = int(lab) >> n2, int(lab) & ((1 << n2) - 1)
+        if k not in first:
+            continue
+        j = np.arange(first[k], N, r, dtype=np.int64)
+        ph = (n * j) % N
+        out[i] = np.exp(2j * np.pi * ph / N).sum() / N
+    return out

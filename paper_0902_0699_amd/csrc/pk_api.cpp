@@ -1,6 +1,7 @@
 // The C-ABI of libpaperkern: argument checks, device tables, graph capture.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -107,6 +108,7 @@ int ensure_device(DevPlan* d) {
     put(buf, t.passes, P.passes);
     put(buf, t.stages, P.stages);
     put(buf, t.flips, P.flips);
+    put(buf, t.phases, P.phases);
     put(buf, t.mats, P.static_mats);
     put(buf, t.mats + P.static_mats.size() * sizeof(double), P.default_angles);
     put(buf, t.mats4, P.static_mats4);
@@ -159,6 +161,7 @@ PassLaunch base_launch(DevPlan* d, void* ws, int op) {
     L.passes = at<Pass>(P.d_tables, t.passes);
     L.stages = at<Stage>(P.d_tables, t.stages);
     L.flips = at<Flip>(P.d_tables, t.flips);
+    L.phases = at<PhaseOp>(P.d_tables, t.phases);
     L.mats = at<double>(ws, w.mats);
     L.mats4 = at<double>(ws, w.mats4);
     L.partials = at<double>(ws, w.partials);
@@ -541,6 +544,32 @@ int pk_pair_indices(int32_t nq, int32_t i_s, int64_t first, int64_t count, int64
     if (count > 0 && (!n0 || !n1)) return fail(nullptr, PK_EINVAL, "NULL output");
     hipError_t e = launch_pairs(nq, i_s, first, count, n0, n1, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? PK_OK : hip_fail(nullptr, e, "pair_index_kernel");
+}
+
+int pk_shor_state(int32_t n1, int32_t n2, int64_t xguess, int64_t M, int32_t prec, void* psi, void* stream) {
+    if (prec != PK_FP64 && prec != PK_FP32) return fail(nullptr, PK_EINVAL, "prec must be PK_FP64 or PK_FP32");
+    const int nq_max = prec == PK_FP64 ? 30 : 31;
+    if (n1 < 1 || n2 < 1 || n1 + n2 > nq_max) return fail(nullptr, PK_EINVAL, "register sizes out of range");
+    if (M < 2 || M > ((int64_t)1 << n2) || M >= ((int64_t)1 << 31))
+        return fail(nullptr, PK_EINVAL, "M must satisfy 2 <= M <= 2^n2 and M < 2^31");
+    if (xguess < 1 || xguess >= M) return fail(nullptr, PK_EINVAL, "xguess must lie in 1..M-1");
+    if (!psi || (reinterpret_cast<uintptr_t>(psi) & 15)) return fail(nullptr, PK_EINVAL, "psi NULL or not 16-byte aligned");
+    // the correctly rounded 2^(-n1/2): an exact power of two, or sqrt(2) (correctly
+    // rounded by IEEE sqrt) times one
+    const double amp = (n1 % 2 == 0) ? std::ldexp(1.0, -n1 / 2) : std::ldexp(std::sqrt(2.0), -(n1 + 1) / 2);
+    hipError_t e = launch_shor_state(n1, n2, (uint64_t)xguess, (uint64_t)M, prec == PK_FP64, amp, psi,
+                                     static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? PK_OK : hip_fail(nullptr, e, "shor_state_kernel");
+}
+
+int pk_marginal(int32_t nq, int32_t n_low, int32_t prec, const void* psi, double* p, void* stream) {
+    if (prec != PK_FP64 && prec != PK_FP32) return fail(nullptr, PK_EINVAL, "prec must be PK_FP64 or PK_FP32");
+    if (nq < 1 || nq > (prec == PK_FP64 ? 30 : 31)) return fail(nullptr, PK_EINVAL, "nq out of range");
+    if (n_low < 0 || n_low > nq) return fail(nullptr, PK_EINVAL, "n_low out of 0..nq");
+    if (!psi || !p || (reinterpret_cast<uintptr_t>(psi) & 15) || (reinterpret_cast<uintptr_t>(p) & 7))
+        return fail(nullptr, PK_EINVAL, "NULL or misaligned pointer");
+    hipError_t e = launch_marginal(nq, n_low, prec == PK_FP64, psi, p, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? PK_OK : hip_fail(nullptr, e, "marginal_kernel");
 }
 
 int pk_time_passes(pk_plan* plan, const void* psi_in, void* psi_out, double* L_out, const double* angles,

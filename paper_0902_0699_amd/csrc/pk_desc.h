@@ -31,6 +31,23 @@ enum OpKind : int32_t {
     OP_D2BWD = 6,  // backward D2: psi <- D^H psi, grad += Re<lambda|dD|psi>, lambda <- D^H lambda
     OP_MAT4 = 7,   // 4x4 complex matrix mats4[arg] on register bits 0 (qubit is1) and 1 (qubit is2)
     OP_D4BWD = 8,  // backward D4 on register bits 0 and 1, as OP_D2BWD with 4x4 matrices
+    OP_PHASE = 9,  // controlled phase (CPHASE, CPHASEK): e^{i theta} where both bits are 1
+};
+
+constexpr int kPhaseSlots = 4;  // phase accumulators per sub-stage
+
+// One controlled phase as the kernel applies it in a sub-stage.  The amplitudes
+// whose two qubits are both 1 get the factor c + i s.  Each qubit's bit sits on
+// a register bit, on the thread's part of the local label, or in the tile index
+// (a qubit outside the tile, so the same for the whole tile).  The register
+// bits involved define the phase's accumulator slot (Stage::phase_pm); a thread
+// multiplies the factors of a slot together and applies the product once to
+// every register whose index has the slot's register bits set.
+struct PhaseOp {
+    int32_t slot;    // accumulator slot of the sub-stage
+    uint32_t tmask;  // local label bits held by the thread index that must be 1
+    int64_t fmask;   // tile-index bits that must be 1
+    double c, s;
 };
 
 // One step of a stage's op list, as the plan compiler schedules it on the host;
@@ -48,8 +65,9 @@ struct Op {
 // them with scalar loads from the constant address space.
 //
 // One sub-stage: a fixed sequence of optional steps applied to the registers,
-// in this order: seed, flip, matrix, Hadamards (mask 1), flip, Hadamards
-// (mask 2), matrix, 4x4 matrix, backward D2, backward D4, scale, read.  A stage's op list is packed into
+// in this order: seed, flip, controlled phases, matrix, Hadamards (mask 1),
+// flip, Hadamards (mask 2), matrix, 4x4 matrix, backward D2, backward D4,
+// scale, read.  A stage's op list is packed into
 // as many sub-stages as its order needs; only the first of them exchanges the
 // tile through LDS (`exchange`), the others keep the layout.  Straight-line
 // steps instead of an op loop let the compiler update the register tile in
@@ -60,6 +78,9 @@ struct Stage {
     int32_t exchange;         // 1: move the tile into this layout through LDS first
     int32_t seed;             // flip index of a SEED (backward start) or -1
     int32_t flip_pre;         // flip index or -1
+    int32_t phase_first;      // first PhaseOp of this sub-stage's controlled phases
+    int32_t phase_count;      // number of them (diagonal: any order)
+    int32_t phase_pm[kPhaseSlots];  // register-bit mask of each accumulator slot, -1 when unused
     int32_t mat_pre_a;        // register bit of a matrix before the Hadamards, or -1
     int32_t mat_pre;          // its matrix index
     int32_t hmask1;           // register bits that get a Hadamard
@@ -116,8 +137,11 @@ struct Pass {
     int32_t rbits;       // register bits per thread
     int32_t ntrun;       // runs of consecutive tile bits
     int32_t nfrun;       // runs of consecutive free bits
-    int32_t tpos[16];    // global bit position of local tile bit l
-    Run trun[kMaxRuns];  // local tile label -> state label
+    int32_t nstrun;      // runs of the store map
+    int32_t tpos[16];    // global bit position of local tile bit l when the tile is read
+    int32_t stpos[16];   // ... when it is written (differs after SWAPs done by relabelling)
+    Run trun[kMaxRuns];  // local tile label -> state label (read)
+    Run strun[kMaxRuns]; // local tile label -> state label (write)
     Run frun[kMaxRuns];  // tile index -> state label
 };
 

@@ -40,6 +40,7 @@ struct KArgs {
     const Pass* passes;
     const Stage* stages;
     const Flip* flips;
+    const PhaseOp* phases;
     const double* mats;
     const double* mats4;  // 4x4 complex matrices of two-qubit gates, 32 doubles each
     const void* src0;  // vector 0 input of the first pass
@@ -124,12 +125,15 @@ struct GOff {
     int64_t g[kMaxRegBits];
 };
 
+// `store` selects the map the tile is written with (SWAPs done by relabelling
+// make it differ from the map it is read with).
 __device__ __forceinline__ GOff make_goff(const PK_CONST Pass* P, const PK_CONST Stage* S, const Layout& L,
-                                          int nrb) {
+                                          int nrb, bool store) {
     GOff G;
-    G.gt = deposit((int64_t)L.jt, P->trun, P->ntrun);
+    G.gt = store ? deposit((int64_t)L.jt, P->strun, P->nstrun) : deposit((int64_t)L.jt, P->trun, P->ntrun);
+    const PK_CONST int32_t* pos = store ? P->stpos : P->tpos;
 #pragma unroll
-    for (int a = 0; a < kMaxRegBits; ++a) G.g[a] = a < nrb ? ((int64_t)1 << P->tpos[S->rb[a]]) : 0;
+    for (int a = 0; a < kMaxRegBits; ++a) G.g[a] = a < nrb ? ((int64_t)1 << pos[S->rb[a]]) : 0;
     return G;
 }
 
@@ -288,6 +292,54 @@ __device__ __forceinline__ void op_d4bwd(T (&v)[NV][NR], const PK_CONST double* 
     }
 }
 
+// The controlled phases of one sub-stage (CPHASE, CPHASEK; Eq. cphasek).  Each
+// phase's factor is multiplied into the accumulator of its slot when the tile
+// index and the thread's part of the label have its other bits set; every
+// register whose index holds the slot's register bits then takes the
+// accumulated product once.  Uniform branches only: the phase list, the tile
+// index and the slot masks are the same for the whole workgroup.
+template <int NV, int NR, typename T>
+__device__ __forceinline__ void apply_phases(const KArgs& a, const PK_CONST Stage* S, T (&v)[NV][NR],
+                                             const Layout& L, int64_t tile) {
+    using R = decltype(v[0][0].x);
+    T acc[kPhaseSlots];
+#pragma unroll
+    for (int u = 0; u < kPhaseSlots; ++u) acc[u] = T{(R)1, (R)0};
+    const PK_CONST PhaseOp* ph = cptr(a.phases) + S->phase_first;
+    const int n = S->phase_count;
+    for (int q = 0; q < n; ++q) {
+        const int64_t fm = ph[q].fmask;
+        if ((tile & fm) != fm) continue;
+        const unsigned tm = ph[q].tmask;
+        const bool on = (L.jt & tm) == tm;
+        const R c = on ? (R)ph[q].c : (R)1, s = on ? (R)ph[q].s : (R)0;
+        const int slot = ph[q].slot;
+#pragma unroll
+        for (int u = 0; u < kPhaseSlots; ++u) {
+            if (slot != u) continue;
+            const R x = acc[u].x, y = acc[u].y;
+            acc[u].x = x * c - y * s;
+            acc[u].y = x * s + y * c;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kPhaseSlots; ++u) {
+        const int pm = S->phase_pm[u];
+        if (pm < 0) continue;
+        const R c = acc[u].x, s = acc[u].y;
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            if ((i & pm) != pm) continue;
+#pragma unroll
+            for (int m = 0; m < NV; ++m) {
+                const R x = v[m][i].x, y = v[m][i].y;
+                v[m][i].x = x * c - y * s;
+                v[m][i].y = x * s + y * c;
+            }
+        }
+    }
+}
+
 // Hadamards on the register bits set in `mask` (distinct bits commute).
 template <int NV, int NR, typename T>
 __device__ __forceinline__ void apply_hmask(T (&v)[NV][NR], int mask) {
@@ -360,8 +412,8 @@ __device__ __forceinline__ PassCtx make_ctx(const KArgs& a, const PK_CONST Pass*
     const PK_CONST Stage* Sl = S0 + (C.nstages - 1);
     C.L0 = make_layout<ESZ>(S0, C.nrb, threadIdx.x);
     C.Ll = make_layout<ESZ>(Sl, C.nrb, threadIdx.x);
-    C.G0 = make_goff(P, S0, C.L0, C.nrb);
-    C.Gl = make_goff(P, Sl, C.Ll, C.nrb);
+    C.G0 = make_goff(P, S0, C.L0, C.nrb, false);
+    C.Gl = make_goff(P, Sl, C.Ll, C.nrb, true);
     return C;
 }
 
@@ -510,6 +562,7 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
             if (S->seed >= 0) element_op<NV, NR, 2>(a, v, L, S->seed, tile, nreg, active);
         }
         if (S->flip_pre >= 0) element_op<NV, NR, 0>(a, v, L, S->flip_pre, tile, nreg, active);
+        if (S->phase_count > 0 && active) apply_phases<NV, NR>(a, S, v, L, tile);
         if (S->mat_pre_a >= 0) {
             R m[8];
             const PK_CONST double* mp = cptr(a.mats) + 8 * S->mat_pre;
@@ -931,6 +984,7 @@ static KArgs kargs(const PassLaunch& L) {
     a.passes = L.passes;
     a.stages = L.stages;
     a.flips = L.flips;
+    a.phases = L.phases;
     a.mats = L.mats;
     a.mats4 = L.mats4;
     a.src0 = L.src0;

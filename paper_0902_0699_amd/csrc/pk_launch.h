@@ -11,6 +11,7 @@ struct PassLaunch {
     const Pass* passes;
     const Stage* stages;
     const Flip* flips;
+    const PhaseOp* phases;
     const double* mats;
     const double* mats4;
     const void* src0;
@@ -74,5 +75,10 @@ hipError_t launch_reduce(const Reduction* red, int n, const double* ws, double* 
                          double* grad_out, hipStream_t st);
 hipError_t launch_pairs(int nq, int i_s, int64_t first, int64_t count, int64_t* n0, int64_t* n1,
                         hipStream_t st);
+// Shor's data path (pk_shor.hip): the loaded state of Eq. Shor2 and the marginal
+// over the n_low low qubits.
+hipError_t launch_shor_state(int n1, int n2, uint64_t x, uint64_t M, bool fp64, double amp, void* psi,
+                             hipStream_t st);
+hipError_t launch_marginal(int nq, int n_low, bool fp64, const void* psi, double* p, hipStream_t st);
 
 }  // namespace pk

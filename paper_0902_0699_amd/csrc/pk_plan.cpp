@@ -1,11 +1,14 @@
 // Plan compiler: validates gate lists and lowers them to pass / stage / op tables.
 //
-// Legality rests on two facts about the gates of the paper: one-qubit gates on
-// different qubits commute (each acts on its own tensor factor, Sec. 2.1), and
-// diagonal sign operations (Oracle, Inv; Sec. 5.1) commute with each other.
-// Any order of the primitives that keeps every non-commuting pair in list
-// order computes the same state, so the compiler may gather all gates on a set
-// of qubits into one pass over the state.
+// Legality rests on two facts about the gates of the paper: gates on disjoint
+// sets of qubits commute (each acts on its own tensor factors, Sec. 2.1), and
+// diagonal operations (Oracle, Inv, Sec. 5.1; the controlled phases CPHASE and
+// CPHASEK, Eq. cphasek) commute with each other.  Any order of the primitives
+// that keeps every non-commuting pair in list order computes the same state, so
+// the compiler may gather all gates on a set of qubits into one pass over the
+// state.  A controlled phase needs no partner amplitude: each amplitude's
+// factor follows from its own label, so it runs in whatever pass and stage its
+// ordering allows, whether or not its qubits are tile or register bits.
 #include "pk_plan.h"
 
 #include <algorithm>
@@ -68,35 +71,52 @@ bool is_unitary4(const double* m) {
 
 // Forward scan: which not-yet-scheduled primitives can run in a pass (or stage)
 // whose register/tile bit set is `in_set`.  A gate is blocked by an earlier
-// unscheduled gate on one of its bits or an earlier unscheduled diagonal op; a
-// diagonal op is blocked by any earlier unscheduled gate.  Two-qubit gates
-// need both bits in the set; `pair` further restricts them: PAIR_ANY (tiles),
-// PAIR_NONE (a stage without two-qubit gates), or (b1 << 8 | b2), the one
-// ordered pair a stage holds on register bits 0 and 1.
+// unscheduled gate or controlled phase on one of its bits, or an earlier
+// unscheduled Oracle/Inv; Oracle/Inv are blocked by any earlier unscheduled
+// gate; a controlled phase only by an earlier unscheduled gate on one of its
+// bits (phases, Oracle and Inv are all diagonal).  Gates need their bits in the
+// set, phases do not.  Two-qubit gates need both bits; `pair` further restricts
+// them: PAIR_ANY (tiles), PAIR_NONE (a stage without two-qubit gates), or
+// (b1 << 8 | b2), the one ordered pair a stage holds on register bits 0 and 1.
 constexpr int PAIR_ANY = -1;
 constexpr int PAIR_NONE = -2;
 
+enum ItemType { IT_GATE = 0, IT_DIAG = 1, IT_PHASE = 2 };
+
 struct ScanItem {
-    bool diag;
-    int bit;
-    int bit2;  // second bit of a two-qubit gate, -1 otherwise
+    int type;
+    int bit;   // IT_GATE, IT_PHASE: first bit (for a phase, -1 when it is outside the tile)
+    int bit2;  // second bit of a two-qubit gate or phase, -1 otherwise
+    bool swap = false;  // a SWAP gate (done by relabelling bits when the pass allows)
 };
 
 int scan(const std::vector<ScanItem>& items, const std::vector<char>& done,
          const std::vector<char>& in_set, int nbits, int max_gates, std::vector<int>* out,
          int pair = PAIR_ANY) {
-    std::vector<char> blocked(nbits, 0);
+    std::vector<char> blocked(nbits, 0);  // later gates on the bit must wait
+    std::vector<char> nd(nbits, 0);       // later phases on the bit must wait (a non-diagonal gate is pending)
     bool blocked_gate = false, blocked_diag = false;
     int count = 0, gates = 0;
     for (size_t i = 0; i < items.size(); ++i) {
         if (done[i]) continue;
         const ScanItem& it = items[i];
-        if (it.diag) {
+        if (it.type == IT_DIAG) {
             if (!blocked_gate) {
                 ++count;
                 if (out) out->push_back((int)i);
             } else {
                 blocked_diag = true;
+            }
+        } else if (it.type == IT_PHASE) {
+            const bool ok = (it.bit < 0 || !nd[it.bit]) && (it.bit2 < 0 || !nd[it.bit2]) &&
+                            (max_gates < 0 || gates < max_gates);
+            if (ok) {
+                ++count;
+                ++gates;
+                if (out) out->push_back((int)i);
+            } else {
+                if (it.bit >= 0) blocked[it.bit] = 1;
+                if (it.bit2 >= 0) blocked[it.bit2] = 1;
             }
         } else {
             const bool two = it.bit2 >= 0;
@@ -110,8 +130,8 @@ int scan(const std::vector<ScanItem>& items, const std::vector<char>& done,
                 ++gates;
                 if (out) out->push_back((int)i);
             } else {
-                blocked[it.bit] = 1;
-                if (two) blocked[it.bit2] = 1;
+                blocked[it.bit] = nd[it.bit] = 1;
+                if (two) blocked[it.bit2] = nd[it.bit2] = 1;
                 blocked_gate = true;
             }
         }
@@ -124,7 +144,9 @@ int scan(const std::vector<ScanItem>& items, const std::vector<char>& done,
 int half_pairs(const std::vector<ScanItem>& items, const std::vector<char>& done, const std::vector<char>& in_set) {
     int c = 0;
     for (size_t i = 0; i < items.size(); ++i)
-        if (!done[i] && items[i].bit2 >= 0 && (in_set[items[i].bit] != in_set[items[i].bit2])) ++c;
+        if (!done[i] && items[i].type == IT_GATE && items[i].bit2 >= 0 &&
+            (in_set[items[i].bit] != in_set[items[i].bit2]))
+            ++c;
     return c;
 }
 
@@ -144,7 +166,8 @@ int64_t extract(int64_t x, const std::vector<int>& bits) {
 // slot, and a new sub-stage (same layout, no exchange) starts when none fits.
 // Hadamards collected in one mask act on distinct register bits and commute.
 enum Slot {
-    S_SEED = 0, S_FLIP_PRE, S_MAT_PRE, S_H1, S_FLIP_MID, S_H2, S_MAT_POST, S_MAT4, S_D2B, S_D4B, S_SCALE, S_READ
+    S_SEED = 0, S_FLIP_PRE, S_PHASE, S_MAT_PRE, S_H1, S_FLIP_MID, S_H2, S_MAT_POST, S_MAT4, S_D2B, S_D4B, S_SCALE,
+    S_READ
 };
 
 Stage blank_sub(const HostStage& hs, int exchange) {
@@ -160,7 +183,41 @@ Stage blank_sub(const HostStage& hs, int exchange) {
     s.seed = s.flip_pre = s.flip_mid = s.read = -1;
     s.mat_pre_a = s.mat_post_a = s.d2b_a = -1;
     s.mat4 = s.d4b_mat = -1;
+    s.phase_first = s.phase_count = 0;
+    for (int u = 0; u < kPhaseSlots; ++u) s.phase_pm[u] = -1;
     return s;
+}
+
+// A phase joins the accumulator slot of its register bits (the register bits of
+// its qubits in this layout), or opens a new one; its other local bits become
+// conditions on the thread's part of the label.
+int place_phase(Stage& s, int cursor, const HostPhase& h, const HostStage& hs, std::vector<PhaseOp>* table) {
+    if (cursor > S_PHASE) return -1;
+    int pm = 0;
+    uint32_t tmask = 0;
+    for (int l : {h.la, h.lb}) {
+        if (l < 0) continue;
+        int a = -1;
+        for (int q = 0; q < kMaxRegBits; ++q)
+            if (hs.rb[q] == l) a = q;
+        if (a >= 0)
+            pm |= 1 << a;
+        else
+            tmask |= 1u << l;
+    }
+    int slot = -1;
+    for (int u = 0; u < kPhaseSlots && slot < 0; ++u)
+        if (s.phase_pm[u] == pm) slot = u;
+    for (int u = 0; u < kPhaseSlots && slot < 0; ++u)
+        if (s.phase_pm[u] < 0) {
+            s.phase_pm[u] = pm;
+            slot = u;
+        }
+    if (slot < 0) return -1;
+    if (s.phase_count == 0) s.phase_first = (int32_t)table->size();
+    table->push_back({slot, tmask, h.fmask, h.c, h.s});
+    ++s.phase_count;
+    return S_PHASE;
 }
 
 int place(Stage& s, int cursor, const Op& o) {
@@ -206,23 +263,38 @@ int place(Stage& s, int cursor, const Op& o) {
     }
 }
 
-std::vector<Stage> pack_stage(const HostStage& hs) {
+std::vector<Stage> pack_stage(const HostStage& hs, const std::vector<HostPhase>& phases, std::vector<PhaseOp>* table) {
     std::vector<Stage> subs;
     Stage cur = blank_sub(hs, 1);
     int cursor = 0;
+    auto put = [&](const Op& o) {
+        return o.kind == OP_PHASE ? place_phase(cur, cursor, phases[o.arg], hs, table) : place(cur, cursor, o);
+    };
     for (const Op& o : hs.ops) {
-        int slot = place(cur, cursor, o);
+        int slot = put(o);
         if (slot < 0) {
             subs.push_back(cur);
             cur = blank_sub(hs, 0);
             cursor = 0;
-            slot = place(cur, cursor, o);
+            slot = put(o);
         }
         cursor = slot;
     }
     subs.push_back(cur);
     return subs;
 }
+
+// A pass's items on local tile bits.  A SWAP whose qubits are both non-carrier
+// tile bits moves no data: from its position on, the two local bits stand for
+// each other's qubits, and the tile is written back with the two state bits
+// exchanged (Pass::stpos).  Such SWAPs leave the item list; every other item
+// keeps the local bits and the read->state map in effect at its position.
+struct LocalPass {
+    std::vector<ScanItem> items;
+    std::vector<int> src;                // index into the pass's selection of each item
+    std::vector<int> map_id;             // entry of `maps` in effect at each item
+    std::vector<std::vector<int>> maps;  // local bit -> state bit; maps[0] when read, back() when written
+};
 
 struct Compiler {
     Plan* plan;
@@ -267,7 +339,7 @@ struct Compiler {
             std::vector<int> pairs;  // ordered pairs of the pending two-qubit gates
             std::set<int> need;
             for (int i = 0; i < n; ++i) {
-                if (done[i] || items[i].diag) continue;
+                if (done[i] || items[i].type != IT_GATE) continue;
                 need.insert(items[i].bit);
                 if (items[i].bit2 >= 0) {
                     need.insert(items[i].bit2);
@@ -402,7 +474,7 @@ struct Compiler {
             // first pending gate instead, which nothing earlier can block
             int first = -1;
             for (size_t i = 0; i < items.size() && first < 0; ++i)
-                if (!done[i] && !items[i].diag) first = (int)i;
+                if (!done[i] && items[i].type == IT_GATE) first = (int)i;
             std::fill(in_t.begin(), in_t.end(), 0);
             t.clear();
             for (int b = 0; b < C; ++b) {
@@ -426,16 +498,29 @@ struct Compiler {
         return t;
     }
 
-    std::vector<ScanItem> local_items(const std::vector<ScanItem>& items, const std::vector<int>& t,
-                                      const std::vector<int>& sel, size_t count) const {
+    LocalPass local_pass(const std::vector<ScanItem>& items, const std::vector<int>& t,
+                         const std::vector<int>& sel, size_t count) const {
+        LocalPass lp;
         std::vector<int> local_of(in->nq, -1);
         for (int l = 0; l < (int)t.size(); ++l) local_of[t[l]] = l;
-        std::vector<ScanItem> litems;
+        lp.maps.push_back(t);
         for (size_t j = 0; j < count; ++j) {
             const ScanItem& it = items[sel[j]];
-            litems.push_back({it.diag, it.diag ? 0 : local_of[it.bit], it.bit2 >= 0 ? local_of[it.bit2] : -1});
+            const int l1 = it.bit >= 0 ? local_of[it.bit] : -1;
+            const int l2 = it.bit2 >= 0 ? local_of[it.bit2] : -1;
+            if (it.type == IT_GATE && it.swap && l1 >= C && l2 >= C) {
+                std::swap(local_of[it.bit], local_of[it.bit2]);
+                std::vector<int> m = lp.maps.back();
+                std::swap(m[l1], m[l2]);
+                lp.maps.push_back(m);
+                continue;
+            }
+            ScanItem li{it.type, it.type == IT_DIAG ? -1 : l1, l2, it.swap};
+            lp.items.push_back(li);
+            lp.src.push_back((int)j);
+            lp.map_id.push_back((int)lp.maps.size() - 1);
         }
-        return litems;
+        return lp;
     }
 
     // Cost of finishing the schedule greedily from `done`: (passes, sum of
@@ -445,7 +530,7 @@ struct Compiler {
         std::vector<int> sel;
         while (left > 0) {
             auto t = choose_tile(items, done, &sel);
-            int ns = (int)plan_stages(local_items(items, t, sel, sel.size())).size();
+            int ns = (int)plan_stages(local_pass(items, t, sel, sel.size()).items).size();
             for (int i : sel) done[i] = 1;
             left -= (int)sel.size();
             ++passes;
@@ -467,7 +552,11 @@ struct Compiler {
         if (cut_cache) {
             int32_t hdr[4] = {nq, k, C, RB};
             key.append((const char*)hdr, sizeof hdr);
-            for (size_t i = 0; i < items.size(); ++i) key.push_back(items[i].diag ? (char)-1 : (char)items[i].bit);
+            for (size_t i = 0; i < items.size(); ++i) {
+                key.push_back((char)(items[i].type * 2 + (items[i].swap ? 1 : 0)));
+                key.push_back((char)items[i].bit);
+                key.push_back((char)items[i].bit2);
+            }
             key.append(done.begin(), done.end());
             auto it = cut_cache->find(key);
             if (it != cut_cache->end()) return it->second;
@@ -475,7 +564,7 @@ struct Compiler {
         auto cost_of = [&](const std::vector<int>& s) {
             std::vector<char> d = done;
             for (int i : s) d[i] = 1;
-            int ns = (int)plan_stages(local_items(items, t, s, s.size())).size();
+            int ns = (int)plan_stages(local_pass(items, t, s, s.size()).items).size();
             auto rest = greedy_rest(items, d, left - (int)s.size());
             return std::pair<int, int>{1 + rest.first, ns * ns + rest.second};
         };
@@ -490,7 +579,8 @@ struct Compiler {
             for (int b : t) {
                 if (!in_t[b]) continue;
                 bool used = false;
-                for (int i : best) used = used || (!items[i].diag && items[i].bit == b);
+                for (int i : best)
+                    used = used || (items[i].type == IT_GATE && (items[i].bit == b || items[i].bit2 == b));
                 if (!used) continue;
                 in_t[b] = 0;
                 std::vector<int> s;
@@ -533,7 +623,13 @@ struct Compiler {
         const int nq = in->nq;
         const int n = (int)prims.size();
         std::vector<ScanItem> items(n);
-        for (int i = 0; i < n; ++i) items[i] = {prims[i].kind != Prim::GATE, prims[i].bit, prims[i].bit2};
+        for (int i = 0; i < n; ++i) {
+            const Prim& p = prims[i];
+            if (p.kind != Prim::GATE)
+                items[i] = {IT_DIAG, -1, -1};
+            else
+                items[i] = {p.gk == Prim::GPHASE ? IT_PHASE : IT_GATE, p.bit, p.bit2, p.gk == Prim::GSWAP};
+        }
         std::vector<char> done(n, 0);
         int left = n;
         ScaleState sc;
@@ -548,13 +644,21 @@ struct Compiler {
             const bool last = (left == 0);
 
             // --- local items and stages
-            std::vector<int> local_of(nq, -1);
-            for (int l = 0; l < k; ++l) local_of[t[l]] = l;
-            auto st = plan_stages(local_items(items, t, sel, sel.size()));
+            const LocalPass lp = local_pass(items, t, sel, sel.size());
+            auto st = plan_stages(lp.items);
+            std::vector<int> fpos(nq, -1);  // position of each bit outside the tile in the tile index
+            {
+                std::vector<char> in_t(nq, 0);
+                for (int b : t) in_t[b] = 1;
+                int f = 0;
+                for (int b = 0; b < nq; ++b)
+                    if (!in_t[b]) fpos[b] = f++;
+            }
 
             HostPass hp;
             hp.k = k;
             hp.tbits = t;
+            hp.sbits = lp.maps.back();
             hp.ntiles = (int64_t)1 << (nq - k);
             hp.rbits = RBITS;
             hp.kmax = std::max(k, RBITS + kWaveBits);
@@ -577,34 +681,48 @@ struct Compiler {
                     }
                 }
                 for (int li : st[s].second) {
-                    const Prim& p = prims[sel[li]];
+                    const Prim& p = prims[sel[lp.src[li]]];
+                    const ScanItem& it = lp.items[li];
+                    const std::vector<int>& map = lp.maps[lp.map_id[li]];
                     if (p.kind == Prim::ORACLE) {
                         for (int64_t x : in->marked) {
                             Op o{};
                             o.kind = OP_FLIP;
-                            o.arg = add_flip(t, x, 0);
+                            o.arg = add_flip(map, x, 0);
                             hs.ops.push_back(o);
                         }
                     } else if (p.kind == Prim::INV) {
                         sc.sign = -sc.sign;
                         Op o{};
                         o.kind = OP_FLIP;
-                        o.arg = add_flip(t, 0, 0);
+                        o.arg = add_flip(map, 0, 0);
+                        hs.ops.push_back(o);
+                    } else if (p.gk == Prim::GPHASE) {
+                        // the adjoint of a phase is its conjugate
+                        HostPhase h{it.bit, it.bit2, 0, -1, -1, p.pc, backward ? -p.ps : p.ps};
+                        if (it.bit < 0) h.fmask |= (int64_t)1 << fpos[p.bit];
+                        if (it.bit2 < 0) h.fmask |= (int64_t)1 << fpos[p.bit2];
+                        h.b1 = it.bit >= 0 ? t[it.bit] : p.bit;
+                        h.b2 = it.bit2 >= 0 ? t[it.bit2] : p.bit2;
+                        Op o{};
+                        o.kind = OP_PHASE;
+                        o.arg = (int32_t)hp.phases.size();
+                        hp.phases.push_back(h);
                         hs.ops.push_back(o);
                     } else {
                         Op o{};
-                        o.a = reg_of(local_of[p.bit]);
+                        o.a = reg_of(it.bit);
                         if (p.gk == Prim::GH) {
                             o.kind = OP_H;
                             ++sc.h;
                         } else if (p.gk == Prim::GMAT) {
                             o.kind = OP_MAT;
                             o.arg = 2 * p.idx + (backward ? 1 : 0);
-                        } else if (p.gk == Prim::GMAT4 || p.gk == Prim::GD4) {
+                        } else if (p.gk == Prim::GMAT4 || p.gk == Prim::GD4 || p.gk == Prim::GSWAP) {
                             // the stage holds the pair on register bits 0 (is1) and 1 (is2)
-                            if (o.a != 0 || reg_of(local_of[p.bit2]) != 1) throw std::logic_error("two-qubit register pair");
+                            if (o.a != 0 || reg_of(it.bit2) != 1) throw std::logic_error("two-qubit register pair");
                             o.a = 0;
-                            if (p.gk == Prim::GMAT4) {
+                            if (p.gk == Prim::GMAT4 || p.gk == Prim::GSWAP) {
                                 o.kind = OP_MAT4;
                                 o.arg = 2 * p.idx + (backward ? 1 : 0);
                             } else if (!backward) {
@@ -656,12 +774,12 @@ struct Compiler {
                 for (size_t m = 0; m < in->marked.size(); ++m) {
                     Op o{};
                     o.kind = OP_READ;
-                    o.arg = add_flip(t, in->marked[m], in->read_base + (int)m);
+                    o.arg = add_flip(lp.maps.back(), in->marked[m], in->read_base + (int)m);
                     fin.ops.push_back(o);
                 }
             }
             for (const HostStage& hs : hp.stages) {
-                std::vector<Stage> sub = pack_stage(hs);
+                std::vector<Stage> sub = pack_stage(hs, hp.phases, &plan->phases);
                 hp.subs.insert(hp.subs.end(), sub.begin(), sub.end());
             }
             out->push_back(hp);
@@ -669,6 +787,44 @@ struct Compiler {
         } while (left > 0);
     }
 };
+
+// CPHASE (k = 0: theta = pi, Sec. 4.2) or CPHASEK (theta = 2 pi / 2^k, Eq. cphasek):
+// diag(1, 1, 1, e^{i theta}) on qubits is1, is2, a phase on the amplitudes whose
+// two qubits are 1, with the exact factors at theta = pi and pi/2.
+Prim phase_prim(int nq, int is1, int is2, int k) {
+    double c = -1.0, sn = 0.0;
+    if (k == 2) {
+        c = 0.0;
+        sn = 1.0;
+    } else if (k > 2) {
+        const double ph = 2.0 * M_PI * std::ldexp(1.0, -k);
+        c = std::cos(ph);
+        sn = std::sin(ph);
+    }
+    Prim pr{Prim::GATE, nq - is1, Prim::GPHASE, 0};
+    pr.bit2 = nq - is2;
+    pr.pc = c;
+    pr.ps = sn;
+    return pr;
+}
+
+// A fixed 4x4 operator in the basis |q_is1 q_is2> (Eq. resmat2), row-major
+// (re, im); the plan keeps it and its adjoint.
+Prim mat4_prim(Plan* plan, int nq, int is1, int is2, const double* m, Prim::GKind gk) {
+    Prim pr{Prim::GATE, nq - is1, gk, plan->n_static4};
+    pr.bit2 = nq - is2;
+    for (int e = 0; e < 32; ++e) plan->static_mats4.push_back(m[e]);
+    for (int a = 0; a < 4; ++a)  // adjoint
+        for (int b = 0; b < 4; ++b) {
+            plan->static_mats4.push_back(m[2 * (4 * b + a)]);
+            plan->static_mats4.push_back(-m[2 * (4 * b + a) + 1]);
+        }
+    ++plan->n_static4;
+    return pr;
+}
+
+const double kSwap4[32] = {1, 0, 0, 0, 0, 0, 0, 0,  0, 0, 0, 0, 1, 0, 0, 0,
+                           0, 0, 1, 0, 0, 0, 0, 0,  0, 0, 0, 0, 0, 0, 1, 0};
 
 std::string fmt(const char* f, long long a = 0, long long b = 0) {
     char buf[256];
@@ -728,7 +884,12 @@ int compile_plan(Plan* plan, const pk_problem* probs, int n_inst, int prec, std:
             const pk_gate& gt = p.gates[g];
             const bool two = gt.kind == PK_GATE_TWOOP || gt.kind == PK_GATE_CNOT || gt.kind == PK_GATE_CPHASE ||
                              gt.kind == PK_GATE_CPHASEK || gt.kind == PK_GATE_SWAP || gt.kind == PK_GATE_D4;
-            if (!two && (gt.is2 != 0 || gt.k != 0)) {
+            if (gt.kind == PK_GATE_QFT) {
+                if (gt.is2 != 0 || gt.k < 1 || gt.is1 < 1 || gt.is1 + gt.k - 1 > p.nq) {
+                    *err = fmt("instance %lld gate %lld: QFT needs qubits is1 .. is1+k-1 within 1..nq and is2 = 0", i, g);
+                    return PK_EINVAL;
+                }
+            } else if (!two && (gt.is2 != 0 || gt.k != 0)) {
                 *err = fmt("instance %lld gate %lld: two-qubit fields must be 0", i, g);
                 return PK_EINVAL;
             }
@@ -812,24 +973,28 @@ int compile_plan(Plan* plan, const pk_problem* probs, int n_inst, int prec, std:
                     if (!is_unitary4(m)) plan->backward_ok = false;
                 } else if (gt.kind == PK_GATE_CNOT) {  // control is1, target is2 (Sec. 4.2)
                     set(0, 0, 1, 0); set(1, 1, 1, 0); set(2, 3, 1, 0); set(3, 2, 1, 0);
-                } else if (gt.kind == PK_GATE_CPHASE) {  // diag(1, 1, 1, -1) (Sec. 4.2)
-                    set(0, 0, 1, 0); set(1, 1, 1, 0); set(2, 2, 1, 0); set(3, 3, -1, 0);
-                } else if (gt.kind == PK_GATE_CPHASEK) {  // diag(1, 1, 1, e^{2 pi i / 2^k}) (Eq. cphasek)
-                    const double ph = 2.0 * M_PI * std::ldexp(1.0, -gt.k);
-                    set(0, 0, 1, 0); set(1, 1, 1, 0); set(2, 2, 1, 0); set(3, 3, std::cos(ph), std::sin(ph));
+                } else if (gt.kind == PK_GATE_CPHASE || gt.kind == PK_GATE_CPHASEK) {
+                    in.prims.push_back(phase_prim(p.nq, gt.is1, gt.is2, gt.kind == PK_GATE_CPHASE ? 0 : gt.k));
+                    break;
                 } else {  // SWAP: |ab> -> |ba>
-                    set(0, 0, 1, 0); set(1, 2, 1, 0); set(2, 1, 1, 0); set(3, 3, 1, 0);
+                    for (int e = 0; e < 32; ++e) m[e] = kSwap4[e];
                 }
-                pr = {Prim::GATE, p.nq - gt.is1, Prim::GMAT4, plan->n_static4};
-                pr.bit2 = p.nq - gt.is2;
-                for (int e = 0; e < 32; ++e) plan->static_mats4.push_back(m[e]);
-                for (int a = 0; a < 4; ++a)  // adjoint
-                    for (int b = 0; b < 4; ++b) {
-                        plan->static_mats4.push_back(m[2 * (4 * b + a)]);
-                        plan->static_mats4.push_back(-m[2 * (4 * b + a) + 1]);
-                    }
-                ++plan->n_static4;
-                in.prims.push_back(pr);
+                in.prims.push_back(mat4_prim(plan, p.nq, gt.is1, gt.is2, m,
+                                             gt.kind == PK_GATE_SWAP ? Prim::GSWAP : Prim::GMAT4));
+                break;
+            }
+            case PK_GATE_QFT: {
+                // the circuit of App. A on the register of qubits is1 .. is1+k-1: per qubit
+                // ic a Hadamard, then CPHASEK between ic and every later qubit q with
+                // exponent q + 1 - ic (register labels); the last Hadamard; the pair
+                // swaps (i, k + 1 - i) that restore standard order
+                const int o = gt.is1 - 1, n1 = gt.k;
+                for (int ic = 1; ic <= n1; ++ic) {
+                    in.prims.push_back({Prim::GATE, p.nq - (o + ic), Prim::GH, 0});
+                    for (int q = ic + 1; q <= n1; ++q) in.prims.push_back(phase_prim(p.nq, o + q, o + ic, q + 1 - ic));
+                }
+                for (int q = 1; q <= n1 / 2; ++q)
+                    in.prims.push_back(mat4_prim(plan, p.nq, o + q, o + n1 + 1 - q, kSwap4, Prim::GSWAP));
                 break;
             }
             case PK_GATE_D4:
@@ -864,6 +1029,7 @@ int recompile(Plan* plan, std::string* err) {
     plan->passes.clear();
     plan->stages.clear();
     plan->flips.clear();
+    plan->phases.clear();
     plan->idesc.clear();
     plan->order.clear();
     plan->d2_grad.clear();
@@ -893,7 +1059,7 @@ int recompile(Plan* plan, std::string* err) {
             c.RBITS = c.backward ? 4 : plan->tiling.reg_bits;
             c.RB = std::min(c.RBITS, c.k);
             bool has_two = false;
-            for (const Prim& pr : in.prims) has_two = has_two || pr.bit2 >= 0;
+            for (const Prim& pr : in.prims) has_two = has_two || (pr.bit2 >= 0 && pr.gk != Prim::GPHASE);
             if (has_two && c.k < in.nq && c.k - c.C < 2) {
                 *err = "two-qubit gates need at least two non-carrier tile bits (tile_bits >= carrier_bits + 2)";
                 return PK_EINVAL;
@@ -922,7 +1088,10 @@ int recompile(Plan* plan, std::string* err) {
         p.part_base = hp.part_base;
         p.kmax = hp.kmax;
         p.rbits = hp.rbits;
-        for (int l = 0; l < 16; ++l) p.tpos[l] = l < hp.k ? hp.tbits[l] : -1;
+        for (int l = 0; l < 16; ++l) {
+            p.tpos[l] = l < hp.k ? hp.tbits[l] : -1;
+            p.stpos[l] = l < hp.k ? hp.sbits[l] : -1;
+        }
         std::vector<char> used(in.nq, 0);
         for (int b : hp.tbits) used[b] = 1;
         std::vector<int> fbits;
@@ -944,16 +1113,18 @@ int recompile(Plan* plan, std::string* err) {
             return n;
         };
         p.ntrun = runs(hp.tbits, p.trun);
+        p.nstrun = runs(hp.sbits, p.strun);
         p.nfrun = runs(fbits, p.frun);
         // byte offsets of a thread inside a tile in the load / store layouts
         const int esz = plan->prec == PK_FP64 ? 16 : 8;
         for (int which = 0; which < 2; ++which) {
             const HostStage& hs = which == 0 ? hp.stages.front() : hp.stages.back();
+            const std::vector<int>& pos = which == 0 ? hp.tbits : hp.sbits;
             uint64_t maxoff = 0;
             for (int l = 0; l < hp.k; ++l) {
                 bool reg = false;
                 for (int a = 0; a < kMaxRegBits; ++a) reg = reg || hs.rb[a] == l;
-                if (!reg) maxoff += (uint64_t)1 << hp.tbits[l];
+                if (!reg) maxoff += (uint64_t)1 << pos[l];
             }
             if (maxoff * (uint64_t)esz >= ((uint64_t)1 << 32)) p.flags |= PASS_WIDE;
         }
@@ -1031,6 +1202,8 @@ TableLayout table_layout(const Plan* plan) {
     o = align256(o + plan->stages.size() * sizeof(Stage));
     t.flips = o;
     o = align256(o + plan->flips.size() * sizeof(Flip));
+    t.phases = o;
+    o = align256(o + plan->phases.size() * sizeof(PhaseOp));
     t.mats = o;  // static matrices followed by the default angles
     o = align256(o + (plan->static_mats.size() + plan->default_angles.size()) * sizeof(double));
     t.mats4 = o;  // static two-qubit matrices
@@ -1113,7 +1286,7 @@ std::string describe(const Plan* plan) {
              std::to_string(plan->params[q].slot) + "]";
     s += "]";
     s += ",\"instances\":[";
-    const char* kinds[] = {"H", "MAT", "FLIP", "SCALE", "READ", "SEED", "D2BWD", "MAT4", "D4BWD"};
+    const char* kinds[] = {"H", "MAT", "FLIP", "SCALE", "READ", "SEED", "D2BWD", "MAT4", "D4BWD", "PHASE"};
     for (size_t i = 0; i < plan->inst.size(); ++i) {
         const Instance& in = plan->inst[i];
         if (i) s += ",";
@@ -1132,6 +1305,8 @@ std::string describe(const Plan* plan) {
                 s += buf;
                 s += ",\"tile_bits\":[";
                 for (size_t l = 0; l < hp.tbits.size(); ++l) s += (l ? "," : "") + std::to_string(hp.tbits[l]);
+                s += "],\"store_bits\":[";
+                for (size_t l = 0; l < hp.sbits.size(); ++l) s += (l ? "," : "") + std::to_string(hp.sbits[l]);
                 s += "],\"stages\":[";
                 for (size_t st = 0; st < hp.stages.size(); ++st) {
                     const HostStage& hs = hp.stages[st];
@@ -1150,8 +1325,14 @@ std::string describe(const Plan* plan) {
                             s += ",\"tile\":" + std::to_string(f.tile) + ",\"j\":" + std::to_string(f.j) +
                                  ",\"slot\":" + std::to_string(f.slot);
                         }
+                        if (op.kind == OP_PHASE) {
+                            const HostPhase& h = hp.phases[op.arg];
+                            s += ",\"b1\":" + std::to_string(h.b1) + ",\"b2\":" + std::to_string(h.b2);
+                            std::snprintf(buf, sizeof buf, ",\"c\":%.17g,\"s\":%.17g", h.c, h.s);
+                            s += buf;
+                        }
                         if (op.kind == OP_D2BWD || op.kind == OP_D4BWD) {
-                            std::snprintf(buf, sizeof buf, "%.9g", (double)op.gscale);
+                            std::snprintf(buf, sizeof buf, "%.17g", (double)op.gscale);
                             s += ",\"gscale\":";
                             s += buf;
                         }
@@ -1163,11 +1344,15 @@ std::string describe(const Plan* plan) {
                 for (size_t q = 0; q < hp.subs.size(); ++q) {
                     const Stage& u = hp.subs[q];
                     if (q) s += ",";
-                    std::snprintf(buf, sizeof buf, "%.9g", (double)u.d2b_gscale);
+                    std::snprintf(buf, sizeof buf, "%.17g", (double)u.d2b_gscale);
                     s += "{\"rb\":[";
                     for (int a = 0; a < kMaxRegBits; ++a) s += (a ? "," : "") + std::to_string(u.rb[a]);
                     s += "],\"exchange\":" + std::to_string(u.exchange) + ",\"seed\":" + std::to_string(u.seed) +
-                         ",\"flip_pre\":" + std::to_string(u.flip_pre) + ",\"mat_pre_a\":" +
+                         ",\"flip_pre\":" + std::to_string(u.flip_pre) + ",\"phase_first\":" +
+                         std::to_string(u.phase_first) + ",\"phase_count\":" + std::to_string(u.phase_count) +
+                         ",\"phase_pm\":[" + std::to_string(u.phase_pm[0]) + "," + std::to_string(u.phase_pm[1]) +
+                         "," + std::to_string(u.phase_pm[2]) + "," + std::to_string(u.phase_pm[3]) + "]" +
+                         ",\"mat_pre_a\":" +
                          std::to_string(u.mat_pre_a) + ",\"mat_pre\":" + std::to_string(u.mat_pre) +
                          ",\"hmask1\":" + std::to_string(u.hmask1) + ",\"flip_mid\":" +
                          std::to_string(u.flip_mid) + ",\"hmask2\":" + std::to_string(u.hmask2) +
@@ -1175,7 +1360,7 @@ std::string describe(const Plan* plan) {
                          std::to_string(u.mat_post) + ",\"d2b_a\":" + std::to_string(u.d2b_a) +
                          ",\"d2b_mat\":" + std::to_string(u.d2b_mat) + ",\"d2b_gscale\":" + buf +
                          ",\"mat4\":" + std::to_string(u.mat4) + ",\"d4b_mat\":" + std::to_string(u.d4b_mat);
-                    std::snprintf(buf, sizeof buf, "%.9g", (double)u.d4b_gscale);
+                    std::snprintf(buf, sizeof buf, "%.17g", (double)u.d4b_gscale);
                     s += ",\"d4b_gscale\":";
                     s += buf;
                     s += ",\"scale\":" + std::to_string(u.scale) + ",\"read\":" + std::to_string(u.read) + "}";
@@ -1185,6 +1370,14 @@ std::string describe(const Plan* plan) {
             s += "]";
         }
         s += "}";
+    }
+    s += "],\"phases\":[";
+    for (size_t q = 0; q < plan->phases.size(); ++q) {
+        const PhaseOp& ph = plan->phases[q];
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "%s[%d,%u,%lld,%.17g,%.17g]", q ? "," : "", ph.slot, ph.tmask,
+                      (long long)ph.fmask, ph.c, ph.s);
+        s += buf;
     }
     s += "],\"flips\":[";
     for (size_t f = 0; f < plan->flips.size(); ++f) {

@@ -10,15 +10,26 @@
 
 namespace pk {
 
-// A primitive operation of the gate list: a one-qubit gate on one state bit,
-// or a diagonal sign operation on the whole state.
+// A primitive operation of the gate list: a one- or two-qubit gate on state
+// bits, a controlled phase, or a diagonal sign operation on the whole state.
 struct Prim {
     enum Kind { GATE, ORACLE, INV } kind;
     int bit;  // GATE: state bit b = nq - i_s (bit 0 is qubit n_q, the least significant)
-    enum GKind { GH, GMAT, GD2, GMAT4, GD4 } gk;
-    int idx;         // GMAT / GMAT4: static matrix index; GD2 / GD4: global D2 / D4 index
-    int bit2 = -1;   // GMAT4 / GD4: state bit of the second qubit is2
+    enum GKind { GH, GMAT, GD2, GMAT4, GD4, GPHASE, GSWAP } gk;
+    int idx;         // GMAT / GMAT4 / GSWAP: static matrix index; GD2 / GD4: global D2 / D4 index
+    int bit2 = -1;   // two-qubit gates and phases: state bit of the second qubit is2
     int param = -1;  // GD2 / GD4: index of the gate's angle triple
+    double pc = 1.0, ps = 0.0;  // GPHASE: the factor e^{i theta} = pc + i ps
+};
+
+// A controlled phase as scheduled in a pass: la / lb are its local tile bits (-1
+// for a qubit outside the tile), fmask the tile-index bits of the qubits outside
+// the tile, b1 / b2 the state bits of both qubits in the tile's read layout.
+struct HostPhase {
+    int la, lb;
+    int64_t fmask;
+    int b1, b2;
+    double c, s;
 };
 
 struct HostStage {
@@ -29,7 +40,9 @@ struct HostStage {
 struct HostPass {
     int k = 0;
     std::vector<int> tbits;  // state bits of the tile: local bit l is tbits[l], carriers first
+    std::vector<int> sbits;  // state bit that local bit l is written to (tbits permuted by SWAPs)
     std::vector<HostStage> stages;
+    std::vector<HostPhase> phases;  // the pass's controlled phases (OP_PHASE arg indexes this)
     std::vector<Stage> subs;  // the stages packed into fixed-slot sub-stages (device form)
     int flags = 0;
     double scale = 1.0;
@@ -117,6 +130,7 @@ struct Plan {
     std::vector<double> static_mats4;  // 32 doubles per fixed two-qubit matrix, then its adjoint
     std::vector<double> default_angles; // 3 per D2 or D4 gate, in order
     std::vector<ParamRef> params;      // what each angle triple drives
+    std::vector<PhaseOp> phases;       // controlled phases as scheduled (device table)
     int n_d2 = 0;
     int n_d4 = 0;
     int n_static = 0;
@@ -155,7 +169,7 @@ std::string describe(const Plan* plan);
 
 // Byte offsets of the device table arrays inside plan->d_tables.
 struct TableLayout {
-    size_t passes, stages, flips, mats, mats4, params, idesc, order, team_off, team_list, red, total;
+    size_t passes, stages, flips, phases, mats, mats4, params, idesc, order, team_off, team_list, red, total;
 };
 TableLayout table_layout(const Plan* plan);
 

@@ -23,7 +23,7 @@ PK_OK, PK_EINVAL, PK_ENOMEM, PK_EDEVICE, PK_EUNSUPPORTED = 0, -1, -2, -3, -4
 PK_FP64, PK_FP32 = 0, 1
 PK_OP_EVAL, PK_OP_BACKWARD = 0, 1
 GATE_KINDS = {"ONEOP": 0, "H": 1, "HALL": 2, "ORACLE": 3, "INV": 4, "D2": 5,
-              "TWOOP": 6, "CNOT": 7, "CPHASE": 8, "CPHASEK": 9, "SWAP": 10, "D4": 11}
+              "TWOOP": 6, "CNOT": 7, "CPHASE": 8, "CPHASEK": 9, "SWAP": 10, "D4": 11, "QFT": 12}
 TWO_QUBIT = ("TWOOP", "CNOT", "CPHASE", "CPHASEK", "SWAP", "D4")
 
 # Entry points declared in include/paperkern.h with their ctypes signatures.
@@ -55,6 +55,8 @@ SIGNATURES = {
     "pk_evaluate_batched": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pk_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pk_pair_indices": (ctypes.c_int, [_c_int32, _c_int32, _c_int64, _c_int64, _vp, _vp, _vp]),
+    "pk_shor_state": (ctypes.c_int, [_c_int32, _c_int32, _c_int64, _c_int64, _c_int32, _vp, _vp]),
+    "pk_marginal": (ctypes.c_int, [_c_int32, _c_int32, _c_int32, _vp, _vp, _vp]),
     "pk_time_passes": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_c_double),
                                       _c_int32, ctypes.POINTER(_c_int32)]),
     "pk_destroy": (None, [_vp]),
@@ -117,6 +119,9 @@ def make_gate(g, nq=None):
                 pg.op[2 * (4 * a + b) + 1] = op[a, b].imag
     if kind == "CPHASEK":
         pg.k = int(g[3])
+    if kind == "QFT":  # ("QFT", first qubit, register size)
+        pg.is1 = int(g[1])
+        pg.k = int(g[2])
     if kind in ("D2", "D4"):
         first = 2 if kind == "D2" else 3
         for t in range(3):
@@ -346,6 +351,44 @@ def pair_indices(nq, i_s, first, count, device="cuda"):
     rc = lib().pk_pair_indices(nq, i_s, first, count, _ptr(n0), _ptr(n1), _stream(n0.device))
     _check(rc, None)
     return n0[:count], n1[:count]
+
+
+def shor_register_sizes(M):
+    """(n1, n2) of Shor's Step 1: n1 = Ceiling(log2 Q), Q = 2^Ceiling(log2 M^2); n2 = Ceiling(log2 M)."""
+    M = int(M)
+    if M < 2:
+        raise ValueError("M must be at least 2")
+    n1 = ((M * M) - 1).bit_length()  # Ceiling(log2 Q) = Ceiling(log2 M^2)
+    return n1, (M - 1).bit_length()
+
+
+def shor_state(n1, n2, xguess, M, prec="fp64", out=None, device="cuda"):
+    """The loaded two-register state of Eq. Shor2 on the device (pk_shor_state)."""
+    import torch
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    if out is None:
+        # sizes the library rejects get a one-element buffer: the C-ABI reports the error
+        ok = n1 >= 1 and n2 >= 1 and n1 + n2 <= (30 if prec == "fp64" else 31)
+        out = torch.empty((1 << (n1 + n2)) if ok else 1, dtype=dt, device=device)
+    elif out.dtype != dt or out.numel() != (1 << (n1 + n2)) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous %s tensor of 2^(n1+n2) amplitudes" % dt)
+    rc = lib().pk_shor_state(n1, n2, int(xguess), int(M), PK_FP64 if prec == "fp64" else PK_FP32, _ptr(out),
+                             _stream(out.device))
+    _check(rc, None)
+    return out
+
+
+def marginal(psi, nq, n_low, out=None):
+    """p[n] = sum over the n_low low qubits of |psi|^2 (pk_marginal), FP64 on the device."""
+    import torch
+    if psi.dtype not in (torch.complex128, torch.complex64) or psi.numel() != (1 << nq) or not psi.is_contiguous():
+        raise ValueError("psi must be a contiguous complex tensor of 2^nq amplitudes")
+    if out is None:
+        out = torch.empty(1 << (nq - n_low) if 0 <= n_low <= nq else 1, dtype=torch.float64, device=psi.device)
+    prec = PK_FP64 if psi.dtype == torch.complex128 else PK_FP32
+    rc = lib().pk_marginal(nq, n_low, prec, _ptr(psi), _ptr(out), _stream(psi.device))
+    _check(rc, None)
+    return out
 
 
 def _autograd_function():

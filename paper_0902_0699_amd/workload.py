@@ -36,7 +36,11 @@ BATCH_INSTANCES = 4096
 BATCH_NQ_MIN = 10
 BATCH_NQ_SPAN = 10
 
-SEEDS = {"small_fp64": 0, "large_fp64": 1, "large_fp32": 2, "batched": 3, "gradient": 4}
+SEEDS = {"small_fp64": 0, "large_fp64": 1, "large_fp32": 2, "batched": 3, "gradient": 4, "shor": 6}
+
+# Shor's data path at n_q = 30: M = 899 = 29 * 31 gives registers of n1 = 20 and
+# n2 = 10 qubits (Step 1), the largest FP64 state of one GPU's share.
+SHOR_M = 899
 
 
 def _block_normals(key, block, size):
@@ -132,3 +136,13 @@ def fd_subset(seed, inst, count=64):
     part = rng.integers(0, 2, count - 5)
     comps += [("psi", (int(i), int(p))) for i, p in zip(idx, part)]
     return comps
+
+
+def shor_xguess(seed, M=SHOR_M):
+    """Step 3's random choice: integers drawn uniformly from 2 .. M-1 until one is
+    coprime to M (the GCD test), from ``default_rng(seed)``."""
+    rng = np.random.default_rng(seed)
+    while True:
+        x = int(rng.integers(2, M))
+        if math.gcd(x, M) == 1:
+            return x

@@ -27,10 +27,10 @@ def _matrix_table(problems, desc):
                 d2.append(tuple(float(v) for v in g[2:5]))
             if g[0] == "TWOOP":
                 statics4.append(np.asarray(g[3], dtype=np.complex128))
-            if g[0] in ("CNOT", "CPHASE", "SWAP"):
+            if g[0] in ("CNOT", "SWAP"):
                 statics4.append(getattr(O, g[0]))
-            if g[0] == "CPHASEK":
-                statics4.append(O.cphasek(g[3]))
+            if g[0] == "QFT":  # lowered with one SWAP per pair of the reversal
+                statics4.extend([O.SWAP] * (g[2] // 2))
             if g[0] == "D4":
                 d4.append(tuple(float(v) for v in g[3:6]))
     assert len(statics) == desc["n_static"] and len(d2) == desc["n_d2"]
@@ -109,6 +109,63 @@ def check_stage_shapes(nq, p):
     assert all(0 <= b < nq for b in p["tile_bits"])
 
 
+def _store(vec, nq, tb, sb):
+    """The pass's write-back: local bit l, read from state bit tb[l], goes to sb[l]."""
+    if list(tb) == list(sb):
+        return vec
+    idx = np.arange(1 << nq, dtype=np.int64)
+    dst = idx.copy()
+    for a, b in zip(tb, sb):
+        dst &= ~np.int64(1 << a)
+    for a, b in zip(tb, sb):
+        dst |= ((idx >> a) & 1) << b
+    out = np.empty_like(vec)
+    out[dst] = vec
+    return out
+
+
+def _phase_mask(nq, b1, b2):
+    idx = np.arange(1 << nq, dtype=np.int64)
+    return (((idx >> b1) & 1) == 1) & (((idx >> b2) & 1) == 1)
+
+
+def _local_label(nq, tb, g):
+    j = np.zeros_like(g)
+    for l, b in enumerate(tb):
+        j |= ((g >> b) & 1) << l
+    return j
+
+
+def _tile_index(nq, tb, g):
+    free = [b for b in range(nq) if b not in tb]
+    t = np.zeros_like(g)
+    for f, b in enumerate(free):
+        t |= ((g >> b) & 1) << f
+    return t
+
+
+def _run_phases(desc, nq, tb, u, vecs):
+    """The sub-stage's controlled phases as the kernel applies them: conditions on
+    the tile index (fmask), the thread's label bits (tmask) and the slot's register
+    bits, with the local label decoded through the read map."""
+    g = np.arange(1 << nq, dtype=np.int64)
+    j = _local_label(nq, tb, g)
+    tile = _tile_index(nq, tb, g)
+    rb = u["rb"]
+    for q in range(u["phase_first"], u["phase_first"] + u["phase_count"]):
+        slot, tmask, fmask, c, s = desc["phases"][q]
+        pm = u["phase_pm"][slot]
+        assert pm >= 0
+        lmask = tmask
+        for a in range(5):
+            if pm >> a & 1:
+                assert rb[a] >= 0 and not (tmask >> rb[a] & 1)
+                lmask |= 1 << rb[a]
+        hit = ((tile & fmask) == fmask) & ((j & lmask) == lmask)
+        for v in vecs:
+            v[hit] *= complex(c, s)
+
+
 def _flip_index(desc, nq, tb, f):
     tile, j, slot = desc["flips"][f]
     return _global_index(nq, tb, tile, j), slot
@@ -135,6 +192,8 @@ def _run_subs(problems, desc, inst, direction, psi, lam=None, dL=1.0):
                 g, _ = _flip_index(desc, nq, tb, u["flip_pre"])
                 for v in vecs:
                     v[g] *= -1
+            if u["phase_count"] > 0:
+                _run_phases(desc, nq, tb, u, vecs)
             if u["mat_pre_a"] >= 0:
                 for v in vecs:
                     _apply_bit(v, nq, tb[rb[u["mat_pre_a"]]], mat(u["mat_pre"]))
@@ -182,6 +241,7 @@ def _run_subs(problems, desc, inst, direction, psi, lam=None, dL=1.0):
             if u["read"] >= 0:
                 g, slot = _flip_index(desc, nq, tb, u["read"])
                 reads[slot] = abs(vecs[0][g]) ** 2
+        vecs = [_store(v, nq, tb, p["store_bits"]) for v in vecs]
     return vecs, reads, grads
 
 
@@ -215,6 +275,8 @@ def run_forward_ops(problems, desc, inst, psi_in):
                     _apply_bit(psi, nq, bit, H if kind == "H" else mat(op["arg"]))
                 elif kind == "MAT4":
                     _apply_pair(psi, nq, tb[st["rb"][0]], tb[st["rb"][1]], mat.four(op["arg"]))
+                elif kind == "PHASE":
+                    psi[_phase_mask(nq, op["b1"], op["b2"])] *= complex(op["c"], op["s"])
                 elif kind == "FLIP":
                     psi[_global_index(nq, tb, op["tile"], op["j"])] *= -1
                 elif kind == "SCALE":
@@ -224,6 +286,7 @@ def run_forward_ops(problems, desc, inst, psi_in):
                     reads[op["slot"]] = abs(psi[g]) ** 2
                 else:
                     raise AssertionError("unexpected forward op %s" % kind)
+        psi = _store(psi, nq, tb, p["store_bits"])
     return psi, sum(reads[s] for s in sorted(reads))
 
 
@@ -276,6 +339,10 @@ def run_backward_ops(problems, desc, inst, psi_out, dL):
                         _apply_pair(dpsi, nq, b1, b2, mat.four(op["arg"] + 2 + t))
                         grads[(d, t)] = 2.0 * op["gscale"] * float(np.vdot(lam, dpsi).real)
                     _apply_pair(lam, nq, b1, b2, mat.four(op["arg"] + 1))
+                elif kind == "PHASE":
+                    m = _phase_mask(nq, op["b1"], op["b2"])
+                    psi[m] *= complex(op["c"], op["s"])
+                    lam[m] *= complex(op["c"], op["s"])
                 elif kind == "FLIP":
                     g = _global_index(nq, tb, op["tile"], op["j"])
                     psi[g] *= -1
@@ -297,6 +364,8 @@ def run_backward_ops(problems, desc, inst, psi_out, dL):
                     _apply_bit(lam, nq, bit, mat(op["arg"] + 1))
                 else:
                     raise AssertionError("unexpected backward op %s" % kind)
+        psi = _store(psi, nq, tb, p["store_bits"])
+        lam = _store(lam, nq, tb, p["store_bits"])
     n_d2 = len({d for d, _ in grads})
     ga = np.zeros((n_d2, 3))
     d0 = min([d for d, _ in grads], default=0)

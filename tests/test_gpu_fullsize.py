@@ -135,3 +135,39 @@ def test_c4_gradient_full_size_against_finite_differences():
     err = float(np.max(np.abs(fd - ad)) / np.max(np.abs(ad)))
     _say("  64 inputs: normwise FD vs adjoint %.3e; angle grads %s" % (err, gang.cpu().numpy()))
     assert err <= 1e-6
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_shor_path_full_size(prec):
+    """Shor's data path at n_q = 30 (M = 899: n1 = 20, n2 = 10) in the launch
+    configuration bench.py times: load (Eq. Shor2), QFT of register one (App. A),
+    marginal.  Every p(n) against Eq. probshor; amplitudes at sampled labels (half
+    of them on the support of the state) against the direct sum of Eq. QFT1."""
+    from paper_0902_0699_amd import paperkern as pk
+
+    M = W.SHOR_M
+    x = W.shor_xguess(W.SEEDS["shor"])
+    n1, n2 = pk.shor_register_sizes(M)
+    nq = n1 + n2
+    _say("full size Shor path: M=%d x=%d n1=%d n2=%d %s" % (M, x, n1, n2, prec))
+    psi = pk.shor_state(n1, n2, x, M, prec=prec)
+    plan = pk.Plan({"nq": nq, "gates": [("QFT", 1, n1)], "marked": []}, prec=prec)
+    pk.evaluate(plan, psi, out=psi, want_norm=False)
+    p = pk.marginal(psi, nq, n2).cpu().numpy()
+    rng = np.random.default_rng(2024)
+    fvals = np.array([pow(x, j, M) for j in range(200)])
+    n = rng.integers(0, 1 << n1, 4096)
+    on = (n[:2048] << n2) + fvals[rng.integers(0, 200, 2048)]
+    labels = np.unique(np.concatenate([on, rng.integers(0, 1 << nq, 2048)]))
+    got = psi[torch.from_numpy(labels).to("cuda")].cpu().numpy().astype(np.complex128)
+    del psi
+    torch.cuda.empty_cache()
+    want_p = O.probshor_marginal(n1, x, M)
+    want_a = O.shor_qft_amplitudes(n1, n2, x, M, labels)
+    tol = TOL64 if prec == "fp64" else TOL32
+    ep = float(np.max(np.abs(p - want_p)) / np.max(want_p))
+    ea = float(np.max(np.abs(got - want_a)) / np.max(np.abs(want_a)))
+    _say("  passes %d  max |dp|/max p %.3e  max |dC|/max |C| %.3e  sum p - 1 = %.3e"
+         % (plan.passes(), ep, ea, p.sum() - 1.0))
+    assert ep <= tol and ea <= tol and abs(p.sum() - 1.0) <= tol

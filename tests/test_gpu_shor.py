@@ -1,0 +1,219 @@
+"""GPU parity of Shor's data path (Sec. 7, App. A) through the C-ABI.
+
+  * QFT (gate kind QFT, and the App. A ladder given gate by gate): against the
+    oracle's DFT along the register axis; controlled phases and relabelled
+    SWAPs at many tilings, including tiles that leave phase qubits outside the
+    tile and SWAPs on carrier bits (applied as 4x4 matrices); FP64 <= 1e-12,
+    FP32 <= 1e-5 normwise; backward against the oracle's adjoint; batched.
+  * The loaded state of Eq. Shor2: bit for bit (integer f, correctly rounded
+    amplitude).
+  * The register-one marginal: every segment shape against the oracle's sums,
+    relative 1e-13 (FP64 sums of the same nonnegative terms in another order).
+  * The whole path (load, QFT, marginal) against the closed form of Eq. probshor.
+Each test prints its case before touching the GPU.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def _pk():
+    from paper_0902_0699_amd import paperkern as pk
+    return pk
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _state(rng, nq):
+    v = rng.standard_normal(1 << nq) + 1j * rng.standard_normal(1 << nq)
+    return v / np.linalg.norm(v)
+
+
+def _relerr(got, want):
+    return float(np.linalg.norm(got - want) / np.linalg.norm(want))
+
+
+def _eval(problem, psi, prec="fp64", tiling=None, launch=None):
+    pk = _pk()
+    plan = pk.Plan(problem, prec=prec)
+    if tiling:
+        plan.set_tiling(*tiling)
+    if launch:
+        plan.set_launch(*launch)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    x = torch.from_numpy(np.ascontiguousarray(psi)).to(dt).to("cuda")
+    out, L, norm = pk.evaluate(plan, x)
+    torch.cuda.synchronize()
+    return plan, out.cpu().numpy().astype(np.complex128), float(L.item())
+
+
+# --------------------------------------------------------------------------- QFT
+
+
+@pytest.mark.parametrize("nq,first,n,tiling,launch,prec", [
+    (6, 1, 6, None, None, "fp64"), (12, 1, 8, None, None, "fp64"), (16, 1, 12, None, None, "fp64"),
+    (16, 3, 10, (8, 3, 1), None, "fp64"), (14, 1, 14, (6, 1, 1), None, "fp64"), (18, 2, 11, None, (0, 5), "fp64"),
+    (13, 1, 9, (5, 0, 1), None, "fp64"), (12, 1, 10, (6, 2, 0), None, "fp64"), (20, 1, 14, None, None, "fp64"),
+    (16, 1, 12, None, None, "fp32"), (18, 4, 9, (9, 4, 1), (0, 4), "fp32"), (20, 1, 14, None, None, "fp32"),
+])
+def test_qft_against_dft(nq, first, n, tiling, launch, prec):
+    rng = np.random.default_rng(nq * 100 + first * 10 + n)
+    gates = [("QFT", first, n), ("ORACLE",)]
+    marked = [int(rng.integers(0, 1 << nq))]
+    psi = _state(rng, nq)
+    if prec == "fp32":
+        psi = psi.astype(np.complex64).astype(np.complex128)
+    _say("QFT n_q=%d register %d..%d tiling %s launch %s %s" % (nq, first, first + n - 1, tiling, launch, prec))
+    plan, got, L = _eval({"nq": nq, "gates": gates, "marked": marked}, psi, prec, tiling, launch)
+    want, Lw, _ = O.evaluate(nq, gates, marked, psi)
+    tol = TOL64 if prec == "fp64" else TOL32
+    err = _relerr(got, want)
+    _say("  passes %d  normwise err %.3e" % (plan.passes(), err))
+    assert err <= tol and abs(L - Lw) <= tol
+
+
+@pytest.mark.parametrize("nq,n1", [(10, 7), (16, 11)])
+def test_qft_ladder_gate_list_against_dft(nq, n1):
+    rng = np.random.default_rng(nq)
+    psi = _state(rng, nq)
+    _say("App. A ladder n_q=%d n1=%d" % (nq, n1))
+    _, got, _ = _eval({"nq": nq, "gates": O.qft_gates(n1), "marked": []}, psi)
+    assert _relerr(got, O.qft_register(psi, nq, 1, n1)) <= TOL64
+
+
+def test_controlled_phases_bit_exact_where_the_factor_is_exact():
+    """CPHASE multiplies by -1 and relabelled SWAPs move data: the GPU matches the
+    oracle bit for bit.  CPHASEK with k = 1, 2 multiplies by exactly -1 and i on the
+    GPU, while the oracle's e^{2 pi i / 2^k} carries a rounding of order 1e-16 in
+    its zero component: within 1e-15 there."""
+    rng = np.random.default_rng(31)
+    nq = 15
+    psi = _state(rng, nq)
+    _say("exact phases n_q=%d" % nq)
+    gates = [("CPHASE", 1, 15), ("SWAP", 4, 12), ("CPHASE", 7, 6), ("SWAP", 15, 2), ("ORACLE",)]
+    _, got, _ = _eval({"nq": nq, "gates": gates, "marked": [77]}, psi)
+    want, _, _ = O.evaluate(nq, gates, [77], psi)
+    np.testing.assert_array_equal(got, want)
+    gates = [("CPHASEK", 2, 9, 1), ("SWAP", 4, 12), ("CPHASEK", 14, 3, 2)]
+    _, got, _ = _eval({"nq": nq, "gates": gates, "marked": []}, psi)
+    want, _, _ = O.evaluate(nq, gates, [], psi)
+    assert np.max(np.abs(got - want)) <= 1e-15 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("nq", [9, 14])
+def test_backward_through_qft_against_oracle_adjoint(nq):
+    pk = _pk()
+    rng = np.random.default_rng(700 + nq)
+    gates = [("HALL",), ("D2", 2, 0.4, 1.1, 0.2), ("QFT", 1, nq - 2), ("CPHASEK", 1, nq, 4), ("ORACLE",),
+             ("D4", 3, nq, 0.5, -0.9, 0.7), ("QFT", 2, nq - 3), ("SWAP", nq, 1)]
+    marked = [int(rng.integers(0, 1 << nq)), 5]
+    psi = _state(rng, nq)
+    plan = pk.Plan({"nq": nq, "gates": gates, "marked": marked})
+    x = torch.from_numpy(psi).to("cuda")
+    out, _, _ = pk.evaluate(plan, x, want_norm=False)
+    dL = torch.tensor([0.7], dtype=torch.float64, device="cuda")
+    _say("backward through QFT n_q=%d" % nq)
+    gpsi, gang = pk.backward(plan, out, dL)
+    torch.cuda.synchronize()
+    wpsi, wang = O.adjoint_grad(nq, gates, marked, psi, 0.7)
+    assert _relerr(gpsi.cpu().numpy(), wpsi) <= 1e-10
+    np.testing.assert_allclose(gang.cpu().numpy().reshape(-1, 3), wang, rtol=1e-9, atol=1e-12)
+
+
+def test_batched_qft_instances():
+    pk = _pk()
+    rng = np.random.default_rng(79)
+    probs, psis = [], []
+    for nq in (4, 15, 9, 12, 17):
+        probs.append({"nq": nq, "gates": [("QFT", 1, nq - 3), ("CPHASEK", 2, nq, 3), ("ORACLE",)], "marked": [3]})
+        psis.append(_state(rng, nq))
+    plan = pk.Plan(probs)
+    _say("batched QFT instances")
+    res, L, _ = pk.evaluate_batched(plan, torch.from_numpy(np.concatenate(psis)).to("cuda"))
+    torch.cuda.synchronize()
+    res = res.cpu().numpy()
+    offs = plan.offsets()
+    for k, (p, psi) in enumerate(zip(probs, psis)):
+        want, Lw, _ = O.evaluate(p["nq"], p["gates"], p["marked"], psi)
+        assert _relerr(res[offs[k]:offs[k + 1]], want) <= TOL64 and abs(float(L[k]) - Lw) <= TOL64
+
+
+# --------------------------------------------------------------------------- loaded state and marginal
+
+
+@pytest.mark.parametrize("n1,n2,x,M,prec", [(8, 4, 7, 15, "fp64"), (9, 5, 2, 21, "fp64"), (3, 2, 3, 4, "fp64"),
+                                            (11, 6, 5, 33, "fp64"), (9, 5, 2, 21, "fp32"), (4, 12, 101, 4000, "fp64"),
+                                            (17, 3, 3, 7, "fp32"), (1, 1, 1, 2, "fp64")])
+def test_shor_state_bit_exact(n1, n2, x, M, prec):
+    pk = _pk()
+    _say("shor_state n1=%d n2=%d x=%d M=%d %s" % (n1, n2, x, M, prec))
+    got = pk.shor_state(n1, n2, x, M, prec=prec)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    want = O.shor_state(n1, n2, x, M)
+    if prec == "fp32":
+        want = want.astype(np.complex64)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_shor_state_rejects_bad_arguments():
+    pk = _pk()
+    for args in ((0, 4, 7, 15), (8, 4, 7, 17), (8, 4, 15, 15), (8, 4, 0, 15), (26, 5, 2, 21)):
+        with pytest.raises(pk.PaperkernError):
+            pk.shor_state(*args)
+
+
+@pytest.mark.parametrize("nq,n_low,prec", [(12, 0, "fp64"), (12, 3, "fp64"), (12, 6, "fp64"), (12, 7, "fp64"),
+                                           (20, 10, "fp64"), (20, 13, "fp64"), (20, 14, "fp64"), (20, 17, "fp64"),
+                                           (12, 12, "fp64"), (5, 2, "fp64"), (3, 3, "fp64"), (18, 9, "fp32"),
+                                           (18, 15, "fp32"), (16, 4, "fp32")])
+def test_marginal_against_oracle(nq, n_low, prec):
+    pk = _pk()
+    rng = np.random.default_rng(nq * 10 + n_low)
+    psi = _state(rng, nq) * 1.3
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    if prec == "fp32":
+        psi = psi.astype(np.complex64).astype(np.complex128)
+    _say("marginal n_q=%d n_low=%d %s" % (nq, n_low, prec))
+    p = pk.marginal(torch.from_numpy(psi).to(dt).to("cuda"), nq, n_low)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(p.cpu().numpy(), O.marginal(psi, nq, n_low), rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("M,x,prec", [(15, 7, "fp64"), (21, 2, "fp64"), (35, 3, "fp64"), (55, 2, "fp64"),
+                                      (21, 5, "fp32"), (39, 7, "fp32")])
+def test_shor_path_against_probshor(M, x, prec):
+    """Load (Eq. Shor2), QFT of register one (App. A), marginal of register one:
+    p(n) against the closed form of Eq. probshor, and amplitudes at sampled labels
+    against the direct sum of Eq. QFT1."""
+    pk = _pk()
+    n1, n2 = pk.shor_register_sizes(M)
+    n1 = min(n1, 20 - n2)
+    nq = n1 + n2
+    _say("Shor path M=%d x=%d n1=%d n2=%d %s" % (M, x, n1, n2, prec))
+    psi = pk.shor_state(n1, n2, x, M, prec=prec)
+    plan = pk.Plan({"nq": nq, "gates": [("QFT", 1, n1)], "marked": []}, prec=prec)
+    pk.evaluate(plan, psi, out=psi, want_norm=False)
+    p = pk.marginal(psi, nq, n2)
+    torch.cuda.synchronize()
+    tol = TOL64 if prec == "fp64" else TOL32
+    want = O.probshor_marginal(n1, x, M)
+    assert np.max(np.abs(p.cpu().numpy() - want)) <= tol * np.max(want)
+    rng = np.random.default_rng(M)
+    labels = np.unique(rng.integers(0, 1 << nq, 2000))
+    got = psi[torch.from_numpy(labels).to("cuda")].cpu().numpy().astype(np.complex128)
+    amp = O.shor_qft_amplitudes(n1, n2, x, M, labels)
+    assert np.max(np.abs(got - amp)) <= tol * max(np.max(np.abs(amp)), 1.0 / (1 << n1))

@@ -640,3 +640,13 @@ def test_probshor_closed_form_equals_qft_of_loaded_state(M, x):
     q = O.probshor_marginal(n1, x, M)
     np.testing.assert_allclose(p, q, rtol=0, atol=1e-14)
     assert abs(q.sum() - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("M,x", [(15, 7), (21, 2), (35, 3), (39, 5)])
+def test_shor_qft_amplitudes_equal_qft_of_loaded_state(M, x):
+    n1, n2 = O.shor_register_sizes(M)
+    n1 = min(n1, 16 - n2)
+    full = O.qft_register(O.shor_state(n1, n2, x, M), n1 + n2, 1, n1)
+    rng = np.random.default_rng(M)
+    labels = np.unique(np.concatenate([rng.integers(0, 1 << (n1 + n2), 300), np.nonzero(np.abs(full) > 1e-3)[0][:200]]))
+    np.testing.assert_allclose(O.shor_qft_amplitudes(n1, n2, x, M, labels), full[labels], rtol=0, atol=1e-14)

@@ -369,3 +369,94 @@ def test_scale_is_exact_power_of_two_for_even_hadamard_count():
     for s in scales:
         m, e = math.frexp(abs(s))
         assert m == 0.5
+
+
+# --------------------------------------------------------------------------- QFT, controlled phases, SWAP relabelling
+
+
+@pytest.mark.parametrize("nq,first,n,tiling,reg_bits", [
+    (6, 1, 6, None, 4), (9, 1, 6, None, 5), (10, 3, 5, (5, 2, 1), 4), (12, 1, 8, (6, 2, 1), 4),
+    (13, 2, 9, (7, 3, 1), 5), (11, 1, 11, (6, 1, 1), 4), (12, 4, 7, (5, 0, 1), 4), (9, 1, 9, (6, 2, 0), 4),
+    (14, 1, 10, None, 4),
+])
+def test_qft_schedule_matches_dft(nq, first, n, tiling, reg_bits):
+    rng = np.random.default_rng(nq * 31 + first * 7 + n)
+    gates = [("H", nq), ("QFT", first, n), ("ORACLE",), ("D2", first, 0.3, 1.1, -0.2)]
+    prob = {"nq": nq, "gates": gates, "marked": [int(rng.integers(0, 1 << nq))]}
+    _check_forward(prob, _state(rng, nq), tiling, reg_bits=reg_bits)
+
+
+@pytest.mark.parametrize("nq,n1,tiling", [(8, 5, None), (12, 8, (6, 2, 1)), (11, 7, (5, 1, 1))])
+def test_qft_ladder_gate_list_matches_dft(nq, n1, tiling):
+    rng = np.random.default_rng(nq + n1)
+    ladder = O.qft_gates(n1)  # the explicit H / CPHASEK / SWAP list of App. A
+    prob = {"nq": nq, "gates": ladder, "marked": []}
+    psi = _state(rng, nq)
+    plan = pk.Plan(prob)
+    if tiling:
+        plan.set_tiling(*tiling)
+    got, _ = run_forward([prob], plan.describe(), 0, psi)
+    np.testing.assert_allclose(got, O.qft_register(psi, nq, 1, n1), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("nq,tiling", [(8, None), (11, (5, 2, 1)), (12, (6, 2, 1)), (10, (4, 0, 0))])
+def test_backward_through_phases_and_relabelled_swaps(nq, tiling):
+    rng = np.random.default_rng(500 + nq)
+    gates = (W.grover_gates((2, 1, 0.9, 0.4, 0.1)) + [("QFT", 2, nq - 2), ("CPHASEK", 1, nq, 3),
+             ("SWAP", 3, nq - 1), ("D4", 1, 4, 0.3, -0.8, 1.2), ("CPHASE", nq, 2)])
+    prob = {"nq": nq, "gates": gates, "marked": [int(rng.integers(0, 1 << nq)), 3]}
+    psi = _state(rng, nq)
+    plan = pk.Plan(prob)
+    if tiling:
+        plan.set_tiling(*tiling)
+    desc = plan.describe()
+    psi_out, _, _ = O.evaluate(nq, gates, prob["marked"], psi)
+    gpsi, gang = run_backward([prob], desc, 0, psi_out, 0.5)
+    wpsi, wang = O.adjoint_grad(nq, gates, prob["marked"], psi, 0.5)
+    np.testing.assert_allclose(gpsi, wpsi, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(gang, wang, rtol=0, atol=1e-12)
+
+
+def test_qft_of_register_one_at_thirty_qubits_takes_four_passes():
+    for prec in ("fp64", "fp32"):
+        desc = pk.Plan({"nq": 30, "gates": [("QFT", 1, 20)], "marked": []}, prec=prec).describe()
+        fw = desc["instances"][0]["forward"]
+        assert len(fw) == 4
+        # every pair swap is a relabelling: no 4x4 matrix, and 20 state bits change place
+        assert not any(op["kind"] == "MAT4" for p in fw for st in p["stages"] for op in st["ops"])
+        assert sum(sum(a != b for a, b in zip(p["tile_bits"], p["store_bits"])) for p in fw) == 20
+        assert sum(op["kind"] == "PHASE" for p in fw for st in p["stages"] for op in st["ops"]) == 190
+
+
+def test_swap_on_a_carrier_bit_stays_a_matrix():
+    # carriers are written in contiguous runs, so a SWAP touching one is applied as a 4x4
+    desc = pk.Plan({"nq": 8, "gates": [("SWAP", 8, 2)], "marked": []}).describe()
+    p = desc["instances"][0]["forward"][0]
+    assert p["tile_bits"] == p["store_bits"]
+    assert any(op["kind"] == "MAT4" for st in p["stages"] for op in st["ops"])
+    desc = pk.Plan({"nq": 8, "gates": [("SWAP", 1, 2)], "marked": []}).describe()
+    p = desc["instances"][0]["forward"][0]
+    assert p["tile_bits"] != p["store_bits"]
+
+
+def test_batched_plan_with_qft_instances():
+    rng = np.random.default_rng(8)
+    probs = [{"nq": nq, "gates": [("QFT", 1, nq - 2), ("CPHASEK", 1, nq, 2)], "marked": [1]} for nq in (5, 9, 12, 7)]
+    plan = pk.Plan(probs)
+    desc = plan.describe()
+    for k, p in enumerate(probs):
+        psi = _state(rng, p["nq"])
+        got, L = run_forward(probs, desc, k, psi)
+        want, Lw, _ = O.evaluate(p["nq"], p["gates"], p["marked"], psi)
+        np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("bad,msg", [
+    ({"nq": 4, "gates": [("QFT", 3, 3)], "marked": []}, "QFT"),
+    ({"nq": 4, "gates": [("QFT", 1, 0)], "marked": []}, "QFT"),
+    ({"nq": 4, "gates": [("QFT", 0, 2)], "marked": []}, "QFT"),
+])
+def test_create_rejects_bad_qft(bad, msg):
+    with pytest.raises(pk.PaperkernError) as e:
+        pk.Plan(bad)
+    assert msg in str(e.value)

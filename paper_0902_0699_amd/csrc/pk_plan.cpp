@@ -646,6 +646,17 @@ struct Compiler {
             // --- local items and stages
             const LocalPass lp = local_pass(items, t, sel, sel.size());
             auto st = plan_stages(lp.items);
+            if (lp.maps.size() > 1 && st.size() == 1) {
+                // The tile is written with another map than it was read with, so
+                // amplitudes change threads: in place, every thread's loads must
+                // complete before any thread stores.  The barrier of an LDS
+                // exchange guarantees that; a one-stage pass has none, so it gets
+                // a second stage in a store layout.
+                std::vector<int> rb;
+                for (int b = k - 1; b >= 0 && (int)rb.size() < RB; --b)
+                    if (k - C < RB || b >= C) rb.push_back(b);
+                st.push_back({rb, {}});
+            }
             std::vector<int> fpos(nq, -1);  // position of each bit outside the tile in the tile index
             {
                 std::vector<char> in_t(nq, 0);

@@ -85,6 +85,29 @@ def test_qft_against_dft(nq, first, n, tiling, launch, prec):
     assert err <= tol and abs(L - Lw) <= tol
 
 
+@pytest.mark.parametrize("nq,n1,prec", [(24, 14, "fp64"), (22, 12, "fp64"), (26, 16, "fp64"), (24, 14, "fp32"),
+                                        (20, 16, "fp64")])
+def test_qft_in_place_without_norm(nq, n1, prec):
+    """In place and without the norm readout (no reduction barrier at the end of the
+    last pass): relabelling passes must still order every load before any store."""
+    pk = _pk()
+    rng = np.random.default_rng(nq + n1)
+    psi = _state(rng, nq)
+    if prec == "fp32":
+        psi = psi.astype(np.complex64).astype(np.complex128)
+    _say("QFT in place, no norm: n_q=%d n1=%d %s" % (nq, n1, prec))
+    plan = pk.Plan({"nq": nq, "gates": [("QFT", 1, n1)], "marked": []}, prec=prec)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    x = torch.from_numpy(psi).to(dt).to("cuda")
+    for _ in range(2):  # the second call replays the captured graph
+        x.copy_(torch.from_numpy(psi).to(dt).to("cuda"))
+        pk.evaluate(plan, x, out=x, want_norm=False)
+        torch.cuda.synchronize()
+        err = _relerr(x.cpu().numpy().astype(np.complex128), O.qft_register(psi, nq, 1, n1))
+        _say("  passes %d  normwise err %.3e" % (plan.passes(), err))
+        assert err <= (TOL64 if prec == "fp64" else TOL32)
+
+
 @pytest.mark.parametrize("nq,n1", [(10, 7), (16, 11)])
 def test_qft_ladder_gate_list_against_dft(nq, n1):
     rng = np.random.default_rng(nq)

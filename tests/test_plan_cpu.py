@@ -460,3 +460,15 @@ def test_create_rejects_bad_qft(bad, msg):
     with pytest.raises(pk.PaperkernError) as e:
         pk.Plan(bad)
     assert msg in str(e.value)
+
+
+def test_relabelling_passes_have_an_exchange():
+    """A pass that writes its tile with another map than it read it with must have
+    at least two stages: the LDS exchange's barrier makes every thread's loads
+    complete before any thread stores in place."""
+    for nq, n1, prec in ((24, 14, "fp64"), (30, 20, "fp64"), (30, 20, "fp32"), (12, 8, "fp64"), (16, 12, "fp32")):
+        desc = pk.Plan({"nq": nq, "gates": [("QFT", 1, n1)], "marked": [1]}, prec=prec).describe()
+        for p in desc["instances"][0]["forward"] + desc["instances"][0]["backward"]:
+            if p["tile_bits"] != p["store_bits"]:
+                assert len(p["stages"]) >= 2
+                assert any(u["exchange"] for u in p["subs"][1:])

@@ -851,14 +851,15 @@ def probshor_marginal(n1, xguess, M):
         |C_{n,k}|^2 = N^-2 [sin(D_k pi n r/N) / sin(pi n r/N)]^2,
 
     which is D_k^2 / N^2 where n r/N is an integer (the 0/0 limit, the sum of D_k
-    ones).  Returns p(n) = sum_k |C_{n,k}|^2, n = 0 .. N-1.  Both sines are taken
-    of exactly reduced arguments (n r mod N, D n r mod N), since only sin^2
-    enters."""
+    ones).  Returns p(n) = sum_k |C_{n,k}|^2, n = 0 .. N-1.  Only sin^2 enters, so
+    each sine is taken of an exactly reduced argument in [0, pi/2]: with
+    a = n r mod N, sin^2(pi a/N) = sin^2(pi min(a, N - a)/N) (and likewise for
+    D n r mod N); near pi the rounded argument would cost relative accuracy."""
     N = 1 << n1
     r = multiplicative_order(xguess, M)
     n = np.arange(N, dtype=np.int64)
     a = (n * r) % N
-    s1 = np.sin(np.pi * a / N)
+    s1 = np.sin(np.pi * np.minimum(a, N - a) / N)
     p = np.zeros(N)
     # D_k takes at most two values; group the k by it
     counts = {}
@@ -867,7 +868,7 @@ def probshor_marginal(n1, xguess, M):
         counts[d] = counts.get(d, 0) + 1
     for d, cnt in counts.items():
         b = (d * a) % N
-        s2 = np.sin(np.pi * b / N)
+        s2 = np.sin(np.pi * np.minimum(b, N - b) / N)
         with np.errstate(divide="ignore", invalid="ignore"):
             ratio2 = np.where(a == 0, float(d) * d, (s2 / np.where(a == 0, 1.0, s1)) ** 2)
         p += cnt * ratio2 / (float(N) * N)

@@ -650,3 +650,23 @@ def test_shor_qft_amplitudes_equal_qft_of_loaded_state(M, x):
     rng = np.random.default_rng(M)
     labels = np.unique(np.concatenate([rng.integers(0, 1 << (n1 + n2), 300), np.nonzero(np.abs(full) > 1e-3)[0][:200]]))
     np.testing.assert_allclose(O.shor_qft_amplitudes(n1, n2, x, M, labels), full[labels], rtol=0, atol=1e-14)
+
+
+def test_probshor_closed_form_at_twenty_qubits_against_direct_sums():
+    """At n1 = 20 (M = 899, the full-size workload) the closed form against
+    p(n) = sum_k |C_{n,k}|^2 from the direct sums of Eq. QFT1, at the peaks
+    (n r / N near an integer, where the sines are smallest), next to them, and at
+    random n."""
+    M, x = 899, W.shor_xguess(W.SEEDS["shor"])
+    n1, n2 = O.shor_register_sizes(M)
+    N = 1 << n1
+    r = O.multiplicative_order(x, M)
+    ks = sorted({pow(x, j, M) for j in range(r)})
+    rng = np.random.default_rng(0)
+    ns = [0, 1, N - 1] + [round(j * N / r) + d for j in (1, 2, 35, 69) for d in (-1, 0, 1)]
+    ns += [int(v) for v in rng.integers(0, N, 4)]
+    q = O.probshor_marginal(n1, x, M)
+    for n in ns:
+        labels = np.array([(n << n2) + k for k in ks], dtype=np.int64)
+        direct = float(np.sum(np.abs(O.shor_qft_amplitudes(n1, n2, x, M, labels)) ** 2))
+        assert abs(q[n] - direct) <= 1e-13 * q.max(), (n, q[n], direct)

@@ -42,12 +42,15 @@ constexpr int kPhaseSlots = 4;  // phase accumulators per sub-stage
 // (a qubit outside the tile, so the same for the whole tile).  The register
 // bits involved define the phase's accumulator slot (Stage::phase_pm); a thread
 // multiplies the factors of a slot together and applies the product once to
-// every register whose index has the slot's register bits set.
+// every register whose index has the slot's register bits set.  A sub-stage's
+// phases are stored grouped by slot (Stage::phase_cnt), so the kernel runs one
+// branch-free loop per slot.
 struct PhaseOp {
     int32_t slot;    // accumulator slot of the sub-stage
     uint32_t tmask;  // local label bits held by the thread index that must be 1
     int64_t fmask;   // tile-index bits that must be 1
-    double c, s;
+    double cm1, s;   // the factor as (c - 1, s): 1 + on * (c - 1) and on * s give the
+                     // factor or 1 without a select (c - 1 is exact for c >= 1/2)
 };
 
 // One step of a stage's op list, as the plan compiler schedules it on the host;
@@ -80,7 +83,8 @@ struct Stage {
     int32_t flip_pre;         // flip index or -1
     int32_t phase_first;      // first PhaseOp of this sub-stage's controlled phases
     int32_t phase_count;      // number of them (diagonal: any order)
-    int32_t phase_pm[kPhaseSlots];  // register-bit mask of each accumulator slot, -1 when unused
+    int32_t phase_pm[kPhaseSlots];   // register-bit mask of each accumulator slot, -1 when unused
+    int32_t phase_cnt[kPhaseSlots];  // phases of each slot, stored slot after slot
     int32_t mat_pre_a;        // register bit of a matrix before the Hadamards, or -1
     int32_t mat_pre;          // its matrix index
     int32_t hmask1;           // register bits that get a Hadamard

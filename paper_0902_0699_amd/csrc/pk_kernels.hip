@@ -292,41 +292,55 @@ __device__ __forceinline__ void op_d4bwd(T (&v)[NV][NR], const PK_CONST double* 
     }
 }
 
-// The controlled phases of one sub-stage (CPHASE, CPHASEK; Eq. cphasek).  Each
-// phase's factor is multiplied into the accumulator of its slot when the tile
-// index and the thread's part of the label have its other bits set; every
-// register whose index holds the slot's register bits then takes the
-// accumulated product once.  Uniform branches only: the phase list, the tile
-// index and the slot masks are the same for the whole workgroup.
+// The controlled phases of one sub-stage (CPHASE, CPHASEK; Eq. cphasek).  For
+// each accumulator slot, the factors of its phases are multiplied together,
+// each switched to 1 unless the tile index and the thread's part of the label
+// have the phase's other bits set; every register whose index holds the slot's
+// register bits then takes the product once.  The loop over a slot's phases is
+// branch-free: a phase's factor is (1 + on (c - 1), on s) with on = 0 or 1, a
+// product the compiler cannot turn into a select (which it would lower to a
+// branch around a late scalar load of c), so every table read is unconditional
+// and the loads of several phases are in flight together.  Two independent
+// product chains halve the dependent multiply latency.
 template <int NV, int NR, typename T>
 __device__ __forceinline__ void apply_phases(const KArgs& a, const PK_CONST Stage* S, T (&v)[NV][NR],
                                              const Layout& L, int64_t tile) {
     using R = decltype(v[0][0].x);
-    T acc[kPhaseSlots];
-#pragma unroll
-    for (int u = 0; u < kPhaseSlots; ++u) acc[u] = T{(R)1, (R)0};
     const PK_CONST PhaseOp* ph = cptr(a.phases) + S->phase_first;
-    const int n = S->phase_count;
-    for (int q = 0; q < n; ++q) {
-        const int64_t fm = ph[q].fmask;
-        if ((tile & fm) != fm) continue;
-        const unsigned tm = ph[q].tmask;
-        const bool on = (L.jt & tm) == tm;
-        const R c = on ? (R)ph[q].c : (R)1, s = on ? (R)ph[q].s : (R)0;
-        const int slot = ph[q].slot;
-#pragma unroll
-        for (int u = 0; u < kPhaseSlots; ++u) {
-            if (slot != u) continue;
-            const R x = acc[u].x, y = acc[u].y;
-            acc[u].x = x * c - y * s;
-            acc[u].y = x * s + y * c;
-        }
-    }
 #pragma unroll
     for (int u = 0; u < kPhaseSlots; ++u) {
+        const int cnt = S->phase_cnt[u];
+        if (cnt == 0) continue;
+        R c0 = 1, s0 = 0, c1 = 1, s1 = 0;
+        int q = 0;
+#pragma unroll 2
+        for (; q + 1 < cnt; q += 2) {
+            const int64_t fa = ph[q].fmask, fb = ph[q + 1].fmask;
+            const unsigned ta = ph[q].tmask, tb = ph[q + 1].tmask;
+            const R oa = (R)(((tile & fa) == fa) & ((L.jt & ta) == ta));
+            const R ob = (R)(((tile & fb) == fb) & ((L.jt & tb) == tb));
+            const R ca = fma(oa, (R)ph[q].cm1, (R)1), sa = oa * (R)ph[q].s;
+            const R cb = fma(ob, (R)ph[q + 1].cm1, (R)1), sb = ob * (R)ph[q + 1].s;
+            R x = c0, y = s0;
+            c0 = x * ca - y * sa;
+            s0 = x * sa + y * ca;
+            x = c1;
+            y = s1;
+            c1 = x * cb - y * sb;
+            s1 = x * sb + y * cb;
+        }
+        if (q < cnt) {
+            const int64_t fa = ph[q].fmask;
+            const unsigned ta = ph[q].tmask;
+            const R oa = (R)(((tile & fa) == fa) & ((L.jt & ta) == ta));
+            const R ca = fma(oa, (R)ph[q].cm1, (R)1), sa = oa * (R)ph[q].s;
+            const R x = c0, y = s0;
+            c0 = x * ca - y * sa;
+            s0 = x * sa + y * ca;
+        }
+        ph += cnt;
+        const R c = c0 * c1 - s0 * s1, s = c0 * s1 + s0 * c1;
         const int pm = S->phase_pm[u];
-        if (pm < 0) continue;
-        const R c = acc[u].x, s = acc[u].y;
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
             if ((i & pm) != pm) continue;

@@ -184,8 +184,19 @@ Stage blank_sub(const HostStage& hs, int exchange) {
     s.mat_pre_a = s.mat_post_a = s.d2b_a = -1;
     s.mat4 = s.d4b_mat = -1;
     s.phase_first = s.phase_count = 0;
-    for (int u = 0; u < kPhaseSlots; ++u) s.phase_pm[u] = -1;
+    for (int u = 0; u < kPhaseSlots; ++u) {
+        s.phase_pm[u] = -1;
+        s.phase_cnt[u] = 0;
+    }
     return s;
+}
+
+// Stores a finished sub-stage's phases grouped by slot (stable) and counts them.
+void group_phases(Stage& s, std::vector<PhaseOp>* table) {
+    if (s.phase_count == 0) return;
+    auto b = table->begin() + s.phase_first, e = b + s.phase_count;
+    std::stable_sort(b, e, [](const PhaseOp& x, const PhaseOp& y) { return x.slot < y.slot; });
+    for (auto it = b; it != e; ++it) ++s.phase_cnt[it->slot];
 }
 
 // A phase joins the accumulator slot of its register bits (the register bits of
@@ -215,7 +226,7 @@ int place_phase(Stage& s, int cursor, const HostPhase& h, const HostStage& hs, s
         }
     if (slot < 0) return -1;
     if (s.phase_count == 0) s.phase_first = (int32_t)table->size();
-    table->push_back({slot, tmask, h.fmask, h.c, h.s});
+    table->push_back({slot, tmask, h.fmask, h.c - 1.0, h.s});
     ++s.phase_count;
     return S_PHASE;
 }
@@ -273,6 +284,7 @@ std::vector<Stage> pack_stage(const HostStage& hs, const std::vector<HostPhase>&
     for (const Op& o : hs.ops) {
         int slot = put(o);
         if (slot < 0) {
+            group_phases(cur, table);
             subs.push_back(cur);
             cur = blank_sub(hs, 0);
             cursor = 0;
@@ -280,6 +292,7 @@ std::vector<Stage> pack_stage(const HostStage& hs, const std::vector<HostPhase>&
         }
         cursor = slot;
     }
+    group_phases(cur, table);
     subs.push_back(cur);
     return subs;
 }
@@ -1363,6 +1376,8 @@ std::string describe(const Plan* plan) {
                          std::to_string(u.phase_first) + ",\"phase_count\":" + std::to_string(u.phase_count) +
                          ",\"phase_pm\":[" + std::to_string(u.phase_pm[0]) + "," + std::to_string(u.phase_pm[1]) +
                          "," + std::to_string(u.phase_pm[2]) + "," + std::to_string(u.phase_pm[3]) + "]" +
+                         ",\"phase_cnt\":[" + std::to_string(u.phase_cnt[0]) + "," + std::to_string(u.phase_cnt[1]) +
+                         "," + std::to_string(u.phase_cnt[2]) + "," + std::to_string(u.phase_cnt[3]) + "]" +
                          ",\"mat_pre_a\":" +
                          std::to_string(u.mat_pre_a) + ",\"mat_pre\":" + std::to_string(u.mat_pre) +
                          ",\"hmask1\":" + std::to_string(u.hmask1) + ",\"flip_mid\":" +
@@ -1387,7 +1402,7 @@ std::string describe(const Plan* plan) {
         const PhaseOp& ph = plan->phases[q];
         char buf[160];
         std::snprintf(buf, sizeof buf, "%s[%d,%u,%lld,%.17g,%.17g]", q ? "," : "", ph.slot, ph.tmask,
-                      (long long)ph.fmask, ph.c, ph.s);
+                      (long long)ph.fmask, ph.cm1, ph.s);
         s += buf;
     }
     s += "],\"flips\":[";

@@ -152,8 +152,12 @@ def _run_phases(desc, nq, tb, u, vecs):
     j = _local_label(nq, tb, g)
     tile = _tile_index(nq, tb, g)
     rb = u["rb"]
+    # stored grouped by slot, with the counts the kernel loops over
+    slots = [desc["phases"][q][0] for q in range(u["phase_first"], u["phase_first"] + u["phase_count"])]
+    assert slots == sorted(slots) and [slots.count(k) for k in range(4)] == u["phase_cnt"]
     for q in range(u["phase_first"], u["phase_first"] + u["phase_count"]):
-        slot, tmask, fmask, c, s = desc["phases"][q]
+        slot, tmask, fmask, cm1, s = desc["phases"][q]
+        c = 1.0 + cm1  # stored as c - 1
         pm = u["phase_pm"][slot]
         assert pm >= 0
         lmask = tmask

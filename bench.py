@@ -285,7 +285,7 @@ def two_qubit_run(torch, pk, nq, steps):
 
 
 def shor_run(torch, pk, W, steps, prec):
-    """Shor's data path at n_q = 30 (Sec. 7): the loaded state of Eq. Shor2, the QFT
+    """Shor's data path at n_q = 30 (Sec. 5.2): the loaded state of Eq. Shor2, the QFT
     of register one (App. A) in place, and the distribution of register one; each
     part timed with HIP events on the current stream."""
     M = W.SHOR_M

@@ -254,7 +254,7 @@ int pk_pair_indices(int32_t nq, int32_t i_s, int64_t first, int64_t count, int64
                     int64_t* n1, void* stream);
 
 /*
- * pk_shor_state -- the loaded two-register state of Shor's algorithm (Sec. 7,
+ * pk_shor_state -- the loaded two-register state of Shor's algorithm (Sec. 5.2,
  * Step 3, Eq. Shor2): register one (n1 qubits, qubits 1..n1, the high bits)
  * holds every n < 2^n1 with equal weight and register two (n2 qubits, the low
  * bits) holds f(n) = xguess^n mod M:

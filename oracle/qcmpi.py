@@ -28,7 +28,7 @@ Gate lists are sequences of tuples, applied left to right (first tuple first):
                                   first .. first+n-1 (App. A), applied by its definition
                                   <n|QFT|n'> = N^(-1/2) e^{2 pi i n n'/N}, N = 2^n
 
-The Shor section (Sec. 7 steps 1-6, App. A) adds the register sizes, the
+The Shor section (Sec. 5.2, Steps 1-6; App. A) adds the register sizes, the
 loaded state of Eq. Shor2, the QFT ladder of App. A as a gate list, the
 register-1 marginal p(n) = sum_k |C_{n,k}|^2 and its closed form (Eq. probshor).
 """
@@ -736,7 +736,7 @@ def grover_sampled(nq, gates, marked, psi_in, indices):
 
 
 # ---------------------------------------------------------------------------
-# Shor's data path (Sec. 7 steps 1-6) and the QFT (App. A)
+# Shor's data path (Sec. 5.2, Steps 1-6) and the QFT (App. A)
 # ---------------------------------------------------------------------------
 
 

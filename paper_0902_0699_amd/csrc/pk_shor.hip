@@ -1,4 +1,4 @@
-// Device kernels of Shor's data path (Sec. 7): the loaded two-register state
+// Device kernels of Shor's data path (Sec. 5.2): the loaded two-register state
 // (Step 3, Eq. Shor2) and the distribution of a measurement of register one
 // (Step 6: p(n) = sum_k |C_{n,k}|^2).  The QFT between them (Step 5, App. A) is
 // an ordinary gate list run by the pass kernels.

@@ -1,4 +1,4 @@
-"""GPU parity of Shor's data path (Sec. 7, App. A) through the C-ABI.
+"""GPU parity of Shor's data path (Sec. 5.2, App. A) through the C-ABI.
 
   * QFT (gate kind QFT, and the App. A ladder given gate by gate): against the
     oracle's DFT along the register axis; controlled phases and relabelled

@@ -31,6 +31,9 @@ Gate lists are sequences of tuples, applied left to right (first tuple first):
 The Shor section (Sec. 5.2, Steps 1-6; App. A) adds the register sizes, the
 loaded state of Eq. Shor2, the QFT ladder of App. A as a gate list, the
 register-1 marginal p(n) = sum_k |C_{n,k}|^2 and its closed form (Eq. probshor).
+
+The density-matrix section (Sec. 6.1) adds the ensemble density matrix of
+weighted universes, its purity Tr rho^2 and its entropy.
 """
 
 import math
@@ -53,6 +56,7 @@ __all__ = [
     "kron_twoop", "TWO_QUBIT", "PARAMETRIC",
     "ceil_log2", "shor_register_sizes", "shor_f", "shor_state", "qft_register", "qft_gates",
     "marginal", "multiplicative_order", "probshor_marginal", "shor_qft_amplitudes",
+    "density_matrix", "density_matrix_loop", "purity", "purity_gram", "entropy_bits", "spectrum",
 ]
 
 # ---------------------------------------------------------------------------
@@ -901,3 +905,59 @@ def shor_qft_amplitudes(n1, n2, xguess, M, labels):
         ph = (n * j) % N
         out[i] = np.exp(2j * np.pi * ph / N).sum() / N
     return out
+
+
+# ---------------------------------------------------------------------------
+# Ensemble density matrix (Sec. 6.1)
+# ---------------------------------------------------------------------------
+
+
+def density_matrix(states, weights):
+    """<n|rho|n'> = sum_alpha P_alpha C_alpha(n) C_alpha^*(n') (Sec. 6.1), for the
+    universes' states as rows of ``states`` (A x N) and their weights P_alpha.
+    One library matmul: rho = (C^T diag(P)) conj(C)."""
+    C = np.asarray(states, dtype=np.complex128)
+    P = np.asarray(weights, dtype=np.float64)
+    return (C.T * P) @ C.conj()
+
+
+def density_matrix_loop(states, weights):
+    """The same sum written out element by element (small sizes only)."""
+    C = np.asarray(states, dtype=np.complex128)
+    A, N = C.shape
+    rho = np.zeros((N, N), dtype=np.complex128)
+    for n in range(N):
+        for m in range(N):
+            rho[n, m] = sum(weights[a] * C[a, n] * np.conj(C[a, m]) for a in range(A))
+    return rho
+
+
+def purity(rho):
+    """Tr rho^2 = sum_{n,n'} |rho_{n n'}|^2 for Hermitian rho (1 for a pure state,
+    below 1 for a mixed one: the footnote to Sec. 6.1 and the noise discussion of
+    Sec. 6.3)."""
+    r = np.asarray(rho)
+    return float(np.sum(np.abs(r) ** 2))
+
+
+def purity_gram(states, weights):
+    """Tr rho^2 from the universes alone: sum_{a,b} P_a P_b |<a|b>|^2, with no N x N
+    matrix."""
+    C = np.asarray(states, dtype=np.complex128)
+    P = np.asarray(weights, dtype=np.float64)
+    G = C.conj() @ C.T
+    return float(np.sum(np.outer(P, P) * np.abs(G) ** 2))
+
+
+def spectrum(rho):
+    """Eigenvalues of the Hermitian rho, ascending (LAPACK through numpy)."""
+    return np.linalg.eigvalsh(np.asarray(rho, dtype=np.complex128))
+
+
+def entropy_bits(eigenvalues):
+    """S = -sum_i lambda_i log2 lambda_i over the positive eigenvalues (Sec. 6.1 leaves
+    the base open; base 2 gives S = n_q for the maximally mixed state).  Eigenvalues
+    at or below zero, which rounding leaves in place of exact zeros, add nothing."""
+    lam = np.asarray(eigenvalues, dtype=np.float64)
+    lam = lam[lam > 0]
+    return float(-np.sum(lam * np.log2(lam)))

@@ -670,3 +670,53 @@ def test_probshor_closed_form_at_twenty_qubits_against_direct_sums():
         labels = np.array([(n << n2) + k for k in ks], dtype=np.int64)
         direct = float(np.sum(np.abs(O.shor_qft_amplitudes(n1, n2, x, M, labels)) ** 2))
         assert abs(q[n] - direct) <= 1e-13 * q.max(), (n, q[n], direct)
+
+
+# --------------------------------------------------------------------------- density matrix (Sec. 6.1)
+
+
+def test_density_matrix_against_element_loop():
+    rng = np.random.default_rng(41)
+    C = np.array([_rand_state(rng, 3) for _ in range(5)])
+    P = rng.uniform(0.1, 1.0, 5)
+    np.testing.assert_allclose(O.density_matrix(C, P), O.density_matrix_loop(C, P), atol=1e-15)
+
+
+def test_pure_state_density_matrix():
+    """Sec. 6.1: for one state rho^2 = rho, Tr rho = 1, eigenvalues 1 and 2^n_q - 1 zeros, S = 0."""
+    rng = np.random.default_rng(42)
+    psi = _rand_state(rng, 5)
+    rho = O.density_matrix(psi[None, :], [1.0])
+    np.testing.assert_allclose(rho @ rho, rho, atol=1e-15)
+    assert abs(np.trace(rho).real - 1.0) < 1e-14
+    lam = O.spectrum(rho)
+    assert abs(lam[-1] - 1.0) < 1e-13 and np.all(np.abs(lam[:-1]) < 1e-13)
+    assert abs(O.entropy_bits(lam)) < 1e-12 and abs(O.purity(rho) - 1.0) < 1e-13
+
+
+def test_orthonormal_universes_have_their_weights_as_eigenvalues():
+    rng = np.random.default_rng(43)
+    Q, _ = np.linalg.qr(rng.standard_normal((16, 16)) + 1j * rng.standard_normal((16, 16)))
+    P = rng.uniform(0.0, 1.0, 6)
+    P /= P.sum()
+    rho = O.density_matrix(Q[:, :6].T, P)
+    lam = O.spectrum(rho)
+    np.testing.assert_allclose(lam[-6:], np.sort(P), atol=1e-14)
+    np.testing.assert_allclose(lam[:-6], 0.0, atol=1e-14)
+    assert abs(O.entropy_bits(lam) - float(-np.sum(P * np.log2(P)))) < 1e-12
+    # the basis ensemble with equal weights is maximally mixed: S = n_q bits
+    lam = O.spectrum(O.density_matrix(np.eye(16), np.full(16, 1 / 16)))
+    assert abs(O.entropy_bits(lam) - 4.0) < 1e-12
+
+
+def test_purity_equals_gram_route_and_trace_is_one():
+    rng = np.random.default_rng(44)
+    C = np.array([_rand_state(rng, 6) for _ in range(9)])
+    P = rng.uniform(0.0, 1.0, 9)
+    P /= P.sum()
+    rho = O.density_matrix(C, P)
+    assert abs(np.trace(rho).real - 1.0) < 1e-14 and abs(np.trace(rho).imag) < 1e-16
+    assert abs(O.purity(rho) - O.purity_gram(C, P)) < 1e-14
+    assert O.purity(rho) < 1.0
+    np.testing.assert_allclose(rho, rho.conj().T, atol=0)
+    assert abs(O.purity(rho) - float(np.sum(O.spectrum(rho) ** 2))) < 1e-13

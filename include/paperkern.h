@@ -283,6 +283,41 @@ int pk_shor_state(int32_t n1, int32_t n2, int64_t xguess, int64_t M, int32_t pre
 int pk_marginal(int32_t nq, int32_t n_low, int32_t prec, const void* psi, double* p, void* stream);
 
 /*
+ * pk_density_matrix -- the ensemble density matrix of Sec. 6.1:
+ *     <n|rho|n'> = sum_a P_a C_a(n) C_a^*(n'),  n, n' < N = 2^nq,
+ * over n_univ universes ("multiverses", Sec. 6.2) of the same size.
+ *   nq       1..16 (rho takes N^2 * 16 bytes: 64 GiB at nq = 16)
+ *   n_univ   >= 1
+ *   states   device complex128, n_univ * N, universe after universe (the packed
+ *            layout of pk_evaluate_batched for equal sizes), 16-byte aligned
+ *   weights  device double[n_univ]: P_a (not normalised by the call)
+ *   rho      device complex128[N * N], row-major rho[n * N + n'], written entirely
+ * FP64 throughout, on the matrix cores.  rho is Hermitian by construction: each
+ * element below the diagonal is computed once and written with its conjugate
+ * above; diagonal elements are real.  PK_EINVAL on range or pointer errors.
+ * Errors are reported through pk_last_error(NULL).
+ */
+int pk_density_matrix(int32_t nq, int32_t n_univ, const void* states, const double* weights, void* rho,
+                      void* stream);
+
+/*
+ * pk_density_spectrum -- eigenvalues of a Hermitian rho (as written by
+ * pk_density_matrix) and two sums over them (Sec. 6.1):
+ *     sums[0] = S = -sum_{lambda > 0} lambda log2 lambda  (entropy in bits; the
+ *               paper leaves the base open; eigenvalues <= 0 from rounding add 0)
+ *     sums[1] = Tr rho^2 = sum lambda^2                   (purity)
+ *   nq           1..15
+ *   rho          device complex128[N * N]; only its lower triangle is read, and it
+ *                is overwritten (used as the solver's workspace)
+ *   eigenvalues  device double[N], ascending
+ *   sums         device double[2]
+ * The eigenvalues come from rocSOLVER (zheevd, no eigenvectors).  The call waits
+ * for the stream to finish (to read the solver's convergence flag).  PK_EDEVICE
+ * when the solver fails or does not converge.
+ */
+int pk_density_spectrum(int32_t nq, void* rho, double* eigenvalues, double* sums, void* stream);
+
+/*
  * pk_time_passes -- measurement helper: runs one evaluation of a single-instance
  * plan pass by pass with HIP events around every kernel on `stream`, waits for
  * it, and writes the duration of each launch in milliseconds to ms[max_n]

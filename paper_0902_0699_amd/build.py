@@ -15,7 +15,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpaperkern.so")
-SOURCES = ["pk_kernels.hip", "pk_shor.hip", "pk_api.cpp", "pk_plan.cpp"]
+SOURCES = ["pk_kernels.hip", "pk_shor.hip", "pk_density.hip", "pk_api.cpp", "pk_plan.cpp"]
+# rocSOLVER (and the rocBLAS handle it runs on) gives the density matrix's eigenvalues
+LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
@@ -59,7 +61,7 @@ def build(verbose=False, jobs=3):
     if failed:
         raise RuntimeError("hipcc failed on %s" % ", ".join(s for s, _ in failed))
     tmp = LIB + ".tmp"
-    link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + LIBS
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.check_call(link)

@@ -1,5 +1,6 @@
 // The C-ABI of libpaperkern: argument checks, device tables, graph capture.
 #include <hip/hip_runtime.h>
+#include <rocsolver/rocsolver.h>
 
 #include <cmath>
 #include <cstdlib>
@@ -570,6 +571,63 @@ int pk_marginal(int32_t nq, int32_t n_low, int32_t prec, const void* psi, double
         return fail(nullptr, PK_EINVAL, "NULL or misaligned pointer");
     hipError_t e = launch_marginal(nq, n_low, prec == PK_FP64, psi, p, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? PK_OK : hip_fail(nullptr, e, "marginal_kernel");
+}
+
+int pk_density_matrix(int32_t nq, int32_t n_univ, const void* states, const double* weights, void* rho,
+                      void* stream) {
+    if (nq < 1 || nq > 16) return fail(nullptr, PK_EINVAL, "nq out of 1..16");
+    if (n_univ < 1) return fail(nullptr, PK_EINVAL, "need at least one universe");
+    if (!states || !weights || !rho || (reinterpret_cast<uintptr_t>(states) & 15) ||
+        (reinterpret_cast<uintptr_t>(rho) & 15) || (reinterpret_cast<uintptr_t>(weights) & 7))
+        return fail(nullptr, PK_EINVAL, "NULL or misaligned pointer");
+    hipError_t e = launch_density(states, weights, rho, (int64_t)1 << nq, n_univ, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? PK_OK : hip_fail(nullptr, e, "density_kernel");
+}
+
+namespace {
+// One rocBLAS handle per thread and device, kept for the process (creating one
+// loads the library's kernels).
+rocblas_handle solver_handle(int dev) {
+    thread_local std::vector<rocblas_handle> handles;
+    if ((int)handles.size() <= dev) handles.resize(dev + 1, nullptr);
+    if (!handles[dev] && rocblas_create_handle(&handles[dev]) != rocblas_status_success) handles[dev] = nullptr;
+    return handles[dev];
+}
+}  // namespace
+
+int pk_density_spectrum(int32_t nq, void* rho, double* eigenvalues, double* sums, void* stream) {
+    if (nq < 1 || nq > 15) return fail(nullptr, PK_EINVAL, "nq out of 1..15");
+    if (!rho || !eigenvalues || !sums || (reinterpret_cast<uintptr_t>(rho) & 15))
+        return fail(nullptr, PK_EINVAL, "NULL or misaligned pointer");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
+    rocblas_handle h = solver_handle(dev);
+    if (!h) return fail(nullptr, PK_EDEVICE, "rocblas_create_handle failed");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (rocblas_set_stream(h, st) != rocblas_status_success) return fail(nullptr, PK_EDEVICE, "rocblas_set_stream");
+    const int64_t n = (int64_t)1 << nq;
+    double* off = nullptr;  // the tridiagonal's off-diagonal, and the convergence flag
+    e = hipMallocAsync(reinterpret_cast<void**>(&off), n * sizeof(double) + 256, st);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipMallocAsync");
+    rocblas_int* info = reinterpret_cast<rocblas_int*>(off + n);
+    // rho is Hermitian and row-major; read as column-major it is conj(rho), whose
+    // eigenvalues are the same.  The lower triangle is read; rho is overwritten.
+    rocblas_status rs = rocsolver_zheevd(h, rocblas_evect_none, rocblas_fill_lower, (rocblas_int)n,
+                                         static_cast<rocblas_double_complex*>(rho), (rocblas_int)n, eigenvalues, off,
+                                         info);
+    rocblas_int hinfo = 0;
+    if (rs == rocblas_status_success) {
+        e = launch_spectrum_sums(eigenvalues, n, sums, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&hinfo, info, sizeof hinfo, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    hipError_t fe = hipFreeAsync(off, st);
+    if (rs != rocblas_status_success) return fail(nullptr, PK_EDEVICE, std::string("rocsolver_zheevd: ") + rocblas_status_to_string(rs));
+    if (e != hipSuccess) return hip_fail(nullptr, e, "spectrum");
+    if (fe != hipSuccess) return hip_fail(nullptr, fe, "hipFreeAsync");
+    if (hinfo != 0) return fail(nullptr, PK_EDEVICE, "rocsolver_zheevd did not converge");
+    return PK_OK;
 }
 
 int pk_time_passes(pk_plan* plan, const void* psi_in, void* psi_out, double* L_out, const double* angles,

@@ -57,6 +57,8 @@ SIGNATURES = {
     "pk_pair_indices": (ctypes.c_int, [_c_int32, _c_int32, _c_int64, _c_int64, _vp, _vp, _vp]),
     "pk_shor_state": (ctypes.c_int, [_c_int32, _c_int32, _c_int64, _c_int64, _c_int32, _vp, _vp]),
     "pk_marginal": (ctypes.c_int, [_c_int32, _c_int32, _c_int32, _vp, _vp, _vp]),
+    "pk_density_matrix": (ctypes.c_int, [_c_int32, _c_int32, _vp, _vp, _vp, _vp]),
+    "pk_density_spectrum": (ctypes.c_int, [_c_int32, _vp, _vp, _vp, _vp]),
     "pk_time_passes": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_c_double),
                                       _c_int32, ctypes.POINTER(_c_int32)]),
     "pk_destroy": (None, [_vp]),
@@ -389,6 +391,42 @@ def marginal(psi, nq, n_low, out=None):
     rc = lib().pk_marginal(nq, n_low, prec, _ptr(psi), _ptr(out), _stream(psi.device))
     _check(rc, None)
     return out
+
+
+def density_matrix(states, weights, out=None):
+    """rho = sum_a P_a C_a C_a^H (pk_density_matrix): ``states`` a contiguous complex128
+    device tensor of shape (A, 2^nq) or the packed 1-D batch, ``weights`` float64 (A,)."""
+    import torch
+    A = int(weights.numel())
+    if states.dtype != torch.complex128 or not states.is_contiguous() or states.numel() % max(A, 1):
+        raise ValueError("states must be contiguous complex128 holding A states of equal size")
+    N = states.numel() // max(A, 1)
+    nq = N.bit_length() - 1
+    if N != 1 << nq:
+        raise ValueError("each state must hold 2^nq amplitudes")
+    _check_f64(weights, A, "weights", states.device)
+    if out is None:
+        out = torch.empty((N, N), dtype=torch.complex128, device=states.device)
+    elif out.dtype != torch.complex128 or out.numel() != N * N or not out.is_contiguous():
+        raise ValueError("out must be a contiguous complex128 tensor of N * N entries")
+    rc = lib().pk_density_matrix(nq, A, _ptr(states), _ptr(weights), _ptr(out), _stream(states.device))
+    _check(rc, None)
+    return out
+
+
+def density_spectrum(rho):
+    """Eigenvalues (ascending), entropy in bits and Tr rho^2 of a Hermitian rho
+    (pk_density_spectrum).  rho is overwritten."""
+    import torch
+    N = rho.shape[0]
+    nq = N.bit_length() - 1
+    if rho.dtype != torch.complex128 or rho.numel() != N * N or N != 1 << nq or not rho.is_contiguous():
+        raise ValueError("rho must be a contiguous complex128 N x N tensor, N = 2^nq")
+    lam = torch.empty(N, dtype=torch.float64, device=rho.device)
+    sums = torch.empty(2, dtype=torch.float64, device=rho.device)
+    rc = lib().pk_density_spectrum(nq, _ptr(rho), _ptr(lam), _ptr(sums), _stream(rho.device))
+    _check(rc, None)
+    return lam, sums[0], sums[1]
 
 
 def _autograd_function():

@@ -11,8 +11,10 @@ FP32 variant's speedup at its stated tolerance, and the CPU oracle's rate.
     python bench.py [--steps K] [--warmup W] [--extra]
 
 --extra adds the 4096-instance batched form, the n_q = 30 gradient check, a
-two-qubit (TwoOpA) brickwork circuit at n_q = 30 and Shor's data path at n_q = 30
-(load, QFT of register one, marginal; M = 899).
+two-qubit (TwoOpA) brickwork circuit at n_q = 30, Shor's data path at n_q = 30
+(load, QFT of register one, marginal; M = 899), the ensemble density matrix of
+4096 noisy Grover universes at n_q = 12 with its spectrum, and the full Grover
+search (n_t iterations) at n_q = 20 and 24.
 """
 
 import argparse
@@ -339,6 +341,80 @@ def shor_run(torch, pk, W, steps, prec):
     return out
 
 
+def density_run(torch, pk, W, steps):
+    """The ensemble density matrix (Sec. 6.1) of 4096 noisy Grover universes at
+    n_q = 12, equal weights: the FP64 matrix-core kernel timed with HIP events on
+    the current stream, then the spectrum (rocSOLVER) once."""
+    nq, A = W.DENSITY_NQ, W.DENSITY_UNIVERSES
+    N = 1 << nq
+    gates, x = W.density_universes(W.SEEDS["density"], nq, A)
+    plan = pk.Plan([{"nq": nq, "gates": g, "marked": [x]} for g in gates])
+    s = torch.full((A * N,), 2.0 ** (-nq / 2), dtype=torch.complex128, device="cuda")
+    C, _, _ = pk.evaluate_batched(plan, s)
+    P = torch.full((A,), 1.0 / A, dtype=torch.float64, device="cuda")
+    rho = torch.empty((N, N), dtype=torch.complex128, device="cuda")
+    pk.density_matrix(C, P, out=rho)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        pk.density_matrix(C, P, out=rho)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    trace = float(torch.diagonal(rho).real.sum().item())
+    t0 = time.time()
+    lam, S, pur = pk.density_spectrum(rho)
+    spec_s = time.time() - t0
+    useful = 8.0 * A * N * (N + 1) / 2  # real flops of the lower triangle with the diagonal
+    out = {"workload": "density matrix of %d noisy Grover universes, n_q=%d, FP64, equal weights" % (A, nq),
+           "ms": ms, "achieved_TFLOPs": useful / (ms * 1e-3) / 1e12, "peak_TFLOPs": 78.6,
+           "frac": useful / (ms * 1e-3) / 1e12 / 78.6, "trace_minus_1": trace - 1.0,
+           "spectrum_s": spec_s, "entropy_bits": float(S), "purity": float(pur)}
+    log("density: %.2f ms (%.1f TFLOP/s), spectrum %.2f s, S = %.4f bits, Tr rho^2 = %.4f"
+        % (ms, out["achieved_TFLOPs"], spec_s, float(S), float(pur)))
+    return out
+
+
+def search_run(torch, pk, W, reps):
+    """The full Grover search of Sec. 5.1: n_t = floor((pi/4) sqrt(N)) noise-free
+    iterations from the uniform state in one replayed graph (pk_evaluate_repeat),
+    at n_q = 20 and 24, FP64; L is the success probability after n_t iterations."""
+    out = {}
+    for nq in (20, 24):
+        nt = pk.grover_iterations(nq)
+        x = int(np.random.default_rng(W.SEEDS["small_fp64"]).integers(0, 1 << nq))
+        plan = pk.Plan({"nq": nq, "gates": W.grover_gates(), "marked": [x]})
+        s = torch.full((1 << nq,), 2.0 ** (-nq / 2), dtype=torch.complex128, device="cuda")
+        y = torch.empty_like(s)
+        L = torch.empty(1, dtype=torch.float64, device="cuda")
+        ws = plan.workspace(pk.PK_OP_EVAL, s.device)
+        st = pk._stream(s.device)
+
+        def run():
+            rc = pk.lib().pk_evaluate_repeat(plan.handle, nt, pk._ptr(s), pk._ptr(y), pk._ptr(L), None, None,
+                                             pk._ptr(ws), st)
+            pk._check(rc, plan.handle)
+
+        run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        theta = math.asin(2.0 ** (-nq / 2))
+        passes = plan.passes() * nt
+        out["nq%d" % nq] = {"iterations": nt, "passes": passes, "ms": ms, "iterations_per_s": nt / (ms * 1e-3),
+                            "mean_pass_GBs": 32.0 * (1 << nq) * passes / (ms * 1e-3) / 1e9,
+                            "L": float(L.item()), "L_closed_form": math.sin((2 * nt + 1) * theta) ** 2}
+        log("search n_q=%d: %d iterations, %d passes, %.2f ms, L = %.12f" % (nq, nt, passes, ms, L.item()))
+        del s, y
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -429,6 +505,10 @@ def main():
         line["two_qubit"] = two_qubit_run(torch, pk, nq, max(3, args.steps // 4))
         torch.cuda.empty_cache()
         line["shor"] = {p: shor_run(torch, pk, W, max(3, args.steps // 4), p) for p in ("fp64", "fp32")}
+        torch.cuda.empty_cache()
+        line["density"] = density_run(torch, pk, W, max(3, args.steps // 4))
+        torch.cuda.empty_cache()
+        line["search"] = search_run(torch, pk, W, 3)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(W, nq, 2 * nq + 2)

@@ -216,6 +216,19 @@ int pk_evaluate(pk_plan* plan, const void* psi_in, void* psi_out, double* L_out,
                 const double* angles, void* workspace, void* stream);
 
 /*
+ * pk_evaluate_repeat -- apply the gate list of a single-instance plan `reps`
+ * times in a row: psi_out = U^reps psi_in.  With the list of one Grover
+ * iteration G = HALL . Inv . HALL . Oracle this is the whole search of Sec. 5.1,
+ * G^{n_t} with n_t = floor((pi/4) sqrt(2^nq)) iterations.  The whole sequence of
+ * passes (about 2 to 5 per iteration) is captured into one hipGraph, keyed by the
+ * pointers and reps, and replayed.  L_out and norm_out refer to the final state.
+ *   reps  1..2^24, with at most 2^20 pass launches in total
+ * Other arguments and errors as pk_evaluate.
+ */
+int pk_evaluate_repeat(pk_plan* plan, int64_t reps, const void* psi_in, void* psi_out, double* L_out,
+                       double* norm_out, const double* angles, void* workspace, void* stream);
+
+/*
  * pk_evaluate_batched -- evaluate every instance of the plan ("multiverses",
  * Sec. 6.2) in one persistent launch replayed from a hipGraph.  States are
  * packed at pk_plan_offsets(); L_out and norm_out (or NULL) hold n_inst doubles.

@@ -19,11 +19,11 @@ namespace {
 
 thread_local std::string g_error;
 
-enum GraphSlot { G_EVAL = 0, G_BATCH = 1, G_BWD = 2, G_SLOTS = 3 };
+enum GraphSlot { G_EVAL = 0, G_BATCH = 1, G_BWD = 2, G_REPEAT = 3, G_SLOTS = 4 };
 
 struct DevPlan {
     Plan host;
-    void* exec[G_SLOTS] = {nullptr, nullptr, nullptr};
+    void* exec[G_SLOTS] = {nullptr, nullptr, nullptr, nullptr};
     const void* key[G_SLOTS][8] = {};
     hipStream_t cap = nullptr;
     int n_cu = 0;
@@ -198,26 +198,32 @@ hipError_t enqueue_prep(DevPlan* d, void* ws, const double* angles, int op, int 
 }
 
 // Evaluation of a single-instance plan: prep, every forward pass, final combine.
-hipError_t enqueue_eval(DevPlan* d, const EvalArgs& a, hipStream_t st, std::vector<hipEvent_t>* ev) {
+// One evaluation, or `reps` applications of the gate list in a row: the first
+// reads psi_in, every later one works on psi_out in place; the matrices are
+// built once, and the norm partials are written by the last application only.
+hipError_t enqueue_eval(DevPlan* d, const EvalArgs& a, hipStream_t st, std::vector<hipEvent_t>* ev,
+                        int64_t reps = 1) {
     Plan& P = d->host;
     hipError_t e = enqueue_prep(d, a.ws, a.angles, PK_OP_EVAL, 0, st);
     if (e != hipSuccess) return e;
     PassLaunch L = base_launch(d, a.ws, PK_OP_EVAL);
-    L.src0 = a.psi_in;
     L.dst0 = a.psi_out;
-    L.want_norm = a.norm_out != nullptr;
     L.nv = 1;
     const Instance& in = P.inst[0];
-    for (size_t p = 0; p < in.fwd.size(); ++p) {
-        L.pass = (int)p;
-        L.kmax = in.fwd[p].kmax;
-        L.ntiles = in.fwd[p].ntiles;
-        L.grid_cap = P.tiling.wgs_per_cu;
-        L.rbits = in.fwd[p].rbits;
-        if (ev) hipEventRecord((*ev)[2 * p], st);
-        e = launch_pass(L, st);
-        if (ev) hipEventRecord((*ev)[2 * p + 1], st);
-        if (e != hipSuccess) return e;
+    for (int64_t r = 0; r < reps; ++r) {
+        L.src0 = r == 0 ? a.psi_in : a.psi_out;
+        L.want_norm = a.norm_out != nullptr && r == reps - 1;
+        for (size_t p = 0; p < in.fwd.size(); ++p) {
+            L.pass = (int)p;
+            L.kmax = in.fwd[p].kmax;
+            L.ntiles = in.fwd[p].ntiles;
+            L.grid_cap = P.tiling.wgs_per_cu;
+            L.rbits = in.fwd[p].rbits;
+            if (ev) hipEventRecord((*ev)[2 * p], st);
+            e = launch_pass(L, st);
+            if (ev) hipEventRecord((*ev)[2 * p + 1], st);
+            if (e != hipSuccess) return e;
+        }
     }
     TableLayout t = table_layout(&P);
     return launch_reduce(at<Reduction>(P.d_tables, t.red), 2 * (int)P.inst.size(), static_cast<double*>(a.ws),
@@ -501,6 +507,25 @@ int pk_evaluate(pk_plan* plan, const void* psi_in, void* psi_out, double* L_out,
     const void* const key[8] = {psi_in, psi_out, L_out, norm_out, angles, workspace, nullptr, nullptr};
     return run_graphed(d, G_EVAL, key, static_cast<hipStream_t>(stream),
                        [&](hipStream_t s) { return enqueue_eval(d, a, s, nullptr); });
+}
+
+int pk_evaluate_repeat(pk_plan* plan, int64_t reps, const void* psi_in, void* psi_out, double* L_out,
+                       double* norm_out, const double* angles, void* workspace, void* stream) {
+    if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");
+    DevPlan* d = dp(plan);
+    if (d->host.inst.size() != 1) return fail(d, PK_EINVAL, "pk_evaluate_repeat needs a single-instance plan");
+    if (reps < 1 || reps > ((int64_t)1 << 24)) return fail(d, PK_EINVAL, "reps out of 1..2^24");
+    if ((int64_t)d->host.inst[0].fwd.size() * reps > ((int64_t)1 << 20))
+        return fail(d, PK_EINVAL, "more than 2^20 pass launches in one graph");
+    int rc = check_eval_args(d, psi_in, psi_out, L_out, norm_out, angles, workspace);
+    if (rc != PK_OK) return rc;
+    rc = ensure_device(d);
+    if (rc != PK_OK) return rc;
+    EvalArgs a{psi_in, psi_out, L_out, norm_out, angles, workspace};
+    const void* const key[8] = {psi_in, psi_out, L_out, norm_out, angles, workspace,
+                                reinterpret_cast<const void*>((intptr_t)reps), nullptr};
+    return run_graphed(d, G_REPEAT, key, static_cast<hipStream_t>(stream),
+                       [&](hipStream_t s) { return enqueue_eval(d, a, s, nullptr, reps); });
 }
 
 int pk_evaluate_batched(pk_plan* plan, const void* psi_in, void* psi_out, double* L_out, double* norm_out,

@@ -58,26 +58,39 @@ __global__ void __launch_bounds__(kThreads) density_kernel(const double2* C, con
             im[x][y] = v4d{0, 0, 0, 0};
         }
 
-    for (int k0 = 0; k0 < A; k0 += kKC) {
-        // stage 16 universes: thread t covers label column t % 64 of 4 universes, both sides
+    // The next stage's universes are fetched into registers before this stage's
+    // MFMAs, so their HBM/L2 latency overlaps the matrix work; they go to LDS after.
+    constexpr int kQ = kKC * kBM / kThreads;  // loads per thread per stage and side
+    double2 pr[kQ], pc[kQ];
+    double pw[kQ];
+    const int c = t & 63;
+    auto fetch = [&](int k0) {
 #pragma unroll
-        for (int q = 0; q < kKC * kBM / kThreads; ++q) {
-            const int kk = (t >> 6) + 4 * q, c = t & 63;
-            const int a = k0 + kk;
-            double2 vr = {0.0, 0.0}, vc = {0.0, 0.0};
-            double w = 0.0;
+        for (int q = 0; q < kQ; ++q) {
+            const int a = k0 + (t >> 6) + 4 * q;
+            pr[q] = double2{0.0, 0.0};
+            pc[q] = double2{0.0, 0.0};
+            pw[q] = 0.0;
             if (a < A) {
                 const double2* row = C + (int64_t)a * N;
-                if (I0 + c < N) vr = row[I0 + c];
-                if (J0 + c < N) vc = row[J0 + c];
-                w = P[a];
+                if (I0 + c < N) pr[q] = row[I0 + c];
+                if (J0 + c < N) pc[q] = row[J0 + c];
+                pw[q] = P[a];
             }
-            sAx[kk][c] = w * vr.x;
-            sAy[kk][c] = w * vr.y;
-            sBx[kk][c] = vc.x;
-            sBy[kk][c] = vc.y;
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < A; k0 += kKC) {
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            const int kk = (t >> 6) + 4 * q;
+            sAx[kk][c] = pw[q] * pr[q].x;
+            sAy[kk][c] = pw[q] * pr[q].y;
+            sBx[kk][c] = pc[q].x;
+            sBy[kk][c] = pc[q].y;
         }
         __syncthreads();
+        if (k0 + kKC < A) fetch(k0 + kKC);
 #pragma unroll
         for (int k4 = 0; k4 < kKC; k4 += 4) {
             double ax[2], ay[2], bx[2], by[2];

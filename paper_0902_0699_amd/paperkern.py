@@ -12,6 +12,7 @@ Gate tuples (applied left to right):
 
 import ctypes
 import json
+import math
 import os
 
 import numpy as np
@@ -53,6 +54,7 @@ SIGNATURES = {
     "pk_workspace_bytes": (ctypes.c_int, [_vp, _c_int32, ctypes.POINTER(_c_int64)]),
     "pk_evaluate": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pk_evaluate_batched": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "pk_evaluate_repeat": (ctypes.c_int, [_vp, _c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pk_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pk_pair_indices": (ctypes.c_int, [_c_int32, _c_int32, _c_int64, _c_int64, _vp, _vp, _vp]),
     "pk_shor_state": (ctypes.c_int, [_c_int32, _c_int32, _c_int64, _c_int64, _c_int32, _vp, _vp]),
@@ -289,6 +291,29 @@ def evaluate(plan, psi_in, angles=None, want_norm=True, out=None):
     norm = torch.empty(1, dtype=torch.float64, device=dev) if want_norm else None
     evaluate_into(plan, psi_in, psi_out, L, norm, angles)
     return psi_out, L, norm
+
+
+def evaluate_repeat(plan, psi_in, reps, angles=None, want_norm=True, out=None):
+    """U^reps psi_in for a single-instance plan (pk_evaluate_repeat): (psi_out, L, norm)."""
+    import torch
+    dev = psi_in.device
+    psi_out = torch.empty_like(psi_in) if out is None else out
+    nelem = plan.offsets()[-1]
+    _check_state(plan, psi_in, nelem, "psi_in")
+    _check_state(plan, psi_out, nelem, "psi_out")
+    _check_f64(angles, 3 * plan.n_angles(), "angles", dev)
+    L = torch.empty(1, dtype=torch.float64, device=dev)
+    norm = torch.empty(1, dtype=torch.float64, device=dev) if want_norm else None
+    ws = plan.workspace(PK_OP_EVAL, dev)
+    rc = lib().pk_evaluate_repeat(plan.handle, int(reps), _ptr(psi_in), _ptr(psi_out), _ptr(L), _ptr(norm),
+                                  _ptr(angles), _ptr(ws), _stream(dev))
+    _check(rc, plan.handle)
+    return psi_out, L, norm
+
+
+def grover_iterations(nq):
+    """n_t = floor((pi/4) sqrt(2^nq)), the iteration count of Sec. 5.1 (reading: floor)."""
+    return int(math.floor(math.pi / 4.0 * math.sqrt(float(1 << nq))))
 
 
 def evaluate_batched(plan, psi_in, angles=None, want_norm=True, out=None):

@@ -36,7 +36,12 @@ BATCH_INSTANCES = 4096
 BATCH_NQ_MIN = 10
 BATCH_NQ_SPAN = 10
 
-SEEDS = {"small_fp64": 0, "large_fp64": 1, "large_fp32": 2, "batched": 3, "gradient": 4, "shor": 6}
+SEEDS = {"small_fp64": 0, "large_fp64": 1, "large_fp32": 2, "batched": 3, "gradient": 4, "shor": 6, "density": 7}
+
+# The ensemble density matrix (Sec. 6.1): universes of the paper's largest
+# tabulated size (Sec. 7.1) in the batch's count.
+DENSITY_NQ = 12
+DENSITY_UNIVERSES = 4096
 
 # Shor's data path at n_q = 30: M = 899 = 29 * 31 gives registers of n1 = 20 and
 # n2 = 10 qubits (Step 1), the largest FP64 state of one GPU's share.
@@ -146,3 +151,20 @@ def shor_xguess(seed, M=SHOR_M):
         x = int(rng.integers(2, M))
         if math.gcd(x, M) == 1:
             return x
+
+
+def density_universes(seed, nq=DENSITY_NQ, count=DENSITY_UNIVERSES):
+    """Noisy multiverses of one Grover search (Sec. 6.2, 6.3): one marked item x
+    shared by all universes, each universe one noisy iteration from the uniform
+    state (the same noise draws as ``draw_instance``), universe 0 noise-free.
+    Returns (gate lists, x); the caller starts every universe from HALL|0..0>."""
+    rng = np.random.default_rng(seed)
+    x = int(rng.integers(0, 1 << nq))
+    gates = []
+    for a in range(count):
+        qhit = int(rng.integers(1, nq + 1))
+        eloc = int(rng.integers(0, 5))
+        alpha = float(rng.uniform(0.0, 2.0 * math.pi))
+        beta = float(rng.uniform(0.0, math.pi))
+        gates.append(grover_gates(None if a == 0 else (qhit, eloc, alpha, beta, 0.0)))
+    return gates, x

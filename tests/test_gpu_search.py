@@ -1,0 +1,90 @@
+"""GPU parity of the full Grover search (Sec. 5.1): G^{n_t} from HALL|0..0> with
+n_t = floor((pi/4) sqrt(N)) through pk_evaluate_repeat (one graph of every pass).
+
+  * noise-free, against the rotation closed form of the oracle (exact at any
+    n_q): C_x = sin((2 n_t + 1) theta), the rest cos((2 n_t + 1) theta)/sqrt(N - 1);
+    normwise error <= tol x max(1, n_t / 10) with the one-iteration tolerance tol
+    (1e-12 FP64, 1e-5 FP32), since the rounding of n_t iterations adds up;
+  * a noisy iteration repeated, against the gate-by-gate oracle;
+  * several marked items; reps = 1 equals pk_evaluate; a second replay of the graph.
+Each test prints its case before touching the GPU.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_0902_0699_amd import workload as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _pk():
+    from paper_0902_0699_amd import paperkern as pk
+    return pk
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _uniform(nq, dt=torch.complex128):
+    return torch.full((1 << nq,), 2.0 ** (-nq / 2), dtype=dt, device="cuda")
+
+
+@pytest.mark.parametrize("nq,prec", [(4, "fp64"), (10, "fp64"), (13, "fp64"), (16, "fp64"), (20, "fp64"),
+                                     (12, "fp32"), (18, "fp32")])
+def test_search_against_closed_form(nq, prec):
+    pk = _pk()
+    nt = pk.grover_iterations(nq)
+    x = int(np.random.default_rng(nq).integers(0, 1 << nq))
+    plan = pk.Plan({"nq": nq, "gates": W.grover_gates(), "marked": [x]}, prec=prec)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    _say("search n_q=%d n_t=%d %s" % (nq, nt, prec))
+    for _ in range(2):  # capture, then a replay of the same graph
+        out, L, norm = pk.evaluate_repeat(plan, _uniform(nq, dt), nt)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().astype(np.complex128)
+        want = O.grover_closed_form(nq, nt, x)
+        err = float(np.linalg.norm(got - want))
+        tol = (1e-12 if prec == "fp64" else 1e-5) * max(1.0, nt / 10.0)
+        _say("  normwise err %.3e  L %.12f (closed form %.12f)" % (err, L.item(), abs(want[x]) ** 2))
+        assert err <= tol
+        assert abs(L.item() - abs(want[x]) ** 2) <= tol and abs(norm.item() - 1.0) <= tol
+    assert abs(want[x]) ** 2 > 0.9  # the search succeeds (Sec. 5.1)
+
+
+def test_noisy_iteration_repeated_against_gate_by_gate_oracle():
+    pk = _pk()
+    nq, reps = 9, 7
+    rng = np.random.default_rng(5)
+    gates = W.grover_gates((3, 2, 1.2, 0.7, 0.0)) + [("D4", 1, 5, 0.3, 0.2, -0.1)]
+    marked = [17, 300]
+    psi = rng.standard_normal(1 << nq) + 1j * rng.standard_normal(1 << nq)
+    psi /= np.linalg.norm(psi)
+    plan = pk.Plan({"nq": nq, "gates": gates, "marked": marked})
+    _say("noisy iteration x%d, n_q=%d" % (reps, nq))
+    out, L, _ = pk.evaluate_repeat(plan, torch.from_numpy(psi).to("cuda"), reps)
+    want = psi
+    for _ in range(reps):
+        want, Lw, _ = O.evaluate(nq, gates, marked, want)
+    got = out.cpu().numpy()
+    assert np.linalg.norm(got - want) <= 1e-12 * reps and abs(L.item() - Lw) <= 1e-12 * reps
+
+
+def test_repeat_once_equals_evaluate_and_rejects_bad_reps():
+    pk = _pk()
+    nq = 11
+    plan = pk.Plan({"nq": nq, "gates": W.grover_gates((2, 4, 0.4, 0.5, 0.0)), "marked": [9]})
+    x = _uniform(nq)
+    _say("repeat once, n_q=%d" % nq)
+    a, La, _ = pk.evaluate_repeat(plan, x, 1)
+    b, Lb, _ = pk.evaluate(plan, x)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and La.item() == Lb.item()
+    with pytest.raises(pk.PaperkernError):
+        pk.evaluate_repeat(plan, x, 0)

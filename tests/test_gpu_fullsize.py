@@ -171,3 +171,40 @@ def test_shor_path_full_size(prec):
     _say("  passes %d  max |dp|/max p %.3e  max |dC|/max |C| %.3e  sum p - 1 = %.3e"
          % (plan.passes(), ep, ea, p.sum() - 1.0))
     assert ep <= tol and ea <= tol and abs(p.sum() - 1.0) <= tol
+
+
+@pytest.mark.timeout(900)
+def test_density_matrix_full_size():
+    """The ensemble density matrix (Sec. 6.1) in the configuration bench.py times:
+    4096 noisy Grover universes at n_q = 12 from the library's batched launch,
+    equal weights.  Every element of rho against the oracle's sum over the same
+    states, Tr rho = 1, Tr rho^2 against the Gram route, and the spectrum, entropy
+    and purity against LAPACK."""
+    from paper_0902_0699_amd import paperkern as pk
+
+    nq, A = W.DENSITY_NQ, W.DENSITY_UNIVERSES
+    N = 1 << nq
+    _say("full size density matrix: %d universes, n_q=%d" % (A, nq))
+    gates, x = W.density_universes(W.SEEDS["density"], nq, A)
+    plan = pk.Plan([{"nq": nq, "gates": g, "marked": [x]} for g in gates])
+    s = torch.full((A * N,), 2.0 ** (-nq / 2), dtype=torch.complex128, device="cuda")
+    C, _, _ = pk.evaluate_batched(plan, s)
+    P = np.full(A, 1.0 / A)
+    rho = pk.density_matrix(C, torch.from_numpy(P).to("cuda"))
+    got = rho.cpu().numpy()
+    lam, S, pur = pk.density_spectrum(rho)
+    lam = lam.cpu().numpy()
+    Ch = C.cpu().numpy().reshape(A, N)
+    del C, s, rho
+    torch.cuda.empty_cache()
+    want = O.density_matrix(Ch, P)
+    err = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+    wl = O.spectrum(want)
+    _say("  max |drho| / max |rho| %.3e  Tr rho - 1 %.3e  max |dlambda| %.3e  S %.6f bits (LAPACK %.6f)"
+         % (err, np.trace(got).real - 1.0, np.max(np.abs(lam - wl)), float(S), O.entropy_bits(wl)))
+    assert err <= 1e-12
+    np.testing.assert_array_equal(got, got.conj().T)
+    assert abs(np.trace(got).real - 1.0) <= 1e-12
+    assert abs(O.purity(got) - O.purity_gram(Ch, P)) <= 1e-12
+    assert np.max(np.abs(lam - wl)) <= 1e-12
+    assert abs(float(S) - O.entropy_bits(wl)) <= 1e-9 and abs(float(pur) - O.purity(want)) <= 1e-12

@@ -75,7 +75,15 @@ struct Op {
 // tile through LDS (`exchange`), the others keep the layout.  Straight-line
 // steps instead of an op loop let the compiler update the register tile in
 // place.
+// Steps present in a sub-stage (Stage::steps): the kernel reads this one word
+// and loads the parameters of the present steps only.
+enum StepBits : int32_t {
+    ST_EXCHANGE = 1, ST_SEED = 2, ST_FLIP_PRE = 4, ST_PHASE = 8, ST_MAT_PRE = 16, ST_H1 = 32, ST_FLIP_MID = 64,
+    ST_H2 = 128, ST_MAT_POST = 256, ST_MAT4 = 512, ST_D2B = 1024, ST_D4B = 2048, ST_SCALE = 4096, ST_READ = 8192,
+};
+
 struct Stage {
+    int32_t steps;            // StepBits of the steps below that are present
     int32_t rb[kMaxRegBits];  // local tile bit held by register bit a (-1 when unused)
     int32_t rbs[kMaxRegBits]; // the same bits sorted ascending (-1 entries last)
     int32_t exchange;         // 1: move the tile into this layout through LDS first
@@ -102,7 +110,6 @@ struct Stage {
     float d4b_gscale;
     int32_t scale;            // 1: multiply by the pass scale
     int32_t read;             // flip index of a READ or -1
-    int32_t pad;
 };
 
 // One amplitude addressed by (tile, local label) in a given pass.

@@ -551,7 +551,9 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
     const PK_CONST Stage* S = cptr(a.stages) + P->stage_begin;
     Layout L = C.L0;
     for (int s = 0; s < C.nstages; ++s, ++S) {
-        if (s > 0 && S->exchange) {
+        // one scalar word says which steps follow; only their parameters are loaded
+        const int steps = S->steps;
+        if (s > 0 && (steps & ST_EXCHANGE)) {
             // ---- LDS exchange: previous layout out, this layout in
             const Layout Ln = (s == C.nstages - 1) ? C.Ll : make_layout<(int)sizeof(R) * 2>(S, C.nrb, tid);
 #pragma unroll
@@ -573,30 +575,30 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
         }
         // ---- the sub-stage's steps, in their fixed order
         if constexpr (NV == 2) {
-            if (S->seed >= 0) element_op<NV, NR, 2>(a, v, L, S->seed, tile, nreg, active);
+            if (steps & ST_SEED) element_op<NV, NR, 2>(a, v, L, S->seed, tile, nreg, active);
         }
-        if (S->flip_pre >= 0) element_op<NV, NR, 0>(a, v, L, S->flip_pre, tile, nreg, active);
-        if (S->phase_count > 0 && active) apply_phases<NV, NR>(a, S, v, L, tile);
-        if (S->mat_pre_a >= 0) {
+        if (steps & ST_FLIP_PRE) element_op<NV, NR, 0>(a, v, L, S->flip_pre, tile, nreg, active);
+        if ((steps & ST_PHASE) && active) apply_phases<NV, NR>(a, S, v, L, tile);
+        if (steps & ST_MAT_PRE) {
             R m[8];
             const PK_CONST double* mp = cptr(a.mats) + 8 * S->mat_pre;
 #pragma unroll
             for (int e = 0; e < 8; ++e) m[e] = (R)mp[e];
             apply_mat<NV, NR>(v, S->mat_pre_a, m);
         }
-        apply_hmask<NV, NR>(v, S->hmask1);
-        if (S->flip_mid >= 0) element_op<NV, NR, 0>(a, v, L, S->flip_mid, tile, nreg, active);
-        apply_hmask<NV, NR>(v, S->hmask2);
-        if (S->mat_post_a >= 0) {
+        if (steps & ST_H1) apply_hmask<NV, NR>(v, S->hmask1);
+        if (steps & ST_FLIP_MID) element_op<NV, NR, 0>(a, v, L, S->flip_mid, tile, nreg, active);
+        if (steps & ST_H2) apply_hmask<NV, NR>(v, S->hmask2);
+        if (steps & ST_MAT_POST) {
             R m[8];
             const PK_CONST double* mp = cptr(a.mats) + 8 * S->mat_post;
 #pragma unroll
             for (int e = 0; e < 8; ++e) m[e] = (R)mp[e];
             apply_mat<NV, NR>(v, S->mat_post_a, m);
         }
-        if (S->mat4 >= 0 && active) op_mat4<NV, NR>(v, cptr(a.mats4) + 32 * S->mat4);
+        if ((steps & ST_MAT4) && active) op_mat4<NV, NR>(v, cptr(a.mats4) + 32 * S->mat4);
         if constexpr (NV == 2) {
-            if (S->d2b_a >= 0) {
+            if (steps & ST_D2B) {
                 R mh[8];
                 const PK_CONST double* mp = cptr(a.mats) + 8 * S->d2b_mat;
 #pragma unroll
@@ -611,7 +613,7 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
                     if (tid == 0) a.gpart[gslot + t * P->ntiles + tile] = scale * tot;
                 }
             }
-            if (S->d4b_mat >= 0) {
+            if (steps & ST_D4B) {
                 double g[3] = {0.0, 0.0, 0.0};
                 if (active) op_d4bwd<NV, NR>(v, cptr(a.mats4) + 32 * S->d4b_mat, g);
                 const double scale = 2.0 * (double)S->d4b_gscale;
@@ -623,7 +625,7 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
                 }
             }
         }
-        if (S->scale) {
+        if (steps & ST_SCALE) {
             const R sc = (R)P->scale;
 #pragma unroll
             for (int n = 0; n < NV; ++n)
@@ -633,7 +635,7 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
                     v[n][i].y *= sc;
                 }
         }
-        if (S->read >= 0) element_op<NV, NR, 1>(a, v, L, S->read, tile, nreg, active);
+        if (steps & ST_READ) element_op<NV, NR, 1>(a, v, L, S->read, tile, nreg, active);
     }
 
     // ---- norm partial of the final state (FP64 for FP64 data; Neumaier-

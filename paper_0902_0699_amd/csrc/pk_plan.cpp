@@ -191,12 +191,19 @@ Stage blank_sub(const HostStage& hs, int exchange) {
     return s;
 }
 
-// Stores a finished sub-stage's phases grouped by slot (stable) and counts them.
-void group_phases(Stage& s, std::vector<PhaseOp>* table) {
-    if (s.phase_count == 0) return;
-    auto b = table->begin() + s.phase_first, e = b + s.phase_count;
-    std::stable_sort(b, e, [](const PhaseOp& x, const PhaseOp& y) { return x.slot < y.slot; });
-    for (auto it = b; it != e; ++it) ++s.phase_cnt[it->slot];
+// Finishes a sub-stage: its phases stored grouped by slot (stable) and counted,
+// and the mask of the steps it holds.
+void finish_sub(Stage& s, std::vector<PhaseOp>* table) {
+    if (s.phase_count > 0) {
+        auto b = table->begin() + s.phase_first, e = b + s.phase_count;
+        std::stable_sort(b, e, [](const PhaseOp& x, const PhaseOp& y) { return x.slot < y.slot; });
+        for (auto it = b; it != e; ++it) ++s.phase_cnt[it->slot];
+    }
+    s.steps = (s.exchange ? ST_EXCHANGE : 0) | (s.seed >= 0 ? ST_SEED : 0) | (s.flip_pre >= 0 ? ST_FLIP_PRE : 0) |
+              (s.phase_count > 0 ? ST_PHASE : 0) | (s.mat_pre_a >= 0 ? ST_MAT_PRE : 0) | (s.hmask1 ? ST_H1 : 0) |
+              (s.flip_mid >= 0 ? ST_FLIP_MID : 0) | (s.hmask2 ? ST_H2 : 0) | (s.mat_post_a >= 0 ? ST_MAT_POST : 0) |
+              (s.mat4 >= 0 ? ST_MAT4 : 0) | (s.d2b_a >= 0 ? ST_D2B : 0) | (s.d4b_mat >= 0 ? ST_D4B : 0) |
+              (s.scale ? ST_SCALE : 0) | (s.read >= 0 ? ST_READ : 0);
 }
 
 // A phase joins the accumulator slot of its register bits (the register bits of
@@ -284,7 +291,7 @@ std::vector<Stage> pack_stage(const HostStage& hs, const std::vector<HostPhase>&
     for (const Op& o : hs.ops) {
         int slot = put(o);
         if (slot < 0) {
-            group_phases(cur, table);
+            finish_sub(cur, table);
             subs.push_back(cur);
             cur = blank_sub(hs, 0);
             cursor = 0;
@@ -292,7 +299,7 @@ std::vector<Stage> pack_stage(const HostStage& hs, const std::vector<HostPhase>&
         }
         cursor = slot;
     }
-    group_phases(cur, table);
+    finish_sub(cur, table);
     subs.push_back(cur);
     return subs;
 }
@@ -1369,7 +1376,7 @@ std::string describe(const Plan* plan) {
                     const Stage& u = hp.subs[q];
                     if (q) s += ",";
                     std::snprintf(buf, sizeof buf, "%.17g", (double)u.d2b_gscale);
-                    s += "{\"rb\":[";
+                    s += "{\"steps\":" + std::to_string(u.steps) + ",\"rb\":[";
                     for (int a = 0; a < kMaxRegBits; ++a) s += (a ? "," : "") + std::to_string(u.rb[a]);
                     s += "],\"exchange\":" + std::to_string(u.exchange) + ",\"seed\":" + std::to_string(u.seed) +
                          ",\"flip_pre\":" + std::to_string(u.flip_pre) + ",\"phase_first\":" +

@@ -170,6 +170,18 @@ def _run_phases(desc, nq, tb, u, vecs):
             v[hit] *= complex(c, s)
 
 
+_STEP_BITS = [("exchange", lambda v: v == 1), ("seed", lambda v: v >= 0), ("flip_pre", lambda v: v >= 0),
+              ("phase_count", lambda v: v > 0), ("mat_pre_a", lambda v: v >= 0), ("hmask1", lambda v: v != 0),
+              ("flip_mid", lambda v: v >= 0), ("hmask2", lambda v: v != 0), ("mat_post_a", lambda v: v >= 0),
+              ("mat4", lambda v: v >= 0), ("d2b_a", lambda v: v >= 0), ("d4b_mat", lambda v: v >= 0),
+              ("scale", lambda v: v != 0), ("read", lambda v: v >= 0)]
+
+
+def _steps_of(u):
+    """The step mask the kernel branches on, recomputed from the sub-stage's fields."""
+    return sum(1 << i for i, (name, present) in enumerate(_STEP_BITS) if present(u[name]))
+
+
 def _flip_index(desc, nq, tb, f):
     tile, j, slot = desc["flips"][f]
     return _global_index(nq, tb, tile, j), slot
@@ -189,6 +201,7 @@ def _run_subs(problems, desc, inst, direction, psi, lam=None, dL=1.0):
         assert p["subs"] and p["subs"][0]["exchange"] == 1
         for u in p["subs"]:
             rb = u["rb"]
+            assert u["steps"] == _steps_of(u)
             if u["seed"] >= 0:
                 g, _ = _flip_index(desc, nq, tb, u["seed"])
                 vecs[1][g] = dL * vecs[0][g]

@@ -424,6 +424,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--extra", action="store_true", help="also time the batched form and the gradient check")
+    ap.add_argument("--legs", default="batched,gradient,two_qubit,shor,density,search",
+                    help="with --extra: comma-separated extra legs to run (default: all)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -498,18 +500,18 @@ def main():
         del r32, x64, y64
         torch.cuda.empty_cache()
     if args.extra:
-        line["batched"] = {p: batched_run(torch, pk, W, autotune, max(3, args.steps // 4), 1, p) for p in ("fp64", "fp32")}
-        torch.cuda.empty_cache()
-        line["gradient"] = gradient_run(torch, pk, W, nq)
-        torch.cuda.empty_cache()
-        line["two_qubit"] = two_qubit_run(torch, pk, nq, max(3, args.steps // 4))
-        torch.cuda.empty_cache()
-        line["shor"] = {p: shor_run(torch, pk, W, max(3, args.steps // 4), p) for p in ("fp64", "fp32")}
-        torch.cuda.empty_cache()
-        line["density"] = density_run(torch, pk, W, max(3, args.steps // 4))
-        torch.cuda.empty_cache()
-        line["search"] = search_run(torch, pk, W, 3)
-        torch.cuda.empty_cache()
+        legs = set(args.legs.split(","))
+        k = max(3, args.steps // 4)
+        runs = [("batched", lambda: {p: batched_run(torch, pk, W, autotune, k, 1, p) for p in ("fp64", "fp32")}),
+                ("gradient", lambda: gradient_run(torch, pk, W, nq)),
+                ("two_qubit", lambda: two_qubit_run(torch, pk, nq, k)),
+                ("shor", lambda: {p: shor_run(torch, pk, W, k, p) for p in ("fp64", "fp32")}),
+                ("density", lambda: density_run(torch, pk, W, k)),
+                ("search", lambda: search_run(torch, pk, W, 3))]
+        for name, run in runs:
+            if name in legs:
+                line[name] = run()
+                torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(W, nq, 2 * nq + 2)
     print(json.dumps(line), flush=True)

@@ -376,10 +376,12 @@ def density_run(torch, pk, W, steps):
     return out
 
 
-def search_run(torch, pk, W, reps):
+def search_run(torch, pk, W, autotune, reps):
     """The full Grover search of Sec. 5.1: n_t = floor((pi/4) sqrt(N)) noise-free
     iterations from the uniform state in one replayed graph (pk_evaluate_repeat),
-    at n_q = 20 and 24, FP64; L is the success probability after n_t iterations."""
+    at n_q = 20 and 24, FP64; L is the success probability after n_t iterations.
+    The tile is tuned on one iteration first (a 2^20 state gives only 128 tiles of
+    the default size, half the CUs)."""
     out = {}
     for nq in (20, 24):
         nt = pk.grover_iterations(nq)
@@ -388,6 +390,8 @@ def search_run(torch, pk, W, reps):
         s = torch.full((1 << nq,), 2.0 ** (-nq / 2), dtype=torch.complex128, device="cuda")
         y = torch.empty_like(s)
         L = torch.empty(1, dtype=torch.float64, device="cuda")
+        best, _ = autotune.tune(plan, lambda: pk.evaluate_into(plan, s, y, L), op="eval", reps=5, warmup=2,
+                                use_cache=False)
         ws = plan.workspace(pk.PK_OP_EVAL, s.device)
         st = pk._stream(s.device)
 
@@ -408,6 +412,7 @@ def search_run(torch, pk, W, reps):
         theta = math.asin(2.0 ** (-nq / 2))
         passes = plan.passes() * nt
         out["nq%d" % nq] = {"iterations": nt, "passes": passes, "ms": ms, "iterations_per_s": nt / (ms * 1e-3),
+                            "tile_bits": best["tile_bits"], "carrier_bits": best["carrier_bits"],
                             "mean_pass_GBs": 32.0 * (1 << nq) * passes / (ms * 1e-3) / 1e9,
                             "L": float(L.item()), "L_closed_form": math.sin((2 * nt + 1) * theta) ** 2}
         log("search n_q=%d: %d iterations, %d passes, %.2f ms, L = %.12f" % (nq, nt, passes, ms, L.item()))
@@ -507,7 +512,7 @@ def main():
                 ("two_qubit", lambda: two_qubit_run(torch, pk, nq, k)),
                 ("shor", lambda: {p: shor_run(torch, pk, W, k, p) for p in ("fp64", "fp32")}),
                 ("density", lambda: density_run(torch, pk, W, k)),
-                ("search", lambda: search_run(torch, pk, W, 3))]
+                ("search", lambda: search_run(torch, pk, W, autotune, 3))]
         for name, run in runs:
             if name in legs:
                 line[name] = run()

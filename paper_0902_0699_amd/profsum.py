@@ -80,7 +80,7 @@ def _match(d, sub):
 
 
 def short(name, width=90):
-    name = name.split("(")[0]
+    name = name.replace("(anonymous namespace)::", "").split("(")[0]
     return name if len(name) <= width else name[: width - 3] + "..."
 
 

@@ -208,3 +208,78 @@ def test_density_matrix_full_size():
     assert abs(O.purity(got) - O.purity_gram(Ch, P)) <= 1e-12
     assert np.max(np.abs(lam - wl)) <= 1e-12
     assert abs(float(S) - O.entropy_bits(wl)) <= 1e-9 and abs(float(pur) - O.purity(want)) <= 1e-12
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec,tiling", [("fp64", None), ("fp64", (12, 5)), ("fp32", None), ("fp32", (12, 4))])
+def test_c3_batched_full_size(prec, tiling):
+    """c3 as bench.py times it: 4096 instances with n_q in [10, 20), seed 3, one
+    persistent launch, at the default tile and at the tile the autotuner picked in
+    bench.py.  L of every instance against the closed form (oracle.grover_sampled at
+    the marked label); the whole state of 24 instances (the noise-free one, the
+    largest, the smallest and a seeded sample) against the gate-by-gate oracle."""
+    from paper_0902_0699_amd import paperkern as pk
+
+    insts = W.batch_instances(W.SEEDS["batched"])
+    _say("full size c3: %d instances %s tiling %s" % (len(insts), prec, tiling))
+    plan = pk.Plan([{"nq": b["nq"], "gates": b["gates"], "marked": b["marked"]} for b in insts], prec=prec)
+    if tiling:
+        plan.set_tiling(tiling[0], tiling[1], 1, 1, -1)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    psi_all = np.concatenate([b["psi"] for b in insts])
+    if prec == "fp32":
+        psi_all = psi_all.astype(np.complex64).astype(np.complex128)
+    out, L, norm = pk.evaluate_batched(plan, torch.from_numpy(psi_all).to(dt).to("cuda"))
+    L = L.cpu().numpy()
+    norm = norm.cpu().numpy()
+    offs = plan.offsets()
+    tol = TOL64 if prec == "fp64" else TOL32
+    worst_L = 0.0
+    for k, b in enumerate(insts):
+        psi = psi_all[offs[k]:offs[k + 1]]
+        _, Lw = O.grover_sampled(b["nq"], b["gates"], b["marked"], psi, [b["marked"][0]])
+        worst_L = max(worst_L, abs(L[k] - Lw))
+        assert abs(norm[k] - 1.0) <= tol
+    rng = np.random.default_rng(33)
+    sizes = np.array([b["nq"] for b in insts])
+    pick = sorted({0, int(np.argmax(sizes)), int(np.argmin(sizes))} | {int(v) for v in rng.integers(0, len(insts), 21)})
+    worst = 0.0
+    for k in pick:
+        b = insts[k]
+        psi = psi_all[offs[k]:offs[k + 1]]
+        want, _, _ = O.evaluate(b["nq"], b["gates"], b["marked"], psi)
+        got = out[offs[k]:offs[k + 1]].cpu().numpy().astype(np.complex128)
+        worst = max(worst, float(np.linalg.norm(got - want) / np.linalg.norm(want)))
+    _say("  max |dL| over %d instances %.3e; max normwise err over %d instances %.3e"
+         % (len(insts), worst_L, len(pick), worst))
+    assert worst_L <= tol and worst <= tol
+
+
+@pytest.mark.timeout(900)
+def test_fp32_at_thirty_one_qubits_sampled():
+    """The largest FP32 state (n_q = 31, 16 GiB; byte offsets beyond 32 bits) against
+    oracle.grover_sampled, as c2."""
+    from paper_0902_0699_amd import paperkern as pk
+
+    nq = 31
+    _say("full size: n_q=%d fp32 seed %d" % (nq, W.SEEDS["large_fp32"]))
+    inst = W.single_instance(W.SEEDS["large_fp32"], nq)
+    psi = inst["psi"].astype(np.complex64)
+    del inst["psi"]
+    x = torch.from_numpy(psi).to("cuda")
+    psi = psi.astype(np.complex128)
+    idx = _labels(dict(inst, nq=nq), W.SEEDS["large_fp32"])
+    want, L_ref = O.grover_sampled(nq, inst["gates"], inst["marked"], psi, idx)
+    norm_in = float(np.vdot(psi, psi).real)
+    del psi
+    plan = pk.Plan({"nq": nq, "gates": inst["gates"], "marked": inst["marked"]}, prec="fp32")
+    y, L, norm = pk.evaluate(plan, x)
+    got = y[torch.from_numpy(idx).to("cuda")].cpu().numpy().astype(np.complex128)
+    L, norm = float(L.item()), float(norm.item())
+    del x, y
+    torch.cuda.empty_cache()
+    err = math.sqrt(np.mean(np.abs(got - want) ** 2) * (1 << nq) / norm_in)
+    _say("  passes %d  est. normwise err %.3e  |dL| %.3e  |dnorm| %.3e" % (plan.passes(), err, abs(L - L_ref),
+                                                                          abs(norm - norm_in)))
+    assert err <= TOL32 and abs(L - L_ref) <= TOL32 * max(1.0, L_ref) * norm_in
+    assert abs(norm - norm_in) <= TOL32 * norm_in

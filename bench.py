@@ -416,6 +416,20 @@ def search_run(torch, pk, W, autotune, reps):
                             "mean_pass_GBs": 32.0 * (1 << nq) * passes / (ms * 1e-3) / 1e9,
                             "L": float(L.item()), "L_closed_form": math.sin((2 * nt + 1) * theta) ** 2}
         log("search n_q=%d: %d iterations, %d passes, %.2f ms, L = %.12f" % (nq, nt, passes, ms, L.item()))
+        # the labelled variant through 2|s><s| - I: one pass per iteration, not the paper's form
+        pk.search_diffusion(nq, [x], nt, s, out=y)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            _, Ld = pk.search_diffusion(nq, [x], nt, s, out=y)
+        e1.record()
+        torch.cuda.synchronize()
+        msd = e0.elapsed_time(e1) / reps
+        out["nq%d" % nq]["diffusion_variant"] = {
+            "method": "(2|s><s| - I) . Oracle, one pass per iteration (not the paper's HALL form)",
+            "ms": msd, "iterations_per_s": nt / (msd * 1e-3),
+            "pass_GBs": 2.0 * (1 << nq) * 16 * nt / (msd * 1e-3) / 1e9, "L": float(Ld.item())}
+        log("search n_q=%d, diffusion variant: %.2f ms, L = %.12f" % (nq, msd, Ld.item()))
         del s, y
     return out
 

@@ -229,6 +229,31 @@ int pk_evaluate_repeat(pk_plan* plan, int64_t reps, const void* psi_in, void* ps
                        double* norm_out, const double* angles, void* workspace, void* stream);
 
 /*
+ * pk_search_diffusion -- a labelled variant of the noise-free search, not the
+ * paper's HALL-based form: `iterations` applications of
+ *     G = HALL . Inv . HALL . Oracle = (2|s><s| - I) . Oracle      (Sec. 5.1)
+ * computed through that identity (Inv = 2|0><0| - I, HALL|0..0> = |s>), i.e.
+ * C_n <- 2 mean(O C) - (O C)_n with O the Oracle's sign flips: one streaming pass
+ * per iteration instead of the HALL sweeps.  Exact in exact arithmetic; it
+ * applies only to the noise-free iteration (a noise rotation between the HALLs
+ * breaks the identity).
+ *   nq          1..30 (PK_FP64) or 1..31 (PK_FP32); prec as for plans
+ *   marked      host int64[n_marked], distinct labels in [0, 2^nq), 0 <= n_marked <= 64
+ *   iterations  >= 1 (the search: n_t = floor((pi/4) sqrt(2^nq)))
+ *   psi_in      device, 2^nq complex, read; may equal psi_out
+ *   psi_out     device, 2^nq complex, written
+ *   L_out       device double[1]: sum_{x in M} |C_x|^2 of the final state
+ *   workspace   device, >= pk_search_workspace_bytes() (FP64 partial sums and the mean)
+ * Means are FP64 sums in a fixed order.  Not captured into a graph: 2 launches
+ * per iteration go to `stream` directly.  PK_EINVAL on range or pointer errors.
+ */
+int pk_search_diffusion(int32_t nq, int32_t prec, const int64_t* marked, int32_t n_marked, int64_t iterations,
+                        const void* psi_in, void* psi_out, double* L_out, void* workspace, void* stream);
+
+/* Workspace pk_search_diffusion needs (bytes). */
+int pk_search_workspace_bytes(int64_t* bytes);
+
+/*
  * pk_evaluate_batched -- evaluate every instance of the plan ("multiverses",
  * Sec. 6.2) in one persistent launch replayed from a hipGraph.  States are
  * packed at pk_plan_offsets(); L_out and norm_out (or NULL) hold n_inst doubles.

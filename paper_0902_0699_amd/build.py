@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpaperkern.so")
-SOURCES = ["pk_kernels.hip", "pk_shor.hip", "pk_density.hip", "pk_api.cpp", "pk_plan.cpp"]
+SOURCES = ["pk_kernels.hip", "pk_shor.hip", "pk_density.hip", "pk_search.hip", "pk_api.cpp", "pk_plan.cpp"]
 # rocSOLVER (and the rocBLAS handle it runs on) gives the density matrix's eigenvalues
 LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

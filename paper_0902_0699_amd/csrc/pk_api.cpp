@@ -528,6 +528,35 @@ int pk_evaluate_repeat(pk_plan* plan, int64_t reps, const void* psi_in, void* ps
                        [&](hipStream_t s) { return enqueue_eval(d, a, s, nullptr, reps); });
 }
 
+int pk_search_workspace_bytes(int64_t* bytes) {
+    if (!bytes) return fail(nullptr, PK_EINVAL, "NULL output");
+    *bytes = (int64_t)search_workspace_bytes();
+    return PK_OK;
+}
+
+int pk_search_diffusion(int32_t nq, int32_t prec, const int64_t* marked, int32_t n_marked, int64_t iterations,
+                        const void* psi_in, void* psi_out, double* L_out, void* workspace, void* stream) {
+    if (prec != PK_FP64 && prec != PK_FP32) return fail(nullptr, PK_EINVAL, "prec must be PK_FP64 or PK_FP32");
+    if (nq < 1 || nq > (prec == PK_FP64 ? 30 : 31)) return fail(nullptr, PK_EINVAL, "nq out of range");
+    if (n_marked < 0 || n_marked > 64 || (n_marked > 0 && !marked))
+        return fail(nullptr, PK_EINVAL, "marked set must hold 0..64 labels");
+    if (iterations < 1) return fail(nullptr, PK_EINVAL, "iterations must be >= 1");
+    if (!psi_in || !psi_out || !L_out || !workspace || (reinterpret_cast<uintptr_t>(psi_in) & 15) ||
+        (reinterpret_cast<uintptr_t>(psi_out) & 15) || (reinterpret_cast<uintptr_t>(workspace) & 15))
+        return fail(nullptr, PK_EINVAL, "NULL or misaligned pointer");
+    MarkedSet ms{};
+    ms.count = n_marked;
+    for (int i = 0; i < n_marked; ++i) {
+        if (marked[i] < 0 || marked[i] >= ((int64_t)1 << nq)) return fail(nullptr, PK_EINVAL, "marked label out of range");
+        for (int j = 0; j < i; ++j)
+            if (marked[j] == marked[i]) return fail(nullptr, PK_EINVAL, "duplicate marked label");
+        ms.label[i] = marked[i];
+    }
+    hipError_t e = launch_search(psi_in, psi_out, nq, prec == PK_FP64, ms, iterations, workspace, L_out,
+                                 static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? PK_OK : hip_fail(nullptr, e, "diffusion search");
+}
+
 int pk_evaluate_batched(pk_plan* plan, const void* psi_in, void* psi_out, double* L_out, double* norm_out,
                         const double* angles, void* workspace, void* stream) {
     if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");

@@ -86,5 +86,14 @@ hipError_t launch_marginal(int nq, int n_low, bool fp64, const void* psi, double
 int64_t density_blocks(int64_t N);
 hipError_t launch_density(const void* C, const double* P, void* rho, int64_t N, int A, hipStream_t st);
 hipError_t launch_spectrum_sums(const double* lam, int64_t n, double* out, hipStream_t st);
+// The noise-free Grover search by the diffusion identity (pk_search.hip).
+struct MarkedSet {
+    int32_t count;
+    int32_t pad;
+    int64_t label[64];
+};
+size_t search_workspace_bytes();
+hipError_t launch_search(const void* psi_in, void* psi_out, int nq, bool fp64, const MarkedSet& ms, int64_t iters,
+                         void* workspace, double* L, hipStream_t st);
 
 }  // namespace pk

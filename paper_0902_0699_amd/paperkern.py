@@ -60,6 +60,8 @@ SIGNATURES = {
     "pk_shor_state": (ctypes.c_int, [_c_int32, _c_int32, _c_int64, _c_int64, _c_int32, _vp, _vp]),
     "pk_marginal": (ctypes.c_int, [_c_int32, _c_int32, _c_int32, _vp, _vp, _vp]),
     "pk_density_matrix": (ctypes.c_int, [_c_int32, _c_int32, _vp, _vp, _vp, _vp]),
+    "pk_search_diffusion": (ctypes.c_int, [_c_int32, _c_int32, _vp, _c_int32, _c_int64, _vp, _vp, _vp, _vp, _vp]),
+    "pk_search_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(_c_int64)]),
     "pk_density_spectrum": (ctypes.c_int, [_c_int32, _vp, _vp, _vp, _vp]),
     "pk_time_passes": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_c_double),
                                       _c_int32, ctypes.POINTER(_c_int32)]),
@@ -309,6 +311,27 @@ def evaluate_repeat(plan, psi_in, reps, angles=None, want_norm=True, out=None):
                                   _ptr(angles), _ptr(ws), _stream(dev))
     _check(rc, plan.handle)
     return psi_out, L, norm
+
+
+def search_diffusion(nq, marked, iterations, psi_in, out=None, workspace=None):
+    """The noise-free search through 2|s><s| - I (pk_search_diffusion, a labelled
+    variant of the HALL-based iteration): returns (psi_out, L)."""
+    import torch
+    dev = psi_in.device
+    if psi_in.dtype not in (torch.complex128, torch.complex64) or psi_in.numel() != (1 << nq):
+        raise ValueError("psi_in must hold 2^nq complex amplitudes")
+    prec = PK_FP64 if psi_in.dtype == torch.complex128 else PK_FP32
+    psi_out = torch.empty_like(psi_in) if out is None else out
+    L = torch.empty(1, dtype=torch.float64, device=dev)
+    if workspace is None:
+        nb = ctypes.c_int64()
+        _check(lib().pk_search_workspace_bytes(ctypes.byref(nb)), None)
+        workspace = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    labels = (ctypes.c_int64 * max(1, len(marked)))(*[int(v) for v in marked])
+    rc = lib().pk_search_diffusion(nq, prec, labels, len(marked), int(iterations), _ptr(psi_in), _ptr(psi_out),
+                                   _ptr(L), _ptr(workspace), _stream(dev))
+    _check(rc, None)
+    return psi_out, L
 
 
 def grover_iterations(nq):

@@ -88,3 +88,58 @@ def test_repeat_once_equals_evaluate_and_rejects_bad_reps():
     assert torch.equal(a, b) and La.item() == Lb.item()
     with pytest.raises(pk.PaperkernError):
         pk.evaluate_repeat(plan, x, 0)
+
+
+# --------------------------------------------------------------------------- the diffusion variant
+
+
+@pytest.mark.parametrize("nq,prec", [(3, "fp64"), (10, "fp64"), (16, "fp64"), (22, "fp64"), (14, "fp32"),
+                                     (20, "fp32")])
+def test_diffusion_variant_against_closed_form(nq, prec):
+    pk = _pk()
+    nt = pk.grover_iterations(nq)
+    x = int(np.random.default_rng(nq + 1).integers(0, 1 << nq))
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    _say("diffusion variant n_q=%d n_t=%d %s" % (nq, nt, prec))
+    out, L = pk.search_diffusion(nq, [x], nt, _uniform(nq, dt))
+    torch.cuda.synchronize()
+    want = O.grover_closed_form(nq, nt, x)
+    err = float(np.linalg.norm(out.cpu().numpy().astype(np.complex128) - want))
+    tol = (1e-12 if prec == "fp64" else 1e-5) * max(1.0, nt / 10.0)
+    _say("  normwise err %.3e  L %.12f" % (err, L.item()))
+    assert err <= tol and abs(L.item() - abs(want[x]) ** 2) <= tol
+
+
+def test_diffusion_variant_equals_hall_form_with_several_marked():
+    """From a random state with three marked items, the identity route and the
+    HALL-based passes give the same state (and one step equals the gate-by-gate
+    oracle)."""
+    pk = _pk()
+    nq, reps = 14, 9
+    rng = np.random.default_rng(12)
+    psi = rng.standard_normal(1 << nq) + 1j * rng.standard_normal(1 << nq)
+    psi /= np.linalg.norm(psi)
+    marked = [5, 999, (1 << nq) - 1]
+    x = torch.from_numpy(psi).to("cuda")
+    _say("diffusion variant vs HALL form, n_q=%d, %d marked" % (nq, len(marked)))
+    a, La = pk.search_diffusion(nq, marked, reps, x)
+    plan = pk.Plan({"nq": nq, "gates": W.grover_gates(), "marked": marked})
+    b, Lb, _ = pk.evaluate_repeat(plan, x, reps)
+    torch.cuda.synchronize()
+    assert torch.linalg.vector_norm(a - b).item() <= 1e-12 * reps and abs(La.item() - Lb.item()) <= 1e-12 * reps
+    one, L1 = pk.search_diffusion(nq, marked, 1, x)
+    want, Lw, _ = O.evaluate(nq, W.grover_gates(), marked, psi)
+    assert np.linalg.norm(one.cpu().numpy() - want) <= 1e-13 and abs(L1.item() - Lw) <= 1e-13
+    # in place
+    y = x.clone()
+    pk.search_diffusion(nq, marked, reps, y, out=y)
+    torch.cuda.synchronize()
+    assert torch.linalg.vector_norm(y - a).item() == 0.0
+
+
+def test_diffusion_variant_rejects_bad_arguments():
+    pk = _pk()
+    x = _uniform(6)
+    for nq, marked, it in ((6, [64], 1), (6, [3, 3], 1), (6, [1], 0), (0, [0], 1)):
+        with pytest.raises((pk.PaperkernError, ValueError)):
+            pk.search_diffusion(nq, marked, it, x)

@@ -2,6 +2,7 @@
 pass schedules the plan compiler emits (executed by tests/schedule_emulator.py
 and compared with the oracle).  No GPU call is made here."""
 
+import ctypes
 import math
 import os
 import re
@@ -472,3 +473,45 @@ def test_relabelling_passes_have_an_exchange():
             if p["tile_bits"] != p["store_bits"]:
                 assert len(p["stages"]) >= 2
                 assert any(u["exchange"] for u in p["subs"][1:])
+
+
+# --------------------------------------------------------------------------- argument checks of the plan-less entry points
+
+
+def _einval(rc, text):
+    assert rc == pk.PK_EINVAL
+    assert text in pk.lib().pk_last_error(None).decode()
+
+
+def test_shor_marginal_density_search_entry_points_reject_bad_arguments():
+    """Every check runs before any device call, so these need no GPU."""
+    lib = pk.lib()
+    buf = ctypes.c_void_p(4096)  # an aligned non-NULL address; never dereferenced on these paths
+    _einval(lib.pk_shor_state(0, 4, 7, 15, pk.PK_FP64, buf, None), "register sizes")
+    _einval(lib.pk_shor_state(20, 11, 7, 15, pk.PK_FP64, buf, None), "register sizes")
+    _einval(lib.pk_shor_state(8, 4, 7, 17, pk.PK_FP64, buf, None), "M must")
+    _einval(lib.pk_shor_state(8, 4, 15, 15, pk.PK_FP64, buf, None), "xguess")
+    _einval(lib.pk_shor_state(8, 4, 7, 15, 7, buf, None), "prec")
+    _einval(lib.pk_shor_state(8, 4, 7, 15, pk.PK_FP64, ctypes.c_void_p(4097), None), "aligned")
+    _einval(lib.pk_marginal(12, 13, pk.PK_FP64, buf, buf, None), "n_low")
+    _einval(lib.pk_marginal(31, 3, pk.PK_FP64, buf, buf, None), "nq")
+    _einval(lib.pk_marginal(12, 3, pk.PK_FP64, None, buf, None), "NULL")
+    _einval(lib.pk_density_matrix(17, 4, buf, buf, buf, None), "nq")
+    _einval(lib.pk_density_matrix(8, 0, buf, buf, buf, None), "universe")
+    _einval(lib.pk_density_spectrum(16, buf, buf, buf, None), "nq")
+    one = (ctypes.c_int64 * 2)(3, 3)
+    _einval(lib.pk_search_diffusion(6, pk.PK_FP64, one, 2, 5, buf, buf, buf, buf, None), "duplicate")
+    _einval(lib.pk_search_diffusion(6, pk.PK_FP64, one, 1, 0, buf, buf, buf, buf, None), "iterations")
+    big = (ctypes.c_int64 * 1)(64)
+    _einval(lib.pk_search_diffusion(6, pk.PK_FP64, big, 1, 5, buf, buf, buf, buf, None), "out of range")
+    _einval(lib.pk_search_diffusion(6, pk.PK_FP64, one, 65, 5, buf, buf, buf, buf, None), "0..64")
+
+
+def test_evaluate_repeat_rejects_bad_reps_before_the_device():
+    plan = pk.Plan({"nq": 6, "gates": W.grover_gates(), "marked": [1]})
+    buf = ctypes.c_void_p(4096)
+    rc = pk.lib().pk_evaluate_repeat(plan.handle, 0, buf, buf, buf, None, None, buf, None)
+    assert rc == pk.PK_EINVAL and "reps" in pk.lib().pk_last_error(plan.handle).decode()
+    batch = pk.Plan([{"nq": 4, "gates": [], "marked": []}] * 2)
+    rc = pk.lib().pk_evaluate_repeat(batch.handle, 3, buf, buf, buf, None, None, buf, None)
+    assert rc == pk.PK_EINVAL and "single-instance" in pk.lib().pk_last_error(batch.handle).decode()

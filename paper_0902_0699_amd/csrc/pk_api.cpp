@@ -110,6 +110,7 @@ int ensure_device(DevPlan* d) {
     put(buf, t.stages, P.stages);
     put(buf, t.flips, P.flips);
     put(buf, t.phases, P.phases);
+    put(buf, t.upairs, P.upairs);
     put(buf, t.mats, P.static_mats);
     put(buf, t.mats + P.static_mats.size() * sizeof(double), P.default_angles);
     put(buf, t.mats4, P.static_mats4);
@@ -163,6 +164,7 @@ PassLaunch base_launch(DevPlan* d, void* ws, int op) {
     L.stages = at<Stage>(P.d_tables, t.stages);
     L.flips = at<Flip>(P.d_tables, t.flips);
     L.phases = at<PhaseOp>(P.d_tables, t.phases);
+    L.upairs = at<UPair>(P.d_tables, t.upairs);
     L.mats = at<double>(ws, w.mats);
     L.mats4 = at<double>(ws, w.mats4);
     L.partials = at<double>(ws, w.partials);

@@ -35,6 +35,7 @@ enum OpKind : int32_t {
 };
 
 constexpr int kPhaseSlots = 4;  // phase accumulators per sub-stage
+constexpr int kMaxUPairs = 128; // tile-uniform slot products per pass (LDS table)
 
 // One controlled phase as the kernel applies it in a sub-stage.  The amplitudes
 // whose two qubits are both 1 get the factor c + i s.  Each qubit's bit sits on
@@ -46,7 +47,8 @@ constexpr int kPhaseSlots = 4;  // phase accumulators per sub-stage
 // phases are stored grouped by slot (Stage::phase_cnt), so the kernel runs one
 // branch-free loop per slot.
 struct PhaseOp {
-    int32_t slot;    // accumulator slot of the sub-stage
+    int32_t slot;    // accumulator slot of the sub-stage (within a slot, the phases
+                     // with tmask == 0 come first: see Stage::phase_ucnt)
     uint32_t tmask;  // local label bits held by the thread index that must be 1
     int64_t fmask;   // tile-index bits that must be 1
     double cm1, s;   // the factor as (c - 1, s): 1 + on * (c - 1) and on * s give the
@@ -93,6 +95,9 @@ struct Stage {
     int32_t phase_count;      // number of them (diagonal: any order)
     int32_t phase_pm[kPhaseSlots];   // register-bit mask of each accumulator slot, -1 when unused
     int32_t phase_cnt[kPhaseSlots];  // phases of each slot, stored slot after slot
+    int32_t phase_ucnt[kPhaseSlots]; // of them, the leading ones whose factor is the same for
+                                     // every thread of a tile (tmask == 0)
+    int32_t phase_upair[kPhaseSlots];// their product's entry in the pass's tile-uniform table, or -1
     int32_t mat_pre_a;        // register bit of a matrix before the Hadamards, or -1
     int32_t mat_pre;          // its matrix index
     int32_t hmask1;           // register bits that get a Hadamard
@@ -135,6 +140,12 @@ struct Run {
     int32_t src, len, dst, pad;
 };
 
+// A tile-uniform product: the phases [first, first + count) of the phase table.
+struct UPair {
+    int32_t first;
+    int32_t count;
+};
+
 struct Pass {
     int32_t k;           // tile bits
     int32_t nstages;
@@ -149,6 +160,8 @@ struct Pass {
     int32_t ntrun;       // runs of consecutive tile bits
     int32_t nfrun;       // runs of consecutive free bits
     int32_t nstrun;      // runs of the store map
+    int32_t upair_begin; // first UPair of the pass
+    int32_t nupair;      // number of them (0: no table)
     int32_t tpos[16];    // global bit position of local tile bit l when the tile is read
     int32_t stpos[16];   // ... when it is written (differs after SWAPs done by relabelling)
     Run trun[kMaxRuns];  // local tile label -> state label (read)

@@ -41,6 +41,7 @@ struct KArgs {
     const Stage* stages;
     const Flip* flips;
     const PhaseOp* phases;
+    const UPair* upairs;
     const double* mats;
     const double* mats4;  // 4x4 complex matrices of two-qubit gates, 32 doubles each
     const void* src0;  // vector 0 input of the first pass
@@ -302,9 +303,60 @@ __device__ __forceinline__ void op_d4bwd(T (&v)[NV][NR], const PK_CONST double* 
 // branch around a late scalar load of c), so every table read is unconditional
 // and the loads of several phases are in flight together.  Two independent
 // product chains halve the dependent multiply latency.
+//
+// A slot's product multiplies the registers whose index holds the slot's register
+// bits.  The mask is uniform but not known at compile time; a switch over the
+// possible masks gives each case a fixed register set (a loop with a run-time
+// mask test compiles to a product for every register and a select).
+template <int PM, int NV, int NR, typename T, typename R>
+__device__ __forceinline__ void slot_mul(T (&v)[NV][NR], R c, R s) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        if ((i & PM) != PM) continue;
+#pragma unroll
+        for (int m = 0; m < NV; ++m) {
+            const R x = v[m][i].x, y = v[m][i].y;
+            v[m][i].x = x * c - y * s;
+            v[m][i].y = x * s + y * c;
+        }
+    }
+}
+
+template <int NV, int NR, typename T, typename R>
+__device__ __forceinline__ void apply_slot(T (&v)[NV][NR], int pm, R c, R s) {
+    switch (pm) {
+    case 0: slot_mul<0, NV, NR>(v, c, s); break;
+    case 1: slot_mul<1, NV, NR>(v, c, s); break;
+    case 2: slot_mul<2, NV, NR>(v, c, s); break;
+    case 4: slot_mul<4, NV, NR>(v, c, s); break;
+    case 8: slot_mul<8, NV, NR>(v, c, s); break;
+    case 3: slot_mul<3, NV, NR>(v, c, s); break;
+    case 5: slot_mul<5, NV, NR>(v, c, s); break;
+    case 6: slot_mul<6, NV, NR>(v, c, s); break;
+    case 9: slot_mul<9, NV, NR>(v, c, s); break;
+    case 10: slot_mul<10, NV, NR>(v, c, s); break;
+    case 12: slot_mul<12, NV, NR>(v, c, s); break;
+    default:
+        if constexpr (NR > 16) {
+            switch (pm) {
+            case 16: slot_mul<16, NV, NR>(v, c, s); break;
+            case 17: slot_mul<17, NV, NR>(v, c, s); break;
+            case 18: slot_mul<18, NV, NR>(v, c, s); break;
+            case 20: slot_mul<20, NV, NR>(v, c, s); break;
+            case 24: slot_mul<24, NV, NR>(v, c, s); break;
+            default: break;
+            }
+        }
+        break;
+    }
+}
+
+// The leading phase_ucnt[u] phases of a slot do not depend on the thread: their
+// product for the current tile was computed once for the workgroup (ufac, see
+// compute_tile) and starts the slot's product.
 template <int NV, int NR, typename T>
 __device__ __forceinline__ void apply_phases(const KArgs& a, const PK_CONST Stage* S, T (&v)[NV][NR],
-                                             const Layout& L, int64_t tile) {
+                                             const Layout& L, int64_t tile, const double* ufac) {
     using R = decltype(v[0][0].x);
     const PK_CONST PhaseOp* ph = cptr(a.phases) + S->phase_first;
 #pragma unroll
@@ -312,7 +364,12 @@ __device__ __forceinline__ void apply_phases(const KArgs& a, const PK_CONST Stag
         const int cnt = S->phase_cnt[u];
         if (cnt == 0) continue;
         R c0 = 1, s0 = 0, c1 = 1, s1 = 0;
-        int q = 0;
+        const int pair = S->phase_upair[u];
+        if (pair >= 0) {
+            c0 = (R)ufac[2 * pair];
+            s0 = (R)ufac[2 * pair + 1];
+        }
+        int q = S->phase_ucnt[u];
 #pragma unroll 2
         for (; q + 1 < cnt; q += 2) {
             const int64_t fa = ph[q].fmask, fb = ph[q + 1].fmask;
@@ -340,17 +397,7 @@ __device__ __forceinline__ void apply_phases(const KArgs& a, const PK_CONST Stag
         }
         ph += cnt;
         const R c = c0 * c1 - s0 * s1, s = c0 * s1 + s0 * c1;
-        const int pm = S->phase_pm[u];
-#pragma unroll
-        for (int i = 0; i < NR; ++i) {
-            if ((i & pm) != pm) continue;
-#pragma unroll
-            for (int m = 0; m < NV; ++m) {
-                const R x = v[m][i].x, y = v[m][i].y;
-                v[m][i].x = x * c - y * s;
-                v[m][i].y = x * s + y * c;
-            }
-        }
+        apply_slot<NV, NR>(v, S->phase_pm[u], c, s);
     }
 }
 
@@ -550,6 +597,29 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
     const int nreg = C.nreg;
     const PK_CONST Stage* S = cptr(a.stages) + P->stage_begin;
     Layout L = C.L0;
+    // tile-uniform phase products of the pass: one thread per product, in FP64,
+    // between two barriers (the previous tile's sub-stages may still read the table)
+    double* ufac = red + 16;
+    const int nup = P->nupair;
+    if (nup > 0) {
+        __syncthreads();
+        const PK_CONST UPair* U = cptr(a.upairs) + P->upair_begin;
+        for (int p = tid; p < nup; p += NT) {
+            const PK_CONST PhaseOp* ph = cptr(a.phases) + U[p].first;
+            double c = 1.0, sn = 0.0;
+            for (int q = 0; q < U[p].count; ++q) {
+                const int64_t fm = ph[q].fmask;
+                if ((tile & fm) != fm) continue;
+                const double cq = 1.0 + ph[q].cm1, sq = ph[q].s;
+                const double x = c;
+                c = x * cq - sn * sq;
+                sn = x * sq + sn * cq;
+            }
+            ufac[2 * p] = c;
+            ufac[2 * p + 1] = sn;
+        }
+        __syncthreads();
+    }
     for (int s = 0; s < C.nstages; ++s, ++S) {
         // one scalar word says which steps follow; only their parameters are loaded
         const int steps = S->steps;
@@ -578,7 +648,7 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
             if (steps & ST_SEED) element_op<NV, NR, 2>(a, v, L, S->seed, tile, nreg, active);
         }
         if (steps & ST_FLIP_PRE) element_op<NV, NR, 0>(a, v, L, S->flip_pre, tile, nreg, active);
-        if ((steps & ST_PHASE) && active) apply_phases<NV, NR>(a, S, v, L, tile);
+        if ((steps & ST_PHASE) && active) apply_phases<NV, NR>(a, S, v, L, tile, ufac);
         if (steps & ST_MAT_PRE) {
             R m[8];
             const PK_CONST double* mp = cptr(a.mats) + 8 * S->mat_pre;
@@ -719,7 +789,7 @@ template <typename R, int NV, int KMAX, int RB>
 __global__ void __launch_bounds__(1 << (KMAX - RB)) pass_kernel(KArgs a) {
     using T = typename Cplx<R>::T;
     __shared__ T lds[1 << KMAX];
-    __shared__ double red[16];
+    __shared__ double red[16 + 2 * kMaxUPairs];  // reduction scratch, then the tile-uniform phase products
     const PK_CONST Pass* P = cptr(a.passes) + a.pass;
     run_tiles<R, NV, KMAX, RB>(a, P, blockIdx.x, gridDim.x, P->ntiles, lds, red);
 }
@@ -786,7 +856,7 @@ __global__ void __launch_bounds__(1 << (KMAX - RB)) batched_kernel(KArgs a, Batc
     using T = typename Cplx<R>::T;
     constexpr int NT = 1 << (KMAX - RB);
     __shared__ T lds[1 << KMAX];
-    __shared__ double red[16];
+    __shared__ double red[16 + 2 * kMaxUPairs];  // reduction scratch, then the tile-uniform phase products
     __shared__ int item;
     __shared__ int flag;
     const PK_CONST InstDesc* idesc = cptr(b.idesc);
@@ -1001,6 +1071,7 @@ static KArgs kargs(const PassLaunch& L) {
     a.stages = L.stages;
     a.flips = L.flips;
     a.phases = L.phases;
+    a.upairs = L.upairs;
     a.mats = L.mats;
     a.mats4 = L.mats4;
     a.src0 = L.src0;

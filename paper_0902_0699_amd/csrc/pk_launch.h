@@ -12,6 +12,7 @@ struct PassLaunch {
     const Stage* stages;
     const Flip* flips;
     const PhaseOp* phases;
+    const UPair* upairs;
     const double* mats;
     const double* mats4;
     const void* src0;

@@ -187,17 +187,37 @@ Stage blank_sub(const HostStage& hs, int exchange) {
     for (int u = 0; u < kPhaseSlots; ++u) {
         s.phase_pm[u] = -1;
         s.phase_cnt[u] = 0;
+        s.phase_ucnt[u] = 0;
+        s.phase_upair[u] = -1;
     }
     return s;
 }
 
-// Finishes a sub-stage: its phases stored grouped by slot (stable) and counted,
-// and the mask of the steps it holds.
-void finish_sub(Stage& s, std::vector<PhaseOp>* table) {
+// Finishes a sub-stage: its phases stored grouped by slot, the tile-uniform ones
+// (no condition on the thread's label bits) first in each slot, and counted; the
+// uniform groups get entries in the pass's table of tile-uniform products (at most
+// kMaxUPairs per pass, the rest stay per thread); then the mask of the steps.
+void finish_sub(Stage& s, std::vector<PhaseOp>* table, std::vector<UPair>* upairs, size_t pass_upairs) {
     if (s.phase_count > 0) {
         auto b = table->begin() + s.phase_first, e = b + s.phase_count;
-        std::stable_sort(b, e, [](const PhaseOp& x, const PhaseOp& y) { return x.slot < y.slot; });
-        for (auto it = b; it != e; ++it) ++s.phase_cnt[it->slot];
+        std::stable_sort(b, e, [](const PhaseOp& x, const PhaseOp& y) {
+            const int kx = 2 * x.slot + (x.tmask != 0), ky = 2 * y.slot + (y.tmask != 0);
+            return kx < ky;
+        });
+        for (auto it = b; it != e; ++it) {
+            ++s.phase_cnt[it->slot];
+            if (it->tmask == 0) ++s.phase_ucnt[it->slot];
+        }
+        int32_t first = s.phase_first;
+        for (int u = 0; u < kPhaseSlots; ++u) {
+            if (s.phase_ucnt[u] > 0 && upairs->size() - pass_upairs < (size_t)kMaxUPairs) {
+                s.phase_upair[u] = (int32_t)(upairs->size() - pass_upairs);
+                upairs->push_back({first, s.phase_ucnt[u]});
+            } else {
+                s.phase_ucnt[u] = 0;  // handled per thread
+            }
+            first += s.phase_cnt[u];
+        }
     }
     s.steps = (s.exchange ? ST_EXCHANGE : 0) | (s.seed >= 0 ? ST_SEED : 0) | (s.flip_pre >= 0 ? ST_FLIP_PRE : 0) |
               (s.phase_count > 0 ? ST_PHASE : 0) | (s.mat_pre_a >= 0 ? ST_MAT_PRE : 0) | (s.hmask1 ? ST_H1 : 0) |
@@ -281,7 +301,8 @@ int place(Stage& s, int cursor, const Op& o) {
     }
 }
 
-std::vector<Stage> pack_stage(const HostStage& hs, const std::vector<HostPhase>& phases, std::vector<PhaseOp>* table) {
+std::vector<Stage> pack_stage(const HostStage& hs, const std::vector<HostPhase>& phases, std::vector<PhaseOp>* table,
+                              std::vector<UPair>* upairs, size_t pass_upairs) {
     std::vector<Stage> subs;
     Stage cur = blank_sub(hs, 1);
     int cursor = 0;
@@ -291,7 +312,7 @@ std::vector<Stage> pack_stage(const HostStage& hs, const std::vector<HostPhase>&
     for (const Op& o : hs.ops) {
         int slot = put(o);
         if (slot < 0) {
-            finish_sub(cur, table);
+            finish_sub(cur, table, upairs, pass_upairs);
             subs.push_back(cur);
             cur = blank_sub(hs, 0);
             cursor = 0;
@@ -299,7 +320,7 @@ std::vector<Stage> pack_stage(const HostStage& hs, const std::vector<HostPhase>&
         }
         cursor = slot;
     }
-    finish_sub(cur, table);
+    finish_sub(cur, table, upairs, pass_upairs);
     subs.push_back(cur);
     return subs;
 }
@@ -809,10 +830,12 @@ struct Compiler {
                     fin.ops.push_back(o);
                 }
             }
+            hp.upair_begin = (int)plan->upairs.size();
             for (const HostStage& hs : hp.stages) {
-                std::vector<Stage> sub = pack_stage(hs, hp.phases, &plan->phases);
+                std::vector<Stage> sub = pack_stage(hs, hp.phases, &plan->phases, &plan->upairs, hp.upair_begin);
                 hp.subs.insert(hp.subs.end(), sub.begin(), sub.end());
             }
+            hp.nupair = (int)plan->upairs.size() - hp.upair_begin;
             out->push_back(hp);
             ++pass_no;
         } while (left > 0);
@@ -1061,6 +1084,7 @@ int recompile(Plan* plan, std::string* err) {
     plan->stages.clear();
     plan->flips.clear();
     plan->phases.clear();
+    plan->upairs.clear();
     plan->idesc.clear();
     plan->order.clear();
     plan->d2_grad.clear();
@@ -1117,6 +1141,8 @@ int recompile(Plan* plan, std::string* err) {
         p.flags = hp.flags;
         p.scale = hp.scale;
         p.part_base = hp.part_base;
+        p.upair_begin = hp.upair_begin;
+        p.nupair = hp.nupair;
         p.kmax = hp.kmax;
         p.rbits = hp.rbits;
         for (int l = 0; l < 16; ++l) {
@@ -1235,6 +1261,8 @@ TableLayout table_layout(const Plan* plan) {
     o = align256(o + plan->flips.size() * sizeof(Flip));
     t.phases = o;
     o = align256(o + plan->phases.size() * sizeof(PhaseOp));
+    t.upairs = o;
+    o = align256(o + plan->upairs.size() * sizeof(UPair));
     t.mats = o;  // static matrices followed by the default angles
     o = align256(o + (plan->static_mats.size() + plan->default_angles.size()) * sizeof(double));
     t.mats4 = o;  // static two-qubit matrices
@@ -1385,6 +1413,8 @@ std::string describe(const Plan* plan) {
                          "," + std::to_string(u.phase_pm[2]) + "," + std::to_string(u.phase_pm[3]) + "]" +
                          ",\"phase_cnt\":[" + std::to_string(u.phase_cnt[0]) + "," + std::to_string(u.phase_cnt[1]) +
                          "," + std::to_string(u.phase_cnt[2]) + "," + std::to_string(u.phase_cnt[3]) + "]" +
+                         ",\"phase_ucnt\":[" + std::to_string(u.phase_ucnt[0]) + "," + std::to_string(u.phase_ucnt[1]) +
+                         "," + std::to_string(u.phase_ucnt[2]) + "," + std::to_string(u.phase_ucnt[3]) + "]" +
                          ",\"mat_pre_a\":" +
                          std::to_string(u.mat_pre_a) + ",\"mat_pre\":" + std::to_string(u.mat_pre) +
                          ",\"hmask1\":" + std::to_string(u.hmask1) + ",\"flip_mid\":" +

@@ -305,49 +305,23 @@ __device__ __forceinline__ void op_d4bwd(T (&v)[NV][NR], const PK_CONST double* 
 // product chains halve the dependent multiply latency.
 //
 // A slot's product multiplies the registers whose index holds the slot's register
-// bits.  The mask is uniform but not known at compile time; a switch over the
-// possible masks gives each case a fixed register set (a loop with a run-time
-// mask test compiles to a product for every register and a select).
-template <int PM, int NV, int NR, typename T, typename R>
-__device__ __forceinline__ void slot_mul(T (&v)[NV][NR], R c, R s) {
+// bits.  The mask is uniform but not known at compile time, so each register's
+// test is a scalar branch around its multiply.  The empty volatile statement in
+// the branch keeps the compiler from speculating the multiply into a product for
+// every register followed by a select, and because each branch updates one
+// register in place, no other register is copied where the paths join.
+template <int NV, int NR, typename T, typename R>
+__device__ __forceinline__ void apply_slot(T (&v)[NV][NR], int pm, R c, R s) {
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
-        if ((i & PM) != PM) continue;
+        if ((i & pm) != pm) continue;
+        __asm__ volatile("");
 #pragma unroll
         for (int m = 0; m < NV; ++m) {
             const R x = v[m][i].x, y = v[m][i].y;
             v[m][i].x = x * c - y * s;
             v[m][i].y = x * s + y * c;
         }
-    }
-}
-
-template <int NV, int NR, typename T, typename R>
-__device__ __forceinline__ void apply_slot(T (&v)[NV][NR], int pm, R c, R s) {
-    switch (pm) {
-    case 0: slot_mul<0, NV, NR>(v, c, s); break;
-    case 1: slot_mul<1, NV, NR>(v, c, s); break;
-    case 2: slot_mul<2, NV, NR>(v, c, s); break;
-    case 4: slot_mul<4, NV, NR>(v, c, s); break;
-    case 8: slot_mul<8, NV, NR>(v, c, s); break;
-    case 3: slot_mul<3, NV, NR>(v, c, s); break;
-    case 5: slot_mul<5, NV, NR>(v, c, s); break;
-    case 6: slot_mul<6, NV, NR>(v, c, s); break;
-    case 9: slot_mul<9, NV, NR>(v, c, s); break;
-    case 10: slot_mul<10, NV, NR>(v, c, s); break;
-    case 12: slot_mul<12, NV, NR>(v, c, s); break;
-    default:
-        if constexpr (NR > 16) {
-            switch (pm) {
-            case 16: slot_mul<16, NV, NR>(v, c, s); break;
-            case 17: slot_mul<17, NV, NR>(v, c, s); break;
-            case 18: slot_mul<18, NV, NR>(v, c, s); break;
-            case 20: slot_mul<20, NV, NR>(v, c, s); break;
-            case 24: slot_mul<24, NV, NR>(v, c, s); break;
-            default: break;
-            }
-        }
-        break;
     }
 }
 

@@ -137,6 +137,28 @@ def test_diffusion_variant_equals_hall_form_with_several_marked():
     assert torch.linalg.vector_norm(y - a).item() == 0.0
 
 
+def test_diffusion_variant_with_many_marks_in_one_block():
+    """At n_q = 14 each block of the streaming pass owns 8 labels: marks 8..12 put
+    five in one block (beyond the two a block keeps by value), 40 and 47 two in
+    another; against the HALL-based passes and, for one step, the oracle."""
+    pk = _pk()
+    nq, reps = 14, 7
+    rng = np.random.default_rng(21)
+    psi = rng.standard_normal(1 << nq) + 1j * rng.standard_normal(1 << nq)
+    psi /= np.linalg.norm(psi)
+    marked = [8, 9, 10, 11, 12, 40, 47, 1000]
+    x = torch.from_numpy(psi).to("cuda")
+    _say("diffusion variant, %d marks, 5 in one block, n_q=%d" % (len(marked), nq))
+    a, La = pk.search_diffusion(nq, marked, reps, x)
+    plan = pk.Plan({"nq": nq, "gates": W.grover_gates(), "marked": marked})
+    b, Lb, _ = pk.evaluate_repeat(plan, x, reps)
+    torch.cuda.synchronize()
+    assert torch.linalg.vector_norm(a - b).item() <= 1e-12 * reps and abs(La.item() - Lb.item()) <= 1e-12 * reps
+    one, L1 = pk.search_diffusion(nq, marked, 1, x)
+    want, Lw, _ = O.evaluate(nq, W.grover_gates(), marked, psi)
+    assert np.linalg.norm(one.cpu().numpy() - want) <= 1e-13 and abs(L1.item() - Lw) <= 1e-13
+
+
 def test_diffusion_variant_rejects_bad_arguments():
     pk = _pk()
     x = _uniform(6)

@@ -969,8 +969,21 @@ __global__ void __launch_bounds__(256) reduce_kernel(const Reduction* red, int32
     const Reduction r = red[e];
     double* out = r.target == 0 ? L_out : (r.target == 1 ? norm_out : grad_out);
     if (!out) return;
+    // thread t adds partials t, t + 256, ... in that order; eight loads are issued
+    // before their adds so that their latencies overlap (same order, same result)
+    constexpr int kBatch = 8;
     double s = 0.0;
-    for (int64_t t = threadIdx.x; t < r.count; t += 256) s += ws[r.src + t];
+    for (int64_t t0 = threadIdx.x; t0 < r.count; t0 += 256 * kBatch) {
+        double v[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const int64_t t = t0 + 256 * j;
+            v[j] = t < r.count ? ws[r.src + t] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j)
+            if (t0 + 256 * j < r.count) s += v[j];
+    }
     const double tot = block_sum<256>(s, sred);
     if (threadIdx.x == 0) out[r.index] = tot;
 }

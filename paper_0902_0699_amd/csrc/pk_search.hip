@@ -87,12 +87,22 @@ template <typename T>
 __global__ void __launch_bounds__(kThreads) combine_kernel(const double2* part, int nparts, MarkedSet ms, T* state,
                                                            int64_t n, double2* mean, double* L, int mode) {
     using R = decltype(state[0].x);
-    // the partial sums: lane l adds parts l, l + 64, ..., then a butterfly (fixed order)
-    double2 s = {0.0, 0.0};
-    for (int b = threadIdx.x; b < nparts; b += 64) {
-        s.x += part[b].x;
-        s.y += part[b].y;
+    // the partial sums: lane l adds parts l, l + 64, ..., then a butterfly (fixed order);
+    // all of a lane's loads are issued before the first add, so their latencies overlap
+    constexpr int kPer = kGrid / 64;
+    double2 pv[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int b = threadIdx.x + 64 * j;
+        pv[j] = b < nparts ? part[b] : double2{0.0, 0.0};
     }
+    double2 s = {0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < kPer; ++j)
+        if (threadIdx.x + 64 * j < nparts) {
+            s.x += pv[j].x;
+            s.y += pv[j].y;
+        }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         s.x += __shfl_xor(s.x, off, 64);

@@ -580,14 +580,29 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
         const PK_CONST UPair* U = cptr(a.upairs) + P->upair_begin;
         for (int p = tid; p < nup; p += NT) {
             const PK_CONST PhaseOp* ph = cptr(a.phases) + U[p].first;
+            const int cnt = U[p].count;
             double c = 1.0, sn = 0.0;
-            for (int q = 0; q < U[p].count; ++q) {
-                const int64_t fm = ph[q].fmask;
-                if ((tile & fm) != fm) continue;
-                const double cq = 1.0 + ph[q].cm1, sq = ph[q].s;
-                const double x = c;
-                c = x * cq - sn * sq;
-                sn = x * sq + sn * cq;
+            // the table entries of eight phases are loaded before any is used, so
+            // their latencies overlap; the product keeps the phases' order
+            constexpr int kB = 8;
+            for (int q0 = 0; q0 < cnt; q0 += kB) {
+                int64_t fm[kB];
+                double cm1[kB], sq[kB];
+#pragma unroll
+                for (int j = 0; j < kB; ++j) {
+                    const bool in = q0 + j < cnt;
+                    fm[j] = in ? ph[q0 + j].fmask : 0;
+                    cm1[j] = in ? ph[q0 + j].cm1 : 0.0;
+                    sq[j] = in ? ph[q0 + j].s : 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < kB; ++j) {
+                    if (q0 + j >= cnt || (tile & fm[j]) != fm[j]) continue;
+                    const double cq = 1.0 + cm1[j];
+                    const double x = c;
+                    c = x * cq - sn * sq[j];
+                    sn = x * sq[j] + sn * cq;
+                }
             }
             ufac[2 * p] = c;
             ufac[2 * p + 1] = sn;

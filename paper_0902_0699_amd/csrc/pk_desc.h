@@ -12,6 +12,7 @@
 // applied to all partner pairs of a qubit at once, grouped so that the state
 // is read from HBM once per group of qubits instead of once per gate.
 #pragma once
+#include <stddef.h>
 #include <stdint.h>
 
 namespace pk {
@@ -84,7 +85,9 @@ enum StepBits : int32_t {
     ST_H2 = 128, ST_MAT_POST = 256, ST_MAT4 = 512, ST_D2B = 1024, ST_D4B = 2048, ST_SCALE = 4096, ST_READ = 8192,
 };
 
-struct Stage {
+// 16-byte aligned so that the slot table (phase_pm .. phase_upair) can be read as
+// four aligned 16-byte words.
+struct alignas(16) Stage {
     int32_t steps;            // StepBits of the steps below that are present
     int32_t rb[kMaxRegBits];  // local tile bit held by register bit a (-1 when unused)
     int32_t rbs[kMaxRegBits]; // the same bits sorted ascending (-1 entries last)
@@ -116,6 +119,10 @@ struct Stage {
     int32_t scale;            // 1: multiply by the pass scale
     int32_t read;             // flip index of a READ or -1
 };
+static_assert(offsetof(Stage, phase_pm) % 16 == 0 && offsetof(Stage, phase_cnt) == offsetof(Stage, phase_pm) + 16 &&
+                  offsetof(Stage, phase_ucnt) == offsetof(Stage, phase_pm) + 32 &&
+                  offsetof(Stage, phase_upair) == offsetof(Stage, phase_pm) + 48,
+              "slot table must be four consecutive aligned 16-byte words");
 
 // One amplitude addressed by (tile, local label) in a given pass.
 struct Flip {

@@ -333,17 +333,24 @@ __device__ __forceinline__ void apply_phases(const KArgs& a, const PK_CONST Stag
                                              const Layout& L, int64_t tile, const double* ufac) {
     using R = decltype(v[0][0].x);
     const PK_CONST PhaseOp* ph = cptr(a.phases) + S->phase_first;
+    // the sub-stage's slot table as four 16-byte loads issued together (reading the
+    // fields where they are used costs one scalar round trip per field and slot)
+    typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+    const i32x4 pms = *reinterpret_cast<const PK_CONST i32x4*>(S->phase_pm);
+    const i32x4 cnts = *reinterpret_cast<const PK_CONST i32x4*>(S->phase_cnt);
+    const i32x4 ucnts = *reinterpret_cast<const PK_CONST i32x4*>(S->phase_ucnt);
+    const i32x4 pairs = *reinterpret_cast<const PK_CONST i32x4*>(S->phase_upair);
 #pragma unroll
     for (int u = 0; u < kPhaseSlots; ++u) {
-        const int cnt = S->phase_cnt[u];
+        const int cnt = cnts[u];
         if (cnt == 0) continue;
         R c0 = 1, s0 = 0, c1 = 1, s1 = 0;
-        const int pair = S->phase_upair[u];
+        const int pair = pairs[u];
         if (pair >= 0) {
             c0 = (R)ufac[2 * pair];
             s0 = (R)ufac[2 * pair + 1];
         }
-        int q = S->phase_ucnt[u];
+        int q = ucnts[u];
 #pragma unroll 2
         for (; q + 1 < cnt; q += 2) {
             const int64_t fa = ph[q].fmask, fb = ph[q + 1].fmask;
@@ -371,7 +378,7 @@ __device__ __forceinline__ void apply_phases(const KArgs& a, const PK_CONST Stag
         }
         ph += cnt;
         const R c = c0 * c1 - s0 * s1, s = c0 * s1 + s0 * c1;
-        apply_slot<NV, NR>(v, S->phase_pm[u], c, s);
+        apply_slot<NV, NR>(v, pms[u], c, s);
     }
 }
 

@@ -123,6 +123,13 @@ static_assert(offsetof(Stage, phase_pm) % 16 == 0 && offsetof(Stage, phase_cnt) 
                   offsetof(Stage, phase_ucnt) == offsetof(Stage, phase_pm) + 32 &&
                   offsetof(Stage, phase_upair) == offsetof(Stage, phase_pm) + 48,
               "slot table must be four consecutive aligned 16-byte words");
+static_assert(offsetof(Stage, mat_pre_a) % 16 == 0 && offsetof(Stage, mat_pre) == offsetof(Stage, mat_pre_a) + 4 &&
+                  offsetof(Stage, hmask1) == offsetof(Stage, mat_pre_a) + 8 &&
+                  offsetof(Stage, flip_mid) == offsetof(Stage, mat_pre_a) + 12 &&
+                  offsetof(Stage, hmask2) == offsetof(Stage, mat_pre_a) + 16 &&
+                  offsetof(Stage, mat_post_a) == offsetof(Stage, mat_pre_a) + 20 &&
+                  offsetof(Stage, mat_post) == offsetof(Stage, mat_pre_a) + 24,
+              "one-qubit step parameters must be two consecutive aligned 16-byte words");
 
 // One amplitude addressed by (tile, local label) in a given pass.
 struct Flip {

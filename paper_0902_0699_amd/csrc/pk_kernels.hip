@@ -619,6 +619,13 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
     for (int s = 0; s < C.nstages; ++s, ++S) {
         // one scalar word says which steps follow; only their parameters are loaded
         const int steps = S->steps;
+        // the one-qubit steps' parameters (mat_pre_a .. mat_post) in two 16-byte loads
+        // issued with the step word, not one scalar round trip per step
+        typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+        const i32x4 sp0 = *reinterpret_cast<const PK_CONST i32x4*>(&S->mat_pre_a);
+        const i32x4 sp1 = *reinterpret_cast<const PK_CONST i32x4*>(&S->hmask2);
+        const int mat_pre_a = sp0.x, mat_pre = sp0.y, hmask1 = sp0.z, flip_mid = sp0.w;
+        const int hmask2 = sp1.x, mat_post_a = sp1.y, mat_post = sp1.z;
         if (s > 0 && (steps & ST_EXCHANGE)) {
             // ---- LDS exchange: previous layout out, this layout in
             const Layout Ln = (s == C.nstages - 1) ? C.Ll : make_layout<(int)sizeof(R) * 2>(S, C.nrb, tid);
@@ -647,20 +654,20 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
         if ((steps & ST_PHASE) && active) apply_phases<NV, NR>(a, S, v, L, tile, ufac);
         if (steps & ST_MAT_PRE) {
             R m[8];
-            const PK_CONST double* mp = cptr(a.mats) + 8 * S->mat_pre;
+            const PK_CONST double* mp = cptr(a.mats) + 8 * mat_pre;
 #pragma unroll
             for (int e = 0; e < 8; ++e) m[e] = (R)mp[e];
-            apply_mat<NV, NR>(v, S->mat_pre_a, m);
+            apply_mat<NV, NR>(v, mat_pre_a, m);
         }
-        if (steps & ST_H1) apply_hmask<NV, NR>(v, S->hmask1);
-        if (steps & ST_FLIP_MID) element_op<NV, NR, 0>(a, v, L, S->flip_mid, tile, nreg, active);
-        if (steps & ST_H2) apply_hmask<NV, NR>(v, S->hmask2);
+        if (steps & ST_H1) apply_hmask<NV, NR>(v, hmask1);
+        if (steps & ST_FLIP_MID) element_op<NV, NR, 0>(a, v, L, flip_mid, tile, nreg, active);
+        if (steps & ST_H2) apply_hmask<NV, NR>(v, hmask2);
         if (steps & ST_MAT_POST) {
             R m[8];
-            const PK_CONST double* mp = cptr(a.mats) + 8 * S->mat_post;
+            const PK_CONST double* mp = cptr(a.mats) + 8 * mat_post;
 #pragma unroll
             for (int e = 0; e < 8; ++e) m[e] = (R)mp[e];
-            apply_mat<NV, NR>(v, S->mat_post_a, m);
+            apply_mat<NV, NR>(v, mat_post_a, m);
         }
         if ((steps & ST_MAT4) && active) op_mat4<NV, NR>(v, cptr(a.mats4) + 32 * S->mat4);
         if constexpr (NV == 2) {

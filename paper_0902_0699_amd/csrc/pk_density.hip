@@ -11,10 +11,12 @@
 // is written as such.
 //
 // Tiling: a workgroup of four waves owns a 64 x 64 block of rho.  The universes
-// are consumed 16 at a time: the block's 64 row labels and 64 column labels of
-// those 16 states are staged in LDS as separate real and imaginary planes (the
+// are consumed 8 at a time: the block's 64 row labels and 64 column labels of
+// those 8 states are staged in LDS as separate real and imaginary planes (the
 // row side already multiplied by P_a), and each wave then runs the MFMA chain
 // for its 32 x 32 quarter, four 16 x 16 tiles, re and im accumulators each.
+// Eight universes per stage keep the kernel within 128 VGPRs, so four waves
+// share each SIMD's matrix pipe (16 per stage allowed three).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -28,13 +30,13 @@ namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int kBM = 64;         // block of rho (rows and columns)
-constexpr int kKC = 16;         // universes per LDS stage
+constexpr int kKC = 8;          // universes per LDS stage
 constexpr int kLd = kBM + 2;    // LDS row length in doubles (padding spreads the rows over banks)
 constexpr int kThreads = 256;
 
 // v_mfma_f64_16x16x4f64 lane layout: lane l holds A[l % 16][l / 16] and
 // B[l / 16][l % 16]; accumulator register r of lane l is D[4 r + l / 16][l % 16].
-__global__ void __launch_bounds__(kThreads) density_kernel(const double2* C, const double* P, double2* rho,
+__global__ void __launch_bounds__(kThreads, 4) density_kernel(const double2* C, const double* P, double2* rho,
                                                            int64_t N, int A) {
     __shared__ double sAx[kKC][kLd], sAy[kKC][kLd], sBx[kKC][kLd], sBy[kKC][kLd];
     // block (bi, bj) with bi >= bj from the linear index

@@ -138,21 +138,24 @@ def test_c4_gradient_full_size_against_finite_differences():
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_shor_path_full_size(prec):
-    """Shor's data path at n_q = 30 (M = 899: n1 = 20, n2 = 10) in the launch
-    configuration bench.py times: load (Eq. Shor2), QFT of register one (App. A),
-    marginal.  Every p(n) against Eq. probshor; amplitudes at sampled labels (half
-    of them on the support of the state) against the direct sum of Eq. QFT1."""
+@pytest.mark.parametrize("prec,tile", [("fp64", None), ("fp64", 12), ("fp32", None), ("fp32", 12)])
+def test_shor_path_full_size(prec, tile):
+    """Shor's data path at n_q = 30 (M = 899: n1 = 20, n2 = 10) at the default tile
+    and at the 2^12 tile the autotuner picks in bench.py: load (Eq. Shor2), QFT of
+    register one (App. A), marginal.  Every p(n) against Eq. probshor; amplitudes at
+    sampled labels (half of them on the support of the state) against the direct
+    sum of Eq. QFT1."""
     from paper_0902_0699_amd import paperkern as pk
 
     M = W.SHOR_M
     x = W.shor_xguess(W.SEEDS["shor"])
     n1, n2 = pk.shor_register_sizes(M)
     nq = n1 + n2
-    _say("full size Shor path: M=%d x=%d n1=%d n2=%d %s" % (M, x, n1, n2, prec))
+    _say("full size Shor path: M=%d x=%d n1=%d n2=%d %s tile %s" % (M, x, n1, n2, prec, tile))
     psi = pk.shor_state(n1, n2, x, M, prec=prec)
     plan = pk.Plan({"nq": nq, "gates": [("QFT", 1, n1)], "marked": []}, prec=prec)
+    if tile is not None:
+        plan.set_tiling(tile, 4, 1)
     pk.evaluate(plan, psi, out=psi, want_norm=False)
     p = pk.marginal(psi, nq, n2).cpu().numpy()
     rng = np.random.default_rng(2024)

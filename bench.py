@@ -341,6 +341,36 @@ def shor_run(torch, pk, W, autotune, steps, prec):
            "marginal_GBs": esz * N / (parts[2] * 1e-3) / 1e9, "sum_p_minus_1": sum_p - 1.0}
     log("shor %s: load %.2f ms, QFT %.2f ms (%d passes), marginal %.2f ms"
         % (prec, parts[0], parts[1], plan.passes(), parts[2]))
+    # A labelled variant, not the paper's circuit: the QFT without its final pair
+    # swaps and the marginal read with register one's bits reversed (same p(n)).
+    p_ref = p.clone()
+    plan2 = pk.Plan({"nq": nq, "gates": [("QFT_NOSWAP", 1, n1)], "marked": []}, prec=prec)
+    pk.shor_state(n1, n2, x, M, prec=prec, out=psi)
+    best2, _ = autotune.tune(plan2, lambda: pk.evaluate_into(plan2, psi, psi, L), op="eval", use_cache=False)
+
+    def run2(ev):
+        ev[0].record()
+        pk.shor_state(n1, n2, x, M, prec=prec, out=psi)
+        ev[1].record()
+        pk.evaluate_into(plan2, psi, psi, L)
+        ev[2].record()
+        pk.marginal(psi, nq, n2, out=p, bitrev=True)
+        ev[3].record()
+
+    parts2 = np.zeros(3)
+    for _ in range(steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        run2(ev)
+        torch.cuda.synchronize()
+        parts2 += [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
+    parts2 /= steps
+    out["noswap_variant"] = {
+        "method": "QFT without the final pair swaps, marginal with register one bit-reversed (not the paper's circuit)",
+        "ms": float(parts2.sum()), "qft_ms": parts2[1], "qft_passes": plan2.passes(), "marginal_ms": parts2[2],
+        "qft_tiling": {k: best2[k] for k in ("tile_bits", "carrier_bits", "reg_bits")},
+        "max_abs_dp_vs_paper_form": float((p - p_ref).abs().max().item())}
+    log("shor %s, no-swap variant: QFT %.2f ms (%d passes), whole path %.2f ms"
+        % (prec, parts2[1], plan2.passes(), parts2.sum()))
     del psi
     return out
 

@@ -72,6 +72,10 @@ extern "C" {
                              register's value with qubit is1 most significant (App. A).  Lowered
                              to the circuit of App. A: Hadamards, CPHASEK(q, ic, q + 1 - ic) and
                              the pair swaps that restore standard order                         */
+#define PK_GATE_QFT_NOSWAP 13 /* a labelled variant, not the paper's circuit: PK_GATE_QFT without the
+                             final pair swaps, so the register comes out with its qubit order
+                             reversed (amplitude of value n at the bit-reversed value).  Read
+                             register one's distribution with pk_marginal_bitrev              */
 
 /* ---- workspace queries ----------------------------------------------------------- */
 #define PK_OP_EVAL 0
@@ -319,6 +323,15 @@ int pk_shor_state(int32_t n1, int32_t n2, int64_t xguess, int64_t M, int32_t pre
  * PK_EINVAL for nq out of range, n_low outside 0..nq, NULL or misaligned pointers.
  */
 int pk_marginal(int32_t nq, int32_t n_low, int32_t prec, const void* psi, double* p, void* stream);
+
+/*
+ * pk_marginal_bitrev -- pk_marginal with the high register read in reversed qubit
+ * order: p[rev(n)] = sum_{k < 2^n_low} |psi[n * 2^n_low + k]|^2, rev reversing the
+ * nq - n_low bits of n.  After PK_GATE_QFT_NOSWAP on the high register this is the
+ * distribution that pk_marginal gives after PK_GATE_QFT (Step 6 of Sec. 5.2) with
+ * one pass fewer.  Same sums, order, arguments and errors as pk_marginal.
+ */
+int pk_marginal_bitrev(int32_t nq, int32_t n_low, int32_t prec, const void* psi, double* p, void* stream);
 
 /*
  * pk_density_matrix -- the ensemble density matrix of Sec. 6.1:

@@ -619,14 +619,24 @@ int pk_shor_state(int32_t n1, int32_t n2, int64_t xguess, int64_t M, int32_t pre
     return e == hipSuccess ? PK_OK : hip_fail(nullptr, e, "shor_state_kernel");
 }
 
-int pk_marginal(int32_t nq, int32_t n_low, int32_t prec, const void* psi, double* p, void* stream) {
+namespace {
+int marginal_entry(int32_t nq, int32_t n_low, int32_t prec, bool bitrev, const void* psi, double* p, void* stream) {
     if (prec != PK_FP64 && prec != PK_FP32) return fail(nullptr, PK_EINVAL, "prec must be PK_FP64 or PK_FP32");
     if (nq < 1 || nq > (prec == PK_FP64 ? 30 : 31)) return fail(nullptr, PK_EINVAL, "nq out of range");
     if (n_low < 0 || n_low > nq) return fail(nullptr, PK_EINVAL, "n_low out of 0..nq");
     if (!psi || !p || (reinterpret_cast<uintptr_t>(psi) & 15) || (reinterpret_cast<uintptr_t>(p) & 7))
         return fail(nullptr, PK_EINVAL, "NULL or misaligned pointer");
-    hipError_t e = launch_marginal(nq, n_low, prec == PK_FP64, psi, p, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_marginal(nq, n_low, prec == PK_FP64, bitrev, psi, p, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? PK_OK : hip_fail(nullptr, e, "marginal_kernel");
+}
+}  // namespace
+
+int pk_marginal(int32_t nq, int32_t n_low, int32_t prec, const void* psi, double* p, void* stream) {
+    return marginal_entry(nq, n_low, prec, false, psi, p, stream);
+}
+
+int pk_marginal_bitrev(int32_t nq, int32_t n_low, int32_t prec, const void* psi, double* p, void* stream) {
+    return marginal_entry(nq, n_low, prec, true, psi, p, stream);
 }
 
 int pk_density_matrix(int32_t nq, int32_t n_univ, const void* states, const double* weights, void* rho,

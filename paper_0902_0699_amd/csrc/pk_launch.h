@@ -80,7 +80,7 @@ hipError_t launch_pairs(int nq, int i_s, int64_t first, int64_t count, int64_t* 
 // over the n_low low qubits.
 hipError_t launch_shor_state(int n1, int n2, uint64_t x, uint64_t M, bool fp64, double amp, void* psi,
                              hipStream_t st);
-hipError_t launch_marginal(int nq, int n_low, bool fp64, const void* psi, double* p, hipStream_t st);
+hipError_t launch_marginal(int nq, int n_low, bool fp64, bool bitrev, const void* psi, double* p, hipStream_t st);
 // The ensemble density matrix (pk_density.hip): rho = sum_a P_a C_a C_a^H for A
 // universe states of N amplitudes (rows of C), and the entropy / purity sums of
 // a spectrum.

@@ -938,7 +938,7 @@ int compile_plan(Plan* plan, const pk_problem* probs, int n_inst, int prec, std:
             const pk_gate& gt = p.gates[g];
             const bool two = gt.kind == PK_GATE_TWOOP || gt.kind == PK_GATE_CNOT || gt.kind == PK_GATE_CPHASE ||
                              gt.kind == PK_GATE_CPHASEK || gt.kind == PK_GATE_SWAP || gt.kind == PK_GATE_D4;
-            if (gt.kind == PK_GATE_QFT) {
+            if (gt.kind == PK_GATE_QFT || gt.kind == PK_GATE_QFT_NOSWAP) {
                 if (gt.is2 != 0 || gt.k < 1 || gt.is1 < 1 || gt.is1 + gt.k - 1 > p.nq) {
                     *err = fmt("instance %lld gate %lld: QFT needs qubits is1 .. is1+k-1 within 1..nq and is2 = 0", i, g);
                     return PK_EINVAL;
@@ -1037,18 +1037,21 @@ int compile_plan(Plan* plan, const pk_problem* probs, int n_inst, int prec, std:
                                              gt.kind == PK_GATE_SWAP ? Prim::GSWAP : Prim::GMAT4));
                 break;
             }
-            case PK_GATE_QFT: {
+            case PK_GATE_QFT:
+            case PK_GATE_QFT_NOSWAP: {
                 // the circuit of App. A on the register of qubits is1 .. is1+k-1: per qubit
                 // ic a Hadamard, then CPHASEK between ic and every later qubit q with
                 // exponent q + 1 - ic (register labels); the last Hadamard; the pair
-                // swaps (i, k + 1 - i) that restore standard order
+                // swaps (i, k + 1 - i) that restore standard order (not in the variant
+                // that leaves the register bit-reversed)
                 const int o = gt.is1 - 1, n1 = gt.k;
                 for (int ic = 1; ic <= n1; ++ic) {
                     in.prims.push_back({Prim::GATE, p.nq - (o + ic), Prim::GH, 0});
                     for (int q = ic + 1; q <= n1; ++q) in.prims.push_back(phase_prim(p.nq, o + q, o + ic, q + 1 - ic));
                 }
-                for (int q = 1; q <= n1 / 2; ++q)
-                    in.prims.push_back(mat4_prim(plan, p.nq, o + q, o + n1 + 1 - q, kSwap4, Prim::GSWAP));
+                if (gt.kind == PK_GATE_QFT)
+                    for (int q = 1; q <= n1 / 2; ++q)
+                        in.prims.push_back(mat4_prim(plan, p.nq, o + q, o + n1 + 1 - q, kSwap4, Prim::GSWAP));
                 break;
             }
             case PK_GATE_D4:

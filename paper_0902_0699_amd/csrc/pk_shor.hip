@@ -80,8 +80,16 @@ __device__ __forceinline__ double wave_sum(double v) {
 //                  groups of L lanes with butterflies;
 //   64 < L < 2^14  one wave per segment, lanes striding by 64;
 //   L >= 2^14      one workgroup per segment, then a workgroup reduction.
+// Where segment s's sum goes: s, or s with its nh bits reversed (the register read
+// in the opposite qubit order).
+__device__ __forceinline__ int64_t out_index(int64_t s, int nh, bool bitrev) {
+    if (!bitrev || nh == 0) return s;
+    return (int64_t)(__brevll((unsigned long long)s) >> (64 - nh));
+}
+
 template <typename T>
-__global__ void __launch_bounds__(kThreads) marginal_kernel(const T* psi, double* p, int nl, int64_t nseg) {
+__global__ void __launch_bounds__(kThreads) marginal_kernel(const T* psi, double* p, int nl, int64_t nseg, int nh,
+                                                            bool bitrev) {
     __shared__ double red[kThreads / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     constexpr int nw = kThreads / 64;
@@ -93,7 +101,7 @@ __global__ void __launch_bounds__(kThreads) marginal_kernel(const T* psi, double
             const int64_t e = base + lane;
             double v = e < total ? norm2(psi[e]) : 0.0;
             for (int off = 1; off < L; off <<= 1) v += __shfl_xor(v, off, 64);
-            if ((lane & (L - 1)) == 0 && e < total) p[e >> nl] = v;
+            if ((lane & (L - 1)) == 0 && e < total) p[out_index(e >> nl, nh, bitrev)] = v;
         }
     } else if (nl < 14) {
         for (int64_t s = (int64_t)blockIdx.x * nw + wave; s < nseg; s += (int64_t)gridDim.x * nw) {
@@ -104,7 +112,7 @@ __global__ void __launch_bounds__(kThreads) marginal_kernel(const T* psi, double
                 a1 += norm2(q[j + 64]);
             }
             const double v = wave_sum(a0 + a1);
-            if (lane == 0) p[s] = v;
+            if (lane == 0) p[out_index(s, nh, bitrev)] = v;
         }
     } else {
         for (int64_t s = blockIdx.x; s < nseg; s += gridDim.x) {
@@ -122,7 +130,7 @@ __global__ void __launch_bounds__(kThreads) marginal_kernel(const T* psi, double
             if (threadIdx.x == 0) {
                 double t = 0.0;
                 for (int w = 0; w < nw; ++w) t += red[w];
-                p[s] = t;
+                p[out_index(s, nh, bitrev)] = t;
             }
             __syncthreads();
         }
@@ -160,7 +168,7 @@ hipError_t launch_shor_state(int n1, int n2, uint64_t x, uint64_t M, bool fp64, 
     return hipGetLastError();
 }
 
-hipError_t launch_marginal(int nq, int nl, bool fp64, const void* psi, double* p, hipStream_t st) {
+hipError_t launch_marginal(int nq, int nl, bool fp64, bool bitrev, const void* psi, double* p, hipStream_t st) {
     const int64_t nseg = (int64_t)1 << (nq - nl);
     int64_t blocks;
     if (nl <= 6)
@@ -172,10 +180,10 @@ hipError_t launch_marginal(int nq, int nl, bool fp64, const void* psi, double* p
     const unsigned grid = grid_for(blocks);
     if (fp64)
         hipLaunchKernelGGL(marginal_kernel<double2>, dim3(grid), dim3(kThreads), 0, st,
-                           static_cast<const double2*>(psi), p, nl, nseg);
+                           static_cast<const double2*>(psi), p, nl, nseg, nq - nl, bitrev);
     else
         hipLaunchKernelGGL(marginal_kernel<float2>, dim3(grid), dim3(kThreads), 0, st,
-                           static_cast<const float2*>(psi), p, nl, nseg);
+                           static_cast<const float2*>(psi), p, nl, nseg, nq - nl, bitrev);
     return hipGetLastError();
 }
 

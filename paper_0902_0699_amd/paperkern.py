@@ -24,7 +24,7 @@ PK_OK, PK_EINVAL, PK_ENOMEM, PK_EDEVICE, PK_EUNSUPPORTED = 0, -1, -2, -3, -4
 PK_FP64, PK_FP32 = 0, 1
 PK_OP_EVAL, PK_OP_BACKWARD = 0, 1
 GATE_KINDS = {"ONEOP": 0, "H": 1, "HALL": 2, "ORACLE": 3, "INV": 4, "D2": 5,
-              "TWOOP": 6, "CNOT": 7, "CPHASE": 8, "CPHASEK": 9, "SWAP": 10, "D4": 11, "QFT": 12}
+              "TWOOP": 6, "CNOT": 7, "CPHASE": 8, "CPHASEK": 9, "SWAP": 10, "D4": 11, "QFT": 12, "QFT_NOSWAP": 13}
 TWO_QUBIT = ("TWOOP", "CNOT", "CPHASE", "CPHASEK", "SWAP", "D4")
 
 # Entry points declared in include/paperkern.h with their ctypes signatures.
@@ -59,6 +59,7 @@ SIGNATURES = {
     "pk_pair_indices": (ctypes.c_int, [_c_int32, _c_int32, _c_int64, _c_int64, _vp, _vp, _vp]),
     "pk_shor_state": (ctypes.c_int, [_c_int32, _c_int32, _c_int64, _c_int64, _c_int32, _vp, _vp]),
     "pk_marginal": (ctypes.c_int, [_c_int32, _c_int32, _c_int32, _vp, _vp, _vp]),
+    "pk_marginal_bitrev": (ctypes.c_int, [_c_int32, _c_int32, _c_int32, _vp, _vp, _vp]),
     "pk_density_matrix": (ctypes.c_int, [_c_int32, _c_int32, _vp, _vp, _vp, _vp]),
     "pk_search_diffusion": (ctypes.c_int, [_c_int32, _c_int32, _vp, _c_int32, _c_int64, _vp, _vp, _vp, _vp, _vp]),
     "pk_search_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(_c_int64)]),
@@ -125,7 +126,7 @@ def make_gate(g, nq=None):
                 pg.op[2 * (4 * a + b) + 1] = op[a, b].imag
     if kind == "CPHASEK":
         pg.k = int(g[3])
-    if kind == "QFT":  # ("QFT", first qubit, register size)
+    if kind in ("QFT", "QFT_NOSWAP"):  # (kind, first qubit, register size)
         pg.is1 = int(g[1])
         pg.k = int(g[2])
     if kind in ("D2", "D4"):
@@ -428,15 +429,17 @@ def shor_state(n1, n2, xguess, M, prec="fp64", out=None, device="cuda"):
     return out
 
 
-def marginal(psi, nq, n_low, out=None):
-    """p[n] = sum over the n_low low qubits of |psi|^2 (pk_marginal), FP64 on the device."""
+def marginal(psi, nq, n_low, out=None, bitrev=False):
+    """p[n] = sum over the n_low low qubits of |psi|^2 (pk_marginal), FP64 on the device;
+    with ``bitrev`` the high register is read in reversed qubit order (pk_marginal_bitrev)."""
     import torch
     if psi.dtype not in (torch.complex128, torch.complex64) or psi.numel() != (1 << nq) or not psi.is_contiguous():
         raise ValueError("psi must be a contiguous complex tensor of 2^nq amplitudes")
     if out is None:
         out = torch.empty(1 << (nq - n_low) if 0 <= n_low <= nq else 1, dtype=torch.float64, device=psi.device)
     prec = PK_FP64 if psi.dtype == torch.complex128 else PK_FP32
-    rc = lib().pk_marginal(nq, n_low, prec, _ptr(psi), _ptr(out), _stream(psi.device))
+    fn = lib().pk_marginal_bitrev if bitrev else lib().pk_marginal
+    rc = fn(nq, n_low, prec, _ptr(psi), _ptr(out), _stream(psi.device))
     _check(rc, None)
     return out
 

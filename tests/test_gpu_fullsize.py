@@ -177,6 +177,43 @@ def test_shor_path_full_size(prec, tile):
 
 
 @pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_shor_noswap_variant_full_size(prec):
+    """The labelled no-swap variant at n_q = 30 at the 2^12 tile: QFT_NOSWAP on
+    register one and the bit-reversed marginal.  Every p(n) against Eq. probshor;
+    sampled amplitudes against the direct sum of Eq. QFT1 at the bit-reversed
+    register value."""
+    from paper_0902_0699_amd import paperkern as pk
+
+    M = W.SHOR_M
+    x = W.shor_xguess(W.SEEDS["shor"])
+    n1, n2 = pk.shor_register_sizes(M)
+    nq = n1 + n2
+    _say("full size Shor path, no-swap variant: M=%d x=%d n1=%d n2=%d %s" % (M, x, n1, n2, prec))
+    psi = pk.shor_state(n1, n2, x, M, prec=prec)
+    plan = pk.Plan({"nq": nq, "gates": [("QFT_NOSWAP", 1, n1)], "marked": []}, prec=prec)
+    plan.set_tiling(12, 4, 1)
+    pk.evaluate(plan, psi, out=psi, want_norm=False)
+    p = pk.marginal(psi, nq, n2, bitrev=True).cpu().numpy()
+    rng = np.random.default_rng(2025)
+    labels = np.unique(rng.integers(0, 1 << nq, 4096))
+    got = psi[torch.from_numpy(labels).to("cuda")].cpu().numpy().astype(np.complex128)
+    del psi
+    torch.cuda.empty_cache()
+    r = labels >> n2
+    rr = np.zeros_like(r)
+    for b in range(n1):
+        rr |= ((r >> b) & 1) << (n1 - 1 - b)
+    want_a = O.shor_qft_amplitudes(n1, n2, x, M, (rr << n2) | (labels & ((1 << n2) - 1)))
+    want_p = O.probshor_marginal(n1, x, M)
+    tol = TOL64 if prec == "fp64" else TOL32
+    ep = float(np.max(np.abs(p - want_p)) / np.max(want_p))
+    ea = float(np.max(np.abs(got - want_a)) / np.max(np.abs(want_a)))
+    _say("  passes %d  max |dp|/max p %.3e  max |dC|/max |C| %.3e" % (plan.passes(), ep, ea))
+    assert plan.passes() == 3 and ep <= tol and ea <= tol
+
+
+@pytest.mark.timeout(900)
 def test_density_matrix_full_size():
     """The ensemble density matrix (Sec. 6.1) in the configuration bench.py times:
     4096 noisy Grover universes at n_q = 12 from the library's batched launch,

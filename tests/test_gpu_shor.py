@@ -240,3 +240,71 @@ def test_shor_path_against_probshor(M, x, prec):
     got = psi[torch.from_numpy(labels).to("cuda")].cpu().numpy().astype(np.complex128)
     amp = O.shor_qft_amplitudes(n1, n2, x, M, labels)
     assert np.max(np.abs(got - amp)) <= tol * max(np.max(np.abs(amp)), 1.0 / (1 << n1))
+
+
+# --------------------------------------------------------------------------- the no-swap variant
+
+
+def _bitrev(v, nbits):
+    v = np.asarray(v, dtype=np.int64)
+    out = np.zeros_like(v)
+    for b in range(nbits):
+        out |= ((v >> b) & 1) << (nbits - 1 - b)
+    return out
+
+
+@pytest.mark.parametrize("nq,n1,prec", [(10, 7, "fp64"), (16, 11, "fp64"), (13, 13, "fp64"), (14, 9, "fp32")])
+def test_qft_noswap_is_the_qft_with_the_register_reversed(nq, n1, prec):
+    """The labelled variant QFT_NOSWAP (the App. A ladder without its pair swaps)
+    leaves the register's qubit order reversed: its amplitude at register value r
+    is the QFT's at rev(r).  Against the oracle's DFT with that permutation, and
+    never more passes than the full QFT."""
+    pk = _pk()
+    rng = np.random.default_rng(3 * nq + n1)
+    psi = _state(rng, nq)
+    if prec == "fp32":
+        psi = psi.astype(np.complex64).astype(np.complex128)
+    _say("QFT_NOSWAP n_q=%d n1=%d %s" % (nq, n1, prec))
+    plan, got, _ = _eval({"nq": nq, "gates": [("QFT_NOSWAP", 1, n1)], "marked": []}, psi, prec=prec)
+    full = pk.Plan({"nq": nq, "gates": [("QFT", 1, n1)], "marked": []}, prec=prec)
+    want = O.qft_register(psi, nq, 1, n1)
+    idx = np.arange(1 << nq, dtype=np.int64)
+    lowbits = nq - n1
+    perm = (_bitrev(idx >> lowbits, n1) << lowbits) | (idx & ((1 << lowbits) - 1))
+    err = _relerr(got, want[perm])
+    _say("  passes %d (full QFT %d)  normwise err %.3e" % (plan.passes(), full.passes(), err))
+    assert err <= (TOL64 if prec == "fp64" else TOL32) and plan.passes() <= full.passes()
+
+
+@pytest.mark.parametrize("nq,n_low", [(12, 0), (12, 3), (12, 7), (16, 14), (15, 15), (18, 4)])
+def test_marginal_bitrev_permutes_the_marginal_exactly(nq, n_low):
+    """pk_marginal_bitrev writes the same sums as pk_marginal (same terms, same
+    order) at the bit-reversed register index: equal bit for bit after the
+    permutation."""
+    pk = _pk()
+    rng = np.random.default_rng(nq * 7 + n_low)
+    x = torch.from_numpy(_state(rng, nq)).to("cuda")
+    _say("marginal_bitrev n_q=%d n_low=%d" % (nq, n_low))
+    p = pk.marginal(x, nq, n_low).cpu().numpy()
+    pr = pk.marginal(x, nq, n_low, bitrev=True).cpu().numpy()
+    nh = nq - n_low
+    np.testing.assert_array_equal(pr[_bitrev(np.arange(1 << nh), nh)], p)
+
+
+@pytest.mark.parametrize("M,x,prec", [(15, 7, "fp64"), (21, 2, "fp64"), (55, 2, "fp64"), (39, 7, "fp32")])
+def test_shor_path_noswap_variant_against_probshor(M, x, prec):
+    """Load, QFT_NOSWAP on register one, the bit-reversed marginal: the
+    distribution of Eq. probshor, as with the full QFT."""
+    pk = _pk()
+    n1, n2 = pk.shor_register_sizes(M)
+    n1 = min(n1, 20 - n2)
+    nq = n1 + n2
+    _say("Shor path, no-swap variant, M=%d x=%d n1=%d n2=%d %s" % (M, x, n1, n2, prec))
+    psi = pk.shor_state(n1, n2, x, M, prec=prec)
+    plan = pk.Plan({"nq": nq, "gates": [("QFT_NOSWAP", 1, n1)], "marked": []}, prec=prec)
+    pk.evaluate(plan, psi, out=psi, want_norm=False)
+    p = pk.marginal(psi, nq, n2, bitrev=True)
+    torch.cuda.synchronize()
+    tol = TOL64 if prec == "fp64" else TOL32
+    want = O.probshor_marginal(n1, x, M)
+    assert np.max(np.abs(p.cpu().numpy() - want)) <= tol * np.max(want)

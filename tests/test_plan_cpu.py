@@ -496,6 +496,9 @@ def test_shor_marginal_density_search_entry_points_reject_bad_arguments():
     _einval(lib.pk_marginal(12, 13, pk.PK_FP64, buf, buf, None), "n_low")
     _einval(lib.pk_marginal(31, 3, pk.PK_FP64, buf, buf, None), "nq")
     _einval(lib.pk_marginal(12, 3, pk.PK_FP64, None, buf, None), "NULL")
+    _einval(lib.pk_marginal_bitrev(12, 13, pk.PK_FP64, buf, buf, None), "n_low")
+    _einval(lib.pk_marginal_bitrev(12, 3, 7, buf, buf, None), "prec")
+    _einval(lib.pk_marginal_bitrev(12, 3, pk.PK_FP64, buf, None, None), "NULL")
     _einval(lib.pk_density_matrix(17, 4, buf, buf, buf, None), "nq")
     _einval(lib.pk_density_matrix(8, 0, buf, buf, buf, None), "universe")
     _einval(lib.pk_density_spectrum(16, buf, buf, buf, None), "nq")
@@ -515,3 +518,17 @@ def test_evaluate_repeat_rejects_bad_reps_before_the_device():
     batch = pk.Plan([{"nq": 4, "gates": [], "marked": []}] * 2)
     rc = pk.lib().pk_evaluate_repeat(batch.handle, 3, buf, buf, buf, None, None, buf, None)
     assert rc == pk.PK_EINVAL and "single-instance" in pk.lib().pk_last_error(batch.handle).decode()
+
+
+def test_qft_noswap_lowers_to_the_ladder_without_swaps():
+    """QFT_NOSWAP (a labelled variant) is the App. A ladder minus its pair swaps:
+    at n_q = 30 with a 20-qubit register it needs 3 passes where the full QFT needs
+    4, and it keeps the full QFT's validation."""
+    full = pk.Plan({"nq": 30, "gates": [("QFT", 1, 20)], "marked": []})
+    nosw = pk.Plan({"nq": 30, "gates": [("QFT_NOSWAP", 1, 20)], "marked": []})
+    assert full.passes() == 4 and nosw.passes() == 3
+    gates = lambda d: sum(len(p["stages"]) for p in d["instances"][0]["forward"])
+    assert gates(nosw.describe()) <= gates(full.describe())
+    for bad in ([("QFT_NOSWAP", 0, 3)], [("QFT_NOSWAP", 5, 7)], [("QFT_NOSWAP", 1, 0)]):
+        with pytest.raises(pk.PaperkernError):
+            pk.Plan({"nq": 10, "gates": bad, "marked": []})

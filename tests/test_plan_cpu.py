@@ -532,3 +532,24 @@ def test_qft_noswap_lowers_to_the_ladder_without_swaps():
     for bad in ([("QFT_NOSWAP", 0, 3)], [("QFT_NOSWAP", 5, 7)], [("QFT_NOSWAP", 1, 0)]):
         with pytest.raises(pk.PaperkernError):
             pk.Plan({"nq": 10, "gates": bad, "marked": []})
+
+
+@pytest.mark.parametrize("nq,n1,tiling", [(8, 5, None), (12, 8, (6, 2, 1)), (11, 7, (5, 1, 1)), (10, 10, (4, 0, 0))])
+def test_qft_noswap_schedule_matches_the_permuted_dft(nq, n1, tiling):
+    """The CPU emulation of a QFT_NOSWAP schedule equals the oracle's DFT of the
+    register with the register's qubit order reversed."""
+    rng = np.random.default_rng(7 * nq + n1)
+    prob = {"nq": nq, "gates": [("QFT_NOSWAP", 1, n1)], "marked": []}
+    psi = _state(rng, nq)
+    plan = pk.Plan(prob)
+    if tiling:
+        plan.set_tiling(*tiling)
+    got, _ = run_forward([prob], plan.describe(), 0, psi)
+    want = O.qft_register(psi, nq, 1, n1)
+    idx = np.arange(1 << nq)
+    low = nq - n1
+    reg = idx >> low
+    rev = np.zeros_like(reg)
+    for b in range(n1):
+        rev |= ((reg >> b) & 1) << (n1 - 1 - b)
+    np.testing.assert_allclose(got, want[(rev << low) | (idx & ((1 << low) - 1))], rtol=0, atol=1e-12)

@@ -50,7 +50,8 @@ __all__ = [
     "grover_gates", "apply_gate", "apply_gate_adjoint", "evaluate",
     "readout", "adjoint_grad", "fd_grad_angles", "fd_grad_psi",
     "kron_operator", "dense_circuit",
-    "grover_closed_form", "diffusion_closed_form", "grover_sampled",
+    "grover_closed_form", "diffusion_closed_form", "grover_sampled", "grover_sampler",
+    "adjoint_gates",
     "CNOT", "CPHASE", "SWAP", "cphasek", "apply_twoop", "apply_twoop_loop",
     "wigner_small_d", "wigner_small_d_prime", "wigner_d", "d4_matrix", "d4_derivatives",
     "kron_twoop", "TWO_QUBIT", "PARAMETRIC",
@@ -647,11 +648,31 @@ def diffusion_closed_form(psi):
     return 2.0 * psi.mean() - psi
 
 
-def grover_sampled(nq, gates, marked, psi_in, indices):
-    """Exact amplitudes of one Grover iteration at chosen labels, for any n_q.
+def adjoint_gates(gates):
+    """The gate list of U^dagger for the list of U: the gates in reverse order, each
+    replaced by its Hermitian adjoint.  HALL, ORACLE and INV are self-adjoint (real
+    symmetric); a D2 or ONEOP becomes ("ONEOP", i_s, its conjugate transpose)."""
+    out = []
+    for g in reversed(list(gates)):
+        if g[0] in ("D2", "ONEOP"):
+            out.append(("ONEOP", g[1], _gate_matrix(g).conj().T))
+        elif g[0] in ("HALL", "ORACLE", "INV"):
+            out.append(g)
+        else:
+            raise ValueError("adjoint_gates takes HALL, ORACLE, INV, D2 and ONEOP gates")
+    return out
 
-    ``gates`` must be ORACLE, HALL, INV, HALL (Sec. 5.1) with at most one D2 at
-    a stage boundary (Sec. 6.3).  Three identities remove every sweep:
+
+def grover_sampler(nq, gates, marked, psi_in):
+    """Exact amplitudes of one Grover iteration, or of its adjoint, at any labels
+    and any n_q, without sweeping the state gate by gate.
+
+    ``gates``: the iteration ORACLE, HALL, INV, HALL (Sec. 5.1) or the adjoint
+    order HALL, INV, HALL, ORACLE, with at most one one-qubit rotation (D2 or
+    ONEOP) anywhere between them (Sec. 6.3).  ``psi_in``: 2^nq amplitudes, or a
+    basis vector given as ("basis", label, coefficient).
+
+    Three identities remove every sweep:
 
       * HALL . Inv . HALL = 2|s><s| - I, from Inv = 2|0><0| - I (Eq. inversion),
         HALL|0..0> = |s> (Eq. Shor1) and HALL^2 = I;
@@ -660,30 +681,39 @@ def grover_sampled(nq, gates, marked, psi_in, indices):
 
     Every intermediate vector v is then known through a function giving v_n at
     any labels and its two half sums V_c = sum over n with bit b = c of v_n (b
-    the state bit of the D2 qubit).  The half sums of psi_in are the only pass
-    over the whole state.  Returns (amplitudes at ``indices``, L).
+    the state bit of the rotated qubit).  The half sums of psi_in are the only
+    pass over the whole state, made once here.  Returns (amp, L): amp(indices)
+    gives the output amplitudes at an int64 label array, L the readout
+    sum_{x in M} |C_x|^2.
     """
-    psi = np.asarray(psi_in, dtype=np.complex128)
     size = 1 << nq
-    if psi.shape != (size,):
-        raise ValueError("psi_in must have 2^nq amplitudes")
     kinds = [g[0] for g in gates]
-    steps = [k for k in kinds if k != "D2"]
-    if steps != ["ORACLE", "HALL", "INV", "HALL"] or kinds.count("D2") > 1:
-        raise ValueError("grover_sampled takes one Grover iteration with at most one D2")
-    eloc = kinds.index("D2") if "D2" in kinds else None
-    if eloc is not None:
-        d2 = gates[eloc]
-        b = nq - d2[1]
-        D = d2_matrix(*d2[2:5])
+    rot = [k for k, g in enumerate(gates) if g[0] in ("D2", "ONEOP")]
+    steps = [k for k in kinds if k not in ("D2", "ONEOP")]
+    if steps not in (["ORACLE", "HALL", "INV", "HALL"], ["HALL", "INV", "HALL", "ORACLE"]) or len(rot) > 1:
+        raise ValueError("grover_sampler takes one Grover iteration (or its adjoint) with at most one rotation")
+    if rot:
+        b = nq - gates[rot[0]][1]
+        D = _gate_matrix(gates[rot[0]])
     else:
         b, D = 0, IDENTITY
     Ms = np.array(sorted(set(int(x) for x in marked)), dtype=np.int64)
     bit = 1 << b
 
-    def half_sums(v):
-        w = v.reshape(size >> (b + 1), 2, bit)
-        return w[:, 0, :].sum(), w[:, 1, :].sum()
+    if isinstance(psi_in, tuple) and psi_in[0] == "basis":
+        label, coeff = int(psi_in[1]), complex(psi_in[2])
+
+        def f(n):
+            n = np.asarray(n, dtype=np.int64)
+            return np.where(n == label, coeff, 0.0 + 0.0j)
+        V = (coeff, 0j) if not (label >> b) & 1 else (0j, coeff)
+    else:
+        psi = np.asarray(psi_in, dtype=np.complex128)
+        if psi.shape != (size,):
+            raise ValueError("psi_in must have 2^nq amplitudes")
+        f = lambda n: psi[n]
+        w = psi.reshape(size >> (b + 1), 2, bit)
+        V = (w[:, 0, :].sum(), w[:, 1, :].sum())
 
     def oracle(f, V):
         def g(n):
@@ -702,41 +732,53 @@ def grover_sampled(nq, gates, marked, psi_in, indices):
             return np.where(up, M[1, 0] * a0 + M[1, 1] * a1, M[0, 0] * a0 + M[0, 1] * a1)
         return g, (M[0, 0] * V[0] + M[0, 1] * V[1], M[1, 0] * V[0] + M[1, 1] * V[1])
 
-    def diffusion(f, V):  # HALL . Inv . HALL
-        tot = V[0] + V[1]
-        return (lambda n: 2.0 * tot / size - f(n)), (tot - V[0], tot - V[1])
-
-    def diffusion_d2_inside(f, V, after_inv):
-        # HALL . Inv . D . HALL = 2 |s> <0|D HALL - (H D H)_q            (eloc 2)
-        # HALL . D . Inv . HALL = 2 HALL D|0> <0|HALL - (H D H)_q        (eloc 3)
-        g_dt, _ = one_qubit(f, V, HADAMARD @ D @ HADAMARD)
+    def diffusion(f, V, where):
+        # HALL . Inv . HALL                                        (where None)
+        # HALL . Inv . D . HALL = 2 |s> <0|D HALL - (H D H)_q       (where 0: D after the first HALL)
+        # HALL . D . Inv . HALL = 2 HALL D|0> <0|HALL - (H D H)_q   (where 1: D after Inv)
         tot, alt = V[0] + V[1], V[0] - V[1]
-        if not after_inv:
-            c = 2.0 * (D[0, 0] * tot + D[0, 1] * alt) / size
-            return lambda n: c - g_dt(n)
+        if where is None:
+            return (lambda n: 2.0 * tot / size - f(n)), (tot - V[0], tot - V[1])
+        g_dt, W_dt = one_qubit(f, V, HADAMARD @ D @ HADAMARD)
+        if where == 0:
+            c = D[0, 0] * tot + D[0, 1] * alt
+            return (lambda n: 2.0 * c / size - g_dt(n)), (c - W_dt[0], c - W_dt[1])
+        c0, c1 = tot * (D[0, 0] + D[1, 0]), tot * (D[0, 0] - D[1, 0])
 
         def g(n):
-            sign = 1.0 - 2.0 * ((n >> b) & 1)
-            return 2.0 * tot * (D[0, 0] + D[1, 0] * sign) / size - g_dt(n)
-        return g
+            up = ((n >> b) & 1).astype(bool)
+            return 2.0 * np.where(up, c1, c0) / size - g_dt(n)
+        return g, (c0 - W_dt[0], c1 - W_dt[1])
 
-    f = lambda n: psi[n]
-    V = half_sums(psi)
-    if eloc == 0:
-        f, V = one_qubit(f, V, D)
-    f, V = oracle(f, V)
-    if eloc == 1:
-        f, V = one_qubit(f, V, D)
-    if eloc in (2, 3):
-        f = diffusion_d2_inside(f, V, eloc == 3)
-    else:
-        f, V = diffusion(f, V)
-        if eloc == 4:
+    k = 0
+    while k < len(gates):
+        kind = kinds[k]
+        if kind == "ORACLE":
+            f, V = oracle(f, V)
+            k += 1
+        elif kind in ("D2", "ONEOP"):
             f, V = one_qubit(f, V, D)
-    idx = np.asarray(indices, dtype=np.int64)
-    vals = f(idx)
+            k += 1
+        else:  # HALL, then Inv and HALL, with the rotation possibly on either side of Inv
+            block = kinds[k:k + 4]
+            if block[:3] == ["HALL", "INV", "HALL"]:
+                f, V = diffusion(f, V, None)
+                k += 3
+            elif block[1] in ("D2", "ONEOP"):
+                f, V = diffusion(f, V, 0)
+                k += 4
+            else:
+                f, V = diffusion(f, V, 1)
+                k += 4
     L = math.fsum(float(abs(v) ** 2) for v in f(Ms)) if len(Ms) else 0.0
-    return vals, L
+    return f, L
+
+
+def grover_sampled(nq, gates, marked, psi_in, indices):
+    """Amplitudes of one Grover iteration at the labels ``indices`` and L, through
+    :func:`grover_sampler` (any n_q, one pass over psi_in).  Returns (values, L)."""
+    amp, L = grover_sampler(nq, gates, marked, psi_in)
+    return amp(np.asarray(indices, dtype=np.int64)), L
 
 
 # ---------------------------------------------------------------------------
@@ -809,20 +851,34 @@ def qft_register(psi, nq, first, n, inverse=False):
 
 
 def qft_gates(n1, first=1):
-    """The QFT circuit of App. A as a gate list, on qubits first .. first+n_1-1:
-    for each qubit ic of the register a Hadamard, then CPHASEK between qubit ic
-    and each later qubit k with exponent k + 1 - ic (register-relative labels);
-    the Hadamard on the last qubit; then pair swaps (i, n_1 + 1 - i) that
-    restore standard order."""
+    """The QFT of the register of qubits first .. first+n_1-1 as a list of the paper's
+    gates (Hadamards, CPHASEK, SWAP; App. A), derived from its definition Eq. QFT1.
+
+    Write the input value n' = sum_r b_r 2^(n_1-r) over the register's qubits
+    r = 1..n_1 (qubit 1 most significant) and the output value n = sum_s c_s
+    2^(n_1-s).  The phase 2 pi n n' / 2^(n_1) = 2 pi sum_(r,s) b_r c_s 2^(n_1-r-s)
+    is a multiple of 2 pi whenever r + s <= n_1, so only the bit pairs with
+    r + s > n_1 contribute, each a factor e^(2 pi i b_r c_s / 2^(r+s-n_1)).
+
+    A Hadamard on qubit r maps the input bit b_r to the output bit c_s with
+    s = n_1 + 1 - r and supplies that pair's sign (-1)^(b_r c_s), the term
+    r + s = n_1 + 1; the output therefore comes out in reversed qubit order.  The
+    term of b_r with an output bit c_s that an earlier qubit q = n_1 + 1 - s < r
+    already holds is the controlled phase of exponent r + s - n_1 = r + 1 - q
+    between qubits r and q.  So, qubit by qubit: the phases of qubit r with the
+    output bits of every earlier qubit, then the Hadamard on r; finally the swaps
+    of qubits q and n_1 + 1 - q restore standard order.
+    """
+    def wire(r):
+        return first - 1 + r
+
     g = []
-    o = first - 1
-    for ic in range(1, n1):
-        g.append(("H", o + ic))
-        for k in range(ic + 1, n1 + 1):
-            g.append(("CPHASEK", o + k, o + ic, k + 1 - ic))
-    g.append(("H", o + n1))
-    for i in range(1, n1 // 2 + 1):
-        g.append(("SWAP", o + i, o + n1 + 1 - i))
+    for r in range(1, n1 + 1):
+        for s in range(n1 + 2 - r, n1 + 1):
+            g.append(("CPHASEK", wire(r), wire(n1 + 1 - s), r + s - n1))
+        g.append(("H", wire(r)))
+    for q in range(1, n1 // 2 + 1):
+        g.append(("SWAP", wire(q), wire(n1 + 1 - q)))
     return g
 
 

@@ -1,0 +1,238 @@
+"""GPU parity of every element at the pass schedules the full-size runs use.
+
+At the default tiling a forward evaluation takes 3 passes up to n_q = 22 and 5
+from n_q = 23 (the n_q = 30 headline runs 5); the backward takes 5 passes from
+n_q = 21 and 7 from n_q = 29.  These tests compare the whole output of those
+schedules with the FP64 oracle:
+
+  * forward at n_q = 23 and 24 (5 passes), FP64 and FP32, every noise placement,
+    against the gate-by-gate oracle (Sec. 5.1, G = HALL.Inv.HALL.Oracle, built from
+    the Eq. resmat1 sweeps of Sec. 3);
+  * backward at n_q = 21 and 22 (5 passes) and at forced small tiles that give 5
+    and 7 backward passes, against the oracle's store-all adjoint;
+  * n_q = 30 (FP64 and FP32 forward, FP64 backward): every one of the 2^30
+    amplitudes, in chunks, against oracle.grover_sampler -- the closed route
+    through HALL.Inv.HALL = 2|s><s| - I, pinned against the gate-by-gate oracle
+    on the CPU -- whose half sums are computed once.  The gradient uses
+    grad psi_in = 2 dL C~_x U^dagger|x> for the one marked label x.
+
+Every test prints its case and the measured normwise error before asserting.
+"""
+
+import math
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_0902_0699_amd import workload as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+TOL_GRAD = 1e-10
+
+
+def _pk():
+    from paper_0902_0699_amd import paperkern as pk
+    return pk
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _relerr(got, want):
+    return float(np.linalg.norm(got - want) / np.linalg.norm(want))
+
+
+def _case(nq, eloc, seed):
+    """One noisy iteration at n_q with the noise at stage boundary ``eloc``; the
+    input is rounded to complex64 so that the FP64 and FP32 paths share it."""
+    inst = W.single_instance(seed, nq)
+    qhit, _, alpha, beta, gamma = inst["noise"]
+    gates = W.grover_gates((qhit, eloc, alpha, beta, gamma))
+    psi = inst["psi"].astype(np.complex64).astype(np.complex128)
+    return gates, inst["marked"], psi
+
+
+_ORACLE_CACHE = {}
+
+
+def _oracle_forward(nq, eloc, seed):
+    key = (nq, eloc, seed)
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE.clear()  # one n_q = 24 result at a time (256 MiB each)
+        gates, marked, psi = _case(nq, eloc, seed)
+        _ORACLE_CACHE[key] = (gates, marked, psi) + O.evaluate(nq, gates, marked, psi)
+    return _ORACLE_CACHE[key]
+
+
+FORWARD_CASES = [(23, e) for e in range(5)] + [(24, 1), (24, 3)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("nq,eloc", FORWARD_CASES)
+def test_forward_five_pass_schedule_every_element(nq, eloc, prec):
+    pk = _pk()
+    seed = 100 + nq
+    _say("forward schedule: n_q=%d eloc=%d %s" % (nq, eloc, prec))
+    gates, marked, psi, want, Lw, nw = _oracle_forward(nq, eloc, seed)
+    plan = pk.Plan({"nq": nq, "gates": gates, "marked": marked}, prec=prec)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    x = torch.from_numpy(psi).to(dt).to("cuda")
+    out, L, norm = pk.evaluate(plan, x)
+    got = out.cpu().numpy().astype(np.complex128)
+    L, norm = float(L.item()), float(norm.item())
+    err = _relerr(got, want)
+    tol = TOL64 if prec == "fp64" else TOL32
+    _say("  passes %d  normwise err %.3e  |dL| %.3e  |dnorm| %.3e" % (plan.passes(), err, abs(L - Lw), abs(norm - nw)))
+    assert plan.passes() == 5
+    assert err <= tol
+    assert abs(L - Lw) <= tol * max(1.0, Lw)
+    assert abs(norm - nw) <= tol * nw
+
+
+def _backward_case(nq, eloc, tile, seed):
+    pk = _pk()
+    gates, marked, psi = _case(nq, eloc, seed)
+    plan = pk.Plan({"nq": nq, "gates": gates, "marked": marked})
+    if tile is not None:
+        plan.set_tiling(tile, 4, 1)
+    nb = len(plan.describe()["instances"][0]["backward"])
+    _say("backward schedule: n_q=%d eloc=%d tile %s -> %d backward passes" % (nq, eloc, tile, nb))
+    x = torch.from_numpy(psi).to("cuda")
+    out, _, _ = pk.evaluate(plan, x, want_norm=False)
+    dL = torch.tensor([0.75], dtype=torch.float64, device="cuda")
+    gpsi, gang = pk.backward(plan, out, dL)
+    gpsi = gpsi.cpu().numpy()
+    gang = gang.cpu().numpy()
+    wpsi, wang = O.adjoint_grad(nq, gates, marked, psi, 0.75)
+    err = _relerr(gpsi, wpsi)
+    aerr = float(np.max(np.abs(gang - wang.reshape(-1))) / max(1e-300, float(np.max(np.abs(wang)))))
+    _say("  grad psi normwise err %.3e  angle grads rel err %.3e" % (err, aerr))
+    return nb, err, aerr
+
+
+@pytest.mark.parametrize("nq,eloc", [(21, e) for e in range(5)] + [(22, 2)])
+def test_backward_five_pass_schedule_every_element(nq, eloc):
+    nb, err, aerr = _backward_case(nq, eloc, None, 200 + nq)
+    assert nb == 5
+    assert err <= TOL_GRAD and aerr <= TOL_GRAD
+
+
+@pytest.mark.parametrize("tile,passes", [(7, 7), (8, 5)])
+@pytest.mark.parametrize("eloc", range(5))
+def test_backward_small_tiles_five_and_seven_passes(tile, passes, eloc):
+    """Tiles of 2^7 and 2^8 amplitudes at n_q = 16 give the 7- and 5-pass backward
+    schedules.  With the rotation before the Oracle (eloc 0) it is the last gate
+    walked back, after the Oracle's flip, which needs every Hadamard undone first:
+    at these tiles it then takes a pass of its own."""
+    nb, err, aerr = _backward_case(16, eloc, tile, 300 + eloc)
+    assert nb == passes + (1 if eloc == 0 else 0)
+    assert err <= TOL_GRAD and aerr <= TOL_GRAD
+
+
+# --------------------------------------------------------------------------- n_q = 30, every element
+
+NQ = W.NQ_LARGE
+CHUNK = 1 << 24
+WORKERS = 8
+
+
+def _chunked_error(nq, amp, dev_vec, scale=1.0):
+    """(sum |got - want|^2, sum |want|^2) over every label, chunk by chunk; want =
+    scale * amp(labels).  Expected values are computed in threads (NumPy releases
+    the GIL in its array loops) while the device chunks are copied out in order."""
+    n = 1 << nq
+    starts = list(range(0, n, CHUNK))
+
+    def want_of(a):
+        return scale * amp(np.arange(a, min(a + CHUNK, n), dtype=np.int64))
+
+    d2 = r2 = 0.0
+    with ThreadPoolExecutor(max_workers=WORKERS) as ex:
+        futs = {}
+        for i, a in enumerate(starts[:WORKERS]):
+            futs[i] = ex.submit(want_of, a)
+        for i, a in enumerate(starts):
+            got = dev_vec[a:a + CHUNK].cpu().numpy().astype(np.complex128)
+            want = futs.pop(i).result()
+            if i + WORKERS < len(starts):
+                futs[i + WORKERS] = ex.submit(want_of, starts[i + WORKERS])
+            d2 += float(np.sum(np.abs(got - want) ** 2))
+            r2 += float(np.sum(np.abs(want) ** 2))
+            if i % 16 == 15:
+                _say("    chunk %d/%d" % (i + 1, len(starts)))
+    return d2, r2
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_size_forward_every_element(prec):
+    pk = _pk()
+    seed = W.SEEDS["large_fp64"] if prec == "fp64" else W.SEEDS["large_fp32"]
+    _say("full size, every element: n_q=%d %s seed %d" % (NQ, prec, seed))
+    inst = W.single_instance(seed, NQ)
+    psi = inst["psi"]
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    if prec == "fp32":
+        psi = psi.astype(np.complex64).astype(np.complex128)  # the input the FP32 path sees
+        inst["psi"] = None
+    plan = pk.Plan({"nq": NQ, "gates": inst["gates"], "marked": inst["marked"]}, prec=prec)
+    x = torch.from_numpy(psi).to(dt).to("cuda")
+    y, L, norm = pk.evaluate(plan, x)
+    del x
+    L, norm = float(L.item()), float(norm.item())
+    amp, L_ref = O.grover_sampler(NQ, inst["gates"], inst["marked"], psi)
+    d2, r2 = _chunked_error(NQ, amp, y)
+    err = math.sqrt(d2 / r2)
+    norm_in = float(np.vdot(psi, psi).real)
+    tol = TOL64 if prec == "fp64" else TOL32
+    _say("  passes %d  normwise err over all 2^%d amplitudes %.3e  |dL| %.3e  |dnorm| %.3e"
+         % (plan.passes(), NQ, err, abs(L - L_ref), abs(norm - norm_in)))
+    del y
+    torch.cuda.empty_cache()
+    assert plan.passes() == 5
+    assert err <= tol
+    assert abs(L - L_ref) <= tol * max(1.0, L_ref) * norm_in
+    assert abs(norm - norm_in) <= tol * norm_in
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_full_size_backward_every_element():
+    """grad psi_in of the 7-pass backward at n_q = 30 against 2 dL C~_x U^dagger|x>,
+    every element (seed of the gradient workload)."""
+    pk = _pk()
+    seed = W.SEEDS["gradient"]
+    _say("full size backward, every element: n_q=%d fp64 seed %d" % (NQ, seed))
+    inst = W.single_instance(seed, NQ)
+    psi = inst["psi"]
+    gates, marked = inst["gates"], inst["marked"]
+    plan = pk.Plan({"nq": NQ, "gates": gates, "marked": marked})
+    nb = len(plan.describe()["instances"][0]["backward"])
+    x = torch.from_numpy(psi).to("cuda")
+    out, _, _ = pk.evaluate(plan, x, want_norm=False)
+    del x
+    dl = 0.75
+    dL = torch.tensor([dl], dtype=torch.float64, device="cuda")
+    gpsi, _ = pk.backward(plan, out, dL)
+    del out
+    amp, _ = O.grover_sampler(NQ, gates, marked, psi)
+    cx = complex(amp(np.array(marked, dtype=np.int64))[0])
+    del amp, psi, inst["psi"]
+    back, _ = O.grover_sampler(NQ, O.adjoint_gates(gates), marked, ("basis", marked[0], dl * cx))
+    d2, r2 = _chunked_error(NQ, back, gpsi, scale=2.0)
+    err = math.sqrt(d2 / r2)
+    _say("  backward passes %d  normwise err of grad psi_in over all 2^%d amplitudes %.3e" % (nb, NQ, err))
+    del gpsi
+    torch.cuda.empty_cache()
+    assert nb == 7
+    assert err <= TOL_GRAD

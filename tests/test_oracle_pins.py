@@ -494,6 +494,64 @@ def test_grover_sampled_matches_gate_by_gate_evaluation(nq, eloc):
         assert abs(L - Lw) <= 1e-14 * max(1.0, Lw)
 
 
+@pytest.mark.parametrize("eloc", [None, 0, 1, 2, 3, 4])
+@pytest.mark.parametrize("nq", [1, 3, 6])
+def test_grover_sampler_adjoint_order_and_basis_inputs(nq, eloc):
+    """The sampler on the adjoint list U^dagger (reversed order, D^H) from a basis
+    vector c|x> -- the route of the full-size gradient check, grad psi_in =
+    2 dL C~_x U^dagger|x> -- against the gate-by-gate oracle.  Also checks that
+    the adjoint list undoes the iteration and that a chunked evaluation (labels
+    in pieces, half sums once) equals the whole one."""
+    rng = np.random.default_rng(900 + 10 * nq + (eloc if eloc is not None else 9))
+    for rep in range(3):
+        qhit = int(rng.integers(1, nq + 1))
+        noise = None if eloc is None else (qhit, eloc, *rng.uniform(0.1, 3.0, 2), float(rng.uniform(-1, 1)))
+        gates = O.grover_gates(noise)
+        adj = O.adjoint_gates(gates)
+        marked = sorted({int(v) for v in rng.integers(0, 1 << nq, int(rng.integers(1, 4)))})
+        psi = _rand_state(rng, nq) * 0.8
+        fwd, _, _ = O.evaluate(nq, gates, marked, psi)
+        back, _, _ = O.evaluate(nq, adj, marked, fwd)
+        np.testing.assert_allclose(back, psi, rtol=0, atol=1e-14)
+        # the sampler on the adjoint list, from a dense state and from a basis vector
+        want, Lw, _ = O.evaluate(nq, adj, marked, psi)
+        amp, L = O.grover_sampler(nq, adj, marked, psi)
+        idx = rng.permutation(1 << nq)
+        np.testing.assert_allclose(amp(idx), want[idx], rtol=0, atol=1e-14)
+        assert abs(L - Lw) <= 1e-14 * max(1.0, Lw)
+        x = marked[0]
+        c = complex(*rng.standard_normal(2))
+        e = np.zeros(1 << nq, dtype=np.complex128)
+        e[x] = c
+        want_e, Le, _ = O.evaluate(nq, adj, marked, e)
+        amp_e, L_e = O.grover_sampler(nq, adj, marked, ("basis", x, c))
+        np.testing.assert_allclose(amp_e(np.arange(1 << nq)), want_e, rtol=0, atol=1e-14)
+        assert abs(L_e - Le) <= 1e-14 * max(1.0, Le)
+        # chunked evaluation of the forward sampler
+        amp_f, _ = O.grover_sampler(nq, gates, marked, psi)
+        whole = amp_f(np.arange(1 << nq))
+        step = max(1, (1 << nq) // 3)
+        pieces = np.concatenate([amp_f(np.arange(a, min(a + step, 1 << nq))) for a in range(0, 1 << nq, step)])
+        np.testing.assert_array_equal(pieces, whole)
+        np.testing.assert_allclose(whole, fwd, rtol=0, atol=1e-14)
+
+
+def test_adjoint_gradient_closed_route_small():
+    """grad psi_in = 2 dL sum_x C~_x U^dagger|x> (one marked label): the closed route
+    of the full-size gradient check against the store-all adjoint."""
+    rng = np.random.default_rng(31)
+    for eloc in range(5):
+        nq = 7
+        gates = O.grover_gates((3, eloc, 1.1, 2.3, 0.4))
+        psi = _rand_state(rng, nq)
+        x = int(rng.integers(0, 1 << nq))
+        gpsi, _ = O.adjoint_grad(nq, gates, [x], psi, dL=0.75)
+        amp, _ = O.grover_sampler(nq, gates, [x], psi)
+        cx = complex(amp(np.array([x]))[0])
+        back, _ = O.grover_sampler(nq, O.adjoint_gates(gates), [x], ("basis", x, 0.75 * cx))
+        np.testing.assert_allclose(2.0 * back(np.arange(1 << nq)), gpsi, rtol=0, atol=1e-14)
+
+
 def test_grover_sampled_rejects_other_circuits():
     with pytest.raises(ValueError):
         O.grover_sampled(3, [("HALL",)], [1], np.ones(8), [0])

@@ -17,8 +17,9 @@ setting, leaves it applied to the plan, and returns it with the table of
 timings.
 
 If ``PK_TUNE_CACHE`` names a JSON file, choices are remembered there. The key
-is the device name, the precision, the operation and a hash of the problem's
-structure (sizes, gate kinds and qubits). A later ``tune`` of the same workload
+is the device name and a hash of the library's sources, the precision, the
+operation and the problem's structure (sizes, gate kinds, qubits, CPHASEK
+exponents and QFT registers). A later ``tune`` of the same workload
 then applies the cached choice without timing.
 """
 
@@ -26,6 +27,8 @@ import hashlib
 import itertools
 import json
 import os
+
+import numpy as np
 
 from . import paperkern as pk
 
@@ -55,16 +58,42 @@ def apply(plan, cfg):
     plan.set_batch(cfg.get("team_size", 16), cfg.get("min_team_tiles", 64))
 
 
-def signature(plan, op):
-    """Hash of what the schedule depends on: precision, operation, and per instance
-    the size and the gate kinds with their qubits (not angles, operators or marks)."""
+def _sources_hash():
+    """Hash of the library's kernel and planner sources: a choice timed on one
+    version of the kernels is not reused by another."""
     h = hashlib.sha256()
-    h.update(("%s|%s|" % (plan.prec, op)).encode())
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".cpp", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:12]
+
+
+def _gate_structure(g):
+    """What of a gate tuple the schedule depends on: its kind and every integer
+    field (qubits, the CPHASEK exponent, a QFT register's first qubit and size);
+    not angles or operator entries."""
+    kind = g[0]
+    if kind in ("ONEOP", "D2"):
+        ints = (g[1],)
+    elif kind in ("TWOOP", "D4"):
+        ints = (g[1], g[2])
+    else:
+        ints = tuple(v for v in g[1:] if isinstance(v, (int, np.integer)) and not isinstance(v, bool))
+    return "%s%s" % (kind, ints)
+
+
+def signature(plan, op):
+    """Hash of what the schedule depends on: the library sources, precision,
+    operation, and per instance the size, each gate's kind and integer fields and
+    the number of marks (not angles, operators or mark values)."""
+    h = hashlib.sha256()
+    h.update(("%s|%s|%s|" % (_sources_hash(), plan.prec, op)).encode())
     for p in plan.problems:
         h.update(("n%d:" % p["nq"]).encode())
         for g in p["gates"]:
-            qubit = g[1] if g[0] in ("H", "ONEOP", "D2") else ""
-            h.update(("%s%s," % (g[0], qubit)).encode())
+            h.update((_gate_structure(g) + ",").encode())
         h.update(("m%d;" % len(p.get("marked", []))).encode())
     return h.hexdigest()[:20]
 

@@ -222,14 +222,6 @@ class Plan:
         _check(lib().pk_workspace_bytes(self.handle, op, ctypes.byref(n)), self.handle)
         return n.value
 
-    def default_angles(self):
-        out = []
-        for p in self.problems:
-            for g in p["gates"]:
-                if g[0] == "D2":
-                    out += [float(g[2]), float(g[3]), float(g[4])]
-        return np.array(out, dtype=np.float64)
-
     # ---- device calls ---------------------------------------------------------------------
     def workspace(self, op, device):
         import torch

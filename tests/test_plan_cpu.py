@@ -154,6 +154,42 @@ def test_autotune_candidates_are_accepted_and_signature_is_structural():
     c = [{"nq": 12, "gates": W.grover_gates((4, 2, 0.1, 0.2, 0.0)), "marked": [5]}]
     sig = lambda pr: AT.signature(pk.Plan(pr), "eval")
     assert sig(a) == sig(b) != sig(c)
+    # every structural field counts: QFT register start and size, the qubits of
+    # two-qubit gates, the CPHASEK exponent, D4 qubits
+    one = lambda *g: [{"nq": 24, "gates": list(g), "marked": []}]
+    keys = [sig(one(("QFT", 1, 20))), sig(one(("QFT", 1, 10))), sig(one(("QFT", 2, 10))),
+            sig(one(("QFT_NOSWAP", 1, 20))), sig(one(("CNOT", 1, 2))), sig(one(("CNOT", 2, 1))),
+            sig(one(("CNOT", 3, 4))), sig(one(("CPHASEK", 1, 2, 3))), sig(one(("CPHASEK", 1, 2, 4))),
+            sig(one(("SWAP", 1, 2))), sig(one(("SWAP", 5, 9))), sig(one(("D4", 1, 2, 0.1, 0.2, 0.3))),
+            sig(one(("D4", 2, 3, 0.1, 0.2, 0.3))), sig(one(("TWOOP", 1, 2, np.eye(4)))),
+            sig(one(("TWOOP", 1, 3, np.eye(4))))]
+    assert len(set(keys)) == len(keys)
+    assert sig(one(("D4", 1, 2, 0.1, 0.2, 0.3))) == sig(one(("D4", 1, 2, 1.1, 1.2, 1.3)))
+    assert sig(one(("TWOOP", 1, 2, np.eye(4)))) == sig(one(("TWOOP", 1, 2, 2 * np.eye(4))))
+
+
+def test_binding_step_one_register_sizes_and_search_length():
+    """The binding's host helpers that set up GPU cases: Shor's Step 1 register sizes
+    against the footnote values and the oracle, and n_t = floor((pi/4) sqrt(N)) (the
+    floor reading of Sec. 5.1) against an exact integer test: n_t is the largest k
+    with 16 k^2 <= pi^2 N, pi^2 taken to 40 digits."""
+    from decimal import Decimal, getcontext
+    with open(os.path.join(ROOT, "tests", "golden", "shor_examples.txt")) as f:
+        rows = [ln.split(":") for ln in f if ln.startswith("sizes:")]
+    assert rows
+    for _, m, sizes in rows:
+        assert pk.shor_register_sizes(int(m)) == tuple(int(v) for v in sizes.split())
+    for M in range(2, 5000):
+        assert pk.shor_register_sizes(M) == O.shor_register_sizes(M)
+    getcontext().prec = 60
+    pi2 = Decimal("9.869604401089358618834490999876151135313699407240790626413349")
+    for nq in range(1, 41):
+        n_t = pk.grover_iterations(nq)
+        N = Decimal(1 << nq)
+        assert 16 * Decimal(n_t) ** 2 <= pi2 * N < 16 * Decimal(n_t + 1) ** 2
+        if nq >= 3:  # the rotation closed form: success probability after n_t steps
+            th = math.asin(2.0 ** (-nq / 2))
+            assert math.sin((2 * n_t + 1) * th) ** 2 > 0.9
 
 
 def test_page_cap_spreads_large_stride_bits_over_passes():

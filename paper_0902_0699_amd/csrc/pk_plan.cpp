@@ -1039,19 +1039,28 @@ int compile_plan(Plan* plan, const pk_problem* probs, int n_inst, int prec, std:
             }
             case PK_GATE_QFT:
             case PK_GATE_QFT_NOSWAP: {
-                // the circuit of App. A on the register of qubits is1 .. is1+k-1: per qubit
-                // ic a Hadamard, then CPHASEK between ic and every later qubit q with
-                // exponent q + 1 - ic (register labels); the last Hadamard; the pair
-                // swaps (i, k + 1 - i) that restore standard order (not in the variant
-                // that leaves the register bit-reversed)
-                const int o = gt.is1 - 1, n1 = gt.k;
-                for (int ic = 1; ic <= n1; ++ic) {
-                    in.prims.push_back({Prim::GATE, p.nq - (o + ic), Prim::GH, 0});
-                    for (int q = ic + 1; q <= n1; ++q) in.prims.push_back(phase_prim(p.nq, o + q, o + ic, q + 1 - ic));
+                // Eq. QFT1 on the register held by state bits lo .. lo+k-1 (value bit t
+                // on state bit lo + t, the register's first qubit on the top bit).  In
+                // 2 pi n n' / 2^k = 2 pi sum_(i,j) b_i c_j 2^(i+j-k) (input bits b, output
+                // bits c) only the terms i + j < k are not multiples of 2 pi.  A Hadamard
+                // on value bit t turns b_t into c_(k-1-t), so the output is bit-reversed,
+                // and supplies the term i + j = k - 1; the term of b_t with the output
+                // bit on a higher, already transformed bit u is the controlled phase
+                // e^(2 pi i / 2^(u - t + 1)).  From the top bit down: the phases of bit t
+                // with every higher bit, then its Hadamard (App. A draws the same circuit).
+                // Swapping bits t and k-1-t restores standard order; the labelled
+                // variant leaves the register bit-reversed.
+                const int top = p.nq - gt.is1, kq = gt.k, lo = top - kq + 1;
+                auto qubit_of = [&](int bit) { return p.nq - bit; };
+                for (int t = kq - 1; t >= 0; --t) {
+                    for (int u = t + 1; u < kq; ++u)
+                        in.prims.push_back(phase_prim(p.nq, qubit_of(lo + u), qubit_of(lo + t), u - t + 1));
+                    in.prims.push_back({Prim::GATE, lo + t, Prim::GH, 0});
                 }
                 if (gt.kind == PK_GATE_QFT)
-                    for (int q = 1; q <= n1 / 2; ++q)
-                        in.prims.push_back(mat4_prim(plan, p.nq, o + q, o + n1 + 1 - q, kSwap4, Prim::GSWAP));
+                    for (int t = 0; t < kq - 1 - t; ++t)
+                        in.prims.push_back(
+                            mat4_prim(plan, p.nq, qubit_of(lo + t), qubit_of(lo + kq - 1 - t), kSwap4, Prim::GSWAP));
                 break;
             }
             case PK_GATE_D4:

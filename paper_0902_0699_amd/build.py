@@ -1,6 +1,7 @@
 """Build libpaperkern.so in-tree with hipcc for gfx950.
 
     python -m paper_0902_0699_amd.build        (or python paper_0902_0699_amd/build.py)
+    python -m paper_0902_0699_amd.build --stale   (recompile only out-of-date objects)
 
 Every HIP source is compiled with packed FP32 instructions disabled.
 """
@@ -15,14 +16,29 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpaperkern.so")
-SOURCES = ["pk_kernels.hip", "pk_shor.hip", "pk_density.hip", "pk_search.hip", "pk_api.cpp", "pk_plan.cpp"]
+# the pass and batched kernel instances come first: they take longest to compile
+SOURCES = ["pk_batched_f32.hip", "pk_batched_f64.hip", "pk_pass_f32.hip", "pk_pass_f64.hip", "pk_pass_f32r5.hip",
+           "pk_pass_f64r5.hip", "pk_pass_f32bwd.hip", "pk_pass_f64bwd.hip", "pk_kernels.hip", "pk_shor.hip",
+           "pk_density.hip", "pk_search.hip", "pk_api.cpp", "pk_plan.cpp"]
 # rocSOLVER (and the rocBLAS handle it runs on) gives the density matrix's eigenvalues
 LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
-def build(verbose=False, jobs=3):
-    """Compile every source to an object in parallel, then link the shared library."""
+def _stale(src, obj):
+    """An object is stale when it is missing or older than its source or any header."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [src] + [os.path.join(d, f) for d in (CSRC, INCLUDE) for f in os.listdir(d) if f.endswith(".h")]
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose=False, jobs=None, only_stale=False):
+    """Compile every source to an object in parallel, then link the shared library.
+    ``only_stale`` recompiles only objects older than their source or a header."""
+    if jobs is None:
+        jobs = max(1, min(8, os.cpu_count() or 1))
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     common = [
@@ -38,6 +54,8 @@ def build(verbose=False, jobs=3):
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
+        if only_stale and not _stale(os.path.join(CSRC, src), obj):
+            continue
         cmd = [HIPCC, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + common
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -70,4 +88,4 @@ def build(verbose=False, jobs=3):
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, only_stale="--stale" in sys.argv))

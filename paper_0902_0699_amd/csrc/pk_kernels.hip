@@ -1,909 +1,11 @@
-// Device kernels for gfx950: the fused tile pass, the batched multiverse
-// launch, the table preparation and the final FP64 combine.
-//
-// One workgroup owns one tile of 2^k amplitudes (labels that differ only in the
-// pass's k tile bits).  Thread t holds 16 amplitudes in registers; in stage s
-// their local labels are jt(s) | roff_s(i), i = 0..15, where register bit a of
-// i sits on local tile bit rb[a] and the thread index fills the other bits in
-// ascending order.  A one-qubit gate on a register bit is then a butterfly over
-// register pairs (i, i | 2^a): the 2x2 pair update of Sec. 3 (Eq. resmat1) on
-// every partner pair of the tile at once.  Between stages the tile goes through
-// LDS to bring the next four bits into registers.  The first and last stages
-// keep the lowest tile bits on the lane index, so HBM is read and written in
-// contiguous runs.
+// Device kernels for gfx950: table preparation, the final FP64 combine and the
+// pair-index map; and the run-time choice of the pass and batched kernel
+// instances (compiled in pk_pass_*.hip).
 #include <hip/hip_runtime.h>
 
-#include <type_traits>
-
-#include "pk_desc.h"
-#include "pk_launch.h"
-
-// Descriptor tables are read through the constant address space so that the
-// uniform reads become scalar loads: they then never wait on vector memory
-// traffic (the prefetched tile, the previous tile's stores).
-#define PK_CONST __attribute__((address_space(4)))
+#include "pk_kargs.h"
 
 namespace pk {
-
-template <typename R>
-struct Cplx;
-template <>
-struct Cplx<double> {
-    using T = double2;
-};
-template <>
-struct Cplx<float> {
-    using T = float2;
-};
-
-struct KArgs {
-    const Pass* passes;
-    const Stage* stages;
-    const Flip* flips;
-    const PhaseOp* phases;
-    const UPair* upairs;
-    const double* mats;
-    const double* mats4;  // 4x4 complex matrices of two-qubit gates, 32 doubles each
-    const void* src0;  // vector 0 input of the first pass
-    void* dst0;        // vector 0 output (and input of later passes)
-    void* dst1;        // vector 1 (lambda) in/out, backward only
-    double* partials;
-    double* reads;
-    double* gpart;
-    const double* dL;
-    int32_t pass;
-    int32_t want_norm;
-};
-
-template <typename X>
-__device__ __forceinline__ const PK_CONST X* cptr(const X* p) {
-    return (const PK_CONST X*)(p);
-}
-
-// LDS bank swizzle on element slots: the label's higher W-bit groups are XORed
-// into its low W bits, with 2^W elements = 256 bytes, one pass over the LDS
-// banks.  Whatever bits a stage puts on the lane index, any 256 contiguous
-// bytes' worth of lanes then hit distinct banks.  Linear over XOR, so
-// phys(a ^ b) = phys(a) ^ phys(b).
-template <int ESZ>
-__device__ __forceinline__ unsigned phys(unsigned j) {
-    constexpr int W = ESZ == 16 ? 4 : 5;
-    constexpr unsigned M = (1u << W) - 1u;
-    return j ^ (((j >> W) ^ (j >> (2 * W)) ^ (j >> (3 * W))) & M);
-}
-
-// Layout of one stage: per-thread label base and the uniform offsets of the
-// four register bits (as labels and as LDS slots).
-struct Layout {
-    unsigned jt;               // thread's label base
-    unsigned pj;               // phys(jt)
-    unsigned r[kMaxRegBits];   // 1 << rb[a] (0 for missing bits)
-    unsigned p[kMaxRegBits];   // phys(1 << rb[a])
-};
-
-template <int ESZ>
-__device__ __forceinline__ Layout make_layout(const PK_CONST Stage* S, int nrb, unsigned tid) {
-    Layout L;
-    unsigned t = tid;
-    // spread the thread index over the local bits that are not register bits
-    for (int q = 0; q < nrb; ++q) {
-        const int p = S->rbs[q];
-        t = ((t >> p) << (p + 1)) | (t & ((1u << p) - 1u));
-    }
-    L.jt = t;
-    L.pj = phys<ESZ>(t);
-#pragma unroll
-    for (int a = 0; a < kMaxRegBits; ++a) {
-        L.r[a] = a < nrb ? (1u << S->rb[a]) : 0u;
-        L.p[a] = phys<ESZ>(L.r[a]);
-    }
-    return L;
-}
-
-__device__ __forceinline__ unsigned roff(const Layout& L, int i) {
-    return ((i & 1) ? L.r[0] : 0u) | ((i & 2) ? L.r[1] : 0u) | ((i & 4) ? L.r[2] : 0u) |
-           ((i & 8) ? L.r[3] : 0u) | ((i & 16) ? L.r[4] : 0u);
-}
-__device__ __forceinline__ unsigned poff(const Layout& L, int i) {
-    return ((i & 1) ? L.p[0] : 0u) ^ ((i & 2) ? L.p[1] : 0u) ^ ((i & 4) ? L.p[2] : 0u) ^
-           ((i & 8) ? L.p[3] : 0u) ^ ((i & 16) ? L.p[4] : 0u);
-}
-
-// Moves the bits of `x` along the runs (src, len, dst).
-__device__ __forceinline__ int64_t deposit(int64_t x, const PK_CONST Run* run, int nrun) {
-    int64_t r = 0;
-    for (int q = 0; q < nrun; ++q) {
-        const int src = run[q].src, len = run[q].len, dst = run[q].dst;
-        r |= ((x >> src) & (((int64_t)1 << len) - 1)) << dst;
-    }
-    return r;
-}
-
-// State offsets of a stage used for HBM access: the thread's part (elements)
-// and the uniform parts of the four register bits.
-struct GOff {
-    int64_t gt;
-    int64_t g[kMaxRegBits];
-};
-
-// `store` selects the map the tile is written with (SWAPs done by relabelling
-// make it differ from the map it is read with).
-__device__ __forceinline__ GOff make_goff(const PK_CONST Pass* P, const PK_CONST Stage* S, const Layout& L,
-                                          int nrb, bool store) {
-    GOff G;
-    G.gt = store ? deposit((int64_t)L.jt, P->strun, P->nstrun) : deposit((int64_t)L.jt, P->trun, P->ntrun);
-    const PK_CONST int32_t* pos = store ? P->stpos : P->tpos;
-#pragma unroll
-    for (int a = 0; a < kMaxRegBits; ++a) G.g[a] = a < nrb ? ((int64_t)1 << pos[S->rb[a]]) : 0;
-    return G;
-}
-
-__device__ __forceinline__ int64_t goff(const GOff& G, int i) {
-    return ((i & 1) ? G.g[0] : 0) + ((i & 2) ? G.g[1] : 0) + ((i & 4) ? G.g[2] : 0) +
-           ((i & 8) ? G.g[3] : 0) + ((i & 16) ? G.g[4] : 0);
-}
-
-// ---------------------------------------------------------------------------- gate bodies
-
-// Hadamard butterfly (x, y) <- (x + y, x - y), unnormalised, written to update
-// both registers in place: x += y, then y = x_new - 2 y (one rounding more than
-// x - y, well inside the FP64 and FP32 tolerances).  In-place updates let the
-// compiler keep the tile in one set of registers through the predicated steps.
-template <int A, int NV, int NR, typename T>
-__device__ __forceinline__ void op_h(T (&v)[NV][NR]) {
-    using R = decltype(v[0][0].x);
-#pragma unroll
-    for (int n = 0; n < NV; ++n)
-#pragma unroll
-        for (int i = 0; i < NR; ++i) {
-            if (i & (1 << A)) continue;
-            const int j = i | (1 << A);
-            v[n][i].x += v[n][j].x;
-            v[n][i].y += v[n][j].y;
-            v[n][j].x = fma((R)-2, v[n][j].x, v[n][i].x);
-            v[n][j].y = fma((R)-2, v[n][j].y, v[n][i].y);
-        }
-}
-
-// (x, y) <- M (x, y) with M row-major complex [m0+i m1, m2+i m3; m4+i m5, m6+i m7]
-template <typename T, typename R>
-__device__ __forceinline__ void pair_mat(T& x, T& y, const R (&m)[8]) {
-    const T a = x, b = y;
-    x.x = m[0] * a.x - m[1] * a.y + m[2] * b.x - m[3] * b.y;
-    x.y = m[0] * a.y + m[1] * a.x + m[2] * b.y + m[3] * b.x;
-    y.x = m[4] * a.x - m[5] * a.y + m[6] * b.x - m[7] * b.y;
-    y.y = m[4] * a.y + m[5] * a.x + m[6] * b.y + m[7] * b.x;
-}
-
-template <int A, int NV, int NR, typename T, typename R>
-__device__ __forceinline__ void op_m(T (&v)[NV][NR], const R (&m)[8]) {
-#pragma unroll
-    for (int n = 0; n < NV; ++n)
-#pragma unroll
-        for (int i = 0; i < NR; ++i) {
-            if (i & (1 << A)) continue;
-            pair_mat(v[n][i], v[n][i | (1 << A)], m);
-        }
-}
-
-// Backward step through a D2 gate: psi <- D^H psi; then for every angle,
-// g += Re( conj(lambda) . (dD/dtheta) psi ); then lambda <- D^H lambda.
-// One derivative matrix at a time keeps the register footprint small.
-template <int A, int NV, int NR, typename T, typename R>
-__device__ __forceinline__ void op_d2bwd(T (&v)[NV][NR], const R (&mh)[8], const PK_CONST double* dmats,
-                                         double (&g)[3]) {
-    if constexpr (NV == 2) {
-#pragma unroll
-        for (int i = 0; i < NR; ++i)
-            if (!(i & (1 << A))) pair_mat(v[0][i], v[0][i | (1 << A)], mh);
-#pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            double m[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) m[e] = dmats[8 * t + e];
-            double acc = 0.0;
-#pragma unroll
-            for (int i = 0; i < NR; ++i) {
-                if (i & (1 << A)) continue;
-                const int j = i | (1 << A);
-                const double p0x = v[0][i].x, p0y = v[0][i].y, p1x = v[0][j].x, p1y = v[0][j].y;
-                const double t0x = m[0] * p0x - m[1] * p0y + m[2] * p1x - m[3] * p1y;
-                const double t0y = m[0] * p0y + m[1] * p0x + m[2] * p1y + m[3] * p1x;
-                const double t1x = m[4] * p0x - m[5] * p0y + m[6] * p1x - m[7] * p1y;
-                const double t1y = m[4] * p0y + m[5] * p0x + m[6] * p1y + m[7] * p1x;
-                acc += (double)v[1][i].x * t0x + (double)v[1][i].y * t0y + (double)v[1][j].x * t1x +
-                       (double)v[1][j].y * t1y;
-            }
-            g[t] += acc;
-        }
-#pragma unroll
-        for (int i = 0; i < NR; ++i)
-            if (!(i & (1 << A))) pair_mat(v[1][i], v[1][i | (1 << A)], mh);
-    }
-}
-
-// A two-qubit gate on register bits 0 (qubit is1) and 1 (qubit is2): the
-// registers i, i+2, i+1, i+3 (i = 0 mod 4) hold the amplitude quartet
-// |q_is1 q_is2> = |00>, |01>, |10>, |11> of one n_00 (Eqs. twoopB, resmat2) and
-// are replaced by M times it.  M is row-major complex (32 doubles), read row by
-// row through scalar loads.
-template <typename T>
-__device__ __forceinline__ void quartet_mat(T& x0, T& x1, T& x2, T& x3, const PK_CONST double* m) {
-    using R = decltype(x0.x);
-    const T in[4] = {x0, x1, x2, x3};
-    T out[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        R re = 0, im = 0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const R mr = (R)m[2 * (4 * r + c)], mi = (R)m[2 * (4 * r + c) + 1];
-            re += mr * in[c].x - mi * in[c].y;
-            im += mr * in[c].y + mi * in[c].x;
-        }
-        out[r].x = re;
-        out[r].y = im;
-    }
-    x0 = out[0];
-    x1 = out[1];
-    x2 = out[2];
-    x3 = out[3];
-}
-
-template <int NV, int NR, typename T>
-__device__ __forceinline__ void op_mat4(T (&v)[NV][NR], const PK_CONST double* m) {
-#pragma unroll
-    for (int n = 0; n < NV; ++n)
-#pragma unroll
-        for (int i = 0; i < NR; i += 4) quartet_mat(v[n][i], v[n][i + 2], v[n][i + 1], v[n][i + 3], m);
-}
-
-// Backward step through a D4 gate, as op_d2bwd with 4x4 matrices: psi <- D^H psi;
-// for every angle g += Re( conj(lambda) . (dD/dtheta) psi ); lambda <- D^H lambda.
-// `m` holds D, D^H, dD/dalpha, dD/dbeta, dD/dgamma (32 doubles each).
-template <int NV, int NR, typename T>
-__device__ __forceinline__ void op_d4bwd(T (&v)[NV][NR], const PK_CONST double* m, double (&g)[3]) {
-    if constexpr (NV == 2) {
-#pragma unroll
-        for (int i = 0; i < NR; i += 4) quartet_mat(v[0][i], v[0][i + 2], v[0][i + 1], v[0][i + 3], m + 32);
-#pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            const PK_CONST double* dm = m + 64 + 32 * t;
-            double acc = 0.0;
-#pragma unroll
-            for (int i = 0; i < NR; i += 4) {
-                const int idx[4] = {i, i + 2, i + 1, i + 3};
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    double re = 0.0, im = 0.0;
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        const double mr = dm[2 * (4 * r + c)], mi = dm[2 * (4 * r + c) + 1];
-                        const double px = v[0][idx[c]].x, py = v[0][idx[c]].y;
-                        re += mr * px - mi * py;
-                        im += mr * py + mi * px;
-                    }
-                    acc += (double)v[1][idx[r]].x * re + (double)v[1][idx[r]].y * im;
-                }
-            }
-            g[t] += acc;
-        }
-#pragma unroll
-        for (int i = 0; i < NR; i += 4) quartet_mat(v[1][i], v[1][i + 2], v[1][i + 1], v[1][i + 3], m + 32);
-    }
-}
-
-// The controlled phases of one sub-stage (CPHASE, CPHASEK; Eq. cphasek).  For
-// each accumulator slot, the factors of its phases are multiplied together,
-// each switched to 1 unless the tile index and the thread's part of the label
-// have the phase's other bits set; every register whose index holds the slot's
-// register bits then takes the product once.  The loop over a slot's phases is
-// branch-free: a phase's factor is (1 + on (c - 1), on s) with on = 0 or 1, a
-// product the compiler cannot turn into a select (which it would lower to a
-// branch around a late scalar load of c), so every table read is unconditional
-// and the loads of several phases are in flight together.  Two independent
-// product chains halve the dependent multiply latency.
-//
-// A slot's product multiplies the registers whose index holds the slot's register
-// bits.  The mask is uniform but not known at compile time, so each register's
-// test is a scalar branch around its multiply.  The empty volatile statement in
-// the branch keeps the compiler from speculating the multiply into a product for
-// every register followed by a select, and because each branch updates one
-// register in place, no other register is copied where the paths join.
-template <int NV, int NR, typename T, typename R>
-__device__ __forceinline__ void apply_slot(T (&v)[NV][NR], int pm, R c, R s) {
-#pragma unroll
-    for (int i = 0; i < NR; ++i) {
-        if ((i & pm) != pm) continue;
-        __asm__ volatile("");
-#pragma unroll
-        for (int m = 0; m < NV; ++m) {
-            const R x = v[m][i].x, y = v[m][i].y;
-            v[m][i].x = x * c - y * s;
-            v[m][i].y = x * s + y * c;
-        }
-    }
-}
-
-// The leading phase_ucnt[u] phases of a slot do not depend on the thread: their
-// product for the current tile was computed once for the workgroup (ufac, see
-// compute_tile) and starts the slot's product.
-template <int NV, int NR, typename T>
-__device__ __forceinline__ void apply_phases(const KArgs& a, const PK_CONST Stage* S, T (&v)[NV][NR],
-                                             const Layout& L, int64_t tile, const double* ufac) {
-    using R = decltype(v[0][0].x);
-    const PK_CONST PhaseOp* ph = cptr(a.phases) + S->phase_first;
-    // the sub-stage's slot table as four 16-byte loads issued together (reading the
-    // fields where they are used costs one scalar round trip per field and slot)
-    typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
-    const i32x4 pms = *reinterpret_cast<const PK_CONST i32x4*>(S->phase_pm);
-    const i32x4 cnts = *reinterpret_cast<const PK_CONST i32x4*>(S->phase_cnt);
-    const i32x4 ucnts = *reinterpret_cast<const PK_CONST i32x4*>(S->phase_ucnt);
-    const i32x4 pairs = *reinterpret_cast<const PK_CONST i32x4*>(S->phase_upair);
-#pragma unroll
-    for (int u = 0; u < kPhaseSlots; ++u) {
-        const int cnt = cnts[u];
-        if (cnt == 0) continue;
-        R c0 = 1, s0 = 0, c1 = 1, s1 = 0;
-        const int pair = pairs[u];
-        if (pair >= 0) {
-            c0 = (R)ufac[2 * pair];
-            s0 = (R)ufac[2 * pair + 1];
-        }
-        int q = ucnts[u];
-#pragma unroll 2
-        for (; q + 1 < cnt; q += 2) {
-            const int64_t fa = ph[q].fmask, fb = ph[q + 1].fmask;
-            const unsigned ta = ph[q].tmask, tb = ph[q + 1].tmask;
-            const R oa = (R)(((tile & fa) == fa) & ((L.jt & ta) == ta));
-            const R ob = (R)(((tile & fb) == fb) & ((L.jt & tb) == tb));
-            const R ca = fma(oa, (R)ph[q].cm1, (R)1), sa = oa * (R)ph[q].s;
-            const R cb = fma(ob, (R)ph[q + 1].cm1, (R)1), sb = ob * (R)ph[q + 1].s;
-            R x = c0, y = s0;
-            c0 = x * ca - y * sa;
-            s0 = x * sa + y * ca;
-            x = c1;
-            y = s1;
-            c1 = x * cb - y * sb;
-            s1 = x * sb + y * cb;
-        }
-        if (q < cnt) {
-            const int64_t fa = ph[q].fmask;
-            const unsigned ta = ph[q].tmask;
-            const R oa = (R)(((tile & fa) == fa) & ((L.jt & ta) == ta));
-            const R ca = fma(oa, (R)ph[q].cm1, (R)1), sa = oa * (R)ph[q].s;
-            const R x = c0, y = s0;
-            c0 = x * ca - y * sa;
-            s0 = x * sa + y * ca;
-        }
-        ph += cnt;
-        const R c = c0 * c1 - s0 * s1, s = c0 * s1 + s0 * c1;
-        apply_slot<NV, NR>(v, pms[u], c, s);
-    }
-}
-
-// Hadamards on the register bits set in `mask` (distinct bits commute).
-template <int NV, int NR, typename T>
-__device__ __forceinline__ void apply_hmask(T (&v)[NV][NR], int mask) {
-    if (mask & 1) op_h<0, NV, NR>(v);
-    if (mask & 2) op_h<1, NV, NR>(v);
-    if (mask & 4) op_h<2, NV, NR>(v);
-    if (mask & 8) op_h<3, NV, NR>(v);
-    if constexpr (NR > 16)
-        if (mask & 16) op_h<4, NV, NR>(v);
-}
-
-template <int NV, int NR, typename T, typename R>
-__device__ __forceinline__ void apply_mat(T (&v)[NV][NR], int a, const R (&m)[8]) {
-    if (a == 0) op_m<0, NV, NR>(v, m);
-    if (a == 1) op_m<1, NV, NR>(v, m);
-    if (a == 2) op_m<2, NV, NR>(v, m);
-    if (a == 3) op_m<3, NV, NR>(v, m);
-    if constexpr (NR > 16)
-        if (a == 4) op_m<4, NV, NR>(v, m);
-}
-
-template <int NV, int NR, typename T, typename R>
-__device__ __forceinline__ void apply_d2bwd(T (&v)[NV][NR], int a, const R (&mh)[8], const PK_CONST double* dmats,
-                                            double (&g)[3]) {
-    if (a == 0) op_d2bwd<0, NV, NR>(v, mh, dmats, g);
-    if (a == 1) op_d2bwd<1, NV, NR>(v, mh, dmats, g);
-    if (a == 2) op_d2bwd<2, NV, NR>(v, mh, dmats, g);
-    if (a == 3) op_d2bwd<3, NV, NR>(v, mh, dmats, g);
-    if constexpr (NR > 16)
-        if (a == 4) op_d2bwd<4, NV, NR>(v, mh, dmats, g);
-}
-
-// Sum of one double per thread over the workgroup; result valid in thread 0.
-template <int NT>
-__device__ __forceinline__ double block_sum(double x, double* red) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) red[wave] = x;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0) {
-        for (int w = 0; w < (NT + 63) / 64; ++w) s += red[w];
-    }
-    __syncthreads();
-    return s;
-}
-
-// ---------------------------------------------------------------------------- one tile
-
-// Per-pass constants of a workgroup: they do not depend on the tile.
-struct PassCtx {
-    int nrb, nreg, flags, nstages;
-    bool active;
-    Layout L0, Ll;  // first (load) and last (store) stage layouts
-    GOff G0, Gl;
-};
-
-template <int ESZ, int RB>
-__device__ __forceinline__ PassCtx make_ctx(const KArgs& a, const PK_CONST Pass* P) {
-    PassCtx C;
-    const int k = P->k;
-    C.nrb = k < RB ? k : RB;
-    C.nreg = 1 << C.nrb;
-    C.flags = P->flags;
-    C.nstages = P->nstages;
-    const unsigned nact = k >= RB ? (1u << (k - RB)) : 1u;
-    C.active = threadIdx.x < nact;
-    const PK_CONST Stage* S0 = cptr(a.stages) + P->stage_begin;
-    const PK_CONST Stage* Sl = S0 + (C.nstages - 1);
-    C.L0 = make_layout<ESZ>(S0, C.nrb, threadIdx.x);
-    C.Ll = make_layout<ESZ>(Sl, C.nrb, threadIdx.x);
-    C.G0 = make_goff(P, S0, C.L0, C.nrb, false);
-    C.Gl = make_goff(P, Sl, C.Ll, C.nrb, true);
-    return C;
-}
-
-// HBM -> registers in the first stage's layout.  `base` is the tile's first
-// state label.  The uniform part (tile base + register offset) and the thread's
-// part stay apart, so each load is a 64-bit scalar base plus a 32-bit lane
-// offset; a wide pass (lane offsets beyond 32 bits) adds in 64 bits.
-template <typename R, int NV, int NR>
-__device__ __forceinline__ void load_tile(const KArgs& a, const PassCtx& C, int64_t base,
-                                          typename Cplx<R>::T (&v)[NV][NR]) {
-    using T = typename Cplx<R>::T;
-    if (C.nreg < NR || NV == 2) {
-#pragma unroll
-        for (int n = 0; n < NV; ++n)
-#pragma unroll
-            for (int i = 0; i < NR; ++i) v[n][i] = T{0, 0};
-    }
-    if (!C.active) return;
-    const char* in0 = reinterpret_cast<const char*>((C.flags & PASS_FIRST) ? a.src0 : a.dst0);
-    const char* in1 = reinterpret_cast<const char*>(a.dst1);
-    const bool read1 = NV == 2 && !(C.flags & PASS_SEED_V1);
-    if (!(C.flags & PASS_WIDE)) {
-        const uint32_t lane = (uint32_t)C.G0.gt * (uint32_t)sizeof(T);
-#pragma unroll
-        for (int i = 0; i < NR; ++i) {
-            if (i >= C.nreg) continue;
-            const int64_t u = (base + goff(C.G0, i)) * (int64_t)sizeof(T);
-            v[0][i] = *reinterpret_cast<const T*>(in0 + u + lane);
-            if constexpr (NV == 2)
-                if (read1) v[1][i] = *reinterpret_cast<const T*>(in1 + u + lane);
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < NR; ++i) {
-            if (i >= C.nreg) continue;
-            const int64_t e = base + C.G0.gt + goff(C.G0, i);
-            v[0][i] = reinterpret_cast<const T*>(in0)[e];
-            if constexpr (NV == 2)
-                if (read1) v[1][i] = reinterpret_cast<const T*>(in1)[e];
-        }
-    }
-}
-
-// Registers -> HBM in the last stage's layout.
-template <typename R, int NV, int NR>
-__device__ __forceinline__ void store_tile(const KArgs& a, const PassCtx& C, int64_t base,
-                                           const typename Cplx<R>::T (&v)[NV][NR]) {
-    using T = typename Cplx<R>::T;
-    if (!C.active) return;
-    char* out0 = reinterpret_cast<char*>(a.dst0);
-    char* out1 = reinterpret_cast<char*>(a.dst1);
-    const bool write0 = !(C.flags & PASS_SKIP_V0);
-    if (!(C.flags & PASS_WIDE)) {
-        const uint32_t lane = (uint32_t)C.Gl.gt * (uint32_t)sizeof(T);
-#pragma unroll
-        for (int i = 0; i < NR; ++i) {
-            if (i >= C.nreg) continue;
-            const int64_t u = (base + goff(C.Gl, i)) * (int64_t)sizeof(T);
-            if (write0) *reinterpret_cast<T*>(out0 + u + lane) = v[0][i];
-            if constexpr (NV == 2) *reinterpret_cast<T*>(out1 + u + lane) = v[1][i];
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < NR; ++i) {
-            if (i >= C.nreg) continue;
-            const int64_t e = base + C.Gl.gt + goff(C.Gl, i);
-            if (write0) reinterpret_cast<T*>(out0)[e] = v[0][i];
-            if constexpr (NV == 2) reinterpret_cast<T*>(out1)[e] = v[1][i];
-        }
-    }
-}
-
-// One-amplitude steps on the element flips[f] when it lies in this tile and
-// thread: KIND 0 negates it (Oracle, Inv's C_0), 1 stores |C|^2 to its readout
-// slot, 2 seeds lambda = dL * psi there.  Written as selects, so the register
-// tile is updated in place.
-template <int NV, int NR, int KIND, typename T>
-__device__ __forceinline__ void element_op(const KArgs& a, T (&v)[NV][NR], const Layout& L, int f, int64_t tile,
-                                           int nreg, bool active) {
-    const PK_CONST Flip* fl = cptr(a.flips) + f;
-    if (fl->tile != tile || !active) return;
-    const unsigned jrel = (unsigned)fl->j ^ L.jt;
-    unsigned rmask = 0;
-#pragma unroll
-    for (int q = 0; q < kMaxRegBits; ++q) rmask |= L.r[q];
-    if ((jrel & ~rmask) != 0u) return;
-    const int slot = fl->slot;
-#pragma unroll
-    for (int i = 0; i < NR; ++i) {
-        if (i >= nreg) continue;
-        const bool hit = roff(L, i) == jrel;
-        if constexpr (KIND == 0) {
-#pragma unroll
-            for (int n = 0; n < NV; ++n) {
-                v[n][i].x = hit ? -v[n][i].x : v[n][i].x;
-                v[n][i].y = hit ? -v[n][i].y : v[n][i].y;
-            }
-        } else if constexpr (KIND == 1) {
-            if (hit) {
-                const double x = v[0][i].x, y = v[0][i].y;
-                a.reads[slot] = x * x + y * y;
-            }
-        } else if constexpr (NV == 2) {
-            const auto d = (decltype(v[0][0].x))a.dL[slot];
-            v[1][i].x = hit ? d * v[0][i].x : v[1][i].x;
-            v[1][i].y = hit ? d * v[0][i].y : v[1][i].y;
-        }
-    }
-}
-
-// Every stage of the pass on one tile held in registers, then the norm partial.
-template <typename R, int NV, int KMAX, int RB>
-__device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass* P, const PassCtx& C,
-                                             int64_t tile, typename Cplx<R>::T (&v)[NV][1 << RB],
-                                             typename Cplx<R>::T* lds, double* red) {
-    constexpr int NT = 1 << (KMAX - RB);
-    constexpr int NR = 1 << RB;
-    const unsigned tid = threadIdx.x;
-    const bool active = C.active;
-    const int nreg = C.nreg;
-    const PK_CONST Stage* S = cptr(a.stages) + P->stage_begin;
-    Layout L = C.L0;
-    // tile-uniform phase products of the pass: one thread per product, in FP64,
-    // between two barriers (the previous tile's sub-stages may still read the table)
-    double* ufac = red + 16;
-    const int nup = P->nupair;
-    if (nup > 0) {
-        __syncthreads();
-        const PK_CONST UPair* U = cptr(a.upairs) + P->upair_begin;
-        for (int p = tid; p < nup; p += NT) {
-            const PK_CONST PhaseOp* ph = cptr(a.phases) + U[p].first;
-            const int cnt = U[p].count;
-            double c = 1.0, sn = 0.0;
-            // the table entries of eight phases are loaded before any is used, so
-            // their latencies overlap; the product keeps the phases' order
-            constexpr int kB = 8;
-            for (int q0 = 0; q0 < cnt; q0 += kB) {
-                int64_t fm[kB];
-                double cm1[kB], sq[kB];
-#pragma unroll
-                for (int j = 0; j < kB; ++j) {
-                    const bool in = q0 + j < cnt;
-                    fm[j] = in ? ph[q0 + j].fmask : 0;
-                    cm1[j] = in ? ph[q0 + j].cm1 : 0.0;
-                    sq[j] = in ? ph[q0 + j].s : 0.0;
-                }
-#pragma unroll
-                for (int j = 0; j < kB; ++j) {
-                    if (q0 + j >= cnt || (tile & fm[j]) != fm[j]) continue;
-                    const double cq = 1.0 + cm1[j];
-                    const double x = c;
-                    c = x * cq - sn * sq[j];
-                    sn = x * sq[j] + sn * cq;
-                }
-            }
-            ufac[2 * p] = c;
-            ufac[2 * p + 1] = sn;
-        }
-        __syncthreads();
-    }
-    for (int s = 0; s < C.nstages; ++s, ++S) {
-        // one scalar word says which steps follow; only their parameters are loaded
-        const int steps = S->steps;
-        // the one-qubit steps' parameters (mat_pre_a .. mat_post) in two 16-byte loads
-        // issued with the step word, not one scalar round trip per step
-        typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
-        const i32x4 sp0 = *reinterpret_cast<const PK_CONST i32x4*>(&S->mat_pre_a);
-        const i32x4 sp1 = *reinterpret_cast<const PK_CONST i32x4*>(&S->hmask2);
-        const int mat_pre_a = sp0.x, mat_pre = sp0.y, hmask1 = sp0.z, flip_mid = sp0.w;
-        const int hmask2 = sp1.x, mat_post_a = sp1.y, mat_post = sp1.z;
-        if (s > 0 && (steps & ST_EXCHANGE)) {
-            // ---- LDS exchange: previous layout out, this layout in
-            const Layout Ln = (s == C.nstages - 1) ? C.Ll : make_layout<(int)sizeof(R) * 2>(S, C.nrb, tid);
-#pragma unroll
-            for (int n = 0; n < NV; ++n) {
-                if (active) {
-#pragma unroll
-                    for (int i = 0; i < NR; ++i)
-                        if (i < nreg) lds[L.pj ^ poff(L, i)] = v[n][i];
-                }
-                __syncthreads();
-                if (active) {
-#pragma unroll
-                    for (int i = 0; i < NR; ++i)
-                        if (i < nreg) v[n][i] = lds[Ln.pj ^ poff(Ln, i)];
-                }
-                __syncthreads();
-            }
-            L = Ln;
-        }
-        // ---- the sub-stage's steps, in their fixed order
-        if constexpr (NV == 2) {
-            if (steps & ST_SEED) element_op<NV, NR, 2>(a, v, L, S->seed, tile, nreg, active);
-        }
-        if (steps & ST_FLIP_PRE) element_op<NV, NR, 0>(a, v, L, S->flip_pre, tile, nreg, active);
-        if ((steps & ST_PHASE) && active) apply_phases<NV, NR>(a, S, v, L, tile, ufac);
-        if (steps & ST_MAT_PRE) {
-            R m[8];
-            const PK_CONST double* mp = cptr(a.mats) + 8 * mat_pre;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) m[e] = (R)mp[e];
-            apply_mat<NV, NR>(v, mat_pre_a, m);
-        }
-        if (steps & ST_H1) apply_hmask<NV, NR>(v, hmask1);
-        if (steps & ST_FLIP_MID) element_op<NV, NR, 0>(a, v, L, flip_mid, tile, nreg, active);
-        if (steps & ST_H2) apply_hmask<NV, NR>(v, hmask2);
-        if (steps & ST_MAT_POST) {
-            R m[8];
-            const PK_CONST double* mp = cptr(a.mats) + 8 * mat_post;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) m[e] = (R)mp[e];
-            apply_mat<NV, NR>(v, mat_post_a, m);
-        }
-        if ((steps & ST_MAT4) && active) op_mat4<NV, NR>(v, cptr(a.mats4) + 32 * S->mat4);
-        if constexpr (NV == 2) {
-            if (steps & ST_D2B) {
-                R mh[8];
-                const PK_CONST double* mp = cptr(a.mats) + 8 * S->d2b_mat;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) mh[e] = (R)mp[8 + e];
-                double g[3] = {0.0, 0.0, 0.0};
-                if (active) apply_d2bwd<NV, NR>(v, S->d2b_a, mh, mp + 16, g);
-                const double scale = 2.0 * (double)S->d2b_gscale;
-                const int gslot = S->d2b_gslot;
-#pragma unroll
-                for (int t = 0; t < 3; ++t) {
-                    const double tot = block_sum<NT>(g[t], red);
-                    if (tid == 0) a.gpart[gslot + t * P->ntiles + tile] = scale * tot;
-                }
-            }
-            if (steps & ST_D4B) {
-                double g[3] = {0.0, 0.0, 0.0};
-                if (active) op_d4bwd<NV, NR>(v, cptr(a.mats4) + 32 * S->d4b_mat, g);
-                const double scale = 2.0 * (double)S->d4b_gscale;
-                const int gslot = S->d4b_gslot;
-#pragma unroll
-                for (int t = 0; t < 3; ++t) {
-                    const double tot = block_sum<NT>(g[t], red);
-                    if (tid == 0) a.gpart[gslot + t * P->ntiles + tile] = scale * tot;
-                }
-            }
-        }
-        if (steps & ST_SCALE) {
-            const R sc = (R)P->scale;
-#pragma unroll
-            for (int n = 0; n < NV; ++n)
-#pragma unroll
-                for (int i = 0; i < NR; ++i) {
-                    v[n][i].x *= sc;
-                    v[n][i].y *= sc;
-                }
-        }
-        if (steps & ST_READ) element_op<NV, NR, 1>(a, v, L, S->read, tile, nreg, active);
-    }
-
-    // ---- norm partial of the final state (FP64 for FP64 data; Neumaier-
-    //      compensated FP32 lane sums, then FP64, for FP32 data)
-    if (a.want_norm && (C.flags & PASS_LAST)) {
-        double part = 0.0;
-        if (active) {
-            if constexpr (sizeof(R) == 8) {
-#pragma unroll
-                for (int i = 0; i < NR; ++i)
-                    if (i < nreg) part += v[0][i].x * v[0][i].x + v[0][i].y * v[0][i].y;
-            } else {
-                float s = 0.0f, c = 0.0f;
-#pragma unroll
-                for (int i = 0; i < NR; ++i) {
-                    if (i >= nreg) continue;
-                    const float term = v[0][i].x * v[0][i].x + v[0][i].y * v[0][i].y;
-                    const float t = s + term;
-                    c += (fabsf(s) >= fabsf(term)) ? ((s - t) + term) : ((term - t) + s);
-                    s = t;
-                }
-                part = (double)s + (double)c;
-            }
-        }
-        const double tot = block_sum<NT>(part, red);
-        if (tid == 0) a.partials[P->part_base + tile] = tot;
-    }
-}
-
-// Tiles first, first + stride, ... (below ntiles) of one pass.  With one vector, two register
-// buffers alternate: the next tile's HBM loads are issued before the current
-// tile's LDS stages, so memory traffic overlaps the exchange work of the one
-// workgroup an LDS-sized tile leaves per CU.  The prefetch is unconditional
-// (past the end it re-reads the current tile) so the wait counts stay static.
-template <typename R, int NV, int KMAX, int RB>
-__device__ __forceinline__ void run_tiles(const KArgs& a, const PK_CONST Pass* P, int64_t first,
-                                          int64_t stride, int64_t ntiles, typename Cplx<R>::T* lds, double* red) {
-    using T = typename Cplx<R>::T;
-    constexpr int NR = 1 << RB;
-    if (first >= ntiles) return;
-    const PassCtx C = make_ctx<(int)sizeof(R) * 2, RB>(a, P);
-    const int64_t off = P->state_off;
-    const int nfrun = P->nfrun;
-    auto base_of = [&](int64_t t) { return off + deposit(t, P->frun, nfrun); };
-    if constexpr (NV == 2) {
-        // two vectors already fill the register file: no second buffer
-        for (int64_t tile = first; tile < ntiles; tile += stride) {
-            T v[NV][NR];
-            const int64_t base = base_of(tile);
-            load_tile<R, NV, NR>(a, C, base, v);
-            compute_tile<R, NV, KMAX, RB>(a, P, C, tile, v, lds, red);
-            store_tile<R, NV, NR>(a, C, base, v);
-        }
-    } else {
-        T va[1][NR], vb[1][NR];
-        int64_t ta = first;
-        int64_t basea = base_of(ta);
-        load_tile<R, 1, NR>(a, C, basea, va);
-        for (;;) {
-            const int64_t tb = ta + stride;
-            const int64_t baseb = base_of(tb < ntiles ? tb : ta);
-            load_tile<R, 1, NR>(a, C, baseb, vb);
-            compute_tile<R, 1, KMAX, RB>(a, P, C, ta, va, lds, red);
-            store_tile<R, 1, NR>(a, C, basea, va);
-            if (tb >= ntiles) break;
-            const int64_t tc = tb + stride;
-            const int64_t basec = base_of(tc < ntiles ? tc : tb);
-            load_tile<R, 1, NR>(a, C, basec, va);
-            compute_tile<R, 1, KMAX, RB>(a, P, C, tb, vb, lds, red);
-            store_tile<R, 1, NR>(a, C, baseb, vb);
-            if (tc >= ntiles) break;
-            ta = tc;
-            basea = basec;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------- kernels
-
-template <typename R, int NV, int KMAX, int RB>
-__global__ void __launch_bounds__(1 << (KMAX - RB)) pass_kernel(KArgs a) {
-    using T = typename Cplx<R>::T;
-    __shared__ T lds[1 << KMAX];
-    __shared__ double red[16 + 2 * kMaxUPairs];  // reduction scratch, then the tile-uniform phase products
-    const PK_CONST Pass* P = cptr(a.passes) + a.pass;
-    run_tiles<R, NV, KMAX, RB>(a, P, blockIdx.x, gridDim.x, P->ntiles, lds, red);
-}
-
-// Team barrier of the batched launch: every member adds one to the team's
-// counter after its tiles, then waits until all team_size members of this
-// round have.  Device-scope fences on both sides make the members' stores
-// visible across CUs and XCDs.  The wait is bounded by `ticks` of the
-// constant-rate wall clock: on time-out (the team's workgroups are not all
-// resident) the barrier returns false, and a workgroup whose barrier failed
-// once no longer waits at later ones, so every wave reaches the kernel's end.
-__device__ __forceinline__ bool team_barrier(unsigned int* bar, unsigned int target, uint64_t ticks, bool broken,
-                                             int* flag) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        atomicAdd(bar, 1u);
-        int ok = 0;
-        if (!broken) {
-            const uint64_t t0 = wall_clock64();
-            for (;;) {
-                if (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) {
-                    ok = 1;
-                    break;
-                }
-                if (wall_clock64() - t0 > ticks) break;
-                __builtin_amdgcn_s_sleep(2);
-            }
-        }
-        __threadfence();
-        *flag = ok;
-    }
-    __syncthreads();
-    return *flag != 0;
-}
-
-// L and the norm of one finished instance, written by one workgroup.
-template <int NT>
-__device__ __forceinline__ void finish_instance(const KArgs& a, const PK_CONST InstDesc* D, int inst, bool ok,
-                                                double* L_out, double* norm_out, double* red) {
-    if (threadIdx.x == 0) {
-        double L = 0.0;
-        for (int m = 0; m < D->nmarked; ++m) L += a.reads[D->read_base + m];
-        L_out[inst] = ok ? L : __builtin_nan("");
-    }
-    if (norm_out) {
-        double s = 0.0;
-        const int64_t nt = D->ntiles_last, pb = D->part_base;
-        for (int64_t t = threadIdx.x; t < nt; t += NT) s += a.partials[pb + t];
-        const double tot = block_sum<NT>(s, red);
-        if (threadIdx.x == 0) norm_out[inst] = ok ? tot : __builtin_nan("");
-    }
-    __syncthreads();
-}
-
-// Multiverse batch in one persistent launch.  First the teams: the j-th
-// workgroup of XCD x (w = j * n_xcd + x) is member j mod team_size of team
-// (j / team_size) * n_xcd + x; a team walks the passes of its large instances
-// together, its members taking the tiles of each pass in turn, with a team
-// barrier between passes.  Then every workgroup takes whole instances from the
-// queue (largest first) and runs all their passes itself.
-template <typename R, int KMAX, int RB>
-__global__ void __launch_bounds__(1 << (KMAX - RB)) batched_kernel(KArgs a, BatchArgs b) {
-    using T = typename Cplx<R>::T;
-    constexpr int NT = 1 << (KMAX - RB);
-    __shared__ T lds[1 << KMAX];
-    __shared__ double red[16 + 2 * kMaxUPairs];  // reduction scratch, then the tile-uniform phase products
-    __shared__ int item;
-    __shared__ int flag;
-    const PK_CONST InstDesc* idesc = cptr(b.idesc);
-    const int w = blockIdx.x;
-    const int xcd = w % b.n_xcd, j = w / b.n_xcd;
-    const int team = b.team_size > 0 ? (j / b.team_size) * b.n_xcd + xcd : b.n_teams;
-    if (team < b.n_teams) {
-        const int member = j % b.team_size;
-        unsigned int target = 0;
-        bool broken = false;
-        const int q0 = cptr(b.team_off)[team], q1 = cptr(b.team_off)[team + 1];
-        for (int q = q0; q < q1; ++q) {
-            const int inst = cptr(b.team_list)[q];
-            const PK_CONST InstDesc* D = idesc + inst;
-            bool ok = true;
-            for (int p = 0; p < D->npass; ++p) {
-                const PK_CONST Pass* P = cptr(a.passes) + D->first_pass + p;
-                run_tiles<R, 1, KMAX, RB>(a, P, member, b.team_size, P->ntiles, lds, red);
-                target += (unsigned int)b.team_size;
-                const bool passed = team_barrier(b.bars + team, target, b.spin_ticks, broken, &flag);
-                broken = broken || !passed;
-                ok = ok && passed;
-            }
-            if (member == 0) finish_instance<NT>(a, D, inst, ok, b.L_out, b.norm_out, red);
-        }
-    }
-    for (;;) {
-        if (threadIdx.x == 0) item = (int)atomicAdd(b.queue, 1u);
-        __syncthreads();
-        const int it = item;
-        __syncthreads();
-        if (it >= b.n_solo) break;
-        const int inst = cptr(b.order)[it];
-        const PK_CONST InstDesc* D = idesc + inst;
-        for (int p = 0; p < D->npass; ++p) {
-            const PK_CONST Pass* P = cptr(a.passes) + D->first_pass + p;
-            run_tiles<R, 1, KMAX, RB>(a, P, 0, 1, P->ntiles, lds, red);
-            // this workgroup's stores must be visible to its own loads of the next pass
-            __threadfence_block();
-            __syncthreads();
-        }
-        finish_instance<NT>(a, D, inst, true, b.L_out, b.norm_out, red);
-    }
-}
 
 // D^(1/2): five 2x2 matrices D, D^H, dD/dalpha, dD/dbeta, dD/dgamma with
 // D = R_z(alpha) R_y(beta) R_z(gamma) written out element by element.
@@ -1033,54 +135,6 @@ __global__ void pair_index_kernel(int32_t nq, int32_t i_s, int64_t first, int64_
 
 // ---------------------------------------------------------------------------- host launchers
 
-// Persistent launch: as many workgroups as fit on the device at once (capped by
-// the tile count); each walks its tiles with the load of the next one in flight.
-template <typename R, int NV, int KMAX, int RB>
-static hipError_t launch_pass_t(const KArgs& a, int64_t ntiles, int64_t wgs_per_cu, hipStream_t st) {
-    static int ncu = 0, per_cu = 0;  // queried once per kernel instance
-    if (ncu == 0) {
-        int dev = 0;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-        auto kfn = pass_kernel<R, NV, KMAX, RB>;
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, 1 << (KMAX - RB), 0);
-        if (ncu <= 0) ncu = 256;
-        if (per_cu <= 0) per_cu = 1;
-    }
-    int64_t grid = (int64_t)ncu * (wgs_per_cu > 0 ? wgs_per_cu : per_cu);
-    if (grid > ntiles) grid = ntiles;
-    if (grid < 1) grid = 1;
-    hipLaunchKernelGGL((pass_kernel<R, NV, KMAX, RB>), dim3((unsigned)grid), dim3(1 << (KMAX - RB)), 0, st, a);
-    return hipGetLastError();
-}
-
-// Kernel instances: one vector with 4 or 5 register bits, two vectors with 4.
-template <typename R, int NV, int RB>
-static hipError_t launch_pass_r(int kmax, const KArgs& a, int64_t ntiles, int64_t cap, hipStream_t st) {
-    if constexpr (RB == 4) {
-        switch (kmax) {
-        case 10: return launch_pass_t<R, NV, 10, 4>(a, ntiles, cap, st);
-        case 11: return launch_pass_t<R, NV, 11, 4>(a, ntiles, cap, st);
-        case 12: return launch_pass_t<R, NV, 12, 4>(a, ntiles, cap, st);
-        case 13: return launch_pass_t<R, NV, 13, 4>(a, ntiles, cap, st);
-        case 14:
-            if constexpr (sizeof(R) == 4) return launch_pass_t<R, NV, 14, 4>(a, ntiles, cap, st);
-            return hipErrorInvalidValue;
-        default: return hipErrorInvalidValue;
-        }
-    } else {
-        switch (kmax) {
-        case 11: return launch_pass_t<R, NV, 11, 5>(a, ntiles, cap, st);
-        case 12: return launch_pass_t<R, NV, 12, 5>(a, ntiles, cap, st);
-        case 13: return launch_pass_t<R, NV, 13, 5>(a, ntiles, cap, st);
-        case 14:
-            if constexpr (sizeof(R) == 4) return launch_pass_t<R, NV, 14, 5>(a, ntiles, cap, st);
-            return hipErrorInvalidValue;
-        default: return hipErrorInvalidValue;
-        }
-    }
-}
-
 static KArgs kargs(const PassLaunch& L) {
     KArgs a;
     a.passes = L.passes;
@@ -1116,48 +170,6 @@ hipError_t launch_pass(const PassLaunch& L, hipStream_t st) {
                   : launch_pass_r<float, 1, 4>(L.kmax, a, L.ntiles, L.grid_cap, st);
 }
 
-template <typename R, int KMAX, int RB>
-static hipError_t launch_batched_t(const KArgs& a, const BatchArgs& B, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL((batched_kernel<R, KMAX, RB>), dim3(grid), dim3(1 << (KMAX - RB)), 0, st, a, B);
-    return hipGetLastError();
-}
-
-template <typename R, int KMAX, int RB>
-static int batched_occupancy_t() {
-    int per_cu = 0;
-    auto kfn = batched_kernel<R, KMAX, RB>;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, 1 << (KMAX - RB), 0) != hipSuccess) return 0;
-    return per_cu;
-}
-
-// Kernel instances of the batched launch: KMAX 10..13 (14 for FP32), RB 4 or 5.
-template <typename R, int RB, typename F>
-static auto batched_instance(int kmax, F&& f) {
-    switch (kmax) {
-    case 10:
-        if constexpr (RB == 4) return f(std::integral_constant<int, 10>{});
-        break;
-    case 11: return f(std::integral_constant<int, 11>{});
-    case 12: return f(std::integral_constant<int, 12>{});
-    case 13: return f(std::integral_constant<int, 13>{});
-    case 14:
-        if constexpr (sizeof(R) == 4) return f(std::integral_constant<int, 14>{});
-        break;
-    default: break;
-    }
-    return decltype(f(std::integral_constant<int, 13>{})){};
-}
-
-template <typename R, int RB>
-static hipError_t launch_batched_r(int kmax, const KArgs& a, const BatchArgs& B, unsigned grid, hipStream_t st) {
-    bool found = false;
-    hipError_t e = batched_instance<R, RB>(kmax, [&](auto K) {
-        found = true;
-        return launch_batched_t<R, decltype(K)::value, RB>(a, B, grid, st);
-    });
-    return found ? e : hipErrorInvalidValue;
-}
-
 hipError_t launch_batched(const PassLaunch& L, const BatchArgs& B, unsigned grid, hipStream_t st) {
     KArgs a = kargs(L);
     a.dst1 = nullptr;
@@ -1169,11 +181,6 @@ hipError_t launch_batched(const PassLaunch& L, const BatchArgs& B, unsigned grid
                       : launch_batched_r<float, 5>(L.kmax, a, B, grid, st);
     return L.fp64 ? launch_batched_r<double, 4>(L.kmax, a, B, grid, st)
                   : launch_batched_r<float, 4>(L.kmax, a, B, grid, st);
-}
-
-template <typename R, int RB>
-static int batched_occupancy_r(int kmax) {
-    return batched_instance<R, RB>(kmax, [&](auto K) { return batched_occupancy_t<R, decltype(K)::value, RB>(); });
 }
 
 int batched_blocks_per_cu(int kmax, int rbits, bool fp64) {

@@ -220,6 +220,28 @@ int pk_evaluate(pk_plan* plan, const void* psi_in, void* psi_out, double* L_out,
                 const double* angles, void* workspace, void* stream);
 
 /*
+ * pk_evaluate_static -- pk_evaluate for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The same kernels as pk_evaluate, but their workspace is a
+ * static device buffer of the library, PK_STATIC_WORKSPACE_BYTES per GPU (held
+ * by each GPU the library runs on until the process ends), and the launches go
+ * to `stream` directly: the call allocates nothing and builds no graph.
+ * Arguments as pk_evaluate, without `workspace`; the caller still owns
+ * psi_in, psi_out, L_out and norm_out.
+ * Set-up: the plan's tables must already be on the current device (any earlier
+ * pk_evaluate or pk_batch_teams with that device current uploads them);
+ * otherwise PK_EINVAL.  PK_EINVAL too when the plan's workspace
+ * (pk_workspace_bytes(PK_OP_EVAL)) exceeds PK_STATIC_WORKSPACE_BYTES.
+ * Every call on one GPU shares that GPU's buffer, which keeps the last call's
+ * contents: calls that overlap on one GPU (other streams, other threads) race
+ * and give wrong results; order them on one stream.  Nothing in the buffer needs
+ * to start at zero.
+ */
+#define PK_STATIC_WORKSPACE_BYTES (8 << 20)
+int pk_evaluate_static(pk_plan* plan, const void* psi_in, void* psi_out, double* L_out, double* norm_out,
+                       const double* angles, void* stream);
+
+/*
  * pk_evaluate_repeat -- apply the gate list of a single-instance plan `reps`
  * times in a row: psi_out = U^reps psi_in.  With the list of one Grover
  * iteration G = HALL . Inv . HALL . Oracle this is the whole search of Sec. 5.1,

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -371,6 +372,33 @@ int recompile_or_restore(DevPlan* d, const Tiling& previous) {
     return fail(d, rc, err);
 }
 
+// The workspace of pk_evaluate_static: a device array of fixed size that every
+// call on a GPU shares (each GPU holds its own copy until the process ends).
+// Host code never passes `scratch` itself to a kernel (its host-side name is not
+// a device address): the device address comes from hipGetSymbolAddress, once per
+// device, with that device current.
+constexpr size_t kStaticWorkspaceBytes = (size_t)8 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's `scratch` (looked up on the first call per device).
+hipError_t static_workspace(int dev, void** out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -509,6 +537,33 @@ int pk_evaluate(pk_plan* plan, const void* psi_in, void* psi_out, double* L_out,
     const void* const key[8] = {psi_in, psi_out, L_out, norm_out, angles, workspace, nullptr, nullptr};
     return run_graphed(d, G_EVAL, key, static_cast<hipStream_t>(stream),
                        [&](hipStream_t s) { return enqueue_eval(d, a, s, nullptr); });
+}
+
+int pk_evaluate_static(pk_plan* plan, const void* psi_in, void* psi_out, double* L_out, double* norm_out,
+                       const double* angles, void* stream) {
+    if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");
+    DevPlan* d = dp(plan);
+    if (d->host.inst.size() != 1) return fail(d, PK_EINVAL, "pk_evaluate_static needs a single-instance plan");
+    const size_t need = workspace_layout(&d->host, PK_OP_EVAL).total;
+    if (need > kStaticWorkspaceBytes)
+        return fail(d, PK_EINVAL,
+                    "the plan needs " + std::to_string(need) + " bytes of workspace; the static buffer holds " +
+                        std::to_string(kStaticWorkspaceBytes) + " (use larger tiles, or pk_evaluate)");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(d, e, "hipGetDevice");
+    if (!d->host.d_tables || d->host.device != dev)
+        return fail(d, PK_EINVAL,
+                    "the plan's tables are not on this device: upload them first (pk_evaluate or pk_batch_teams "
+                    "with this device current)");
+    void* ws = nullptr;
+    e = static_workspace(dev, &ws);
+    if (e != hipSuccess) return hip_fail(d, e, "hipGetSymbolAddress(scratch)");
+    int rc = check_eval_args(d, psi_in, psi_out, L_out, norm_out, angles, ws);
+    if (rc != PK_OK) return rc;
+    EvalArgs a{psi_in, psi_out, L_out, norm_out, angles, ws};
+    e = enqueue_eval(d, a, static_cast<hipStream_t>(stream), nullptr);
+    return e == hipSuccess ? PK_OK : hip_fail(d, e, "pk_evaluate_static");
 }
 
 int pk_evaluate_repeat(pk_plan* plan, int64_t reps, const void* psi_in, void* psi_out, double* L_out,

@@ -55,6 +55,7 @@ SIGNATURES = {
     "pk_evaluate": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pk_evaluate_batched": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pk_evaluate_repeat": (ctypes.c_int, [_vp, _c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "pk_evaluate_static": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pk_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pk_pair_indices": (ctypes.c_int, [_c_int32, _c_int32, _c_int64, _c_int64, _vp, _vp, _vp]),
     "pk_shor_state": (ctypes.c_int, [_c_int32, _c_int32, _c_int64, _c_int64, _c_int32, _vp, _vp]),
@@ -274,6 +275,21 @@ def evaluate_into(plan, psi_in, psi_out, L_out, norm_out=None, angles=None):
     ws = plan.workspace(PK_OP_EVAL, psi_in.device)
     rc = lib().pk_evaluate(plan.handle, _ptr(psi_in), _ptr(psi_out), _ptr(L_out), _ptr(norm_out), _ptr(angles),
                            _ptr(ws), _stream(psi_in.device))
+    _check(rc, plan.handle)
+
+
+def evaluate_static(plan, psi_in, psi_out, L_out, norm_out=None, angles=None):
+    """pk_evaluate_static: pk_evaluate with the library's static workspace, on
+    preallocated device tensors; allocates nothing (the plan's tables must already
+    be on the device, e.g. after one ``evaluate``)."""
+    nelem = plan.offsets()[-1]
+    _check_f64(L_out, 1, "L_out", psi_in.device)
+    _check_f64(norm_out, 1, "norm_out", psi_in.device)
+    _check_f64(angles, 3 * plan.n_angles(), "angles", psi_in.device)
+    _check_state(plan, psi_in, nelem, "psi_in")
+    _check_state(plan, psi_out, nelem, "psi_out")
+    rc = lib().pk_evaluate_static(plan.handle, _ptr(psi_in), _ptr(psi_out), _ptr(L_out), _ptr(norm_out),
+                                  _ptr(angles), _stream(psi_in.device))
     _check(rc, plan.handle)
 
 

@@ -6,15 +6,21 @@ noise rotation) on an n_q = 30 state in FP64 (2^30 amplitudes, 16 GiB), seed 1,
 inputs resident in HBM.  One step = one evaluation of that iteration (every
 pass over the state plus the FP64 readout of L and the norm).  Prints one JSON
 line: evaluations/s, the roofline of the dominant kernel (the fused pass), the
-FP32 variant's speedup at its stated tolerance, and the CPU oracle's rate.
+FP32 variant's speedup and error, the 4096-instance batched form (FP64 and FP32,
+at the setting recorded in paper_0902_0699_amd/tuning.json) against a loop of
+single launches, the n_q = 30 gradient (adjoint kernel timed, 64 inputs against
+central differences), and the oracle leg: the CPU oracle's rate on a bounded
+sample, and the error of the FP64 and FP32 outputs against the oracle over all
+2^30 amplitudes (outside the timed regions).
 
-    python bench.py [--steps K] [--warmup W] [--extra]
+    python bench.py [--steps K] [--warmup W] [--extra] [--retune OUT.json]
 
---extra adds the 4096-instance batched form, the n_q = 30 gradient check, a
-two-qubit (TwoOpA) brickwork circuit at n_q = 30, Shor's data path at n_q = 30
-(load, QFT of register one, marginal; M = 899), the ensemble density matrix of
-4096 noisy Grover universes at n_q = 12 with its spectrum, and the full Grover
-search (n_t iterations) at n_q = 20 and 24.
+--extra adds a two-qubit (TwoOpA) brickwork circuit at n_q = 30, Shor's data
+path at n_q = 30 (load, QFT of register one, marginal; M = 899), the ensemble
+density matrix of 4096 noisy Grover universes at n_q = 12 with its spectrum, and
+the full Grover search (n_t iterations) at n_q = 20 and 24.  --retune runs the
+autotuner on the batched workload instead of the recorded setting and writes
+the new record to OUT.json.
 """
 
 import argparse
@@ -36,6 +42,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pass_kernel.json")
 CSRC = os.path.join(ROOT, "paper_0902_0699_amd", "csrc")
 FP32_TOL = 1e-5
 CPU_SAMPLE_NQ = 26
+TUNING_FILE = os.path.join(ROOT, "paper_0902_0699_amd", "tuning.json")
 
 
 def log(msg):
@@ -128,9 +135,28 @@ def copy_probe(torch, x, y):
     return 2.0 * x.numel() * x.element_size() / (ms * 1e-3) / 1e9, ms
 
 
-def cpu_baseline(W, nq_target, amp_sweeps_target):
-    """The oracle, as it stands, on one bounded sample: one evaluation at n_q = 24."""
-    import oracle as O
+def host_description():
+    """CPU model and thread counts of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "usable_cpus": usable}
+
+
+def cpu_baseline(W, O, nq_target, amp_sweeps_target):
+    """The oracle, as it stands, on one bounded sample: one evaluation of the same
+    noisy iteration at n_q = CPU_SAMPLE_NQ (26), scaled to n_q = nq_target by the
+    amplitude sweeps.  NumPy's elementwise loops run on one thread, so one core."""
     inst = W.single_instance(1, CPU_SAMPLE_NQ)
     t0 = time.perf_counter()
     O.evaluate(CPU_SAMPLE_NQ, inst["gates"], inst["marked"], inst["psi"])
@@ -138,27 +164,95 @@ def cpu_baseline(W, nq_target, amp_sweeps_target):
     sweeps_sample = 2 * CPU_SAMPLE_NQ + 2
     scale = (2.0 ** nq_target / 2.0 ** CPU_SAMPLE_NQ) * (amp_sweeps_target / sweeps_sample)
     log("cpu oracle: %.2fs at n_q=%d, x%.1f to n_q=%d" % (t, CPU_SAMPLE_NQ, scale, nq_target))
-    return {"value": 1.0 / (t * scale), "unit": "evaluations/s", "cores": 1, "kind": "oracle",
-            "sample": "one FP64 NumPy oracle evaluation of the same noisy iteration at n_q=%d (seed 1), "
-                      "%.2f s, scaled by N*(2 n_q + 2) amplitude-sweeps to n_q=%d" % (CPU_SAMPLE_NQ, t, nq_target),
-            "sample_seconds": t}
+    out = {"value": 1.0 / (t * scale), "unit": "evaluations/s", "cores": 1, "kind": "oracle",
+           "sample": "one FP64 NumPy oracle evaluation of the same noisy iteration at n_q=%d (seed 1), "
+                     "%.2f s, scaled by N*(2 n_q + 2) amplitude-sweeps to n_q=%d" % (CPU_SAMPLE_NQ, t, nq_target),
+           "sample_seconds": t}
+    out.update(host_description())
+    return out
 
 
-def batched_run(torch, pk, W, autotune, steps, warmup, prec):
-    t0 = time.perf_counter()
-    insts = W.batch_instances(W.SEEDS["batched"])
-    log("generated %d batched instances in %.1fs" % (len(insts), time.perf_counter() - t0))
+ACC_CHUNK = 1 << 24
+
+
+def whole_state_error(torch, O, nq, gates, marked, psi_in, y, workers):
+    """Normwise error of the device output y against the oracle's closed route for
+    one Grover iteration (half sums of psi_in once, then every label in chunks,
+    expected values computed in threads) and the oracle's L."""
+    from concurrent.futures import ThreadPoolExecutor
+    amp, L_ref = O.grover_sampler(nq, gates, marked, psi_in)
+    n = 1 << nq
+    starts = list(range(0, n, ACC_CHUNK))
+    want_of = lambda a: amp(np.arange(a, min(a + ACC_CHUNK, n), dtype=np.int64))
+    d2 = r2 = 0.0
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        futs = {i: ex.submit(want_of, a) for i, a in enumerate(starts[:workers])}
+        for i, a in enumerate(starts):
+            got = y[a:a + ACC_CHUNK].cpu().numpy().astype(np.complex128)
+            want = futs.pop(i).result()
+            if i + workers < len(starts):
+                futs[i + workers] = ex.submit(want_of, starts[i + workers])
+            d2 += float(np.sum(np.abs(got - want) ** 2))
+            r2 += float(np.sum(np.abs(want) ** 2))
+    return math.sqrt(d2 / r2), L_ref
+
+
+def oracle_leg(torch, W, nq, kept, line):
+    """The oracle on the host: its rate on a bounded sample (cpu_baseline), then the
+    error of each kept device output against it over every amplitude."""
+    import oracle as O
+    line["cpu_baseline"] = cpu_baseline(W, O, nq, 2 * nq + 2)
+    workers = max(1, min(16, line["cpu_baseline"]["usable_cpus"] or 1))
+    acc = {}
+    for prec, seed, y, L_gpu in kept:
+        t0 = time.perf_counter()
+        inst = W.single_instance(seed, nq)
+        err, L_ref = whole_state_error(torch, O, nq, inst["gates"], inst["marked"], inst["psi"], y, workers)
+        del inst
+        acc[prec] = {"rel_err_psi": err, "abs_err_L": abs(L_gpu - L_ref), "L_oracle": L_ref,
+                     "amplitudes_compared": 1 << nq,
+                     "tol": 1e-12 if prec == "fp64" else FP32_TOL}
+        acc[prec]["within_tol"] = err <= acc[prec]["tol"] and acc[prec]["abs_err_L"] <= acc[prec]["tol"]
+        log("oracle accuracy %s: normwise %.3e over 2^%d amplitudes, |dL| %.3e (%.1fs)"
+            % (prec, err, nq, acc[prec]["abs_err_L"], time.perf_counter() - t0))
+    line["accuracy_vs_oracle"] = {
+        "reference": "oracle closed route for one Grover iteration (HALL.Inv.HALL = 2|s><s| - I), every "
+                     "amplitude, from the original FP64 input (FP32 error includes the input rounding)",
+        **acc}
+    if "mixed" in line and "fp32" in acc:
+        line["mixed"]["rel_err_psi"] = acc["fp32"]["rel_err_psi"]
+        line["mixed"]["abs_err_L"] = acc["fp32"]["abs_err_L"]
+        line["mixed"]["within_tol"] = acc["fp32"]["within_tol"]
+        line["mixed"]["reference"] = "FP64 oracle, every amplitude, original FP64 input"
+
+
+def load_tuning():
+    try:
+        with open(TUNING_FILE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def batched_run(torch, pk, W, autotune, steps, warmup, prec, insts, record=None):
+    """The 4096-instance batch (Sec. 6.2) in one persistent graph-replayed launch, at
+    the recorded setting (or retuned when ``record`` is None), against a loop of
+    single-instance evaluations of the same instances."""
     probs = [{"nq": i["nq"], "gates": i["gates"], "marked": i["marked"]} for i in insts]
     plan = pk.Plan(probs, prec=prec)
     dt = torch.complex128 if prec == "fp64" else torch.complex64
     packed = torch.from_numpy(np.concatenate([i["psi"] for i in insts])).to(dt).to("cuda")
     out = torch.empty_like(packed)
-    t0 = time.perf_counter()
-    best, table = autotune.tune(plan, lambda: pk.evaluate_batched(plan, packed, out=out), op="batched")
-    default = [ms for c, ms in table if c["tile_bits"] == 13 and c["carrier_bits"] == 4
-               and c["reg_bits"] == (4 if prec == "fp64" else 5) and c["min_team_tiles"] == 64]
-    log("batched %s: tuned over %d settings in %.1fs: %s (%.3f ms; default tile %.3f ms)"
-        % (prec, len(table), time.perf_counter() - t0, best, table[0][1], default[0] if default else float("nan")))
+    if record is not None:
+        best, n_cands, tuned = record["setting"], None, False
+        autotune.apply(plan, best)
+    else:
+        t0 = time.perf_counter()
+        best, table = autotune.tune(plan, lambda: pk.evaluate_batched(plan, packed, out=out), op="batched",
+                                    use_cache=False)
+        n_cands, tuned = len(table), True
+        log("batched %s: tuned over %d settings in %.1fs: %s (%.3f ms)"
+            % (prec, len(table), time.perf_counter() - t0, best, table[0][1]))
     for _ in range(warmup):
         pk.evaluate_batched(plan, packed, out=out)
     torch.cuda.synchronize()
@@ -173,23 +267,30 @@ def batched_run(torch, pk, W, autotune, steps, warmup, prec):
     offs = plan.offsets()
     singles = [pk.Plan(p, prec=prec) for p in probs]
     views = [(packed[offs[k]:offs[k + 1]], out[offs[k]:offs[k + 1]]) for k in range(len(probs))]
-    for s, (a, b) in zip(singles, views):
-        pk.evaluate(s, a, out=b)
+    for sp, (a, b) in zip(singles, views):
+        pk.evaluate(sp, a, out=b)
     torch.cuda.synchronize()
     e0.record()
-    for s, (a, b) in zip(singles, views):
-        pk.evaluate(s, a, out=b)
+    for sp, (a, b) in zip(singles, views):
+        pk.evaluate(sp, a, out=b)
     e1.record()
     torch.cuda.synchronize()
     ms_loop = e0.elapsed_time(e1)
     total = offs[-1]
     esz = 16 if prec == "fp64" else 8
-    return {"instances": len(insts), "amplitudes": total, "dtype": "f64" if prec == "fp64" else "f32",
-            "ms_per_batch": ms_batched, "instances_per_s": len(insts) / (ms_batched * 1e-3),
-            "ms_loop_of_singles": ms_loop, "speedup_vs_loop": ms_loop / ms_batched,
-            "compulsory_GBs": 2.0 * total * esz / (ms_batched * 1e-3) / 1e9,
-            "tuned": best, "tuning_candidates": len(table),
-            "ms_default_tile": default[0] if default else None}
+    log("batched %s: %.3f ms per batch, loop of singles %.2f ms" % (prec, ms_batched, ms_loop))
+    res = {"instances": len(insts), "amplitudes": total, "dtype": "f64" if prec == "fp64" else "f32",
+           "ms_per_batch": ms_batched, "instances_per_s": len(insts) / (ms_batched * 1e-3),
+           "ms_loop_of_singles": ms_loop, "speedup_vs_loop": ms_loop / ms_batched,
+           "compulsory_GBs": 2.0 * total * esz / (ms_batched * 1e-3) / 1e9,
+           "compulsory_frac": 2.0 * total * esz / (ms_batched * 1e-3) / 1e9 / PEAK_HBM_GBS,
+           "setting": {k: best[k] for k in autotune.FIELDS if k in best},
+           "setting_from": "autotuned now over %d settings" % n_cands if tuned else "tuning record",
+           "passes_max": max(plan.passes(i) for i in range(len(insts)))}
+    if record is not None:
+        res["record_sources"] = record.get("sources")
+    del packed, out
+    return res, best
 
 
 def gradient_run(torch, pk, W, nq):
@@ -476,9 +577,12 @@ def main():
     ap.add_argument("--nq", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--extra", action="store_true", help="also time the batched form and the gradient check")
+    ap.add_argument("--extra", action="store_true",
+                    help="also time the two-qubit brickwork, Shor's data path, the density matrix and the search")
     ap.add_argument("--legs", default="batched,gradient,two_qubit,shor,density,search",
-                    help="with --extra: comma-separated extra legs to run (default: all)")
+                    help="comma-separated legs to run (batched and gradient always, the others with --extra)")
+    ap.add_argument("--retune", metavar="OUT.json",
+                    help="autotune the batched workload instead of using the recorded setting; write the record")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -532,32 +636,51 @@ def main():
                        "pass_frac_of_copy": achieved / copy_gbs},
         "L": r64["L"], "norm": r64["norm"],
     }
-    del r64
     torch.cuda.empty_cache()
+    # the copy probe overwrote y: one more evaluation restores the output kept for the oracle leg
+    pk.evaluate_into(r64["plan"], r64["x"], r64["y"], torch.empty(1, dtype=torch.float64, device="cuda"))
+    kept = [("fp64", W.SEEDS["large_fp64"], r64["y"], r64["L"])]
+    del r64["x"]
     if not args.no_mixed:
         r32 = single_run(torch, pk, W, "fp32", W.SEEDS["large_fp32"], nq, args.steps, args.warmup)
-        # accuracy at full size: the same instance through the FP64 path (parity-tested
-        # against the FP64 oracle) as the reference
-        plan64 = pk.Plan(r32["plan"].problems[0])
-        x64 = r32["x"].to(torch.complex128)
-        y64, L64, n64 = pk.evaluate(plan64, x64)
-        err = float(torch.linalg.vector_norm(r32["y"].to(torch.complex128) - y64) / torch.linalg.vector_norm(y64))
-        dL = abs(r32["L"] - L64.item())
         line["mixed"] = {"dtype": "f32", "value": 1000.0 / r32["ms"], "ms_per_step": r32["ms"],
                          "speedup_vs_fp64": line["ms_per_step"] / r32["ms"], "passes": r32["passes"],
-                         "rel_err_psi": err, "abs_err_L": dL, "L": r32["L"], "tol": FP32_TOL,
-                         "within_tol": err <= FP32_TOL and dL <= FP32_TOL,
-                         "reference": "FP64 path on the same FP32-rounded input",
+                         "rel_err_psi": None, "abs_err_L": None, "L": r32["L"], "tol": FP32_TOL,
+                         "within_tol": None, "reference": "set by the oracle leg",
                          "avg_launch_ms": float(np.mean(r32["per_pass_ms"])),
                          "achieved_GBs": 16.0 * N / (float(np.mean(r32["per_pass_ms"])) * 1e-3) / 1e9}
-        del r32, x64, y64
+        kept.append(("fp32", W.SEEDS["large_fp32"], r32["y"], r32["L"]))
+        del r32["x"]
+        torch.cuda.empty_cache()
+    legs = set(args.legs.split(","))
+    k = max(3, args.steps // 4)
+    if "batched" in legs:
+        t0 = time.perf_counter()
+        insts = W.batch_instances(W.SEEDS["batched"])
+        log("generated %d batched instances in %.1fs" % (len(insts), time.perf_counter() - t0))
+        records = load_tuning()
+        line["batched"] = {"workload": "%d noisy Grover instances, n_q = 10..19 log-uniform, seed %d, one "
+                                       "persistent graph-replayed launch" % (len(insts), W.SEEDS["batched"])}
+        new_records = {}
+        for p in ("fp64", "fp32"):
+            rec = None if args.retune else records.get("batched_" + p)
+            line["batched"][p], best = batched_run(torch, pk, W, autotune, k, 1, p, insts, rec)
+            new_records["batched_" + p] = {"setting": best, "sources": autotune._sources_hash(),
+                                           "device": torch.cuda.get_device_name(0),
+                                           "ms_per_batch": line["batched"][p]["ms_per_batch"]}
+            torch.cuda.empty_cache()
+        if args.retune:
+            with open(args.retune, "w") as f:
+                json.dump(new_records, f, indent=1)
+        del insts
+    if "gradient" in legs:
+        line["gradient"] = gradient_run(torch, pk, W, nq)
+        log("gradient: backward %.2f ms (%d passes), FD normwise rel err %.3e"
+            % (line["gradient"]["ms_backward"], line["gradient"]["backward_passes"],
+               line["gradient"]["normwise_rel_err"]))
         torch.cuda.empty_cache()
     if args.extra:
-        legs = set(args.legs.split(","))
-        k = max(3, args.steps // 4)
-        runs = [("batched", lambda: {p: batched_run(torch, pk, W, autotune, k, 1, p) for p in ("fp64", "fp32")}),
-                ("gradient", lambda: gradient_run(torch, pk, W, nq)),
-                ("two_qubit", lambda: two_qubit_run(torch, pk, nq, k)),
+        runs = [("two_qubit", lambda: two_qubit_run(torch, pk, nq, k)),
                 ("shor", lambda: {p: shor_run(torch, pk, W, autotune, k, p) for p in ("fp64", "fp32")}),
                 ("density", lambda: density_run(torch, pk, W, k)),
                 ("search", lambda: search_run(torch, pk, W, autotune, 3))]
@@ -566,7 +689,8 @@ def main():
                 line[name] = run()
                 torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(W, nq, 2 * nq + 2)
+        oracle_leg(torch, W, nq, kept, line)
+    del kept
     print(json.dumps(line), flush=True)
 
 

@@ -246,9 +246,16 @@ int pk_evaluate_static(pk_plan* plan, const void* psi_in, void* psi_out, double*
  * times in a row: psi_out = U^reps psi_in.  With the list of one Grover
  * iteration G = HALL . Inv . HALL . Oracle this is the whole search of Sec. 5.1,
  * G^{n_t} with n_t = floor((pi/4) sqrt(2^nq)) iterations.  The whole sequence of
- * passes (about 2 to 5 per iteration) is captured into one hipGraph, keyed by the
- * pointers and reps, and replayed.  L_out and norm_out refer to the final state.
- *   reps  1..2^24, with at most 2^20 pass launches in total
+ * passes (about 2 to 5 per iteration), one launch each, is captured into one
+ * hipGraph, keyed by the pointers and reps, and replayed.  With the environment
+ * variable PK_REPEAT_PERSISTENT=1 (and reps > 1, every pass on one kernel
+ * instance) the passes run instead in one persistent launch of as many
+ * workgroups as the GPU holds at once, with a grid-wide barrier between passes;
+ * same results bit for bit, but on MI355X the barrier's device-scope fences cost
+ * more than the kernel boundaries.  If its workgroups cannot all be resident (the
+ * GPU is shared), a barrier gives up after about half a second and L_out and
+ * norm_out are NaN.  L_out and norm_out refer to the final state.
+ *   reps  1..2^24, with at most 2^20 passes in total
  * Other arguments and errors as pk_evaluate.
  */
 int pk_evaluate_repeat(pk_plan* plan, int64_t reps, const void* psi_in, void* psi_out, double* L_out,

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 #include <rocsolver/rocsolver.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -97,7 +98,11 @@ int ensure_device(DevPlan* d) {
     int wall_khz = 0;
     if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || wall_khz <= 0)
         wall_khz = 100000;
-    d->spin_ticks = (uint64_t)wall_khz * 500;  // 0.5 s
+    // bound of one barrier wait: 0.5 s, or PK_BARRIER_SPIN_US microseconds (tests
+    // force the time-out path with a tiny value)
+    uint64_t spin_us = 500000;
+    if (const char* v = std::getenv("PK_BARRIER_SPIN_US")) spin_us = std::strtoull(v, nullptr, 10);
+    d->spin_ticks = (uint64_t)wall_khz * spin_us / 1000;
     // batched launch: as many workgroups as are resident at once, in teams
     int per_cu = batched_blocks_per_cu(batched_kmax(P), P.inst[0].fwd[0].rbits, P.prec == PK_FP64);
     if (per_cu < 1) per_cu = 1;
@@ -228,6 +233,60 @@ hipError_t enqueue_eval(DevPlan* d, const EvalArgs& a, hipStream_t st, std::vect
             if (e != hipSuccess) return e;
         }
     }
+    TableLayout t = table_layout(&P);
+    return launch_reduce(at<Reduction>(P.d_tables, t.red), 2 * (int)P.inst.size(), static_cast<double*>(a.ws),
+                         a.L_out, a.norm_out, nullptr, st);
+}
+
+// The persistent form of pk_evaluate_repeat is opt-in (PK_REPEAT_PERSISTENT=1): on
+// MI355X its grid barrier (device-scope fences in every workgroup) costs more than
+// the kernel boundary it replaces.
+bool repeat_persistent() {
+    const char* v = std::getenv("PK_REPEAT_PERSISTENT");
+    return v && v[0] && v[0] != '0';
+}
+
+// G^reps in one persistent launch when every forward pass runs on the same kernel
+// instance; 0 when the plan needs the launch-per-pass form.
+unsigned repeat_grid(DevPlan* d) {
+    const Instance& in = d->host.inst[0];
+    const int kmax = in.fwd[0].kmax, rbits = in.fwd[0].rbits;
+    int64_t tiles = 0;
+    for (const auto& hp : in.fwd) {
+        if (hp.kmax != kmax || hp.rbits != rbits) return 0;
+        tiles = std::max<int64_t>(tiles, hp.ntiles);
+    }
+    int per_cu = repeat_blocks_per_cu(kmax, rbits, d->host.prec == PK_FP64);
+    if (per_cu < 1) return 0;
+    const int64_t grid = std::min<int64_t>((int64_t)d->n_cu * per_cu, tiles);
+    return (unsigned)std::max<int64_t>(grid, 1);
+}
+
+// prep (clears the barrier counter), the persistent launch, the final combine.
+hipError_t enqueue_repeat(DevPlan* d, const EvalArgs& a, hipStream_t st, int64_t reps, unsigned grid) {
+    Plan& P = d->host;
+    hipError_t e = enqueue_prep(d, a.ws, a.angles, PK_OP_EVAL, 64, st);  // arrival counter and release word
+    if (e != hipSuccess) return e;
+    PassLaunch L = base_launch(d, a.ws, PK_OP_EVAL);
+    const Instance& in = P.inst[0];
+    L.src0 = a.psi_in;
+    L.dst0 = a.psi_out;
+    L.nv = 1;
+    L.want_norm = a.norm_out != nullptr;
+    L.kmax = in.fwd[0].kmax;
+    L.rbits = in.fwd[0].rbits;
+    WsLayout w = workspace_layout(&P, PK_OP_EVAL);
+    RepeatArgs r{};
+    r.bar = at<unsigned int>(a.ws, w.counters);
+    r.reps = reps;
+    r.pass0 = 0;
+    r.npass = (int32_t)in.fwd.size();
+    r.spin_ticks = d->spin_ticks;
+    r.n_reads = P.n_reads;
+    r.part_base = in.fwd.back().part_base;
+    r.n_part = in.fwd.back().ntiles;
+    e = launch_repeat(L, r, grid, st);
+    if (e != hipSuccess) return e;
     TableLayout t = table_layout(&P);
     return launch_reduce(at<Reduction>(P.d_tables, t.red), 2 * (int)P.inst.size(), static_cast<double*>(a.ws),
                          a.L_out, a.norm_out, nullptr, st);
@@ -579,8 +638,13 @@ int pk_evaluate_repeat(pk_plan* plan, int64_t reps, const void* psi_in, void* ps
     rc = ensure_device(d);
     if (rc != PK_OK) return rc;
     EvalArgs a{psi_in, psi_out, L_out, norm_out, angles, workspace};
+    const unsigned grid = (reps > 1 && repeat_persistent()) ? repeat_grid(d) : 0u;
     const void* const key[8] = {psi_in, psi_out, L_out, norm_out, angles, workspace,
-                                reinterpret_cast<const void*>((intptr_t)reps), nullptr};
+                                reinterpret_cast<const void*>((intptr_t)reps),
+                                reinterpret_cast<const void*>((intptr_t)grid)};
+    if (grid > 0)
+        return run_graphed(d, G_REPEAT, key, static_cast<hipStream_t>(stream),
+                           [&](hipStream_t s) { return enqueue_repeat(d, a, s, reps, grid); });
     return run_graphed(d, G_REPEAT, key, static_cast<hipStream_t>(stream),
                        [&](hipStream_t s) { return enqueue_eval(d, a, s, nullptr, reps); });
 }

@@ -30,7 +30,7 @@ enum OpKind : int32_t {
     OP_READ = 4,   // reads[flips[arg].slot] = |C|^2 of the amplitude flips[arg]
     OP_SEED = 5,   // lambda = dL * psi at the amplitude flips[arg] (backward start)
     OP_D2BWD = 6,  // backward D2: psi <- D^H psi, grad += Re<lambda|dD|psi>, lambda <- D^H lambda
-    OP_MAT4 = 7,   // 4x4 complex matrix mats4[arg] on register bits 0 (qubit is1) and 1 (qubit is2)
+    OP_MAT4 = 7,   // 4x4 complex matrix mats4[arg] on register bits a (qubit is1) and a + 1 (qubit is2), a = 0 or 2
     OP_D4BWD = 8,  // backward D4 on register bits 0 and 1, as OP_D2BWD with 4x4 matrices
     OP_PHASE = 9,  // controlled phase (CPHASE, CPHASEK): e^{i theta} where both bits are 1
 };
@@ -72,8 +72,8 @@ struct Op {
 //
 // One sub-stage: a fixed sequence of optional steps applied to the registers,
 // in this order: seed, flip, controlled phases, matrix, Hadamards (mask 1),
-// flip, Hadamards (mask 2), matrix, 4x4 matrix, backward D2, backward D4,
-// scale, read.  A stage's op list is packed into
+// flip, Hadamards (mask 2), matrix, 4x4 matrix on register bits 0 and 1, 4x4
+// matrix on register bits 2 and 3, backward D2, backward D4, scale, read.  A stage's op list is packed into
 // as many sub-stages as its order needs; only the first of them exchanges the
 // tile through LDS (`exchange`), the others keep the layout.  Straight-line
 // steps instead of an op loop let the compiler update the register tile in
@@ -83,6 +83,7 @@ struct Op {
 enum StepBits : int32_t {
     ST_EXCHANGE = 1, ST_SEED = 2, ST_FLIP_PRE = 4, ST_PHASE = 8, ST_MAT_PRE = 16, ST_H1 = 32, ST_FLIP_MID = 64,
     ST_H2 = 128, ST_MAT_POST = 256, ST_MAT4 = 512, ST_D2B = 1024, ST_D4B = 2048, ST_SCALE = 4096, ST_READ = 8192,
+    ST_MAT4B = 16384,
 };
 
 // 16-byte aligned so that the slot table (phase_pm .. phase_upair) can be read as
@@ -118,6 +119,8 @@ struct alignas(16) Stage {
     float d4b_gscale;
     int32_t scale;            // 1: multiply by the pass scale
     int32_t read;             // flip index of a READ or -1
+    int32_t mat4b;            // 4x4 matrix on register bits 2 (qubit is1) and 3 (qubit is2), or -1: a
+                              // second, disjoint qubit pair of the same stage
 };
 static_assert(offsetof(Stage, phase_pm) % 16 == 0 && offsetof(Stage, phase_cnt) == offsetof(Stage, phase_pm) + 16 &&
                   offsetof(Stage, phase_ucnt) == offsetof(Stage, phase_pm) + 32 &&

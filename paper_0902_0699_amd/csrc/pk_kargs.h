@@ -54,5 +54,9 @@ template <typename R, int RB>
 hipError_t launch_batched_r(int kmax, const KArgs& a, const BatchArgs& B, unsigned grid, hipStream_t st);
 template <typename R, int RB>
 int batched_occupancy_r(int kmax);
+template <typename R, int RB>
+hipError_t launch_repeat_r(int kmax, const KArgs& a, const RepeatArgs& r, unsigned grid, hipStream_t st);
+template <typename R, int RB>
+int repeat_occupancy_r(int kmax);
 
 }  // namespace pk

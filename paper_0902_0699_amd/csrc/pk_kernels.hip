@@ -183,6 +183,24 @@ hipError_t launch_batched(const PassLaunch& L, const BatchArgs& B, unsigned grid
                   : launch_batched_r<float, 4>(L.kmax, a, B, grid, st);
 }
 
+hipError_t launch_repeat(const PassLaunch& L, const RepeatArgs& r, unsigned grid, hipStream_t st) {
+    KArgs a = kargs(L);
+    a.dst1 = nullptr;
+    a.gpart = nullptr;
+    a.dL = nullptr;
+    a.pass = 0;
+    if (L.rbits == 5)
+        return L.fp64 ? launch_repeat_r<double, 5>(L.kmax, a, r, grid, st)
+                      : launch_repeat_r<float, 5>(L.kmax, a, r, grid, st);
+    return L.fp64 ? launch_repeat_r<double, 4>(L.kmax, a, r, grid, st)
+                  : launch_repeat_r<float, 4>(L.kmax, a, r, grid, st);
+}
+
+int repeat_blocks_per_cu(int kmax, int rbits, bool fp64) {
+    if (rbits == 5) return fp64 ? repeat_occupancy_r<double, 5>(kmax) : repeat_occupancy_r<float, 5>(kmax);
+    return fp64 ? repeat_occupancy_r<double, 4>(kmax) : repeat_occupancy_r<float, 4>(kmax);
+}
+
 int batched_blocks_per_cu(int kmax, int rbits, bool fp64) {
     if (rbits == 5) return fp64 ? batched_occupancy_r<double, 5>(kmax) : batched_occupancy_r<float, 5>(kmax);
     return fp64 ? batched_occupancy_r<double, 4>(kmax) : batched_occupancy_r<float, 4>(kmax);

@@ -49,7 +49,25 @@ struct BatchArgs {
     int32_t n_xcd;
 };
 
+// Device arguments of the persistent repeat launch (see repeat_kernel).
+struct RepeatArgs {
+    unsigned int* bar;     // grid barrier counter (cleared before the launch)
+    int64_t reps;          // applications of the gate list
+    int32_t pass0;         // first pass of the instance in the pass table
+    int32_t npass;         // passes per application
+    uint64_t spin_ticks;   // bound of one barrier wait, in wall-clock ticks
+    int32_t n_reads;       // readout slots (set to NaN when a barrier timed out)
+    int32_t pad;
+    int64_t part_base;     // norm partials of the last pass (likewise)
+    int64_t n_part;
+};
+
 hipError_t launch_pass(const PassLaunch& L, hipStream_t st);
+// G^reps of a single-instance plan in one persistent launch of `grid` resident
+// workgroups (L.kmax, L.rbits, L.fp64 select the kernel instance).
+hipError_t launch_repeat(const PassLaunch& L, const RepeatArgs& r, unsigned grid, hipStream_t st);
+// Resident workgroups per CU of that instance (0 if unknown).
+int repeat_blocks_per_cu(int kmax, int rbits, bool fp64);
 hipError_t launch_batched(const PassLaunch& L, const BatchArgs& B, unsigned grid, hipStream_t st);
 // Resident workgroups per CU of the batched kernel instance (0 if unknown).
 int batched_blocks_per_cu(int kmax, int rbits, bool fp64);

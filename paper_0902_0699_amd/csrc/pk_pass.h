@@ -240,6 +240,18 @@ __device__ __forceinline__ void op_mat4(T (&v)[NV][NR], const PK_CONST double* m
         for (int i = 0; i < NR; i += 4) quartet_mat(v[n][i], v[n][i + 2], v[n][i + 1], v[n][i + 3], m);
 }
 
+// The same on register bits 2 (qubit is1) and 3 (qubit is2): a second qubit pair,
+// disjoint from the first, in the same stage.  Registers i, i+8, i+4, i+12 (bits
+// 2 and 3 of i clear) hold its quartet |00>, |01>, |10>, |11>.
+template <int NV, int NR, typename T>
+__device__ __forceinline__ void op_mat4_hi(T (&v)[NV][NR], const PK_CONST double* m) {
+#pragma unroll
+    for (int n = 0; n < NV; ++n)
+#pragma unroll
+        for (int i = 0; i < NR; ++i)
+            if ((i & 12) == 0) quartet_mat(v[n][i], v[n][i + 8], v[n][i + 4], v[n][i + 12], m);
+}
+
 // Backward step through a D4 gate, as op_d2bwd with 4x4 matrices: psi <- D^H psi;
 // for every angle g += Re( conj(lambda) . (dD/dtheta) psi ); lambda <- D^H lambda.
 // `m` holds D, D^H, dD/dalpha, dD/dbeta, dD/dgamma (32 doubles each).
@@ -636,6 +648,7 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
             apply_mat<NV, NR>(v, mat_post_a, m);
         }
         if ((steps & ST_MAT4) && active) op_mat4<NV, NR>(v, cptr(a.mats4) + 32 * S->mat4);
+        if ((steps & ST_MAT4B) && active) op_mat4_hi<NV, NR>(v, cptr(a.mats4) + 32 * S->mat4b);
         if constexpr (NV == 2) {
             if (steps & ST_D2B) {
                 R mh[8];
@@ -772,6 +785,9 @@ __global__ void __launch_bounds__(1 << (KMAX - RB)) pass_kernel(KArgs a) {
 // once no longer waits at later ones, so every wave reaches the kernel's end.
 __device__ __forceinline__ bool team_barrier(unsigned int* bar, unsigned int target, uint64_t ticks, bool broken,
                                              int* flag) {
+    // every wave first waits for its own stores to reach the L2 (__syncthreads waits
+    // only for LDS traffic), so that thread 0's fence below covers the whole tile
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
@@ -781,6 +797,40 @@ __device__ __forceinline__ bool team_barrier(unsigned int* bar, unsigned int tar
             const uint64_t t0 = wall_clock64();
             for (;;) {
                 if (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) {
+                    ok = 1;
+                    break;
+                }
+                if (wall_clock64() - t0 > ticks) break;
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __threadfence();
+        *flag = ok;
+    }
+    __syncthreads();
+    return *flag != 0;
+}
+
+// Grid-wide barrier of the persistent repeat launch.  As team_barrier, but the
+// workgroup whose arrival completes the round stores the round's target to a
+// release word on another cache line, and the others poll that word: polling the
+// arrival counter itself (hundreds of workgroups) delays the arrivals queued
+// behind the polls on the same line.  bar[0] counts arrivals, bar[32] is the
+// release word; both start at zero.
+__device__ __forceinline__ bool grid_barrier(unsigned int* bar, unsigned int target, uint64_t ticks, bool broken,
+                                             int* flag) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned int old = atomicAdd(bar, 1u);
+        unsigned int* release = bar + 32;
+        if (old + 1u == target) __hip_atomic_store(release, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 0;
+        if (!broken) {
+            const uint64_t t0 = wall_clock64();
+            for (;;) {
+                if (__hip_atomic_load(release, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) {
                     ok = 1;
                     break;
                 }
@@ -863,11 +913,48 @@ __global__ void __launch_bounds__(1 << (KMAX - RB)) batched_kernel(KArgs a, Batc
         for (int p = 0; p < D->npass; ++p) {
             const PK_CONST Pass* P = cptr(a.passes) + D->first_pass + p;
             run_tiles<R, 1, KMAX, RB>(a, P, 0, 1, P->ntiles, lds, red);
-            // this workgroup's stores must be visible to its own loads of the next pass
+            // this workgroup's stores must be visible to its own loads of the next pass:
+            // every wave waits for its stores to complete before the barrier
+            __builtin_amdgcn_s_waitcnt(0);
             __threadfence_block();
             __syncthreads();
         }
         finish_instance<NT>(a, D, inst, true, b.L_out, b.norm_out, red);
+    }
+}
+
+// G^reps in one persistent launch (the full search of Sec. 5.1: n_t applications
+// of one Grover iteration): every workgroup walks its tiles of each pass, then
+// waits at a grid-wide barrier (grid_barrier) before the next pass.  The first application reads src0, the later ones work in place on
+// dst0; the norm partials are written by the last application only.  Every
+// workgroup of the grid must be resident at once (the grid is the occupancy
+// limit); if a barrier times out, the workgroup stops waiting at later ones and
+// the readouts and norm partials are overwritten with NaN, so a failed run is
+// visible in L and the norm instead of hanging.
+template <typename R, int KMAX, int RB>
+__global__ void __launch_bounds__(1 << (KMAX - RB)) repeat_kernel(KArgs a, RepeatArgs r) {
+    using T = typename Cplx<R>::T;
+    __shared__ T lds[1 << KMAX];
+    __shared__ double red[16 + 2 * kMaxUPairs];
+    __shared__ int flag;
+    unsigned int target = 0;
+    bool broken = false;
+    for (int64_t rep = 0; rep < r.reps; ++rep) {
+        KArgs ar = a;
+        if (rep > 0) ar.src0 = a.dst0;
+        ar.want_norm = a.want_norm && rep == r.reps - 1;
+        for (int p = 0; p < r.npass; ++p) {
+            const PK_CONST Pass* P = cptr(a.passes) + r.pass0 + p;
+            run_tiles<R, 1, KMAX, RB>(ar, P, blockIdx.x, gridDim.x, P->ntiles, lds, red);
+            if (rep == r.reps - 1 && p == r.npass - 1) break;
+            target += gridDim.x;
+            broken = !grid_barrier(r.bar, target, r.spin_ticks, broken, &flag) || broken;
+        }
+    }
+    if (broken) {
+        const double nan = __builtin_nan("");
+        for (int i = threadIdx.x; i < r.n_reads; i += blockDim.x) a.reads[i] = nan;
+        for (int64_t i = threadIdx.x; i < r.n_part; i += blockDim.x) a.partials[r.part_base + i] = nan;
     }
 }
 
@@ -966,6 +1053,36 @@ hipError_t launch_batched_r(int kmax, const KArgs& a, const BatchArgs& B, unsign
 template <typename R, int RB>
 int batched_occupancy_r(int kmax) {
     return batched_instance<R, RB>(kmax, [&](auto K) { return batched_occupancy_t<R, decltype(K)::value, RB>(); });
+}
+
+
+template <typename R, int KMAX, int RB>
+static hipError_t launch_repeat_t(const KArgs& a, const RepeatArgs& r, unsigned grid, hipStream_t st) {
+    hipLaunchKernelGGL((repeat_kernel<R, KMAX, RB>), dim3(grid), dim3(1 << (KMAX - RB)), 0, st, a, r);
+    return hipGetLastError();
+}
+
+template <typename R, int RB>
+hipError_t launch_repeat_r(int kmax, const KArgs& a, const RepeatArgs& r, unsigned grid, hipStream_t st) {
+    bool found = false;
+    hipError_t e = batched_instance<R, RB>(kmax, [&](auto K) {
+        found = true;
+        return launch_repeat_t<R, decltype(K)::value, RB>(a, r, grid, st);
+    });
+    return found ? e : hipErrorInvalidValue;
+}
+
+template <typename R, int KMAX, int RB>
+static int repeat_occupancy_t() {
+    int per_cu = 0;
+    auto kfn = repeat_kernel<R, KMAX, RB>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, 1 << (KMAX - RB), 0) != hipSuccess) return 0;
+    return per_cu;
+}
+
+template <typename R, int RB>
+int repeat_occupancy_r(int kmax) {
+    return batched_instance<R, RB>(kmax, [&](auto K) { return repeat_occupancy_t<R, decltype(K)::value, RB>(); });
 }
 
 }  // namespace pk

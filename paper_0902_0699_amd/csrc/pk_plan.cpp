@@ -77,7 +77,9 @@ bool is_unitary4(const double* m) {
 // bits (phases, Oracle and Inv are all diagonal).  Gates need their bits in the
 // set, phases do not.  Two-qubit gates need both bits; `pair` further restricts
 // them: PAIR_ANY (tiles), PAIR_NONE (a stage without two-qubit gates), or
-// (b1 << 8 | b2), the one ordered pair a stage holds on register bits 0 and 1.
+// (b1 << 8 | b2), the ordered pair a stage holds on register bits 0 and 1;
+// `pair2` is a second, disjoint pair on register bits 2 and 3 (or PAIR_NONE),
+// which takes only the gates whose kernel step exists for those bits.
 constexpr int PAIR_ANY = -1;
 constexpr int PAIR_NONE = -2;
 
@@ -88,11 +90,12 @@ struct ScanItem {
     int bit;   // IT_GATE, IT_PHASE: first bit (for a phase, -1 when it is outside the tile)
     int bit2;  // second bit of a two-qubit gate or phase, -1 otherwise
     bool swap = false;  // a SWAP gate (done by relabelling bits when the pass allows)
+    bool pair_b = true; // a two-qubit gate the second register pair (bits 2, 3) can take
 };
 
 int scan(const std::vector<ScanItem>& items, const std::vector<char>& done,
          const std::vector<char>& in_set, int nbits, int max_gates, std::vector<int>* out,
-         int pair = PAIR_ANY) {
+         int pair = PAIR_ANY, int pair2 = PAIR_NONE) {
     std::vector<char> blocked(nbits, 0);  // later gates on the bit must wait
     std::vector<char> nd(nbits, 0);       // later phases on the bit must wait (a non-diagonal gate is pending)
     bool blocked_gate = false, blocked_diag = false;
@@ -122,9 +125,12 @@ int scan(const std::vector<ScanItem>& items, const std::vector<char>& done,
             const bool two = it.bit2 >= 0;
             bool ok = !blocked[it.bit] && !blocked_diag && in_set[it.bit] &&
                       (max_gates < 0 || gates < max_gates);
-            if (two)
-                ok = ok && !blocked[it.bit2] && in_set[it.bit2] && pair != PAIR_NONE &&
-                     (pair == PAIR_ANY || pair == ((it.bit << 8) | it.bit2));
+            if (two) {
+                const int code = (it.bit << 8) | it.bit2;
+                const bool placed = pair == PAIR_ANY ||
+                                    (pair >= 0 && (pair == code || (pair2 >= 0 && pair2 == code && it.pair_b)));
+                ok = ok && !blocked[it.bit2] && in_set[it.bit2] && placed;
+            }
             if (ok) {
                 ++count;
                 ++gates;
@@ -166,8 +172,8 @@ int64_t extract(int64_t x, const std::vector<int>& bits) {
 // slot, and a new sub-stage (same layout, no exchange) starts when none fits.
 // Hadamards collected in one mask act on distinct register bits and commute.
 enum Slot {
-    S_SEED = 0, S_FLIP_PRE, S_PHASE, S_MAT_PRE, S_H1, S_FLIP_MID, S_H2, S_MAT_POST, S_MAT4, S_D2B, S_D4B, S_SCALE,
-    S_READ
+    S_SEED = 0, S_FLIP_PRE, S_PHASE, S_MAT_PRE, S_H1, S_FLIP_MID, S_H2, S_MAT_POST, S_MAT4, S_MAT4B, S_D2B, S_D4B,
+    S_SCALE, S_READ
 };
 
 Stage blank_sub(const HostStage& hs, int exchange) {
@@ -182,7 +188,7 @@ Stage blank_sub(const HostStage& hs, int exchange) {
     s.exchange = exchange;
     s.seed = s.flip_pre = s.flip_mid = s.read = -1;
     s.mat_pre_a = s.mat_post_a = s.d2b_a = -1;
-    s.mat4 = s.d4b_mat = -1;
+    s.mat4 = s.mat4b = s.d4b_mat = -1;
     s.phase_first = s.phase_count = 0;
     for (int u = 0; u < kPhaseSlots; ++u) {
         s.phase_pm[u] = -1;
@@ -223,7 +229,7 @@ void finish_sub(Stage& s, std::vector<PhaseOp>* table, std::vector<UPair>* upair
               (s.phase_count > 0 ? ST_PHASE : 0) | (s.mat_pre_a >= 0 ? ST_MAT_PRE : 0) | (s.hmask1 ? ST_H1 : 0) |
               (s.flip_mid >= 0 ? ST_FLIP_MID : 0) | (s.hmask2 ? ST_H2 : 0) | (s.mat_post_a >= 0 ? ST_MAT_POST : 0) |
               (s.mat4 >= 0 ? ST_MAT4 : 0) | (s.d2b_a >= 0 ? ST_D2B : 0) | (s.d4b_mat >= 0 ? ST_D4B : 0) |
-              (s.scale ? ST_SCALE : 0) | (s.read >= 0 ? ST_READ : 0);
+              (s.scale ? ST_SCALE : 0) | (s.read >= 0 ? ST_READ : 0) | (s.mat4b >= 0 ? ST_MAT4B : 0);
 }
 
 // A phase joins the accumulator slot of its register bits (the register bits of
@@ -282,7 +288,8 @@ int place(Stage& s, int cursor, const Op& o) {
         }
         return -1;
     case OP_MAT4:
-        if (cursor <= S_MAT4 && s.mat4 < 0) { s.mat4 = o.arg; return S_MAT4; }
+        if (o.a == 0 && cursor <= S_MAT4 && s.mat4 < 0) { s.mat4 = o.arg; return S_MAT4; }
+        if (o.a == 2 && cursor <= S_MAT4B && s.mat4b < 0) { s.mat4b = o.arg; return S_MAT4B; }
         return -1;
     case OP_D4BWD:
         if (cursor <= S_D4B && s.d4b_mat < 0) {
@@ -346,6 +353,9 @@ struct Compiler {
     // cut decisions depend only on the structure (nq, tiling, item kinds and bits,
     // what is done); instances of a batch often share it
     std::map<std::string, std::vector<int>>* cut_cache = nullptr;
+    // the large-stride tile-bit preference of this compile (Tiling::page_cap, or 0
+    // where that preference would cost passes)
+    int pcap = 0;
 
     std::vector<int> free_bits(const std::vector<int>& tbits) const {
         std::vector<char> used(in->nq, 0);
@@ -367,7 +377,8 @@ struct Compiler {
 
     // Stage planning inside one pass.  `items` are the pass's primitives in
     // scheduled order with bits given as local tile bits.  A stage holds at most
-    // one ordered pair of two-qubit gate bits, on register bits 0 and 1.
+    // two disjoint ordered pairs of two-qubit gate bits, on register bits 0 and 1
+    // and on register bits 2 and 3.
     std::vector<std::pair<std::vector<int>, std::vector<int>>> plan_stages(
         const std::vector<ScanItem>& items) const {
         const int n = (int)items.size();
@@ -388,13 +399,32 @@ struct Compiler {
                     if (std::find(pairs.begin(), pairs.end(), pr) == pairs.end()) pairs.push_back(pr);
                 }
             }
+            // which pending pairs the second register pair may take (every pending
+            // gate on it has a kernel step for register bits 2 and 3)
+            std::vector<char> pb(pairs.size(), 1);
+            for (int i = 0; i < n; ++i) {
+                if (done[i] || items[i].type != IT_GATE || items[i].bit2 < 0) continue;
+                const int pr = (items[i].bit << 8) | items[i].bit2;
+                const size_t q = std::find(pairs.begin(), pairs.end(), pr) - pairs.begin();
+                pb[q] = pb[q] && items[i].pair_b;
+            }
+            auto disjoint = [](int x, int y) {
+                return (x >> 8) != (y >> 8) && (x >> 8) != (y & 255) && (x & 255) != (y >> 8) &&
+                       (x & 255) != (y & 255);
+            };
             // Does everything left fit in one stage that can also store?
-            bool fits = (int)need.size() <= RB && pairs.size() <= 1;
+            bool fits = (int)need.size() <= RB &&
+                        (pairs.size() <= 1 ||
+                         (pairs.size() == 2 && RB >= 4 && disjoint(pairs[0], pairs[1]) && (pb[0] || pb[1])));
             for (int b : need) fits = fits && io_ok(b);
             std::vector<int> rb;
-            int pair = PAIR_NONE;
+            int pair = PAIR_NONE, pair2 = PAIR_NONE;
             if (fits) {
-                if (!pairs.empty()) {
+                if (pairs.size() == 2) {
+                    pair = pb[1] ? pairs[0] : pairs[1];
+                    pair2 = pb[1] ? pairs[1] : pairs[0];
+                    rb = {pair >> 8, pair & 255, pair2 >> 8, pair2 & 255};
+                } else if (!pairs.empty()) {
                     pair = pairs[0];
                     rb = {pair >> 8, pair & 255};
                 }
@@ -403,17 +433,29 @@ struct Compiler {
                 for (int b = k - 1; b >= 0 && (int)rb.size() < RB; --b)
                     if (io_ok(b) && std::find(rb.begin(), rb.end(), b) == rb.end()) rb.push_back(b);
             } else {
-                // options: no two-qubit gate, or one of the first few pending pairs
-                std::vector<int> options = {PAIR_NONE};
-                for (size_t q = 0; q < pairs.size() && q < 4; ++q) options.push_back(pairs[q]);
+                // options: no two-qubit gate, one of the first few pending pairs, or two
+                // disjoint ones (the first on register bits 0 and 1, the second on 2 and 3)
+                std::vector<std::pair<int, int>> options = {{PAIR_NONE, PAIR_NONE}};
+                const size_t nopt = std::min<size_t>(pairs.size(), 4);
+                for (size_t q = 0; q < nopt; ++q) options.push_back({pairs[q], PAIR_NONE});
+                if (RB >= 4)
+                    for (size_t q0 = 0; q0 < nopt; ++q0)
+                        for (size_t q1 = q0 + 1; q1 < nopt; ++q1)
+                            if (disjoint(pairs[q0], pairs[q1]) && (pb[q0] || pb[q1]))
+                                options.push_back(pb[q1] ? std::make_pair(pairs[q0], pairs[q1])
+                                                         : std::make_pair(pairs[q1], pairs[q0]));
                 int best_gain = -1;
-                for (int opt : options) {
+                for (const auto& opt : options) {
                     std::vector<int> r;
-                    if (opt >= 0) {
-                        const int b1 = opt >> 8, b2 = opt & 255;
-                        if (first && (!io_ok(b1) || !io_ok(b2))) continue;
-                        r = {b1, b2};
+                    bool usable = true;
+                    for (int pr : {opt.first, opt.second}) {
+                        if (pr < 0) continue;
+                        const int b1 = pr >> 8, b2 = pr & 255;
+                        if (first && (!io_ok(b1) || !io_ok(b2))) usable = false;
+                        r.push_back(b1);
+                        r.push_back(b2);
                     }
+                    if (!usable) continue;
                     while ((int)r.size() < RB) {
                         int best = -1, bg = -1, best_pref = -1;
                         for (int b = 0; b < k; ++b) {
@@ -422,7 +464,7 @@ struct Compiler {
                             std::vector<char> in_set(k, 0);
                             for (int x : r) in_set[x] = 1;
                             in_set[b] = 1;
-                            int g = scan(items, done, in_set, k, -1, nullptr, opt);
+                            int g = scan(items, done, in_set, k, -1, nullptr, opt.first, opt.second);
                             // first stage: prefer high bits; later: bits that cannot be
                             // stored from (low carriers) first, then low bits
                             int pref = first ? b : ((!io_ok(b) ? 1000 : 0) + (k - b));
@@ -437,18 +479,19 @@ struct Compiler {
                     }
                     std::vector<char> in_set(k, 0);
                     for (int x : r) in_set[x] = 1;
-                    const int g = scan(items, done, in_set, k, -1, nullptr, opt);
+                    const int g = scan(items, done, in_set, k, -1, nullptr, opt.first, opt.second);
                     if (g > best_gain) {
                         best_gain = g;
                         rb = r;
-                        pair = opt;
+                        pair = opt.first;
+                        pair2 = opt.second;
                     }
                 }
             }
             std::vector<char> in_set(k, 0);
             for (int r : rb) in_set[r] = 1;
             std::vector<int> sel;
-            scan(items, done, in_set, k, -1, &sel, pair);
+            scan(items, done, in_set, k, -1, &sel, pair, pair2);
             for (int i : sel) done[i] = 1;
             left -= (int)sel.size();
             stages.push_back({rb, sel});
@@ -482,7 +525,6 @@ struct Compiler {
         // Among bits of equal gain, take bits at byte strides of 2 MiB or more (each
         // doubles the pages a tile touches) first while the tile has fewer than
         // page_cap of them, so that no later pass is left with all of them.
-        const int pcap = plan->tiling.page_cap;
         const int pbit = kPageByteBit - (plan->prec == PK_FP64 ? 4 : 3);
         while ((int)t.size() < k) {
             int best = -1, best_gain = -1;
@@ -556,7 +598,7 @@ struct Compiler {
                 lp.maps.push_back(m);
                 continue;
             }
-            ScanItem li{it.type, it.type == IT_DIAG ? -1 : l1, l2, it.swap};
+            ScanItem li{it.type, it.type == IT_DIAG ? -1 : l1, l2, it.swap, it.pair_b};
             lp.items.push_back(li);
             lp.src.push_back((int)j);
             lp.map_id.push_back((int)lp.maps.size() - 1);
@@ -591,10 +633,10 @@ struct Compiler {
         const int nq = in->nq;
         std::string key;
         if (cut_cache) {
-            int32_t hdr[4] = {nq, k, C, RB};
+            int32_t hdr[5] = {nq, k, C, RB, pcap};
             key.append((const char*)hdr, sizeof hdr);
             for (size_t i = 0; i < items.size(); ++i) {
-                key.push_back((char)(items[i].type * 2 + (items[i].swap ? 1 : 0)));
+                key.push_back((char)(items[i].type * 4 + (items[i].swap ? 2 : 0) + (items[i].pair_b ? 1 : 0)));
                 key.push_back((char)items[i].bit);
                 key.push_back((char)items[i].bit2);
             }
@@ -660,6 +702,24 @@ struct Compiler {
         });
     }
 
+    // Passes the tile and cut choices make for `items` with large-stride preference p.
+    int count_passes(const std::vector<ScanItem>& items, int p) {
+        const int saved = pcap;
+        pcap = p;
+        std::vector<char> done(items.size(), 0);
+        int left = (int)items.size(), passes = 0;
+        while (left > 0) {
+            std::vector<int> sel;
+            std::vector<int> t = choose_tile(items, done, &sel);
+            sel = choose_cut(items, done, left, t, sel);
+            for (int i : sel) done[i] = 1;
+            left -= (int)sel.size();
+            ++passes;
+        }
+        pcap = saved;
+        return passes;
+    }
+
     void compile(const std::vector<Prim>& prims, std::vector<HostPass>* out) {
         const int nq = in->nq;
         const int n = (int)prims.size();
@@ -669,8 +729,14 @@ struct Compiler {
             if (p.kind != Prim::GATE)
                 items[i] = {IT_DIAG, -1, -1};
             else
-                items[i] = {p.gk == Prim::GPHASE ? IT_PHASE : IT_GATE, p.bit, p.bit2, p.gk == Prim::GSWAP};
+                items[i] = {p.gk == Prim::GPHASE ? IT_PHASE : IT_GATE, p.bit, p.bit2, p.gk == Prim::GSWAP,
+                            !(backward && p.gk == Prim::GD4)};
         }
+        // The large-stride preference only breaks ties between equally useful tile
+        // bits; where it nevertheless costs passes (two-qubit gates on neighbouring
+        // qubits, whose single bits are all "half useful"), this compile drops it.
+        pcap = plan->tiling.page_cap;
+        if (pcap > 0 && n > 0 && count_passes(items, 0) < count_passes(items, pcap)) pcap = 0;
         std::vector<char> done(n, 0);
         int left = n;
         ScaleState sc;
@@ -771,9 +837,13 @@ struct Compiler {
                             o.kind = OP_MAT;
                             o.arg = 2 * p.idx + (backward ? 1 : 0);
                         } else if (p.gk == Prim::GMAT4 || p.gk == Prim::GD4 || p.gk == Prim::GSWAP) {
-                            // the stage holds the pair on register bits 0 (is1) and 1 (is2)
-                            if (o.a != 0 || reg_of(it.bit2) != 1) throw std::logic_error("two-qubit register pair");
-                            o.a = 0;
+                            // the stage holds the pair on register bits 0 (is1) and 1 (is2),
+                            // or, as its second pair, on bits 2 and 3
+                            const int r2 = reg_of(it.bit2);
+                            if (!((o.a == 0 && r2 == 1) || (o.a == 2 && r2 == 3)))
+                                throw std::logic_error("two-qubit register pair");
+                            if (backward && p.gk == Prim::GD4 && o.a != 0)
+                                throw std::logic_error("backward D4 on the second register pair");
                             if (p.gk == Prim::GMAT4 || p.gk == Prim::GSWAP) {
                                 o.kind = OP_MAT4;
                                 o.arg = 2 * p.idx + (backward ? 1 : 0);
@@ -1434,7 +1504,8 @@ std::string describe(const Plan* plan) {
                          ",\"mat_post_a\":" + std::to_string(u.mat_post_a) + ",\"mat_post\":" +
                          std::to_string(u.mat_post) + ",\"d2b_a\":" + std::to_string(u.d2b_a) +
                          ",\"d2b_mat\":" + std::to_string(u.d2b_mat) + ",\"d2b_gscale\":" + buf +
-                         ",\"mat4\":" + std::to_string(u.mat4) + ",\"d4b_mat\":" + std::to_string(u.d4b_mat);
+                         ",\"mat4\":" + std::to_string(u.mat4) + ",\"mat4b\":" + std::to_string(u.mat4b) +
+                         ",\"d4b_mat\":" + std::to_string(u.d4b_mat);
                     std::snprintf(buf, sizeof buf, "%.17g", (double)u.d4b_gscale);
                     s += ",\"d4b_gscale\":";
                     s += buf;

@@ -83,6 +83,50 @@ def test_search_against_closed_form(nq, prec):
     assert abs(want[x]) ** 2 > 0.9  # the search succeeds (Sec. 5.1)
 
 
+@pytest.mark.parametrize("nq,prec,tile", [(12, "fp64", None), (20, "fp64", 12), (20, "fp64", None),
+                                          (18, "fp32", None), (16, "fp64", 8)])
+def test_persistent_launch_equals_launch_per_pass(nq, prec, tile, monkeypatch):
+    """pk_evaluate_repeat runs one launch per pass; PK_REPEAT_PERSISTENT=1 runs every
+    pass of every iteration in one persistent launch with grid barriers.  The same
+    kernels run on the same tiles in the same order, so the states agree bit for
+    bit."""
+    pk = _pk()
+    nt = pk.grover_iterations(nq)
+    x = int(np.random.default_rng(nq + 7).integers(0, 1 << nq))
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    out = {}
+    for mode in ("persistent", "per_pass"):
+        monkeypatch.setenv("PK_REPEAT_PERSISTENT", "1" if mode == "persistent" else "0")
+        plan = pk.Plan({"nq": nq, "gates": W.grover_gates((2, 3, 0.3, 0.4, 0.0)), "marked": [x]}, prec=prec)
+        if tile:
+            plan.set_tiling(tile, 4, 1)
+        _say("repeat n_q=%d n_t=%d %s tile %s: %s" % (nq, nt, prec, tile, mode))
+        for _ in range(2):  # capture, then a replay
+            y, L, norm = pk.evaluate_repeat(plan, _uniform(nq, dt), nt)
+        torch.cuda.synchronize()
+        out[mode] = (y, L.item(), norm.item())
+    assert torch.equal(out["persistent"][0], out["per_pass"][0])
+    assert out["persistent"][1:] == out["per_pass"][1:]
+    assert np.isfinite(out["persistent"][1])
+
+
+def test_persistent_barrier_time_out_gives_nan(monkeypatch):
+    """A grid barrier that is not complete within its bound gives up: forced here
+    from the host with a zero wait bound (PK_BARRIER_SPIN_US=0), so workgroups
+    that arrive before the last one stop waiting.  Every kernel still ends; L and
+    the norm come out NaN instead of a hang or a silently wrong value."""
+    pk = _pk()
+    monkeypatch.setenv("PK_BARRIER_SPIN_US", "0")
+    monkeypatch.setenv("PK_REPEAT_PERSISTENT", "1")
+    nq = 20
+    plan = pk.Plan({"nq": nq, "gates": W.grover_gates(), "marked": [5]})
+    plan.set_tiling(12, 4, 1)
+    _say("repeat with a zero barrier bound, n_q=%d" % nq)
+    y, L, norm = pk.evaluate_repeat(plan, _uniform(nq), 50)
+    torch.cuda.synchronize()
+    assert np.isnan(L.item()) and np.isnan(norm.item())
+
+
 def test_noisy_iteration_repeated_against_gate_by_gate_oracle():
     pk = _pk()
     nq, reps = 9, 7

@@ -6,12 +6,17 @@
         writes under DIR.
 
     python -m paper_0902_0699_amd.profsum traffic FETCH_DIR WRITE_DIR --kernel SUBSTR
-            --copy SUBSTR --copy-bytes B [--json OUT]
+            --copy SUBSTR --copy-bytes B [--skip N] [--take M] [--json OUT]
         HBM bytes per dispatch of the kernels whose name contains --kernel, from two
         `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs.  Each counter is
         scaled by what it reads for a plain copy kernel (name contains --copy) that
         reads B bytes and writes B bytes, so the figure does not depend on the
-        counter's unit or on caching of the copy's traffic.
+        counter's unit or on caching of the copy's traffic.  --skip / --take keep
+        only dispatches N .. N+M-1 of the matching kernels in dispatch order (a run
+        that launches one kernel for two workloads, one after the other).
+
+    python -m paper_0902_0699_amd.profsum counters DIR --kernel SUBSTR [--skip N] [--take M]
+        average per dispatch of every counter collected in DIR for those kernels.
 """
 
 import argparse
@@ -56,26 +61,41 @@ def kernel_stats(directory):
 
 
 def counter_per_dispatch(directory, counter):
-    """{kernel name: [value per dispatch]} for one counter (summed over dimensions)."""
+    """{kernel name: [value per dispatch]} for one counter (summed over dimensions),
+    each list in dispatch order."""
     per = {}
     for path in _one(os.path.join(directory, "**", "*counter_collection.csv")):
         with open(path, newline="") as f:
             for r in csv.DictReader(f):
                 if r["Counter_Name"] != counter:
                     continue
-                key = (r["Kernel_Name"], r["Dispatch_Id"])
+                key = (r["Kernel_Name"], int(r["Dispatch_Id"]))
                 per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
     out = {}
-    for (name, _), v in per.items():
+    for (name, _), v in sorted(per.items(), key=lambda kv: kv[0][1]):
         out.setdefault(name, []).append(v)
     return out
 
 
-def _match(d, sub):
+def counter_names(directory):
+    names = set()
+    for path in _one(os.path.join(directory, "**", "*counter_collection.csv")):
+        with open(path, newline="") as f:
+            for r in csv.DictReader(f):
+                names.add(r["Counter_Name"])
+    return sorted(names)
+
+
+def _match(d, sub, skip=0, take=None):
     hits = {k: v for k, v in d.items() if sub in k}
     if not hits:
         raise SystemExit("no kernel name contains %r; have: %s" % (sub, ", ".join(sorted(d))[:2000]))
+    if len(hits) > 1 and (skip or take):
+        raise SystemExit("--skip/--take need one kernel name; %r matches %s" % (sub, sorted(hits)))
     vals = [x for v in hits.values() for x in v]
+    vals = vals[skip:] if take is None else vals[skip:skip + take]
+    if not vals:
+        raise SystemExit("no dispatch left after --skip/--take")
     return sum(vals) / len(vals), len(vals), sorted(hits)
 
 
@@ -95,9 +115,11 @@ def cmd_stats(args):
 
 def cmd_traffic(args):
     res = {"kernel": args.kernel, "copy_kernel": args.copy, "copy_bytes_each_way": args.copy_bytes}
+    if args.skip or args.take:
+        res["dispatches"] = {"skip": args.skip, "take": args.take}
     for counter, d in (("FETCH_SIZE", args.fetch_dir), ("WRITE_SIZE", args.write_dir)):
         vals = counter_per_dispatch(d, counter)
-        k_avg, k_n, k_names = _match(vals, args.kernel)
+        k_avg, k_n, k_names = _match(vals, args.kernel, args.skip, args.take)
         c_avg, c_n, _ = _match(vals, args.copy)
         scale = args.copy_bytes / c_avg
         res[counter] = {"kernel_raw_avg": k_avg, "kernel_dispatches": k_n, "copy_raw_avg": c_avg,
@@ -112,6 +134,18 @@ def cmd_traffic(args):
     print(text)
 
 
+def cmd_counters(args):
+    print("| counter | dispatches | average per dispatch |")
+    print("|---|---|---|")
+    for c in counter_names(args.dir):
+        vals = counter_per_dispatch(args.dir, c)
+        try:
+            avg, n, _ = _match(vals, args.kernel, args.skip, args.take)
+        except SystemExit:
+            continue
+        print("| %s | %d | %.6g |" % (c, n, avg))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="rocprofv3 CSV summaries")
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -124,8 +158,15 @@ def main(argv=None):
     t.add_argument("--copy", required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--json")
+    t.add_argument("--skip", type=int, default=0)
+    t.add_argument("--take", type=int, default=None)
+    c = sub.add_parser("counters")
+    c.add_argument("dir")
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--skip", type=int, default=0)
+    c.add_argument("--take", type=int, default=None)
     args = ap.parse_args(argv)
-    {"stats": cmd_stats, "traffic": cmd_traffic}[args.cmd](args)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters}[args.cmd](args)
 
 
 if __name__ == "__main__":

@@ -103,7 +103,9 @@ def check_stage_shapes(nq, p):
         for op in st["ops"]:
             if op["kind"] in ("H", "MAT", "D2BWD"):
                 assert 0 <= op["a"] < len(rb)
-            if op["kind"] in ("MAT4", "D4BWD"):
+            if op["kind"] == "MAT4":  # a pair on register bits 0, 1 or (second pair) 2, 3
+                assert op["a"] in (0, 2) and len(rb) >= op["a"] + 2
+            if op["kind"] == "D4BWD":
                 assert op["a"] == 0 and len(rb) >= 2
     assert len(set(p["tile_bits"])) == len(p["tile_bits"]) == k
     assert all(0 <= b < nq for b in p["tile_bits"])
@@ -174,7 +176,7 @@ _STEP_BITS = [("exchange", lambda v: v == 1), ("seed", lambda v: v >= 0), ("flip
               ("phase_count", lambda v: v > 0), ("mat_pre_a", lambda v: v >= 0), ("hmask1", lambda v: v != 0),
               ("flip_mid", lambda v: v >= 0), ("hmask2", lambda v: v != 0), ("mat_post_a", lambda v: v >= 0),
               ("mat4", lambda v: v >= 0), ("d2b_a", lambda v: v >= 0), ("d4b_mat", lambda v: v >= 0),
-              ("scale", lambda v: v != 0), ("read", lambda v: v >= 0)]
+              ("scale", lambda v: v != 0), ("read", lambda v: v >= 0), ("mat4b", lambda v: v >= 0)]
 
 
 def _steps_of(u):
@@ -232,6 +234,9 @@ def _run_subs(problems, desc, inst, direction, psi, lam=None, dL=1.0):
             if u["mat4"] >= 0:
                 for v in vecs:
                     _apply_pair(v, nq, tb[rb[0]], tb[rb[1]], mat.four(u["mat4"]))
+            if u["mat4b"] >= 0:
+                for v in vecs:
+                    _apply_pair(v, nq, tb[rb[2]], tb[rb[3]], mat.four(u["mat4b"]))
             if u["d2b_a"] >= 0:
                 bit = tb[rb[u["d2b_a"]]]
                 m0 = u["d2b_mat"]
@@ -291,7 +296,8 @@ def run_forward_ops(problems, desc, inst, psi_in):
                     bit = tb[st["rb"][op["a"]]]
                     _apply_bit(psi, nq, bit, H if kind == "H" else mat(op["arg"]))
                 elif kind == "MAT4":
-                    _apply_pair(psi, nq, tb[st["rb"][0]], tb[st["rb"][1]], mat.four(op["arg"]))
+                    a = op["a"]
+                    _apply_pair(psi, nq, tb[st["rb"][a]], tb[st["rb"][a + 1]], mat.four(op["arg"]))
                 elif kind == "PHASE":
                     psi[_phase_mask(nq, op["b1"], op["b2"])] *= complex(op["c"], op["s"])
                 elif kind == "FLIP":
@@ -344,7 +350,7 @@ def run_backward_ops(problems, desc, inst, psi_out, dL):
                     _apply_bit(psi, nq, bit, M)
                     _apply_bit(lam, nq, bit, M)
                 elif kind == "MAT4":
-                    b1, b2 = tb[st["rb"][0]], tb[st["rb"][1]]
+                    b1, b2 = tb[st["rb"][op["a"]]], tb[st["rb"][op["a"] + 1]]
                     _apply_pair(psi, nq, b1, b2, mat.four(op["arg"]))
                     _apply_pair(lam, nq, b1, b2, mat.four(op["arg"]))
                 elif kind == "D4BWD":

@@ -277,6 +277,29 @@ def test_batched_against_oracle(prec, reg_bits):
         assert abs(norm[k] - nw) <= tol, k
 
 
+@pytest.mark.parametrize("nq,prec,tile", [(16, "fp64", None), (20, "fp64", None), (24, "fp64", None),
+                                          (20, "fp32", None), (18, "fp64", 10), (22, "fp32", 12)])
+def test_brickwork_two_pairs_per_stage_against_oracle(nq, prec, tile):
+    """Random unitary TwoOpA gates on neighbouring qubits (Eq. resmat2) in two
+    brickwork layers: stages hold two disjoint qubit pairs (register bits 0, 1 and
+    2, 3).  Every element against the gate-by-gate oracle."""
+    import bench
+    rng = np.random.default_rng(800 + nq)
+    gates = bench.brickwork_gates(nq, 11 + nq)
+    marked = [int(rng.integers(0, 1 << nq))]
+    prob = {"nq": nq, "gates": gates, "marked": marked}
+    psi = _state(rng, nq)
+    _say("brickwork n_q=%d %s tile %s" % (nq, prec, tile))
+    plan, got, L, norm = _run(prob, psi, prec=prec, tiling=(tile, 4, 1) if tile else None)
+    desc = plan.describe()["instances"][0]["forward"]
+    assert any(u["mat4b"] >= 0 for p in desc for u in p["subs"])
+    want, Lw, nw = O.evaluate(nq, gates, marked, psi)
+    tol = TOL64 if prec == "fp64" else TOL32
+    err = _relerr(got, want)
+    _say("  passes %d  normwise err %.3e" % (plan.passes(), err))
+    assert err <= tol and abs(L - Lw) <= tol and abs(norm - nw) <= tol
+
+
 # --------------------------------------------------------------------------- gradients
 
 

@@ -353,8 +353,48 @@ def test_two_qubit_gate_schedules_match_oracle(seed):
     plan, desc = _check_forward(prob, _state(rng, nq), tiling, reg_bits=5 if seed % 3 == 2 else 4)
     for p in desc["instances"][0]["forward"]:
         for st in p["stages"]:
-            pairs = {(st["rb"][0], st["rb"][1]) for op in st["ops"] if op["kind"] == "MAT4"}
-            assert len(pairs) <= 1
+            pairs = {(st["rb"][op["a"]], st["rb"][op["a"] + 1]) for op in st["ops"] if op["kind"] == "MAT4"}
+            assert len(pairs) <= 2 and len({b for pr in pairs for b in pr}) == 2 * len(pairs)
+
+
+@pytest.mark.parametrize("nq,tiling,reg_bits", [(8, (6, 2, 1), 4), (12, (7, 3, 1), 4), (14, (8, 4, 1), 5),
+                                                (16, None, 4), (11, (6, 2, 1), 5)])
+def test_brickwork_stages_hold_two_disjoint_pairs(nq, tiling, reg_bits):
+    """A brickwork of random unitary TwoOpA gates on neighbouring qubits (Eq. resmat2):
+    stages take two disjoint qubit pairs, on register bits 0, 1 and 2, 3; the packed
+    schedule, executed on the CPU, equals the gate-by-gate oracle, forward and back."""
+    import bench
+    rng = np.random.default_rng(500 + nq)
+    gates = bench.brickwork_gates(nq, 7 + nq)
+    prob = {"nq": nq, "gates": gates, "marked": [int(rng.integers(0, 1 << nq))]}
+    psi = _state(rng, nq)
+    plan, desc = _check_forward(prob, psi, tiling, reg_bits=reg_bits)
+    two = [st for p in desc["instances"][0]["forward"] for st in p["stages"]
+           if len({op["a"] for op in st["ops"] if op["kind"] == "MAT4"}) == 2]
+    assert two, "no stage holds two pairs"
+    subs = [u for p in desc["instances"][0]["forward"] for u in p["subs"]]
+    assert any(u["mat4b"] >= 0 for u in subs)
+    psi_out, _, _ = O.evaluate(nq, gates, prob["marked"], psi)
+    gpsi, _ = run_backward([prob], desc, 0, psi_out, 0.5)
+    wpsi, _ = O.adjoint_grad(nq, gates, prob["marked"], psi, 0.5)
+    np.testing.assert_allclose(gpsi, wpsi, rtol=0, atol=1e-12)
+
+
+def test_brickwork_at_thirty_qubits_takes_four_passes():
+    """The 29-gate brickwork at n_q = 30 in 2^13 tiles: 4 passes.  The large-stride
+    tile-bit preference (page_cap) would cost three more here, so the compiler drops
+    it for this list; the noisy Grover iteration keeps it (5 passes either way)."""
+    import bench
+    plan = pk.Plan({"nq": 30, "gates": bench.brickwork_gates(30, 5), "marked": [0]})
+    assert plan.passes() == 4
+    stages = [len(p["stages"]) for p in plan.describe()["instances"][0]["forward"]]
+    assert sum(stages) <= 18
+    inst = W.draw_instance(np.random.default_rng(1), 30, with_state=False)
+    g = pk.Plan({"nq": 30, "gates": inst["gates"], "marked": inst["marked"]})
+    assert g.passes() == 5
+    # bits at byte strides of 2 MiB or more (17 and up in FP64) stay spread: at most 5 a pass
+    big = [sum(b >= 17 for b in p["tile_bits"]) for p in g.describe()["instances"][0]["forward"]]
+    assert max(big) <= 5
 
 
 @pytest.mark.parametrize("nq,tiling", [(6, None), (9, (5, 2, 1)), (12, (6, 2, 1)), (11, (4, 0, 0))])

@@ -70,8 +70,9 @@ extern "C" {
 #define PK_GATE_QFT 12    /* quantum Fourier transform of the register of qubits is1 .. is1+k-1
                              (k >= 1, is2 = 0): <n|QFT|n'> = 2^(-k/2) e^{2 pi i n n' / 2^k}, n the
                              register's value with qubit is1 most significant (App. A).  Lowered
-                             to the circuit of App. A: Hadamards, CPHASEK(q, ic, q + 1 - ic) and
-                             the pair swaps that restore standard order                         */
+                             to the circuit App. A draws, derived from that definition: per qubit,
+                             CPHASEK with each earlier qubit (exponent: their distance + 1), then
+                             its Hadamard; then the pair swaps that restore standard order      */
 #define PK_GATE_QFT_NOSWAP 13 /* a labelled variant, not the paper's circuit: PK_GATE_QFT without the
                              final pair swaps, so the register comes out with its qubit order
                              reversed (amplitude of value n at the bit-reversed value).  Read

@@ -234,7 +234,7 @@ def load_tuning():
         return {}
 
 
-def batched_run(torch, pk, W, autotune, steps, warmup, prec, insts, record=None):
+def batched_run(torch, pk, W, autotune, steps, warmup, prec, insts, record=None, loop=True):
     """The 4096-instance batch (Sec. 6.2) in one persistent graph-replayed launch, at
     the recorded setting (or retuned when ``record`` is None), against a loop of
     single-instance evaluations of the same instances."""
@@ -265,23 +265,25 @@ def batched_run(torch, pk, W, autotune, steps, warmup, prec, insts, record=None)
     ms_batched = e0.elapsed_time(e1) / steps
     # plain form: one single-instance evaluation per instance, back to back
     offs = plan.offsets()
-    singles = [pk.Plan(p, prec=prec) for p in probs]
-    views = [(packed[offs[k]:offs[k + 1]], out[offs[k]:offs[k + 1]]) for k in range(len(probs))]
-    for sp, (a, b) in zip(singles, views):
-        pk.evaluate(sp, a, out=b)
-    torch.cuda.synchronize()
-    e0.record()
-    for sp, (a, b) in zip(singles, views):
-        pk.evaluate(sp, a, out=b)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_loop = e0.elapsed_time(e1)
+    ms_loop = None
+    if loop:
+        singles = [pk.Plan(p, prec=prec) for p in probs]
+        views = [(packed[offs[k]:offs[k + 1]], out[offs[k]:offs[k + 1]]) for k in range(len(probs))]
+        for sp, (a, b) in zip(singles, views):
+            pk.evaluate(sp, a, out=b)
+        torch.cuda.synchronize()
+        e0.record()
+        for sp, (a, b) in zip(singles, views):
+            pk.evaluate(sp, a, out=b)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_loop = e0.elapsed_time(e1)
     total = offs[-1]
     esz = 16 if prec == "fp64" else 8
-    log("batched %s: %.3f ms per batch, loop of singles %.2f ms" % (prec, ms_batched, ms_loop))
+    log("batched %s: %.3f ms per batch, loop of singles %s ms" % (prec, ms_batched, ms_loop))
     res = {"instances": len(insts), "amplitudes": total, "dtype": "f64" if prec == "fp64" else "f32",
            "ms_per_batch": ms_batched, "instances_per_s": len(insts) / (ms_batched * 1e-3),
-           "ms_loop_of_singles": ms_loop, "speedup_vs_loop": ms_loop / ms_batched,
+           "ms_loop_of_singles": ms_loop, "speedup_vs_loop": ms_loop / ms_batched if ms_loop else None,
            "compulsory_GBs": 2.0 * total * esz / (ms_batched * 1e-3) / 1e9,
            "compulsory_frac": 2.0 * total * esz / (ms_batched * 1e-3) / 1e9 / PEAK_HBM_GBS,
            "setting": {k: best[k] for k in autotune.FIELDS if k in best},
@@ -313,7 +315,9 @@ def gradient_run(torch, pk, W, nq):
     h = 1e-6
     L_of = lambda xx, aa: pk.evaluate(plan, xx, angles=aa, want_norm=False)[1].item()
     fd, ad = [], []
-    for kind, where in comps:
+    for q, (kind, where) in enumerate(comps):
+        if q % 16 == 0:
+            log("gradient: central differences, input %d of %d" % (q, len(comps)))
         if kind == "angle":
             ap, am = ang.clone(), ang.clone()
             ap[where] += h
@@ -581,6 +585,8 @@ def main():
                     help="also time the two-qubit brickwork, Shor's data path, the density matrix and the search")
     ap.add_argument("--legs", default="batched,gradient,two_qubit,shor,density,search",
                     help="comma-separated legs to run (batched and gradient always, the others with --extra)")
+    ap.add_argument("--no-loop", action="store_true",
+                    help="skip the batched leg's loop of single launches (for counter runs: thousands of dispatches)")
     ap.add_argument("--retune", metavar="OUT.json",
                     help="autotune the batched workload instead of using the recorded setting; write the record")
     args = ap.parse_args()
@@ -664,7 +670,7 @@ def main():
         new_records = {}
         for p in ("fp64", "fp32"):
             rec = None if args.retune else records.get("batched_" + p)
-            line["batched"][p], best = batched_run(torch, pk, W, autotune, k, 1, p, insts, rec)
+            line["batched"][p], best = batched_run(torch, pk, W, autotune, k, 1, p, insts, rec, not args.no_loop)
             new_records["batched_" + p] = {"setting": best, "sources": autotune._sources_hash(),
                                            "device": torch.cuda.get_device_name(0),
                                            "ms_per_batch": line["batched"][p]["ms_per_batch"]}

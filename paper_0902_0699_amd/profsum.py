@@ -17,6 +17,11 @@
 
     python -m paper_0902_0699_amd.profsum counters DIR --kernel SUBSTR [--skip N] [--take M]
         average per dispatch of every counter collected in DIR for those kernels.
+
+    python -m paper_0902_0699_amd.profsum trace DIR --kernel SUBSTR [--min-ms T] [--skip N] [--take M]
+        durations of one kernel's dispatches from the *kernel_trace.csv of a
+        `--kernel-trace` run: those of at least T ms (a workload's size), then
+        dispatches N .. N+M-1 of them in dispatch order.
 """
 
 import argparse
@@ -146,6 +151,27 @@ def cmd_counters(args):
         print("| %s | %d | %.6g |" % (c, n, avg))
 
 
+def cmd_trace(args):
+    ms = []
+    for path in _one(os.path.join(args.dir, "**", "*kernel_trace.csv")):
+        with open(path, newline="") as f:
+            for r in csv.DictReader(f):
+                if args.kernel not in r["Kernel_Name"]:
+                    continue
+                t = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6
+                if t >= args.min_ms:
+                    ms.append((int(r["Dispatch_Id"]), t, r["Kernel_Name"]))
+    ms.sort()
+    ms = ms[args.skip:] if args.take is None else ms[args.skip:args.skip + args.take]
+    if not ms:
+        raise SystemExit("no dispatch matches")
+    names = sorted({short(n, 200) for _, _, n in ms})
+    t = [x for _, x, _ in ms]
+    print("| kernel | dispatches | avg ms | min ms | max ms |")
+    print("|---|---|---|---|---|")
+    print("| %s | %d | %.4f | %.4f | %.4f |" % (", ".join(names), len(t), sum(t) / len(t), min(t), max(t)))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="rocprofv3 CSV summaries")
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -165,8 +191,14 @@ def main(argv=None):
     c.add_argument("--kernel", required=True)
     c.add_argument("--skip", type=int, default=0)
     c.add_argument("--take", type=int, default=None)
+    r = sub.add_parser("trace")
+    r.add_argument("dir")
+    r.add_argument("--kernel", required=True)
+    r.add_argument("--min-ms", type=float, default=0.0)
+    r.add_argument("--skip", type=int, default=0)
+    r.add_argument("--take", type=int, default=None)
     args = ap.parse_args(argv)
-    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters}[args.cmd](args)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters, "trace": cmd_trace}[args.cmd](args)
 
 
 if __name__ == "__main__":

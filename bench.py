@@ -391,11 +391,17 @@ def two_qubit_run(torch, pk, nq, steps):
     return out
 
 
-def shor_run(torch, pk, W, autotune, steps, prec):
+def shor_run(torch, pk, W, autotune, steps, prec, qft_tiling=None):
     """Shor's data path at n_q = 30 (Sec. 5.2): the loaded state of Eq. Shor2, the QFT
     of register one (App. A) in place, and the distribution of register one; each
     part timed with HIP events on the current stream.  The QFT plan's tiling is
-    tuned first on the same buffer."""
+    tuned first on the same buffer, or fixed to ``qft_tiling`` = (tile bits, carrier
+    bits, register bits), which keeps a profiled run's dispatches the same each
+    time: the first evaluation's passes come first."""
+    cands = None
+    if qft_tiling:
+        t, c, r = qft_tiling
+        cands = [{"tile_bits": t, "carrier_bits": c, "lane_order": 1, "reg_bits": r, "wgs_per_cu": 0}]
     M = W.SHOR_M
     x = W.shor_xguess(W.SEEDS["shor"])
     n1, n2 = pk.shor_register_sizes(M)
@@ -408,7 +414,8 @@ def shor_run(torch, pk, W, autotune, steps, prec):
     L = torch.empty(1, dtype=torch.float64, device="cuda")
     plan = pk.Plan({"nq": nq, "gates": [("QFT", 1, n1)], "marked": []}, prec=prec)
     pk.shor_state(n1, n2, x, M, prec=prec, out=psi)
-    best, _ = autotune.tune(plan, lambda: pk.evaluate_into(plan, psi, psi, L), op="eval", use_cache=False)
+    best, _ = autotune.tune(plan, lambda: pk.evaluate_into(plan, psi, psi, L), op="eval", use_cache=False,
+                            cands=cands)
 
     def run(ev=None):
         if ev:
@@ -451,7 +458,8 @@ def shor_run(torch, pk, W, autotune, steps, prec):
     p_ref = p.clone()
     plan2 = pk.Plan({"nq": nq, "gates": [("QFT_NOSWAP", 1, n1)], "marked": []}, prec=prec)
     pk.shor_state(n1, n2, x, M, prec=prec, out=psi)
-    best2, _ = autotune.tune(plan2, lambda: pk.evaluate_into(plan2, psi, psi, L), op="eval", use_cache=False)
+    best2, _ = autotune.tune(plan2, lambda: pk.evaluate_into(plan2, psi, psi, L), op="eval", use_cache=False,
+                             cands=cands)
 
     def run2(ev):
         ev[0].record()
@@ -585,6 +593,9 @@ def main():
                     help="also time the two-qubit brickwork, Shor's data path, the density matrix and the search")
     ap.add_argument("--legs", default="batched,gradient,two_qubit,shor,density,search",
                     help="comma-separated legs to run (batched and gradient always, the others with --extra)")
+    ap.add_argument("--qft-tiling", metavar="T,C,R",
+                    help="fixed QFT tiling for the shor leg (tile, carrier, register bits) instead of tuning")
+    ap.add_argument("--shor-precs", default="fp64,fp32", help="precisions of the shor leg")
     ap.add_argument("--no-loop", action="store_true",
                     help="skip the batched leg's loop of single launches (for counter runs: thousands of dispatches)")
     ap.add_argument("--retune", metavar="OUT.json",
@@ -596,6 +607,9 @@ def main():
               "(instances and amplitude blocks would shard across GPUs, but that path is not built)"
               % max(args.gpus, world), file=sys.stderr)
         sys.exit(2)
+    qft_tiling = tuple(int(v) for v in args.qft_tiling.split(",")) if args.qft_tiling else None
+    if qft_tiling is not None and len(qft_tiling) != 3:
+        ap.error("--qft-tiling takes three integers")
 
     import torch
     from paper_0902_0699_amd import autotune
@@ -687,7 +701,8 @@ def main():
         torch.cuda.empty_cache()
     if args.extra:
         runs = [("two_qubit", lambda: two_qubit_run(torch, pk, nq, k)),
-                ("shor", lambda: {p: shor_run(torch, pk, W, autotune, k, p) for p in ("fp64", "fp32")}),
+                ("shor", lambda: {p: shor_run(torch, pk, W, autotune, k, p, qft_tiling)
+                                  for p in args.shor_precs.split(",")}),
                 ("density", lambda: density_run(torch, pk, W, k)),
                 ("search", lambda: search_run(torch, pk, W, autotune, 3))]
         for name, run in runs:

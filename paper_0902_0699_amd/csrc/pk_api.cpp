@@ -116,7 +116,8 @@ int ensure_device(DevPlan* d) {
     put(buf, t.stages, P.stages);
     put(buf, t.flips, P.flips);
     put(buf, t.phases, P.phases);
-    put(buf, t.upairs, P.upairs);
+    put(buf, t.twid, P.twid);
+    put(buf, t.urefs, P.urefs);
     put(buf, t.mats, P.static_mats);
     put(buf, t.mats + P.static_mats.size() * sizeof(double), P.default_angles);
     put(buf, t.mats4, P.static_mats4);
@@ -170,7 +171,8 @@ PassLaunch base_launch(DevPlan* d, void* ws, int op) {
     L.stages = at<Stage>(P.d_tables, t.stages);
     L.flips = at<Flip>(P.d_tables, t.flips);
     L.phases = at<PhaseOp>(P.d_tables, t.phases);
-    L.upairs = at<UPair>(P.d_tables, t.upairs);
+    L.twid = at<double>(P.d_tables, t.twid);
+    L.urefs = at<URef>(P.d_tables, t.urefs);
     L.mats = at<double>(ws, w.mats);
     L.mats4 = at<double>(ws, w.mats4);
     L.partials = at<double>(ws, w.partials);

@@ -36,7 +36,8 @@ enum OpKind : int32_t {
 };
 
 constexpr int kPhaseSlots = 4;  // phase accumulators per sub-stage
-constexpr int kMaxUPairs = 128; // tile-uniform slot products per pass (LDS table)
+constexpr int kTwidBits = 10;   // index bits of one product table (2^10 entries at most)
+constexpr int kMaxURefs = 64;   // tile-part tables one pass reads (one per lane of a wave)
 
 // One controlled phase as the kernel applies it in a sub-stage.  The amplitudes
 // whose two qubits are both 1 get the factor c + i s.  Each qubit's bit sits on
@@ -45,11 +46,22 @@ constexpr int kMaxUPairs = 128; // tile-uniform slot products per pass (LDS tabl
 // bits involved define the phase's accumulator slot (Stage::phase_pm); a thread
 // multiplies the factors of a slot together and applies the product once to
 // every register whose index has the slot's register bits set.  A sub-stage's
-// phases are stored grouped by slot (Stage::phase_cnt), so the kernel runs one
-// branch-free loop per slot.
+// phases are stored grouped by slot (Stage::phase_cnt).
+//
+// Product tables.  The factors of a slot's phases that depend only on the tile
+// index (tmask == 0) multiply to a function of the tile-index bits they name,
+// and those that depend only on the thread (fmask == 0) to a function of the
+// thread's label bits.  The host tabulates both (Plan::twid): up to two tables
+// for the tile part, indexed by the named tile-index bits (at most kTwidBits
+// each; bits tied by one phase share a table), and one for the thread part.
+// A pass lists its tile-part tables (URef, at most kMaxURefs); when a wave
+// issues a tile's loads, lane r also loads the entry of the pass's table r for
+// that tile, and the phase step reads it back from the lane.  The thread part
+// is one vector load per slot.  The phases left over, and every phase that did
+// not fit a table, run in a branch-free loop.
 struct PhaseOp {
     int32_t slot;    // accumulator slot of the sub-stage (within a slot, the phases
-                     // with tmask == 0 come first: see Stage::phase_ucnt)
+                     // in the product tables come first: see Stage::phase_ucnt)
     uint32_t tmask;  // local label bits held by the thread index that must be 1
     int64_t fmask;   // tile-index bits that must be 1
     double cm1, s;   // the factor as (c - 1, s): 1 + on * (c - 1) and on * s give the
@@ -86,7 +98,7 @@ enum StepBits : int32_t {
     ST_MAT4B = 16384,
 };
 
-// 16-byte aligned so that the slot table (phase_pm .. phase_upair) can be read as
+// 16-byte aligned so that the slot table (phase_pm .. phase_tt) can be read as
 // four aligned 16-byte words.
 struct alignas(16) Stage {
     int32_t steps;            // StepBits of the steps below that are present
@@ -99,9 +111,9 @@ struct alignas(16) Stage {
     int32_t phase_count;      // number of them (diagonal: any order)
     int32_t phase_pm[kPhaseSlots];   // register-bit mask of each accumulator slot, -1 when unused
     int32_t phase_cnt[kPhaseSlots];  // phases of each slot, stored slot after slot
-    int32_t phase_ucnt[kPhaseSlots]; // of them, the leading ones whose factor is the same for
-                                     // every thread of a tile (tmask == 0)
-    int32_t phase_upair[kPhaseSlots];// their product's entry in the pass's tile-uniform table, or -1
+    int32_t phase_ucnt[kPhaseSlots]; // of them, the leading ones whose factors the slot's product
+                                     // tables hold (the kernel loops over the rest)
+    int32_t phase_tt[kPhaseSlots];   // Plan::twid entry of the slot's thread-part table, or -1
     int32_t mat_pre_a;        // register bit of a matrix before the Hadamards, or -1
     int32_t mat_pre;          // its matrix index
     int32_t hmask1;           // register bits that get a Hadamard
@@ -121,10 +133,18 @@ struct alignas(16) Stage {
     int32_t read;             // flip index of a READ or -1
     int32_t mat4b;            // 4x4 matrix on register bits 2 (qubit is1) and 3 (qubit is2), or -1: a
                               // second, disjoint qubit pair of the same stage
+    // product tables of the slots (see PhaseOp): the tile part's first and second
+    // table (index into the pass's URef list, or -1), the thread part's local
+    // label bits
+    alignas(16) int32_t phase_ut0[kPhaseSlots];
+    int32_t phase_ut1[kPhaseSlots];
+    uint32_t phase_ttm[kPhaseSlots];
 };
 static_assert(offsetof(Stage, phase_pm) % 16 == 0 && offsetof(Stage, phase_cnt) == offsetof(Stage, phase_pm) + 16 &&
                   offsetof(Stage, phase_ucnt) == offsetof(Stage, phase_pm) + 32 &&
-                  offsetof(Stage, phase_upair) == offsetof(Stage, phase_pm) + 48,
+                  offsetof(Stage, phase_tt) == offsetof(Stage, phase_pm) + 48 &&
+                  offsetof(Stage, phase_ut0) % 16 == 0 && offsetof(Stage, phase_ut1) == offsetof(Stage, phase_ut0) + 16 &&
+                  offsetof(Stage, phase_ttm) == offsetof(Stage, phase_ut0) + 32,
               "slot table must be four consecutive aligned 16-byte words");
 static_assert(offsetof(Stage, mat_pre_a) % 16 == 0 && offsetof(Stage, mat_pre) == offsetof(Stage, mat_pre_a) + 4 &&
                   offsetof(Stage, hmask1) == offsetof(Stage, mat_pre_a) + 8 &&
@@ -157,10 +177,12 @@ struct Run {
     int32_t src, len, dst, pad;
 };
 
-// A tile-uniform product: the phases [first, first + count) of the phase table.
-struct UPair {
-    int32_t first;
-    int32_t count;
+// A tile-part product table of a pass: its first Plan::twid entry and the
+// tile-index bits that index it.
+struct URef {
+    int32_t base;
+    int32_t pad;
+    int64_t mask;
 };
 
 struct Pass {
@@ -177,8 +199,8 @@ struct Pass {
     int32_t ntrun;       // runs of consecutive tile bits
     int32_t nfrun;       // runs of consecutive free bits
     int32_t nstrun;      // runs of the store map
-    int32_t upair_begin; // first UPair of the pass
-    int32_t nupair;      // number of them (0: no table)
+    int32_t uref_begin;  // first URef of the pass
+    int32_t nuref;       // number of them (at most kMaxURefs)
     int32_t tpos[16];    // global bit position of local tile bit l when the tile is read
     int32_t stpos[16];   // ... when it is written (differs after SWAPs done by relabelling)
     Run trun[kMaxRuns];  // local tile label -> state label (read)

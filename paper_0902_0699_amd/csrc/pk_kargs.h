@@ -16,7 +16,8 @@ struct KArgs {
     const Stage* stages;
     const Flip* flips;
     const PhaseOp* phases;
-    const UPair* upairs;
+    const double* twid;  // product tables of the controlled phases (re, im pairs)
+    const URef* urefs;   // tile-part tables of each pass
     const double* mats;
     const double* mats4;  // 4x4 complex matrices of two-qubit gates, 32 doubles each
     const void* src0;  // vector 0 input of the first pass

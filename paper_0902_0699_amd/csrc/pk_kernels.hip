@@ -141,7 +141,8 @@ static KArgs kargs(const PassLaunch& L) {
     a.stages = L.stages;
     a.flips = L.flips;
     a.phases = L.phases;
-    a.upairs = L.upairs;
+    a.twid = L.twid;
+    a.urefs = L.urefs;
     a.mats = L.mats;
     a.mats4 = L.mats4;
     a.src0 = L.src0;

@@ -12,7 +12,8 @@ struct PassLaunch {
     const Stage* stages;
     const Flip* flips;
     const PhaseOp* phases;
-    const UPair* upairs;
+    const double* twid;  // product tables of the controlled phases (re, im pairs)
+    const URef* urefs;   // tile-part tables of each pass
     const double* mats;
     const double* mats4;
     const void* src0;

@@ -319,40 +319,103 @@ __device__ __forceinline__ void apply_slot(T (&v)[NV][NR], int pm, R c, R s) {
     }
 }
 
-// The leading phase_ucnt[u] phases of a slot do not depend on the thread: their
-// product for the current tile was computed once for the workgroup (ufac, see
-// compute_tile) and starts the slot's product.
-template <int NV, int NR, typename T>
+// Bits of x at the positions set in m, packed (bit k of the result is the k-th
+// set bit of m, counted from the least significant).
+__device__ __forceinline__ unsigned extract_bits(uint64_t x, uint64_t m) {
+    unsigned r = 0;
+    for (int k = 0; m; ++k) {
+        const int b = __builtin_ctzll(m);
+        r |= (unsigned)((x >> b) & 1u) << k;
+        m &= m - 1;
+    }
+    return r;
+}
+
+// A tile's entries of the pass's tile-part product tables: lane r of every wave
+// holds the entry of table r (entry 0, the factor 1, where the pass has no table r).
+template <typename R>
+struct TileRefs {
+    R c, s;
+};
+
+template <typename R>
+__device__ __forceinline__ TileRefs<R> load_refs(const KArgs& a, const PK_CONST Pass* P, int64_t tile) {
+    const int lane = (int)(threadIdx.x & 63u);
+    int e = 0;
+    if (lane < P->nuref) {
+        const URef r = a.urefs[P->uref_begin + lane];
+        e = r.base + (int)extract_bits((uint64_t)tile, (uint64_t)r.mask);
+    }
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 x = *reinterpret_cast<const d2*>(a.twid + 2 * e);
+    return {(R)x.x, (R)x.y};
+}
+
+__device__ __forceinline__ float lane_value(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+__device__ __forceinline__ double lane_value(double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// The leading phase_ucnt[u] phases of a slot are in its product tables: the
+// tile part is one or two of the tile's entries held by the lanes (U), the thread
+// part one entry indexed by the thread's label bits.  The remaining phases
+// multiply in one factor each.
+// The lanes are read with every lane of the wave active (a lane that is inactive
+// at a cross-lane read need not hold its value there); only the rest of the step
+// runs under `active`.
+template <int NV, int NR, typename T, typename R>
 __device__ __forceinline__ void apply_phases(const KArgs& a, const PK_CONST Stage* S, T (&v)[NV][NR],
-                                             const Layout& L, int64_t tile, const double* ufac) {
-    using R = decltype(v[0][0].x);
+                                             const Layout& L, int64_t tile, const TileRefs<R>& U, bool active) {
     const PK_CONST PhaseOp* ph = cptr(a.phases) + S->phase_first;
-    // the sub-stage's slot table as four 16-byte loads issued together (reading the
+    // the sub-stage's slot table in 16-byte loads issued together (reading the
     // fields where they are used costs one scalar round trip per field and slot)
     typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
     const i32x4 pms = *reinterpret_cast<const PK_CONST i32x4*>(S->phase_pm);
     const i32x4 cnts = *reinterpret_cast<const PK_CONST i32x4*>(S->phase_cnt);
     const i32x4 ucnts = *reinterpret_cast<const PK_CONST i32x4*>(S->phase_ucnt);
-    const i32x4 pairs = *reinterpret_cast<const PK_CONST i32x4*>(S->phase_upair);
+    const i32x4 tts = *reinterpret_cast<const PK_CONST i32x4*>(S->phase_tt);
+    const i32x4 ut0s = *reinterpret_cast<const PK_CONST i32x4*>(S->phase_ut0);
+    const i32x4 ut1s = *reinterpret_cast<const PK_CONST i32x4*>(S->phase_ut1);
+    const i32x4 ttms = *reinterpret_cast<const PK_CONST i32x4*>(S->phase_ttm);
 #pragma unroll
     for (int u = 0; u < kPhaseSlots; ++u) {
         const int cnt = cnts[u];
         if (cnt == 0) continue;
         R c0 = 1, s0 = 0, c1 = 1, s1 = 0;
-        const int pair = pairs[u];
-        if (pair >= 0) {
-            c0 = (R)ufac[2 * pair];
-            s0 = (R)ufac[2 * pair + 1];
+        if (ut0s[u] >= 0) {
+            c0 = lane_value(U.c, ut0s[u]);
+            s0 = lane_value(U.s, ut0s[u]);
+            if (ut1s[u] >= 0) {
+                const R cf = lane_value(U.c, ut1s[u]), sf = lane_value(U.s, ut1s[u]);
+                const R x = c0, y = s0;
+                c0 = x * cf - y * sf;
+                s0 = x * sf + y * cf;
+            }
+        }
+        const PK_CONST PhaseOp* ps = ph;
+        ph += cnt;
+        if (!active) continue;
+        if (tts[u] >= 0) {
+            const unsigned ix = extract_bits((uint64_t)L.jt, (uint64_t)(unsigned)ttms[u]);
+            const double* e = a.twid + 2 * (tts[u] + (int)ix);
+            c1 = (R)e[0];
+            s1 = (R)e[1];
         }
         int q = ucnts[u];
 #pragma unroll 2
         for (; q + 1 < cnt; q += 2) {
-            const int64_t fa = ph[q].fmask, fb = ph[q + 1].fmask;
-            const unsigned ta = ph[q].tmask, tb = ph[q + 1].tmask;
+            const int64_t fa = ps[q].fmask, fb = ps[q + 1].fmask;
+            const unsigned ta = ps[q].tmask, tb = ps[q + 1].tmask;
             const R oa = (R)(((tile & fa) == fa) & ((L.jt & ta) == ta));
             const R ob = (R)(((tile & fb) == fb) & ((L.jt & tb) == tb));
-            const R ca = fma(oa, (R)ph[q].cm1, (R)1), sa = oa * (R)ph[q].s;
-            const R cb = fma(ob, (R)ph[q + 1].cm1, (R)1), sb = ob * (R)ph[q + 1].s;
+            const R ca = fma(oa, (R)ps[q].cm1, (R)1), sa = oa * (R)ps[q].s;
+            const R cb = fma(ob, (R)ps[q + 1].cm1, (R)1), sb = ob * (R)ps[q + 1].s;
             R x = c0, y = s0;
             c0 = x * ca - y * sa;
             s0 = x * sa + y * ca;
@@ -362,15 +425,14 @@ __device__ __forceinline__ void apply_phases(const KArgs& a, const PK_CONST Stag
             s1 = x * sb + y * cb;
         }
         if (q < cnt) {
-            const int64_t fa = ph[q].fmask;
-            const unsigned ta = ph[q].tmask;
+            const int64_t fa = ps[q].fmask;
+            const unsigned ta = ps[q].tmask;
             const R oa = (R)(((tile & fa) == fa) & ((L.jt & ta) == ta));
-            const R ca = fma(oa, (R)ph[q].cm1, (R)1), sa = oa * (R)ph[q].s;
+            const R ca = fma(oa, (R)ps[q].cm1, (R)1), sa = oa * (R)ps[q].s;
             const R x = c0, y = s0;
             c0 = x * ca - y * sa;
             s0 = x * sa + y * ca;
         }
-        ph += cnt;
         const R c = c0 * c1 - s0 * s1, s = c0 * s1 + s0 * c1;
         apply_slot<NV, NR>(v, pms[u], c, s);
     }
@@ -548,7 +610,7 @@ __device__ __forceinline__ void element_op(const KArgs& a, T (&v)[NV][NR], const
 template <typename R, int NV, int KMAX, int RB>
 __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass* P, const PassCtx& C,
                                              int64_t tile, typename Cplx<R>::T (&v)[NV][1 << RB],
-                                             typename Cplx<R>::T* lds, double* red) {
+                                             const TileRefs<R>& U, typename Cplx<R>::T* lds, double* red) {
     constexpr int NT = 1 << (KMAX - RB);
     constexpr int NR = 1 << RB;
     const unsigned tid = threadIdx.x;
@@ -556,44 +618,6 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
     const int nreg = C.nreg;
     const PK_CONST Stage* S = cptr(a.stages) + P->stage_begin;
     Layout L = C.L0;
-    // tile-uniform phase products of the pass: one thread per product, in FP64,
-    // between two barriers (the previous tile's sub-stages may still read the table)
-    double* ufac = red + 16;
-    const int nup = P->nupair;
-    if (nup > 0) {
-        __syncthreads();
-        const PK_CONST UPair* U = cptr(a.upairs) + P->upair_begin;
-        for (int p = tid; p < nup; p += NT) {
-            const PK_CONST PhaseOp* ph = cptr(a.phases) + U[p].first;
-            const int cnt = U[p].count;
-            double c = 1.0, sn = 0.0;
-            // the table entries of eight phases are loaded before any is used, so
-            // their latencies overlap; the product keeps the phases' order
-            constexpr int kB = 8;
-            for (int q0 = 0; q0 < cnt; q0 += kB) {
-                int64_t fm[kB];
-                double cm1[kB], sq[kB];
-#pragma unroll
-                for (int j = 0; j < kB; ++j) {
-                    const bool in = q0 + j < cnt;
-                    fm[j] = in ? ph[q0 + j].fmask : 0;
-                    cm1[j] = in ? ph[q0 + j].cm1 : 0.0;
-                    sq[j] = in ? ph[q0 + j].s : 0.0;
-                }
-#pragma unroll
-                for (int j = 0; j < kB; ++j) {
-                    if (q0 + j >= cnt || (tile & fm[j]) != fm[j]) continue;
-                    const double cq = 1.0 + cm1[j];
-                    const double x = c;
-                    c = x * cq - sn * sq[j];
-                    sn = x * sq[j] + sn * cq;
-                }
-            }
-            ufac[2 * p] = c;
-            ufac[2 * p + 1] = sn;
-        }
-        __syncthreads();
-    }
     for (int s = 0; s < C.nstages; ++s, ++S) {
         // one scalar word says which steps follow; only their parameters are loaded
         const int steps = S->steps;
@@ -629,7 +653,7 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
             if (steps & ST_SEED) element_op<NV, NR, 2>(a, v, L, S->seed, tile, nreg, active);
         }
         if (steps & ST_FLIP_PRE) element_op<NV, NR, 0>(a, v, L, S->flip_pre, tile, nreg, active);
-        if ((steps & ST_PHASE) && active) apply_phases<NV, NR>(a, S, v, L, tile, ufac);
+        if (steps & ST_PHASE) apply_phases<NV, NR>(a, S, v, L, tile, U, active);
         if (steps & ST_MAT_PRE) {
             R m[8];
             const PK_CONST double* mp = cptr(a.mats) + 8 * mat_pre;
@@ -722,41 +746,49 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
 // tile's LDS stages, so memory traffic overlaps the exchange work of the one
 // workgroup an LDS-sized tile leaves per CU.  The prefetch is unconditional
 // (past the end it re-reads the current tile) so the wait counts stay static.
-template <typename R, int NV, int KMAX, int RB>
-__device__ __forceinline__ void run_tiles(const KArgs& a, const PK_CONST Pass* P, int64_t first,
-                                          int64_t stride, int64_t ntiles, typename Cplx<R>::T* lds, double* red) {
+// PH: the pass has tile-part product tables, whose entries are loaded with the
+// tile's amplitudes.
+template <typename R, int NV, int KMAX, int RB, bool PH>
+__device__ __forceinline__ void run_tiles_ph(const KArgs& a, const PK_CONST Pass* P, int64_t first,
+                                             int64_t stride, int64_t ntiles, typename Cplx<R>::T* lds, double* red) {
     using T = typename Cplx<R>::T;
     constexpr int NR = 1 << RB;
-    if (first >= ntiles) return;
     const PassCtx C = make_ctx<(int)sizeof(R) * 2, RB>(a, P);
     const int64_t off = P->state_off;
     const int nfrun = P->nfrun;
     auto base_of = [&](int64_t t) { return off + deposit(t, P->frun, nfrun); };
+    auto refs_of = [&](int64_t t) { return PH ? load_refs<R>(a, P, t) : TileRefs<R>{(R)1, (R)0}; };
     if constexpr (NV == 2) {
         // two vectors already fill the register file: no second buffer
         for (int64_t tile = first; tile < ntiles; tile += stride) {
             T v[NV][NR];
             const int64_t base = base_of(tile);
+            const TileRefs<R> u = refs_of(tile);
             load_tile<R, NV, NR>(a, C, base, v);
-            compute_tile<R, NV, KMAX, RB>(a, P, C, tile, v, lds, red);
+            compute_tile<R, NV, KMAX, RB>(a, P, C, tile, v, u, lds, red);
             store_tile<R, NV, NR>(a, C, base, v);
         }
     } else {
         T va[1][NR], vb[1][NR];
         int64_t ta = first;
         int64_t basea = base_of(ta);
+        TileRefs<R> ua = refs_of(ta);
         load_tile<R, 1, NR>(a, C, basea, va);
         for (;;) {
             const int64_t tb = ta + stride;
-            const int64_t baseb = base_of(tb < ntiles ? tb : ta);
+            const int64_t tbc = tb < ntiles ? tb : ta;
+            const int64_t baseb = base_of(tbc);
+            const TileRefs<R> ub = refs_of(tbc);
             load_tile<R, 1, NR>(a, C, baseb, vb);
-            compute_tile<R, 1, KMAX, RB>(a, P, C, ta, va, lds, red);
+            compute_tile<R, 1, KMAX, RB>(a, P, C, ta, va, ua, lds, red);
             store_tile<R, 1, NR>(a, C, basea, va);
             if (tb >= ntiles) break;
             const int64_t tc = tb + stride;
-            const int64_t basec = base_of(tc < ntiles ? tc : tb);
+            const int64_t tcc = tc < ntiles ? tc : tb;
+            const int64_t basec = base_of(tcc);
+            ua = refs_of(tcc);
             load_tile<R, 1, NR>(a, C, basec, va);
-            compute_tile<R, 1, KMAX, RB>(a, P, C, tb, vb, lds, red);
+            compute_tile<R, 1, KMAX, RB>(a, P, C, tb, vb, ub, lds, red);
             store_tile<R, 1, NR>(a, C, baseb, vb);
             if (tc >= ntiles) break;
             ta = tc;
@@ -765,13 +797,23 @@ __device__ __forceinline__ void run_tiles(const KArgs& a, const PK_CONST Pass* P
     }
 }
 
+template <typename R, int NV, int KMAX, int RB>
+__device__ __forceinline__ void run_tiles(const KArgs& a, const PK_CONST Pass* P, int64_t first,
+                                          int64_t stride, int64_t ntiles, typename Cplx<R>::T* lds, double* red) {
+    if (first >= ntiles) return;
+    if (P->nuref > 0)
+        run_tiles_ph<R, NV, KMAX, RB, true>(a, P, first, stride, ntiles, lds, red);
+    else
+        run_tiles_ph<R, NV, KMAX, RB, false>(a, P, first, stride, ntiles, lds, red);
+}
+
 // ---------------------------------------------------------------------------- kernels
 
 template <typename R, int NV, int KMAX, int RB>
 __global__ void __launch_bounds__(1 << (KMAX - RB)) pass_kernel(KArgs a) {
     using T = typename Cplx<R>::T;
     __shared__ T lds[1 << KMAX];
-    __shared__ double red[16 + 2 * kMaxUPairs];  // reduction scratch, then the tile-uniform phase products
+    __shared__ double red[16];  // reduction scratch
     const PK_CONST Pass* P = cptr(a.passes) + a.pass;
     run_tiles<R, NV, KMAX, RB>(a, P, blockIdx.x, gridDim.x, P->ntiles, lds, red);
 }
@@ -875,7 +917,7 @@ __global__ void __launch_bounds__(1 << (KMAX - RB)) batched_kernel(KArgs a, Batc
     using T = typename Cplx<R>::T;
     constexpr int NT = 1 << (KMAX - RB);
     __shared__ T lds[1 << KMAX];
-    __shared__ double red[16 + 2 * kMaxUPairs];  // reduction scratch, then the tile-uniform phase products
+    __shared__ double red[16];  // reduction scratch
     __shared__ int item;
     __shared__ int flag;
     const PK_CONST InstDesc* idesc = cptr(b.idesc);
@@ -935,7 +977,7 @@ template <typename R, int KMAX, int RB>
 __global__ void __launch_bounds__(1 << (KMAX - RB)) repeat_kernel(KArgs a, RepeatArgs r) {
     using T = typename Cplx<R>::T;
     __shared__ T lds[1 << KMAX];
-    __shared__ double red[16 + 2 * kMaxUPairs];
+    __shared__ double red[16];
     __shared__ int flag;
     unsigned int target = 0;
     bool broken = false;

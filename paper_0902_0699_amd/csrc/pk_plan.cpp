@@ -194,35 +194,134 @@ Stage blank_sub(const HostStage& hs, int exchange) {
         s.phase_pm[u] = -1;
         s.phase_cnt[u] = 0;
         s.phase_ucnt[u] = 0;
-        s.phase_upair[u] = -1;
+        s.phase_tt[u] = s.phase_ut0[u] = s.phase_ut1[u] = -1;
+        s.phase_ttm[u] = 0;
     }
     return s;
 }
 
-// Finishes a sub-stage: its phases stored grouped by slot, the tile-uniform ones
-// (no condition on the thread's label bits) first in each slot, and counted; the
-// uniform groups get entries in the pass's table of tile-uniform products (at most
-// kMaxUPairs per pass, the rest stay per thread); then the mask of the steps.
-void finish_sub(Stage& s, std::vector<PhaseOp>* table, std::vector<UPair>* upairs, size_t pass_upairs) {
+// Entries of the product table of `ops` over the label bits `mask`: entry ix is
+// the product of the factors of the phases whose condition bits are all set in
+// the pattern that deposits ix's bits at mask's positions.
+template <typename Cond>
+void tabulate(const std::vector<PhaseOp>& ops, uint64_t mask, Cond cond, std::vector<double>* twid) {
+    int pos[64], m = 0;
+    for (int b = 0; b < 64; ++b)
+        if (mask >> b & 1) pos[m++] = b;
+    for (uint64_t ix = 0; ix < (1ull << m); ++ix) {
+        uint64_t pat = 0;
+        for (int k = 0; k < m; ++k)
+            if (ix >> k & 1) pat |= 1ull << pos[k];
+        double c = 1.0, sn = 0.0;
+        for (const PhaseOp& o : ops) {
+            const uint64_t need = cond(o);
+            if ((pat & need) != need) continue;
+            const double fc = 1.0 + o.cm1, x = c;
+            c = x * fc - sn * o.s;
+            sn = x * o.s + sn * fc;
+        }
+        twid->push_back(c);
+        twid->push_back(sn);
+    }
+}
+
+// Finishes a sub-stage: its phases stored grouped by slot; in each slot the phases
+// that go into product tables first (phase_ucnt), then the rest; then the mask of
+// the steps.  The tile part of a slot (phases with no condition on the thread's
+// label bits) is split into groups of phases tied by a shared tile-index bit, and
+// the groups are packed, largest first, into at most two tables of at most
+// kTwidBits index bits, each one of the pass's URefs while the pass has fewer
+// than kMaxURefs; the thread part (no condition on the tile index) takes one
+// table when its label bits fit.  A phase with no condition at all joins the
+// tile part.  Phases of groups that fit no table stay in the kernel's loop.
+void finish_sub(Stage& s, std::vector<PhaseOp>* table, std::vector<double>* twid, std::vector<URef>* urefs,
+                size_t pass_urefs) {
     if (s.phase_count > 0) {
         auto b = table->begin() + s.phase_first, e = b + s.phase_count;
-        std::stable_sort(b, e, [](const PhaseOp& x, const PhaseOp& y) {
-            const int kx = 2 * x.slot + (x.tmask != 0), ky = 2 * y.slot + (y.tmask != 0);
-            return kx < ky;
-        });
-        for (auto it = b; it != e; ++it) {
-            ++s.phase_cnt[it->slot];
-            if (it->tmask == 0) ++s.phase_ucnt[it->slot];
-        }
+        std::stable_sort(b, e, [](const PhaseOp& x, const PhaseOp& y) { return x.slot < y.slot; });
+        for (auto it = b; it != e; ++it) ++s.phase_cnt[it->slot];
         int32_t first = s.phase_first;
         for (int u = 0; u < kPhaseSlots; ++u) {
-            if (s.phase_ucnt[u] > 0 && upairs->size() - pass_upairs < (size_t)kMaxUPairs) {
-                s.phase_upair[u] = (int32_t)(upairs->size() - pass_upairs);
-                upairs->push_back({first, s.phase_ucnt[u]});
-            } else {
-                s.phase_ucnt[u] = 0;  // handled per thread
+            const int cnt = s.phase_cnt[u];
+            std::vector<PhaseOp> ops(table->begin() + first, table->begin() + first + cnt);
+            // class of each phase: 0 / 1 the first / second tile table, 2 the thread
+            // table, 3 the loop
+            std::vector<int> cls(cnt, 3);
+            // tile part: groups of phases joined by shared tile-index bits
+            std::vector<int> tile_ix;
+            for (int q = 0; q < cnt; ++q)
+                if (ops[q].tmask == 0) tile_ix.push_back(q);
+            std::vector<uint64_t> gmask;     // tile-index bits of each group
+            std::vector<std::vector<int>> gmem;
+            for (int q : tile_ix) {
+                uint64_t m = (uint64_t)ops[q].fmask;
+                std::vector<int> mem{q};
+                for (size_t g = 0; g < gmask.size();) {
+                    if (gmask[g] & m) {
+                        m |= gmask[g];
+                        mem.insert(mem.end(), gmem[g].begin(), gmem[g].end());
+                        gmask.erase(gmask.begin() + g);
+                        gmem.erase(gmem.begin() + g);
+                    } else {
+                        ++g;
+                    }
+                }
+                gmask.push_back(m);
+                gmem.push_back(mem);
             }
-            first += s.phase_cnt[u];
+            std::vector<size_t> gorder(gmask.size());
+            for (size_t g = 0; g < gorder.size(); ++g) gorder[g] = g;
+            std::stable_sort(gorder.begin(), gorder.end(), [&](size_t x, size_t y) {
+                return __builtin_popcountll(gmask[x]) > __builtin_popcountll(gmask[y]);
+            });
+            uint64_t umask[2] = {0, 0};
+            bool used[2] = {false, false};
+            const size_t room = (size_t)kMaxURefs - (urefs->size() - pass_urefs);
+            for (size_t g : gorder) {
+                for (int t = 0; t < 2 && (size_t)t < room; ++t) {
+                    if (__builtin_popcountll(umask[t] | gmask[g]) > kTwidBits) continue;
+                    umask[t] |= gmask[g];
+                    used[t] = true;
+                    for (int q : gmem[g]) cls[q] = t;
+                    break;
+                }
+            }
+            // thread part
+            uint32_t tmask = 0;
+            int nthr = 0;
+            for (int q = 0; q < cnt; ++q)
+                if (ops[q].fmask == 0 && ops[q].tmask != 0) {
+                    tmask |= ops[q].tmask;
+                    ++nthr;
+                }
+            if (nthr > 0 && __builtin_popcount(tmask) <= kTwidBits)
+                for (int q = 0; q < cnt; ++q)
+                    if (ops[q].fmask == 0 && ops[q].tmask != 0) cls[q] = 2;
+            for (int t = 0; t < 2; ++t) {
+                if (!used[t]) continue;
+                std::vector<PhaseOp> part;
+                for (int q = 0; q < cnt; ++q)
+                    if (cls[q] == t) part.push_back(ops[q]);
+                (t == 0 ? s.phase_ut0 : s.phase_ut1)[u] = (int32_t)(urefs->size() - pass_urefs);
+                urefs->push_back({(int32_t)(twid->size() / 2), 0, (int64_t)umask[t]});
+                tabulate(part, umask[t], [](const PhaseOp& o) { return (uint64_t)o.fmask; }, twid);
+            }
+            if (nthr > 0 && __builtin_popcount(tmask) <= kTwidBits) {
+                std::vector<PhaseOp> part;
+                for (int q = 0; q < cnt; ++q)
+                    if (cls[q] == 2) part.push_back(ops[q]);
+                s.phase_tt[u] = (int32_t)(twid->size() / 2);
+                s.phase_ttm[u] = tmask;
+                tabulate(part, tmask, [](const PhaseOp& o) { return (uint64_t)o.tmask; }, twid);
+            }
+            // tabulated phases first (any order), then the loop's
+            int w = first;
+            for (int pass = 0; pass < 2; ++pass)
+                for (int q = 0; q < cnt; ++q)
+                    if ((cls[q] < 3) == (pass == 0)) (*table)[w++] = ops[q];
+            s.phase_ucnt[u] = 0;
+            for (int q = 0; q < cnt; ++q) s.phase_ucnt[u] += cls[q] < 3;
+            first += cnt;
         }
     }
     s.steps = (s.exchange ? ST_EXCHANGE : 0) | (s.seed >= 0 ? ST_SEED : 0) | (s.flip_pre >= 0 ? ST_FLIP_PRE : 0) |
@@ -309,7 +408,7 @@ int place(Stage& s, int cursor, const Op& o) {
 }
 
 std::vector<Stage> pack_stage(const HostStage& hs, const std::vector<HostPhase>& phases, std::vector<PhaseOp>* table,
-                              std::vector<UPair>* upairs, size_t pass_upairs) {
+                              std::vector<double>* twid, std::vector<URef>* urefs, size_t pass_urefs) {
     std::vector<Stage> subs;
     Stage cur = blank_sub(hs, 1);
     int cursor = 0;
@@ -319,7 +418,7 @@ std::vector<Stage> pack_stage(const HostStage& hs, const std::vector<HostPhase>&
     for (const Op& o : hs.ops) {
         int slot = put(o);
         if (slot < 0) {
-            finish_sub(cur, table, upairs, pass_upairs);
+            finish_sub(cur, table, twid, urefs, pass_urefs);
             subs.push_back(cur);
             cur = blank_sub(hs, 0);
             cursor = 0;
@@ -327,7 +426,7 @@ std::vector<Stage> pack_stage(const HostStage& hs, const std::vector<HostPhase>&
         }
         cursor = slot;
     }
-    finish_sub(cur, table, upairs, pass_upairs);
+    finish_sub(cur, table, twid, urefs, pass_urefs);
     subs.push_back(cur);
     return subs;
 }
@@ -900,12 +999,13 @@ struct Compiler {
                     fin.ops.push_back(o);
                 }
             }
-            hp.upair_begin = (int)plan->upairs.size();
+            hp.uref_begin = (int)plan->urefs.size();
             for (const HostStage& hs : hp.stages) {
-                std::vector<Stage> sub = pack_stage(hs, hp.phases, &plan->phases, &plan->upairs, hp.upair_begin);
+                std::vector<Stage> sub =
+                    pack_stage(hs, hp.phases, &plan->phases, &plan->twid, &plan->urefs, (size_t)hp.uref_begin);
                 hp.subs.insert(hp.subs.end(), sub.begin(), sub.end());
             }
-            hp.nupair = (int)plan->upairs.size() - hp.upair_begin;
+            hp.nuref = (int)plan->urefs.size() - hp.uref_begin;
             out->push_back(hp);
             ++pass_no;
         } while (left > 0);
@@ -1166,7 +1266,8 @@ int recompile(Plan* plan, std::string* err) {
     plan->stages.clear();
     plan->flips.clear();
     plan->phases.clear();
-    plan->upairs.clear();
+    plan->twid.assign({1.0, 0.0});
+    plan->urefs.clear();
     plan->idesc.clear();
     plan->order.clear();
     plan->d2_grad.clear();
@@ -1223,8 +1324,8 @@ int recompile(Plan* plan, std::string* err) {
         p.flags = hp.flags;
         p.scale = hp.scale;
         p.part_base = hp.part_base;
-        p.upair_begin = hp.upair_begin;
-        p.nupair = hp.nupair;
+        p.uref_begin = hp.uref_begin;
+        p.nuref = hp.nuref;
         p.kmax = hp.kmax;
         p.rbits = hp.rbits;
         for (int l = 0; l < 16; ++l) {
@@ -1343,8 +1444,10 @@ TableLayout table_layout(const Plan* plan) {
     o = align256(o + plan->flips.size() * sizeof(Flip));
     t.phases = o;
     o = align256(o + plan->phases.size() * sizeof(PhaseOp));
-    t.upairs = o;
-    o = align256(o + plan->upairs.size() * sizeof(UPair));
+    t.twid = o;
+    o = align256(o + plan->twid.size() * sizeof(double));
+    t.urefs = o;
+    o = align256(o + plan->urefs.size() * sizeof(URef));
     t.mats = o;  // static matrices followed by the default angles
     o = align256(o + (plan->static_mats.size() + plan->default_angles.size()) * sizeof(double));
     t.mats4 = o;  // static two-qubit matrices
@@ -1440,6 +1543,13 @@ std::string describe(const Plan* plan) {
                 if (p) s += ",";
                 s += "{\"k\":" + std::to_string(hp.k) + ",\"rbits\":" + std::to_string(hp.rbits) +
                      ",\"flags\":" + std::to_string(hp.flags);
+                s += ",\"urefs\":[";
+                for (int r = 0; r < hp.nuref; ++r) {
+                    const URef& ur = plan->urefs[hp.uref_begin + r];
+                    if (r) s += ",";
+                    s += "[" + std::to_string(ur.base) + "," + std::to_string((long long)ur.mask) + "]";
+                }
+                s += "]";
                 char buf[64];
                 std::snprintf(buf, sizeof buf, "%.17g", hp.scale);
                 s += ",\"scale\":";
@@ -1497,6 +1607,14 @@ std::string describe(const Plan* plan) {
                          "," + std::to_string(u.phase_cnt[2]) + "," + std::to_string(u.phase_cnt[3]) + "]" +
                          ",\"phase_ucnt\":[" + std::to_string(u.phase_ucnt[0]) + "," + std::to_string(u.phase_ucnt[1]) +
                          "," + std::to_string(u.phase_ucnt[2]) + "," + std::to_string(u.phase_ucnt[3]) + "]" +
+                         ",\"phase_tt\":[" + std::to_string(u.phase_tt[0]) + "," + std::to_string(u.phase_tt[1]) +
+                         "," + std::to_string(u.phase_tt[2]) + "," + std::to_string(u.phase_tt[3]) + "]" +
+                         ",\"phase_ttm\":[" + std::to_string(u.phase_ttm[0]) + "," + std::to_string(u.phase_ttm[1]) +
+                         "," + std::to_string(u.phase_ttm[2]) + "," + std::to_string(u.phase_ttm[3]) + "]" +
+                         ",\"phase_ut0\":[" + std::to_string(u.phase_ut0[0]) + "," + std::to_string(u.phase_ut0[1]) +
+                         "," + std::to_string(u.phase_ut0[2]) + "," + std::to_string(u.phase_ut0[3]) + "]" +
+                         ",\"phase_ut1\":[" + std::to_string(u.phase_ut1[0]) + "," + std::to_string(u.phase_ut1[1]) +
+                         "," + std::to_string(u.phase_ut1[2]) + "," + std::to_string(u.phase_ut1[3]) + "]" +
                          ",\"mat_pre_a\":" +
                          std::to_string(u.mat_pre_a) + ",\"mat_pre\":" + std::to_string(u.mat_pre) +
                          ",\"hmask1\":" + std::to_string(u.hmask1) + ",\"flip_mid\":" +
@@ -1525,7 +1643,21 @@ std::string describe(const Plan* plan) {
                       (long long)ph.fmask, ph.cm1, ph.s);
         s += buf;
     }
-    s += "],\"flips\":[";
+    // the product tables only while they are small (the emulated sizes): at full
+    // size they run to megabytes
+    s += "],\"twid_entries\":" + std::to_string(plan->twid.size() / 2) + ",\"twid\":";
+    if (plan->twid.size() <= (size_t)1 << 17) {
+        s += "[";
+        for (size_t q = 0; q < plan->twid.size(); ++q) {
+            char buf[40];
+            std::snprintf(buf, sizeof buf, "%s%.17g", q ? "," : "", plan->twid[q]);
+            s += buf;
+        }
+        s += "]";
+    } else {
+        s += "null";
+    }
+    s += ",\"flips\":[";
     for (size_t f = 0; f < plan->flips.size(); ++f) {
         const Flip& fl = plan->flips[f];
         if (f) s += ",";

@@ -50,8 +50,8 @@ struct HostPass {
     int part_base = 0;
     int kmax = 13;
     int rbits = 4;
-    int upair_begin = 0;  // tile-uniform phase products of the pass (Plan::upairs)
-    int nupair = 0;
+    int uref_begin = 0;  // tile-part tables of the pass (Plan::urefs)
+    int nuref = 0;
 };
 
 struct Instance {
@@ -133,7 +133,9 @@ struct Plan {
     std::vector<double> default_angles; // 3 per D2 or D4 gate, in order
     std::vector<ParamRef> params;      // what each angle triple drives
     std::vector<PhaseOp> phases;       // controlled phases as scheduled (device table)
-    std::vector<UPair> upairs;         // tile-uniform phase products of every pass (device table)
+    std::vector<double> twid;          // product tables of the controlled phases (re, im pairs);
+                                       // entry 0 is 1 (what lanes without a table load)
+    std::vector<URef> urefs;           // tile-part tables of every pass
     int n_d2 = 0;
     int n_d4 = 0;
     int n_static = 0;
@@ -172,7 +174,7 @@ std::string describe(const Plan* plan);
 
 // Byte offsets of the device table arrays inside plan->d_tables.
 struct TableLayout {
-    size_t passes, stages, flips, phases, upairs, mats, mats4, params, idesc, order, team_off, team_list, red, total;
+    size_t passes, stages, flips, phases, twid, urefs, mats, mats4, params, idesc, order, team_off, team_list, red, total;
 };
 TableLayout table_layout(const Plan* plan);
 

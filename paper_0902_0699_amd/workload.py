@@ -97,6 +97,23 @@ def grover_gates(noise=None):
     return steps[:eloc] + [("D2", int(qhit), float(alpha), float(beta), float(gamma))] + steps[eloc:]
 
 
+def phase_circuit(rng, nq, count):
+    """Hadamards on every qubit, then ``count`` controlled phases (CPHASE, or
+    CPHASEK with k in 1..5) on random distinct qubit pairs, each followed by a
+    Hadamard on a random qubit with probability 0.1: a circuit whose stages carry
+    many controlled phases over tile-index, thread and register bits at once."""
+    gates = [("H", q) for q in range(1, nq + 1)]
+    for _ in range(count):
+        a, b = rng.choice(np.arange(1, nq + 1), 2, replace=False)
+        if rng.random() < 0.5:
+            gates.append(("CPHASE", int(a), int(b)))
+        else:
+            gates.append(("CPHASEK", int(a), int(b), int(rng.integers(1, 6))))
+        if rng.random() < 0.1:
+            gates.append(("H", int(rng.integers(1, nq + 1))))
+    return gates
+
+
 def draw_instance(rng, nq, noisy=True, with_state=True):
     """One noisy Grover instance: dict(nq, marked, noise, gates, psi)."""
     size = 1 << nq

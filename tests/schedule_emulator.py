@@ -146,30 +146,68 @@ def _tile_index(nq, tb, g):
     return t
 
 
-def _run_phases(desc, nq, tb, u, vecs):
-    """The sub-stage's controlled phases as the kernel applies them: conditions on
-    the tile index (fmask), the thread's label bits (tmask) and the slot's register
-    bits, with the local label decoded through the read map."""
+def _extract(x, mask):
+    """Bits of x at mask's set positions, packed from the least significant."""
+    out = np.zeros_like(x)
+    k = 0
+    for b in range(64):
+        if mask >> b & 1:
+            out |= ((x >> b) & 1) << k
+            k += 1
+    return out
+
+
+def _run_phases(desc, nq, tb, p, u, vecs):
+    """The sub-stage's controlled phases as the kernel applies them: per slot, the
+    leading phase_ucnt phases through the product tables (two of the pass's tile-part
+    tables, indexed by tile-index bits, and one indexed by the thread's label bits),
+    the rest one factor each with their
+    conditions on the tile index (fmask) and the thread's label bits (tmask); the
+    product applies where the slot's register bits are set, the local label
+    decoded through the read map."""
     g = np.arange(1 << nq, dtype=np.int64)
     j = _local_label(nq, tb, g)
     tile = _tile_index(nq, tb, g)
     rb = u["rb"]
+    twid = desc["twid"]
+    assert twid is not None, "product tables are described for small plans only"
+    tw = np.array(twid[0::2]) + 1j * np.array(twid[1::2])
+    assert tw[0] == 1  # what lanes without a table load
     # stored grouped by slot, with the counts the kernel loops over
     slots = [desc["phases"][q][0] for q in range(u["phase_first"], u["phase_first"] + u["phase_count"])]
     assert slots == sorted(slots) and [slots.count(k) for k in range(4)] == u["phase_cnt"]
-    for q in range(u["phase_first"], u["phase_first"] + u["phase_count"]):
-        slot, tmask, fmask, cm1, s = desc["phases"][q]
-        c = 1.0 + cm1  # stored as c - 1
+    q = u["phase_first"]
+    for slot in range(4):
+        cnt = u["phase_cnt"][slot]
+        if cnt == 0:
+            continue
         pm = u["phase_pm"][slot]
         assert pm >= 0
-        lmask = tmask
+        rmask = 0
         for a in range(5):
             if pm >> a & 1:
-                assert rb[a] >= 0 and not (tmask >> rb[a] & 1)
-                lmask |= 1 << rb[a]
-        hit = ((tile & fmask) == fmask) & ((j & lmask) == lmask)
+                assert rb[a] >= 0
+                rmask |= 1 << rb[a]
+        fac = np.ones(1 << nq, dtype=complex)
+        assert len(p["urefs"]) <= 64
+        for r in (u["phase_ut0"][slot], u["phase_ut1"][slot]):
+            if r >= 0:
+                first, mask = p["urefs"][r]
+                assert bin(mask).count("1") <= 10
+                fac *= tw[first + _extract(tile, mask)]
+        if u["phase_tt"][slot] >= 0:
+            mask = u["phase_ttm"][slot]
+            assert bin(mask).count("1") <= 10 and not mask & rmask
+            fac *= tw[u["phase_tt"][slot] + _extract(j, mask)]
+        for r in range(q + u["phase_ucnt"][slot], q + cnt):
+            _, tmask, fmask, cm1, s = desc["phases"][r]
+            assert not tmask & rmask
+            hit = ((tile & fmask) == fmask) & ((j & tmask) == tmask)
+            fac[hit] *= complex(1.0 + cm1, s)  # stored as c - 1
+        q += cnt
+        sel = (j & rmask) == rmask
         for v in vecs:
-            v[hit] *= complex(c, s)
+            v[sel] *= fac[sel]
 
 
 _STEP_BITS = [("exchange", lambda v: v == 1), ("seed", lambda v: v >= 0), ("flip_pre", lambda v: v >= 0),
@@ -212,7 +250,7 @@ def _run_subs(problems, desc, inst, direction, psi, lam=None, dL=1.0):
                 for v in vecs:
                     v[g] *= -1
             if u["phase_count"] > 0:
-                _run_phases(desc, nq, tb, u, vecs)
+                _run_phases(desc, nq, tb, p, u, vecs)
             if u["mat_pre_a"] >= 0:
                 for v in vecs:
                     _apply_bit(v, nq, tb[rb[u["mat_pre_a"]]], mat(u["mat_pre"]))

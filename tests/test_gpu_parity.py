@@ -196,6 +196,33 @@ def test_random_gate_lists_fp64():
         assert abs(L - Lw) <= TOL64 * max(1.0, abs(Lw))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("seed,nq,tiling", [(4, 16, (5, 0, 1)), (5, 16, (5, 0, 1)), (6, 16, None), (7, 3, None),
+                                           (8, 7, None)])
+def test_phase_product_tables_against_oracle(prec, seed, nq, tiling):
+    """Circuits dense in controlled phases: every path of the phase step (tile-part
+    tables read from the lanes, the thread-part table, the per-phase loop, the
+    last in the backward passes), forward and, in FP64, backward.  At n_q = 3 and
+    7 most threads of the workgroup hold no amplitude."""
+    pk = _pk()
+    rng = np.random.default_rng(seed)
+    gates = W.phase_circuit(rng, nq, 120 if nq > 8 else 30)
+    prob = {"nq": nq, "gates": gates, "marked": [int(rng.integers(0, 1 << nq))]}
+    psi = _state(rng, nq)
+    _say("phase tables seed %d n_q=%d %s %s" % (seed, nq, prec, tiling))
+    plan, got, L, _ = _run(prob, psi, prec=prec, tiling=tiling)
+    want, Lw, _ = O.evaluate(nq, gates, prob["marked"], psi)
+    tol = TOL64 if prec == "fp64" else TOL32
+    assert _relerr(got, want) <= tol and abs(L - Lw) <= tol
+    if prec == "fp64":
+        out, _, _ = pk.evaluate(plan, _dev(psi))
+        dL = torch.tensor([0.75], dtype=torch.float64, device="cuda")
+        gpsi, _ = pk.backward(plan, out, dL)
+        torch.cuda.synchronize()
+        wpsi, _ = O.adjoint_grad(nq, gates, prob["marked"], psi, 0.75)
+        assert _relerr(gpsi.cpu().numpy(), wpsi) <= 1e-10
+
+
 def test_graph_replay_is_stable():
     """Repeated calls on the same buffers replay one captured graph; every replay
     matches the first, with eager torch work in between."""

@@ -494,6 +494,46 @@ def test_backward_through_phases_and_relabelled_swaps(nq, tiling):
     np.testing.assert_allclose(gang, wang, rtol=0, atol=1e-12)
 
 
+def _table_use(desc):
+    """Slots (forward and backward passes) using the first / second tile-part
+    table, the thread-part table, and the phases left to the kernel's loop."""
+    c = {"ut0": 0, "ut1": 0, "tt": 0, "loop": 0}
+    for inst in desc["instances"]:
+        for p in inst["forward"] + inst["backward"]:
+            for u in p["subs"]:
+                for k in range(4):
+                    if u["phase_cnt"][k]:
+                        c["ut0"] += u["phase_ut0"][k] >= 0
+                        c["ut1"] += u["phase_ut1"][k] >= 0
+                        c["tt"] += u["phase_tt"][k] >= 0
+                        c["loop"] += u["phase_cnt"][k] - u["phase_ucnt"][k]
+    return c
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_phase_product_tables_match_oracle(seed):
+    """Circuits dense in controlled phases at 16 qubits in 2^5 tiles (11 tile-index
+    bits): their slots use the second tile-part table, the thread-part table and
+    (in the backward passes, where a phase can miss every register bit) the
+    kernel's loop; the emulated schedules still equal the oracle both ways."""
+    rng = np.random.default_rng(seed)
+    nq = 16
+    gates = W.phase_circuit(rng, nq, 120)
+    prob = {"nq": nq, "gates": gates, "marked": [int(rng.integers(0, 1 << nq))]}
+    psi = _state(rng, nq)
+    plan, desc = _check_forward(prob, psi, (5, 0, 1))
+    use = _table_use(desc)
+    assert use["ut0"] > 0 and use["tt"] > 0
+    if seed == 4:
+        assert use["ut1"] > 0
+    else:
+        assert use["loop"] > 0
+    psi_out, _, _ = O.evaluate(nq, gates, prob["marked"], psi)
+    gpsi, _ = run_backward([prob], desc, 0, psi_out, 0.5)
+    wpsi, _ = O.adjoint_grad(nq, gates, prob["marked"], psi, 0.5)
+    np.testing.assert_allclose(gpsi, wpsi, rtol=0, atol=1e-12)
+
+
 def test_qft_of_register_one_at_thirty_qubits_takes_four_passes():
     for prec in ("fp64", "fp32"):
         desc = pk.Plan({"nq": 30, "gates": [("QFT", 1, 20)], "marked": []}, prec=prec).describe()

@@ -499,11 +499,34 @@ __device__ __forceinline__ PassCtx make_ctx(const KArgs& a, const PK_CONST Pass*
     return C;
 }
 
+// Nontemporal (streaming) 16- or 8-byte accesses of one complex amplitude.
+template <typename T>
+__device__ __forceinline__ void store_stream(T* p, const T& v) {
+    using R = decltype(v.x);
+    typedef R V __attribute__((ext_vector_type(2)));
+    V w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, reinterpret_cast<V*>(p));
+}
+
+template <typename T>
+__device__ __forceinline__ T load_stream(const T* p) {
+    using R = decltype(p->x);
+    typedef R V __attribute__((ext_vector_type(2)));
+    const V w = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+    T r;
+    r.x = w.x;
+    r.y = w.y;
+    return r;
+}
+
 // HBM -> registers in the first stage's layout.  `base` is the tile's first
 // state label.  The uniform part (tile base + register offset) and the thread's
 // part stay apart, so each load is a 64-bit scalar base plus a 32-bit lane
-// offset; a wide pass (lane offsets beyond 32 bits) adds in 64 bits.
-template <typename R, int NV, int NR>
+// offset; a wide pass (lane offsets beyond 32 bits) adds in 64 bits.  NT: the
+// one-vector loads are nontemporal.
+template <typename R, int NV, int NR, bool NT = false>
 __device__ __forceinline__ void load_tile(const KArgs& a, const PassCtx& C, int64_t base,
                                           typename Cplx<R>::T (&v)[NV][NR]) {
     using T = typename Cplx<R>::T;
@@ -523,7 +546,10 @@ __device__ __forceinline__ void load_tile(const KArgs& a, const PassCtx& C, int6
         for (int i = 0; i < NR; ++i) {
             if (i >= C.nreg) continue;
             const int64_t u = (base + goff(C.G0, i)) * (int64_t)sizeof(T);
-            v[0][i] = *reinterpret_cast<const T*>(in0 + u + lane);
+            if constexpr (NT)
+                v[0][i] = load_stream(reinterpret_cast<const T*>(in0 + u + lane));
+            else
+                v[0][i] = *reinterpret_cast<const T*>(in0 + u + lane);
             if constexpr (NV == 2)
                 if (read1) v[1][i] = *reinterpret_cast<const T*>(in1 + u + lane);
         }
@@ -539,8 +565,8 @@ __device__ __forceinline__ void load_tile(const KArgs& a, const PassCtx& C, int6
     }
 }
 
-// Registers -> HBM in the last stage's layout.
-template <typename R, int NV, int NR>
+// Registers -> HBM in the last stage's layout (NT: nontemporal one-vector stores).
+template <typename R, int NV, int NR, bool NT = false>
 __device__ __forceinline__ void store_tile(const KArgs& a, const PassCtx& C, int64_t base,
                                            const typename Cplx<R>::T (&v)[NV][NR]) {
     using T = typename Cplx<R>::T;
@@ -554,7 +580,11 @@ __device__ __forceinline__ void store_tile(const KArgs& a, const PassCtx& C, int
         for (int i = 0; i < NR; ++i) {
             if (i >= C.nreg) continue;
             const int64_t u = (base + goff(C.Gl, i)) * (int64_t)sizeof(T);
-            if (write0) *reinterpret_cast<T*>(out0 + u + lane) = v[0][i];
+            if constexpr (NT) {
+                if (write0) store_stream(reinterpret_cast<T*>(out0 + u + lane), v[0][i]);
+            } else {
+                if (write0) *reinterpret_cast<T*>(out0 + u + lane) = v[0][i];
+            }
             if constexpr (NV == 2) *reinterpret_cast<T*>(out1 + u + lane) = v[1][i];
         }
     } else {
@@ -747,8 +777,8 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
 // workgroup an LDS-sized tile leaves per CU.  The prefetch is unconditional
 // (past the end it re-reads the current tile) so the wait counts stay static.
 // PH: the pass has tile-part product tables, whose entries are loaded with the
-// tile's amplitudes.
-template <typename R, int NV, int KMAX, int RB, bool PH>
+// tile's amplitudes.  NT: the pass streams (PASS_STREAM).
+template <typename R, int NV, int KMAX, int RB, bool PH, bool NT>
 __device__ __forceinline__ void run_tiles_ph(const KArgs& a, const PK_CONST Pass* P, int64_t first,
                                              int64_t stride, int64_t ntiles, typename Cplx<R>::T* lds, double* red) {
     using T = typename Cplx<R>::T;
@@ -764,32 +794,32 @@ __device__ __forceinline__ void run_tiles_ph(const KArgs& a, const PK_CONST Pass
             T v[NV][NR];
             const int64_t base = base_of(tile);
             const TileRefs<R> u = refs_of(tile);
-            load_tile<R, NV, NR>(a, C, base, v);
+            load_tile<R, NV, NR, NT>(a, C, base, v);
             compute_tile<R, NV, KMAX, RB>(a, P, C, tile, v, u, lds, red);
-            store_tile<R, NV, NR>(a, C, base, v);
+            store_tile<R, NV, NR, NT>(a, C, base, v);
         }
     } else {
         T va[1][NR], vb[1][NR];
         int64_t ta = first;
         int64_t basea = base_of(ta);
         TileRefs<R> ua = refs_of(ta);
-        load_tile<R, 1, NR>(a, C, basea, va);
+        load_tile<R, 1, NR, NT>(a, C, basea, va);
         for (;;) {
             const int64_t tb = ta + stride;
             const int64_t tbc = tb < ntiles ? tb : ta;
             const int64_t baseb = base_of(tbc);
             const TileRefs<R> ub = refs_of(tbc);
-            load_tile<R, 1, NR>(a, C, baseb, vb);
+            load_tile<R, 1, NR, NT>(a, C, baseb, vb);
             compute_tile<R, 1, KMAX, RB>(a, P, C, ta, va, ua, lds, red);
-            store_tile<R, 1, NR>(a, C, basea, va);
+            store_tile<R, 1, NR, NT>(a, C, basea, va);
             if (tb >= ntiles) break;
             const int64_t tc = tb + stride;
             const int64_t tcc = tc < ntiles ? tc : tb;
             const int64_t basec = base_of(tcc);
             ua = refs_of(tcc);
-            load_tile<R, 1, NR>(a, C, basec, va);
+            load_tile<R, 1, NR, NT>(a, C, basec, va);
             compute_tile<R, 1, KMAX, RB>(a, P, C, tb, vb, ub, lds, red);
-            store_tile<R, 1, NR>(a, C, baseb, vb);
+            store_tile<R, 1, NR, NT>(a, C, baseb, vb);
             if (tc >= ntiles) break;
             ta = tc;
             basea = basec;
@@ -797,14 +827,23 @@ __device__ __forceinline__ void run_tiles_ph(const KArgs& a, const PK_CONST Pass
     }
 }
 
-template <typename R, int NV, int KMAX, int RB>
+// STREAM: honour PASS_STREAM (single-instance launches; a batched launch's
+// instances are small).
+template <typename R, int NV, int KMAX, int RB, bool STREAM = false>
 __device__ __forceinline__ void run_tiles(const KArgs& a, const PK_CONST Pass* P, int64_t first,
                                           int64_t stride, int64_t ntiles, typename Cplx<R>::T* lds, double* red) {
     if (first >= ntiles) return;
-    if (P->nuref > 0)
-        run_tiles_ph<R, NV, KMAX, RB, true>(a, P, first, stride, ntiles, lds, red);
-    else
-        run_tiles_ph<R, NV, KMAX, RB, false>(a, P, first, stride, ntiles, lds, red);
+    if (P->nuref > 0) {
+        run_tiles_ph<R, NV, KMAX, RB, true, false>(a, P, first, stride, ntiles, lds, red);
+        return;
+    }
+    if constexpr (STREAM && NV == 1) {
+        if (P->flags & PASS_STREAM) {
+            run_tiles_ph<R, NV, KMAX, RB, false, true>(a, P, first, stride, ntiles, lds, red);
+            return;
+        }
+    }
+    run_tiles_ph<R, NV, KMAX, RB, false, false>(a, P, first, stride, ntiles, lds, red);
 }
 
 // ---------------------------------------------------------------------------- kernels
@@ -815,7 +854,7 @@ __global__ void __launch_bounds__(1 << (KMAX - RB)) pass_kernel(KArgs a) {
     __shared__ T lds[1 << KMAX];
     __shared__ double red[16];  // reduction scratch
     const PK_CONST Pass* P = cptr(a.passes) + a.pass;
-    run_tiles<R, NV, KMAX, RB>(a, P, blockIdx.x, gridDim.x, P->ntiles, lds, red);
+    run_tiles<R, NV, KMAX, RB, true>(a, P, blockIdx.x, gridDim.x, P->ntiles, lds, red);
 }
 
 // Team barrier of the batched launch: every member adds one to the team's

@@ -534,6 +534,18 @@ def test_phase_product_tables_match_oracle(seed):
     np.testing.assert_allclose(gpsi, wpsi, rtol=0, atol=1e-12)
 
 
+def test_only_the_last_pass_of_a_large_fp64_state_streams():
+    """PASS_STREAM (64) marks the last forward pass of an FP64 instance of at least
+    1 GiB (n_q >= 26): never another pass, a backward pass, FP32 or a smaller state."""
+    gates = W.grover_gates((3, 2, 0.4, 0.2, 0.1))
+    for nq, prec, want in ((30, "fp64", True), (26, "fp64", True), (25, "fp64", False), (30, "fp32", False)):
+        d = pk.Plan({"nq": nq, "gates": gates, "marked": [5]}, prec=prec).describe()["instances"][0]
+        flags = [p["flags"] for p in d["forward"]]
+        assert [bool(f & 64) for f in flags] == [want and i == len(flags) - 1 for i in range(len(flags))]
+        assert bool(flags[-1] & 2)
+        assert not any(p["flags"] & 64 for p in d["backward"])
+
+
 def test_qft_of_register_one_at_thirty_qubits_takes_four_passes():
     for prec in ("fp64", "fp32"):
         desc = pk.Plan({"nq": 30, "gates": [("QFT", 1, 20)], "marked": []}, prec=prec).describe()

@@ -169,15 +169,17 @@ enum PassFlags : int32_t {
     PASS_SEED_V1 = 16, // vector 1 is not read: it starts as zero and is seeded (backward start)
     PASS_WIDE = 32,    // a thread's byte offset inside a tile may exceed 32 bits
     PASS_STREAM = 64,  // loads and stores are nontemporal (streaming): the last forward pass of
-                       // an FP64 instance far larger than the memory-side cache
+                       // an FP64 instance far larger than the memory-side cache, when it
+                       // writes the tile back in the layout it read
 };
 
 // State size from which an FP64 instance's last forward pass streams
 // (PASS_STREAM).  Measured at n_q = 30 (16 GiB): the last pass of the Grover
 // iteration went from 6.7 to 5.9 ms (the iteration from 35.1 to 34.4 ms);
 // streaming the other passes made two of them slower, and in FP32 (8-byte
-// accesses) the last pass too.  Small states are left alone: their next launch
-// re-reads them from the caches.
+// accesses) the last pass too, as did the last pass of the QFT, which writes the
+// tile back in another layout (relabelled SWAPs; 8.05 -> 8.37 ms).  Small states
+// are left alone: their next launch re-reads them from the caches.
 constexpr int64_t kStreamBytes = (int64_t)1 << 30;
 
 constexpr int kMaxRuns = 16;

@@ -1375,7 +1375,8 @@ int recompile(Plan* plan, std::string* err) {
     for (size_t i = 0; i < plan->inst.size(); ++i)
         for (auto& hp : plan->inst[i].fwd) {
             const int64_t bytes = ((int64_t)1 << plan->inst[i].nq) * (plan->prec == PK_FP64 ? 16 : 8);
-            if (plan->prec == PK_FP64 && (hp.flags & PASS_LAST) && bytes >= kStreamBytes) hp.flags |= PASS_STREAM;
+            if (plan->prec == PK_FP64 && (hp.flags & PASS_LAST) && bytes >= kStreamBytes && hp.sbits == hp.tbits)
+                hp.flags |= PASS_STREAM;
             emit(plan->inst[i], (int)i, hp);
         }
     plan->n_fwd_passes = (int)plan->passes.size();

@@ -536,7 +536,8 @@ def test_phase_product_tables_match_oracle(seed):
 
 def test_only_the_last_pass_of_a_large_fp64_state_streams():
     """PASS_STREAM (64) marks the last forward pass of an FP64 instance of at least
-    1 GiB (n_q >= 26): never another pass, a backward pass, FP32 or a smaller state."""
+    1 GiB (n_q >= 26) that stores in the layout it read: never another pass, a
+    backward pass, FP32, a smaller state or a relabelling last pass."""
     gates = W.grover_gates((3, 2, 0.4, 0.2, 0.1))
     for nq, prec, want in ((30, "fp64", True), (26, "fp64", True), (25, "fp64", False), (30, "fp32", False)):
         d = pk.Plan({"nq": nq, "gates": gates, "marked": [5]}, prec=prec).describe()["instances"][0]
@@ -544,6 +545,10 @@ def test_only_the_last_pass_of_a_large_fp64_state_streams():
         assert [bool(f & 64) for f in flags] == [want and i == len(flags) - 1 for i in range(len(flags))]
         assert bool(flags[-1] & 2)
         assert not any(p["flags"] & 64 for p in d["backward"])
+    # a last pass that writes the tile back relabelled (the QFT's SWAPs) does not stream
+    d = pk.Plan({"nq": 30, "gates": [("QFT", 1, 20)], "marked": []}).describe()["instances"][0]
+    assert d["forward"][-1]["tile_bits"] != d["forward"][-1]["store_bits"]
+    assert not any(p["flags"] & 64 for p in d["forward"])
 
 
 def test_qft_of_register_one_at_thirty_qubits_takes_four_passes():

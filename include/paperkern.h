@@ -146,11 +146,13 @@ int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_
 /*
  * pk_set_launch -- launch shape of the pass kernels: wgs_per_cu resident
  * workgroups per CU (1..8, or 0 for as many as the kernel's resources allow,
- * the default; more than fit only queue up), and reg_bits = 4 or 5 register
- * bits per thread in forward passes (16 or 32 amplitudes per thread, a
- * workgroup of 2^(tile_bits - reg_bits) threads; 0 selects the default: 4 for
- * FP64, 5 for FP32).  Backward passes always use 4.  Changing reg_bits
- * re-compiles the schedule.  Drops captured graphs.  PK_EINVAL when out of range.
+ * the default; more than fit only queue up), and reg_bits = 3, 4 or 5 register
+ * bits per thread in forward passes (8, 16 or 32 amplitudes per thread, a
+ * workgroup of 2^(tile_bits - reg_bits) threads, at most 1024; 0 selects the
+ * default: 4 for FP64, 5 for FP32).  With 3, a stage holds one two-qubit pair
+ * and pk_evaluate_batched returns PK_EUNSUPPORTED.  Backward passes always use
+ * 4.  Changing reg_bits re-compiles the schedule.  Drops captured graphs.
+ * PK_EINVAL when out of range.
  */
 int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu, int32_t reg_bits);
 

@@ -37,15 +37,20 @@ FIELDS = ("tile_bits", "carrier_bits", "lane_order", "reg_bits", "wgs_per_cu", "
 
 def candidates(prec, op):
     """Candidate settings for one precision (pk.PK_FP64 / pk.PK_FP32) and operation
-    ("eval" or "batched")."""
+    ("eval" or "batched").  Single-instance evaluations also try 3 register bits
+    (more threads a tile: 4 resident waves per SIMD at 2^13 FP64 tiles) and 3
+    carriers (fewer passes where the circuit needs many tile bits, as the QFT does);
+    the batched launch has 4 and 5 register bits only."""
     kmax = 13 if prec == pk.PK_FP64 else 14
     tiles = [kmax, kmax - 1, kmax - 2]
     if op == "batched":
         tiles.append(kmax - 3)
     teams = ((16, 64), (16, 8)) if op == "batched" else ((16, 64),)
+    carriers = (4, 5) if op == "batched" else (3, 4, 5)
+    regs = (4, 5) if op == "batched" else (3, 4, 5)
     out = []
-    for k, c, rb, (ts, mt) in itertools.product(tiles, (4, 5), (4, 5), teams):
-        if k - rb < 6:
+    for k, c, rb, (ts, mt) in itertools.product(tiles, carriers, regs, teams):
+        if k - rb < 6 or k - rb > 10:
             continue
         out.append({"tile_bits": k, "carrier_bits": c, "lane_order": 1, "reg_bits": rb, "wgs_per_cu": 0,
                     "team_size": ts, "min_team_tiles": mt})
@@ -53,6 +58,9 @@ def candidates(prec, op):
 
 
 def apply(plan, cfg):
+    # 4 register bits while the tile changes keep the workgroup within 1024 threads
+    # whatever the previous and the next setting are
+    plan.set_launch(cfg["wgs_per_cu"], 4)
     plan.set_tiling(cfg["tile_bits"], cfg["carrier_bits"], 1, cfg["lane_order"], cfg.get("page_cap", -1))
     plan.set_launch(cfg["wgs_per_cu"], cfg["reg_bits"])
     plan.set_batch(cfg.get("team_size", 16), cfg.get("min_team_tiles", 64))

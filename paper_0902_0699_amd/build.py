@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpaperkern.so")
 # the pass and batched kernel instances come first: they take longest to compile
 SOURCES = ["pk_batched_f32.hip", "pk_batched_f64.hip", "pk_repeat_f32.hip", "pk_repeat_f64.hip", "pk_pass_f32.hip", "pk_pass_f64.hip", "pk_pass_f32r5.hip",
-           "pk_pass_f64r5.hip", "pk_pass_f32bwd.hip", "pk_pass_f64bwd.hip", "pk_kernels.hip", "pk_shor.hip",
+           "pk_pass_f64r5.hip", "pk_pass_f32r3.hip", "pk_pass_f64r3.hip", "pk_pass_f32bwd.hip", "pk_pass_f64bwd.hip", "pk_kernels.hip", "pk_shor.hip",
            "pk_density.hip", "pk_search.hip", "pk_api.cpp", "pk_plan.cpp"]
 # rocSOLVER (and the rocBLAS handle it runs on) gives the density matrix's eigenvalues
 LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]

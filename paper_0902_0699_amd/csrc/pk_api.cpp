@@ -253,6 +253,7 @@ bool repeat_persistent() {
 unsigned repeat_grid(DevPlan* d) {
     const Instance& in = d->host.inst[0];
     const int kmax = in.fwd[0].kmax, rbits = in.fwd[0].rbits;
+    if (rbits == 3) return 0;  // the persistent kernel has 4 and 5 register bits
     int64_t tiles = 0;
     for (const auto& hp : in.fwd) {
         if (hp.kmax != kmax || hp.rbits != rbits) return 0;
@@ -499,6 +500,8 @@ int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_
     if (fuse != 0 && fuse != 1) return fail(d, PK_EINVAL, "fuse must be 0 or 1");
     if (lane_order != 0 && lane_order != 1) return fail(d, PK_EINVAL, "lane_order must be 0 or 1");
     if (page_cap < -1 || page_cap > 16) return fail(d, PK_EINVAL, "page_cap must be -1..16");
+    if (tile_bits - d->host.tiling.reg_bits > 10)
+        return fail(d, PK_EINVAL, "tile_bits - reg_bits must be at most 10 (1024 threads a workgroup)");
     const Tiling previous = d->host.tiling;
     d->host.tiling = Tiling{tile_bits, carrier_bits, fuse, d->host.tiling.wgs_per_cu, d->host.tiling.reg_bits,
                             lane_order, page_cap < 0 ? default_page_cap(d->host.prec) : page_cap};
@@ -510,8 +513,10 @@ int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu, int32_t reg_bits) {
     if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");
     DevPlan* d = dp(plan);
     if (wgs_per_cu < 0 || wgs_per_cu > 8) return fail(d, PK_EINVAL, "wgs_per_cu must be 0..8");
-    if (reg_bits != 0 && reg_bits != 4 && reg_bits != 5) return fail(d, PK_EINVAL, "reg_bits must be 0, 4 or 5");
+    if (reg_bits != 0 && (reg_bits < 3 || reg_bits > 5)) return fail(d, PK_EINVAL, "reg_bits must be 0, 3, 4 or 5");
     const int rb = reg_bits == 0 ? default_reg_bits(d->host.prec) : reg_bits;
+    if (d->host.tiling.tile_bits - rb > 10)
+        return fail(d, PK_EINVAL, "tile_bits - reg_bits must be at most 10 (1024 threads a workgroup)");
     const bool recompile_needed = rb != d->host.tiling.reg_bits;
     const Tiling previous = d->host.tiling;
     d->host.tiling.wgs_per_cu = wgs_per_cu;
@@ -684,6 +689,8 @@ int pk_evaluate_batched(pk_plan* plan, const void* psi_in, void* psi_out, double
                         const double* angles, void* workspace, void* stream) {
     if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");
     DevPlan* d = dp(plan);
+    if (d->host.tiling.reg_bits == 3)
+        return fail(d, PK_EUNSUPPORTED, "the batched launch has 4 or 5 register bits (pk_set_launch)");
     int rc = check_eval_args(d, psi_in, psi_out, L_out, norm_out, angles, workspace);
     if (rc != PK_OK) return rc;
     rc = ensure_device(d);

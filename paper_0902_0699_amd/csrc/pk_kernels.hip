@@ -167,6 +167,9 @@ hipError_t launch_pass(const PassLaunch& L, hipStream_t st) {
     if (L.rbits == 5)
         return L.fp64 ? launch_pass_r<double, 1, 5>(L.kmax, a, L.ntiles, L.grid_cap, st)
                       : launch_pass_r<float, 1, 5>(L.kmax, a, L.ntiles, L.grid_cap, st);
+    if (L.rbits == 3)
+        return L.fp64 ? launch_pass_r<double, 1, 3>(L.kmax, a, L.ntiles, L.grid_cap, st)
+                      : launch_pass_r<float, 1, 3>(L.kmax, a, L.ntiles, L.grid_cap, st);
     return L.fp64 ? launch_pass_r<double, 1, 4>(L.kmax, a, L.ntiles, L.grid_cap, st)
                   : launch_pass_r<float, 1, 4>(L.kmax, a, L.ntiles, L.grid_cap, st);
 }

@@ -444,7 +444,8 @@ __device__ __forceinline__ void apply_hmask(T (&v)[NV][NR], int mask) {
     if (mask & 1) op_h<0, NV, NR>(v);
     if (mask & 2) op_h<1, NV, NR>(v);
     if (mask & 4) op_h<2, NV, NR>(v);
-    if (mask & 8) op_h<3, NV, NR>(v);
+    if constexpr (NR > 8)
+        if (mask & 8) op_h<3, NV, NR>(v);
     if constexpr (NR > 16)
         if (mask & 16) op_h<4, NV, NR>(v);
 }
@@ -454,7 +455,8 @@ __device__ __forceinline__ void apply_mat(T (&v)[NV][NR], int a, const R (&m)[8]
     if (a == 0) op_m<0, NV, NR>(v, m);
     if (a == 1) op_m<1, NV, NR>(v, m);
     if (a == 2) op_m<2, NV, NR>(v, m);
-    if (a == 3) op_m<3, NV, NR>(v, m);
+    if constexpr (NR > 8)
+        if (a == 3) op_m<3, NV, NR>(v, m);
     if constexpr (NR > 16)
         if (a == 4) op_m<4, NV, NR>(v, m);
 }
@@ -465,7 +467,8 @@ __device__ __forceinline__ void apply_d2bwd(T (&v)[NV][NR], int a, const R (&mh)
     if (a == 0) op_d2bwd<0, NV, NR>(v, mh, dmats, g);
     if (a == 1) op_d2bwd<1, NV, NR>(v, mh, dmats, g);
     if (a == 2) op_d2bwd<2, NV, NR>(v, mh, dmats, g);
-    if (a == 3) op_d2bwd<3, NV, NR>(v, mh, dmats, g);
+    if constexpr (NR > 8)
+        if (a == 3) op_d2bwd<3, NV, NR>(v, mh, dmats, g);
     if constexpr (NR > 16)
         if (a == 4) op_d2bwd<4, NV, NR>(v, mh, dmats, g);
 }
@@ -702,7 +705,8 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
             apply_mat<NV, NR>(v, mat_post_a, m);
         }
         if ((steps & ST_MAT4) && active) op_mat4<NV, NR>(v, cptr(a.mats4) + 32 * S->mat4);
-        if ((steps & ST_MAT4B) && active) op_mat4_hi<NV, NR>(v, cptr(a.mats4) + 32 * S->mat4b);
+        if constexpr (NR > 8)
+            if ((steps & ST_MAT4B) && active) op_mat4_hi<NV, NR>(v, cptr(a.mats4) + 32 * S->mat4b);
         if constexpr (NV == 2) {
             if (steps & ST_D2B) {
                 R mh[8];
@@ -1065,7 +1069,17 @@ static hipError_t launch_pass_t(const KArgs& a, int64_t ntiles, int64_t wgs_per_
 // Kernel instances: one vector with 4 or 5 register bits, two vectors with 4.
 template <typename R, int NV, int RB>
 hipError_t launch_pass_r(int kmax, const KArgs& a, int64_t ntiles, int64_t cap, hipStream_t st) {
-    if constexpr (RB == 4) {
+    if constexpr (RB == 3) {
+        // 2^(KMAX - 3) threads: at most 1024, so at most 2^13-amplitude tiles
+        switch (kmax) {
+        case 9: return launch_pass_t<R, NV, 9, 3>(a, ntiles, cap, st);
+        case 10: return launch_pass_t<R, NV, 10, 3>(a, ntiles, cap, st);
+        case 11: return launch_pass_t<R, NV, 11, 3>(a, ntiles, cap, st);
+        case 12: return launch_pass_t<R, NV, 12, 3>(a, ntiles, cap, st);
+        case 13: return launch_pass_t<R, NV, 13, 3>(a, ntiles, cap, st);
+        default: return hipErrorInvalidValue;
+        }
+    } else if constexpr (RB == 4) {
         switch (kmax) {
         case 10: return launch_pass_t<R, NV, 10, 4>(a, ntiles, cap, st);
         case 11: return launch_pass_t<R, NV, 11, 4>(a, ntiles, cap, st);

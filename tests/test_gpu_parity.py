@@ -122,7 +122,8 @@ def test_ragged_sizes_fp64(nq, eloc):
 @pytest.mark.parametrize("tiling,launch", [((4, 0, 1), None), ((6, 2, 1), None), ((10, 4, 1), None),
                                            ((11, 4, 1), (2, 4)), ((12, 4, 1), None), ((13, 6, 1), None),
                                            ((10, 4, 0), None), ((13, 4, 0), None), ((13, 4, 1), (0, 5)),
-                                           ((12, 4, 1), (0, 5)), ((7, 2, 1), (0, 5)), ((11, 3, 1), (1, 5))])
+                                           ((12, 4, 1), (0, 5)), ((7, 2, 1), (0, 5)), ((11, 3, 1), (1, 5)),
+                                           ((13, 4, 1), (0, 3)), ((12, 3, 1), (0, 3)), ((9, 2, 1), (0, 3))])
 def test_tilings_fp64(tiling, launch):
     nq = 15
     rng = np.random.default_rng(sum(tiling))
@@ -508,7 +509,8 @@ def _gates2(rng, nq, count, unitary=True):
                                                    (10, (6, 2, 1), None, "fp64"), (14, None, None, "fp64"),
                                                    (14, (13, 4, 1), (0, 5), "fp64"), (12, (5, 0, 0), None, "fp64"),
                                                    (15, (10, 4, 1), (2, 4), "fp64"), (14, None, None, "fp32"),
-                                                   (9, (6, 2, 1), (0, 4), "fp32")])
+                                                   (9, (6, 2, 1), (0, 4), "fp32"), (14, (13, 4, 1), (0, 3), "fp64"),
+                                                   (13, (12, 3, 1), (0, 3), "fp32")])
 def test_two_qubit_gates_against_oracle(nq, tiling, launch, prec):
     rng = np.random.default_rng(500 + nq + (tiling[0] if tiling else 0))
     gates = _gates2(rng, nq, 24, unitary=(nq % 2 == 0)) + [("CNOT", 1, nq), ("D4", nq, 1, 0.3, 1.9, -0.6)]

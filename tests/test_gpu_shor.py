@@ -68,6 +68,7 @@ def _eval(problem, psi, prec="fp64", tiling=None, launch=None):
     (16, 3, 10, (8, 3, 1), None, "fp64"), (14, 1, 14, (6, 1, 1), None, "fp64"), (18, 2, 11, None, (0, 5), "fp64"),
     (13, 1, 9, (5, 0, 1), None, "fp64"), (12, 1, 10, (6, 2, 0), None, "fp64"), (20, 1, 14, None, None, "fp64"),
     (16, 1, 12, None, None, "fp32"), (18, 4, 9, (9, 4, 1), (0, 4), "fp32"), (20, 1, 14, None, None, "fp32"),
+    (18, 1, 14, (13, 3, 1), (0, 3), "fp64"), (16, 2, 12, (12, 4, 1), (0, 3), "fp32"),
 ])
 def test_qft_against_dft(nq, first, n, tiling, launch, prec):
     rng = np.random.default_rng(nq * 100 + first * 10 + n)

@@ -148,6 +148,13 @@ def test_autotune_candidates_are_accepted_and_signature_is_structural():
         for c in cands:
             AT.apply(plan, c)  # host-side recompile; raises if a candidate were invalid
         assert plan.passes() >= 1
+        assert all(c["reg_bits"] in (4, 5) for c in cands)
+        single = pk.Plan(probs[:1], prec=prec)
+        ev = AT.candidates(single.prec, "eval")
+        assert {c["reg_bits"] for c in ev} == {3, 4, 5} and {c["carrier_bits"] for c in ev} == {3, 4, 5}
+        for c in ev:
+            AT.apply(single, c)
+            assert c["tile_bits"] - c["reg_bits"] <= 10
     # same structure, other angles and marks: same key; other qubit: other key
     a = [{"nq": 12, "gates": W.grover_gates((3, 2, 0.1, 0.2, 0.0)), "marked": [5]}]
     b = [{"nq": 12, "gates": W.grover_gates((3, 2, 1.1, 2.2, 0.0)), "marked": [77]}]
@@ -166,6 +173,26 @@ def test_autotune_candidates_are_accepted_and_signature_is_structural():
     assert len(set(keys)) == len(keys)
     assert sig(one(("D4", 1, 2, 0.1, 0.2, 0.3))) == sig(one(("D4", 1, 2, 1.1, 1.2, 1.3)))
     assert sig(one(("TWOOP", 1, 2, np.eye(4)))) == sig(one(("TWOOP", 1, 2, 2 * np.eye(4))))
+
+
+def test_three_register_bits_limits():
+    """reg_bits 3: at most 1024 threads a workgroup (tile_bits - reg_bits <= 10), and
+    the batched launch, which has 4 and 5 register bits only, refuses the plan
+    before it touches the device."""
+    import ctypes
+    prob = {"nq": 16, "gates": W.grover_gates((3, 2, 0.4, 0.2, 0.1)), "marked": [5]}
+    p32 = pk.Plan(prob, prec="fp32")
+    p32.set_tiling(14, 4, 1)
+    with pytest.raises(pk.PaperkernError, match="1024 threads"):
+        p32.set_launch(0, 3)
+    p32.set_tiling(13, 4, 1)
+    p32.set_launch(0, 3)
+    with pytest.raises(pk.PaperkernError, match="1024 threads"):
+        p32.set_tiling(14, 4, 1)
+    assert pk.lib().pk_evaluate_batched(p32.handle, None, None, None, None, None, None, None) == pk.PK_EUNSUPPORTED
+    d = p32.describe()
+    assert {p["rbits"] for p in d["instances"][0]["forward"]} == {3}
+    assert all(p["rbits"] == 4 for p in d["instances"][0]["backward"])
 
 
 def test_binding_step_one_register_sizes_and_search_length():
@@ -233,7 +260,7 @@ def _check_forward(problem, psi, tiling=None, prec="fp64", reg_bits=4):
 
 @pytest.mark.parametrize("nq", [1, 2, 3, 4, 5, 8, 13, 14, 16])
 @pytest.mark.parametrize("eloc", [0, 2, 4])
-@pytest.mark.parametrize("reg_bits", [4, 5])
+@pytest.mark.parametrize("reg_bits", [3, 4, 5])
 def test_grover_schedule_matches_oracle(nq, eloc, reg_bits):
     rng = np.random.default_rng(nq * 10 + eloc)
     qhit = int(rng.integers(1, nq + 1))
@@ -454,7 +481,7 @@ def test_scale_is_exact_power_of_two_for_even_hadamard_count():
 @pytest.mark.parametrize("nq,first,n,tiling,reg_bits", [
     (6, 1, 6, None, 4), (9, 1, 6, None, 5), (10, 3, 5, (5, 2, 1), 4), (12, 1, 8, (6, 2, 1), 4),
     (13, 2, 9, (7, 3, 1), 5), (11, 1, 11, (6, 1, 1), 4), (12, 4, 7, (5, 0, 1), 4), (9, 1, 9, (6, 2, 0), 4),
-    (14, 1, 10, None, 4),
+    (14, 1, 10, None, 4), (14, 1, 12, (9, 3, 1), 3), (12, 2, 8, None, 3),
 ])
 def test_qft_schedule_matches_dft(nq, first, n, tiling, reg_bits):
     rng = np.random.default_rng(nq * 31 + first * 7 + n)

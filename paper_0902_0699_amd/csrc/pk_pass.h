@@ -852,8 +852,11 @@ __device__ __forceinline__ void run_tiles(const KArgs& a, const PK_CONST Pass* P
 
 // ---------------------------------------------------------------------------- kernels
 
+// With 3 register bits the kernel is held to 128 VGPRs (four waves per SIMD): two
+// 2^12-tile workgroups of 512 threads then share a CU, as their LDS allows.
 template <typename R, int NV, int KMAX, int RB>
-__global__ void __launch_bounds__(1 << (KMAX - RB)) pass_kernel(KArgs a) {
+__global__ void __launch_bounds__(1 << (KMAX - RB)) __attribute__((amdgpu_waves_per_eu(RB == 3 ? 4 : 1)))
+pass_kernel(KArgs a) {
     using T = typename Cplx<R>::T;
     __shared__ T lds[1 << KMAX];
     __shared__ double red[16];  // reduction scratch

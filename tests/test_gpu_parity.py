@@ -224,6 +224,28 @@ def test_phase_product_tables_against_oracle(prec, seed, nq, tiling):
         assert _relerr(gpsi.cpu().numpy(), wpsi) <= 1e-10
 
 
+def test_phase_tables_at_the_per_pass_limit_against_oracle():
+    """Passes that list the 64 tile-part tables a pass may hold (one per lane of a
+    wave), with the phases past the limit in the per-phase loop: forward and
+    backward against the oracle."""
+    pk = _pk()
+    rng = np.random.default_rng(2)
+    nq = 14
+    gates = W.phase_circuit(rng, nq, 500)
+    prob = {"nq": nq, "gates": gates, "marked": [int(rng.integers(0, 1 << nq))]}
+    psi = _state(rng, nq)
+    _say("phase tables at the per-pass limit, n_q=%d" % nq)
+    plan, got, L, _ = _run(prob, psi, tiling=(8, 2, 1))
+    assert max(len(p["urefs"]) for p in plan.describe()["instances"][0]["forward"]) == 64
+    want, Lw, _ = O.evaluate(nq, gates, prob["marked"], psi)
+    assert _relerr(got, want) <= TOL64 and abs(L - Lw) <= TOL64
+    out, _, _ = pk.evaluate(plan, _dev(psi))
+    gpsi, _ = pk.backward(plan, out, torch.tensor([0.75], dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    wpsi, _ = O.adjoint_grad(nq, gates, prob["marked"], psi, 0.75)
+    assert _relerr(gpsi.cpu().numpy(), wpsi) <= 1e-10
+
+
 def test_graph_replay_is_stable():
     """Repeated calls on the same buffers replay one captured graph; every replay
     matches the first, with eager torch work in between."""

@@ -561,6 +561,25 @@ def test_phase_product_tables_match_oracle(seed):
     np.testing.assert_allclose(gpsi, wpsi, rtol=0, atol=1e-12)
 
 
+def test_phase_tables_at_the_per_pass_limit():
+    """500 controlled phases at 14 qubits in 2^8 tiles: passes reach the 64 tile-part
+    tables a pass may list (one per lane); the slots past the limit keep their
+    phases in the kernel's loop, and the emulated schedules still equal the oracle."""
+    rng = np.random.default_rng(2)
+    nq = 14
+    gates = W.phase_circuit(rng, nq, 500)
+    prob = {"nq": nq, "gates": gates, "marked": [int(rng.integers(0, 1 << nq))]}
+    psi = _state(rng, nq)
+    plan, desc = _check_forward(prob, psi, (8, 2, 1))
+    passes = desc["instances"][0]["forward"] + desc["instances"][0]["backward"]
+    assert max(len(p["urefs"]) for p in passes) == 64
+    assert _table_use(desc)["loop"] > 0
+    psi_out, _, _ = O.evaluate(nq, gates, prob["marked"], psi)
+    gpsi, _ = run_backward([prob], desc, 0, psi_out, 0.5)
+    wpsi, _ = O.adjoint_grad(nq, gates, prob["marked"], psi, 0.5)
+    np.testing.assert_allclose(gpsi, wpsi, rtol=0, atol=1e-12)
+
+
 def test_only_the_last_pass_of_a_large_fp64_state_streams():
     """PASS_STREAM (64) marks the last forward pass of an FP64 instance of at least
     1 GiB (n_q >= 26) that stores in the layout it read: never another pass, a

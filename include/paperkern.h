@@ -248,9 +248,12 @@ int pk_evaluate_static(pk_plan* plan, const void* psi_in, void* psi_out, double*
  * pk_evaluate_repeat -- apply the gate list of a single-instance plan `reps`
  * times in a row: psi_out = U^reps psi_in.  With the list of one Grover
  * iteration G = HALL . Inv . HALL . Oracle this is the whole search of Sec. 5.1,
- * G^{n_t} with n_t = floor((pi/4) sqrt(2^nq)) iterations.  The whole sequence of
- * passes (about 2 to 5 per iteration), one launch each, is captured into one
- * hipGraph, keyed by the pointers and reps, and replayed.  With the environment
+ * G^{n_t} with n_t = floor((pi/4) sqrt(2^nq)) iterations.  For a plan without
+ * angle parameters, 8 consecutive applications are scheduled as one gate list,
+ * so that a pass can end one application and begin the next (a Grover iteration
+ * at n_q = 20 takes 3 passes alone, 8 take 17); reps mod 8 applications run
+ * alone, first.  The whole sequence of passes, one launch each, is captured into
+ * one hipGraph, keyed by the pointers and reps, and replayed.  With the environment
  * variable PK_REPEAT_PERSISTENT=1 (and reps > 1, every pass on one kernel
  * instance) the passes run instead in one persistent launch of as many
  * workgroups as the GPU holds at once, with a grid-wide barrier between passes;
@@ -263,6 +266,14 @@ int pk_evaluate_static(pk_plan* plan, const void* psi_in, void* psi_out, double*
  */
 int pk_evaluate_repeat(pk_plan* plan, int64_t reps, const void* psi_in, void* psi_out, double* L_out,
                        double* norm_out, const double* angles, void* workspace, void* stream);
+
+/*
+ * pk_repeat_launches -- the number of pass launches pk_evaluate_repeat(plan,
+ * reps, ...) runs in its graph form (after the fusing described there).
+ * Host-side only (the fused schedule is compiled, not uploaded).  Single-instance
+ * plans; reps 1..2^24.  PK_EINVAL otherwise.
+ */
+int pk_repeat_launches(pk_plan* plan, int64_t reps, int64_t* launches);
 
 /*
  * pk_search_diffusion -- a labelled variant of the noise-free search, not the

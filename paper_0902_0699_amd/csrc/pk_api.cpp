@@ -31,7 +31,13 @@ struct DevPlan {
     int n_cu = 0;
     unsigned batch_grid = 0;  // persistent grid of the batched launch
     uint64_t spin_ticks = 0;  // half a second of the device wall clock
+    DevPlan* fused = nullptr; // pk_evaluate_repeat: kRepeatFuse applications as one schedule
 };
+
+// pk_evaluate_repeat schedules this many consecutive applications of the gate list
+// as one gate list: a pass can then finish one application and start the next
+// (at n_q = 20 a Grover iteration takes 3 passes alone, 8 take 17).
+constexpr int64_t kRepeatFuse = 8;
 
 // MI355X has 8 XCDs and dispatches workgroups round-robin over them; the count
 // only shapes the batched teams (which workgroups share an L2), not results.
@@ -63,11 +69,20 @@ bool valid(const pk_plan* p) { return p && dp(p)->host.magic == 0x504b504cu; }
 
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
+void drop_device(DevPlan* d);
+
+// Captured graphs, and the fused repeat schedule (it copies the plan's settings).
 void drop_graphs(DevPlan* d) {
     for (int s = 0; s < G_SLOTS; ++s) {
         if (d->exec[s]) hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(d->exec[s]));
         d->exec[s] = nullptr;
         std::memset(d->key[s], 0, sizeof d->key[s]);
+    }
+    if (d->fused) {
+        drop_device(d->fused);
+        if (d->fused->cap) hipStreamDestroy(d->fused->cap);
+        delete d->fused;
+        d->fused = nullptr;
     }
 }
 
@@ -238,6 +253,101 @@ hipError_t enqueue_eval(DevPlan* d, const EvalArgs& a, hipStream_t st, std::vect
     TableLayout t = table_layout(&P);
     return launch_reduce(at<Reduction>(P.d_tables, t.red), 2 * (int)P.inst.size(), static_cast<double*>(a.ws),
                          a.L_out, a.norm_out, nullptr, st);
+}
+
+// The gate list applied kRepeatFuse times, compiled as one plan with the same
+// settings, or nullptr where that does not apply: a plan with angle parameters
+// (each application would need its own), or one whose fused schedule would not use
+// the same workspace layout.  Built on first use and kept until the plan's
+// settings change.
+DevPlan* fused_plan(DevPlan* d) {
+    if (d->fused) return d->fused;
+    const Plan& P = d->host;
+    if (P.inst.size() != 1 || !P.params.empty()) return nullptr;
+    DevPlan* f = new (std::nothrow) DevPlan();
+    if (!f) return nullptr;
+    f->host = P;
+    f->host.d_tables = nullptr;
+    f->host.d_tables_bytes = 0;
+    f->host.device = -1;
+    std::vector<Prim>& prims = f->host.inst[0].prims;
+    const std::vector<Prim> one = prims;
+    for (int64_t r = 1; r < kRepeatFuse; ++r) prims.insert(prims.end(), one.begin(), one.end());
+    std::string err;
+    int rc;
+    try {
+        rc = recompile(&f->host, &err);
+    } catch (...) {
+        rc = PK_EINVAL;
+    }
+    bool same = false;
+    if (rc == PK_OK) {
+        const WsLayout wa = workspace_layout(&P, PK_OP_EVAL), wb = workspace_layout(&f->host, PK_OP_EVAL);
+        same = wa.mats == wb.mats && wa.mats4 == wb.mats4 && wa.partials == wb.partials && wa.reads == wb.reads &&
+               wa.counters == wb.counters && wa.total == wb.total && f->host.n_partials == P.n_partials &&
+               f->host.n_reads == P.n_reads;
+    }
+    if (!same || f->host.inst[0].fwd.size() >= (size_t)kRepeatFuse * P.inst[0].fwd.size()) {
+        delete f;
+        return nullptr;
+    }
+    d->fused = f;
+    return f;
+}
+
+// How pk_evaluate_repeat splits reps: `single` applications of the plan, then
+// `rounds` of the fused schedule (none when it does not apply).
+struct RepeatSplit {
+    DevPlan* fused;
+    int64_t single, rounds;
+};
+
+RepeatSplit repeat_split(DevPlan* d, int64_t reps) {
+    DevPlan* f = reps >= kRepeatFuse ? fused_plan(d) : nullptr;
+    if (!f) return {nullptr, reps, 0};
+    return {f, reps % kRepeatFuse, reps / kRepeatFuse};
+}
+
+// The passes of one application of `src`'s forward schedule.
+hipError_t enqueue_passes(DevPlan* src, void* ws, const void* in, void* out, bool want_norm, hipStream_t st) {
+    Plan& P = src->host;
+    PassLaunch L = base_launch(src, ws, PK_OP_EVAL);
+    L.src0 = in;
+    L.dst0 = out;
+    L.nv = 1;
+    L.want_norm = want_norm;
+    const Instance& inst = P.inst[0];
+    for (size_t p = 0; p < inst.fwd.size(); ++p) {
+        L.pass = (int)p;
+        L.kmax = inst.fwd[p].kmax;
+        L.ntiles = inst.fwd[p].ntiles;
+        L.grid_cap = P.tiling.wgs_per_cu;
+        L.rbits = inst.fwd[p].rbits;
+        hipError_t e = launch_pass(L, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// pk_evaluate_repeat with the fused schedule: prep, the single applications, the
+// fused rounds, then the final combine of the last one (same workspace layout).
+hipError_t enqueue_repeat_fused(DevPlan* d, const RepeatSplit& sp, const EvalArgs& a, hipStream_t st) {
+    hipError_t e = enqueue_prep(d, a.ws, a.angles, PK_OP_EVAL, 0, st);
+    if (e != hipSuccess) return e;
+    int64_t done = 0;
+    for (int64_t r = 0; r < sp.single; ++r, ++done) {
+        e = enqueue_passes(d, a.ws, done == 0 ? a.psi_in : a.psi_out, a.psi_out, false, st);
+        if (e != hipSuccess) return e;
+    }
+    for (int64_t r = 0; r < sp.rounds; ++r, ++done) {
+        e = enqueue_passes(sp.fused, a.ws, done == 0 ? a.psi_in : a.psi_out, a.psi_out,
+                           a.norm_out != nullptr && r == sp.rounds - 1, st);
+        if (e != hipSuccess) return e;
+    }
+    Plan& F = sp.fused->host;
+    TableLayout t = table_layout(&F);
+    return launch_reduce(at<Reduction>(F.d_tables, t.red), 2, static_cast<double*>(a.ws), a.L_out, a.norm_out,
+                         nullptr, st);
 }
 
 // The persistent form of pk_evaluate_repeat is opt-in (PK_REPEAT_PERSISTENT=1): on
@@ -652,8 +762,27 @@ int pk_evaluate_repeat(pk_plan* plan, int64_t reps, const void* psi_in, void* ps
     if (grid > 0)
         return run_graphed(d, G_REPEAT, key, static_cast<hipStream_t>(stream),
                            [&](hipStream_t s) { return enqueue_repeat(d, a, s, reps, grid); });
+    const RepeatSplit sp = repeat_split(d, reps);
+    if (sp.fused) {
+        rc = ensure_device(sp.fused);
+        if (rc != PK_OK) return fail(d, rc, sp.fused->host.last_error);
+        return run_graphed(d, G_REPEAT, key, static_cast<hipStream_t>(stream),
+                           [&](hipStream_t s) { return enqueue_repeat_fused(d, sp, a, s); });
+    }
     return run_graphed(d, G_REPEAT, key, static_cast<hipStream_t>(stream),
                        [&](hipStream_t s) { return enqueue_eval(d, a, s, nullptr, reps); });
+}
+
+int pk_repeat_launches(pk_plan* plan, int64_t reps, int64_t* launches) {
+    if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");
+    DevPlan* d = dp(plan);
+    if (!launches) return fail(d, PK_EINVAL, "NULL output");
+    if (d->host.inst.size() != 1) return fail(d, PK_EINVAL, "pk_repeat_launches needs a single-instance plan");
+    if (reps < 1 || reps > ((int64_t)1 << 24)) return fail(d, PK_EINVAL, "reps out of 1..2^24");
+    const RepeatSplit sp = repeat_split(d, reps);
+    *launches = sp.single * (int64_t)d->host.inst[0].fwd.size() +
+                (sp.fused ? sp.rounds * (int64_t)sp.fused->host.inst[0].fwd.size() : 0);
+    return PK_OK;
 }
 
 int pk_search_workspace_bytes(int64_t* bytes) {

@@ -55,6 +55,7 @@ SIGNATURES = {
     "pk_evaluate": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pk_evaluate_batched": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pk_evaluate_repeat": (ctypes.c_int, [_vp, _c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "pk_repeat_launches": (ctypes.c_int, [_vp, _c_int64, ctypes.POINTER(_c_int64)]),
     "pk_evaluate_static": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pk_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pk_pair_indices": (ctypes.c_int, [_c_int32, _c_int32, _c_int64, _c_int64, _vp, _vp, _vp]),
@@ -320,6 +321,13 @@ def evaluate_repeat(plan, psi_in, reps, angles=None, want_norm=True, out=None):
                                   _ptr(angles), _ptr(ws), _stream(dev))
     _check(rc, plan.handle)
     return psi_out, L, norm
+
+
+def repeat_launches(plan, reps):
+    """Pass launches of evaluate_repeat(plan, ..., reps) (pk_repeat_launches)."""
+    n = ctypes.c_int64()
+    _check(lib().pk_repeat_launches(plan.handle, int(reps), ctypes.byref(n)), plan.handle)
+    return n.value
 
 
 def search_diffusion(nq, marked, iterations, psi_in, out=None, workspace=None):

@@ -145,6 +145,43 @@ def test_noisy_iteration_repeated_against_gate_by_gate_oracle():
     assert np.linalg.norm(got - want) <= 1e-12 * reps and abs(L.item() - Lw) <= 1e-12 * reps
 
 
+@pytest.mark.parametrize("nq,reps,tiling,prec", [(14, 11, None, "fp64"), (15, 16, (9, 3, 1), "fp64"),
+                                                  (16, 19, (12, 4, 1), "fp32"), (7, 9, None, "fp64")])
+def test_fused_repeat_against_gate_by_gate_oracle(nq, reps, tiling, prec):
+    """reps >= 8 applications of a list without angle parameters run 8 at a time as
+    one fused schedule (reps mod 8 alone, first): every element against the oracle
+    applying the list reps times; the launch count is the fused one."""
+    pk = _pk()
+    rng = np.random.default_rng(nq + reps)
+    gates = [("H", 1), ("ONEOP", 3, O.PAULI_Y), ("CPHASE", 2, nq), ("HALL",), ("ORACLE",), ("INV",),
+             ("CPHASEK", nq - 1, 1, 3), ("HALL",), ("H", nq)]
+    marked = [int(rng.integers(0, 1 << nq)), 5]
+    psi = rng.standard_normal(1 << nq) + 1j * rng.standard_normal(1 << nq)
+    psi /= np.linalg.norm(psi)
+    plan = pk.Plan({"nq": nq, "gates": gates, "marked": marked}, prec=prec)
+    if tiling:
+        plan.set_tiling(*tiling)
+    launches = pk.repeat_launches(plan, reps)
+    _say("fused repeat x%d n_q=%d %s %s: %d launches (%d unfused)" % (reps, nq, tiling, prec, launches,
+                                                                    reps * plan.passes()))
+    assert launches < reps * plan.passes() or plan.passes() == 1
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    out, L, norm = pk.evaluate_repeat(plan, torch.from_numpy(psi).to(dt).to("cuda"), reps)
+    torch.cuda.synchronize()
+    want = psi
+    for _ in range(reps):
+        want, Lw, nw = O.evaluate(nq, gates, marked, want)
+    tol = (1e-12 if prec == "fp64" else 1e-5) * reps
+    got = out.cpu().numpy().astype(np.complex128)
+    assert np.linalg.norm(got - want) <= tol and abs(L.item() - Lw) <= tol and abs(norm.item() - nw) <= tol
+    # a settings change rebuilds the fused schedule
+    plan.set_tiling(8, 2, 1)
+    out2, L2, _ = pk.evaluate_repeat(plan, torch.from_numpy(psi).to(dt).to("cuda"), reps)
+    torch.cuda.synchronize()
+    got2 = out2.cpu().numpy().astype(np.complex128)
+    assert np.linalg.norm(got2 - want) <= tol and abs(L2.item() - Lw) <= tol
+
+
 def test_repeat_once_equals_evaluate_and_rejects_bad_reps():
     pk = _pk()
     nq = 11

@@ -689,6 +689,25 @@ def test_shor_marginal_density_search_entry_points_reject_bad_arguments():
     _einval(lib.pk_search_diffusion(6, pk.PK_FP64, one, 65, 5, buf, buf, buf, buf, None), "0..64")
 
 
+def test_repeat_launch_counts():
+    """pk_evaluate_repeat fuses 8 applications into one schedule when the plan has
+    no angle parameters: at n_q = 20 a Grover iteration takes 3 passes, 8 take 17,
+    so n_t = 804 iterations take 100 x 17 + 4 x 3 launches; a noisy plan (D2
+    angles) and fewer than 8 applications are not fused."""
+    g20 = pk.Plan({"nq": 20, "gates": W.grover_gates(), "marked": [5]})
+    assert g20.passes() == 3
+    assert pk.repeat_launches(g20, 804) == 100 * 17 + 4 * 3
+    assert pk.repeat_launches(g20, 7) == 21
+    assert pk.repeat_launches(g20, 8) == 17
+    noisy = pk.Plan({"nq": 20, "gates": W.grover_gates((3, 2, 0.1, 0.2, 0.3)), "marked": [5]})
+    assert pk.repeat_launches(noisy, 804) == 804 * noisy.passes()
+    with pytest.raises(pk.PaperkernError):
+        pk.repeat_launches(g20, 0)
+    batch = pk.Plan([{"nq": 10, "gates": W.grover_gates(), "marked": [1]}] * 2)
+    with pytest.raises(pk.PaperkernError):
+        pk.repeat_launches(batch, 10)
+
+
 def test_evaluate_repeat_rejects_bad_reps_before_the_device():
     plan = pk.Plan({"nq": 6, "gates": W.grover_gates(), "marked": [1]})
     buf = ctypes.c_void_p(4096)

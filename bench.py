@@ -71,7 +71,7 @@ def stored_traffic(kernel_name):
     return t.get("bytes_per_launch")
 
 
-def single_run(torch, pk, W, prec, seed, nq, steps, warmup):
+def single_run(torch, pk, W, autotune, prec, seed, nq, steps, warmup):
     """Times `steps` evaluations of one instance; returns a dict of figures."""
     t0 = time.perf_counter()
     inst = W.single_instance(seed, nq)
@@ -83,6 +83,11 @@ def single_run(torch, pk, W, prec, seed, nq, steps, warmup):
     y = torch.empty_like(x)
     L = torch.empty(1, dtype=torch.float64, device="cuda")
     norm = torch.empty(1, dtype=torch.float64, device="cuda")
+    # per pass, the faster of the two tile walks, measured on these buffers
+    walk, walk_ms = autotune.tune_walk(plan, x, y)
+    log("%s: tile walk in blocks for passes %s (strided %s ms, blocks %s ms)"
+        % (prec, [p for p in range(plan.passes()) if walk >> p & 1],
+           [round(v, 2) for v in walk_ms[0]], [round(v, 2) for v in walk_ms[(1 << plan.passes()) - 1]]))
     for _ in range(warmup):
         pk.evaluate_into(plan, x, y, L, norm)
     torch.cuda.synchronize()
@@ -104,7 +109,8 @@ def single_run(torch, pk, W, prec, seed, nq, steps, warmup):
         reps.append(pk.time_passes(plan, x, y))
     per_pass = [float(np.mean([r[p] for r in reps])) for p in range(len(reps[0]))]
     return {"plan": plan, "x": x, "y": y, "L": float(L.item()), "norm": float(norm.item()),
-            "ms": ms, "wall": wall, "per_pass_ms": per_pass, "passes": plan.passes(), "inst": inst}
+            "ms": ms, "wall": wall, "per_pass_ms": per_pass, "passes": plan.passes(), "inst": inst,
+            "walk_mask": walk}
 
 
 COPY_SLICE_BYTES = 1 << 30
@@ -623,7 +629,7 @@ def main():
         sys.exit(1)
     nq = args.nq
     N = 1 << nq
-    r64 = single_run(torch, pk, W, "fp64", W.SEEDS["large_fp64"], nq, args.steps, args.warmup)
+    r64 = single_run(torch, pk, W, autotune, "fp64", W.SEEDS["large_fp64"], nq, args.steps, args.warmup)
     value = 1000.0 / r64["ms"]
     passes = r64["passes"]
     # dominant kernel: the fused pass (every pass moves the whole state once: 32 B per amplitude)
@@ -652,7 +658,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": kname, "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "avg_launch_ms": pass_ms, "per_pass_ms": r64["per_pass_ms"]},
+                     "avg_launch_ms": pass_ms, "per_pass_ms": r64["per_pass_ms"],
+                     "block_walk_passes": [p for p in range(passes) if r64["walk_mask"] >> p & 1]},
         "compulsory_floor_frac": (32.0 * N / (r64["ms"] * 1e-3) / 1e9) / PEAK_HBM_GBS,
         "copy_probe": {"GBs": copy_gbs, "ms": copy_ms, "frac_of_peak": copy_gbs / PEAK_HBM_GBS,
                        "pass_frac_of_copy": achieved / copy_gbs},
@@ -664,13 +671,14 @@ def main():
     kept = [("fp64", W.SEEDS["large_fp64"], r64["y"], r64["L"])]
     del r64["x"]
     if not args.no_mixed:
-        r32 = single_run(torch, pk, W, "fp32", W.SEEDS["large_fp32"], nq, args.steps, args.warmup)
+        r32 = single_run(torch, pk, W, autotune, "fp32", W.SEEDS["large_fp32"], nq, args.steps, args.warmup)
         line["mixed"] = {"dtype": "f32", "value": 1000.0 / r32["ms"], "ms_per_step": r32["ms"],
                          "speedup_vs_fp64": line["ms_per_step"] / r32["ms"], "passes": r32["passes"],
                          "rel_err_psi": None, "abs_err_L": None, "L": r32["L"], "tol": FP32_TOL,
                          "within_tol": None, "reference": "set by the oracle leg",
                          "avg_launch_ms": float(np.mean(r32["per_pass_ms"])),
-                         "achieved_GBs": 16.0 * N / (float(np.mean(r32["per_pass_ms"])) * 1e-3) / 1e9}
+                         "achieved_GBs": 16.0 * N / (float(np.mean(r32["per_pass_ms"])) * 1e-3) / 1e9,
+                         "block_walk_passes": [p for p in range(r32["passes"]) if r32["walk_mask"] >> p & 1]}
         kept.append(("fp32", W.SEEDS["large_fp32"], r32["y"], r32["L"]))
         del r32["x"]
         torch.cuda.empty_cache()

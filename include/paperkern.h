@@ -157,6 +157,19 @@ int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_
 int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu, int32_t reg_bits);
 
 /*
+ * pk_set_pass_walk -- the order in which a single-instance plan's forward
+ * passes hand tiles to workgroups: bit p of block_mask set, pass p gives each
+ * workgroup a contiguous block of tile indices (its consecutive tiles are
+ * neighbours in memory); clear, workgroup w takes tiles w, w + grid, ... (the
+ * default: the workgroups resident at once cover neighbouring tiles).  Results
+ * do not change; which order is faster depends on the pass's tile bits and is
+ * measured (paper_0902_0699_amd.autotune.tune_walk).  Reset to 0 by
+ * pk_set_tiling and by a register-bit change in pk_set_launch.  Drops captured
+ * graphs.  PK_EINVAL for a batched plan or a bit beyond the plan's passes.
+ */
+int pk_set_pass_walk(pk_plan* plan, uint64_t block_mask);
+
+/*
  * pk_set_batch -- shape of pk_evaluate_batched's persistent launch (Sec. 6.2:
  * independent multiverses).  Workgroups that share an XCD, and so an L2, form
  * teams of team_size; each team runs the passes of its large instances

@@ -171,6 +171,8 @@ enum PassFlags : int32_t {
     PASS_STREAM = 64,  // loads and stores are nontemporal (streaming): the last forward pass of
                        // an FP64 instance far larger than the memory-side cache, when it
                        // writes the tile back in the layout it read
+    PASS_BLOCKWALK = 128,  // single-instance launch: workgroup w takes the contiguous block of
+                           // tiles [w per, (w + 1) per) instead of tiles w, w + grid, ...
 };
 
 // State size from which an FP64 instance's last forward pass streams

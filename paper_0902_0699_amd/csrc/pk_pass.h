@@ -861,7 +861,17 @@ pass_kernel(KArgs a) {
     __shared__ T lds[1 << KMAX];
     __shared__ double red[16];  // reduction scratch
     const PK_CONST Pass* P = cptr(a.passes) + a.pass;
-    run_tiles<R, NV, KMAX, RB, true>(a, P, blockIdx.x, gridDim.x, P->ntiles, lds, red);
+    const int64_t ntiles = P->ntiles;
+    if (P->flags & PASS_BLOCKWALK) {
+        // consecutive tiles of one workgroup are neighbours in the tile index (the
+        // lowest free state bits): its next tile's loads reach the DRAM rows it just
+        // opened
+        const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+        const int64_t first = (int64_t)blockIdx.x * per;
+        run_tiles<R, NV, KMAX, RB, true>(a, P, first, 1, first + per < ntiles ? first + per : ntiles, lds, red);
+    } else {
+        run_tiles<R, NV, KMAX, RB, true>(a, P, blockIdx.x, gridDim.x, ntiles, lds, red);
+    }
 }
 
 // Team barrier of the batched launch: every member adds one to the team's

@@ -1373,10 +1373,13 @@ int recompile(Plan* plan, std::string* err) {
         plan->passes.push_back(p);
     };
     for (size_t i = 0; i < plan->inst.size(); ++i)
-        for (auto& hp : plan->inst[i].fwd) {
+        for (size_t p = 0; p < plan->inst[i].fwd.size(); ++p) {
+            HostPass& hp = plan->inst[i].fwd[p];
             const int64_t bytes = ((int64_t)1 << plan->inst[i].nq) * (plan->prec == PK_FP64 ? 16 : 8);
             if (plan->prec == PK_FP64 && (hp.flags & PASS_LAST) && bytes >= kStreamBytes && hp.sbits == hp.tbits)
                 hp.flags |= PASS_STREAM;
+            hp.flags &= ~PASS_BLOCKWALK;
+            if (i == 0 && plan->inst.size() == 1 && p < 64 && (plan->walk_mask >> p & 1)) hp.flags |= PASS_BLOCKWALK;
             emit(plan->inst[i], (int)i, hp);
         }
     plan->n_fwd_passes = (int)plan->passes.size();

@@ -689,6 +689,26 @@ def test_shor_marginal_density_search_entry_points_reject_bad_arguments():
     _einval(lib.pk_search_diffusion(6, pk.PK_FP64, one, 65, 5, buf, buf, buf, buf, None), "0..64")
 
 
+def test_pass_walk_mask():
+    """pk_set_pass_walk marks the chosen forward passes (PASS_BLOCKWALK = 128) and
+    nothing else; a tiling change resets it; batched plans and bits beyond the
+    passes are refused."""
+    prob = {"nq": 20, "gates": W.grover_gates((3, 2, 0.4, 0.2, 0.1)), "marked": [5]}
+    plan = pk.Plan(prob)
+    n = plan.passes()
+    plan.set_pass_walk(0b101)
+    d = plan.describe()["instances"][0]
+    assert [bool(p["flags"] & 128) for p in d["forward"]] == [p in (0, 2) for p in range(n)]
+    assert not any(p["flags"] & 128 for p in d["backward"])
+    with pytest.raises(pk.PaperkernError):
+        plan.set_pass_walk(1 << n)
+    plan.set_tiling(12, 4, 1)
+    assert not any(p["flags"] & 128 for p in plan.describe()["instances"][0]["forward"])
+    batch = pk.Plan([prob, prob])
+    with pytest.raises(pk.PaperkernError):
+        batch.set_pass_walk(1)
+
+
 def test_repeat_launch_counts():
     """pk_evaluate_repeat fuses 8 applications into one schedule when the plan has
     no angle parameters: at n_q = 20 a Grover iteration takes 3 passes, 8 take 17,

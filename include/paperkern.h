@@ -158,16 +158,18 @@ int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu, int32_t reg_bits);
 
 /*
  * pk_set_pass_walk -- the order in which a single-instance plan's forward
- * passes hand tiles to workgroups: bit p of block_mask set, pass p gives each
- * workgroup a contiguous block of tile indices (its consecutive tiles are
- * neighbours in memory); clear, workgroup w takes tiles w, w + grid, ... (the
- * default: the workgroups resident at once cover neighbouring tiles).  Results
- * do not change; which order is faster depends on the pass's tile bits and is
- * measured (paper_0902_0699_amd.autotune.tune_walk).  Reset to 0 by
- * pk_set_tiling and by a register-bit change in pk_set_launch.  Drops captured
- * graphs.  PK_EINVAL for a batched plan or a bit beyond the plan's passes.
+ * passes hand tiles to workgroups, one entry per forward pass (n = the plan's
+ * pass count; n = 0 resets every pass to 0).  Over a grid of G workgroups,
+ * workgroup w takes: 0, tiles w, w + G, ... (the default: the workgroups
+ * resident at once cover neighbouring tiles); c in 2..65536, runs of c
+ * consecutive tiles starting at tiles w c, (w + G) c, ...; -1, one contiguous
+ * block of ceil(ntiles / G) tiles.  Results do not change; which walk is faster
+ * depends on the pass's tile bits and is measured
+ * (paper_0902_0699_amd.autotune.tune_walk).  Reset by pk_set_tiling and by a
+ * register-bit change in pk_set_launch.  Drops captured graphs.  PK_EINVAL for a
+ * batched plan, a wrong n or an entry out of range.
  */
-int pk_set_pass_walk(pk_plan* plan, uint64_t block_mask);
+int pk_set_pass_walk(pk_plan* plan, int32_t n, const int32_t* walk);
 
 /*
  * pk_set_batch -- shape of pk_evaluate_batched's persistent launch (Sec. 6.2:

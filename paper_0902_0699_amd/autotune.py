@@ -66,21 +66,23 @@ def apply(plan, cfg):
     plan.set_batch(cfg.get("team_size", 16), cfg.get("min_team_tiles", 64))
 
 
-def tune_walk(plan, psi_in, psi_out, reps=3):
+WALKS = (0, 2, 4, 16, 64, -1)
+
+
+def tune_walk(plan, psi_in, psi_out, reps=3, walks=WALKS):
     """Per-pass choice of the tile walk of a single-instance plan: every pass timed
-    (pk.time_passes, HIP events) with tiles handed out strided across the grid and
-    in contiguous blocks; each pass keeps the faster (pk_set_pass_walk).  Returns
-    (mask, {mask: per-pass ms})."""
+    (pk.time_passes, HIP events) under each walk (0 strided over the grid, c runs of
+    c consecutive tiles, -1 one block a workgroup); each pass keeps its fastest
+    (pk_set_pass_walk).  Returns (walk per pass, {walk: per-pass ms})."""
     n = plan.passes()
-    full = (1 << n) - 1
     times = {}
-    for mask in (0, full):
-        plan.set_pass_walk(mask)
+    for w in walks:
+        plan.set_pass_walk([w] * n)
         pk.time_passes(plan, psi_in, psi_out)
-        times[mask] = np.median(np.array([pk.time_passes(plan, psi_in, psi_out) for _ in range(reps)]), axis=0)
-    best = sum(1 << p for p in range(n) if times[full][p] < times[0][p])
+        times[w] = np.median(np.array([pk.time_passes(plan, psi_in, psi_out) for _ in range(reps)]), axis=0)
+    best = [min(walks, key=lambda w: times[w][p]) for p in range(n)]
     plan.set_pass_walk(best)
-    return best, {m: [float(v) for v in t] for m, t in times.items()}
+    return best, {w: [float(v) for v in t] for w, t in times.items()}
 
 
 def _sources_hash():

@@ -270,7 +270,7 @@ DevPlan* fused_plan(DevPlan* d) {
     f->host.d_tables = nullptr;
     f->host.d_tables_bytes = 0;
     f->host.device = -1;
-    f->host.walk_mask = 0;
+    f->host.walk.clear();
     std::vector<Prim>& prims = f->host.inst[0].prims;
     const std::vector<Prim> one = prims;
     for (int64_t r = 1; r < kRepeatFuse; ++r) prims.insert(prims.end(), one.begin(), one.end());
@@ -614,26 +614,30 @@ int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_
     if (tile_bits - d->host.tiling.reg_bits > 10)
         return fail(d, PK_EINVAL, "tile_bits - reg_bits must be at most 10 (1024 threads a workgroup)");
     const Tiling previous = d->host.tiling;
-    d->host.walk_mask = 0;  // the passes change with the tiling
+    d->host.walk.clear();  // the passes change with the tiling
     d->host.tiling = Tiling{tile_bits, carrier_bits, fuse, d->host.tiling.wgs_per_cu, d->host.tiling.reg_bits,
                             lane_order, page_cap < 0 ? default_page_cap(d->host.prec) : page_cap};
     drop_device(d);
     return recompile_or_restore(d, previous);
 }
 
-int pk_set_pass_walk(pk_plan* plan, uint64_t block_mask) {
+int pk_set_pass_walk(pk_plan* plan, int32_t n, const int32_t* walk) {
     if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");
     DevPlan* d = dp(plan);
     if (d->host.inst.size() != 1) return fail(d, PK_EINVAL, "pk_set_pass_walk needs a single-instance plan");
-    const size_t n = d->host.inst[0].fwd.size();
-    if (n < 64 && (block_mask >> n) != 0) return fail(d, PK_EINVAL, "block_mask names a pass the plan does not have");
-    if (block_mask == d->host.walk_mask) return PK_OK;
+    const size_t np = d->host.inst[0].fwd.size();
+    if (n != 0 && (size_t)n != np) return fail(d, PK_EINVAL, "walk needs one entry per forward pass, or n = 0");
+    if (n > 0 && !walk) return fail(d, PK_EINVAL, "walk is NULL");
+    std::vector<int32_t> w(walk, walk + n);
+    for (int32_t c : w)
+        if (c < -1 || c == 1 || c > (1 << 16)) return fail(d, PK_EINVAL, "walk entries are 0, -1 or 2..65536");
+    if (w == d->host.walk) return PK_OK;
     const Tiling previous = d->host.tiling;
-    const uint64_t before = d->host.walk_mask;
-    d->host.walk_mask = block_mask;
+    const std::vector<int32_t> before = d->host.walk;
+    d->host.walk = w;
     drop_device(d);
     const int rc = recompile_or_restore(d, previous);
-    if (rc != PK_OK) d->host.walk_mask = before;
+    if (rc != PK_OK) d->host.walk = before;
     return rc;
 }
 
@@ -650,7 +654,7 @@ int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu, int32_t reg_bits) {
     d->host.tiling.wgs_per_cu = wgs_per_cu;
     d->host.tiling.reg_bits = rb;
     if (recompile_needed) {
-        d->host.walk_mask = 0;  // the passes change with the register bits
+        d->host.walk.clear();  // the passes change with the register bits
         drop_device(d);
         return recompile_or_restore(d, previous);
     }

@@ -171,8 +171,6 @@ enum PassFlags : int32_t {
     PASS_STREAM = 64,  // loads and stores are nontemporal (streaming): the last forward pass of
                        // an FP64 instance far larger than the memory-side cache, when it
                        // writes the tile back in the layout it read
-    PASS_BLOCKWALK = 128,  // single-instance launch: workgroup w takes the contiguous block of
-                           // tiles [w per, (w + 1) per) instead of tiles w, w + grid, ...
 };
 
 // State size from which an FP64 instance's last forward pass streams
@@ -215,6 +213,10 @@ struct Pass {
     int32_t nstrun;      // runs of the store map
     int32_t uref_begin;  // first URef of the pass
     int32_t nuref;       // number of them (at most kMaxURefs)
+    int32_t walk;        // tiles of workgroup w in a single-instance launch over a grid of G:
+                         // 0: w, w + G, ...; c > 1: runs of c consecutive tiles starting at
+                         // w c, (w + G) c, ...; -1: one contiguous block of ceil(ntiles / G)
+    int32_t pad;
     int32_t tpos[16];    // global bit position of local tile bit l when the tile is read
     int32_t stpos[16];   // ... when it is written (differs after SWAPs done by relabelling)
     Run trun[kMaxRuns];  // local tile label -> state label (read)

@@ -784,7 +784,8 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
 // tile's amplitudes.  NT: the pass streams (PASS_STREAM).
 template <typename R, int NV, int KMAX, int RB, bool PH, bool NT>
 __device__ __forceinline__ void run_tiles_ph(const KArgs& a, const PK_CONST Pass* P, int64_t first,
-                                             int64_t stride, int64_t ntiles, typename Cplx<R>::T* lds, double* red) {
+                                             int64_t stride, int64_t ntiles, typename Cplx<R>::T* lds, double* red,
+                                             int64_t chunk) {
     using T = typename Cplx<R>::T;
     constexpr int NR = 1 << RB;
     const PassCtx C = make_ctx<(int)sizeof(R) * 2, RB>(a, P);
@@ -792,9 +793,21 @@ __device__ __forceinline__ void run_tiles_ph(const KArgs& a, const PK_CONST Pass
     const int nfrun = P->nfrun;
     auto base_of = [&](int64_t t) { return off + deposit(t, P->frun, nfrun); };
     auto refs_of = [&](int64_t t) { return PH ? load_refs<R>(a, P, t) : TileRefs<R>{(R)1, (R)0}; };
+    // the workgroup's tiles come in runs of `chunk` consecutive ones, the runs
+    // `stride` runs apart (chunk 1: every stride-th tile)
+    const int64_t jump = (stride - 1) * chunk;
+    auto next = [&](int64_t t, int64_t& j) {
+        if (j + 1 < chunk) {
+            ++j;
+            return t + 1;
+        }
+        j = 0;
+        return t + 1 + jump;
+    };
     if constexpr (NV == 2) {
         // two vectors already fill the register file: no second buffer
-        for (int64_t tile = first; tile < ntiles; tile += stride) {
+        int64_t j = 0;
+        for (int64_t tile = first; tile < ntiles; tile = next(tile, j)) {
             T v[NV][NR];
             const int64_t base = base_of(tile);
             const TileRefs<R> u = refs_of(tile);
@@ -804,12 +817,13 @@ __device__ __forceinline__ void run_tiles_ph(const KArgs& a, const PK_CONST Pass
         }
     } else {
         T va[1][NR], vb[1][NR];
-        int64_t ta = first;
+        int64_t ta = first, ja = 0;
         int64_t basea = base_of(ta);
         TileRefs<R> ua = refs_of(ta);
         load_tile<R, 1, NR, NT>(a, C, basea, va);
         for (;;) {
-            const int64_t tb = ta + stride;
+            int64_t jb = ja;
+            const int64_t tb = next(ta, jb);
             const int64_t tbc = tb < ntiles ? tb : ta;
             const int64_t baseb = base_of(tbc);
             const TileRefs<R> ub = refs_of(tbc);
@@ -817,7 +831,8 @@ __device__ __forceinline__ void run_tiles_ph(const KArgs& a, const PK_CONST Pass
             compute_tile<R, 1, KMAX, RB>(a, P, C, ta, va, ua, lds, red);
             store_tile<R, 1, NR, NT>(a, C, basea, va);
             if (tb >= ntiles) break;
-            const int64_t tc = tb + stride;
+            int64_t jc = jb;
+            const int64_t tc = next(tb, jc);
             const int64_t tcc = tc < ntiles ? tc : tb;
             const int64_t basec = base_of(tcc);
             ua = refs_of(tcc);
@@ -826,6 +841,7 @@ __device__ __forceinline__ void run_tiles_ph(const KArgs& a, const PK_CONST Pass
             store_tile<R, 1, NR, NT>(a, C, baseb, vb);
             if (tc >= ntiles) break;
             ta = tc;
+            ja = jc;
             basea = basec;
         }
     }
@@ -835,19 +851,20 @@ __device__ __forceinline__ void run_tiles_ph(const KArgs& a, const PK_CONST Pass
 // instances are small).
 template <typename R, int NV, int KMAX, int RB, bool STREAM = false>
 __device__ __forceinline__ void run_tiles(const KArgs& a, const PK_CONST Pass* P, int64_t first,
-                                          int64_t stride, int64_t ntiles, typename Cplx<R>::T* lds, double* red) {
+                                          int64_t stride, int64_t ntiles, typename Cplx<R>::T* lds, double* red,
+                                          int64_t chunk = 1) {
     if (first >= ntiles) return;
     if (P->nuref > 0) {
-        run_tiles_ph<R, NV, KMAX, RB, true, false>(a, P, first, stride, ntiles, lds, red);
+        run_tiles_ph<R, NV, KMAX, RB, true, false>(a, P, first, stride, ntiles, lds, red, chunk);
         return;
     }
     if constexpr (STREAM && NV == 1) {
         if (P->flags & PASS_STREAM) {
-            run_tiles_ph<R, NV, KMAX, RB, false, true>(a, P, first, stride, ntiles, lds, red);
+            run_tiles_ph<R, NV, KMAX, RB, false, true>(a, P, first, stride, ntiles, lds, red, chunk);
             return;
         }
     }
-    run_tiles_ph<R, NV, KMAX, RB, false, false>(a, P, first, stride, ntiles, lds, red);
+    run_tiles_ph<R, NV, KMAX, RB, false, false>(a, P, first, stride, ntiles, lds, red, chunk);
 }
 
 // ---------------------------------------------------------------------------- kernels
@@ -862,15 +879,16 @@ pass_kernel(KArgs a) {
     __shared__ double red[16];  // reduction scratch
     const PK_CONST Pass* P = cptr(a.passes) + a.pass;
     const int64_t ntiles = P->ntiles;
-    if (P->flags & PASS_BLOCKWALK) {
-        // consecutive tiles of one workgroup are neighbours in the tile index (the
-        // lowest free state bits): its next tile's loads reach the DRAM rows it just
-        // opened
-        const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
-        const int64_t first = (int64_t)blockIdx.x * per;
-        run_tiles<R, NV, KMAX, RB, true>(a, P, first, 1, first + per < ntiles ? first + per : ntiles, lds, red);
+    const int64_t G = gridDim.x;
+    const int walk = P->walk;
+    if (walk == 0) {
+        run_tiles<R, NV, KMAX, RB, true>(a, P, blockIdx.x, G, ntiles, lds, red);
     } else {
-        run_tiles<R, NV, KMAX, RB, true>(a, P, blockIdx.x, gridDim.x, ntiles, lds, red);
+        // runs of c tiles that are neighbours in the tile index (the lowest free state
+        // bits): a workgroup's next tile, whose loads are in flight, lies next to the
+        // one it works on
+        const int64_t c = walk > 0 ? walk : (ntiles + G - 1) / G;
+        run_tiles<R, NV, KMAX, RB, true>(a, P, (int64_t)blockIdx.x * c, G, ntiles, lds, red, c);
     }
 }
 

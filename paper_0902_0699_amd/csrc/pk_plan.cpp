@@ -1378,9 +1378,8 @@ int recompile(Plan* plan, std::string* err) {
             const int64_t bytes = ((int64_t)1 << plan->inst[i].nq) * (plan->prec == PK_FP64 ? 16 : 8);
             if (plan->prec == PK_FP64 && (hp.flags & PASS_LAST) && bytes >= kStreamBytes && hp.sbits == hp.tbits)
                 hp.flags |= PASS_STREAM;
-            hp.flags &= ~PASS_BLOCKWALK;
-            if (i == 0 && plan->inst.size() == 1 && p < 64 && (plan->walk_mask >> p & 1)) hp.flags |= PASS_BLOCKWALK;
             emit(plan->inst[i], (int)i, hp);
+            if (i == 0 && plan->inst.size() == 1 && p < plan->walk.size()) plan->passes.back().walk = plan->walk[p];
         }
     plan->n_fwd_passes = (int)plan->passes.size();
     for (size_t i = 0; i < plan->inst.size(); ++i)
@@ -1550,7 +1549,8 @@ std::string describe(const Plan* plan) {
                 const HostPass& hp = ps[p];
                 if (p) s += ",";
                 s += "{\"k\":" + std::to_string(hp.k) + ",\"rbits\":" + std::to_string(hp.rbits) +
-                     ",\"flags\":" + std::to_string(hp.flags);
+                     ",\"flags\":" + std::to_string(hp.flags) + ",\"walk\":" +
+                     std::to_string(dir == 0 && plan->inst.size() == 1 && p < plan->walk.size() ? plan->walk[p] : 0);
                 s += ",\"urefs\":[";
                 for (int r = 0; r < hp.nuref; ++r) {
                     const URef& ur = plan->urefs[hp.uref_begin + r];

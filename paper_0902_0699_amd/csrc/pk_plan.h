@@ -136,7 +136,7 @@ struct Plan {
     std::vector<double> twid;          // product tables of the controlled phases (re, im pairs);
                                        // entry 0 is 1 (what lanes without a table load)
     std::vector<URef> urefs;           // tile-part tables of every pass
-    uint64_t walk_mask = 0;            // forward passes of instance 0 that walk tiles in blocks (PASS_BLOCKWALK)
+    std::vector<int32_t> walk;         // Pass::walk of each forward pass of instance 0 (empty: all 0)
     int n_d2 = 0;
     int n_d4 = 0;
     int n_static = 0;

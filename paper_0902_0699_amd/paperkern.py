@@ -56,7 +56,7 @@ SIGNATURES = {
     "pk_evaluate_batched": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pk_evaluate_repeat": (ctypes.c_int, [_vp, _c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pk_repeat_launches": (ctypes.c_int, [_vp, _c_int64, ctypes.POINTER(_c_int64)]),
-    "pk_set_pass_walk": (ctypes.c_int, [_vp, ctypes.c_uint64]),
+    "pk_set_pass_walk": (ctypes.c_int, [_vp, _c_int32, ctypes.POINTER(_c_int32)]),
     "pk_evaluate_static": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pk_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pk_pair_indices": (ctypes.c_int, [_c_int32, _c_int32, _c_int64, _c_int64, _vp, _vp, _vp]),
@@ -198,9 +198,12 @@ class Plan:
         _check(lib().pk_set_launch(self.handle, wgs_per_cu, reg_bits), self.handle)
         self._ws = {}
 
-    def set_pass_walk(self, block_mask):
-        """Bit p set: forward pass p hands each workgroup a contiguous block of tiles."""
-        _check(lib().pk_set_pass_walk(self.handle, int(block_mask)), self.handle)
+    def set_pass_walk(self, walk):
+        """Per forward pass: 0 strided over the grid, c > 1 runs of c consecutive
+        tiles, -1 one contiguous block per workgroup; an empty list resets."""
+        walk = [int(c) for c in walk]
+        arr = (_c_int32 * max(1, len(walk)))(*walk)
+        _check(lib().pk_set_pass_walk(self.handle, len(walk), arr), self.handle)
         self._ws = {}
 
     def passes(self, inst=0):

@@ -173,13 +173,13 @@ def _chunked_error(nq, amp, dev_vec, scale=1.0):
 
 
 @pytest.mark.parametrize("nq,prec", [(16, "fp64"), (26, "fp64"), (30, "fp64"), (30, "fp32")])
-def test_block_walk_is_bit_identical(nq, prec):
-    """Handing each workgroup a contiguous block of tiles (pk_set_pass_walk) changes
-    only which workgroup computes which tile: the state and L equal those of the
-    strided walk bit for bit, at the sizes the bench tunes the walk on.  The norm
-    partial of a tile is summed by whichever of the tile loop's two register
-    buffers holds it, code the compiler may round differently (FP32 sums a thread's
-    terms in FP32), so the norm agrees to 1e-12 relative."""
+def test_tile_walks_are_bit_identical(nq, prec):
+    """The tile walk (pk_set_pass_walk: strided, runs of c tiles, one block a
+    workgroup) changes only which workgroup computes which tile: the state and L
+    equal those of the strided walk bit for bit, at the sizes the bench tunes the
+    walk on.  The norm partial of a tile is summed by whichever of the tile loop's
+    two register buffers holds it, code the compiler may round differently (FP32
+    sums a thread's terms in FP32), so the norm agrees to 1e-12 relative."""
     pk = _pk()
     seed = W.SEEDS["large_fp64"] if prec == "fp64" else W.SEEDS["large_fp32"]
     inst = W.single_instance(seed, nq)
@@ -187,17 +187,19 @@ def test_block_walk_is_bit_identical(nq, prec):
     plan = pk.Plan({"nq": nq, "gates": inst["gates"], "marked": inst["marked"]}, prec=prec)
     x = torch.from_numpy(inst["psi"]).to(dt).to("cuda")
     del inst["psi"]
-    _say("block walk, n_q=%d %s: %d passes" % (nq, prec, plan.passes()))
+    n = plan.passes()
     a, La, na = pk.evaluate(plan, x)
-    plan.set_pass_walk((1 << plan.passes()) - 1)
-    flags = [p["flags"] for p in plan.describe()["instances"][0]["forward"]]
-    assert all(f & 128 for f in flags)
-    b, Lb, nb = pk.evaluate(plan, x)
-    torch.cuda.synchronize()
-    same = bool(torch.equal(a, b))
-    del a, b, x
+    for walks in ([-1] * n, [2] * n, [64] * n, [(0, 2, 4, 16, -1)[p % 5] for p in range(n)], [3] * n):
+        _say("tile walk %s, n_q=%d %s" % (walks, nq, prec))
+        plan.set_pass_walk(walks)
+        assert [p["walk"] for p in plan.describe()["instances"][0]["forward"]] == walks
+        b, Lb, nb = pk.evaluate(plan, x)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(a, b))
+        del b
+        assert same and La.item() == Lb.item() and abs(na.item() - nb.item()) <= 1e-12 * abs(na.item())
+    del a, x
     torch.cuda.empty_cache()
-    assert same and La.item() == Lb.item() and abs(na.item() - nb.item()) <= 1e-12 * abs(na.item())
 
 
 @pytest.mark.slow

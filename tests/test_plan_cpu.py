@@ -689,24 +689,30 @@ def test_shor_marginal_density_search_entry_points_reject_bad_arguments():
     _einval(lib.pk_search_diffusion(6, pk.PK_FP64, one, 65, 5, buf, buf, buf, buf, None), "0..64")
 
 
-def test_pass_walk_mask():
-    """pk_set_pass_walk marks the chosen forward passes (PASS_BLOCKWALK = 128) and
-    nothing else; a tiling change resets it; batched plans and bits beyond the
-    passes are refused."""
+def test_pass_walk_settings():
+    """pk_set_pass_walk sets each forward pass's tile walk (0 strided, c runs of c
+    tiles, -1 blocks) and nothing else; a tiling change resets it; wrong lengths,
+    values and batched plans are refused."""
     prob = {"nq": 20, "gates": W.grover_gates((3, 2, 0.4, 0.2, 0.1)), "marked": [5]}
     plan = pk.Plan(prob)
     n = plan.passes()
-    plan.set_pass_walk(0b101)
+    walks = [-1, 0, 2, 64, 4][:n]
+    plan.set_pass_walk(walks)
     d = plan.describe()["instances"][0]
-    assert [bool(p["flags"] & 128) for p in d["forward"]] == [p in (0, 2) for p in range(n)]
-    assert not any(p["flags"] & 128 for p in d["backward"])
-    with pytest.raises(pk.PaperkernError):
-        plan.set_pass_walk(1 << n)
+    assert [p["walk"] for p in d["forward"]] == walks
+    assert all(p["walk"] == 0 for p in d["backward"])
+    for bad in ([0] * (n + 1), [1] + [0] * (n - 1), [-2] + [0] * (n - 1), [1 << 17] + [0] * (n - 1)):
+        with pytest.raises(pk.PaperkernError):
+            plan.set_pass_walk(bad)
+    assert [p["walk"] for p in plan.describe()["instances"][0]["forward"]] == walks
     plan.set_tiling(12, 4, 1)
-    assert not any(p["flags"] & 128 for p in plan.describe()["instances"][0]["forward"])
+    assert all(p["walk"] == 0 for p in plan.describe()["instances"][0]["forward"])
+    plan.set_pass_walk(walks[:1] * plan.passes())
+    plan.set_pass_walk([])
+    assert all(p["walk"] == 0 for p in plan.describe()["instances"][0]["forward"])
     batch = pk.Plan([prob, prob])
     with pytest.raises(pk.PaperkernError):
-        batch.set_pass_walk(1)
+        batch.set_pass_walk([0])
 
 
 def test_repeat_launch_counts():

@@ -300,13 +300,15 @@ def batched_run(torch, pk, W, autotune, steps, warmup, prec, insts, record=None,
     return res, best
 
 
-def gradient_run(torch, pk, W, nq):
+def gradient_run(torch, pk, W, autotune, nq):
     inst = W.single_instance(W.SEEDS["gradient"], nq)
     plan = pk.Plan({"nq": nq, "gates": inst["gates"], "marked": inst["marked"]})
     x = torch.from_numpy(inst["psi"]).to("cuda")
     ang = torch.tensor(list(inst["noise"][2:5]), dtype=torch.float64, device="cuda")
     out, L, _ = pk.evaluate(plan, x, angles=ang, want_norm=False)
     dL = torch.ones(1, dtype=torch.float64, device="cuda")
+    walk, walk_ms = autotune.tune_backward_walk(plan, out, dL, angles=ang)
+    log("gradient: backward tile walk %d (ms per walk %s)" % (walk, {w: round(t, 1) for w, t in walk_ms.items()}))
     gpsi, gang = pk.backward(plan, out, dL, angles=ang)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -345,7 +347,7 @@ def gradient_run(torch, pk, W, nq):
     err = float(np.max(np.abs(fd - ad)) / np.max(np.abs(ad)))
     return {"nq": nq, "ms_backward": ms_bwd, "fd_inputs": len(comps), "fd_h": h,
             "normwise_rel_err": err, "tol": 1e-6, "within_tol": err <= 1e-6,
-            "backward_passes": len(plan.describe()["instances"][0]["backward"])}
+            "backward_passes": len(plan.describe()["instances"][0]["backward"]), "backward_tile_walk": walk}
 
 
 def brickwork_gates(nq, seed):
@@ -360,7 +362,7 @@ def brickwork_gates(nq, seed):
     return gates
 
 
-def two_qubit_run(torch, pk, nq, steps):
+def two_qubit_run(torch, pk, autotune, nq, steps):
     """TwoOpA sweeps (Eq. resmat2) at full size: a brickwork circuit, fused and one
     sweep per gate; the unitary circuit must keep the norm."""
     gates = brickwork_gates(nq, 5)
@@ -376,6 +378,9 @@ def two_qubit_run(torch, pk, nq, steps):
         plan = pk.Plan({"nq": nq, "gates": gates, "marked": [0]})
         if not fuse:
             plan.set_tiling(13, 4, 0)
+        else:
+            walk, _ = autotune.tune_walk(plan, x, y)
+            out["fused_tile_walk"] = walk
         pk.evaluate_into(plan, x, y, L, norm)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -421,6 +426,7 @@ def shor_run(torch, pk, W, autotune, steps, prec, qft_tiling=None):
     pk.shor_state(n1, n2, x, M, prec=prec, out=psi)
     best, _ = autotune.tune(plan, lambda: pk.evaluate_into(plan, psi, psi, L), op="eval", use_cache=False,
                             cands=cands)
+    walk, _ = autotune.tune_walk(plan, psi, psi)
 
     def run(ev=None):
         if ev:
@@ -450,7 +456,7 @@ def shor_run(torch, pk, W, autotune, steps, prec, qft_tiling=None):
     ms = float(parts.sum())
     out = {"workload": "Shor data path, M=%d xguess=%d: n1=%d, n2=%d (n_q=%d), %s" % (M, x, n1, n2, nq, prec.upper()),
            "ms": ms, "runs_per_s": 1e3 / ms, "qft_passes": plan.passes(),
-           "qft_tiling": {k: best[k] for k in ("tile_bits", "carrier_bits", "reg_bits")},
+           "qft_tiling": {k: best[k] for k in ("tile_bits", "carrier_bits", "reg_bits")}, "qft_tile_walk": walk,
            "load_ms": parts[0], "qft_ms": parts[1], "marginal_ms": parts[2],
            "load_GBs": esz * N / (parts[0] * 1e-3) / 1e9,
            "qft_mean_pass_GBs": 2.0 * esz * N / (np.mean(per_pass) * 1e-3) / 1e9,
@@ -465,6 +471,7 @@ def shor_run(torch, pk, W, autotune, steps, prec, qft_tiling=None):
     pk.shor_state(n1, n2, x, M, prec=prec, out=psi)
     best2, _ = autotune.tune(plan2, lambda: pk.evaluate_into(plan2, psi, psi, L), op="eval", use_cache=False,
                              cands=cands)
+    walk2, _ = autotune.tune_walk(plan2, psi, psi)
 
     def run2(ev):
         ev[0].record()
@@ -485,7 +492,7 @@ def shor_run(torch, pk, W, autotune, steps, prec, qft_tiling=None):
     out["noswap_variant"] = {
         "method": "QFT without the final pair swaps, marginal with register one bit-reversed (not the paper's circuit)",
         "ms": float(parts2.sum()), "qft_ms": parts2[1], "qft_passes": plan2.passes(), "marginal_ms": parts2[2],
-        "qft_tiling": {k: best2[k] for k in ("tile_bits", "carrier_bits", "reg_bits")},
+        "qft_tiling": {k: best2[k] for k in ("tile_bits", "carrier_bits", "reg_bits")}, "qft_tile_walk": walk2,
         "max_abs_dp_vs_paper_form": float((p - p_ref).abs().max().item())}
     log("shor %s, no-swap variant: QFT %.2f ms (%d passes), whole path %.2f ms"
         % (prec, parts2[1], plan2.passes(), parts2.sum()))
@@ -703,13 +710,13 @@ def main():
                 json.dump(new_records, f, indent=1)
         del insts
     if "gradient" in legs:
-        line["gradient"] = gradient_run(torch, pk, W, nq)
+        line["gradient"] = gradient_run(torch, pk, W, autotune, nq)
         log("gradient: backward %.2f ms (%d passes), FD normwise rel err %.3e"
             % (line["gradient"]["ms_backward"], line["gradient"]["backward_passes"],
                line["gradient"]["normwise_rel_err"]))
         torch.cuda.empty_cache()
     if args.extra:
-        runs = [("two_qubit", lambda: two_qubit_run(torch, pk, nq, k)),
+        runs = [("two_qubit", lambda: two_qubit_run(torch, pk, autotune, nq, k)),
                 ("shor", lambda: {p: shor_run(torch, pk, W, autotune, k, p, qft_tiling)
                                   for p in args.shor_precs.split(",")}),
                 ("density", lambda: density_run(torch, pk, W, k)),

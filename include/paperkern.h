@@ -157,9 +157,10 @@ int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_
 int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu, int32_t reg_bits);
 
 /*
- * pk_set_pass_walk -- the order in which a single-instance plan's forward
- * passes hand tiles to workgroups, one entry per forward pass (n = the plan's
- * pass count; n = 0 resets every pass to 0).  Over a grid of G workgroups,
+ * pk_set_pass_walk -- the order in which a single-instance plan's passes hand
+ * tiles to workgroups: one entry per forward pass (n = pk_plan_passes), or one
+ * per forward pass followed by one per backward pass (pk_backward); n = 0
+ * resets every pass to 0.  Over a grid of G workgroups,
  * workgroup w takes: 0, tiles w, w + G, ... (the default: the workgroups
  * resident at once cover neighbouring tiles); c in 2..65536, runs of c
  * consecutive tiles starting at tiles w c, (w + G) c, ...; -1, one contiguous

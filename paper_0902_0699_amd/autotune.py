@@ -85,6 +85,33 @@ def tune_walk(plan, psi_in, psi_out, reps=3, walks=WALKS):
     return best, {w: [float(v) for v in t] for w, t in times.items()}
 
 
+def tune_backward_walk(plan, psi_out, dL, angles=None, reps=2, walks=WALKS):
+    """One tile walk for every backward pass of a single-instance plan, the fastest
+    whole pk_backward among ``walks`` (HIP events); the forward passes keep theirs.
+    Returns (walk, {walk: ms})."""
+    import torch
+    d = plan.describe()["instances"][0]
+    fwd = [p["walk"] for p in d["forward"]]
+    nb = len(d["backward"])
+    times = {}
+    for w in walks:
+        plan.set_pass_walk(fwd + [w] * nb)
+        pk.backward(plan, psi_out, dL, angles=angles)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            pk.backward(plan, psi_out, dL, angles=angles)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        times[w] = float(np.median(ts))
+    best = min(walks, key=lambda w: times[w])
+    plan.set_pass_walk(fwd + [best] * nb)
+    return best, times
+
+
 def _sources_hash():
     """Hash of the library's kernel and planner sources: a choice timed on one
     version of the kernels is not reused by another."""

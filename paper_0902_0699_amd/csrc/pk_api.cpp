@@ -625,8 +625,9 @@ int pk_set_pass_walk(pk_plan* plan, int32_t n, const int32_t* walk) {
     if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");
     DevPlan* d = dp(plan);
     if (d->host.inst.size() != 1) return fail(d, PK_EINVAL, "pk_set_pass_walk needs a single-instance plan");
-    const size_t np = d->host.inst[0].fwd.size();
-    if (n != 0 && (size_t)n != np) return fail(d, PK_EINVAL, "walk needs one entry per forward pass, or n = 0");
+    const size_t nf = d->host.inst[0].fwd.size(), nb = d->host.inst[0].bwd.size();
+    if (n != 0 && (size_t)n != nf && (size_t)n != nf + nb)
+        return fail(d, PK_EINVAL, "walk needs one entry per forward pass (then, optionally, per backward pass), or n = 0");
     if (n > 0 && !walk) return fail(d, PK_EINVAL, "walk is NULL");
     std::vector<int32_t> w(walk, walk + n);
     for (int32_t c : w)

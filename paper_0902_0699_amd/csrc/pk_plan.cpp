@@ -1383,7 +1383,12 @@ int recompile(Plan* plan, std::string* err) {
         }
     plan->n_fwd_passes = (int)plan->passes.size();
     for (size_t i = 0; i < plan->inst.size(); ++i)
-        for (auto& hp : plan->inst[i].bwd) emit(plan->inst[i], (int)i, hp);
+        for (size_t p = 0; p < plan->inst[i].bwd.size(); ++p) {
+            emit(plan->inst[i], (int)i, plan->inst[i].bwd[p]);
+            const size_t nf = plan->inst[i].fwd.size();
+            if (i == 0 && plan->inst.size() == 1 && plan->walk.size() == nf + plan->inst[i].bwd.size())
+                plan->passes.back().walk = plan->walk[nf + p];
+        }
 
     // batched launch tables
     int first = 0;
@@ -1550,7 +1555,9 @@ std::string describe(const Plan* plan) {
                 if (p) s += ",";
                 s += "{\"k\":" + std::to_string(hp.k) + ",\"rbits\":" + std::to_string(hp.rbits) +
                      ",\"flags\":" + std::to_string(hp.flags) + ",\"walk\":" +
-                     std::to_string(dir == 0 && plan->inst.size() == 1 && p < plan->walk.size() ? plan->walk[p] : 0);
+                     std::to_string(plan->inst.size() != 1 ? 0
+                                    : dir == 0 ? (p < plan->walk.size() ? plan->walk[p] : 0)
+                                    : (plan->walk.size() == in.fwd.size() + in.bwd.size() ? plan->walk[in.fwd.size() + p] : 0));
                 s += ",\"urefs\":[";
                 for (int r = 0; r < hp.nuref; ++r) {
                     const URef& ur = plan->urefs[hp.uref_begin + r];

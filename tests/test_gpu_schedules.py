@@ -202,6 +202,25 @@ def test_tile_walks_are_bit_identical(nq, prec):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("nq", [14, 24])
+def test_backward_tile_walks_are_bit_identical(nq):
+    """Tile walks of the backward passes (pk_set_pass_walk with backward entries)
+    leave the gradient bit for bit as with the strided walk."""
+    pk = _pk()
+    gates, marked, psi = _case(nq, 2, 40 + nq)
+    plan = pk.Plan({"nq": nq, "gates": gates, "marked": marked})
+    out, _, _ = pk.evaluate(plan, torch.from_numpy(psi).to("cuda"))
+    dL = torch.tensor([0.5], dtype=torch.float64, device="cuda")
+    g0, a0 = pk.backward(plan, out, dL)
+    nf, nb = plan.passes(), len(plan.describe()["instances"][0]["backward"])
+    for w in (2, 64, -1, 3):
+        _say("backward tile walk %d, n_q=%d" % (w, nq))
+        plan.set_pass_walk([0] * nf + [w] * nb)
+        g1, a1 = pk.backward(plan, out, dL)
+        torch.cuda.synchronize()
+        assert bool(torch.equal(g0, g1)) and bool(torch.equal(a0, a1))
+
+
 @pytest.mark.slow
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])

@@ -710,6 +710,12 @@ def test_pass_walk_settings():
     plan.set_pass_walk(walks[:1] * plan.passes())
     plan.set_pass_walk([])
     assert all(p["walk"] == 0 for p in plan.describe()["instances"][0]["forward"])
+    nb = len(plan.describe()["instances"][0]["backward"])
+    plan.set_pass_walk([0] * plan.passes() + [64] * nb)
+    d = plan.describe()["instances"][0]
+    assert all(p["walk"] == 0 for p in d["forward"]) and all(p["walk"] == 64 for p in d["backward"])
+    with pytest.raises(pk.PaperkernError):
+        plan.set_pass_walk([0] * (plan.passes() + nb + 1))
     batch = pk.Plan([prob, prob])
     with pytest.raises(pk.PaperkernError):
         batch.set_pass_walk([0])

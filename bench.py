@@ -85,7 +85,7 @@ def single_run(torch, pk, W, autotune, prec, seed, nq, steps, warmup):
     norm = torch.empty(1, dtype=torch.float64, device="cuda")
     # per pass, the faster of the two tile walks, measured on these buffers
     walk, walk_ms = autotune.tune_walk(plan, x, y)
-    log("%s: tile walk per pass %s (0 strided, c runs of c tiles, -1 blocks; per-pass ms %s)"
+    log("%s: tile walk per pass %s (0 strided, c runs of c tiles, -1 blocks, +o overlapped loop; per-pass ms %s)"
         % (prec, walk, {w: [round(v, 2) for v in t] for w, t in walk_ms.items()}))
     for _ in range(warmup):
         pk.evaluate_into(plan, x, y, L, norm)
@@ -109,7 +109,7 @@ def single_run(torch, pk, W, autotune, prec, seed, nq, steps, warmup):
     per_pass = [float(np.mean([r[p] for r in reps])) for p in range(len(reps[0]))]
     return {"plan": plan, "x": x, "y": y, "L": float(L.item()), "norm": float(norm.item()),
             "ms": ms, "wall": wall, "per_pass_ms": per_pass, "passes": plan.passes(), "inst": inst,
-            "walk": walk}
+            "walk": walk, "overlap": [p["overlap"] for p in plan.describe()["instances"][0]["forward"]]}
 
 
 COPY_SLICE_BYTES = 1 << 30
@@ -665,7 +665,7 @@ def main():
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": kname, "algorithmic_bytes_per_launch": bytes_per_launch,
                      "avg_launch_ms": pass_ms, "per_pass_ms": r64["per_pass_ms"],
-                     "tile_walk": r64["walk"]},
+                     "tile_walk": r64["walk"], "overlap": r64["overlap"]},
         "compulsory_floor_frac": (32.0 * N / (r64["ms"] * 1e-3) / 1e9) / PEAK_HBM_GBS,
         "copy_probe": {"GBs": copy_gbs, "ms": copy_ms, "frac_of_peak": copy_gbs / PEAK_HBM_GBS,
                        "pass_frac_of_copy": achieved / copy_gbs},
@@ -684,7 +684,7 @@ def main():
                          "within_tol": None, "reference": "set by the oracle leg",
                          "avg_launch_ms": float(np.mean(r32["per_pass_ms"])),
                          "achieved_GBs": 16.0 * N / (float(np.mean(r32["per_pass_ms"])) * 1e-3) / 1e9,
-                         "tile_walk": r32["walk"]}
+                         "tile_walk": r32["walk"], "overlap": r32["overlap"]}
         kept.append(("fp32", W.SEEDS["large_fp32"], r32["y"], r32["L"]))
         del r32["x"]
         torch.cuda.empty_cache()

@@ -173,6 +173,33 @@ int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu, int32_t reg_bits);
 int pk_set_pass_walk(pk_plan* plan, int32_t n, const int32_t* walk);
 
 /*
+ * pk_set_pass_overlap -- how a single-instance plan's forward passes pipeline
+ * HBM and LDS: one entry per forward pass (n = pk_plan_passes) or n = 0 to reset
+ * every pass to 0.  1: the pass keeps the next tile's loads in flight through
+ * all of the current tile's LDS exchanges (the tile loop that issues the same
+ * loads on every path, so that only the current tile's loads are waited for);
+ * 0: they are waited for at the first exchange.  It applies to the FP64 kernels
+ * with 4 register bits and to passes whose tiles fill the workgroup; elsewhere
+ * it is accepted and changes nothing.  Results do not change; which setting is
+ * faster depends on the pass and is measured
+ * (paper_0902_0699_amd.autotune.tune_walk).  Reset by pk_set_tiling and by a
+ * register-bit change in pk_set_launch.  Drops captured graphs.  PK_EINVAL for a
+ * batched plan, a wrong n or an entry other than 0 or 1.
+ */
+int pk_set_pass_overlap(pk_plan* plan, int32_t n, const int32_t* on);
+
+/*
+ * pk_set_lane_maps -- on = 1 (the default): a stage layout that moves through LDS
+ * only (neither a pass's first nor its last) gets a thread-to-label map whose low
+ * thread bits sit on local bits of distinct residue modulo the LDS slot swizzle's
+ * group width, so that the lanes of one LDS access cycle hit distinct banks; on =
+ * 0: every layout takes the thread bits in ascending order.  Results do not
+ * change (each amplitude meets the same arithmetic in either map).  Re-compiles
+ * the schedule and drops captured graphs.  PK_EINVAL when on is not 0 or 1.
+ */
+int pk_set_lane_maps(pk_plan* plan, int32_t on);
+
+/*
  * pk_set_batch -- shape of pk_evaluate_batched's persistent launch (Sec. 6.2:
  * independent multiverses).  Workgroups that share an XCD, and so an L2, form
  * teams of team_size; each team runs the passes of its large instances

@@ -69,20 +69,35 @@ def apply(plan, cfg):
 WALKS = (0, 2, 4, 16, 64, -1)
 
 
-def tune_walk(plan, psi_in, psi_out, reps=3, walks=WALKS):
-    """Per-pass choice of the tile walk of a single-instance plan: every pass timed
-    (pk.time_passes, HIP events) under each walk (0 strided over the grid, c runs of
-    c consecutive tiles, -1 one block a workgroup); each pass keeps its fastest
-    (pk_set_pass_walk).  Returns (walk per pass, {walk: per-pass ms})."""
+def has_overlap(plan):
+    """Whether Pass::overlap can change a forward pass of this plan: the FP64
+    single-instance kernels with 4 register bits have the overlapped tile loop."""
+    if plan.prec != pk.PK_FP64 or plan.n_inst != 1:
+        return False
+    return any(p["rbits"] == 4 for p in plan.describe()["instances"][0]["forward"])
+
+
+def tune_walk(plan, psi_in, psi_out, reps=3, walks=WALKS, overlap=True):
+    """Per-pass choice of the tile walk of a single-instance plan (0 strided over
+    the grid, c runs of c consecutive tiles, -1 one block a workgroup) and, where
+    the kernel has it, of the overlapped tile loop (pk_set_pass_overlap): every
+    pass timed (pk.time_passes, HIP events) under each combination; each pass
+    keeps its fastest.  Returns (walk per pass, {setting: per-pass ms}), the
+    settings named by the walk, with "+o" for the overlapped loop."""
     n = plan.passes()
+    modes = (0, 1) if overlap and has_overlap(plan) else (0,)
     times = {}
-    for w in walks:
-        plan.set_pass_walk([w] * n)
-        pk.time_passes(plan, psi_in, psi_out)
-        times[w] = np.median(np.array([pk.time_passes(plan, psi_in, psi_out) for _ in range(reps)]), axis=0)
-    best = [min(walks, key=lambda w: times[w][p]) for p in range(n)]
-    plan.set_pass_walk(best)
-    return best, {w: [float(v) for v in t] for w, t in times.items()}
+    for ov in modes:
+        plan.set_pass_overlap([ov] * n)
+        for w in walks:
+            plan.set_pass_walk([w] * n)
+            pk.time_passes(plan, psi_in, psi_out)
+            times[(w, ov)] = np.median(np.array([pk.time_passes(plan, psi_in, psi_out) for _ in range(reps)]), axis=0)
+    best = [min(times, key=lambda c: times[c][p]) for p in range(n)]
+    plan.set_pass_overlap([c[1] for c in best] if len(modes) > 1 else [])
+    plan.set_pass_walk([c[0] for c in best])
+    named = {("%d+o" % w if ov else str(w)): [float(v) for v in t] for (w, ov), t in times.items()}
+    return [c[0] for c in best], named
 
 
 def tune_backward_walk(plan, psi_out, dL, angles=None, reps=2, walks=WALKS):

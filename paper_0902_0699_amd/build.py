@@ -17,9 +17,12 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpaperkern.so")
 # the pass and batched kernel instances come first: they take longest to compile
-SOURCES = ["pk_batched_f32.hip", "pk_batched_f64.hip", "pk_repeat_f32.hip", "pk_repeat_f64.hip", "pk_pass_f32.hip", "pk_pass_f64.hip", "pk_pass_f32r5.hip",
-           "pk_pass_f64r5.hip", "pk_pass_f32r3.hip", "pk_pass_f64r3.hip", "pk_pass_f32bwd.hip", "pk_pass_f64bwd.hip", "pk_kernels.hip", "pk_shor.hip",
-           "pk_density.hip", "pk_search.hip", "pk_api.cpp", "pk_plan.cpp"]
+SOURCES = [
+    # longest compiles first, so that the parallel build ends with short ones
+    "pk_pass_f64r5.hip", "pk_batched_f64.hip", "pk_batched_f32.hip", "pk_pass_f64bwd.hip", "pk_pass_f32r5.hip",
+    "pk_pass_f32bwd.hip", "pk_pass_f64r3.hip", "pk_pass_f64t.hip", "pk_plan.cpp", "pk_api.cpp", "pk_search.hip",
+    "pk_density.hip", "pk_shor.hip", "pk_kernels.hip", "pk_pass_f32r3.hip", "pk_repeat_f64.hip", "pk_pass_f64.hip",
+    "pk_pass_f32.hip", "pk_repeat_f32.hip"]
 # rocSOLVER (and the rocBLAS handle it runs on) gives the density matrix's eigenvalues
 LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

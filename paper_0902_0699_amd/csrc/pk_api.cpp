@@ -271,6 +271,7 @@ DevPlan* fused_plan(DevPlan* d) {
     f->host.d_tables_bytes = 0;
     f->host.device = -1;
     f->host.walk.clear();
+    f->host.overlap.clear();
     std::vector<Prim>& prims = f->host.inst[0].prims;
     const std::vector<Prim> one = prims;
     for (int64_t r = 1; r < kRepeatFuse; ++r) prims.insert(prims.end(), one.begin(), one.end());
@@ -615,6 +616,7 @@ int pk_set_tiling(pk_plan* plan, int32_t tile_bits, int32_t carrier_bits, int32_
         return fail(d, PK_EINVAL, "tile_bits - reg_bits must be at most 10 (1024 threads a workgroup)");
     const Tiling previous = d->host.tiling;
     d->host.walk.clear();  // the passes change with the tiling
+    d->host.overlap.clear();
     d->host.tiling = Tiling{tile_bits, carrier_bits, fuse, d->host.tiling.wgs_per_cu, d->host.tiling.reg_bits,
                             lane_order, page_cap < 0 ? default_page_cap(d->host.prec) : page_cap};
     drop_device(d);
@@ -642,6 +644,39 @@ int pk_set_pass_walk(pk_plan* plan, int32_t n, const int32_t* walk) {
     return rc;
 }
 
+int pk_set_pass_overlap(pk_plan* plan, int32_t n, const int32_t* on) {
+    if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");
+    DevPlan* d = dp(plan);
+    if (d->host.inst.size() != 1) return fail(d, PK_EINVAL, "pk_set_pass_overlap needs a single-instance plan");
+    const size_t nf = d->host.inst[0].fwd.size();
+    if (n != 0 && (size_t)n != nf) return fail(d, PK_EINVAL, "overlap needs one entry per forward pass, or n = 0");
+    if (n > 0 && !on) return fail(d, PK_EINVAL, "on is NULL");
+    std::vector<int32_t> w(on, on + n);
+    for (int32_t c : w)
+        if (c != 0 && c != 1) return fail(d, PK_EINVAL, "overlap entries are 0 or 1");
+    if (w == d->host.overlap) return PK_OK;
+    const Tiling previous = d->host.tiling;
+    const std::vector<int32_t> before = d->host.overlap;
+    d->host.overlap = w;
+    drop_device(d);
+    const int rc = recompile_or_restore(d, previous);
+    if (rc != PK_OK) d->host.overlap = before;
+    return rc;
+}
+
+int pk_set_lane_maps(pk_plan* plan, int32_t on) {
+    if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");
+    DevPlan* d = dp(plan);
+    if (on != 0 && on != 1) return fail(d, PK_EINVAL, "on must be 0 or 1");
+    if (on == d->host.lane_maps) return PK_OK;
+    const Tiling previous = d->host.tiling;
+    d->host.lane_maps = on;
+    drop_device(d);
+    const int rc = recompile_or_restore(d, previous);
+    if (rc != PK_OK) d->host.lane_maps = 1 - on;
+    return rc;
+}
+
 int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu, int32_t reg_bits) {
     if (!valid(plan)) return fail(nullptr, PK_EINVAL, "invalid plan");
     DevPlan* d = dp(plan);
@@ -656,6 +691,7 @@ int pk_set_launch(pk_plan* plan, int32_t wgs_per_cu, int32_t reg_bits) {
     d->host.tiling.reg_bits = rb;
     if (recompile_needed) {
         d->host.walk.clear();  // the passes change with the register bits
+        d->host.overlap.clear();
         drop_device(d);
         return recompile_or_restore(d, previous);
     }

@@ -139,6 +139,15 @@ struct alignas(16) Stage {
     alignas(16) int32_t phase_ut0[kPhaseSlots];
     int32_t phase_ut1[kPhaseSlots];
     uint32_t phase_ttm[kPhaseSlots];
+    // Thread -> local label map of the layout.  nlanes == 0: the thread index's bits
+    // go to the local bits that are not register bits, in ascending order.  Else
+    // thread bit i < nlanes goes to local bit (lanes >> 4 i) & 15 and the thread's
+    // higher bits to the bits of lanes_rest in ascending order: the planner picks
+    // the low bits so that the lanes sharing an LDS access cycle hit distinct banks
+    // under the slot swizzle (only for layouts that neither load nor store HBM).
+    int32_t nlanes;
+    uint32_t lanes;
+    uint32_t lanes_rest;
 };
 static_assert(offsetof(Stage, phase_pm) % 16 == 0 && offsetof(Stage, phase_cnt) == offsetof(Stage, phase_pm) + 16 &&
                   offsetof(Stage, phase_ucnt) == offsetof(Stage, phase_pm) + 32 &&
@@ -216,7 +225,8 @@ struct Pass {
     int32_t walk;        // tiles of workgroup w in a single-instance launch over a grid of G:
                          // 0: w, w + G, ...; c > 1: runs of c consecutive tiles starting at
                          // w c, (w + G) c, ...; -1: one contiguous block of ceil(ntiles / G)
-    int32_t pad;
+    int32_t overlap;     // single-instance launch, forward pass of full tiles: 1 keeps the next
+                         // tile's loads in flight through the LDS exchanges (see run_tiles)
     int32_t tpos[16];    // global bit position of local tile bit l when the tile is read
     int32_t stpos[16];   // ... when it is written (differs after SWAPs done by relabelling)
     Run trun[kMaxRuns];  // local tile label -> state label (read)

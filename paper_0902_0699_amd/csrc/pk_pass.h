@@ -67,10 +67,27 @@ template <int ESZ>
 __device__ __forceinline__ Layout make_layout(const PK_CONST Stage* S, int nrb, unsigned tid) {
     Layout L;
     unsigned t = tid;
-    // spread the thread index over the local bits that are not register bits
-    for (int q = 0; q < nrb; ++q) {
-        const int p = S->rbs[q];
-        t = ((t >> p) << (p + 1)) | (t & ((1u << p) - 1u));
+    if (S->nlanes == 0) {
+        // spread the thread index over the local bits that are not register bits
+        for (int q = 0; q < nrb; ++q) {
+            const int p = S->rbs[q];
+            t = ((t >> p) << (p + 1)) | (t & ((1u << p) - 1u));
+        }
+    } else {
+        // the low W thread bits to the chosen local bits, one per swizzle group bit,
+        // the others in order to the remaining free bits (the masks are uniform)
+        constexpr int W = ESZ == 16 ? 4 : 5;
+        const unsigned lanes = S->lanes;
+        t = 0u;
+#pragma unroll
+        for (int i = 0; i < W; ++i) t |= ((tid >> i) & 1u) << ((lanes >> (4 * i)) & 15u);
+        unsigned rest = S->lanes_rest, x = tid >> W;
+        while (rest != 0u) {
+            const unsigned low = rest & (0u - rest);
+            if (x & 1u) t |= low;
+            x >>= 1;
+            rest ^= low;
+        }
     }
     L.jt = t;
     L.pj = phys<ESZ>(t);
@@ -781,14 +798,24 @@ __device__ __forceinline__ void compute_tile(const KArgs& a, const PK_CONST Pass
 // workgroup an LDS-sized tile leaves per CU.  The prefetch is unconditional
 // (past the end it re-reads the current tile) so the wait counts stay static.
 // PH: the pass has tile-part product tables, whose entries are loaded with the
-// tile's amplitudes.  NT: the pass streams (PASS_STREAM).
-template <typename R, int NV, int KMAX, int RB, bool PH, bool NT>
+// tile's amplitudes.  NT: the pass streams (PASS_STREAM).  FULL: the tile fills
+// the workgroup (k == KMAX: every thread active, every register used) and lane
+// offsets fit 32 bits, so every thread issues the same loads on every path; the
+// compiler can then wait for exactly the current tile's loads (the next tile's
+// stay in flight through the exchanges), where path-dependent load counts make
+// it wait for all of them at the first LDS write.
+template <typename R, int NV, int KMAX, int RB, bool PH, bool NT, bool FULL>
 __device__ __forceinline__ void run_tiles_ph(const KArgs& a, const PK_CONST Pass* P, int64_t first,
                                              int64_t stride, int64_t ntiles, typename Cplx<R>::T* lds, double* red,
                                              int64_t chunk) {
     using T = typename Cplx<R>::T;
     constexpr int NR = 1 << RB;
-    const PassCtx C = make_ctx<(int)sizeof(R) * 2, RB>(a, P);
+    PassCtx C = make_ctx<(int)sizeof(R) * 2, RB>(a, P);
+    if constexpr (FULL) {
+        C.active = true;
+        C.nreg = NR;
+        C.flags &= ~PASS_WIDE;
+    }
     const int64_t off = P->state_off;
     const int nfrun = P->nfrun;
     auto base_of = [&](int64_t t) { return off + deposit(t, P->frun, nfrun); };
@@ -847,24 +874,34 @@ __device__ __forceinline__ void run_tiles_ph(const KArgs& a, const PK_CONST Pass
     }
 }
 
-// STREAM: honour PASS_STREAM (single-instance launches; a batched launch's
-// instances are small).
+// STREAM: a single-instance launch: honour PASS_STREAM and Pass::overlap (a
+// batched launch's instances are small).
 template <typename R, int NV, int KMAX, int RB, bool STREAM = false>
 __device__ __forceinline__ void run_tiles(const KArgs& a, const PK_CONST Pass* P, int64_t first,
                                           int64_t stride, int64_t ntiles, typename Cplx<R>::T* lds, double* red,
                                           int64_t chunk = 1) {
     if (first >= ntiles) return;
+    // Pass::overlap selects the FULL loop where it applies (single-instance launches).
+    // Only the FP64 kernels with 4 register bits have it: its two register buffers
+    // take no more registers there than the other loops (237 at 2^13 tiles), while
+    // the FP32 kernel with 5 would go from 241 to 359 VGPRs (one workgroup a CU
+    // instead of two, 17.7 -> 21.6 ms an iteration) or spill under a 256 cap.
+    constexpr bool kHasFull = STREAM && NV == 1 && sizeof(R) == 8 && RB == 4;
+    const bool full = kHasFull && P->overlap && P->k == KMAX && !(P->flags & PASS_WIDE);
     if (P->nuref > 0) {
-        run_tiles_ph<R, NV, KMAX, RB, true, false>(a, P, first, stride, ntiles, lds, red, chunk);
+        if (full) run_tiles_ph<R, NV, KMAX, RB, true, false, true>(a, P, first, stride, ntiles, lds, red, chunk);
+        else run_tiles_ph<R, NV, KMAX, RB, true, false, false>(a, P, first, stride, ntiles, lds, red, chunk);
         return;
     }
     if constexpr (STREAM && NV == 1) {
         if (P->flags & PASS_STREAM) {
-            run_tiles_ph<R, NV, KMAX, RB, false, true>(a, P, first, stride, ntiles, lds, red, chunk);
+            if (full) run_tiles_ph<R, NV, KMAX, RB, false, true, true>(a, P, first, stride, ntiles, lds, red, chunk);
+            else run_tiles_ph<R, NV, KMAX, RB, false, true, false>(a, P, first, stride, ntiles, lds, red, chunk);
             return;
         }
     }
-    run_tiles_ph<R, NV, KMAX, RB, false, false>(a, P, first, stride, ntiles, lds, red, chunk);
+    if (full) run_tiles_ph<R, NV, KMAX, RB, false, false, true>(a, P, first, stride, ntiles, lds, red, chunk);
+    else run_tiles_ph<R, NV, KMAX, RB, false, false, false>(a, P, first, stride, ntiles, lds, red, chunk);
 }
 
 // ---------------------------------------------------------------------------- kernels
@@ -1079,7 +1116,7 @@ __global__ void __launch_bounds__(1 << (KMAX - RB)) repeat_kernel(KArgs a, Repea
 // Persistent launch: as many workgroups as fit on the device at once (capped by
 // the tile count); each walks its tiles with the load of the next one in flight.
 template <typename R, int NV, int KMAX, int RB>
-static hipError_t launch_pass_t(const KArgs& a, int64_t ntiles, int64_t wgs_per_cu, hipStream_t st) {
+hipError_t launch_pass_t(const KArgs& a, int64_t ntiles, int64_t wgs_per_cu, hipStream_t st) {
     static int ncu = 0, per_cu = 0;  // queried once per kernel instance
     if (ncu == 0) {
         int dev = 0;

@@ -407,6 +407,48 @@ int place(Stage& s, int cursor, const Op& o) {
     }
 }
 
+// LDS lane map of a layout that moves through LDS only (neither the first nor the
+// last of its pass).  The slot swizzle XORs each 2^W-slot group of a label into
+// its low W bits, so local bit p lands on swizzle bit p mod W; lanes that share
+// one LDS access cycle differ in the thread's low bits, and they hit distinct
+// banks when thread bit i sits on a local bit of residue i (W = 4 for 16-byte,
+// 5 for 8-byte amplitudes).  The ascending map already does that for most
+// layouts; one whose register bits take the bit of residue i that the ascending
+// map would use gets, per residue, the lowest free local bit of that residue.
+// Returns false (ascending map kept) when that holds already or a residue has no
+// free bit.
+bool choose_lanes(const HostStage& hs, int k, int W, int32_t* nlanes, uint32_t* lanes, uint32_t* rest) {
+    uint32_t reg = 0;
+    for (int a = 0; a < kMaxRegBits; ++a)
+        if (hs.rb[a] >= 0) reg |= 1u << hs.rb[a];
+    std::vector<int> fr;
+    for (int l = 0; l < k; ++l)
+        if (!(reg >> l & 1)) fr.push_back(l);
+    if ((int)fr.size() < W) return false;
+    bool ordered = true;
+    for (int i = 0; i < W; ++i) ordered = ordered && fr[i] % W == i;
+    if (ordered) return false;
+    uint32_t pk = 0, used = 0;
+    for (int i = 0; i < W; ++i) {
+        int pick = -1;
+        for (int l : fr)
+            if (l % W == i && !(used >> l & 1)) {
+                pick = l;
+                break;
+            }
+        if (pick < 0) return false;
+        used |= 1u << pick;
+        pk |= (uint32_t)pick << (4 * i);
+    }
+    uint32_t r = 0;
+    for (int l : fr)
+        if (!(used >> l & 1)) r |= 1u << l;
+    *nlanes = W;
+    *lanes = pk;
+    *rest = r;
+    return true;
+}
+
 std::vector<Stage> pack_stage(const HostStage& hs, const std::vector<HostPhase>& phases, std::vector<PhaseOp>* table,
                               std::vector<double>* twid, std::vector<URef>* urefs, size_t pass_urefs) {
     std::vector<Stage> subs;
@@ -1000,9 +1042,20 @@ struct Compiler {
                 }
             }
             hp.uref_begin = (int)plan->urefs.size();
-            for (const HostStage& hs : hp.stages) {
+            const int lane_w = plan->prec == PK_FP64 ? 4 : 5;
+            for (size_t si = 0; si < hp.stages.size(); ++si) {
+                const HostStage& hs = hp.stages[si];
                 std::vector<Stage> sub =
                     pack_stage(hs, hp.phases, &plan->phases, &plan->twid, &plan->urefs, (size_t)hp.uref_begin);
+                int32_t nl = 0;
+                uint32_t ln = 0, lr = 0;
+                if (plan->lane_maps && si > 0 && si + 1 < hp.stages.size() &&
+                    choose_lanes(hs, hp.k, lane_w, &nl, &ln, &lr))
+                    for (Stage& st : sub) {
+                        st.nlanes = nl;
+                        st.lanes = ln;
+                        st.lanes_rest = lr;
+                    }
                 hp.subs.insert(hp.subs.end(), sub.begin(), sub.end());
             }
             hp.nuref = (int)plan->urefs.size() - hp.uref_begin;
@@ -1380,6 +1433,8 @@ int recompile(Plan* plan, std::string* err) {
                 hp.flags |= PASS_STREAM;
             emit(plan->inst[i], (int)i, hp);
             if (i == 0 && plan->inst.size() == 1 && p < plan->walk.size()) plan->passes.back().walk = plan->walk[p];
+            if (i == 0 && plan->inst.size() == 1 && p < plan->overlap.size())
+                plan->passes.back().overlap = plan->overlap[p];
         }
     plan->n_fwd_passes = (int)plan->passes.size();
     for (size_t i = 0; i < plan->inst.size(); ++i)
@@ -1558,6 +1613,9 @@ std::string describe(const Plan* plan) {
                      std::to_string(plan->inst.size() != 1 ? 0
                                     : dir == 0 ? (p < plan->walk.size() ? plan->walk[p] : 0)
                                     : (plan->walk.size() == in.fwd.size() + in.bwd.size() ? plan->walk[in.fwd.size() + p] : 0));
+                s += ",\"overlap\":" + std::to_string(plan->inst.size() == 1 && dir == 0 && p < plan->overlap.size()
+                                                           ? plan->overlap[p]
+                                                           : 0);
                 s += ",\"urefs\":[";
                 for (int r = 0; r < hp.nuref; ++r) {
                     const URef& ur = plan->urefs[hp.uref_begin + r];
@@ -1642,7 +1700,10 @@ std::string describe(const Plan* plan) {
                     std::snprintf(buf, sizeof buf, "%.17g", (double)u.d4b_gscale);
                     s += ",\"d4b_gscale\":";
                     s += buf;
-                    s += ",\"scale\":" + std::to_string(u.scale) + ",\"read\":" + std::to_string(u.read) + "}";
+                    s += ",\"scale\":" + std::to_string(u.scale) + ",\"read\":" + std::to_string(u.read) +
+                         ",\"nlanes\":" + std::to_string(u.nlanes) + ",\"lanes\":[";
+                    for (int i = 0; i < u.nlanes; ++i) s += (i ? "," : "") + std::to_string((u.lanes >> (4 * i)) & 15u);
+                    s += "],\"lanes_rest\":" + std::to_string(u.lanes_rest) + "}";
                 }
                 s += "]}";
             }

@@ -137,6 +137,8 @@ struct Plan {
                                        // entry 0 is 1 (what lanes without a table load)
     std::vector<URef> urefs;           // tile-part tables of every pass
     std::vector<int32_t> walk;         // Pass::walk of each forward pass of instance 0 (empty: all 0)
+    std::vector<int32_t> overlap;      // Pass::overlap of each forward pass of instance 0 (empty: all 0)
+    int lane_maps = 1;                 // 1: LDS-only layouts get bank-spreading lane maps (Stage::lanes)
     int n_d2 = 0;
     int n_d4 = 0;
     int n_static = 0;

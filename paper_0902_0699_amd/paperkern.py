@@ -57,6 +57,8 @@ SIGNATURES = {
     "pk_evaluate_repeat": (ctypes.c_int, [_vp, _c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pk_repeat_launches": (ctypes.c_int, [_vp, _c_int64, ctypes.POINTER(_c_int64)]),
     "pk_set_pass_walk": (ctypes.c_int, [_vp, _c_int32, ctypes.POINTER(_c_int32)]),
+    "pk_set_lane_maps": (ctypes.c_int, [_vp, _c_int32]),
+    "pk_set_pass_overlap": (ctypes.c_int, [_vp, _c_int32, ctypes.POINTER(_c_int32)]),
     "pk_evaluate_static": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pk_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pk_pair_indices": (ctypes.c_int, [_c_int32, _c_int32, _c_int64, _c_int64, _vp, _vp, _vp]),
@@ -204,6 +206,19 @@ class Plan:
         walk = [int(c) for c in walk]
         arr = (_c_int32 * max(1, len(walk)))(*walk)
         _check(lib().pk_set_pass_walk(self.handle, len(walk), arr), self.handle)
+        self._ws = {}
+
+    def set_pass_overlap(self, on):
+        """Per forward pass: 1 keeps the next tile's loads in flight through the LDS
+        exchanges (FP64 kernels with 4 register bits, full tiles); an empty list resets."""
+        on = [int(c) for c in on]
+        arr = (_c_int32 * max(1, len(on)))(*on)
+        _check(lib().pk_set_pass_overlap(self.handle, len(on), arr), self.handle)
+        self._ws = {}
+
+    def set_lane_maps(self, on):
+        """1: bank-spreading thread maps for the LDS-only stage layouts (default); 0: off."""
+        _check(lib().pk_set_lane_maps(self.handle, int(on)), self.handle)
         self._ws = {}
 
     def passes(self, inst=0):

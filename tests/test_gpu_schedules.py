@@ -221,6 +221,90 @@ def test_backward_tile_walks_are_bit_identical(nq):
         assert bool(torch.equal(g0, g1)) and bool(torch.equal(a0, a1))
 
 
+@pytest.mark.parametrize("kind,nq", [("grover", 16), ("grover", 30), ("phases", 20), ("qft", 22)])
+def test_overlapped_tile_loop_is_bit_identical(kind, nq):
+    """The overlapped tile loop (pk_set_pass_overlap) only changes when the next
+    tile's loads are waited for: state and L equal those of the default loop bit
+    for bit, with every tile walk the bench may pick for it, at the headline size
+    (whose last pass streams) and on passes with product tables.  The norm partial
+    is summed by whichever register buffer holds the tile, code the compiler may
+    round differently, so it agrees to 1e-12 relative."""
+    pk = _pk()
+    rng = np.random.default_rng(700 + nq)
+    if kind == "grover":
+        seed = W.SEEDS["large_fp64"]
+        inst = W.single_instance(seed, nq)
+        gates, marked, psi = inst["gates"], inst["marked"], inst["psi"]
+        del inst
+    else:
+        gates = W.phase_circuit(rng, nq, 40) if kind == "phases" else [("QFT", 1, nq)]
+        marked = [int(rng.integers(0, 1 << nq))]
+        v = rng.standard_normal(1 << nq) + 1j * rng.standard_normal(1 << nq)
+        psi = v / np.linalg.norm(v)
+    plan = pk.Plan({"nq": nq, "gates": gates, "marked": marked})
+    x = torch.from_numpy(psi).to("cuda")
+    del psi
+    n = plan.passes()
+    a, La, na = pk.evaluate(plan, x)
+    for walks in ([0] * n, [2] * n, [64] * n, [-1] * n):
+        _say("overlapped loop, walks %s: %s n_q=%d" % (walks, kind, nq))
+        plan.set_pass_walk(walks)
+        plan.set_pass_overlap([1] * n)
+        assert all(p["overlap"] == 1 for p in plan.describe()["instances"][0]["forward"])
+        b, Lb, nb = pk.evaluate(plan, x)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(a, b))
+        del b
+        assert same and La.item() == Lb.item() and abs(na.item() - nb.item()) <= 1e-12 * abs(na.item())
+        plan.set_pass_overlap([])
+    del a, x
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("kind,nq,prec", [("grover", 18, "fp64"), ("grover", 20, "fp32"), ("phases", 16, "fp64"),
+                                           ("phases", 16, "fp32"), ("qft", 14, "fp64"), ("qft", 20, "fp32")])
+def test_lane_maps_are_bit_identical(kind, nq, prec):
+    """The LDS lane maps (pk_set_lane_maps) change only which thread holds which
+    amplitudes between exchanges: forward state, L and norm, and the backward's
+    gradient of psi_in, equal those of the ascending thread map bit for bit.  The
+    D2 angle gradients are tile sums taken thread by thread in the layout of the
+    stage that holds the D2, so another thread map adds the same terms in another
+    order: they agree to 1e-13 relative."""
+    pk = _pk()
+    rng = np.random.default_rng(500 + nq)
+    if kind == "grover":
+        gates, marked, psi = _case(nq, 2, 60 + nq)
+    else:
+        gates = W.phase_circuit(rng, nq, 40) if kind == "phases" else [("QFT", 1, nq)]
+        marked = [int(rng.integers(0, 1 << nq))]
+        v = rng.standard_normal(1 << nq) + 1j * rng.standard_normal(1 << nq)
+        psi = v / np.linalg.norm(v)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    plan = pk.Plan({"nq": nq, "gates": gates, "marked": marked}, prec=prec)
+    inst = plan.describe()["instances"][0]
+    assert any(s["nlanes"] for p in inst["forward"] + inst["backward"] for s in p["subs"])
+    x = torch.from_numpy(psi).to(dt).to("cuda")
+    runs = []
+    for on in (1, 0):
+        _say("lane maps %d: %s n_q=%d %s" % (on, kind, nq, prec))
+        plan.set_lane_maps(on)
+        y, L, norm = pk.evaluate(plan, x)
+        grads = None
+        if prec == "fp64":
+            dL = torch.tensor([0.5], dtype=torch.float64, device="cuda")
+            grads = pk.backward(plan, y, dL)
+        torch.cuda.synchronize()
+        runs.append((y, L.item(), norm.item(), grads))
+    (a, La, na, ga), (b, Lb, nb, gb) = runs
+    assert bool(torch.equal(a, b)) and La == Lb and na == nb
+    if ga is not None:
+        assert bool(torch.equal(ga[0], gb[0]))
+        assert ga[1].shape == gb[1].shape
+        if ga[1].numel():
+            scale = float(torch.max(torch.abs(ga[1])))
+            assert float(torch.max(torch.abs(ga[1] - gb[1]))) <= 1e-13 * max(scale, 1e-300)
+
+
 @pytest.mark.slow
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])

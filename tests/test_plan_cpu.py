@@ -783,3 +783,121 @@ def test_qft_noswap_schedule_matches_the_permuted_dft(nq, n1, tiling):
     for b in range(n1):
         rev |= ((reg >> b) & 1) << (n1 - 1 - b)
     np.testing.assert_allclose(got, want[(rev << low) | (idx & ((1 << low) - 1))], rtol=0, atol=1e-12)
+
+
+def _thread_label(sub, tid):
+    """The label base a thread holds in one sub-stage's layout (the kernel's
+    make_layout, restated): ascending over the free local bits, or the lane map."""
+    if sub["nlanes"] == 0:
+        t = tid
+        for p in sorted(b for b in sub["rb"] if b >= 0):
+            t = ((t >> p) << (p + 1)) | (t & ((1 << p) - 1))
+        return t
+    w = sub["nlanes"]
+    t = 0
+    for i, p in enumerate(sub["lanes"]):
+        t |= ((tid >> i) & 1) << p
+    x = tid >> w
+    rest = [b for b in range(32) if sub["lanes_rest"] >> b & 1]
+    for p in rest:
+        t |= (x & 1) << p
+        x >>= 1
+    return t
+
+
+def _bank_group_conflicts(sub, k, w):
+    """Lane groups (2^w consecutive threads: 256 bytes of amplitudes) of one layout
+    whose LDS slots, under the XOR swizzle of 2^w-slot groups, repeat a bank."""
+    nrb = sum(1 for b in sub["rb"] if b >= 0)
+    m = (1 << w) - 1
+    bad = 0
+    for g in range(0, 1 << (k - nrb), 1 << w):
+        slots = set()
+        for tid in range(g, g + (1 << w)):
+            j = _thread_label(sub, tid)
+            slots.add((j ^ (j >> w) ^ (j >> 2 * w) ^ (j >> 3 * w)) & m)
+        bad += len(slots) < (1 << w)
+    return bad
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_lane_maps_spread_lds_banks(prec):
+    """Stage layouts that move through LDS only get a thread map whose lane groups
+    hit distinct banks; the first and last layout of each pass (the HBM load and
+    store) keep the ascending map; every map is a bijection onto the labels with
+    zero register bits; pk_set_lane_maps(0) turns the maps off."""
+    w = 4 if prec == "fp64" else 5
+    rng = np.random.default_rng(11)
+    probs = [
+        {"nq": 30, "gates": W.grover_gates((16, 3, 0.9, 3.0, 0.0)), "marked": [5]},
+        {"nq": 30, "gates": [("QFT", 1, 20)], "marked": []},
+        {"nq": 24, "gates": W.phase_circuit(rng, 24, 40), "marked": [3]},
+    ]
+    seen = 0
+    for prob in probs:
+        plan = pk.Plan(prob, prec=prec)
+        before = None
+        for on in (0, 1):
+            plan.set_lane_maps(on)
+            inst = plan.describe()["instances"][0]
+            conflicts = 0
+            for p in inst["forward"] + inst["backward"]:
+                k = p["k"]
+                groups = []
+                for s in p["subs"]:
+                    if s["exchange"] or not groups:
+                        groups.append([])
+                    groups[-1].append(s)
+                for gi, grp in enumerate(groups):
+                    assert all(s["nlanes"] == grp[0]["nlanes"] and s["lanes"] == grp[0]["lanes"] for s in grp)
+                    sub = grp[0]
+                    if on == 0 or gi == 0 or gi == len(groups) - 1:
+                        assert sub["nlanes"] == 0
+                    nrb = sum(1 for b in sub["rb"] if b >= 0)
+                    if k - nrb > 12:
+                        continue
+                    labels = sorted(_thread_label(sub, t) for t in range(1 << (k - nrb)))
+                    regmask = sum(1 << b for b in sub["rb"] if b >= 0)
+                    assert labels == [j for j in range(1 << k) if not j & regmask]
+                    if sub["nlanes"]:
+                        seen += 1
+                        assert [q % w for q in sub["lanes"]] == list(range(w))
+                    if 0 < gi < len(groups) - 1 and k - nrb >= w:
+                        conflicts += _bank_group_conflicts(sub, k, w)
+            if on == 0:
+                before = conflicts
+            else:
+                assert conflicts <= before
+                if prec == "fp64":
+                    assert conflicts == 0
+    assert seen > 0
+
+
+def test_pass_overlap_settings():
+    """pk_set_pass_overlap sets each forward pass's tile-loop pipelining (0 or 1)
+    and nothing else; walks survive it, a tiling change resets it; wrong lengths,
+    values and batched plans are refused."""
+    prob = {"nq": 24, "gates": W.grover_gates((3, 2, 0.4, 0.2, 0.1)), "marked": [5]}
+    plan = pk.Plan(prob)
+    n = plan.passes()
+    plan.set_pass_walk([2] * n)
+    before = plan.describe()["instances"][0]
+    on = [p % 2 for p in range(n)]
+    plan.set_pass_overlap(on)
+    d = plan.describe()["instances"][0]
+    assert [p["overlap"] for p in d["forward"]] == on
+    assert [p["walk"] for p in d["forward"]] == [2] * n
+    strip = lambda inst: [{k: v for k, v in p.items() if k != "overlap"} for p in inst["forward"] + inst["backward"]]
+    assert strip(d) == strip(before)
+    for bad in ([0] * (n + 1), [2] + [0] * (n - 1), [-1] + [0] * (n - 1)):
+        with pytest.raises(pk.PaperkernError):
+            plan.set_pass_overlap(bad)
+    assert [p["overlap"] for p in plan.describe()["instances"][0]["forward"]] == on
+    plan.set_pass_overlap([])
+    assert all(p["overlap"] == 0 for p in plan.describe()["instances"][0]["forward"])
+    plan.set_pass_overlap([1] * n)
+    plan.set_tiling(12, 4, 1)
+    assert all(p["overlap"] == 0 for p in plan.describe()["instances"][0]["forward"])
+    batch = pk.Plan([prob, prob])
+    with pytest.raises(pk.PaperkernError):
+        batch.set_pass_overlap([0])

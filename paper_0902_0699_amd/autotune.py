@@ -70,9 +70,9 @@ WALKS = (0, 2, 4, 16, 64, -1)
 
 
 def has_overlap(plan):
-    """Whether Pass::overlap can change a forward pass of this plan: the FP64
+    """Whether Pass::overlap can change a forward pass of this plan: the
     single-instance kernels with 4 register bits have the overlapped tile loop."""
-    if plan.prec != pk.PK_FP64 or plan.n_inst != 1:
+    if plan.n_inst != 1:
         return False
     return any(p["rbits"] == 4 for p in plan.describe()["instances"][0]["forward"])
 

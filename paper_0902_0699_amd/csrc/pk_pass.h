@@ -882,11 +882,12 @@ __device__ __forceinline__ void run_tiles(const KArgs& a, const PK_CONST Pass* P
                                           int64_t chunk = 1) {
     if (first >= ntiles) return;
     // Pass::overlap selects the FULL loop where it applies (single-instance launches).
-    // Only the FP64 kernels with 4 register bits have it: its two register buffers
-    // take no more registers there than the other loops (237 at 2^13 tiles), while
-    // the FP32 kernel with 5 would go from 241 to 359 VGPRs (one workgroup a CU
-    // instead of two, 17.7 -> 21.6 ms an iteration) or spill under a 256 cap.
-    constexpr bool kHasFull = STREAM && NV == 1 && sizeof(R) == 8 && RB == 4;
+    // Only the kernels with 4 register bits have it: there it keeps the occupancy
+    // the other loops allow (FP64 2^13 tiles: 237 VGPRs either way; FP32: 146 -> 201,
+    // one workgroup a CU either way), while the FP32 kernel with 5 would go from 241
+    // to 359 VGPRs (one workgroup a CU instead of two, 17.7 -> 21.6 ms an iteration)
+    // or spill under a 256 cap, and with 3 it spills under the 128 cap.
+    constexpr bool kHasFull = STREAM && NV == 1 && RB == 4;
     const bool full = kHasFull && P->overlap && P->k == KMAX && !(P->flags & PASS_WIDE);
     if (P->nuref > 0) {
         if (full) run_tiles_ph<R, NV, KMAX, RB, true, false, true>(a, P, first, stride, ntiles, lds, red, chunk);

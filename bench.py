@@ -381,6 +381,7 @@ def two_qubit_run(torch, pk, autotune, nq, steps):
         else:
             walk, _ = autotune.tune_walk(plan, x, y)
             out["fused_tile_walk"] = walk
+            out["fused_overlap"] = [p["overlap"] for p in plan.describe()["instances"][0]["forward"]]
         pk.evaluate_into(plan, x, y, L, norm)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
